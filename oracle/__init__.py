@@ -1,0 +1,180 @@
+"""CPU oracle for the columnar query hot path (TEST INFRASTRUCTURE ONLY).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+import this package; the product path never does, and it shares no code with
+the GPU library. The arithmetic lives in ``oracle.c`` (plain C, built into
+``liboracle.so``); this wrapper only marshals numpy arrays.
+
+What it computes is the plain relational definition of each step (the paper
+delegates its operators to a GPU library and gives them no semantics of its
+own, Section 2): selection, projection with int64 arithmetic modulo 2^64,
+inner equi-join, group-by with COUNT/SUM/AVG, and the 64-bit multiplicative
+hash partition of Section 3.2. Parity pins: see ``tests/test_oracle_pins.py``
+(brute force, closed forms, library special cases, invariants).
+
+Query descriptions are duck-typed: predicates have ``col, lo, hi``; factors
+have ``col, sign, add``; expressions are sequences of factors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class _Col(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32)]
+
+
+_vp, _i64, _i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(_LIB_PATH)
+        L.oc_filter.restype = _i64
+        L.oc_filter.argtypes = [_vp, _i64, _i32, _vp, _vp, _vp, _vp]
+        L.oc_project.restype = None
+        L.oc_project.argtypes = [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]
+        L.oc_groupby.restype = _i64
+        L.oc_groupby.argtypes = [_i64, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i64]
+        L.oc_join.restype = _i64
+        L.oc_join.argtypes = [_vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _i64]
+        L.oc_partition_ids.restype = None
+        L.oc_partition_ids.argtypes = [_vp, _i64, _i32, _vp]
+        L.oc_partition.restype = None
+        L.oc_partition.argtypes = [_vp, _i64, _i32, _vp, _vp]
+        _lib = L
+    return _lib
+
+
+_WIDTH = {np.dtype(np.uint8): 1, np.dtype(np.int32): 4, np.dtype(np.int64): 8}
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _cols(arrays: Sequence[np.ndarray]):
+    arr = (_Col * max(1, len(arrays)))()
+    for i, a in enumerate(arrays):
+        assert a.flags["C_CONTIGUOUS"], "oracle columns must be contiguous"
+        arr[i].data = a.ctypes.data
+        arr[i].width = _WIDTH[a.dtype]
+    return arr
+
+
+def filter_mask(table: Dict[str, np.ndarray], preds) -> np.ndarray:
+    """uint8 mask of the rows that satisfy every predicate (selection)."""
+    n = len(next(iter(table.values())))
+    names = sorted({p.col for p in preds})
+    cols = [np.ascontiguousarray(table[c]) for c in names]
+    pcol = np.array([names.index(p.col) for p in preds], dtype=np.int32)
+    lo = np.array([p.lo for p in preds], dtype=np.int64)
+    hi = np.array([p.hi for p in preds], dtype=np.int64)
+    mask = np.empty(n, dtype=np.uint8)
+    lib().oc_filter(_cols(cols), n, len(preds), _p(pcol), _p(lo), _p(hi), _p(mask))
+    return mask
+
+
+def project(table: Dict[str, np.ndarray], expr, n: Optional[int] = None):
+    """Evaluate one product expression for every row. Returns (values, overflow)."""
+    if n is None:
+        n = len(next(iter(table.values())))
+    names = sorted({f.col for f in expr if f.col is not None})
+    cols = [np.ascontiguousarray(table[c]) for c in names]
+    fcol = np.array([-1 if f.col is None else names.index(f.col) for f in expr], dtype=np.int32)
+    fsign = np.array([f.sign for f in expr], dtype=np.int64)
+    fadd = np.array([f.add for f in expr], dtype=np.int64)
+    out = np.empty(n, dtype=np.int64)
+    ovf = np.empty(n, dtype=np.uint8)
+    lib().oc_project(_cols(cols), n, len(expr), _p(fcol), _p(fsign), _p(fadd), _p(out), _p(ovf))
+    return out, ovf
+
+
+def groupby(key_cols: Sequence[np.ndarray], values: Sequence[np.ndarray], mask: Optional[np.ndarray] = None,
+            max_groups: Optional[int] = None) -> dict:
+    """Sort-based group-by. Returns keys [g][nkey], count [g], sums [g][nval],
+    avg [g][nval] (float64) and the overflow flags [g][nval]."""
+    n = len(key_cols[0])
+    nkey, nval = len(key_cols), len(values)
+    kc = [np.ascontiguousarray(k) for k in key_cols]
+    vals = [np.ascontiguousarray(v, dtype=np.int64) for v in values]
+    vp = (ctypes.c_void_p * max(1, nval))(*[v.ctypes.data for v in vals])
+    cap = n if max_groups is None else max_groups
+    cap = max(cap, 1)
+    keys = np.empty((cap, nkey), dtype=np.int64)
+    count = np.empty(cap, dtype=np.int64)
+    sums = np.empty((cap, max(nval, 1)), dtype=np.int64)
+    avg = np.empty((cap, max(nval, 1)), dtype=np.float64)
+    ovf = np.empty((cap, max(nval, 1)), dtype=np.uint8)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    g = lib().oc_groupby(n, _p(m), nkey, _cols(kc), nval, vp, _p(keys), _p(count), _p(sums), _p(avg),
+                         _p(ovf), cap)
+    if g < 0:
+        raise ValueError("more groups than max_groups")
+    return {"keys": keys[:g], "count": count[:g], "sums": sums[:g, :nval], "avg": avg[:g, :nval],
+            "overflow": ovf[:g, :nval]}
+
+
+def join_pairs(build_keys: np.ndarray, probe_keys: np.ndarray, build_mask=None, probe_mask=None,
+               with_pairs: bool = True):
+    """Inner equi-join. Returns (cardinality, probe_rows, build_rows) ordered by
+    (probe_row, build_row)."""
+    bk = np.ascontiguousarray(build_keys, dtype=np.int64)
+    pk = np.ascontiguousarray(probe_keys, dtype=np.int64)
+    bm = None if build_mask is None else np.ascontiguousarray(build_mask, dtype=np.uint8)
+    pm = None if probe_mask is None else np.ascontiguousarray(probe_mask, dtype=np.uint8)
+    total = lib().oc_join(_p(bk), len(bk), _p(bm), _p(pk), len(pk), _p(pm), None, None, 0)
+    if not with_pairs:
+        return total, None, None
+    pr = np.empty(max(total, 1), dtype=np.int64)
+    br = np.empty(max(total, 1), dtype=np.int64)
+    lib().oc_join(_p(bk), len(bk), _p(bm), _p(pk), len(pk), _p(pm), _p(pr), _p(br), total)
+    return total, pr[:total], br[:total]
+
+
+def filter_groupby(table: Dict[str, np.ndarray], query) -> dict:
+    """sigma, pi and gamma for a filter + group-by query description."""
+    mask = filter_mask(table, query.preds) if query.preds else None
+    vals = [project(table, e)[0] for e in query.sums]
+    keys = [table[c] for c in query.key.cols]
+    return groupby(keys, vals, mask)
+
+
+def join_agg(dim: Dict[str, np.ndarray], fact: Dict[str, np.ndarray], query) -> dict:
+    """sigma on both sides, inner join on build_key = probe_key, then group by
+    the build payload with SUM/COUNT/AVG of probe-side expressions."""
+    bm = filter_mask(dim, query.build_preds) if query.build_preds else None
+    pm = filter_mask(fact, query.probe_preds) if query.probe_preds else None
+    total, pr, br = join_pairs(dim[query.build_key], fact[query.probe_key], bm, pm)
+    keys = np.ascontiguousarray(dim[query.build_payload][br])
+    vals = [project(fact, e)[0][pr] for e in query.sums]
+    res = groupby([keys], vals)
+    res["join_rows"] = total
+    return res
+
+
+def partition_ids(keys: np.ndarray, bits: int) -> np.ndarray:
+    k = np.ascontiguousarray(keys, dtype=np.int64)
+    out = np.empty(len(k), dtype=np.int32)
+    lib().oc_partition_ids(_p(k), len(k), bits, _p(out))
+    return out
+
+
+def partition(keys: np.ndarray, bits: int):
+    """Stable hash partition. Returns (perm, offsets[2^bits + 1])."""
+    k = np.ascontiguousarray(keys, dtype=np.int64)
+    perm = np.empty(max(len(k), 1), dtype=np.int64)
+    offs = np.empty((1 << bits) + 1, dtype=np.int64)
+    lib().oc_partition(_p(k), len(k), bits, _p(perm), _p(offs))
+    return perm[:len(k)], offs
