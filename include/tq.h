@@ -1,0 +1,208 @@
+/*
+ * tq — a columnar query hot path for AMD MI355X (gfx950).
+ *
+ * C ABI of libtq.so. Plain pointers and sizes only.
+ *
+ * Conventions
+ *   d_*      device pointer (HIP global memory) owned by the CALLER
+ *   h_*      host pointer owned by the caller
+ *   stream   a hipStream_t; work is enqueued on it and every call returns
+ *            without synchronising unless its comment says otherwise
+ *   columns  Arrow-style fixed-width value buffers (the paper keeps device
+ *            batches in Arrow's columnar layout, Section 3.4); a batch is a
+ *            set of columns with the same row count (Section 3.1). Device
+ *            column pointers must be 16-byte aligned.
+ *   errors   argument errors are detected before anything is enqueued and
+ *            returned synchronously; errors found by a kernel (a full table,
+ *            a group key outside its domain) are latched in the header of the
+ *            table or group-by state and returned by tq_check().
+ *            tq_last_error() gives the text of the last failure on the
+ *            calling thread.
+ *   integers all sums and products are int64 with two's-complement wrap
+ *            (mod 2^64), so results are independent of the order in which
+ *            threads and atomics combine them.
+ */
+#ifndef TQ_H
+#define TQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+
+typedef int32_t tq_status;
+#define TQ_OK 0
+#define TQ_EINVAL (-1)   /* bad argument, detected before enqueueing */
+#define TQ_ENOMEM (-2)   /* page pool or device budget exhausted */
+#define TQ_EFULL (-3)    /* hash table or output capacity too small */
+#define TQ_EDOMAIN (-4)  /* a group key fell outside [0, domain) */
+#define TQ_EHIP (-5)     /* a HIP runtime call failed */
+
+const char* tq_strerror(tq_status s);
+const char* tq_last_error(void); /* thread-local; "" when none */
+int32_t tq_version(void);
+
+/* --------------------------------------------------------- row descriptors */
+
+typedef enum { TQ_U8 = 1, TQ_I32 = 4, TQ_I64 = 8 } tq_type; /* values widen to int64 */
+
+typedef struct {
+  const void* data; /* d_ column values */
+  int32_t type;     /* tq_type */
+} tq_col;
+
+/* lo <= col <= hi on the widened value; a list of predicates is a conjunction. */
+typedef struct {
+  int32_t col;
+  int64_t lo, hi;
+} tq_pred;
+
+/* sign * col + add; col = -1 means the constant `add`. */
+typedef struct {
+  int32_t col;
+  int32_t sign;
+  int64_t add;
+} tq_factor;
+
+/* Product of nf (1..3) factors, evaluated left to right in int64 mod 2^64. */
+typedef struct {
+  int32_t nf;
+  tq_factor f[3];
+} tq_expr;
+
+/* Group key: col[0] * mult + col[1] (ncol = 2) or col[0] (ncol = 1). */
+typedef struct {
+  int32_t ncol;
+  int32_t col[2];
+  int64_t mult;
+} tq_gkey;
+
+#define TQ_MAX_COLS 8
+#define TQ_MAX_PREDS 4
+#define TQ_MAX_SUMS 6
+
+/* ---------------------------------------------------- filter and project */
+
+/* Selection and projection (the Filter operator of Section 3.1 and the
+ * per-task computation of Section 3.3.1). For every row of `in` that
+ * satisfies all `np` predicates, writes the `ne` expression values to
+ * d_out[e][i] and, if d_sel is not NULL, the source row index to d_sel[i],
+ * for i < *d_out_rows. Each output must hold nrows values. The order of the
+ * output rows is unspecified; d_sel identifies them. *d_out_rows (device) is
+ * set by the call. */
+tq_status tq_filter_project(const tq_col* in, int32_t ncol, int64_t nrows, const tq_pred* p, int32_t np,
+                            const tq_expr* e, int32_t ne, int64_t* const* d_out, int64_t* d_sel,
+                            int64_t* d_out_rows, hipStream_t stream);
+
+/* ------------------------------------------------------------ hash partition */
+
+/* Hash partitioning, the exchange in front of a join (Section 3.2): row r goes
+ * to partition p(r) = bits [skip, skip + log2_fanout) counted from the most
+ * significant end of h = key_r * 0x9E3779B97F4A7C15 (mod 2^64). Writes the
+ * keys and every payload column partition by partition (partition p occupies
+ * rows d_offsets[p] .. d_offsets[p+1]-1; d_offsets has 2^log2_fanout + 1
+ * entries); the order inside a partition is unspecified. Payload columns keep
+ * their type. Needs a device scratch buffer of
+ * tq_hash_partition_scratch_bytes(n, log2_fanout) bytes. log2_fanout <= 10,
+ * skip + log2_fanout <= 64. */
+size_t tq_hash_partition_scratch_bytes(int64_t n, int32_t log2_fanout);
+tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_t npay, int64_t n,
+                            int32_t log2_fanout, int32_t skip, int64_t* d_out_keys, void* const* d_out_payload,
+                            int64_t* d_offsets, void* d_scratch, size_t scratch_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------- hash join */
+
+/* An open-addressing hash table (linear probing) for the build side of an
+ * equi-join (the Adaptive Join of Section 3.2). Layout: a 256-byte header, a
+ * 32-bit tag per slot (0 = empty) and a 16-byte {key, payload} slot array.
+ * Any int64 key is allowed; duplicate build keys are kept (many-to-many).
+ * tq_join_table_bytes gives the size for at most n_build_max rows at the given
+ * load factor (0 < load_factor <= 0.9). The capacity actually used by a build
+ * is the smallest power of two >= rows / load_factor, computed on the device
+ * from the number of rows that pass the build filter. */
+size_t tq_join_table_bytes(int64_t n_build_max, double load_factor);
+
+/* Prepare a table buffer once after allocation (zeroes its header). */
+tq_status tq_join_table_init(void* d_table, size_t bytes, hipStream_t stream);
+
+#define TQ_UNIQUE_KEYS 1u /* build keys are unique: a probe stops at its first match */
+
+/* Build: insert (keys[r], payload[r]) for every row r < n that satisfies the
+ * optional predicates over `filt` (the dimension filter fused into the build).
+ * `skip` high hash bits are ignored by the slot index (set it to the partition
+ * bits when the input is one hash partition). Latches TQ_EFULL if the rows do
+ * not fit in the buffer. */
+tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_col payload, int64_t n,
+                        const tq_col* filt, int32_t nfilt, const tq_pred* p, int32_t np, double load_factor,
+                        int32_t skip, uint32_t flags, hipStream_t stream);
+
+/* Fused group-by applied to probe matches: group key = the matched build
+ * payload, sums = expressions over the probe-side columns passed to
+ * tq_join_probe. d_state comes from tq_groupby_init. */
+typedef struct {
+  void* d_state;
+  int64_t domain; /* as passed to tq_groupby_init */
+  const tq_expr* sums;
+  int32_t nsum;   /* as passed to tq_groupby_init */
+} tq_agg;
+
+/* Probe: for every probe row r < n that satisfies the optional predicates over
+ * `cols`, find every build slot with key == d_probe_keys[r].
+ *   agg == NULL  write pairs (r, payload) to d_out_probe_row / d_out_payload
+ *                (order unspecified, at most `capacity`); *d_out_count gets
+ *                the total match count, which may exceed capacity (then the
+ *                pairs past `capacity` are dropped; the caller compares).
+ *   agg != NULL  aggregate the matches into agg->d_state instead; the pair
+ *                outputs may be NULL and *d_out_count (if not NULL) gets the
+ *                match count. */
+tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_t n, const tq_col* cols,
+                        int32_t ncol, const tq_pred* p, int32_t np, int64_t* d_out_probe_row,
+                        int64_t* d_out_payload, int64_t capacity, int64_t* d_out_count, const tq_agg* agg,
+                        hipStream_t stream);
+
+/* ------------------------------------------------------------- group-by */
+
+/* Group-by state for keys in [0, domain) with COUNT and `nsum` int64 SUMs
+ * (the aggregations of Section 2). It accumulates across any number of
+ * tq_groupby_agg / fused-probe calls (batches, partitions, requests). */
+size_t tq_groupby_state_bytes(int64_t domain, int32_t nsum);
+tq_status tq_groupby_init(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream);
+
+/* Accumulate the rows of `in` that satisfy the predicates: key from `key`
+ * (must lie in [0, domain), else TQ_EDOMAIN is latched and the row dropped),
+ * COUNT += 1 and SUM_j += sums[j](row). `domain` and `nsum` must be the values
+ * the state was initialised with; if they are not, the kernel writes nothing
+ * and latches TQ_EINVAL. */
+tq_status tq_groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_t ncol, int64_t nrows,
+                         const tq_pred* p, int32_t np, const tq_gkey* key, const tq_expr* sums, int32_t nsum,
+                         hipStream_t stream);
+
+/* Emit the groups with COUNT > 0 in ascending key order: d_keys[g],
+ * d_count[g], d_sums[g * nsum + j] and, if d_avg is not NULL,
+ * d_avg[g * nsum + j] = (double)SUM_j / (double)COUNT (IEEE round to nearest
+ * even). Outputs must hold `domain` groups; *d_ngroups gets the count. */
+tq_status tq_groupby_finalize(const void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums,
+                              double* d_avg, int64_t* d_ngroups, hipStream_t stream);
+
+/* Synchronise `stream`, then return the error latched in a join table or a
+ * group-by state (TQ_OK if none). */
+tq_status tq_check(const void* d_obj, hipStream_t stream);
+
+/* ------------------------------------------------------- measurement kernels */
+
+/* Read `bytes` (multiple of 16) and write one checksum to *d_sink: the
+ * streaming-read ceiling of the device. */
+tq_status tq_read_peak(const void* d_src, size_t bytes, int64_t* d_sink, hipStream_t stream);
+/* Write `bytes` (multiple of 16) of a pattern; used to evict caches between timed repetitions. */
+tq_status tq_fill(void* d_dst, size_t bytes, uint32_t pattern, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TQ_H */

@@ -1,0 +1,118 @@
+// Status codes, thread-local error text and argument validation of the C ABI.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "common.h"
+
+namespace tq {
+
+static thread_local char g_last_error[512];
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+  va_end(ap);
+}
+
+tq_status fail(tq_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+tq_status hip_fail(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return TQ_EHIP;
+}
+
+int device_cu_count() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
+static bool valid_type(int32_t t) { return t == TQ_U8 || t == TQ_I32 || t == TQ_I64; }
+
+tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p, int32_t np, const tq_expr* e,
+                    int32_t ne, const tq_gkey* key, int64_t nrows) {
+  memset(P, 0, sizeof *P);
+  if (nrows < 0) return fail(TQ_EINVAL, "nrows < 0");
+  if (ncol < 0 || ncol > TQ_MAX_COLS) return fail(TQ_EINVAL, "ncol %d outside [0, %d]", ncol, TQ_MAX_COLS);
+  if (np < 0 || np > TQ_MAX_PREDS) return fail(TQ_EINVAL, "np %d outside [0, %d]", np, TQ_MAX_PREDS);
+  if (ne < 0 || ne > TQ_MAX_SUMS) return fail(TQ_EINVAL, "expression count %d outside [0, %d]", ne, TQ_MAX_SUMS);
+  if (ncol > 0 && in == nullptr) return fail(TQ_EINVAL, "columns are NULL");
+  if (np > 0 && p == nullptr) return fail(TQ_EINVAL, "predicates are NULL");
+  if (ne > 0 && e == nullptr) return fail(TQ_EINVAL, "expressions are NULL");
+  P->ncol = ncol;
+  for (int c = 0; c < ncol; c++) {
+    if (!valid_type(in[c].type)) return fail(TQ_EINVAL, "column %d: bad type %d", c, in[c].type);
+    if (nrows > 0 && in[c].data == nullptr) return fail(TQ_EINVAL, "column %d: NULL data", c);
+    if (((uintptr_t)in[c].data & 15) != 0) return fail(TQ_EINVAL, "column %d: not 16-byte aligned", c);
+    P->col[c].p = in[c].data;
+    P->col[c].w = in[c].type;
+  }
+  P->np = np;
+  for (int j = 0; j < np; j++) {
+    if (p[j].col < 0 || p[j].col >= ncol) return fail(TQ_EINVAL, "predicate %d: column %d out of range", j, p[j].col);
+    P->pred[j].col = p[j].col;
+    P->pred[j].lo = p[j].lo;
+    P->pred[j].hi = p[j].hi;
+  }
+  P->ne = ne;
+  for (int j = 0; j < ne; j++) {
+    if (e[j].nf < 1 || e[j].nf > 3) return fail(TQ_EINVAL, "expression %d: %d factors (1..3)", j, e[j].nf);
+    P->expr[j].nf = e[j].nf;
+    for (int f = 0; f < e[j].nf; f++) {
+      const tq_factor& F = e[j].f[f];
+      if (F.col < -1 || F.col >= ncol) return fail(TQ_EINVAL, "expression %d factor %d: column %d", j, f, F.col);
+      P->expr[j].f[f].col = F.col;
+      P->expr[j].f[f].sign = F.sign;
+      P->expr[j].f[f].add = F.add;
+    }
+  }
+  if (key) {
+    if (key->ncol < 1 || key->ncol > 2) return fail(TQ_EINVAL, "group key: %d columns (1..2)", key->ncol);
+    for (int c = 0; c < key->ncol; c++)
+      if (key->col[c] < 0 || key->col[c] >= ncol) return fail(TQ_EINVAL, "group key column %d", key->col[c]);
+    P->key_ncol = key->ncol;
+    P->key_col[0] = key->col[0];
+    P->key_col[1] = key->ncol == 2 ? key->col[1] : 0;
+    P->key_mult = key->mult;
+  }
+  return TQ_OK;
+}
+
+}  // namespace tq
+
+extern "C" {
+
+const char* tq_strerror(tq_status s) {
+  switch (s) {
+    case TQ_OK: return "ok";
+    case TQ_EINVAL: return "invalid argument";
+    case TQ_ENOMEM: return "out of pool pages or device budget";
+    case TQ_EFULL: return "hash table or output capacity too small";
+    case TQ_EDOMAIN: return "group key outside its domain";
+    case TQ_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* tq_last_error(void) { return tq::g_last_error; }
+
+int32_t tq_version(void) { return 1; }
+
+}  // extern "C"

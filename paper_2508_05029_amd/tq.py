@@ -1,0 +1,234 @@
+"""ctypes binding of libtq.so: argument marshalling only.
+
+Every function here has the name of a C entry point (``tq_`` dropped) and
+passes torch tensor pointers and a HIP stream straight through; all the work
+runs in the library's HIP kernels. Loading fails loudly if the library is not
+built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtq.so")
+
+TQ_OK, TQ_EINVAL, TQ_ENOMEM, TQ_EFULL, TQ_EDOMAIN, TQ_EHIP = 0, -1, -2, -3, -4, -5
+TQ_U8, TQ_I32, TQ_I64 = 1, 4, 8
+TQ_UNIQUE_KEYS = 1
+MAX_COLS, MAX_PREDS, MAX_SUMS = 8, 4, 6
+
+
+class TqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tq status {status}: {msg}")
+        self.status = status
+
+
+class Col(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("type", ctypes.c_int32)]
+
+
+class PredS(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("lo", ctypes.c_int64), ("hi", ctypes.c_int64)]
+
+
+class FactorS(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("sign", ctypes.c_int32), ("add", ctypes.c_int64)]
+
+
+class ExprS(ctypes.Structure):
+    _fields_ = [("nf", ctypes.c_int32), ("f", FactorS * 3)]
+
+
+class GKey(ctypes.Structure):
+    _fields_ = [("ncol", ctypes.c_int32), ("col", ctypes.c_int32 * 2), ("mult", ctypes.c_int64)]
+
+
+class Agg(ctypes.Structure):
+    _fields_ = [("d_state", ctypes.c_void_p), ("domain", ctypes.c_int64), ("sums", ctypes.POINTER(ExprS)),
+                ("nsum", ctypes.c_int32)]
+
+
+_vp, _i64, _i32, _u32, _sz, _f64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                    ctypes.c_size_t, ctypes.c_double)
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build(); "
+                               "there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "tq_strerror": (ctypes.c_char_p, [_i32]),
+            "tq_last_error": (ctypes.c_char_p, []),
+            "tq_version": (_i32, []),
+            "tq_filter_project": (_i32, [_vp, _i32, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
+            "tq_hash_partition_scratch_bytes": (_sz, [_i64, _i32]),
+            "tq_hash_partition": (_i32, [_vp, _vp, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+            "tq_join_table_bytes": (_sz, [_i64, _f64]),
+            "tq_join_table_init": (_i32, [_vp, _sz, _vp]),
+            "tq_join_build": (_i32, [_vp, _sz, _vp, Col, _i64, _vp, _i32, _vp, _i32, _f64, _i32, _u32, _vp]),
+            "tq_join_probe": (_i32, [_vp, _vp, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp]),
+            "tq_groupby_state_bytes": (_sz, [_i64, _i32]),
+            "tq_groupby_init": (_i32, [_vp, _sz, _i64, _i32, _vp]),
+            "tq_groupby_agg": (_i32, [_vp, _i64, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp]),
+            "tq_groupby_finalize": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tq_check": (_i32, [_vp, _vp]),
+            "tq_read_peak": (_i32, [_vp, _sz, _vp, _vp]),
+            "tq_fill": (_i32, [_vp, _sz, _u32, _vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != TQ_OK:
+        raise TqError(status, lib().tq_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+_TYPE = {torch.uint8: TQ_U8, torch.int32: TQ_I32, torch.int64: TQ_I64}
+
+
+def cols(tensors: Sequence[torch.Tensor]):
+    arr = (Col * max(1, len(tensors)))()
+    for i, t in enumerate(tensors):
+        arr[i].data = t.data_ptr()
+        arr[i].type = _TYPE[t.dtype]
+    return arr
+
+
+def col(t: torch.Tensor) -> Col:
+    return Col(t.data_ptr(), _TYPE[t.dtype])
+
+
+def preds(ps: Sequence[tuple]):
+    """ps: (col_index, lo, hi) triples."""
+    arr = (PredS * max(1, len(ps)))()
+    for i, (c, lo, hi) in enumerate(ps):
+        arr[i] = PredS(c, lo, hi)
+    return arr
+
+
+def exprs(es: Sequence[Sequence[tuple]]):
+    """es: each a sequence of (col_index or -1, sign, add) factors."""
+    arr = (ExprS * max(1, len(es)))()
+    for i, e in enumerate(es):
+        arr[i].nf = len(e)
+        for j, (c, s, a) in enumerate(e):
+            arr[i].f[j] = FactorS(c, s, a)
+    return arr
+
+
+def gkey(key_cols: Sequence[int], mult: int = 1) -> GKey:
+    k = GKey()
+    k.ncol = len(key_cols)
+    k.col[0] = key_cols[0]
+    k.col[1] = key_cols[1] if len(key_cols) > 1 else 0
+    k.mult = mult
+    return k
+
+
+# ------------------------------------------------------------------ entry points
+
+def version() -> int:
+    return lib().tq_version()
+
+
+def filter_project(in_cols, nrows, ps, es, out, sel, out_rows, stream=None):
+    E = exprs(es)
+    outp = (ctypes.c_void_p * max(1, len(out)))(*[t.data_ptr() for t in out])
+    _check(lib().tq_filter_project(cols(in_cols), len(in_cols), nrows, preds(ps), len(ps), E, len(es), outp,
+                                   _ptr(sel), out_rows.data_ptr(), _stream(stream)))
+
+
+def hash_partition_scratch_bytes(n: int, log2_fanout: int) -> int:
+    return lib().tq_hash_partition_scratch_bytes(n, log2_fanout)
+
+
+def hash_partition(keys, payload, n, log2_fanout, skip, out_keys, out_payload, offsets, scratch, stream=None):
+    outp = (ctypes.c_void_p * max(1, len(out_payload)))(*[t.data_ptr() for t in out_payload])
+    _check(lib().tq_hash_partition(_ptr(keys), cols(payload), len(payload), n, log2_fanout, skip, _ptr(out_keys),
+                                   outp, offsets.data_ptr(), _ptr(scratch),
+                                   0 if scratch is None else scratch.numel() * scratch.element_size(),
+                                   _stream(stream)))
+
+
+def join_table_bytes(n_build_max: int, load_factor: float) -> int:
+    return lib().tq_join_table_bytes(n_build_max, load_factor)
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def join_table_init(table, stream=None):
+    _check(lib().tq_join_table_init(table.data_ptr(), _nbytes(table), _stream(stream)))
+
+
+def join_build(table, keys, payload, n, filt_cols=(), ps=(), load_factor=0.5, skip=0, flags=0, stream=None):
+    _check(lib().tq_join_build(table.data_ptr(), _nbytes(table), _ptr(keys), col(payload), n, cols(filt_cols),
+                               len(filt_cols), preds(ps), len(ps), load_factor, skip, flags, _stream(stream)))
+
+
+def join_probe(table, probe_keys, n, probe_cols=(), ps=(), out_row=None, out_payload=None, capacity=0,
+               out_count=None, agg=None, stream=None):
+    """agg: None, or (state, domain, exprs) for the fused group-by."""
+    A = None
+    if agg is not None:
+        state, domain, es = agg
+        E = exprs(es)
+        A = Agg(state.data_ptr(), domain, ctypes.cast(E, ctypes.POINTER(ExprS)), len(es))
+    _check(lib().tq_join_probe(table.data_ptr(), _ptr(probe_keys), n, cols(probe_cols), len(probe_cols), preds(ps),
+                               len(ps), _ptr(out_row), _ptr(out_payload), capacity, _ptr(out_count),
+                               None if A is None else ctypes.addressof(A), _stream(stream)))
+
+
+def groupby_state_bytes(domain: int, nsum: int) -> int:
+    return lib().tq_groupby_state_bytes(domain, nsum)
+
+
+def groupby_init(state, domain, nsum, stream=None):
+    _check(lib().tq_groupby_init(state.data_ptr(), _nbytes(state), domain, nsum, _stream(stream)))
+
+
+def groupby_agg(state, domain, in_cols, nrows, ps, key: GKey, es, stream=None):
+    _check(lib().tq_groupby_agg(state.data_ptr(), domain, cols(in_cols), len(in_cols), nrows, preds(ps), len(ps),
+                                ctypes.byref(key), exprs(es), len(es), _stream(stream)))
+
+
+def groupby_finalize(state, keys, count, sums, avg, ngroups, stream=None):
+    _check(lib().tq_groupby_finalize(state.data_ptr(), keys.data_ptr(), count.data_ptr(), sums.data_ptr(),
+                                     _ptr(avg), ngroups.data_ptr(), _stream(stream)))
+
+
+def check(obj, stream=None):
+    _check(lib().tq_check(obj.data_ptr(), _stream(stream)))
+
+
+def read_peak(src, sink, stream=None):
+    _check(lib().tq_read_peak(src.data_ptr(), _nbytes(src), sink.data_ptr(), _stream(stream)))
+
+
+def fill(dst, pattern=0, stream=None):
+    _check(lib().tq_fill(dst.data_ptr(), _nbytes(dst), pattern, _stream(stream)))

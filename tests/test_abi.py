@@ -1,0 +1,93 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, sizes buffers as documented, and rejects bad arguments before it
+enqueues anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2508_05029_amd import tq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x100000  # never dereferenced: validation fails first
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(tq_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_declared_function_is_exported():
+    L = tq.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    L = tq.lib()
+    assert tq.version() >= 1
+    for s in (tq.TQ_OK, tq.TQ_EINVAL, tq.TQ_ENOMEM, tq.TQ_EFULL, tq.TQ_EDOMAIN, tq.TQ_EHIP):
+        assert L.tq_strerror(s)
+
+
+def test_buffer_sizes():
+    # 227,600 filtered dimension rows at load factor 0.5 -> 2^19 slots
+    assert tq.join_table_bytes(227_600, 0.5) == 256 + (1 << 19) * 4 + (1 << 19) * 16
+    assert tq.join_table_bytes(0, 0.5) == 256 + 256 + 64 * 16
+    assert tq.join_table_bytes(10, 0.95) == 0  # load factor above 0.9 is refused
+    b = tq.groupby_state_bytes(25, 1)
+    assert b >= 256 + 25 * 2 * 8 and (b - 256) % (25 * 2 * 8) == 0
+    assert tq.groupby_state_bytes(65536, 1) == 256 + 65536 * 2 * 8
+    assert tq.groupby_state_bytes(0, 1) == 0
+    assert tq.hash_partition_scratch_bytes(4096 * 10, 8) >= 10 * 256 * 8
+    assert tq.hash_partition_scratch_bytes(10, 11) == 0
+
+
+def _st(v):
+    return ctypes.c_void_p(v)
+
+
+def test_invalid_arguments_are_rejected_synchronously():
+    L = tq.lib()
+    cols = tq.cols([])
+    # too many columns
+    assert L.tq_filter_project(cols, 9, 10, None, 0, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    assert b"ncol" in L.tq_last_error()
+    # predicate on a column that does not exist
+    c = (tq.Col * 1)(tq.Col(FAKE, tq.TQ_I64))
+    assert L.tq_filter_project(c, 1, 10, tq.preds([(3, 0, 1)]), 1, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    # misaligned column
+    c = (tq.Col * 1)(tq.Col(FAKE + 8, tq.TQ_I64))
+    assert L.tq_filter_project(c, 1, 10, None, 0, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    assert b"aligned" in L.tq_last_error()
+    # bad type
+    c = (tq.Col * 1)(tq.Col(FAKE, 3))
+    assert L.tq_filter_project(c, 1, 10, None, 0, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    # load factor out of range, skip out of range
+    pay = tq.Col(FAKE, tq.TQ_I64)
+    assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.0, 0, 0, None) == tq.TQ_EINVAL
+    assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 40, 0, None) == tq.TQ_EINVAL
+    # a table buffer too small for even 64 slots
+    assert L.tq_join_table_init(FAKE, 100, None) == tq.TQ_EINVAL
+    # group-by state: nsum, domain, size
+    assert L.tq_groupby_init(FAKE, 1 << 20, 10, 7, None) == tq.TQ_EINVAL
+    assert L.tq_groupby_init(FAKE, 1 << 20, 0, 1, None) == tq.TQ_EINVAL
+    assert L.tq_groupby_init(FAKE, 10, 10, 1, None) == tq.TQ_EINVAL
+    # partition fan-out and scratch
+    assert L.tq_hash_partition(FAKE, None, 0, 10, 11, 0, FAKE, None, FAKE, FAKE, 1 << 20, None) == tq.TQ_EINVAL
+    assert L.tq_hash_partition(FAKE, None, 0, 100000, 8, 0, FAKE, None, FAKE, FAKE, 16, None) == tq.TQ_EINVAL
+    # probe: expression factor count
+    e = tq.exprs([[(0, 1, 0)] * 3])
+    e[0].nf = 4
+    agg = tq.Agg(FAKE, 10, ctypes.cast(e, ctypes.POINTER(tq.ExprS)), 1)
+    c = (tq.Col * 1)(tq.Col(FAKE, tq.TQ_I64))
+    assert L.tq_join_probe(FAKE, FAKE, 10, c, 1, None, 0, None, None, 0, None, ctypes.byref(agg), None) == tq.TQ_EINVAL
+    assert L.tq_read_peak(FAKE, 15, FAKE, None) == tq.TQ_EINVAL

@@ -1,0 +1,305 @@
+"""GPU parity: every C-ABI operator against the CPU oracle on the same seeded inputs.
+
+Integers are compared bit for bit; AVG within 1e-12 relative (both sides do
+one IEEE double division, so they normally agree exactly). Where the output
+order is unspecified (compacted rows, pairs, rows inside a partition) the
+outputs are compared as sorted multisets.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2508_05029_amd import pipeline, tq  # noqa: E402
+from paper_2508_05029_amd.datagen import uniform, permutation, zipf  # noqa: E402
+from paper_2508_05029_amd.datagen import workloads as wl  # noqa: E402
+from paper_2508_05029_amd.datagen.workloads import Factor, Pred  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def assert_groups_equal(got, want, avg_of=None):
+    assert got["keys"].tolist() == want["keys"].tolist()
+    assert got["count"].tolist() == want["count"].tolist()
+    assert got["sums"].tolist() == want["sums"].tolist()
+    cols = range(want["avg"].shape[1]) if avg_of is None else avg_of
+    for j in cols:
+        a, b = got["avg"][:, j], want["avg"][:, j]
+        assert np.all(np.abs(a - b) <= 1e-12 * np.abs(b)), (a, b)
+
+
+# ---------------------------------------------------------------- filter + group-by
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 1000, 4097, 100_003, 1_000_000])
+def test_filter_groupby_matches_oracle(n):
+    say(f"filter_groupby n={n}")
+    t = wl.filter_groupby_tables(n)
+    q = wl.FILTER_GROUPBY_QUERY
+    fg = pipeline.FilterGroupBy(q)
+    fg.run(pipeline.to_device(t))
+    got = fg.result()
+    want = oracle.filter_groupby(t, q)
+    assert_groups_equal(got, want, q.avg_of)
+
+
+def test_filter_groupby_is_repeatable_and_accumulates():
+    t = wl.filter_groupby_tables(50_000)
+    q = wl.FILTER_GROUPBY_QUERY
+    fg = pipeline.FilterGroupBy(q)
+    d = pipeline.to_device(t)
+    fg.run(d)
+    a = fg.result()
+    fg.run(d)
+    b = fg.result()
+    assert a["sums"].tolist() == b["sums"].tolist()
+    # two batches into one state equal one pass over both
+    tq.groupby_init(fg.state, fg.domain, fg.nsum)
+    cols = [d[c] for c in fg.names]
+    half = 24_000  # a multiple of 16 rows keeps the second slice 16-byte aligned for every width
+    tq.groupby_agg(fg.state, fg.domain, [c[:half] for c in cols], half, fg.preds, fg.key, fg.exprs)
+    tq.groupby_agg(fg.state, fg.domain, [c[half:] for c in cols], 50_000 - half, fg.preds, fg.key, fg.exprs)
+    out = fg.out
+    tq.groupby_finalize(fg.state, out.keys, out.count, out.sums, out.avg, out.ngroups)
+    c = out.host()
+    assert c["sums"].tolist() == a["sums"].tolist()
+
+
+@pytest.mark.parametrize("domain,skew", [(25, None), (4000, None), (65_536, 1.1), (100_000, None)])
+def test_groupby_lds_modes_match_oracle(domain, skew):
+    """Dense LDS partials, the LDS hot-key hash table, and its global overflow."""
+    say(f"groupby domain={domain} skew={skew}")
+    n = 300_000
+    g = zipf(n, domain, skew, 4, 0) if skew else uniform(n, 0, domain - 1, np.int64, 4, 0)
+    v = uniform(n, -10**12, 10**12, np.int64, 4, 1)
+    w = uniform(n, 0, 100, np.int32, 4, 2)
+    t = {"g": g, "v": v, "w": w}
+    q = wl.FilterGroupByQuery(preds=[Pred("w", 5, 95)], key=wl.GroupKey(("g",), 1, domain),
+                              sums=[(Factor("v"),), (Factor("v"), Factor("w", -1, 7))], avg_of=[0, 1])
+    fg = pipeline.FilterGroupBy(q)
+    fg.run(pipeline.to_device(t))
+    got = fg.result()
+    want = oracle.filter_groupby(t, q)
+    assert_groups_equal(got, want)
+
+
+def test_groupby_key_outside_domain_is_latched():
+    t = {"g": np.array([0, 1, 7, 2], np.int64), "v": np.arange(4, dtype=np.int64)}
+    q = wl.FilterGroupByQuery(preds=[], key=wl.GroupKey(("g",), 1, 4), sums=[(Factor("v"),)], avg_of=[])
+    fg = pipeline.FilterGroupBy(q)
+    fg.run(pipeline.to_device(t))
+    with pytest.raises(tq.TqError) as e:
+        fg.result()
+    assert e.value.status == tq.TQ_EDOMAIN
+
+
+# ---------------------------------------------------------------- filter + project
+
+@pytest.mark.parametrize("n", [0, 7, 64, 1000, 65_537])
+def test_filter_project_matches_oracle(n):
+    rng = np.random.default_rng(n)
+    t = {"a": rng.integers(-50, 50, n).astype(np.int64), "b": rng.integers(0, 256, n).astype(np.uint8),
+         "c": rng.integers(-1000, 1000, n).astype(np.int32)}
+    preds = [Pred("a", -20, 30), Pred("b", 0, 200)]
+    exprs = [(Factor("a"), Factor("c", -1, 100)), (Factor("b", 1, 1), Factor("c"), Factor(None, 1, 3)), (Factor("c"),)]
+    names = ["a", "b", "c"]
+    d = pipeline.to_device(t)
+    out = [torch.empty(max(n, 1), dtype=torch.int64, device=DEV) for _ in exprs]
+    sel = torch.empty(max(n, 1), dtype=torch.int64, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+    tq.filter_project([d[c] for c in names], n, pipeline.plan_preds(names, preds),
+                      pipeline.plan_exprs(names, exprs), out, sel, cnt)
+    m = int(cnt.item())
+    mask = oracle.filter_mask(t, preds)
+    assert m == int(mask.sum())
+    rows = sel[:m].cpu().numpy()
+    order = np.argsort(rows)
+    assert rows[order].tolist() == np.nonzero(mask)[0].tolist()
+    for j, e in enumerate(exprs):
+        want = oracle.project(t, e)[0][mask.astype(bool)]
+        assert out[j][:m].cpu().numpy()[order].tolist() == want.tolist()
+
+
+# ---------------------------------------------------------------- join
+
+def _pairs(build_keys, probe_keys, lf=0.5, unique=False, capacity=None):
+    nb, np_ = len(build_keys), len(probe_keys)
+    bk = torch.from_numpy(np.asarray(build_keys, np.int64)).to(DEV)
+    pk = torch.from_numpy(np.asarray(probe_keys, np.int64)).to(DEV)
+    pay = torch.arange(nb, dtype=torch.int64, device=DEV)
+    table = torch.empty(tq.join_table_bytes(nb, lf), dtype=torch.uint8, device=DEV)
+    tq.join_table_init(table)
+    tq.join_build(table, bk, pay, nb, load_factor=lf, flags=tq.TQ_UNIQUE_KEYS if unique else 0)
+    total, _, _ = oracle.join_pairs(bk.cpu().numpy(), pk.cpu().numpy(), with_pairs=False)
+    cap = max(total, 1) if capacity is None else capacity
+    rows = torch.empty(cap, dtype=torch.int64, device=DEV)
+    bro = torch.empty(cap, dtype=torch.int64, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+    tq.join_probe(table, pk, np_, out_row=rows, out_payload=bro, capacity=cap, out_count=cnt)
+    tq.check(table)
+    m = int(cnt.item())
+    k = min(m, cap)
+    got = sorted(zip(rows[:k].cpu().tolist(), bro[:k].cpu().tolist()))
+    return m, got
+
+
+@pytest.mark.parametrize("lf", [0.25, 0.5, 0.9])
+def test_join_pairs_many_to_many(lf):
+    rng = np.random.default_rng(3)
+    bk, pk = rng.integers(0, 3000, 10_000), rng.integers(-100, 3500, 40_000)
+    m, got = _pairs(bk, pk, lf)
+    total, pr, br = oracle.join_pairs(bk, pk)
+    assert m == total
+    assert got == list(zip(pr.tolist(), br.tolist()))
+
+
+def test_join_pairs_extreme_keys_and_empty_sides():
+    I64_MIN, I64_MAX = -(2 ** 63), 2 ** 63 - 1
+    bk = [I64_MAX, I64_MIN, I64_MIN + 1, -1, 0, 5, 5]
+    pk = [5, -1, I64_MAX, 7, I64_MIN, I64_MIN + 1, 0, 5]
+    m, got = _pairs(bk, pk)
+    total, pr, br = oracle.join_pairs(np.array(bk), np.array(pk))
+    assert m == total and got == list(zip(pr.tolist(), br.tolist()))
+    assert _pairs([], [1, 2, 3])[0] == 0
+    assert _pairs([1, 2, 3], [])[0] == 0
+
+
+def test_join_pairs_capacity_overflow_reports_total():
+    bk = np.arange(100)
+    pk = np.concatenate([np.arange(100)] * 3)
+    m, got = _pairs(bk, pk, capacity=50)
+    assert m == 300 and len(got) == 50
+
+
+def test_join_same_slot_collisions():
+    # keys that share their top hash bits land on the same home slot
+    keys = (np.arange(2000, dtype=np.int64) << 40)
+    m, got = _pairs(keys, keys[::-1].copy(), lf=0.9, unique=True)
+    total, pr, br = oracle.join_pairs(keys, keys[::-1].copy())
+    assert m == total == 2000 and got == list(zip(pr.tolist(), br.tolist()))
+
+
+def test_join_table_too_small_latches_full():
+    table = torch.empty(tq.join_table_bytes(100, 0.5), dtype=torch.uint8, device=DEV)
+    tq.join_table_init(table)
+    keys = torch.arange(10_000, dtype=torch.int64, device=DEV)
+    tq.join_build(table, keys, keys, 10_000, load_factor=0.5)
+    with pytest.raises(tq.TqError) as e:
+        tq.check(table)
+    assert e.value.status == tq.TQ_EFULL
+
+
+@pytest.mark.parametrize("lf,unique", [(0.5, True), (0.25, False), (0.9, True)])
+def test_join_agg_full_size_matches_oracle(lf, unique):
+    say(f"join_agg 1.5M x 6M lf={lf} unique={unique}")
+    dim, fact = wl.join_agg_tables()
+    q = wl.JOIN_AGG_QUERY
+    ja = pipeline.JoinAgg(q, len(dim["key"]), lf, unique=unique)
+    ja.run(pipeline.to_device(dim), pipeline.to_device(fact))
+    got = ja.result()
+    want = oracle.join_agg(dim, fact, q)
+    assert got["join_rows"] == want["join_rows"]
+    assert_groups_equal(got, want, q.avg_of)
+
+
+@pytest.mark.parametrize("nd,nf", [(1, 1), (3, 10), (100, 5), (4097, 20_001)])
+def test_join_agg_small_and_ragged(nd, nf):
+    dim, fact = wl.join_agg_tables(nd, nf, seed=17 + nd)
+    dim["date"][: max(1, nd // 2)] = 800  # make sure some dimension rows pass
+    q = wl.JOIN_AGG_QUERY
+    ja = pipeline.JoinAgg(q, nd, 0.5)
+    ja.run(pipeline.to_device(dim), pipeline.to_device(fact))
+    got = ja.result()
+    want = oracle.join_agg(dim, fact, q)
+    assert got["join_rows"] == want["join_rows"]
+    assert_groups_equal(got, want, q.avg_of)
+
+
+# ---------------------------------------------------------------- hash partition
+
+@pytest.mark.parametrize("n,bits,skip", [(0, 4, 0), (1, 0, 0), (5000, 1, 0), (100_001, 8, 0), (300_000, 10, 0),
+                                         (70_000, 6, 8)])
+def test_hash_partition_matches_oracle(n, bits, skip):
+    say(f"partition n={n} bits={bits} skip={skip}")
+    keys = uniform(n, -(2 ** 62), 2 ** 62, np.int64, 9, 0)
+    p64 = uniform(n, -10**15, 10**15, np.int64, 9, 1)
+    p32 = uniform(n, -10**9, 10**9, np.int32, 9, 2)
+    p8 = uniform(n, 0, 255, np.uint8, 9, 3)
+    d = [torch.from_numpy(a).to(DEV) for a in (keys, p64, p32, p8)]
+    out = [torch.empty(max(n, 1), dtype=t.dtype, device=DEV) for t in d]
+    offs = torch.empty((1 << bits) + 1, dtype=torch.int64, device=DEV)
+    scratch = torch.empty(max(1, tq.hash_partition_scratch_bytes(n, bits)), dtype=torch.uint8, device=DEV)
+    tq.hash_partition(d[0], d[1:], n, bits, skip, out[0], out[1:], offs, scratch)
+    torch.cuda.synchronize()
+    # the oracle partitions by the top bits; with skip the id is taken from the bits below
+    pid = oracle.partition_ids(keys, bits + skip) & ((1 << bits) - 1) if skip else oracle.partition_ids(keys, bits)
+    counts = np.bincount(pid, minlength=1 << bits) if n else np.zeros(1 << bits, np.int64)
+    want_offs = np.concatenate([[0], np.cumsum(counts)])
+    got_offs = offs.cpu().numpy()
+    assert got_offs.tolist() == want_offs.tolist()
+    host = [o[:n].cpu().numpy() for o in out]
+    src = [keys, p64, p32, p8]
+    for p in range(1 << bits):
+        a, b = got_offs[p], got_offs[p + 1]
+        rows = np.nonzero(pid == p)[0]
+        # rows travel together: sort both sides by key then compare every column
+        go = np.lexsort((host[1][a:b], host[0][a:b]))
+        wo = np.lexsort((p64[rows], keys[rows]))
+        for j in range(4):
+            assert host[j][a:b][go].tolist() == src[j][rows][wo].tolist()
+
+
+def test_partition_then_join_equals_unpartitioned():
+    """Join partition by partition (with the table slot bits below the
+    partition bits) and compare with the plain join result."""
+    dim, fact = wl.join_agg_tables(200_000, 800_000, seed=23)
+    q = wl.JOIN_AGG_QUERY
+    want = oracle.join_agg(dim, fact, q)
+    dd, fd = pipeline.to_device(dim), pipeline.to_device(fact)
+    bits = 4
+    nb = 1 << bits
+
+    def part(keys, pay):
+        n = keys.numel()
+        ok = torch.empty_like(keys)
+        op = [torch.empty_like(t) for t in pay]
+        offs = torch.empty(nb + 1, dtype=torch.int64, device=DEV)
+        sc = torch.empty(tq.hash_partition_scratch_bytes(n, bits), dtype=torch.uint8, device=DEV)
+        tq.hash_partition(keys, pay, n, bits, 0, ok, op, offs, sc)
+        return ok, op, offs.cpu().tolist()
+
+    dk, (dg, dt), doff = part(dd["key"], [dd["group"], dd["date"]])
+    fk, (fp, fdc), foff = part(fd["fk"], [fd["price"], fd["disc"]])
+    ja = pipeline.JoinAgg(q, 200_000, 0.5)
+    ja.init_state()
+    for p in range(nb):
+        a, b = doff[p], doff[p + 1]
+        # 16-byte alignment of the slices: copy each partition to fresh buffers
+        dpart = {"key": dk[a:b].clone(), "group": dg[a:b].clone(), "date": dt[a:b].clone()}
+        c, e = foff[p], foff[p + 1]
+        fpart = {"fk": fk[c:e].clone(), "price": fp[c:e].clone(), "disc": fdc[c:e].clone()}
+        ja.build(dpart, skip=bits)
+        ja.probe(fpart, count=False)
+    ja.finalize()
+    got = ja.result()
+    assert_groups_equal(got, want, q.avg_of)
+
+
+# ---------------------------------------------------------------- measurement kernels
+
+def test_read_peak_and_fill():
+    x = torch.empty(1 << 20, dtype=torch.int64, device=DEV)
+    tq.fill(x, 0x01010101)
+    assert int(x[123].item()) == 0x0101010101010101
+    sink = torch.zeros(1, dtype=torch.int64, device=DEV)
+    tq.read_peak(x, sink)
+    torch.cuda.synchronize()
