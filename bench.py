@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the columnar query hot path on one MI355X.
+
+Default workload (join_agg): dimension 1.5M rows (key, group, date), fact 6M
+rows (fk, price, discount). One step = filter the dimension to a 365-day
+window, build the open-addressing table, probe it with every fact row while
+aggregating SUM(price * (100 - discount)) and COUNT per group, and finalize the
+25 groups in key order. Inputs are device resident; four copies rotate so that
+consecutive steps do not find their input in the 256 MiB Infinity Cache.
+
+value = input bytes the query must read (16 B per dimension row + 24 B per fact
+row = 168 MB) / wall time per step, in GB/s. Steps are replayed from HIP graphs
+(several steps per graph) so that host launch cost does not set the pace.
+
+Prints ONE JSON line. Other workloads: --workload filter_groupby | ooc | batched | serving.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def events_ms(pairs):
+    import torch
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in pairs]
+
+
+def cpu_baseline_join_agg(dim, fact, q, budget_s=12.0):
+    """The oracle as it stands, single-threaded, on the full workload."""
+    import oracle
+    times = []
+    res = None
+    while len(times) < 5 and sum(times) < budget_s:
+        t0 = time.perf_counter()
+        res = oracle.join_agg(dim, fact, q)
+        times.append(time.perf_counter() - t0)
+    return res, float(np.median(times)), len(times)
+
+
+def bench_join_agg(args):
+    import torch
+    from paper_2508_05029_amd import pipeline
+    from paper_2508_05029_amd.datagen import workloads as wl
+
+    n_dim, n_fact = 1_500_000, 6_000_000
+    dim, fact = wl.join_agg_tables(n_dim, n_fact)
+    q = wl.JOIN_AGG_QUERY
+    in_bytes = n_dim * 16 + n_fact * 24
+    probe_bytes = n_fact * 24
+    copies = [(pipeline.to_device(dim), pipeline.to_device(fact)) for _ in range(args.copies)]
+    ja = pipeline.JoinAgg(q, n_dim, args.load_factor)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        d, f = copies[i % len(copies)]
+        ja.init_state()
+        ja.build(d)
+        ja.probe(f)
+        ja.finalize()
+
+    # eager warmup, then per-kernel timing with HIP events on the launch stream
+    for i in range(max(args.warmup, 3)):
+        step(i)
+    torch.cuda.synchronize()
+    ev = {k: [] for k in ("init", "build", "probe", "finalize")}
+    for i in range(args.event_steps):
+        d, f = copies[i % len(copies)]
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        marks[0].record(stream)
+        ja.init_state()
+        marks[1].record(stream)
+        ja.build(d)
+        marks[2].record(stream)
+        ja.probe(f)
+        marks[3].record(stream)
+        ja.finalize()
+        marks[4].record(stream)
+        for j, k in enumerate(ev):
+            ev[k].append((marks[j], marks[j + 1]))
+    kern_ms = {k: float(np.mean(events_ms(v))) for k, v in ev.items()}
+
+    # graph: args.graph_steps consecutive steps per replay, rotating the copies
+    gs = args.graph_steps
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        for i in range(gs):
+            step(i)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(gs):
+            step(i)
+    torch.cuda.synchronize()
+    for _ in range(max(1, args.warmup // gs)):
+        graph.replay()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // gs)
+    steps = reps * gs
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / steps
+
+    # timed probe launches inside graph replays are measured by the eager events above;
+    # the result of the last replay is checked against the oracle below
+    got = ja.result()
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        want, t_cpu, runs = cpu_baseline_join_agg(dim, fact, q)
+        parity = (got["keys"].tolist() == want["keys"].tolist() and got["count"].tolist() == want["count"].tolist()
+                  and got["sums"].tolist() == want["sums"].tolist())
+        cpu = {"value": round(in_bytes / t_cpu / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole workload (1.5M x 6M rows), median of {runs} runs of the sort-based C oracle, "
+                         f"{t_cpu:.2f} s per run"}
+    gbs = in_bytes / (ms_step / 1e3) / 1e9
+    probe_gbs = probe_bytes / (kern_ms["probe"] / 1e3) / 1e9
+    line = {
+        "metric": "input GB/s filter-join-aggregate (% of HBM peak)",
+        "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic (seeded generators; stands in for TPC-H/TPC-DS tables)",
+        "config": {"workload": "join_agg: dim 1.5M rows (key perm, group U0..24, date U0..2405), fact 6M rows "
+                               "(fk U over dim keys, price, discount); date window [730,1094]; "
+                               "SUM(price*(100-disc)), COUNT by group",
+                   "input_bytes": in_bytes, "load_factor": args.load_factor, "copies": args.copies,
+                   "graph_steps": gs},
+        "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "rows_per_s": round((n_dim + n_fact) / (ms_step / 1e3), 1),
+        "kernel_ms": {k: round(v, 5) for k, v in kern_ms.items()},
+        "roofline": {"bound": "hbm", "achieved": round(probe_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(probe_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_probe (join probe + fused group-by)", "bytes_per_launch": probe_bytes},
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+    }
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--workload", default="join_agg",
+                    choices=["join_agg", "filter_groupby", "ooc", "batched", "serving"])
+    ap.add_argument("--copies", type=int, default=4)
+    ap.add_argument("--graph-steps", type=int, default=8)
+    ap.add_argument("--event-steps", type=int, default=20)
+    ap.add_argument("--load-factor", type=float, default=0.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    fn = {"join_agg": bench_join_agg}.get(args.workload)
+    if fn is None:
+        from paper_2508_05029_amd import bench_more
+        fn = getattr(bench_more, "bench_" + args.workload)
+    line = fn(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,12 +93,14 @@ typedef struct {
  * per-task computation of Section 3.3.1). For every row of `in` that
  * satisfies all `np` predicates, writes the `ne` expression values to
  * d_out[e][i] and, if d_sel is not NULL, the source row index to d_sel[i],
- * for i < *d_out_rows. Each output must hold nrows values. The order of the
- * output rows is unspecified; d_sel identifies them. *d_out_rows (device) is
- * set by the call. */
+ * for i < *d_out_rows, in ascending row order (a stable compaction). Each
+ * output must hold nrows values. *d_out_rows (device) is set by the call.
+ * d_scratch (device) must hold tq_filter_project_scratch_bytes(nrows) bytes
+ * and must not be shared by calls that overlap. */
+size_t tq_filter_project_scratch_bytes(int64_t nrows);
 tq_status tq_filter_project(const tq_col* in, int32_t ncol, int64_t nrows, const tq_pred* p, int32_t np,
                             const tq_expr* e, int32_t ne, int64_t* const* d_out, int64_t* d_sel,
-                            int64_t* d_out_rows, hipStream_t stream);
+                            int64_t* d_out_rows, void* d_scratch, size_t scratch_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------ hash partition */
 
@@ -120,7 +122,8 @@ tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_
 
 /* An open-addressing hash table (linear probing) for the build side of an
  * equi-join (the Adaptive Join of Section 3.2). Layout: a 256-byte header, a
- * 32-bit tag per slot (0 = empty) and a 16-byte {key, payload} slot array.
+ * 16 KiB area of per-workgroup partial counts, a 32-bit tag per slot
+ * (0 = empty) and a 16-byte {key, payload} slot array.
  * Any int64 key is allowed; duplicate build keys are kept (many-to-many).
  * tq_join_table_bytes gives the size for at most n_build_max rows at the given
  * load factor (0 < load_factor <= 0.9). The capacity actually used by a build
@@ -155,12 +158,15 @@ typedef struct {
 /* Probe: for every probe row r < n that satisfies the optional predicates over
  * `cols`, find every build slot with key == d_probe_keys[r].
  *   agg == NULL  write pairs (r, payload) to d_out_probe_row / d_out_payload
- *                (order unspecified, at most `capacity`); *d_out_count gets
+ *                in ascending probe-row order (the matches of one row in
+ *                slot order), at most `capacity` of them; *d_out_count gets
  *                the total match count, which may exceed capacity (then the
  *                pairs past `capacity` are dropped; the caller compares).
- *   agg != NULL  aggregate the matches into agg->d_state instead; the pair
- *                outputs may be NULL and *d_out_count (if not NULL) gets the
- *                match count. */
+ *                Uses the table's partial-count area: materialising probes
+ *                of one table must not overlap.
+ *   agg != NULL  aggregate the matches into agg->d_state instead (the
+ *                state's COUNT column counts them); the pair outputs and
+ *                d_out_count must be NULL. */
 tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_t n, const tq_col* cols,
                         int32_t ncol, const tq_pred* p, int32_t np, int64_t* d_out_probe_row,
                         int64_t* d_out_payload, int64_t capacity, int64_t* d_out_count, const tq_agg* agg,
@@ -170,7 +176,10 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
 
 /* Group-by state for keys in [0, domain) with COUNT and `nsum` int64 SUMs
  * (the aggregations of Section 2). It accumulates across any number of
- * tq_groupby_agg / fused-probe calls (batches, partitions, requests). */
+ * tq_groupby_agg / fused-probe calls (batches, partitions, requests). Calls
+ * that update one state must not overlap (issue them on one stream). Small
+ * domains (domain * (1 + nsum) <= 1024) keep one private partial row per
+ * workgroup, folded by tq_groupby_finalize; larger ones one shared table. */
 size_t tq_groupby_state_bytes(int64_t domain, int32_t nsum);
 tq_status tq_groupby_init(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream);
 
@@ -196,9 +205,11 @@ tq_status tq_check(const void* d_obj, hipStream_t stream);
 
 /* ------------------------------------------------------- measurement kernels */
 
-/* Read `bytes` (multiple of 16) and write one checksum to *d_sink: the
- * streaming-read ceiling of the device. */
-tq_status tq_read_peak(const void* d_src, size_t bytes, int64_t* d_sink, hipStream_t stream);
+/* Read `bytes` (multiple of 16) and write one partial checksum per workgroup
+ * to d_partial (tq_read_peak_scratch_bytes() bytes): the streaming-read
+ * ceiling of the device. */
+size_t tq_read_peak_scratch_bytes(void);
+tq_status tq_read_peak(const void* d_src, size_t bytes, int64_t* d_partial, hipStream_t stream);
 /* Write `bytes` (multiple of 16) of a pattern; used to evict caches between timed repetitions. */
 tq_status tq_fill(void* d_dst, size_t bytes, uint32_t pattern, hipStream_t stream);
 

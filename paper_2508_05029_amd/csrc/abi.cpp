@@ -67,7 +67,7 @@ tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p
   P->np = np;
   for (int j = 0; j < np; j++) {
     if (p[j].col < 0 || p[j].col >= ncol) return fail(TQ_EINVAL, "predicate %d: column %d out of range", j, p[j].col);
-    P->pred[j].col = p[j].col;
+    P->pred[j].mask = 1u << p[j].col;
     P->pred[j].lo = p[j].lo;
     P->pred[j].hi = p[j].hi;
   }
@@ -78,7 +78,7 @@ tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p
     for (int f = 0; f < e[j].nf; f++) {
       const tq_factor& F = e[j].f[f];
       if (F.col < -1 || F.col >= ncol) return fail(TQ_EINVAL, "expression %d factor %d: column %d", j, f, F.col);
-      P->expr[j].f[f].col = F.col;
+      P->expr[j].f[f].mask = F.col < 0 ? 0u : 1u << F.col;
       P->expr[j].f[f].sign = F.sign;
       P->expr[j].f[f].add = F.add;
     }
@@ -88,8 +88,8 @@ tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p
     for (int c = 0; c < key->ncol; c++)
       if (key->col[c] < 0 || key->col[c] >= ncol) return fail(TQ_EINVAL, "group key column %d", key->col[c]);
     P->key_ncol = key->ncol;
-    P->key_col[0] = key->col[0];
-    P->key_col[1] = key->ncol == 2 ? key->col[1] : 0;
+    P->key_mask[0] = 1u << key->col[0];
+    P->key_mask[1] = key->ncol == 2 ? 1u << key->col[1] : 0u;
     P->key_mult = key->mult;
   }
   return TQ_OK;

@@ -1,4 +1,14 @@
 // Shared device and host definitions of libtq (gfx950, wave64).
+//
+// Design rules that the kernels follow on MI355X:
+//   * no contended device-scope atomics and no __threadfence on hot paths:
+//     a device-scope atomic on one address serialises across the 8 XCDs and a
+//     release fence writes back the XCD's L2; per-workgroup partials plus a
+//     scan or a fold in the next kernel take their place
+//   * LDS atomics go through __shared__-typed pointers (ds_* instructions,
+//     never flat atomics)
+//   * the kernels are instantiated for the number of columns a query reads
+//     (NC), so that the loaded rows stay in registers
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,11 +29,22 @@ tq_status fail(tq_status s, const char* fmt, ...);
 tq_status hip_fail(hipError_t e, const char* what);
 int device_cu_count();
 
-#define TQ_HIP(call)                                   \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
+#define TQ_HIP(call)                                        \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
     if (e_ != hipSuccess) return ::tq::hip_fail(e_, #call); \
   } while (0)
+
+// Smallest supported column-count bucket >= ncol.
+inline int nc_bucket(int ncol) { return ncol <= 1 ? 1 : ncol <= 2 ? 2 : ncol <= 4 ? 4 : 8; }
+
+#define TQ_DISPATCH_NC(ncol, NCV, ...)                  \
+  switch (::tq::nc_bucket(ncol)) {                      \
+    case 1: { constexpr int NCV = 1; __VA_ARGS__; break; } \
+    case 2: { constexpr int NCV = 2; __VA_ARGS__; break; } \
+    case 4: { constexpr int NCV = 4; __VA_ARGS__; break; } \
+    default: { constexpr int NCV = 8; __VA_ARGS__; break; } \
+  }
 
 // ------------------------------------------------------- plan descriptors
 // Passed to kernels by value. Columns widen to int64.
@@ -33,13 +54,15 @@ struct DCol {
   int32_t w;  // byte width 1, 4 or 8
 };
 
+// Columns are referenced through one-bit masks (bit c = plan column c; 0 = the
+// constant 0), which the kernels resolve with a short chain of selects.
 struct DPred {
-  int32_t col;
+  uint32_t mask;
   int64_t lo, hi;
 };
 
 struct DFactor {
-  int32_t col;  // -1: constant
+  uint32_t mask;  // 0: the factor is the constant `add`
   int64_t sign;
   int64_t add;
 };
@@ -57,7 +80,7 @@ struct RowPlan {
   DExpr expr[TQ_MAX_SUMS];
   int32_t ne;
   int32_t key_ncol;  // group key (0 when unused)
-  int32_t key_col[2];
+  uint32_t key_mask[2];
   int64_t key_mult;
 };
 
@@ -67,9 +90,10 @@ tq_status make_plan(RowPlan* plan, const tq_col* in, int32_t ncol, const tq_pred
 
 // ------------------------------------------------------- object headers
 
-constexpr uint32_t kTableMagic = 0x54514A54u;  // "TJQT"
-constexpr uint32_t kStateMagic = 0x54514753u;  // "SGQT"
+constexpr uint32_t kTableMagic = 0x54514A54u;
+constexpr uint32_t kStateMagic = 0x54514753u;
 constexpr size_t kHeaderBytes = 256;
+constexpr int kMaxPartBlocks = 2048;  // per-block partial counts kept in a table
 
 struct TableHeader {
   uint32_t magic;
@@ -78,8 +102,7 @@ struct TableHeader {
   int32_t log2cap;   // slots used by the current build
   int32_t skip;      // high hash bits ignored by the slot index
   int64_t n;         // rows inserted by the current build
-  int64_t n_acc;     // counting accumulator (self-resetting)
-  uint32_t ticket;   // last-block ticket (self-resetting)
+  int32_t nblk;      // blocks that wrote partial counts
   uint32_t flags;
   double lf;
 };
@@ -90,17 +113,30 @@ struct StateHeader {
   int32_t err;
   int64_t domain;
   int32_t nsum;
-  int32_t replicas;  // power of two; replica r of entry e at data[r * domain * stride + e]
-  int64_t matches;   // unused by the kernels; reserved
+  int32_t rows;  // partial rows: > 1 for block-private partials, 1 for one shared table
+  int64_t used;  // private rows written since init (the largest grid of an aggregating launch)
 };
 static_assert(sizeof(StateHeader) <= kHeaderBytes, "header");
 
+// Table: header | int64 partial[kMaxPartBlocks] | uint16 tag[cap_max] | {key, payload}[cap_max].
+// Slots form buckets of kBucket; the 16-bit tags of one bucket are one 16-byte
+// word group, read with a single load.
+constexpr int kBucket = 8;
+constexpr int kLog2Bucket = 3;
+
+__host__ __device__ inline size_t table_tag_bytes(int64_t cap_max) {
+  return ((size_t)cap_max * 2 + 255) & ~(size_t)255;
+}
+__host__ __device__ inline int64_t* table_partials(void* t) {
+  return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(t) + kHeaderBytes);
+}
+// Tag words: two 16-bit tags per uint32, bucket b = words [4b, 4b + 4).
 __host__ __device__ inline uint32_t* table_tags(void* t) {
-  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t) + kHeaderBytes);
+  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(t) + kHeaderBytes + kMaxPartBlocks * 8);
 }
 __host__ __device__ inline int64_t* table_slots(void* t, int64_t cap_max) {
-  size_t tag_bytes = ((size_t)cap_max * 4 + 255) & ~(size_t)255;
-  return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(t) + kHeaderBytes + tag_bytes);
+  return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(t) + kHeaderBytes + kMaxPartBlocks * 8 +
+                                    table_tag_bytes(cap_max));
 }
 __host__ __device__ inline int64_t* state_data(void* s) {
   return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(s) + kHeaderBytes);
@@ -112,14 +148,15 @@ __device__ __forceinline__ void latch_error(int32_t* err, int32_t code) { atomic
 
 __device__ __forceinline__ uint64_t mulhash(int64_t k) { return (uint64_t)k * kFib; }
 
-// Tag of a hash: its low 32 bits, with 0 reserved for "empty".
+// Tag of a hash: its low 16 bits, with 0 reserved for "empty".
 __device__ __forceinline__ uint32_t hash_tag(uint64_t h) {
-  uint32_t t = (uint32_t)h;
+  uint32_t t = (uint32_t)h & 0xffffu;
   return t ? t : 1u;
 }
 
-__device__ __forceinline__ uint64_t slot_of(uint64_t h, int skip, int log2cap) {
-  return (h << skip) >> (64 - log2cap);
+// Home bucket: the high bits of the hash below the `skip` partition bits.
+__device__ __forceinline__ uint64_t bucket_of(uint64_t h, int skip, int log2buckets) {
+  return (h << skip) >> (64 - log2buckets);
 }
 
 template <typename T>
@@ -137,62 +174,103 @@ __device__ __forceinline__ int64_t load1(const DCol& c, int64_t r) {
 typedef long long v2i64 __attribute__((ext_vector_type(2)));
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 
-// kRows consecutive values starting at row r0 (a multiple of kRows); `full`
-// means all kRows rows exist. Column pointers are 16-byte aligned.
-__device__ __forceinline__ void load4(const DCol& c, int64_t r0, bool full, int64_t n, int64_t (&v)[kRows]) {
+// R (2 or 4) consecutive values starting at row r0 (a multiple of R); `full`
+// means all R rows exist. Column pointers are 16-byte aligned.
+template <int R = kRows>
+__device__ __forceinline__ void load4(const DCol& c, int64_t r0, bool full, int64_t n, int64_t (&v)[R]) {
+  static_assert(R == 2 || R == 4, "rows per thread");
   if (full) {
     if (c.w == 8) {
       const v2i64* q = reinterpret_cast<const v2i64*>(static_cast<const int64_t*>(c.p) + r0);
-      v2i64 a = ntload(q), b = ntload(q + 1);
-      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+#pragma unroll
+      for (int h = 0; h < R / 2; h++) {
+        v2i64 a = ntload(q + h);
+        v[2 * h] = a.x;
+        v[2 * h + 1] = a.y;
+      }
     } else if (c.w == 4) {
-      v4i32 a = ntload(reinterpret_cast<const v4i32*>(static_cast<const int32_t*>(c.p) + r0));
-      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      if (R == 4) {
+        v4i32 a = ntload(reinterpret_cast<const v4i32*>(static_cast<const int32_t*>(c.p) + r0));
+        v[0] = a.x; v[1] = a.y; v[R > 2 ? 2 : 0] = a.z; v[R > 2 ? 3 : 1] = a.w;
+      } else {
+        uint64_t a = ntload(reinterpret_cast<const uint64_t*>(static_cast<const int32_t*>(c.p) + r0));
+        v[0] = (int32_t)(uint32_t)a;
+        v[1] = (int32_t)(uint32_t)(a >> 32);
+      }
     } else {
-      uint32_t a = ntload(reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(c.p) + r0));
-      v[0] = a & 0xff; v[1] = (a >> 8) & 0xff; v[2] = (a >> 16) & 0xff; v[3] = a >> 24;
+      if (R == 4) {
+        uint32_t a = ntload(reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(c.p) + r0));
+#pragma unroll
+        for (int i = 0; i < R; i++) v[i] = (a >> (8 * i)) & 0xff;
+      } else {
+        uint32_t a = ntload(reinterpret_cast<const uint16_t*>(static_cast<const uint8_t*>(c.p) + r0));
+        v[0] = a & 0xff;
+        v[1] = (a >> 8) & 0xff;
+      }
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < kRows; i++) v[i] = (r0 + i < n) ? load1(c, r0 + i) : 0;
+    for (int i = 0; i < R; i++) v[i] = (r0 + i < n) ? load1(c, r0 + i) : 0;
   }
 }
 
-// Value of column `idx` among the loaded ones (idx is uniform).
-__device__ __forceinline__ int64_t pick(const int64_t (&vals)[TQ_MAX_COLS], int idx) {
-  int64_t r = vals[0];
+// The rows r0..r0+R-1 of the first NC plan columns: v[c][i].
+template <int NC, int R = kRows>
+__device__ __forceinline__ void load_rows(const RowPlan& P, int64_t r0, bool full, int64_t n, int64_t (&v)[NC][R]) {
 #pragma unroll
-  for (int i = 1; i < TQ_MAX_COLS; i++) r = (idx == i) ? vals[i] : r;
+  for (int c = 0; c < NC; c++) {
+    if (c < P.ncol) load4<R>(P.col[c], r0, full, n, v[c]);
+    else {
+#pragma unroll
+      for (int i = 0; i < R; i++) v[c][i] = 0;
+    }
+  }
+}
+
+// Value of the column selected by `mask` (one bit, uniform) for row i; 0 if mask is 0.
+template <int NC, int R>
+__device__ __forceinline__ int64_t pick(const int64_t (&v)[NC][R], int i, uint32_t mask) {
+  int64_t r = 0;
+#pragma unroll
+  for (int c = 0; c < NC; c++) r = ((mask >> c) & 1u) ? v[c][i] : r;
   return r;
 }
 
-__device__ __forceinline__ bool eval_preds(const RowPlan& P, const int64_t (&vals)[TQ_MAX_COLS]) {
+template <int NC, int R>
+__device__ __forceinline__ bool eval_preds(const RowPlan& P, const int64_t (&v)[NC][R], int i) {
   bool ok = true;
-  for (int j = 0; j < P.np; j++) {
-    int64_t x = pick(vals, P.pred[j].col);
-    ok = ok && (x >= P.pred[j].lo) && (x <= P.pred[j].hi);
+#pragma unroll
+  for (int j = 0; j < TQ_MAX_PREDS; j++) {
+    if (j < P.np) {
+      int64_t x = pick<NC, R>(v, i, P.pred[j].mask);
+      ok = ok && (x >= P.pred[j].lo) && (x <= P.pred[j].hi);
+    }
   }
   return ok;
 }
 
-__device__ __forceinline__ int64_t eval_expr(const DExpr& E, const int64_t (&vals)[TQ_MAX_COLS]) {
+template <int NC, int R>
+__device__ __forceinline__ int64_t eval_expr(const DExpr& E, const int64_t (&v)[NC][R], int i) {
   uint64_t acc = 1;
-  for (int f = 0; f < E.nf; f++) {
-    int64_t x = E.f[f].col < 0 ? 0 : pick(vals, E.f[f].col);
-    uint64_t fac = (uint64_t)E.f[f].sign * (uint64_t)x + (uint64_t)E.f[f].add;
-    acc = f == 0 ? fac : acc * fac;
+#pragma unroll
+  for (int f = 0; f < 3; f++) {
+    if (f < E.nf) {
+      int64_t x = pick<NC, R>(v, i, E.f[f].mask);
+      uint64_t fac = (uint64_t)E.f[f].sign * (uint64_t)x + (uint64_t)E.f[f].add;
+      acc = f == 0 ? fac : acc * fac;
+    }
   }
   return (int64_t)acc;
 }
 
-__device__ __forceinline__ int64_t eval_key(const RowPlan& P, const int64_t (&vals)[TQ_MAX_COLS]) {
-  int64_t k = pick(vals, P.key_col[0]);
-  if (P.key_ncol == 2) k = (int64_t)((uint64_t)k * (uint64_t)P.key_mult + (uint64_t)pick(vals, P.key_col[1]));
+template <int NC, int R>
+__device__ __forceinline__ int64_t eval_key(const RowPlan& P, const int64_t (&v)[NC][R], int i) {
+  int64_t k = pick<NC, R>(v, i, P.key_mask[0]);
+  if (P.key_ncol == 2) k = (int64_t)((uint64_t)k * (uint64_t)P.key_mult + (uint64_t)pick<NC, R>(v, i, P.key_mask[1]));
   return k;
 }
 
-// Inclusive prefix sum over the wave of a 32-bit value; returns the exclusive
-// prefix and sets *total to the wave sum.
+// Exclusive prefix over the wave of a 32-bit value; *total gets the wave sum.
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
   int lane = __lane_id();
   uint32_t s = x;
@@ -203,6 +281,35 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) 
   }
   *total = __shfl(s, kWave - 1, kWave);
   return s - x;
+}
+
+// Block-wide exclusive scan of one int64 per thread (blockDim a multiple of 64,
+// at most 1024); returns the block total. Contains two barriers.
+__device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t* excl, int64_t* wave_sums) {
+  const int lane = __lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  int64_t s = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int64_t y = __shfl_up(s, d, kWave);
+    if (lane >= d) s += y;
+  }
+  if (lane == kWave - 1) wave_sums[wid] = s;
+  __syncthreads();
+  int64_t off = 0, total = 0;
+  for (int w = 0; w < nw; w++) {
+    int64_t t = wave_sums[w];
+    off += w < wid ? t : 0;
+    total += t;
+  }
+  __syncthreads();
+  *excl = off + s - x;
+  return total;
+}
+
+// Block-wide sum of one int64 per thread, result valid in every thread.
+__device__ __forceinline__ int64_t block_sum(int64_t x, int64_t* wave_sums) {
+  int64_t e;
+  return block_excl_scan(x, &e, wave_sums);
 }
 
 }  // namespace tq

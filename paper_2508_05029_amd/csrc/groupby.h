@@ -1,48 +1,51 @@
-// Per-workgroup group-by partials in LDS, flushed to a replicated global state.
+// Group-by partials: per-workgroup in LDS, then folded into the global state.
 //
-// Three modes, chosen on the host from the key domain and the entry width:
+// LDS modes (chosen on the host from the key domain and the entry width):
 //   kDense   the whole domain fits in LDS: direct-indexed int64 partials
 //   kHash    an LDS open-addressing table of hot keys (Zipf-skewed groups stay
-//            on chip); rows whose key finds no LDS slot within a few probes go
-//            straight to global atomics
-//   kGlobal  no LDS; every row is a global atomic
-// A global entry (key k, value j) lives at data[r * domain * stride + k * stride + j]
-// for replica r = blockIdx.x mod replicas; finalization sums the replicas.
-// Value 0 of every entry is COUNT, values 1..nsum are the SUMs.
+//            on chip); a row whose key finds no LDS slot within a few probes
+//            goes straight to a global atomic
+// Global layouts of the state data (entry e = key * stride + j, value 0 is
+// COUNT, values 1..nsum the SUMs):
+//   rows = kAggRows  small domains: one private row per workgroup slot,
+//                    data[b * entries + e]; workgroup b adds its LDS partials
+//                    to row b with plain loads and stores (calls on one state
+//                    are stream ordered, so rows are never written
+//                    concurrently) and finalization folds the rows
+//   rows = 1         large domains: one shared table updated with atomics,
+//                    whose addresses are spread over the whole domain
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 
 namespace tq {
 
-enum AggMode { kDense = 0, kHash = 1, kGlobal = 2 };
+enum AggMode { kDense = 0, kHash = 1 };
 
 constexpr int kLdsAggBytes = 32 * 1024;
 constexpr int kHashProbes = 8;
+constexpr int kAggRows = 1024;            // grid cap of the aggregating kernels
+constexpr int kPrivateRowsMaxEntries = 1024;
+constexpr int kAggBlock = 512;            // threads per aggregating workgroup
+constexpr int kAggBlocksPerCU = 3;
 
 struct AggTarget {
   const StateHeader* hdr;
-  int64_t* data;    // global replicas
-  int32_t* err;     // latched error of the state
+  int64_t* data;
+  int32_t* err;
   int64_t domain;
   int32_t stride;   // 1 + nsum
-  int32_t replicas;
+  int32_t rows;     // kAggRows or 1
   int32_t log2hcap; // kHash: LDS slots = 1 << log2hcap
 };
 
-// The launch parameters must describe the state the buffer was initialised
-// with; otherwise the kernel writes nothing (tq_check then reports the error).
-__device__ __forceinline__ bool state_matches(const AggTarget& T) {
-  const StateHeader* h = T.hdr;
-  if (h->magic != kStateMagic) return false;
-  if (h->domain != T.domain || h->nsum != T.stride - 1 || h->replicas != T.replicas) {
-    if (threadIdx.x == 0) latch_error(T.err, TQ_EINVAL);
-    return false;
-  }
-  return true;
+inline int state_rows(int64_t domain, int stride) {
+  return domain * stride <= kPrivateRowsMaxEntries ? kAggRows : 1;
 }
 
-// Host: pick the mode and the dynamic LDS size for a state.
+// Host: pick the LDS mode and its dynamic LDS size.
 inline AggMode agg_mode(int64_t domain, int stride, int* log2hcap, size_t* lds_bytes) {
   if (domain * stride * 8 <= kLdsAggBytes) {
     *log2hcap = 0;
@@ -50,35 +53,39 @@ inline AggMode agg_mode(int64_t domain, int stride, int* log2hcap, size_t* lds_b
     return kDense;
   }
   int per_slot = 4 + stride * 8;
-  int l = 0;
+  int l = 6;
   while ((size_t)(2 << l) * per_slot <= (size_t)kLdsAggBytes && l < 14) l++;
-  if (l >= 6) {
-    *log2hcap = l;
-    *lds_bytes = ((size_t)(1 << l) * 4 + 15) / 16 * 16 + (size_t)(1 << l) * stride * 8;
-    return kHash;
-  }
-  *log2hcap = 0;
-  *lds_bytes = 0;
-  return kGlobal;
+  *log2hcap = l;
+  *lds_bytes = ((size_t)(1 << l) * 4 + 15) / 16 * 16 + (size_t)(1 << l) * stride * 8;
+  return kHash;
 }
 
-inline int choose_replicas(int64_t domain, int stride) {
-  int64_t e = domain * stride;
-  int r = 1;
-  while (r < 32 && (int64_t)r * 2 * e <= 16384) r *= 2;
-  return r;
+// The launch must describe the state the buffer was initialised with;
+// otherwise the kernel writes nothing and latches TQ_EINVAL.
+__device__ __forceinline__ bool state_matches(const AggTarget& T) {
+  const StateHeader* h = T.hdr;
+  if (h->magic != kStateMagic) return false;
+  if (h->domain != T.domain || h->nsum != T.stride - 1 || h->rows != T.rows) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) latch_error(T.err, TQ_EINVAL);
+    return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ void global_add(unsigned long long* p, int64_t v) {
+  atomicAdd(p, (unsigned long long)v);
 }
 
 template <int MODE>
 struct LdsAgg {
-  int64_t* vals;   // kDense: [domain][stride]; kHash: [hcap][stride]
-  uint32_t* keys;  // kHash: key + 1, 0 = empty
+  int64_t* vals;   // LDS. kDense: [domain][stride]; kHash: [hcap][stride]
+  uint32_t* keys;  // LDS. kHash: key + 1, 0 = empty
 
   __device__ void init(const AggTarget& T, char* smem) {
     if (MODE == kDense) {
       vals = reinterpret_cast<int64_t*>(smem);
-      for (int64_t i = threadIdx.x; i < T.domain * T.stride; i += blockDim.x) vals[i] = 0;
-    } else if (MODE == kHash) {
+      for (int i = threadIdx.x; i < T.domain * T.stride; i += blockDim.x) vals[i] = 0;
+    } else {
       int hcap = 1 << T.log2hcap;
       keys = reinterpret_cast<uint32_t*>(smem);
       vals = reinterpret_cast<int64_t*>(smem + (((size_t)hcap * 4 + 15) / 16 * 16));
@@ -87,62 +94,117 @@ struct LdsAgg {
     }
   }
 
-  __device__ __forceinline__ int64_t* global_entry(const AggTarget& T, int64_t key) const {
-    int r = blockIdx.x & (T.replicas - 1);
-    return T.data + (int64_t)r * T.domain * T.stride + key * T.stride;
-  }
-
-  // Adds COUNT 1 and the nsum values v[0..nsum) to group `key`.
-  __device__ __forceinline__ void add(const AggTarget& T, int64_t key, const int64_t (&v)[TQ_MAX_SUMS], int nsum) {
+  // COUNT += 1 and SUM_j += v[j] for group `key` (j < nsum <= NE).
+  template <int NE>
+  __device__ __forceinline__ void add(const AggTarget& T, int64_t key, const int64_t (&v)[NE], int nsum) {
     if ((uint64_t)key >= (uint64_t)T.domain) {
       latch_error(T.err, TQ_EDOMAIN);
       return;
     }
-    int64_t* dst = nullptr;
     if (MODE == kDense) {
-      dst = vals + key * T.stride;
-    } else if (MODE == kHash) {
+      unsigned long long* d = reinterpret_cast<unsigned long long*>(vals + key * T.stride);
+      atomicAdd(d, 1ull);
+#pragma unroll
+      for (int j = 0; j < NE; j++)
+        if (j < nsum) atomicAdd(d + 1 + j, (unsigned long long)v[j]);
+    } else {
       uint32_t k1 = (uint32_t)key + 1u;
       uint32_t mask = (1u << T.log2hcap) - 1u;
       uint32_t s = ((uint32_t)key * 0x9E3779B1u) >> (32 - T.log2hcap);
+      int found = -1;
       for (int i = 0; i < kHashProbes; i++) {
         uint32_t cur = keys[s];
-        if (cur == 0) cur = atomicCAS(&keys[s], 0u, k1), cur = cur == 0 ? k1 : cur;
+        if (cur == 0) {
+          uint32_t prev = atomicCAS(&keys[s], 0u, k1);
+          cur = prev == 0 ? k1 : prev;
+        }
         if (cur == k1) {
-          dst = vals + (int64_t)s * T.stride;
+          found = (int)s;
           break;
         }
         s = (s + 1) & mask;
       }
-    }
-    if (dst == nullptr) dst = global_entry(T, key);  // kGlobal, or no LDS slot found
-    atomicAdd(reinterpret_cast<unsigned long long*>(dst), 1ull);
+      if (found >= 0) {
+        unsigned long long* d = reinterpret_cast<unsigned long long*>(vals + (int64_t)found * T.stride);
+        atomicAdd(d, 1ull);
 #pragma unroll
-    for (int j = 0; j < TQ_MAX_SUMS; j++)
-      if (j < nsum) atomicAdd(reinterpret_cast<unsigned long long*>(dst + 1 + j), (unsigned long long)v[j]);
+        for (int j = 0; j < NE; j++)
+          if (j < nsum) atomicAdd(d + 1 + j, (unsigned long long)v[j]);
+      } else {
+        unsigned long long* g = reinterpret_cast<unsigned long long*>(T.data + key * T.stride);
+        global_add(g, 1);
+#pragma unroll
+        for (int j = 0; j < NE; j++)
+          if (j < nsum) global_add(g + 1 + j, v[j]);
+      }
+    }
   }
 
-  // Adds the LDS partials of this workgroup to the global state.
+  // Folds this workgroup's LDS partials into the global state.
   __device__ void flush(const AggTarget& T) {
     __syncthreads();
     if (MODE == kDense) {
-      for (int64_t k = threadIdx.x; k < T.domain; k += blockDim.x) {
-        const int64_t* src = vals + k * T.stride;
-        if (src[0] == 0) continue;
-        int64_t* dst = global_entry(T, k);
-        for (int j = 0; j < T.stride; j++) atomicAdd(reinterpret_cast<unsigned long long*>(dst + j), (unsigned long long)src[j]);
+      const int64_t entries = T.domain * T.stride;
+      if (T.rows > 1) {
+        int64_t* row = T.data + (int64_t)blockIdx.x * entries;
+        for (int64_t e = threadIdx.x; e < entries; e += blockDim.x) row[e] += vals[e];
+        // calls on one state are stream ordered, so one writer suffices
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          StateHeader* h = const_cast<StateHeader*>(T.hdr);
+          if (h->used < (int64_t)gridDim.x) h->used = gridDim.x;
+        }
+      } else {
+        for (int64_t k = threadIdx.x; k < T.domain; k += blockDim.x) {
+          const int64_t* src = vals + k * T.stride;
+          if (src[0] == 0) continue;
+          unsigned long long* g = reinterpret_cast<unsigned long long*>(T.data + k * T.stride);
+          for (int j = 0; j < T.stride; j++) global_add(g + j, src[j]);
+        }
       }
-    } else if (MODE == kHash) {
+    } else {
       int hcap = 1 << T.log2hcap;
       for (int s = threadIdx.x; s < hcap; s += blockDim.x) {
         uint32_t k1 = keys[s];
         if (k1 == 0) continue;
         const int64_t* src = vals + (int64_t)s * T.stride;
-        int64_t* dst = global_entry(T, (int64_t)(k1 - 1));
-        for (int j = 0; j < T.stride; j++) atomicAdd(reinterpret_cast<unsigned long long*>(dst + j), (unsigned long long)src[j]);
+        unsigned long long* g = reinterpret_cast<unsigned long long*>(T.data + (int64_t)(k1 - 1) * T.stride);
+        for (int j = 0; j < T.stride; j++) global_add(g + j, src[j]);
       }
     }
   }
 };
+
+tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T, AggMode* mode, size_t* lds);
+int agg_grid(int64_t n);
+
+// Smallest supported sum-count bucket >= ne (the aggregating kernels are
+// instantiated per bucket so that only live sums occupy registers).
+inline int ne_bucket(int ne) { return ne <= 1 ? 1 : ne <= 2 ? 2 : 6; }
+
+#define TQ_DISPATCH_AGG(mode, ncol, ne, MODEV, NCV, NEV, ...)                           \
+  do {                                                                                  \
+    auto run_ = [&](auto mode_c, auto nc_c, auto ne_c) {                                \
+      constexpr int MODEV = decltype(mode_c)::value;                                    \
+      constexpr int NCV = decltype(nc_c)::value;                                        \
+      constexpr int NEV = decltype(ne_c)::value;                                        \
+      __VA_ARGS__;                                                                      \
+    };                                                                                  \
+    auto ne_ = [&](auto m_c, auto n_c) {                                                \
+      switch (::tq::ne_bucket(ne)) {                                                    \
+        case 1: run_(m_c, n_c, std::integral_constant<int, 1>{}); break;                \
+        case 2: run_(m_c, n_c, std::integral_constant<int, 2>{}); break;                \
+        default: run_(m_c, n_c, std::integral_constant<int, 6>{}); break;               \
+      }                                                                                 \
+    };                                                                                  \
+    auto nc_ = [&](auto m_c) {                                                          \
+      switch (::tq::nc_bucket(ncol)) {                                                  \
+        case 1: case 2: ne_(m_c, std::integral_constant<int, 2>{}); break;              \
+        case 4: ne_(m_c, std::integral_constant<int, 4>{}); break;                      \
+        default: ne_(m_c, std::integral_constant<int, 8>{}); break;                     \
+      }                                                                                 \
+    };                                                                                  \
+    if ((mode) == ::tq::kDense) nc_(std::integral_constant<int, ::tq::kDense>{});       \
+    else nc_(std::integral_constant<int, ::tq::kHash>{});                               \
+  } while (0)
 
 }  // namespace tq

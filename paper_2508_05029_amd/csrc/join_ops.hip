@@ -1,12 +1,20 @@
 // Open-addressing hash join: build (with the dimension filter fused in) and
-// probe (materialising pairs, or aggregating matches in LDS).
+// probe (aggregating matches in LDS, or materialising pairs in row order).
 //
-// Table layout: 256-byte header | uint32 tag[cap_max] | {int64 key, int64 payload}[cap_max].
-// A slot is empty iff its tag is 0; the tag is the low 32 bits of the hash
-// (0 mapped to 1). A probe walks tags, which stay resident in L2 (4 bytes per
-// slot), and reads the 16-byte slot only when the tag matches, so most misses
-// never touch the slot array.
+// Table layout: 256-byte header | int64 partial[2048] | uint16 tag[cap_max] |
+// {int64 key, int64 payload}[cap_max]. Open addressing with linear probing over
+// buckets of 8 slots: a key's home bucket is taken from the high bits of its
+// 64-bit multiplicative hash, its tag from the low 16 bits (0 means empty).
+// Inserts fill a bucket's free slots, then move to the next bucket; a probe
+// reads the 8 tags of a bucket with one 16-byte load and stops at the first
+// bucket that has an empty slot. The tags (2 bytes per slot) stay resident in
+// L2, and the 16-byte slot is read only on a tag match, so at the load factors
+// used here almost every probe costs one tag load (plus one slot load on a
+// hit). Each lane walks the chains of its four rows in lockstep, so that four
+// independent loads are in flight.
 #include <math.h>
+
+#include <algorithm>
 
 #include "common.h"
 #include "groupby.h"
@@ -14,13 +22,8 @@
 namespace tq {
 
 constexpr int kBlock = 256;
-
-static int blocks_for(int64_t n, int per_cu) {
-  int64_t want = (n + (int64_t)kBlock * kRows - 1) / ((int64_t)kBlock * kRows);
-  int64_t cap = (int64_t)device_cu_count() * per_cu;
-  if (want < 1) want = 1;
-  return (int)(want < cap ? want : cap);
-}
+constexpr int kChunk = kBlock * kRows;
+constexpr int kPR = 2;  // rows per lane in the aggregating probe (fewer registers, more waves)
 
 __host__ __device__ inline int log2cap_for(int64_t rows, double lf) {
   double need = ceil((double)rows / lf);
@@ -30,7 +33,7 @@ __host__ __device__ inline int log2cap_for(int64_t rows, double lf) {
 }
 
 __host__ __device__ inline size_t table_bytes_for(int64_t cap) {
-  return kHeaderBytes + (((size_t)cap * 4 + 255) & ~(size_t)255) + (size_t)cap * 16;
+  return kHeaderBytes + (size_t)kMaxPartBlocks * 8 + table_tag_bytes(cap) + (size_t)cap * 16;
 }
 
 static int64_t cap_max_for_bytes(size_t bytes) {
@@ -42,6 +45,24 @@ static int64_t cap_max_for_bytes(size_t bytes) {
   return cap;
 }
 
+struct Range {
+  int64_t per;  // rows per block, a multiple of kChunk
+  int nblk;
+};
+
+static Range split_rows(int64_t n, int max_blocks) {
+  int64_t chunks = (n + kChunk - 1) / kChunk;
+  int64_t nblk = std::min<int64_t>(std::max<int64_t>(chunks, 1), max_blocks);
+  int64_t per = ((chunks + nblk - 1) / nblk) * kChunk;
+  nblk = std::max<int64_t>(1, (n + per - 1) / per);
+  return Range{per, (int)nblk};
+}
+
+static int stream_grid(int64_t n, int per_cu) {
+  int64_t want = (n + kChunk - 1) / kChunk;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)device_cu_count() * per_cu));
+}
+
 __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
   h->magic = kTableMagic;
   h->err = 0;
@@ -49,55 +70,40 @@ __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
   h->log2cap = 6;
   h->skip = 0;
   h->n = 0;
-  h->n_acc = 0;
-  h->ticket = 0;
+  h->nblk = 0;
   h->flags = 0;
   h->lf = 0.5;
 }
 
-// Count the build rows that pass the filter; the last workgroup publishes the total.
-__global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, TableHeader* h) {
-  __shared__ int64_t part[kBlock / kWave];
-  int64_t cnt = 0;
-  const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
-  for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
-    bool full = r0 + kRows <= n;
-    int64_t v[TQ_MAX_COLS][kRows];
+// ------------------------------------------------------------------ build
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, int64_t per, TableHeader* h) {
+  __shared__ int64_t ws[kBlock / kWave];
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  int64_t c = 0;
+  for (int64_t r0 = lo + threadIdx.x * kRows; r0 < hi; r0 += kChunk) {
+    int64_t v[NC][kRows];
+    load_rows<NC>(P, r0, r0 + kRows <= hi, hi, v);
 #pragma unroll
-    for (int c = 0; c < TQ_MAX_COLS; c++)
-      if (c < P.ncol) load4(P.col[c], r0, full, n, v[c]);
-#pragma unroll
-    for (int i = 0; i < kRows; i++) {
-      int64_t vals[TQ_MAX_COLS];
-#pragma unroll
-      for (int c = 0; c < TQ_MAX_COLS; c++) vals[c] = v[c][i];
-      cnt += (r0 + i < n) && eval_preds(P, vals);
-    }
+    for (int i = 0; i < kRows; i++) c += (r0 + i < hi) && eval_preds<NC>(P, v, i);
   }
-  for (int d = 32; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, kWave);
-  if (__lane_id() == 0) part[threadIdx.x / kWave] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t t = 0;
-    for (int w = 0; w < kBlock / kWave; w++) t += part[w];
-    atomicAdd(reinterpret_cast<unsigned long long*>(&h->n_acc), (unsigned long long)t);
-    __threadfence();
-    uint32_t ticket = atomicAdd(&h->ticket, 1u);
-    if (ticket == gridDim.x - 1) {
-      __threadfence();
-      int64_t total = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&h->n_acc), 0ull);
-      h->n = total;
-      h->n_acc = 0;
-      h->ticket = 0;
-    }
-  }
+  int64_t t = block_sum(c, ws);
+  if (threadIdx.x == 0) table_partials(h)[blockIdx.x] = t;
 }
 
-// Fix the capacity from the row count and clear the tags it uses.
-__global__ __launch_bounds__(kBlock) void k_build_clear(TableHeader* h, int64_t cap_max, int64_t n_host, double lf,
-                                                        int skip, uint32_t flags) {
+// Fix the capacity from the row count (host-given, or the sum of the per-block
+// counts) and clear the tags it uses.
+__global__ __launch_bounds__(kBlock) void k_build_clear(TableHeader* h, int64_t cap_max, int64_t n_host, int nblk,
+                                                        double lf, int skip, uint32_t flags) {
+  __shared__ int64_t ws[kBlock / kWave];
   if (h->magic != kTableMagic) return;  // never initialised: the insert kernel does nothing either
-  const int64_t rows = n_host >= 0 ? n_host : h->n;
+  int64_t rows = n_host;
+  if (n_host < 0) {
+    int64_t c = 0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) c += table_partials(h)[b];
+    rows = block_sum(c, ws);
+  }
   int l = log2cap_for(rows, lf);
   bool full = ((int64_t)1 << l) > cap_max;
   if (full) {
@@ -114,187 +120,367 @@ __global__ __launch_bounds__(kBlock) void k_build_clear(TableHeader* h, int64_t 
     if (full) latch_error(&h->err, TQ_EFULL);
   }
   v4i32* tags = reinterpret_cast<v4i32*>(table_tags(h));
-  const int64_t n16 = ((int64_t)1 << l) / 4;
+  const int64_t nb = ((int64_t)1 << l) >> kLog2Bucket;  // one 16-byte tag group per bucket
   const v4i32 z = {0, 0, 0, 0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x)
     tags[i] = z;
 }
 
+// Bits j (0..7) of the result: tag j of the bucket equals t.
+__device__ __forceinline__ uint32_t tag_match(const v4i32& w, uint32_t t) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    uint32_t x = (uint32_t)w[q];
+    m |= (uint32_t)((x & 0xffffu) == t) << (2 * q);
+    m |= (uint32_t)((x >> 16) == t) << (2 * q + 1);
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint32_t word_of(const v4i32& w, int q) {
+  uint32_t r = (uint32_t)w[0];
+  r = q == 1 ? (uint32_t)w[1] : r;
+  r = q == 2 ? (uint32_t)w[2] : r;
+  r = q == 3 ? (uint32_t)w[3] : r;
+  return r;
+}
+
+__device__ __forceinline__ void set_word(v4i32& w, int q, uint32_t v) {
+  w[0] = q == 0 ? (int)v : w[0];
+  w[1] = q == 1 ? (int)v : w[1];
+  w[2] = q == 2 ? (int)v : w[2];
+  w[3] = q == 3 ? (int)v : w[3];
+}
+
+template <int NC>
 __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
                                                          TableHeader* h) {
   if (h->magic != kTableMagic) return;
   const int l = h->log2cap, skip = h->skip;
-  const int64_t cap = (int64_t)1 << l, mask = cap - 1;
+  const int64_t cap = (int64_t)1 << l, bmask = (cap >> kLog2Bucket) - 1;
   if (h->n > cap) return;  // does not fit: TQ_EFULL is latched, nothing is inserted
-  uint32_t* tags = table_tags(h);
+  uint32_t* words = table_tags(h);
   v2i64* slots = reinterpret_cast<v2i64*>(table_slots(h, h->cap_max));
   const DCol kc = {keys, 8};
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
-    bool full = r0 + kRows <= n;
-    int64_t v[TQ_MAX_COLS][kRows], k[kRows], pay[kRows];
-#pragma unroll
-    for (int c = 0; c < TQ_MAX_COLS; c++)
-      if (c < P.ncol) load4(P.col[c], r0, full, n, v[c]);
+    const bool full = r0 + kRows <= n;
+    int64_t v[NC][kRows], k[kRows], pay[kRows], b[kRows];
+    uint32_t tg[kRows];
+    bool pend[kRows];
+    int st[kRows];
+    v4i32 w[kRows];
+    load_rows<NC>(P, r0, full, n, v);
     load4(kc, r0, full, n, k);
     load4(payload, r0, full, n, pay);
 #pragma unroll
     for (int i = 0; i < kRows; i++) {
-      if (r0 + i >= n) break;
-      int64_t vals[TQ_MAX_COLS];
-#pragma unroll
-      for (int c = 0; c < TQ_MAX_COLS; c++) vals[c] = v[c][i];
-      if (!eval_preds(P, vals)) continue;
+      pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
       uint64_t hh = mulhash(k[i]);
-      int64_t s = (int64_t)slot_of(hh, skip, l);
-      uint32_t tag = hash_tag(hh);
-      for (int64_t t = 0; t < cap; t++) {
-        if (atomicCAS(&tags[s], 0u, tag) == 0u) {
-          v2i64 kv = {k[i], pay[i]};
-          slots[s] = kv;
-          break;
+      b[i] = (int64_t)bucket_of(hh, skip, l - kLog2Bucket);
+      tg[i] = hash_tag(hh);
+      st[i] = (int)(hh >> 16) & (kBucket - 1);
+      w[i] = v4i32{0, 0, 0, 0};
+    }
+    // Each round issues at most one CAS per row, for the first free slot at or
+    // after the row's start slot (hash bits, so that inserters into one bucket
+    // spread over its slots) in the row's view of its bucket. The view starts
+    // as "empty" and is corrected by the word a failed CAS returns, so every
+    // round claims a slot, learns of a newly taken one, or moves on.
+    for (int64_t round = 0; round < 2 * cap + 8; round++) {
+      uint32_t expect[kRows], prev[kRows];
+      int slot[kRows];
+      bool tried[kRows];
+#pragma unroll
+      for (int i = 0; i < kRows; i++) {
+        tried[i] = false;
+        slot[i] = 0;
+        expect[i] = 0;
+        prev[i] = 0;
+        if (!pend[i]) continue;
+        uint32_t zero = tag_match(w[i], 0u);
+        if (zero == 0u) {  // bucket full: linear probing moves to the next bucket
+          b[i] = (b[i] + 1) & bmask;
+          w[i] = v4i32{0, 0, 0, 0};
+          continue;
         }
-        s = (s + 1) & mask;
+        uint32_t rot = ((zero >> st[i]) | (zero << (kBucket - st[i]))) & 0xffu;
+        slot[i] = (__builtin_ctz(rot) + st[i]) & (kBucket - 1);
+        int q = slot[i] >> 1;
+        expect[i] = word_of(w[i], q);
+        uint32_t desired = expect[i] | (tg[i] << ((slot[i] & 1) * 16));
+        prev[i] = atomicCAS(&words[b[i] * 4 + q], expect[i], desired);
+        tried[i] = true;
       }
+      bool more = false;
+#pragma unroll
+      for (int i = 0; i < kRows; i++) {
+        if (tried[i]) {
+          if (prev[i] == expect[i]) {
+            v2i64 kv = {k[i], pay[i]};
+            slots[b[i] * kBucket + slot[i]] = kv;
+            pend[i] = false;
+          } else {
+            set_word(w[i], slot[i] >> 1, prev[i]);
+          }
+        }
+        more = more || pend[i];
+      }
+      if (!more) break;
     }
   }
 }
 
 // ------------------------------------------------------------------ probe
 
-constexpr int kPairs = 3;  // materialise (row, payload) pairs instead of aggregating
+struct Probe {
+  const v4i32* groups;
+  const v2i64* slots;
+  int64_t bmask, cap;
+  int log2b, skip;
+  bool unique;
 
-struct PairOut {
-  int64_t* row;
-  int64_t* payload;
-  int64_t capacity;
-};
+  __device__ __forceinline__ void setup(const TableHeader* h) {
+    log2b = h->log2cap - kLog2Bucket;
+    skip = h->skip;
+    unique = (h->flags & TQ_UNIQUE_KEYS) != 0;
+    cap = (int64_t)1 << h->log2cap;
+    bmask = ((int64_t)1 << log2b) - 1;
+    groups = reinterpret_cast<const v4i32*>(table_tags(const_cast<TableHeader*>(h)));
+    slots = reinterpret_cast<const v2i64*>(table_slots(const_cast<TableHeader*>(h), h->cap_max));
+  }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_probe(const TableHeader* h, const int64_t* pkeys, int64_t n, RowPlan P,
-                                                  PairOut out, unsigned long long* count, AggTarget T) {
-  extern __shared__ __align__(16) char smem[];
-  if (h->magic != kTableMagic) return;
-  if (MODE != kPairs && !state_matches(T)) return;
-  LdsAgg<MODE == kPairs ? kGlobal : MODE> agg;
-  if (MODE != kPairs) agg.init(T, smem);
-  __syncthreads();
+  // Walks the chains of one lane's rows in lockstep. Each round checks one
+  // tag-matching slot per row (or moves the row to its next bucket) and calls
+  // on_round(hit, payload): hit[i] is set when row i matched in this round (a
+  // row can match again in later rounds unless the build keys are unique).
+  template <int R, typename F>
+  __device__ __forceinline__ void walk(const bool (&ok)[R], const int64_t (&k)[R], F&& on_round) const {
+    walk(ok, k, on_round, [] {});
+  }
 
-  const int l = h->log2cap, skip = h->skip;
-  const bool unique = (h->flags & TQ_UNIQUE_KEYS) != 0;
-  const int64_t cap = (int64_t)1 << l, mask = cap - 1;
-  const uint32_t* tags = table_tags(const_cast<TableHeader*>(h));
-  const v2i64* slots = reinterpret_cast<const v2i64*>(table_slots(const_cast<TableHeader*>(h), h->cap_max));
-  const DCol kc = {pkeys, 8};
-  const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
-  uint32_t matches = 0;
-
-  // Pairs mode runs whole waves through the loop so that the wave scan sees every lane.
-  for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows;
-       MODE == kPairs ? (r0 - (int64_t)threadIdx.x * kRows < n) : (r0 < n); r0 += step) {
-    const bool any = r0 < n;
-    bool full = r0 + kRows <= n;
-    int64_t v[TQ_MAX_COLS][kRows], k[kRows];
+  // As above; `issued()` runs once, right after the first tag loads are issued
+  // (a caller prefetches its next rows there, so that the wait for the tags
+  // does not also wait for the prefetch).
+  template <int R, typename F, typename G>
+  __device__ __forceinline__ void walk(const bool (&ok)[R], const int64_t (&k)[R], F&& on_round, G&& issued) const {
+    int64_t b[R];
+    uint32_t tg[R], m[R];
+    bool act[R], empty[R], load[R];
 #pragma unroll
-    for (int c = 0; c < TQ_MAX_COLS; c++)
-      if (c < P.ncol && any) load4(P.col[c], r0, full, n, v[c]);
-    if (any) load4(kc, r0, full, n, k);
-    bool ok[kRows];
-    int64_t s[kRows];
-    uint32_t tg[kRows], t0[kRows];
-#pragma unroll
-    for (int i = 0; i < kRows; i++) {
-      int64_t vals[TQ_MAX_COLS];
-#pragma unroll
-      for (int c = 0; c < TQ_MAX_COLS; c++) vals[c] = v[c][i];
-      ok[i] = any && (r0 + i < n) && eval_preds(P, vals);
+    for (int i = 0; i < R; i++) {
       uint64_t hh = mulhash(k[i]);
-      s[i] = (int64_t)slot_of(hh, skip, l);
+      b[i] = (int64_t)bucket_of(hh, skip, log2b);
       tg[i] = hash_tag(hh);
+      act[i] = ok[i];
+      load[i] = true;
+      m[i] = 0;
+      empty[i] = false;
     }
-    // issue the first tag load of every row before walking any chain
+    for (int64_t round = 0; round < 2 * cap + 8; round++) {
+      v4i32 w[R];
 #pragma unroll
-    for (int i = 0; i < kRows; i++) t0[i] = ok[i] ? tags[s[i]] : 0u;
-
-    if (MODE == kPairs) {
-      uint32_t mine = 0;
+      for (int i = 0; i < R; i++)
+        if (act[i] && load[i]) w[i] = groups[b[i]];
+      if (round == 0) issued();
 #pragma unroll
-      for (int i = 0; i < kRows; i++) {
-        int64_t si = s[i];
-        uint32_t t = t0[i];
-        for (int64_t it = 0; t != 0 && it < cap; it++) {
-          if (t == tg[i] && slots[si].x == k[i]) {
-            mine++;
-            if (unique) break;
-          }
-          si = (si + 1) & mask;
-          t = tags[si];
+      for (int i = 0; i < R; i++) {
+        if (act[i] && load[i]) {
+          m[i] = tag_match(w[i], tg[i]);
+          empty[i] = tag_match(w[i], 0u) != 0u;
+          load[i] = false;
         }
       }
-      uint32_t total;
-      uint32_t pre = wave_excl_scan(mine, &total);
-      unsigned long long base = 0;
-      if (__lane_id() == kWave - 1 && total) base = atomicAdd(count, (unsigned long long)total);
-      base = __shfl(base, kWave - 1, kWave);
-      int64_t w = (int64_t)base + pre;
+      v2i64 kv[R];
+      bool cand[R], hit[R];
+      int64_t pay[R];
 #pragma unroll
-      for (int i = 0; i < kRows; i++) {
-        int64_t si = s[i];
-        uint32_t t = t0[i];
-        for (int64_t it = 0; t != 0 && it < cap; it++) {
-          if (t == tg[i]) {
-            v2i64 kv = slots[si];
-            if (kv.x == k[i]) {
-              if (w < out.capacity) {
-                out.row[w] = r0 + i;
-                out.payload[w] = kv.y;
-              }
-              w++;
-              if (unique) break;
-            }
-          }
-          si = (si + 1) & mask;
-          t = tags[si];
-        }
+      for (int i = 0; i < R; i++) {
+        cand[i] = act[i] && m[i] != 0u;
+        int j = cand[i] ? __builtin_ctz(m[i]) : 0;
+        kv[i] = cand[i] ? slots[b[i] * kBucket + j] : v2i64{0, 0};
+        m[i] &= m[i] - 1u;
       }
-    } else {
 #pragma unroll
-      for (int i = 0; i < kRows; i++) {
-        int64_t si = s[i];
-        uint32_t t = t0[i];
-        for (int64_t it = 0; t != 0 && it < cap; it++) {
-          if (t == tg[i]) {
-            v2i64 kv = slots[si];
-            if (kv.x == k[i]) {
-              int64_t vals[TQ_MAX_COLS], e[TQ_MAX_SUMS];
-#pragma unroll
-              for (int c = 0; c < TQ_MAX_COLS; c++) vals[c] = v[c][i];
-#pragma unroll
-              for (int j = 0; j < TQ_MAX_SUMS; j++)
-                if (j < P.ne) e[j] = eval_expr(P.expr[j], vals);
-              agg.add(T, kv.y, e, P.ne);
-              matches++;
-              if (unique) break;
-            }
-          }
-          si = (si + 1) & mask;
-          t = tags[si];
-        }
+      for (int i = 0; i < R; i++) {
+        hit[i] = cand[i] && kv[i].x == k[i];
+        pay[i] = kv[i].y;
       }
+      on_round(hit, pay);
+      bool more = false;
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        if (!act[i]) continue;
+        if (hit[i] && unique) act[i] = false;
+        else if (m[i] == 0u) {
+          if (empty[i]) act[i] = false;  // an empty slot ends the chain
+          else {
+            b[i] = (b[i] + 1) & bmask;
+            load[i] = true;
+          }
+        }
+        more = more || act[i];
+      }
+      if (!more) break;
     }
   }
-  if (MODE != kPairs) {
-    agg.flush(T);
-    if (count) {
-      for (int d = 32; d > 0; d >>= 1) matches += __shfl_xor(matches, d, kWave);
-      if (__lane_id() == 0 && matches) atomicAdd(count, (unsigned long long)matches);
+};
+
+template <int MODE, int NC, int NE>
+__global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const TableHeader* h, const int64_t* pkeys, int64_t n, RowPlan P,
+                                                         AggTarget T) {
+  extern __shared__ __align__(16) char smem[];
+  if (h->magic != kTableMagic) return;
+  if (!state_matches(T)) return;
+  LdsAgg<MODE> agg;
+  agg.init(T, smem);
+  __syncthreads();
+  Probe pr;
+  pr.setup(h);
+  const DCol kc = {pkeys, 8};
+  const int64_t step = (int64_t)gridDim.x * blockDim.x * kPR;
+  // Software pipeline: the columns of the next rows are loaded while the
+  // current rows walk the table.
+  int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kPR;
+  int64_t vn[NC][kPR], kn[kPR];
+  if (r0 < n) {
+    load_rows<NC>(P, r0, r0 + kPR <= n, n, vn);
+    load4(kc, r0, r0 + kPR <= n, n, kn);
+  }
+  for (; r0 < n; r0 += step) {
+    int64_t k[kPR], e[kPR][NE];
+    bool ok[kPR];
+#pragma unroll
+    for (int i = 0; i < kPR; i++) {
+      ok[i] = (r0 + i < n) && eval_preds<NC>(P, vn, i);
+#pragma unroll
+      for (int j = 0; j < NE; j++) e[i][j] = j < P.ne ? eval_expr<NC>(P.expr[j], vn, i) : 0;
+      k[i] = kn[i];
     }
+    const int64_t r1 = r0 + step;
+    pr.walk(
+        ok, k,
+        [&](const bool (&hit)[kPR], const int64_t (&pay)[kPR]) {
+#pragma unroll
+          for (int i = 0; i < kPR; i++)
+            if (hit[i]) agg.add(T, pay[i], e[i], P.ne);
+        },
+        [&] {
+          if (r1 < n) {
+            load_rows<NC>(P, r1, r1 + kPR <= n, n, vn);
+            load4(kc, r1, r1 + kPR <= n, n, kn);
+          }
+        });
+  }
+  agg.flush(T);
+}
+
+// Match count of each block's contiguous row range (pairs mode, pass 1).
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_probe_count(const TableHeader* h, const int64_t* pkeys, int64_t n,
+                                                        int64_t per, RowPlan P, int64_t* cnt) {
+  __shared__ int64_t ws[kBlock / kWave];
+  if (h->magic != kTableMagic) return;
+  Probe pr;
+  pr.setup(h);
+  const DCol kc = {pkeys, 8};
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  int64_t c = 0;
+  for (int64_t r0 = lo + threadIdx.x * kRows; r0 < hi; r0 += kChunk) {
+    const bool full = r0 + kRows <= hi;
+    int64_t v[NC][kRows], k[kRows];
+    bool ok[kRows];
+    load_rows<NC>(P, r0, full, hi, v);
+    load4(kc, r0, full, hi, k);
+#pragma unroll
+    for (int i = 0; i < kRows; i++) ok[i] = (r0 + i < hi) && eval_preds<NC>(P, v, i);
+    pr.walk(ok, k, [&](const bool (&hit)[kRows], const int64_t (&)[kRows]) {
+#pragma unroll
+      for (int i = 0; i < kRows; i++) c += hit[i];
+    });
+  }
+  int64_t t = block_sum(c, ws);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = t;
+}
+
+// Pairs mode, pass 2: write (row, payload) in probe-row order.
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_probe_write(const TableHeader* h, const int64_t* pkeys, int64_t n,
+                                                        int64_t per, RowPlan P, const int64_t* base, int64_t* out_row,
+                                                        int64_t* out_pay, int64_t capacity) {
+  __shared__ int64_t ws[kBlock / kWave];
+  if (h->magic != kTableMagic) return;
+  Probe pr;
+  pr.setup(h);
+  const DCol kc = {pkeys, 8};
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  int64_t w0 = base[blockIdx.x];
+  for (int64_t c0 = lo; c0 < hi; c0 += kChunk) {  // uniform loop: every thread takes part in the scan
+    const int64_t r0 = c0 + threadIdx.x * kRows;
+    const bool full = r0 + kRows <= hi;
+    int64_t v[NC][kRows], k[kRows];
+    bool ok[kRows];
+    if (r0 < hi) {
+      load_rows<NC>(P, r0, full, hi, v);
+      load4(kc, r0, full, hi, k);
+    }
+#pragma unroll
+    for (int i = 0; i < kRows; i++) ok[i] = (r0 + i < hi) && eval_preds<NC>(P, v, i);
+    int64_t mine = 0;
+    pr.walk(ok, k, [&](const bool (&hit)[kRows], const int64_t (&)[kRows]) {
+#pragma unroll
+      for (int i = 0; i < kRows; i++) mine += hit[i];
+    });
+    int64_t excl;
+    int64_t tot = block_excl_scan(mine, &excl, ws);
+    int64_t w = w0 + excl;
+    // a second walk emits the matches of each row in chain order
+#pragma unroll
+    for (int i = 0; i < kRows; i++) {
+      bool one[kRows];
+      int64_t kk[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; j++) {
+        one[j] = ok[j] && j == i;
+        kk[j] = k[j];
+      }
+      pr.walk(one, kk, [&](const bool (&hit)[kRows], const int64_t (&pay)[kRows]) {
+#pragma unroll
+        for (int j = 0; j < kRows; j++) {
+          if (hit[j]) {
+            if (w < capacity) {
+              out_row[w] = r0 + i;
+              out_pay[w] = pay[j];
+            }
+            w++;
+          }
+        }
+      });
+    }
+    w0 += tot;
   }
 }
 
-__global__ void k_zero1(int64_t* p) { *p = 0; }
+template <int D>
+__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t* cnt, int nblk, int64_t* total) {
+  __shared__ int64_t ws[1024 / kWave];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nblk; b0 += 1024) {
+    int b = b0 + threadIdx.x;
+    int64_t x = b < nblk ? cnt[b] : 0, e;
+    int64_t t = block_excl_scan(x, &e, ws);
+    if (b < nblk) cnt[b] = carry + e;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += t;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
 
-tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T, AggMode* mode, size_t* lds);
+__global__ void k_zero1(int64_t* p) { *p = 0; }
 
 }  // namespace tq
 
@@ -322,6 +508,7 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   if (!d_table) return fail(TQ_EINVAL, "table is NULL");
   if (!(load_factor > 0.0 && load_factor <= 0.9)) return fail(TQ_EINVAL, "load factor %g outside (0, 0.9]", load_factor);
   if (skip < 0 || skip > 32) return fail(TQ_EINVAL, "skip %d outside [0, 32]", skip);
+  if (n < 0) return fail(TQ_EINVAL, "n < 0");
   if (n > 0 && (!d_keys || !payload.data)) return fail(TQ_EINVAL, "NULL keys or payload");
   if (((uintptr_t)d_keys & 15) || ((uintptr_t)payload.data & 15)) return fail(TQ_EINVAL, "keys/payload not 16-byte aligned");
   if (payload.type != TQ_U8 && payload.type != TQ_I32 && payload.type != TQ_I64) return fail(TQ_EINVAL, "payload type");
@@ -331,18 +518,21 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   tq_status s = make_plan(&P, filt, nfilt, p, np, nullptr, 0, nullptr, n);
   if (s) return s;
   TableHeader* h = static_cast<TableHeader*>(d_table);
-  int grid = blocks_for(n, 8);
+  int nblk = 0;
   if (np > 0 && n > 0) {
-    hipLaunchKernelGGL(k_build_count, dim3(grid), dim3(kBlock), 0, stream, P, n, h);
+    Range R = split_rows(n, kMaxPartBlocks);
+    nblk = R.nblk;
+    TQ_DISPATCH_NC(nfilt, NC, hipLaunchKernelGGL(k_build_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, n, R.per, h));
     TQ_HIP(hipGetLastError());
   }
   int64_t clear_blocks = std::max<int64_t>(1, std::min<int64_t>(cap_max / 4 / kBlock, device_cu_count() * 4));
   hipLaunchKernelGGL(k_build_clear, dim3((int)clear_blocks), dim3(kBlock), 0, stream, h, cap_max,
-                     np > 0 ? (int64_t)-1 : n, load_factor, skip, flags);
+                     np > 0 ? (int64_t)-1 : n, nblk, load_factor, skip, flags);
   TQ_HIP(hipGetLastError());
   if (n > 0) {
     DCol pc = {payload.data, payload.type};
-    hipLaunchKernelGGL(k_build_insert, dim3(grid), dim3(kBlock), 0, stream, P, d_keys, pc, n, h);
+    TQ_DISPATCH_NC(nfilt, NC, hipLaunchKernelGGL(k_build_insert<NC>, dim3(stream_grid(n, 8)), dim3(kBlock), 0, stream, P,
+                                                 d_keys, pc, n, h));
     TQ_HIP(hipGetLastError());
   }
   return TQ_OK;
@@ -352,34 +542,41 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
                         const tq_pred* p, int32_t np, int64_t* d_out_probe_row, int64_t* d_out_payload,
                         int64_t capacity, int64_t* d_out_count, const tq_agg* agg, hipStream_t stream) {
   if (!d_table) return fail(TQ_EINVAL, "table is NULL");
+  if (n < 0) return fail(TQ_EINVAL, "n < 0");
   if (n > 0 && !d_probe_keys) return fail(TQ_EINVAL, "probe keys are NULL");
   if ((uintptr_t)d_probe_keys & 15) return fail(TQ_EINVAL, "probe keys not 16-byte aligned");
   RowPlan P;
   tq_status s = make_plan(&P, cols, ncol, p, np, agg ? agg->sums : nullptr, agg ? agg->nsum : 0, nullptr, n);
   if (s) return s;
   const TableHeader* h = static_cast<const TableHeader*>(d_table);
-  AggTarget T{};
-  AggMode mode = kGlobal;
-  size_t lds = 0;
   if (agg) {
+    AggTarget T{};
+    AggMode mode;
+    size_t lds = 0;
     if ((s = make_target(agg->d_state, agg->domain, agg->nsum, &T, &mode, &lds))) return s;
-  } else {
-    if (!d_out_count) return fail(TQ_EINVAL, "d_out_count is NULL");
-    if (capacity < 0 || (capacity > 0 && (!d_out_probe_row || !d_out_payload)))
-      return fail(TQ_EINVAL, "bad pair outputs");
+    if (d_out_count) return fail(TQ_EINVAL, "the fused group-by counts matches in its COUNT column; pass d_out_count = NULL");
+    if (n == 0) return TQ_OK;
+    dim3 grid(agg_grid(n)), block(kAggBlock);
+    TQ_DISPATCH_AGG(mode, ncol, agg->nsum, M, NC, NE,
+                    hipLaunchKernelGGL((k_probe_agg<M, NC, NE>), grid, block, lds, stream, h, d_probe_keys, n, P, T));
+    TQ_HIP(hipGetLastError());
+    return TQ_OK;
   }
-  if (d_out_count) {
+  if (!d_out_count) return fail(TQ_EINVAL, "d_out_count is NULL");
+  if (capacity < 0 || (capacity > 0 && (!d_out_probe_row || !d_out_payload))) return fail(TQ_EINVAL, "bad pair outputs");
+  if (n == 0) {
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, stream, d_out_count);
     TQ_HIP(hipGetLastError());
+    return TQ_OK;
   }
-  if (n == 0) return TQ_OK;
-  PairOut out = {d_out_probe_row, d_out_payload, capacity};
-  auto* cnt = reinterpret_cast<unsigned long long*>(d_out_count);
-  dim3 grid(blocks_for(n, agg ? 4 : 8)), block(kBlock);
-  if (!agg) hipLaunchKernelGGL(k_probe<kPairs>, grid, block, 0, stream, h, d_probe_keys, n, P, out, cnt, T);
-  else if (mode == kDense) hipLaunchKernelGGL(k_probe<kDense>, grid, block, lds, stream, h, d_probe_keys, n, P, out, cnt, T);
-  else if (mode == kHash) hipLaunchKernelGGL(k_probe<kHash>, grid, block, lds, stream, h, d_probe_keys, n, P, out, cnt, T);
-  else hipLaunchKernelGGL(k_probe<kGlobal>, grid, block, 0, stream, h, d_probe_keys, n, P, out, cnt, T);
+  Range R = split_rows(n, kMaxPartBlocks);
+  // the per-block counts live in the table's partial area: materialising probes of one table must not overlap
+  int64_t* cnt = table_partials(const_cast<void*>(d_table));
+  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_probe_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, h, d_probe_keys, n,
+                                              R.per, P, cnt));
+  hipLaunchKernelGGL(k_scan_blocks<0>, dim3(1), dim3(1024), 0, stream, cnt, R.nblk, d_out_count);
+  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_probe_write<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, h, d_probe_keys, n,
+                                              R.per, P, cnt, d_out_probe_row, d_out_payload, capacity));
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }

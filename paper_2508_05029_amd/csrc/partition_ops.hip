@@ -40,25 +40,6 @@ __global__ __launch_bounds__(kPBlock) void k_part_hist(const int64_t* keys, int6
   for (int b = threadIdx.x; b < nb; b += kPBlock) counts[(int64_t)b * ntiles + blockIdx.x] = hist[b];
 }
 
-// Block-wide exclusive scan of one int64 per thread; returns the block total.
-__device__ int64_t block_excl_scan(int64_t x, int64_t* excl, int64_t* wave_sums) {
-  const int lane = __lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  int64_t s = x;
-  for (int d = 1; d < kWave; d <<= 1) {
-    int64_t y = __shfl_up(s, d, kWave);
-    if (lane >= d) s += y;
-  }
-  if (lane == kWave - 1) wave_sums[wid] = s;
-  __syncthreads();
-  int64_t off = 0, total = 0;
-  for (int w = 0; w < nw; w++) {
-    if (w < wid) off += wave_sums[w];
-    total += wave_sums[w];
-  }
-  __syncthreads();
-  *excl = off + s - x;
-  return total;
-}
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const int64_t* a, int64_t L, int64_t* bsum) {
   __shared__ int64_t ws[kScanBlock / kWave];

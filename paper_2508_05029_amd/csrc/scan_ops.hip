@@ -1,6 +1,8 @@
-// Filter / project, group-by accumulation and finalization, and the two
-// measurement kernels (streaming read, cache-evicting fill).
+// Filter / project (stable compaction), group-by accumulation and
+// finalization, and the two measurement kernels (streaming read, fill).
 #include <string.h>
+
+#include <algorithm>
 
 #include "common.h"
 #include "groupby.h"
@@ -8,16 +10,30 @@
 namespace tq {
 
 constexpr int kBlock = 256;
-
-static int stream_blocks(int64_t n, int per_cu) {
-  int64_t want = (n + (int64_t)kBlock * kRows - 1) / ((int64_t)kBlock * kRows);
-  int64_t cap = (int64_t)device_cu_count() * per_cu;
-  if (want < 1) want = 1;
-  return (int)(want < cap ? want : cap);
-}
+constexpr int kChunk = kBlock * kRows;  // rows per block step of the compaction kernels
+constexpr int kMaxScanBlocks = 2048;
 
 __global__ void k_zero_i64(int64_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Exclusive scan of up to kMaxScanBlocks per-block counts in one workgroup;
+// writes the total to *total (if not NULL).
+__global__ __launch_bounds__(1024) void k_scan_counts(int64_t* cnt, int nblk, int64_t* total) {
+  __shared__ int64_t ws[1024 / kWave];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nblk; b0 += 1024) {
+    int b = b0 + threadIdx.x;
+    int64_t x = b < nblk ? cnt[b] : 0, e;
+    int64_t t = block_excl_scan(x, &e, ws);
+    if (b < nblk) cnt[b] = carry + e;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += t;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
 }
 
 // ------------------------------------------------------------ filter/project
@@ -26,50 +42,77 @@ struct OutPtrs {
   int64_t* p[TQ_MAX_SUMS];
 };
 
-__global__ __launch_bounds__(kBlock) void k_filter_project(RowPlan P, int64_t n, OutPtrs out, int64_t* sel,
-                                                           unsigned long long* count) {
-  const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
-  for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 - (int64_t)threadIdx.x * kRows < n;
-       r0 += step) {
-    // every lane of the wave takes part in the scan, also past the end
-    bool full = r0 + kRows <= n;
-    int64_t v[TQ_MAX_COLS][kRows];
+struct Range {
+  int64_t per;  // rows per block, a multiple of kChunk
+  int nblk;
+};
+
+static Range split_rows(int64_t n) {
+  int64_t chunks = (n + kChunk - 1) / kChunk;
+  int64_t nblk = std::min<int64_t>(std::max<int64_t>(chunks, 1), kMaxScanBlocks);
+  int64_t per = ((chunks + nblk - 1) / nblk) * kChunk;
+  nblk = std::max<int64_t>(1, (n + per - 1) / per);
+  return Range{per, (int)nblk};
+}
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_fp_count(RowPlan P, int64_t n, int64_t per, int64_t* cnt) {
+  __shared__ int64_t ws[kBlock / kWave];
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  int64_t c = 0;
+  for (int64_t r0 = lo + threadIdx.x * kRows; r0 < hi; r0 += kChunk) {
+    int64_t v[NC][kRows];
+    load_rows<NC>(P, r0, r0 + kRows <= hi, hi, v);
 #pragma unroll
-    for (int c = 0; c < TQ_MAX_COLS; c++)
-      if (c < P.ncol && r0 < n) load4(P.col[c], r0, full, n, v[c]);
+    for (int i = 0; i < kRows; i++) c += (r0 + i < hi) && eval_preds<NC>(P, v, i);
+  }
+  int64_t t = block_sum(c, ws);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = t;
+}
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_fp_write(RowPlan P, int64_t n, int64_t per, const int64_t* base,
+                                                     OutPtrs out, int64_t* sel) {
+  __shared__ int64_t ws[kBlock / kWave];
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  int64_t w0 = base[blockIdx.x];
+  for (int64_t c0 = lo; c0 < hi; c0 += kChunk) {  // uniform loop: every thread takes part in the scan
+    const int64_t r0 = c0 + threadIdx.x * kRows;
+    int64_t v[NC][kRows];
     bool ok[kRows];
-    uint32_t mine = 0;
+    int64_t mine = 0;
+    if (r0 < hi) load_rows<NC>(P, r0, r0 + kRows <= hi, hi, v);
 #pragma unroll
     for (int i = 0; i < kRows; i++) {
-      int64_t vals[TQ_MAX_COLS];
-#pragma unroll
-      for (int c = 0; c < TQ_MAX_COLS; c++) vals[c] = v[c][i];
-      ok[i] = (r0 + i < n) && eval_preds(P, vals);
+      ok[i] = (r0 + i < hi) && eval_preds<NC>(P, v, i);
       mine += ok[i];
     }
-    uint32_t total;
-    uint32_t pre = wave_excl_scan(mine, &total);
-    unsigned long long base = 0;
-    if (__lane_id() == kWave - 1 && total) base = atomicAdd(count, (unsigned long long)total);
-    base = __shfl(base, kWave - 1, kWave);
-    int64_t w = (int64_t)base + pre;
+    int64_t excl;
+    int64_t tot = block_excl_scan(mine, &excl, ws);
+    int64_t w = w0 + excl;
 #pragma unroll
     for (int i = 0; i < kRows; i++) {
       if (!ok[i]) continue;
-      int64_t vals[TQ_MAX_COLS];
 #pragma unroll
-      for (int c = 0; c < TQ_MAX_COLS; c++) vals[c] = v[c][i];
-      for (int e = 0; e < P.ne; e++) out.p[e][w] = eval_expr(P.expr[e], vals);
+      for (int e = 0; e < TQ_MAX_SUMS; e++)
+        if (e < P.ne) out.p[e][w] = eval_expr<NC>(P.expr[e], v, i);
       if (sel) sel[w] = r0 + i;
       w++;
     }
+    w0 += tot;
   }
 }
 
 // ------------------------------------------------------------ group-by
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_groupby(RowPlan P, int64_t n, AggTarget T) {
+int agg_grid(int64_t n) {
+  int64_t want = (n + (int64_t)kAggBlock * kRows - 1) / ((int64_t)kAggBlock * kRows);
+  int64_t cap = std::min<int64_t>(kAggRows, kAggBlocksPerCU * (int64_t)device_cu_count());
+  return (int)std::max<int64_t>(1, std::min(want, cap));
+}
+
+template <int MODE, int NC, int NE>
+__global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_groupby(RowPlan P, int64_t n, AggTarget T) {
   extern __shared__ __align__(16) char smem[];
   if (!state_matches(T)) return;
   LdsAgg<MODE> agg;
@@ -77,53 +120,61 @@ __global__ __launch_bounds__(kBlock) void k_groupby(RowPlan P, int64_t n, AggTar
   __syncthreads();
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
-    bool full = r0 + kRows <= n;
-    int64_t v[TQ_MAX_COLS][kRows];
-#pragma unroll
-    for (int c = 0; c < TQ_MAX_COLS; c++)
-      if (c < P.ncol) load4(P.col[c], r0, full, n, v[c]);
+    int64_t v[NC][kRows];
+    load_rows<NC>(P, r0, r0 + kRows <= n, n, v);
 #pragma unroll
     for (int i = 0; i < kRows; i++) {
-      if (r0 + i >= n) break;
-      int64_t vals[TQ_MAX_COLS];
+      if (r0 + i < n && eval_preds<NC>(P, v, i)) {
+        int64_t s[NE];
 #pragma unroll
-      for (int c = 0; c < TQ_MAX_COLS; c++) vals[c] = v[c][i];
-      if (!eval_preds(P, vals)) continue;
-      int64_t s[TQ_MAX_SUMS];
-#pragma unroll
-      for (int e = 0; e < TQ_MAX_SUMS; e++)
-        if (e < P.ne) s[e] = eval_expr(P.expr[e], vals);
-      agg.add(T, eval_key(P, vals), s, P.ne);
+        for (int e = 0; e < NE; e++) s[e] = e < P.ne ? eval_expr<NC>(P.expr[e], v, i) : 0;
+        agg.add(T, eval_key<NC>(P, v, i), s, P.ne);
+      }
     }
   }
   agg.flush(T);
 }
 
-__global__ void k_state_init(StateHeader* h, int64_t domain, int32_t nsum, int32_t replicas, int64_t entries) {
+__global__ void k_state_init(StateHeader* h, int64_t domain, int32_t nsum, int32_t rows, int64_t entries) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     h->magic = kStateMagic;
     h->err = 0;
     h->domain = domain;
     h->nsum = nsum;
-    h->replicas = replicas;
-    h->matches = 0;
+    h->rows = rows;
+    h->used = 0;
   }
   int64_t* d = state_data(h);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries; i += (int64_t)gridDim.x * blockDim.x)
     d[i] = 0;
 }
 
-// One workgroup: sum the replicas, keep COUNT > 0, emit in key order.
+// One workgroup: fold the private rows (if any), keep COUNT > 0, emit in key order.
 constexpr int kFinBlock = 1024;
 
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, int64_t* keys, int64_t* count,
                                                         int64_t* sums, double* avg, int64_t* ngroups) {
   __shared__ uint32_t wave_tot[kFinBlock / kWave];
+  __shared__ int64_t fold[kPrivateRowsMaxEntries];
   __shared__ int64_t base_s;
+  if (h->magic != kStateMagic) return;
   const int64_t domain = h->domain;
-  const int nsum = h->nsum, stride = 1 + nsum, R = h->replicas;
-  const int64_t rstride = domain * stride;
+  const int nsum = h->nsum, stride = 1 + nsum, rows = h->rows;
   const int64_t* d = state_data(const_cast<StateHeader*>(h));
+  const int entries = (int)(domain * stride);
+  if (rows > 1) {
+    for (int e = threadIdx.x; e < entries; e += kFinBlock) fold[e] = 0;
+    __syncthreads();
+    // thread t < lim always lands on entry t % entries: it sums its share of
+    // the used rows in a register, then one LDS atomic per thread folds them
+    const int per = kFinBlock / entries, lim = per * entries;
+    const int total = (int)min<int64_t>(h->used, rows) * entries;
+    if ((int)threadIdx.x < lim) {
+      uint64_t acc = 0;
+      for (int i = threadIdx.x; i < total; i += lim) acc += (uint64_t)d[i];
+      if (acc) atomicAdd(reinterpret_cast<unsigned long long*>(&fold[threadIdx.x % entries]), (unsigned long long)acc);
+    }
+  }
   if (threadIdx.x == 0) base_s = 0;
   __syncthreads();
   const int wid = threadIdx.x / kWave, lane = __lane_id();
@@ -132,11 +183,9 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, in
     int64_t e[1 + TQ_MAX_SUMS];
     bool live = false;
     if (k < domain) {
-      for (int j = 0; j < stride; j++) {
-        uint64_t acc = 0;
-        for (int r = 0; r < R; r++) acc += (uint64_t)d[r * rstride + k * stride + j];
-        e[j] = (int64_t)acc;
-      }
+#pragma unroll
+      for (int j = 0; j < 1 + TQ_MAX_SUMS; j++)
+        if (j < stride) e[j] = rows > 1 ? fold[k * stride + j] : d[k * stride + j];
       live = e[0] != 0;
     }
     uint64_t m = __ballot(live);
@@ -149,9 +198,12 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, in
       int64_t g = off + pre;
       keys[g] = k;
       count[g] = e[0];
-      for (int j = 0; j < nsum; j++) {
-        sums[g * nsum + j] = e[1 + j];
-        if (avg) avg[g * nsum + j] = (double)e[1 + j] / (double)e[0];
+#pragma unroll
+      for (int j = 0; j < TQ_MAX_SUMS; j++) {
+        if (j < nsum) {
+          sums[g * nsum + j] = e[1 + j];
+          if (avg) avg[g * nsum + j] = (double)e[1 + j] / (double)e[0];
+        }
       }
     }
     __syncthreads();
@@ -167,20 +219,21 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, in
 
 // ------------------------------------------------------------ measurement
 
-__global__ __launch_bounds__(kBlock) void k_read_peak(const v2i64* src, int64_t n16, unsigned long long* sink) {
+__global__ __launch_bounds__(kBlock) void k_read_peak(const v2i64* src, int64_t n16, int64_t* part) {
+  __shared__ int64_t ws[kBlock / kWave];
   long long acc = 0;
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i + 3 * step < n16; i += 4 * step) {
     v2i64 a = ntload(src + i), b = ntload(src + i + step), c = ntload(src + i + 2 * step), e = ntload(src + i + 3 * step);
-    acc ^= a.x + a.y + b.x + b.y + c.x + c.y + e.x + e.y;
+    acc += a.x + a.y + b.x + b.y + c.x + c.y + e.x + e.y;
   }
   for (; i < n16; i += step) {
     v2i64 a = ntload(src + i);
-    acc ^= a.x + a.y;
+    acc += a.x + a.y;
   }
-  for (int d = 32; d > 0; d >>= 1) acc ^= __shfl_xor(acc, d, kWave);
-  if (__lane_id() == 0) atomicAdd(sink, (unsigned long long)acc);
+  int64_t t = block_sum(acc, ws);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(v4i32* dst, int64_t n16, uint32_t pattern) {
@@ -188,59 +241,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(v4i32* dst, int64_t n16, uint32
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
     __builtin_nontemporal_store(v, dst + i);
 }
-
-}  // namespace tq
-
-using namespace tq;
-
-extern "C" {
-
-tq_status tq_filter_project(const tq_col* in, int32_t ncol, int64_t nrows, const tq_pred* p, int32_t np,
-                            const tq_expr* e, int32_t ne, int64_t* const* d_out, int64_t* d_sel, int64_t* d_out_rows,
-                            hipStream_t stream) {
-  RowPlan P;
-  tq_status s = make_plan(&P, in, ncol, p, np, e, ne, nullptr, nrows);
-  if (s) return s;
-  if (!d_out_rows) return fail(TQ_EINVAL, "d_out_rows is NULL");
-  OutPtrs out{};
-  for (int j = 0; j < ne; j++) {
-    if (!d_out || !d_out[j]) return fail(TQ_EINVAL, "output %d is NULL", j);
-    out.p[j] = d_out[j];
-  }
-  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, stream, d_out_rows, (int64_t)1);
-  TQ_HIP(hipGetLastError());
-  if (nrows == 0) return TQ_OK;
-  hipLaunchKernelGGL(k_filter_project, dim3(stream_blocks(nrows, 8)), dim3(kBlock), 0, stream, P, nrows, out, d_sel,
-                     reinterpret_cast<unsigned long long*>(d_out_rows));
-  TQ_HIP(hipGetLastError());
-  return TQ_OK;
-}
-
-size_t tq_groupby_state_bytes(int64_t domain, int32_t nsum) {
-  if (domain <= 0 || nsum < 0 || nsum > TQ_MAX_SUMS) return 0;
-  int stride = 1 + nsum;
-  return kHeaderBytes + (size_t)choose_replicas(domain, stride) * (size_t)domain * stride * 8;
-}
-
-tq_status tq_groupby_init(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream) {
-  if (!d_state) return fail(TQ_EINVAL, "state is NULL");
-  if (domain <= 0 || domain > (int64_t)1 << 31) return fail(TQ_EINVAL, "domain %lld outside [1, 2^31]", (long long)domain);
-  if (nsum < 0 || nsum > TQ_MAX_SUMS) return fail(TQ_EINVAL, "nsum %d outside [0, %d]", nsum, TQ_MAX_SUMS);
-  size_t need = tq_groupby_state_bytes(domain, nsum);
-  if (bytes < need) return fail(TQ_EINVAL, "state buffer has %zu bytes, needs %zu", bytes, need);
-  int stride = 1 + nsum;
-  int R = choose_replicas(domain, stride);
-  int64_t entries = (int64_t)R * domain * stride;
-  int blocks = (int)std::min<int64_t>((entries + kBlock - 1) / kBlock, 1024);
-  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(kBlock), 0, stream, static_cast<StateHeader*>(d_state), domain,
-                     nsum, R, entries);
-  TQ_HIP(hipGetLastError());
-  return TQ_OK;
-}
-
-}  // extern "C"
-
-namespace tq {
 
 tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T, AggMode* mode, size_t* lds) {
   if (!d_state) return fail(TQ_EINVAL, "group-by state is NULL");
@@ -251,14 +251,71 @@ tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T,
   T->err = &static_cast<StateHeader*>(d_state)->err;
   T->domain = domain;
   T->stride = 1 + nsum;
-  T->replicas = choose_replicas(domain, 1 + nsum);
+  T->rows = state_rows(domain, 1 + nsum);
   *mode = agg_mode(domain, 1 + nsum, &T->log2hcap, lds);
   return TQ_OK;
 }
 
 }  // namespace tq
 
+using namespace tq;
+
 extern "C" {
+
+size_t tq_filter_project_scratch_bytes(int64_t nrows) {
+  if (nrows < 0) return 0;
+  return (size_t)kMaxScanBlocks * 8;
+}
+
+tq_status tq_filter_project(const tq_col* in, int32_t ncol, int64_t nrows, const tq_pred* p, int32_t np,
+                            const tq_expr* e, int32_t ne, int64_t* const* d_out, int64_t* d_sel, int64_t* d_out_rows,
+                            void* d_scratch, size_t scratch_bytes, hipStream_t stream) {
+  RowPlan P;
+  tq_status s = make_plan(&P, in, ncol, p, np, e, ne, nullptr, nrows);
+  if (s) return s;
+  if (!d_out_rows) return fail(TQ_EINVAL, "d_out_rows is NULL");
+  if (!d_scratch || scratch_bytes < tq_filter_project_scratch_bytes(nrows))
+    return fail(TQ_EINVAL, "scratch needs %zu bytes", tq_filter_project_scratch_bytes(nrows));
+  OutPtrs out{};
+  for (int j = 0; j < ne; j++) {
+    if (!d_out || !d_out[j]) return fail(TQ_EINVAL, "output %d is NULL", j);
+    out.p[j] = d_out[j];
+  }
+  if (nrows == 0) {
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, stream, d_out_rows, (int64_t)1);
+    TQ_HIP(hipGetLastError());
+    return TQ_OK;
+  }
+  Range R = split_rows(nrows);
+  int64_t* cnt = static_cast<int64_t*>(d_scratch);
+  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_fp_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, nrows, R.per, cnt));
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, cnt, R.nblk, d_out_rows);
+  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_fp_write<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, nrows, R.per, cnt, out, d_sel));
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+size_t tq_groupby_state_bytes(int64_t domain, int32_t nsum) {
+  if (domain <= 0 || domain > ((int64_t)1 << 31) || nsum < 0 || nsum > TQ_MAX_SUMS) return 0;
+  int stride = 1 + nsum;
+  return kHeaderBytes + (size_t)state_rows(domain, stride) * (size_t)domain * stride * 8;
+}
+
+tq_status tq_groupby_init(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream) {
+  if (!d_state) return fail(TQ_EINVAL, "state is NULL");
+  if (domain <= 0 || domain > (int64_t)1 << 31) return fail(TQ_EINVAL, "domain %lld outside [1, 2^31]", (long long)domain);
+  if (nsum < 0 || nsum > TQ_MAX_SUMS) return fail(TQ_EINVAL, "nsum %d outside [0, %d]", nsum, TQ_MAX_SUMS);
+  size_t need = tq_groupby_state_bytes(domain, nsum);
+  if (bytes < need) return fail(TQ_EINVAL, "state buffer has %zu bytes, needs %zu", bytes, need);
+  int stride = 1 + nsum;
+  int rows = state_rows(domain, stride);
+  int64_t entries = (int64_t)rows * domain * stride;
+  int blocks = (int)std::min<int64_t>((entries + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(kBlock), 0, stream, static_cast<StateHeader*>(d_state), domain,
+                     nsum, rows, entries);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
 
 tq_status tq_groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_t ncol, int64_t nrows,
                          const tq_pred* p, int32_t np, const tq_gkey* key, const tq_expr* sums, int32_t nsum,
@@ -272,10 +329,9 @@ tq_status tq_groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_
   size_t lds;
   if ((s = make_target(d_state, domain, nsum, &T, &mode, &lds))) return s;
   if (nrows == 0) return TQ_OK;
-  dim3 grid(stream_blocks(nrows, 4)), block(kBlock);
-  if (mode == kDense) hipLaunchKernelGGL(k_groupby<kDense>, grid, block, lds, stream, P, nrows, T);
-  else if (mode == kHash) hipLaunchKernelGGL(k_groupby<kHash>, grid, block, lds, stream, P, nrows, T);
-  else hipLaunchKernelGGL(k_groupby<kGlobal>, grid, block, 0, stream, P, nrows, T);
+  dim3 grid(agg_grid(nrows)), block(kAggBlock);
+  TQ_DISPATCH_AGG(mode, ncol, nsum, M, NC, NE,
+                  hipLaunchKernelGGL((k_groupby<M, NC, NE>), grid, block, lds, stream, P, nrows, T));
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -301,11 +357,13 @@ tq_status tq_check(const void* d_obj, hipStream_t stream) {
   return TQ_OK;
 }
 
-tq_status tq_read_peak(const void* d_src, size_t bytes, int64_t* d_sink, hipStream_t stream) {
-  if (!d_src || !d_sink || bytes % 16) return fail(TQ_EINVAL, "bad arguments");
-  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, stream, d_sink, (int64_t)1);
-  hipLaunchKernelGGL(k_read_peak, dim3(device_cu_count() * 8), dim3(kBlock), 0, stream,
-                     static_cast<const v2i64*>(d_src), (int64_t)(bytes / 16), reinterpret_cast<unsigned long long*>(d_sink));
+size_t tq_read_peak_scratch_bytes(void) { return (size_t)8 * 4096; }
+
+tq_status tq_read_peak(const void* d_src, size_t bytes, int64_t* d_partial, hipStream_t stream) {
+  if (!d_src || !d_partial || bytes % 16) return fail(TQ_EINVAL, "bad arguments");
+  int grid = std::min(device_cu_count() * 8, 4096);
+  hipLaunchKernelGGL(k_read_peak, dim3(grid), dim3(kBlock), 0, stream, static_cast<const v2i64*>(d_src),
+                     (int64_t)(bytes / 16), d_partial);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }

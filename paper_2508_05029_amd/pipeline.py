@@ -108,7 +108,6 @@ class JoinAgg:
         tq.join_table_init(self.table)
         self.state = torch.empty(tq.groupby_state_bytes(self.domain, self.nsum), dtype=torch.uint8, device=device)
         self.out = GroupByResult(self.domain, self.nsum, device)
-        self.matches = torch.zeros(1, dtype=torch.int64, device=device)
 
     def build(self, dim: Dict[str, torch.Tensor], n: Optional[int] = None, skip: int = 0, stream=None):
         keys = dim[self.q.build_key]
@@ -116,11 +115,10 @@ class JoinAgg:
         tq.join_build(self.table, keys, dim[self.q.build_payload], n, [dim[c] for c in self.bnames], self.bpreds,
                       self.lf, skip, self.flags, stream)
 
-    def probe(self, fact: Dict[str, torch.Tensor], n: Optional[int] = None, stream=None, count: bool = True):
+    def probe(self, fact: Dict[str, torch.Tensor], n: Optional[int] = None, stream=None):
         keys = fact[self.q.probe_key]
         n = keys.numel() if n is None else n
         tq.join_probe(self.table, keys, n, [fact[c] for c in self.pnames], self.ppreds,
-                      out_count=self.matches if count else None,
                       agg=(self.state, self.domain, self.exprs), stream=stream)
 
     def init_state(self, stream=None):
@@ -130,10 +128,10 @@ class JoinAgg:
         tq.groupby_finalize(self.state, self.out.keys, self.out.count, self.out.sums, self.out.avg,
                             self.out.ngroups, stream)
 
-    def run(self, dim, fact, stream=None, count: bool = True):
+    def run(self, dim, fact, stream=None):
         self.init_state(stream)
         self.build(dim, stream=stream)
-        self.probe(fact, stream=stream, count=count)
+        self.probe(fact, stream=stream)
         self.finalize(stream)
 
     def result(self, stream=None) -> dict:
@@ -141,5 +139,5 @@ class JoinAgg:
         tq.check(self.state, stream)
         r = self.out.host()
         r["keys"] = r["keys"].reshape(-1, 1)
-        r["join_rows"] = int(self.matches.item())
+        r["join_rows"] = int(r["count"].sum())  # every match lands in exactly one group
         return r

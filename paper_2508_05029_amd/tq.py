@@ -69,7 +69,8 @@ def lib():
             "tq_strerror": (ctypes.c_char_p, [_i32]),
             "tq_last_error": (ctypes.c_char_p, []),
             "tq_version": (_i32, []),
-            "tq_filter_project": (_i32, [_vp, _i32, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
+            "tq_filter_project_scratch_bytes": (_sz, [_i64]),
+            "tq_filter_project": (_i32, [_vp, _i32, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
             "tq_hash_partition_scratch_bytes": (_sz, [_i64, _i32]),
             "tq_hash_partition": (_i32, [_vp, _vp, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
             "tq_join_table_bytes": (_sz, [_i64, _f64]),
@@ -81,6 +82,7 @@ def lib():
             "tq_groupby_agg": (_i32, [_vp, _i64, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp]),
             "tq_groupby_finalize": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tq_check": (_i32, [_vp, _vp]),
+            "tq_read_peak_scratch_bytes": (_sz, []),
             "tq_read_peak": (_i32, [_vp, _sz, _vp, _vp]),
             "tq_fill": (_i32, [_vp, _sz, _u32, _vp]),
         }
@@ -155,11 +157,16 @@ def version() -> int:
     return lib().tq_version()
 
 
-def filter_project(in_cols, nrows, ps, es, out, sel, out_rows, stream=None):
+def filter_project_scratch_bytes(nrows: int) -> int:
+    return lib().tq_filter_project_scratch_bytes(nrows)
+
+
+def filter_project(in_cols, nrows, ps, es, out, sel, out_rows, scratch, stream=None):
     E = exprs(es)
     outp = (ctypes.c_void_p * max(1, len(out)))(*[t.data_ptr() for t in out])
     _check(lib().tq_filter_project(cols(in_cols), len(in_cols), nrows, preds(ps), len(ps), E, len(es), outp,
-                                   _ptr(sel), out_rows.data_ptr(), _stream(stream)))
+                                   _ptr(sel), out_rows.data_ptr(), scratch.data_ptr(), _nbytes(scratch),
+                                   _stream(stream)))
 
 
 def hash_partition_scratch_bytes(n: int, log2_fanout: int) -> int:
@@ -226,8 +233,12 @@ def check(obj, stream=None):
     _check(lib().tq_check(obj.data_ptr(), _stream(stream)))
 
 
-def read_peak(src, sink, stream=None):
-    _check(lib().tq_read_peak(src.data_ptr(), _nbytes(src), sink.data_ptr(), _stream(stream)))
+def read_peak_scratch_bytes() -> int:
+    return lib().tq_read_peak_scratch_bytes()
+
+
+def read_peak(src, partial, stream=None):
+    _check(lib().tq_read_peak(src.data_ptr(), _nbytes(src), partial.data_ptr(), _stream(stream)))
 
 
 def fill(dst, pattern=0, stream=None):

@@ -40,11 +40,11 @@ def test_status_strings_and_version():
 
 def test_buffer_sizes():
     # 227,600 filtered dimension rows at load factor 0.5 -> 2^19 slots
-    assert tq.join_table_bytes(227_600, 0.5) == 256 + (1 << 19) * 4 + (1 << 19) * 16
-    assert tq.join_table_bytes(0, 0.5) == 256 + 256 + 64 * 16
+    part = 2048 * 8
+    assert tq.join_table_bytes(227_600, 0.5) == 256 + part + (1 << 19) * 2 + (1 << 19) * 16
+    assert tq.join_table_bytes(0, 0.5) == 256 + part + 256 + 64 * 16
     assert tq.join_table_bytes(10, 0.95) == 0  # load factor above 0.9 is refused
-    b = tq.groupby_state_bytes(25, 1)
-    assert b >= 256 + 25 * 2 * 8 and (b - 256) % (25 * 2 * 8) == 0
+    assert tq.groupby_state_bytes(25, 1) == 256 + 1024 * 25 * 2 * 8  # one private row per workgroup slot
     assert tq.groupby_state_bytes(65536, 1) == 256 + 65536 * 2 * 8
     assert tq.groupby_state_bytes(0, 1) == 0
     assert tq.hash_partition_scratch_bytes(4096 * 10, 8) >= 10 * 256 * 8
@@ -59,18 +59,23 @@ def test_invalid_arguments_are_rejected_synchronously():
     L = tq.lib()
     cols = tq.cols([])
     # too many columns
-    assert L.tq_filter_project(cols, 9, 10, None, 0, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    S = 1 << 20
+    assert L.tq_filter_project(cols, 9, 10, None, 0, None, 0, None, None, FAKE, FAKE, S, None) == tq.TQ_EINVAL
     assert b"ncol" in L.tq_last_error()
     # predicate on a column that does not exist
     c = (tq.Col * 1)(tq.Col(FAKE, tq.TQ_I64))
-    assert L.tq_filter_project(c, 1, 10, tq.preds([(3, 0, 1)]), 1, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_filter_project(c, 1, 10, tq.preds([(3, 0, 1)]), 1, None, 0, None, None, FAKE, FAKE, S,
+                               None) == tq.TQ_EINVAL
     # misaligned column
     c = (tq.Col * 1)(tq.Col(FAKE + 8, tq.TQ_I64))
-    assert L.tq_filter_project(c, 1, 10, None, 0, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_filter_project(c, 1, 10, None, 0, None, 0, None, None, FAKE, FAKE, S, None) == tq.TQ_EINVAL
     assert b"aligned" in L.tq_last_error()
     # bad type
     c = (tq.Col * 1)(tq.Col(FAKE, 3))
-    assert L.tq_filter_project(c, 1, 10, None, 0, None, 0, None, None, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_filter_project(c, 1, 10, None, 0, None, 0, None, None, FAKE, FAKE, S, None) == tq.TQ_EINVAL
+    # scratch too small
+    c = (tq.Col * 1)(tq.Col(FAKE, tq.TQ_I64))
+    assert L.tq_filter_project(c, 1, 10, None, 0, None, 0, None, None, FAKE, FAKE, 8, None) == tq.TQ_EINVAL
     # load factor out of range, skip out of range
     pay = tq.Col(FAKE, tq.TQ_I64)
     assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.0, 0, 0, None) == tq.TQ_EINVAL

