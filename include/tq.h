@@ -203,6 +203,129 @@ tq_status tq_groupby_finalize(const void* d_state, int64_t* d_keys, int64_t* d_c
  * group-by state (TQ_OK if none). */
 tq_status tq_check(const void* d_obj, hipStream_t stream);
 
+/* ------------------------------------------------------------ page pool */
+
+/* A pool of fixed-size page-locked host pages, allocated once when the pool is
+ * created (the fixed-size page-locked buffer pool of Section 3.4; the paper
+ * found per-request pinned allocation slow and fragmenting). Batches are laid
+ * out over chains of pages: the columns of a batch follow each other in the
+ * chain's byte stream, each starting 256-byte aligned, and may straddle page
+ * boundaries; the tail of the last page is unused. Pages also serve as spill
+ * targets and staging buffers. Thread-safe. */
+typedef struct tq_pagepool tq_pagepool;
+
+#define TQ_POOL_PAGEABLE 1u /* ordinary host memory instead of pinned (no GPU needed; slower copies) */
+
+tq_status tq_pagepool_create(size_t page_bytes, int64_t n_pages, uint32_t flags, tq_pagepool** out);
+void tq_pagepool_destroy(tq_pagepool* pool);
+/* Take n pages (all or nothing): page ids to h_page_ids; TQ_ENOMEM if fewer are free. */
+tq_status tq_pagepool_alloc(tq_pagepool* pool, int64_t n, int32_t* h_page_ids);
+void tq_pagepool_free(tq_pagepool* pool, const int32_t* h_page_ids, int64_t n);
+void* tq_pagepool_page(tq_pagepool* pool, int32_t id); /* host address of a page; NULL if id is invalid */
+int64_t tq_pagepool_free_pages(tq_pagepool* pool);
+size_t tq_pagepool_page_bytes(tq_pagepool* pool);
+
+/* Column offsets of a batch of `nrows` rows with the given column types in a
+ * page chain: h_col_offset[c] (bytes from the start of the chain), the bytes
+ * the batch occupies (*h_bytes) and the pages it needs (*h_npages). */
+tq_status tq_batch_layout(int64_t nrows, int32_t ncol, const int32_t* h_types, size_t page_bytes,
+                          int64_t* h_col_offset, size_t* h_bytes, int64_t* h_npages);
+
+typedef struct {
+  int32_t npages;
+  const int32_t* page_ids; /* the chain */
+  int64_t nrows;
+  int32_t ncol;
+  const int64_t* col_offset; /* from tq_batch_layout */
+  const int32_t* col_type;
+} tq_batch;
+
+/* Called once per batch, on the calling thread, after the batch's copy has
+ * been enqueued: `d_cols` point into the device staging slot that will hold
+ * the batch once `compute` reaches the work enqueued next, so the callback
+ * enqueues its kernels on `compute` and returns. A non-OK return stops the
+ * stream and is returned by tq_pagepool_stream. */
+typedef tq_status (*tq_batch_fn)(void* user, int64_t batch_idx, const tq_col* d_cols, int32_t ncol,
+                                 int64_t nrows, hipStream_t compute);
+
+/* Stream batches host -> device with the copies overlapped with compute
+ * (compute-task pre-loading, Section 3.3.3): batch i is copied page by page
+ * into staging slot i mod nslots on `copy` (so straddling columns become
+ * contiguous on the device) while earlier batches compute on `compute`; a
+ * slot is refilled only after the compute work of the batch it held is done.
+ * d_staging holds nslots slots of staging_bytes / nslots bytes each (a slot
+ * must hold the largest batch, rounded to whole pages). Returns after
+ * enqueueing everything; synchronise `compute` to wait for the last batch. */
+tq_status tq_pagepool_stream(tq_pagepool* pool, const tq_batch* batches, int64_t nb, void* d_staging,
+                             size_t staging_bytes, int32_t nslots, tq_batch_fn on_resident, void* user,
+                             hipStream_t copy, hipStream_t compute);
+
+/* ------------------------------------------------------------ budget */
+
+/* Device-memory reservations (Section 3.3.2): a task reserves before it
+ * allocates; a reservation that does not fit returns TQ_ENOMEM (the caller
+ * then spills and retries). Thread-safe, host-only accounting. */
+typedef struct tq_budget tq_budget;
+tq_status tq_budget_create(size_t cap_bytes, tq_budget** out);
+void tq_budget_destroy(tq_budget* b);
+tq_status tq_budget_reserve(tq_budget* b, size_t bytes);
+void tq_budget_release(tq_budget* b, size_t bytes);
+size_t tq_budget_used(const tq_budget* b);
+size_t tq_budget_peak(const tq_budget* b);
+size_t tq_budget_cap(const tq_budget* b);
+
+/* ------------------------------------------------------------ out-of-core join */
+
+/* The partitioned out-of-core join + aggregate (Section 3.2's exchange in
+ * front of a join, run on one GPU): both sides stream from page-pool batches
+ * (tq_pagepool_stream); the dimension is filtered and both sides are hash
+ * partitioned into 2^log2_fanout partitions whose rows are appended to
+ * per-partition holders of fixed-size device chunks reserved from `budget`.
+ * When a reservation fails, the resident chunks of the partition scheduled
+ * latest are copied to pool pages (device -> host, on a stream of their own)
+ * and released (Section 3.3.2: spill the data whose compute is furthest
+ * away). Pass 2 joins partition by partition in order, reloading spilled
+ * chunks one partition ahead of use, and aggregates into `agg` (group key =
+ * dimension payload column). All library device memory counts against the
+ * budget. */
+typedef struct {
+  int32_t dim_key_col;     /* int64 */
+  int32_t dim_payload_col; /* group id */
+  const tq_pred* dim_preds;
+  int32_t dim_np;
+  int32_t fact_key_col;    /* int64 */
+  int32_t fact_keep_mask;  /* fact columns carried through the exchange (bit c = column c; must
+                              include the key and every column the sums read) */
+  const tq_expr* sums;     /* over fact column indices */
+  int32_t nsum;
+  int64_t domain;
+  int32_t log2_fanout;     /* <= 10 */
+  double load_factor;
+  uint32_t join_flags;     /* TQ_UNIQUE_KEYS when the dimension keys are unique */
+  size_t chunk_bytes;      /* device holder chunk size, a divisor of the pool's page size */
+  int32_t nslots;          /* staging slots of the streaming passes (>= 2) */
+} tq_ooc_plan;
+
+typedef struct {
+  int64_t bytes_h2d, bytes_d2h;      /* bytes copied by the streaming passes, spills and reloads */
+  int64_t spilled_chunks, reloaded_chunks;
+  int64_t dim_rows_kept, fact_rows;
+  int64_t peak_budget_bytes;
+  double ms_pass1, ms_pass2, ms_total; /* host wall clock */
+} tq_ooc_stats;
+
+/* d_work: the device memory the call may use (work_bytes >= the budget's
+ * capacity is not required: the call never uses more than the smaller of the
+ * two). d_state: a group-by state initialised by the caller for
+ * (domain, nsum); the call accumulates into it and leaves finalization to the
+ * caller. Spilled chunks use free pool pages. Blocks until the work is done.
+ * Returns TQ_ENOMEM if the budget cannot hold the fixed buffers plus one
+ * partition's working set, or the pool has no page left to spill to. */
+tq_status tq_ooc_join_agg(tq_pagepool* pool, const tq_batch* dim, int64_t n_dim_batches, const tq_batch* fact,
+                          int64_t n_fact_batches, const tq_ooc_plan* plan, tq_budget* budget, void* d_work,
+                          size_t work_bytes, void* d_state, tq_ooc_stats* stats, hipStream_t copy,
+                          hipStream_t compute);
+
 /* ------------------------------------------------------- measurement kernels */
 
 /* Read `bytes` (multiple of 16) and write one partial checksum per workgroup

@@ -1,0 +1,665 @@
+// Out-of-core partitioned join + aggregate over page-pool batches.
+//
+//   pass 1  stream the dimension (filter, hash partition) and the fact table
+//           (hash partition) from pool pages; append each partition's slice
+//           of every batch to that partition's holder, a list of fixed-size
+//           device chunks reserved from the budget
+//   spill   when a chunk cannot be reserved, chunks of the partition that
+//           pass 2 reaches last are copied to pool pages on a stream of
+//           their own and returned to the arena once the copy is done
+//   pass 2  for p = 0, 1, ...: reload p's spilled chunks (and those of p + 1
+//           ahead of use), gather p's dimension rows, build the table, probe
+//           it with each fact chunk of p into the group-by state
+//
+// Holder chunk layout: R rows per chunk, column j of the side at byte offset
+// off[j] (256-byte aligned), so that every chunk can be probed in place.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <vector>
+
+#include "common.h"
+
+namespace tq {
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct CopyDesc {
+  const void* src;
+  void* dst;
+  int64_t n;  // elements
+  int32_t w;  // element bytes
+  int32_t pad;
+};
+
+__global__ __launch_bounds__(256) void k_gather_copy(const CopyDesc* d, int nd) {
+  for (int i = blockIdx.x; i < nd; i += gridDim.x) {
+    const CopyDesc c = d[i];
+    if (c.w == 8) {
+      for (int64_t j = threadIdx.x; j < c.n; j += blockDim.x)
+        static_cast<int64_t*>(c.dst)[j] = static_cast<const int64_t*>(c.src)[j];
+    } else if (c.w == 4) {
+      for (int64_t j = threadIdx.x; j < c.n; j += blockDim.x)
+        static_cast<int32_t*>(c.dst)[j] = static_cast<const int32_t*>(c.src)[j];
+    } else {
+      for (int64_t j = threadIdx.x; j < c.n; j += blockDim.x)
+        static_cast<uint8_t*>(c.dst)[j] = static_cast<const uint8_t*>(c.src)[j];
+    }
+  }
+}
+
+struct ChunkRef {
+  int64_t dev = -1;  // arena chunk id, or -1 when not resident
+  int32_t page = -1, sub = -1;  // spill location
+  int64_t rows = 0;
+};
+
+struct Holder {
+  std::vector<ChunkRef> chunks;
+  int64_t rows = 0;
+};
+
+struct Side {
+  int ncol = 0;
+  int32_t type[TQ_MAX_COLS];
+  int64_t rows_per_chunk = 0;
+  size_t off[TQ_MAX_COLS];
+  std::vector<Holder> parts;
+};
+
+class Driver {
+ public:
+  tq_pagepool* pool;
+  tq_budget* budget;
+  const tq_ooc_plan& plan;
+  hipStream_t copy, compute, spill = nullptr;
+  tq_ooc_stats st{};
+  int nparts;
+  size_t chunk_bytes;
+
+  // workspace
+  char* work;
+  size_t work_cap;
+  size_t fixed_used = 0;
+  size_t reserved_fixed = 0;
+
+  // arena of chunks
+  char* arena = nullptr;
+  int64_t n_chunks = 0;
+  std::vector<int64_t> free_chunks;
+  std::vector<uint8_t> chunk_busy;  // taken for a contiguous region
+  struct Pending {
+    hipEvent_t ev;
+    int64_t chunk;
+  };
+  std::deque<Pending> pending;  // chunks to return once an event completes
+
+  // spill store
+  std::vector<int32_t> spill_pages;
+  int32_t cur_page = -1, cur_sub = 0, subs_per_page = 0;
+
+  Side dim, fact;
+  int phase = 1;     // 1: partitioning, 2: joining
+  int pin_lo = 0, pin_hi = -1;  // partitions that must stay resident in pass 2
+
+  // descriptors
+  CopyDesc* h_desc = nullptr;
+  CopyDesc* d_desc = nullptr;
+  int max_desc = 0;
+  int64_t* h_counts = nullptr;  // pinned: offsets or counts read back per batch
+
+  Driver(tq_pagepool* p, tq_budget* b, const tq_ooc_plan& pl, hipStream_t c, hipStream_t k, void* w, size_t wb)
+      : pool(p), budget(b), plan(pl), copy(c), compute(k), work(static_cast<char*>(w)), work_cap(wb) {
+    nparts = 1 << plan.log2_fanout;
+    chunk_bytes = plan.chunk_bytes;
+  }
+
+  ~Driver() {
+    if (spill) {
+      (void)hipStreamSynchronize(spill);
+      (void)hipStreamDestroy(spill);
+    }
+    (void)hipStreamSynchronize(compute);
+    (void)hipStreamSynchronize(copy);
+    for (auto& q : pending) (void)hipEventDestroy(q.ev);
+    if (!spill_pages.empty()) tq_pagepool_free(pool, spill_pages.data(), (int64_t)spill_pages.size());
+    if (h_desc) (void)hipHostFree(h_desc);
+    if (h_counts) (void)hipHostFree(h_counts);
+    if (reserved_fixed) tq_budget_release(budget, reserved_fixed);
+    if (chunks_out) tq_budget_release(budget, (size_t)chunks_out * chunk_bytes);
+  }
+
+  int64_t chunks_out = 0;  // chunks taken from the arena and not yet returned (each holds a reservation)
+
+  // Carve `bytes` from the front of the workspace, reserved from the budget.
+  tq_status carve(size_t bytes, void** out) {
+    bytes = align_up(bytes, kAlign);
+    if (fixed_used + bytes > work_cap) return fail(TQ_ENOMEM, "workspace too small for the fixed buffers");
+    tq_status s = tq_budget_reserve(budget, bytes);
+    if (s) return fail(TQ_ENOMEM, "budget cannot hold the fixed buffers (%zu bytes more)", bytes);
+    reserved_fixed += bytes;
+    *out = work + fixed_used;
+    fixed_used += bytes;
+    return TQ_OK;
+  }
+
+  void setup_side(Side& s, int ncol, const int32_t* types) {
+    s.ncol = ncol;
+    size_t row = 0;
+    for (int c = 0; c < ncol; c++) {
+      s.type[c] = types[c];
+      row += types[c];
+    }
+    int64_t R = (int64_t)((chunk_bytes - kAlign * ncol) / row) / 64 * 64;
+    s.rows_per_chunk = R;
+    size_t off = 0;
+    for (int c = 0; c < ncol; c++) {
+      s.off[c] = off;
+      off = align_up(off + (size_t)R * s.type[c], kAlign);
+    }
+    s.parts.assign(nparts, Holder());
+  }
+
+  char* chunk_ptr(int64_t id) { return arena + (size_t)id * chunk_bytes; }
+
+  // -------------------------------------------------------------- chunks
+
+  tq_status reclaim_one(bool wait) {
+    if (pending.empty()) return TQ_ENOMEM;
+    Pending q = pending.front();
+    if (wait) TQ_HIP(hipEventSynchronize(q.ev));
+    else if (hipEventQuery(q.ev) != hipSuccess) return TQ_ENOMEM;
+    pending.pop_front();
+    (void)hipEventDestroy(q.ev);
+    free_chunks.push_back(q.chunk);
+    tq_budget_release(budget, chunk_bytes);
+    chunks_out--;
+    return TQ_OK;
+  }
+
+  // Returns chunk `id` to the arena once the work enqueued so far on `s` is done.
+  tq_status retire(int64_t id, hipStream_t s) {
+    hipEvent_t ev;
+    TQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    TQ_HIP(hipEventRecord(ev, s));
+    pending.push_back(Pending{ev, id});
+    return TQ_OK;
+  }
+
+  bool spillable(int p, const Holder& h, size_t idx) const {
+    const ChunkRef& c = h.chunks[idx];
+    if (c.dev < 0) return false;
+    if (phase == 1) return idx + 1 < h.chunks.size();  // the tail chunk still receives appends
+    return p < pin_lo || p > pin_hi;
+  }
+
+  // Spill one resident chunk of the partition that pass 2 reaches last.
+  tq_status spill_one(bool* done) {
+    *done = false;
+    for (int p = nparts - 1; p >= 0; p--) {
+      if (phase == 2 && p <= pin_hi) break;  // earlier partitions are done or pinned
+      for (Side* s : {&fact, &dim}) {
+        Holder& h = s->parts[p];
+        for (size_t i = h.chunks.size(); i-- > 0;) {
+          if (!spillable(p, h, i)) continue;
+          TQ_HIP(spill_chunk(h.chunks[i]));
+          *done = true;
+          return TQ_OK;
+        }
+      }
+    }
+    return TQ_OK;
+  }
+
+  hipError_t spill_chunk(ChunkRef& c) {
+    if (!spill) {
+      hipError_t e = hipStreamCreateWithFlags(&spill, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    if (cur_page < 0 || cur_sub == subs_per_page) {
+      int32_t id;
+      if (tq_pagepool_alloc(pool, 1, &id) != TQ_OK) return hipErrorOutOfMemory;
+      spill_pages.push_back(id);
+      cur_page = id;
+      cur_sub = 0;
+    }
+    // the spill copy follows everything already enqueued on the compute stream
+    hipEvent_t fence;
+    hipError_t e = hipEventCreateWithFlags(&fence, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(fence, compute)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(spill, fence, 0)) != hipSuccess) return e;
+    (void)hipEventDestroy(fence);
+    char* host = static_cast<char*>(tq_pagepool_page(pool, cur_page)) + (size_t)cur_sub * chunk_bytes;
+    if ((e = hipMemcpyAsync(host, chunk_ptr(c.dev), chunk_bytes, hipMemcpyDeviceToHost, spill)) != hipSuccess) return e;
+    st.bytes_d2h += (int64_t)chunk_bytes;
+    st.spilled_chunks++;
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev, spill)) != hipSuccess) return e;
+    pending.push_back(Pending{ev, c.dev});
+    c.dev = -1;
+    c.page = cur_page;
+    c.sub = cur_sub++;
+    return hipSuccess;
+  }
+
+  // A free chunk, reserved from the budget; spills when none is available.
+  tq_status take_chunk(int64_t* out) {
+    for (int guard = 0; guard < (1 << 30); guard++) {
+      while (reclaim_one(false) == TQ_OK) {
+      }
+      if (!free_chunks.empty() && tq_budget_reserve(budget, chunk_bytes) == TQ_OK) {
+        *out = free_chunks.back();
+        free_chunks.pop_back();
+        chunks_out++;
+        return TQ_OK;
+      }
+      if (!pending.empty()) {
+        tq_status s = reclaim_one(true);
+        if (s) return s;
+        continue;
+      }
+      bool spilled = false;
+      tq_status s = spill_one(&spilled);
+      if (s) return s;
+      if (!spilled) return fail(TQ_ENOMEM, "device budget exhausted and nothing left to spill");
+    }
+    return fail(TQ_ENOMEM, "chunk allocation did not converge");
+  }
+
+  tq_status reload(ChunkRef& c) {
+    if (c.dev >= 0) return TQ_OK;
+    int64_t id;
+    tq_status s = take_chunk(&id);
+    if (s) return s;
+    const char* host = static_cast<const char*>(tq_pagepool_page(pool, c.page)) + (size_t)c.sub * chunk_bytes;
+    TQ_HIP(hipMemcpyAsync(chunk_ptr(id), host, chunk_bytes, hipMemcpyHostToDevice, copy));
+    st.bytes_h2d += (int64_t)chunk_bytes;
+    st.reloaded_chunks++;
+    c.dev = id;
+    return TQ_OK;
+  }
+
+  // -------------------------------------------------------------- appends
+
+  std::vector<CopyDesc> descs;
+
+  // Append rows [off[p], off[p+1]) of every partition p from the partitioned
+  // columns `src` (side column j at src[j]) to the holders.
+  tq_status append(Side& s, char* const* src, const int64_t* off) {
+    descs.clear();
+    for (int p = 0; p < nparts; p++) {
+      int64_t at = off[p], left = off[p + 1] - off[p];
+      Holder& h = s.parts[p];
+      h.rows += left;
+      while (left > 0) {
+        if (h.chunks.empty() || h.chunks.back().rows == s.rows_per_chunk) {
+          int64_t id;
+          tq_status e = take_chunk(&id);
+          if (e) return e;
+          ChunkRef c;
+          c.dev = id;
+          h.chunks.push_back(c);
+        }
+        ChunkRef& c = h.chunks.back();
+        int64_t m = std::min(left, s.rows_per_chunk - c.rows);
+        for (int j = 0; j < s.ncol; j++) {
+          int w = s.type[j];
+          descs.push_back(CopyDesc{src[j] + (size_t)at * w, chunk_ptr(c.dev) + s.off[j] + (size_t)c.rows * w, m, w, 0});
+        }
+        c.rows += m;
+        at += m;
+        left -= m;
+      }
+    }
+    return launch_copies();
+  }
+
+  tq_status launch_copies() {
+    if (descs.empty()) return TQ_OK;
+    if ((int)descs.size() > max_desc) return fail(TQ_EINVAL, "too many copy descriptors");
+    // the previous batch's descriptors were consumed before the host read this batch's offsets
+    memcpy(h_desc, descs.data(), descs.size() * sizeof(CopyDesc));
+    TQ_HIP(hipMemcpyAsync(d_desc, h_desc, descs.size() * sizeof(CopyDesc), hipMemcpyHostToDevice, compute));
+    int grid = (int)std::min<size_t>(descs.size(), 2048);
+    hipLaunchKernelGGL(k_gather_copy, dim3(grid), dim3(256), 0, compute, d_desc, (int)descs.size());
+    TQ_HIP(hipGetLastError());
+    return TQ_OK;
+  }
+
+  // Waits for `compute` and reads n int64 values from device memory.
+  tq_status read_back(const int64_t* d, int64_t n) {
+    TQ_HIP(hipMemcpyAsync(h_counts, d, (size_t)n * 8, hipMemcpyDeviceToHost, compute));
+    TQ_HIP(hipStreamSynchronize(compute));
+    return TQ_OK;
+  }
+
+  // -------------------------------------------------------------- passes
+
+  // pass-1 buffers
+  int64_t* d_off = nullptr;
+  void* d_part_scratch = nullptr;
+  size_t part_scratch_bytes = 0;
+  char* tmp_a = nullptr;  // dimension filter output: key, payload (int64)
+  char* tmp_b = nullptr;  // partition output
+  size_t tmp_b_bytes = 0;
+  void* fp_scratch = nullptr;
+  int64_t* d_count = nullptr;
+  int64_t max_dim_rows = 0, max_fact_rows = 0;
+  int fact_map[TQ_MAX_COLS];  // fact column -> side column (or -1)
+  int fact_src[TQ_MAX_COLS];  // side column -> fact column
+
+  static tq_status on_dim(void* user, int64_t, const tq_col* cols, int32_t ncol, int64_t nrows, hipStream_t) {
+    return static_cast<Driver*>(user)->dim_batch(cols, ncol, nrows);
+  }
+  static tq_status on_fact(void* user, int64_t, const tq_col* cols, int32_t ncol, int64_t nrows, hipStream_t) {
+    return static_cast<Driver*>(user)->fact_batch(cols, ncol, nrows);
+  }
+
+  tq_status dim_batch(const tq_col* cols, int32_t ncol, int64_t nrows) {
+    if (nrows == 0) return TQ_OK;
+    // sigma + pi: keep (key, payload) of the rows that pass, as int64
+    tq_expr e[2];
+    memset(e, 0, sizeof e);
+    e[0].nf = 1;
+    e[0].f[0] = tq_factor{plan.dim_key_col, 1, 0};
+    e[1].nf = 1;
+    e[1].f[0] = tq_factor{plan.dim_payload_col, 1, 0};
+    int64_t* outs[2] = {reinterpret_cast<int64_t*>(tmp_a), reinterpret_cast<int64_t*>(tmp_a + align_up((size_t)nrows * 8, kAlign))};
+    tq_status s = tq_filter_project(cols, ncol, nrows, plan.dim_preds, plan.dim_np, e, 2, outs, nullptr, d_count, fp_scratch,
+                                    tq_filter_project_scratch_bytes(nrows), compute);
+    if (s) return s;
+    if ((s = read_back(d_count, 1))) return s;
+    const int64_t kept = h_counts[0];
+    st.dim_rows_kept += kept;
+    char* out_key = tmp_b;
+    char* out_pay = tmp_b + align_up((size_t)kept * 8, kAlign);
+    tq_col pay = {outs[1], TQ_I64};
+    void* outp[1] = {out_pay};
+    s = tq_hash_partition(outs[0], &pay, 1, kept, plan.log2_fanout, 0, reinterpret_cast<int64_t*>(out_key), outp, d_off,
+                          d_part_scratch, part_scratch_bytes, compute);
+    if (s) return s;
+    if ((s = read_back(d_off, nparts + 1))) return s;
+    char* src[2] = {out_key, out_pay};
+    return append(dim, src, h_counts);
+  }
+
+  tq_status fact_batch(const tq_col* cols, int32_t ncol, int64_t nrows) {
+    if (nrows == 0) return TQ_OK;
+    st.fact_rows += nrows;
+    char* src[TQ_MAX_COLS];
+    tq_col pay[TQ_MAX_COLS];
+    void* outp[TQ_MAX_COLS];
+    size_t off = 0;
+    for (int j = 0; j < fact.ncol; j++) {
+      src[j] = tmp_b + off;
+      off = align_up(off + (size_t)nrows * fact.type[j], kAlign);
+      if (j > 0) {
+        pay[j - 1] = cols[fact_src[j]];
+        outp[j - 1] = src[j];
+      }
+    }
+    (void)ncol;
+    tq_status s = tq_hash_partition(static_cast<const int64_t*>(cols[plan.fact_key_col].data), pay, fact.ncol - 1, nrows,
+                                    plan.log2_fanout, 0, reinterpret_cast<int64_t*>(src[0]), outp, d_off, d_part_scratch,
+                                    part_scratch_bytes, compute);
+    if (s) return s;
+    if ((s = read_back(d_off, nparts + 1))) return s;
+    return append(fact, src, h_counts);
+  }
+
+  tq_status run(const tq_batch* dimb, int64_t nd, const tq_batch* factb, int64_t nf, void* d_state) {
+    auto t0 = std::chrono::steady_clock::now();
+    // ---- sides
+    int32_t dim_types[2] = {TQ_I64, TQ_I64};
+    setup_side(dim, 2, dim_types);
+    int32_t ft[TQ_MAX_COLS];
+    int nk = 0;
+    const tq_batch& f0 = factb[0];
+    for (int c = 0; c < TQ_MAX_COLS; c++) fact_map[c] = -1;
+    ft[nk] = f0.col_type[plan.fact_key_col];
+    fact_map[plan.fact_key_col] = nk;
+    fact_src[nk++] = plan.fact_key_col;
+    for (int c = 0; c < f0.ncol; c++)
+      if (((plan.fact_keep_mask >> c) & 1) && c != plan.fact_key_col) {
+        ft[nk] = f0.col_type[c];
+        fact_map[c] = nk;
+        fact_src[nk++] = c;
+      }
+    setup_side(fact, nk, ft);
+    if (dim.rows_per_chunk < 64 || fact.rows_per_chunk < 64) return fail(TQ_EINVAL, "chunk_bytes too small for a row");
+    subs_per_page = (int32_t)(tq_pagepool_page_bytes(pool) / chunk_bytes);
+
+    // ---- fixed buffers
+    size_t max_batch = 0;
+    for (int64_t i = 0; i < nd; i++) {
+      max_batch = std::max(max_batch, (size_t)dimb[i].npages * tq_pagepool_page_bytes(pool));
+      max_dim_rows = std::max(max_dim_rows, dimb[i].nrows);
+    }
+    for (int64_t i = 0; i < nf; i++) {
+      max_batch = std::max(max_batch, (size_t)factb[i].npages * tq_pagepool_page_bytes(pool));
+      max_fact_rows = std::max(max_fact_rows, factb[i].nrows);
+    }
+    const int64_t max_rows = std::max(max_dim_rows, max_fact_rows);
+    void* staging;
+    tq_status s;
+    if ((s = carve(max_batch * plan.nslots, &staging))) return s;
+    void* p;
+    if ((s = carve(2 * align_up((size_t)max_dim_rows * 8, kAlign), &p))) return s;
+    tmp_a = static_cast<char*>(p);
+    size_t fact_row = 0;
+    for (int j = 0; j < fact.ncol; j++) fact_row += fact.type[j];
+    tmp_b_bytes = std::max((size_t)max_fact_rows * fact_row + kAlign * fact.ncol, 2 * align_up((size_t)max_dim_rows * 8, kAlign));
+    if ((s = carve(tmp_b_bytes, &p))) return s;
+    tmp_b = static_cast<char*>(p);
+    part_scratch_bytes = tq_hash_partition_scratch_bytes(max_rows, plan.log2_fanout);
+    if ((s = carve(part_scratch_bytes, &d_part_scratch))) return s;
+    if ((s = carve((size_t)(nparts + 1) * 8, &p))) return s;
+    d_off = static_cast<int64_t*>(p);
+    if ((s = carve(tq_filter_project_scratch_bytes(max_dim_rows) + 64, &fp_scratch))) return s;
+    if ((s = carve(64, &p))) return s;
+    d_count = static_cast<int64_t*>(p);
+    max_desc = nparts * (TQ_MAX_COLS + 1) * 4 + 64;
+    if ((s = carve((size_t)max_desc * sizeof(CopyDesc), &p))) return s;
+    d_desc = static_cast<CopyDesc*>(p);
+    TQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc), (size_t)max_desc * sizeof(CopyDesc), hipHostMallocDefault));
+    TQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_counts), (size_t)(nparts + 8) * 8, hipHostMallocDefault));
+
+    // ---- arena: the rest of the workspace, within the budget
+    size_t cap_left = tq_budget_cap(budget) > tq_budget_used(budget) ? tq_budget_cap(budget) - tq_budget_used(budget) : 0;
+    size_t room = std::min(work_cap - align_up(fixed_used, chunk_bytes), cap_left);
+    arena = work + align_up(fixed_used, chunk_bytes);
+    n_chunks = (int64_t)(room / chunk_bytes);
+    if (n_chunks < 4) return fail(TQ_ENOMEM, "budget leaves room for %lld chunks", (long long)n_chunks);
+    for (int64_t i = n_chunks - 1; i >= 0; i--) free_chunks.push_back(i);
+
+    // ---- pass 1
+    phase = 1;
+    if ((s = tq_pagepool_stream(pool, dimb, nd, staging, max_batch * plan.nslots, plan.nslots, on_dim, this, copy, compute)))
+      return s;
+    for (int64_t i = 0; i < nd; i++) st.bytes_h2d += batch_bytes(dimb[i]);
+    if ((s = tq_pagepool_stream(pool, factb, nf, staging, max_batch * plan.nslots, plan.nslots, on_fact, this, copy, compute)))
+      return s;
+    for (int64_t i = 0; i < nf; i++) st.bytes_h2d += batch_bytes(factb[i]);
+    TQ_HIP(hipStreamSynchronize(compute));
+    auto t1 = std::chrono::steady_clock::now();
+
+    // ---- pass 2 buffers: the largest dimension partition, gathered, and its table
+    int64_t max_part = 1;
+    for (int q = 0; q < nparts; q++) max_part = std::max(max_part, dim.parts[q].rows);
+    size_t gather_bytes = 2 * align_up((size_t)max_part * 8, kAlign);
+    size_t table_bytes = tq_join_table_bytes(max_part, plan.load_factor);
+    char* region;
+    if ((s = take_region(gather_bytes + table_bytes, &region))) return s;
+    int64_t* g_key = reinterpret_cast<int64_t*>(region);
+    int64_t* g_pay = reinterpret_cast<int64_t*>(region + align_up((size_t)max_part * 8, kAlign));
+    void* table = region + gather_bytes;
+    if ((s = tq_join_table_init(table, table_bytes, compute))) return s;
+
+    // ---- pass 2
+    phase = 2;
+    tq_agg agg{d_state, plan.domain, plan.sums, plan.nsum};
+    hipEvent_t loaded;
+    TQ_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
+    for (int q = 0; q < nparts; q++) {
+      pin_lo = q;
+      pin_hi = q;  // chunks prefetched for later partitions may be spilled again if q needs the room
+      if ((s = make_resident(q))) return s;
+      TQ_HIP(hipEventRecord(loaded, copy));
+      TQ_HIP(hipStreamWaitEvent(compute, loaded, 0));
+      // gather the partition's dimension rows
+      descs.clear();
+      int64_t at = 0;
+      for (ChunkRef& c : dim.parts[q].chunks) {
+        descs.push_back(CopyDesc{chunk_ptr(c.dev) + dim.off[0], g_key + at, c.rows, 8, 0});
+        descs.push_back(CopyDesc{chunk_ptr(c.dev) + dim.off[1], g_pay + at, c.rows, 8, 0});
+        at += c.rows;
+      }
+      if ((s = launch_copies())) return s;
+      tq_col pc = {g_pay, TQ_I64};
+      if ((s = tq_join_build(table, table_bytes, g_key, pc, at, nullptr, 0, nullptr, 0, plan.load_factor,
+                             plan.log2_fanout, plan.join_flags, compute)))
+        return s;
+      for (ChunkRef& c : fact.parts[q].chunks) {
+        tq_col cols[TQ_MAX_COLS];
+        int ncols = 0;
+        for (int fc = 0; fc < TQ_MAX_COLS; fc++) {
+          int j = fact_map[fc];
+          if (j >= 0) ncols = fc + 1;
+          cols[fc].data = chunk_ptr(c.dev) + (j >= 0 ? fact.off[j] : fact.off[0]);
+          cols[fc].type = j >= 0 ? fact.type[j] : fact.type[0];
+        }
+        if ((s = tq_join_probe(table, reinterpret_cast<const int64_t*>(chunk_ptr(c.dev) + fact.off[0]), c.rows, cols, ncols,
+                               nullptr, 0, nullptr, nullptr, 0, nullptr, &agg, compute)))
+          return s;
+      }
+      // partition q is done once the compute stream passes this point
+      for (Side* sd : {&dim, &fact})
+        for (ChunkRef& c : sd->parts[q].chunks) {
+          if ((s = retire(c.dev, compute))) return s;
+          c.dev = -1;
+        }
+      if (q + 1 < nparts) {
+        // reload ahead of use, overlapping q's compute; if the budget cannot
+        // hold both partitions, the rest of q + 1 is loaded when it is reached
+        pin_lo = q;
+        pin_hi = q + 1;
+        s = make_resident(q + 1);
+        if (s == TQ_ENOMEM) s = TQ_OK;
+        if (s) return s;
+      }
+      // the next gather reuses the descriptor buffers
+      TQ_HIP(hipStreamSynchronize(compute));
+    }
+    (void)hipEventDestroy(loaded);
+    TQ_HIP(hipStreamSynchronize(compute));
+    auto t2 = std::chrono::steady_clock::now();
+    st.ms_pass1 = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    st.ms_pass2 = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    st.ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
+    st.peak_budget_bytes = (int64_t)tq_budget_peak(budget);
+    return TQ_OK;
+  }
+
+  static int64_t batch_bytes(const tq_batch& b) {
+    int64_t end = 0;
+    for (int c = 0; c < b.ncol; c++) end = std::max(end, b.col_offset[c] + b.nrows * b.col_type[c]);
+    return end;
+  }
+
+  tq_status make_resident(int q) {
+    for (Side* sd : {&dim, &fact})
+      for (ChunkRef& c : sd->parts[q].chunks) {
+        tq_status s = reload(c);
+        if (s) return s;
+      }
+    return TQ_OK;
+  }
+
+  // A contiguous run of arena chunks (reserved from the budget) for pass-2 buffers.
+  tq_status take_region(size_t bytes, char** out) {
+    int64_t need = (int64_t)((bytes + chunk_bytes - 1) / chunk_bytes);
+    for (int attempt = 0; attempt < 4; attempt++) {
+      while (reclaim_one(false) == TQ_OK) {
+      }
+      std::vector<uint8_t> is_free((size_t)n_chunks, 0);
+      for (int64_t id : free_chunks) is_free[(size_t)id] = 1;
+      int64_t run = 0;
+      for (int64_t id = n_chunks - 1; id >= 0; id--) {
+        run = is_free[(size_t)id] ? run + 1 : 0;
+        if (run == need) {
+          if (tq_budget_reserve(budget, (size_t)need * chunk_bytes) != TQ_OK) {
+            run = 0;
+            break;
+          }
+          std::vector<int64_t> rest;
+          for (int64_t f : free_chunks)
+            if (f < id || f >= id + need) rest.push_back(f);
+          free_chunks.swap(rest);
+          reserved_fixed += (size_t)need * chunk_bytes;
+          *out = chunk_ptr(id);
+          return TQ_OK;
+        }
+      }
+      // make room: spill pass-1 data of the last partitions, then retry
+      phase = 2;
+      pin_lo = 0;
+      pin_hi = -1;
+      for (int64_t k = 0; k < need; k++) {
+        bool spilled = false;
+        tq_status s = spill_one(&spilled);
+        if (s || !spilled) break;
+      }
+      while (!pending.empty())
+        if (reclaim_one(true)) break;
+    }
+    return fail(TQ_ENOMEM, "no contiguous %zu bytes for the pass-2 buffers", bytes);
+  }
+};
+
+}  // namespace
+}  // namespace tq
+
+extern "C" tq_status tq_ooc_join_agg(tq_pagepool* pool, const tq_batch* dim, int64_t nd, const tq_batch* fact, int64_t nf,
+                                     const tq_ooc_plan* plan, tq_budget* budget, void* d_work, size_t work_bytes,
+                                     void* d_state, tq_ooc_stats* stats, hipStream_t copy, hipStream_t compute) {
+  using tq::fail;
+  if (!pool || !plan || !budget || !d_work || !d_state) return fail(TQ_EINVAL, "NULL argument");
+  if (nd < 0 || nf < 1 || (nd > 0 && !dim) || !fact) return fail(TQ_EINVAL, "batch lists");
+  if (plan->log2_fanout < 0 || plan->log2_fanout > 10) return fail(TQ_EINVAL, "log2_fanout outside [0, 10]");
+  if (plan->nslots < 2 || plan->nslots > 8) return fail(TQ_EINVAL, "nslots outside [2, 8]");
+  size_t pb = tq_pagepool_page_bytes(pool);
+  if (plan->chunk_bytes < 65536 || plan->chunk_bytes % 256 || pb % plan->chunk_bytes)
+    return fail(TQ_EINVAL, "chunk_bytes must be a multiple of 256, at least 64 KiB, and divide the page size");
+  for (int64_t i = 0; i < nf; i++) {
+    const tq_batch& b = fact[i];
+    if (b.ncol != fact[0].ncol || b.ncol > TQ_MAX_COLS) return fail(TQ_EINVAL, "fact batches differ in columns");
+    for (int c = 0; c < b.ncol; c++)
+      if (b.col_type[c] != fact[0].col_type[c]) return fail(TQ_EINVAL, "fact batches differ in column types");
+  }
+  const tq_batch& f0 = fact[0];
+  if (plan->fact_key_col < 0 || plan->fact_key_col >= f0.ncol || f0.col_type[plan->fact_key_col] != TQ_I64)
+    return fail(TQ_EINVAL, "fact key column");
+  if (!((plan->fact_keep_mask >> plan->fact_key_col) & 1)) return fail(TQ_EINVAL, "fact_keep_mask must include the key");
+  for (int j = 0; j < plan->nsum; j++)
+    for (int f = 0; f < plan->sums[j].nf; f++) {
+      int c = plan->sums[j].f[f].col;
+      if (c >= 0 && (c >= f0.ncol || !((plan->fact_keep_mask >> c) & 1)))
+        return fail(TQ_EINVAL, "sum %d reads fact column %d, which is not kept", j, c);
+    }
+  for (int64_t i = 0; i < nd; i++) {
+    const tq_batch& b = dim[i];
+    if (plan->dim_key_col < 0 || plan->dim_key_col >= b.ncol || b.col_type[plan->dim_key_col] != TQ_I64 ||
+        plan->dim_payload_col < 0 || plan->dim_payload_col >= b.ncol)
+      return fail(TQ_EINVAL, "dimension key/payload column");
+  }
+  tq::Driver d(pool, budget, *plan, copy, compute, d_work, work_bytes);
+  tq_status s = d.run(dim, nd, fact, nf, d_state);
+  if (stats) *stats = d.st;
+  return s;
+}

@@ -7,6 +7,7 @@ the library calls on a stream. It does no arithmetic of its own.
 """
 from __future__ import annotations
 
+import ctypes
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -140,4 +141,57 @@ class JoinAgg:
         r = self.out.host()
         r["keys"] = r["keys"].reshape(-1, 1)
         r["join_rows"] = int(r["count"].sum())  # every match lands in exactly one group
+        return r
+
+
+class OocJoinAgg:
+    """The out-of-core join + aggregate over page-pool tables (tq_ooc_join_agg).
+
+    keep_all: carry every fact column through the exchange (as a generic
+    exchange that does not know which columns the join needs would); else only
+    the key and the columns the sums read."""
+
+    def __init__(self, query, dim_table, fact_table, budget_bytes: int, log2_fanout: int = 8,
+                 load_factor: float = 0.5, chunk_bytes: int = 4 << 20, nslots: int = 3, keep_all: bool = True,
+                 unique: bool = True, device="cuda"):
+        self.q = query
+        self.dim, self.fact = dim_table, fact_table
+        dn, fn = dim_table.names, fact_table.names
+        self._preds = tq.preds([(dn.index(p.col), p.lo, p.hi) for p in query.build_preds])
+        self._sums = tq.exprs([[(-1 if f.col is None else fn.index(f.col), f.sign, f.add) for f in e]
+                               for e in query.sums])
+        keep = (1 << len(fn)) - 1 if keep_all else 0
+        keep |= 1 << fn.index(query.probe_key)
+        for e in query.sums:
+            for f in e:
+                if f.col is not None:
+                    keep |= 1 << fn.index(f.col)
+        self.plan = tq.OocPlan(dn.index(query.build_key), dn.index(query.build_payload),
+                               ctypes.cast(self._preds, ctypes.POINTER(tq.PredS)), len(query.build_preds),
+                               fn.index(query.probe_key), keep, ctypes.cast(self._sums, ctypes.POINTER(tq.ExprS)),
+                               len(query.sums), query.domain, log2_fanout, load_factor,
+                               tq.TQ_UNIQUE_KEYS if unique else 0, chunk_bytes, nslots)
+        self.budget = tq.Budget(budget_bytes)
+        self.domain, self.nsum = query.domain, len(query.sums)
+        # the group-by state and its outputs live outside the budgeted workspace
+        self.state = torch.empty(tq.groupby_state_bytes(self.domain, self.nsum), dtype=torch.uint8, device=device)
+        self.out = GroupByResult(self.domain, self.nsum, device)
+        self.work = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
+        self.copy_stream = torch.cuda.Stream()
+        self.stats = None
+
+    def run(self):
+        stream = torch.cuda.current_stream()
+        tq.groupby_init(self.state, self.domain, self.nsum, stream)
+        self.stats = tq.ooc_join_agg(self.dim.pool, self.dim.c_batches(), self.fact.c_batches(), self.plan,
+                                     self.budget, self.work, self.state, self.copy_stream, stream)
+        tq.groupby_finalize(self.state, self.out.keys, self.out.count, self.out.sums, self.out.avg, self.out.ngroups,
+                            stream)
+        return self.stats
+
+    def result(self) -> dict:
+        tq.check(self.state)
+        r = self.out.host()
+        r["keys"] = r["keys"].reshape(-1, 1)
+        r["join_rows"] = int(r["count"].sum())
         return r

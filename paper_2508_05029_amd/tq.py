@@ -243,3 +243,179 @@ def read_peak(src, partial, stream=None):
 
 def fill(dst, pattern=0, stream=None):
     _check(lib().tq_fill(dst.data_ptr(), _nbytes(dst), pattern, _stream(stream)))
+
+
+# ------------------------------------------------------------------ page pool, budget, streaming
+
+class Batch(ctypes.Structure):
+    _fields_ = [("npages", ctypes.c_int32), ("page_ids", ctypes.POINTER(ctypes.c_int32)), ("nrows", ctypes.c_int64),
+                ("ncol", ctypes.c_int32), ("col_offset", ctypes.POINTER(ctypes.c_int64)),
+                ("col_type", ctypes.POINTER(ctypes.c_int32))]
+
+
+class OocPlan(ctypes.Structure):
+    _fields_ = [("dim_key_col", ctypes.c_int32), ("dim_payload_col", ctypes.c_int32),
+                ("dim_preds", ctypes.POINTER(PredS)), ("dim_np", ctypes.c_int32),
+                ("fact_key_col", ctypes.c_int32), ("fact_keep_mask", ctypes.c_int32),
+                ("sums", ctypes.POINTER(ExprS)), ("nsum", ctypes.c_int32), ("domain", ctypes.c_int64),
+                ("log2_fanout", ctypes.c_int32), ("load_factor", ctypes.c_double), ("join_flags", ctypes.c_uint32),
+                ("chunk_bytes", ctypes.c_size_t), ("nslots", ctypes.c_int32)]
+
+
+class OocStats(ctypes.Structure):
+    _fields_ = [("bytes_h2d", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64), ("spilled_chunks", ctypes.c_int64),
+                ("reloaded_chunks", ctypes.c_int64), ("dim_rows_kept", ctypes.c_int64), ("fact_rows", ctypes.c_int64),
+                ("peak_budget_bytes", ctypes.c_int64), ("ms_pass1", ctypes.c_double), ("ms_pass2", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+BATCH_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Col), ctypes.c_int32,
+                            ctypes.c_int64, ctypes.c_void_p)
+TQ_POOL_PAGEABLE = 1
+
+_more_sig = {
+    "tq_pagepool_create": (_i32, [_sz, _i64, _u32, ctypes.POINTER(ctypes.c_void_p)]),
+    "tq_pagepool_destroy": (None, [_vp]),
+    "tq_pagepool_alloc": (_i32, [_vp, _i64, _vp]),
+    "tq_pagepool_free": (None, [_vp, _vp, _i64]),
+    "tq_pagepool_page": (_vp, [_vp, _i32]),
+    "tq_pagepool_free_pages": (_i64, [_vp]),
+    "tq_pagepool_page_bytes": (_sz, [_vp]),
+    "tq_batch_layout": (_i32, [_i64, _i32, _vp, _sz, _vp, ctypes.POINTER(_sz), ctypes.POINTER(_i64)]),
+    "tq_pagepool_stream": (_i32, [_vp, _vp, _i64, _vp, _sz, _i32, BATCH_FN, _vp, _vp, _vp]),
+    "tq_budget_create": (_i32, [_sz, ctypes.POINTER(ctypes.c_void_p)]),
+    "tq_budget_destroy": (None, [_vp]),
+    "tq_budget_reserve": (_i32, [_vp, _sz]),
+    "tq_budget_release": (None, [_vp, _sz]),
+    "tq_budget_used": (_sz, [_vp]),
+    "tq_budget_peak": (_sz, [_vp]),
+    "tq_budget_cap": (_sz, [_vp]),
+    "tq_ooc_join_agg": (_i32, [_vp, _vp, _i64, _vp, _i64, ctypes.POINTER(OocPlan), _vp, _vp, _sz, _vp,
+                               ctypes.POINTER(OocStats), _vp, _vp]),
+}
+
+
+def _bind_more():
+    L = lib()
+    if getattr(L, "_more_bound", False):
+        return L
+    for name, (res, args) in _more_sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    L._more_bound = True
+    return L
+
+
+class PagePool:
+    """Fixed-size page-locked host pages, allocated once (tq_pagepool_*)."""
+
+    def __init__(self, page_bytes: int, n_pages: int, pinned: bool = True):
+        L = _bind_more()
+        h = ctypes.c_void_p()
+        _check(L.tq_pagepool_create(page_bytes, n_pages, 0 if pinned else TQ_POOL_PAGEABLE, ctypes.byref(h)))
+        self.h = h
+        self.page_bytes = page_bytes
+        self.n_pages = n_pages
+
+    def alloc(self, n: int):
+        ids = (ctypes.c_int32 * max(1, n))()
+        _check(_bind_more().tq_pagepool_alloc(self.h, n, ids))
+        return [ids[i] for i in range(n)]
+
+    def free(self, ids):
+        arr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
+        _bind_more().tq_pagepool_free(self.h, arr, len(ids))
+
+    def page(self, pid: int) -> int:
+        return _bind_more().tq_pagepool_page(self.h, pid) or 0
+
+    def free_pages(self) -> int:
+        return _bind_more().tq_pagepool_free_pages(self.h)
+
+    def close(self):
+        if self.h:
+            _bind_more().tq_pagepool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_layout(nrows: int, types, page_bytes: int):
+    t = (ctypes.c_int32 * max(1, len(types)))(*types)
+    offs = (ctypes.c_int64 * max(1, len(types)))()
+    nbytes = _sz()
+    npages = _i64()
+    _check(_bind_more().tq_batch_layout(nrows, len(types), t, page_bytes, offs, ctypes.byref(nbytes),
+                                        ctypes.byref(npages)))
+    return [offs[i] for i in range(len(types))], nbytes.value, npages.value
+
+
+def pagepool_stream(pool: PagePool, batches, staging, nslots, fn, copy_stream=None, compute_stream=None):
+    """fn(batch_idx, cols: list[(ptr, type)], nrows, compute_stream_handle) -> status; runs on this thread."""
+    def cb(_user, idx, cols, ncol, nrows, stream):
+        try:
+            return fn(idx, [(cols[i].data, cols[i].type) for i in range(ncol)], nrows, stream) or 0
+        except Exception:  # the error crosses the C boundary as a status
+            return TQ_EINVAL
+    c = BATCH_FN(cb)
+    arr, _keep = batches
+    _check(_bind_more().tq_pagepool_stream(pool.h, arr, len(arr), staging.data_ptr(), _nbytes(staging), nslots, c,
+                                           None, _stream(copy_stream), _stream(compute_stream)))
+
+
+class Budget:
+    def __init__(self, cap_bytes: int):
+        h = ctypes.c_void_p()
+        _check(_bind_more().tq_budget_create(cap_bytes, ctypes.byref(h)))
+        self.h = h
+
+    def reserve(self, n):
+        _check(_bind_more().tq_budget_reserve(self.h, n))
+
+    def try_reserve(self, n) -> bool:
+        return _bind_more().tq_budget_reserve(self.h, n) == TQ_OK
+
+    def release(self, n):
+        _bind_more().tq_budget_release(self.h, n)
+
+    @property
+    def used(self):
+        return _bind_more().tq_budget_used(self.h)
+
+    @property
+    def peak(self):
+        return _bind_more().tq_budget_peak(self.h)
+
+    @property
+    def cap(self):
+        return _bind_more().tq_budget_cap(self.h)
+
+    def close(self):
+        if self.h:
+            _bind_more().tq_budget_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ooc_join_agg(pool, dim_batches, fact_batches, plan: OocPlan, budget: Budget, work, state, copy_stream=None,
+                 compute_stream=None) -> OocStats:
+    st = OocStats()
+    d_arr, _ = dim_batches
+    f_arr, _ = fact_batches
+    _check(_bind_more().tq_ooc_join_agg(pool.h, d_arr, len(d_arr), f_arr, len(f_arr), ctypes.byref(plan), budget.h,
+                                        work.data_ptr(), _nbytes(work), state.data_ptr(), ctypes.byref(st),
+                                        _stream(copy_stream), _stream(compute_stream)))
+    return st

@@ -19,7 +19,8 @@ def declared_functions():
         if h.endswith(".h"):
             text = open(os.path.join(ROOT, "include", h)).read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-            names |= set(re.findall(r"\b(tq_[a-z0-9_]+)\s*\(", text))
+            # function declarations: a name followed by "(" but not a function-pointer typedef "(*"
+            names |= set(re.findall(r"\b(tq_[a-z0-9_]+)\s*\((?!\s*\*)", text)) - {"tq_status"}
     return sorted(names)
 
 
