@@ -326,6 +326,137 @@ tq_status tq_ooc_join_agg(tq_pagepool* pool, const tq_batch* dim, int64_t n_dim_
                           size_t work_bytes, void* d_state, tq_ooc_stats* stats, hipStream_t copy,
                           hipStream_t compute);
 
+/* ------------------------------------------------------------ batched instances */
+
+/* Many independent join + group-by instances of one query shape (the
+ * task-on-batch model of Section 3.1 taken to thousands of small, uneven
+ * batches). Dimension columns: [0] the int64 key, [1] the group id, the rest
+ * filter columns; fact columns: [0] the int64 foreign key, the rest read by
+ * the sums. Per instance the caller provides the table, the group-by state and
+ * the outputs; tile sizes and the load factor are per instance (autotuned by
+ * size bucket). */
+typedef struct {
+  int32_t dim_types[4];
+  int32_t ndim;
+  tq_pred preds[2]; /* the build filter, over dimension columns */
+  int32_t np;
+  int32_t fact_types[4];
+  int32_t nfact;
+  tq_expr sums[2]; /* over fact columns */
+  int32_t nsum;
+  uint32_t join_flags; /* TQ_UNIQUE_KEYS */
+} tq_batch_query;
+
+typedef struct {
+  const void* dim_cols[4];
+  int64_t n_dim;
+  const void* fact_cols[4];
+  int64_t n_fact;
+  int64_t domain;     /* group ids lie in [0, domain) */
+  void* d_table;      /* tq_join_table_bytes(n_dim, load_factor) bytes */
+  size_t table_bytes;
+  void* d_state;      /* tq_batched_state_bytes(domain, nsum) bytes */
+  size_t state_bytes;
+  int64_t* d_keys;    /* outputs: `domain` entries each (sums, avg: domain * nsum) */
+  int64_t* d_count;
+  int64_t* d_sums;
+  double* d_avg;
+  int64_t* d_ngroups;
+  double load_factor;
+  int32_t build_tile; /* rows per build work item */
+  int32_t probe_tile; /* rows per probe work item */
+} tq_instance;
+
+size_t tq_batched_state_bytes(int64_t domain, int32_t nsum);
+/* Device work area for n instances (descriptors, the work-item list, counters). */
+size_t tq_batched_work_bytes(const tq_instance* h_inst, int32_t n);
+
+/* Upload the descriptors and the work-item list for tq_batched_run (copies
+ * synchronously; not part of the timed work). */
+tq_status tq_batched_prepare(const tq_batch_query* q, const tq_instance* h_inst, int32_t n, void* d_work,
+                             size_t work_bytes, hipStream_t stream);
+
+/* One pass over the n prepared instances: a preparation kernel (table headers,
+ * tags, states, counters) and ONE persistent launch whose workgroups take
+ * work items (build tiles, probe tiles, finalize chunks, in that order) from
+ * an atomic queue; a probe item waits until its instance's build items are
+ * done, a finalize item until its probe items are done (bounded waits: a wait
+ * that times out latches TQ_EHIP in the work area instead of hanging). Only
+ * kernels are enqueued, so the call can be captured in a hipGraph and
+ * replayed. tq_batched_check reads the error latched by the last run. */
+tq_status tq_batched_run(const tq_batch_query* q, void* d_work, int32_t n, hipStream_t stream);
+tq_status tq_batched_check(const void* d_work, hipStream_t stream);
+
+/* The same work as separate stand-alone calls, one build, probe and finalize
+ * launch per instance (the baseline the persistent launch is compared with). */
+tq_status tq_batched_run_per_instance(const tq_batch_query* q, const tq_instance* h_inst, int32_t n,
+                                      hipStream_t stream);
+
+/* ------------------------------------------------------------ serving */
+
+/* A request loop over three query templates (shape 0: filter + group-by over
+ * a device table; shape 1: join + group-by over device tables; shape 2: the
+ * same join with the fact rows streamed from page-pool batches). A request
+ * is a row window of the shape's base tables. Requests are admitted in
+ * arrival order when their device memory (table, group-by state, outputs,
+ * staging) can be reserved from the budget (Section 3.3.2), then run on one
+ * of `workers` worker threads, each with its own HIP streams, so requests
+ * that arrive while others run overlap on the device; their tables and
+ * partial aggregates stay resident until they complete. workers = 1 is the
+ * one-at-a-time FIFO baseline. */
+typedef struct {
+  int32_t shape;     /* 0, 1 or 2 */
+  int64_t fact_first; /* shapes 0, 1: first row (a multiple of 16); shape 2: first batch */
+  int64_t n_fact;     /* shapes 0, 1: rows; shape 2: batches */
+  int64_t dim_first, n_dim; /* shapes 1, 2: dimension window (first a multiple of 16) */
+  double arrival_s;  /* arrival time, seconds after the start of the run */
+} tq_request;
+
+typedef struct {
+  /* shape 0 */
+  tq_col fg_cols[TQ_MAX_COLS];
+  int32_t fg_ncol;
+  tq_pred fg_preds[TQ_MAX_PREDS];
+  int32_t fg_np;
+  tq_gkey fg_key;
+  tq_expr fg_sums[TQ_MAX_SUMS];
+  int32_t fg_nsum;
+  int64_t fg_domain;
+  /* shapes 1 and 2: dimension (device) = key, payload, filter columns */
+  tq_col dim_cols[4];
+  int32_t dim_ncol;
+  tq_pred dim_preds[2];
+  int32_t dim_np;
+  /* shape 1: fact (device) = key, then the columns the sums read */
+  tq_col fact_cols[4];
+  int32_t fact_ncol;
+  tq_expr join_sums[2];
+  int32_t join_nsum;
+  int64_t join_domain;
+  double load_factor;
+  /* shape 2: fact batches in `pool`; fact_map[j] = batch column of fact column j */
+  tq_pagepool* pool;
+  const tq_batch* fact_batches;
+  int64_t n_fact_batches;
+  int32_t fact_map[4];
+  int32_t nslots;
+} tq_serve_tables;
+
+typedef struct {
+  double start_s, end_s; /* run on a worker from .. results on the host at */
+  int32_t status;        /* TQ_OK or the error of the request */
+  int32_t worker;
+  int64_t ngroups;
+} tq_request_result;
+
+/* Runs all requests and blocks until they are done. d_arena / arena_bytes is
+ * the device memory requests are carved from; the budget bounds it. Group
+ * results go to h_keys / h_count / h_sums (max_groups and max_groups * 6
+ * entries per request); per-request timing to `res`. */
+tq_status tq_serve_run(const tq_serve_tables* t, const tq_request* reqs, int64_t n, int32_t workers,
+                       tq_budget* budget, void* d_arena, size_t arena_bytes, int64_t max_groups, int64_t* h_keys,
+                       int64_t* h_count, int64_t* h_sums, tq_request_result* res);
+
 /* ------------------------------------------------------- measurement kernels */
 
 /* Read `bytes` (multiple of 16) and write one partial checksum per workgroup

@@ -1,0 +1,548 @@
+// Batched join + group-by instances in one persistent launch.
+//
+// Work area: WorkHeader | BInst[n] | int64 ctr[n][kCtr] | uint64 item[n_items].
+// An item is (type, instance, index). The list holds every build tile, then
+// every probe tile, then the finalize items, so an item's dependencies always
+// sit earlier in the queue: whoever waits has been preceded by workgroups that
+// already took the items it waits for, and waits end. Each wait is bounded in
+// any case; a timed-out wait latches an error and skips the item's work.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "groupby.h"
+#include "table.h"
+
+namespace tq {
+namespace {
+
+constexpr int kBBlock = 512;
+constexpr int kFinChunk = 8192;  // keys per finalize chunk
+constexpr int kMaxChunks = 8;    // domain <= 65536
+constexpr int kCtr = 16;         // counters per instance: build, probe, fcount, -, chunk counts [8..16)
+constexpr int64_t kSpinLimit = (int64_t)1 << 19;  // polls: well under a second
+constexpr int kBPR = 2;          // rows per lane in probe items
+
+enum ItemType { kItBuild = 0, kItProbe = 1, kItFinOne = 2, kItFinCount = 3, kItFinWrite = 4 };
+
+__host__ __device__ inline uint64_t make_item(int type, int64_t inst, int64_t idx) {
+  return ((uint64_t)type << 60) | ((uint64_t)inst << 36) | (uint64_t)idx;
+}
+
+struct BInst {
+  const void* dcol[4];
+  const void* fcol[4];
+  int64_t n_dim, n_fact, domain;
+  void* table;
+  int64_t cap_max;
+  int32_t log2cap, build_tile, probe_tile, nchunks;
+  int64_t n_build_items, n_probe_items;
+  void* state;
+  int64_t* keys;
+  int64_t* count;
+  int64_t* sums;
+  double* avg;
+  int64_t* ngroups;
+};
+
+struct WorkHeader {
+  int64_t head;
+  int64_t n_items;
+  int32_t n_inst;
+  int32_t err;
+  int64_t pad[4];
+};
+static_assert(sizeof(WorkHeader) <= 256, "header");
+
+struct BQuery {
+  int32_t dtype[4];
+  int32_t ndim;
+  DPred pred[2];
+  int32_t np;
+  int32_t ftype[4];
+  int32_t nfact;
+  DExpr sums[2];
+  int32_t nsum;
+  uint32_t flags;
+};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+  size_t inst_off, item_off, ctr_off, bytes;
+};
+
+Layout layout(int32_t n, int64_t n_items) {
+  Layout L;
+  L.inst_off = 256;
+  L.ctr_off = L.inst_off + al((size_t)n * sizeof(BInst));
+  L.item_off = L.ctr_off + al((size_t)n * kCtr * 8);
+  L.bytes = L.item_off + al((size_t)n_items * 8);
+  return L;
+}
+
+int log2cap_for_rows(int64_t rows, double lf) {
+  double need = ceil((double)rows / lf);
+  int l = 6;
+  while (l < 62 && (double)((int64_t)1 << l) < need) l++;
+  return l;
+}
+
+int64_t cap_max_for(size_t bytes) {
+  int64_t cap = 0;
+  for (int l = 6; l < 62; l++) {
+    int64_t c = (int64_t)1 << l;
+    size_t need = kHeaderBytes + (size_t)kMaxPartBlocks * 8 + table_tag_bytes(c) + (size_t)c * 16;
+    if (need > bytes) break;
+    cap = c;
+  }
+  return cap;
+}
+
+int64_t count_items(const tq_instance* h, int32_t n) {
+  int64_t t = 0;
+  for (int i = 0; i < n; i++) {
+    t += (h[i].n_dim + h[i].build_tile - 1) / h[i].build_tile;
+    t += (h[i].n_fact + h[i].probe_tile - 1) / h[i].probe_tile;
+    int64_t ch = (h[i].domain + kFinChunk - 1) / kFinChunk;
+    t += ch == 1 ? 1 : 2 * ch;
+  }
+  return t;
+}
+
+// Spins until *p >= target. Gives up after kSpinLimit polls, or at once when
+// another wait has already timed out (*err set), so a failure cannot make the
+// launch run long.
+__device__ bool wait_at_least(int64_t* p, int64_t target, int32_t* err) {
+  for (int64_t i = 0; i < kSpinLimit; i++) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+      __threadfence();  // acquire: the producers' writes are visible from here on
+      return true;
+    }
+    if ((i & 63) == 63 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(8);
+  }
+  return false;
+}
+
+__device__ void signal(int64_t* p) {
+  __threadfence();  // release this workgroup's writes before the counter moves
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), 1ull);
+}
+
+__global__ __launch_bounds__(256) void k_batched_prep(WorkHeader* hdr, const BInst* insts, int64_t* ctrs, int32_t n,
+                                                      int32_t nsum, uint32_t flags) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr->head = 0;
+    hdr->err = 0;
+  }
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BInst& I = insts[i];
+    if (threadIdx.x < kCtr) ctrs[(int64_t)i * kCtr + threadIdx.x] = 0;
+    TableHeader* th = static_cast<TableHeader*>(I.table);
+    if (threadIdx.x == 0) {
+      th->magic = kTableMagic;
+      th->err = 0;
+      th->cap_max = I.cap_max;
+      th->log2cap = I.log2cap;
+      th->skip = 0;
+      th->n = I.n_dim;
+      th->nblk = 0;
+      th->flags = flags;
+      th->lf = 0;
+      StateHeader* sh = static_cast<StateHeader*>(I.state);
+      sh->magic = kStateMagic;
+      sh->err = 0;
+      sh->domain = I.domain;
+      sh->nsum = nsum;
+      sh->rows = 1;
+      sh->used = 0;
+    }
+    v4i32* tags = reinterpret_cast<v4i32*>(table_tags(th));
+    const v4i32 z = {0, 0, 0, 0};
+    for (int64_t g = threadIdx.x; g < ((int64_t)1 << I.log2cap) / kBucket; g += blockDim.x) tags[g] = z;
+    int64_t* d = state_data(I.state);
+    for (int64_t e = threadIdx.x; e < I.domain * (1 + nsum); e += blockDim.x) d[e] = 0;
+  }
+}
+
+// Compaction of keys [k_lo, k_hi) of a rows=1 state into the outputs at `base`; returns the live count.
+__device__ int64_t fin_write(const BInst& I, int nsum, int64_t k_lo, int64_t k_hi, int64_t base, int64_t* ws) {
+  const int stride = 1 + nsum;
+  const int64_t* d = state_data(I.state);
+  for (int64_t k0 = k_lo; k0 < k_hi; k0 += blockDim.x) {
+    int64_t k = k0 + threadIdx.x;
+    int64_t e[3] = {0, 0, 0};
+    bool live = false;
+    if (k < k_hi) {
+#pragma unroll
+      for (int j = 0; j < 3; j++)
+        if (j < stride) e[j] = d[k * stride + j];
+      live = e[0] != 0;
+    }
+    int64_t excl;
+    int64_t tot = block_excl_scan(live ? 1 : 0, &excl, ws);
+    if (live) {
+      int64_t g = base + excl;
+      I.keys[g] = k;
+      I.count[g] = e[0];
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        if (j < nsum) {
+          I.sums[g * nsum + j] = e[1 + j];
+          I.avg[g * nsum + j] = (double)e[1 + j] / (double)e[0];
+        }
+      }
+    }
+    base += tot;
+  }
+  return base;
+}
+
+__device__ int64_t fin_count(const BInst& I, int nsum, int64_t k_lo, int64_t k_hi, int64_t* ws) {
+  const int stride = 1 + nsum;
+  const int64_t* d = state_data(I.state);
+  int64_t c = 0;
+  for (int64_t k = k_lo + threadIdx.x; k < k_hi; k += blockDim.x) c += d[k * stride] != 0;
+  return block_sum(c, ws);
+}
+
+template <int MODE>
+__device__ void probe_item(const BQuery& Q, const BInst& I, int64_t idx, char* smem, int32_t* err) {
+  AggTarget T;
+  T.hdr = static_cast<const StateHeader*>(I.state);
+  T.data = state_data(I.state);
+  T.err = &static_cast<StateHeader*>(I.state)->err;
+  T.domain = I.domain;
+  T.stride = 1 + Q.nsum;
+  T.rows = 1;
+  size_t lds;
+  agg_mode(I.domain, T.stride, &T.log2hcap, &lds);
+  LdsAgg<MODE> agg;
+  agg.init(T, smem);
+  __syncthreads();
+  const TableHeader* th = static_cast<const TableHeader*>(I.table);
+  Probe pr;
+  pr.setup(th);
+  const int64_t lo = idx * I.probe_tile, hi = min(I.n_fact, lo + I.probe_tile);
+  DCol fc[4];
+#pragma unroll
+  for (int c = 0; c < 4; c++) fc[c] = DCol{I.fcol[c] ? I.fcol[c] : I.fcol[0], Q.ftype[c] ? Q.ftype[c] : 8};
+  for (int64_t r0 = lo + (int64_t)threadIdx.x * kBPR; r0 < hi; r0 += (int64_t)blockDim.x * kBPR) {
+    const bool full = r0 + kBPR <= hi;
+    int64_t v[4][kBPR], k[kBPR], e[kBPR][2];
+    bool ok[kBPR];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      if (c < Q.nfact) load4<kBPR>(fc[c], r0, full, hi, v[c]);
+      else {
+#pragma unroll
+        for (int i = 0; i < kBPR; i++) v[c][i] = 0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kBPR; i++) {
+      ok[i] = r0 + i < hi;
+      k[i] = v[0][i];
+#pragma unroll
+      for (int j = 0; j < 2; j++) e[i][j] = j < Q.nsum ? eval_expr<4, kBPR>(Q.sums[j], v, i) : 0;
+    }
+    pr.walk(ok, k, [&](const bool (&hit)[kBPR], const int64_t (&pay)[kBPR]) {
+#pragma unroll
+      for (int i = 0; i < kBPR; i++)
+        if (hit[i]) agg.add(T, pay[i], e[i], Q.nsum);
+    });
+  }
+  agg.flush(T);
+  (void)err;
+}
+
+__global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, const BInst* insts,
+                                                      const uint64_t* items, int64_t* ctrs) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ uint64_t s_item;
+  __shared__ int s_ok;
+  __shared__ int64_t s_base;
+  __shared__ int64_t ws[kBBlock / kWave];
+  const int64_t n_items = hdr->n_items;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int64_t i = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->head), 1ull);
+      s_item = i < n_items ? items[i] : ~0ull;
+    }
+    __syncthreads();
+    const uint64_t it = s_item;
+    __syncthreads();
+    if (it == ~0ull) break;
+    const int type = (int)(it >> 60);
+    const int64_t inst = (int64_t)((it >> 36) & 0xffffffull);
+    const int64_t idx = (int64_t)(it & 0xfffffffffull);
+    const BInst& I = insts[inst];
+    int64_t* ctr = ctrs + inst * kCtr;
+
+    if (type == kItBuild) {
+      const TableHeader* th = static_cast<const TableHeader*>(I.table);
+      uint32_t* words = table_tags(const_cast<TableHeader*>(th));
+      v2i64* slots = reinterpret_cast<v2i64*>(table_slots(const_cast<TableHeader*>(th), I.cap_max));
+      const int64_t lo = idx * I.build_tile, hi = min(I.n_dim, lo + I.build_tile);
+      DCol dc[4];
+#pragma unroll
+      for (int c = 0; c < 4; c++) dc[c] = DCol{I.dcol[c] ? I.dcol[c] : I.dcol[0], Q.dtype[c] ? Q.dtype[c] : 8};
+      RowPlan P;
+      P.np = Q.np;
+      P.pred[0] = Q.pred[0];
+      P.pred[1] = Q.pred[1];
+      for (int64_t r0 = lo + (int64_t)threadIdx.x * kRows; r0 < hi; r0 += (int64_t)blockDim.x * kRows) {
+        const bool full = r0 + kRows <= hi;
+        int64_t v[4][kRows];
+        bool pend[kRows];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          if (c < Q.ndim) load4(dc[c], r0, full, hi, v[c]);
+          else {
+#pragma unroll
+            for (int i = 0; i < kRows; i++) v[c][i] = 0;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < hi) && eval_preds<4, kRows>(P, v, i);
+        table_insert<kRows>(words, slots, I.log2cap, 0, pend, v[0], v[1]);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) signal(&ctr[0]);
+    } else if (type == kItProbe) {
+      if (threadIdx.x == 0) s_ok = wait_at_least(&ctr[0], I.n_build_items, &hdr->err);
+      __syncthreads();
+      if (s_ok) {
+        int stride = 1 + Q.nsum;
+        if (I.domain * stride * 8 <= kLdsAggBytes) probe_item<kDense>(Q, I, idx, smem, &hdr->err);
+        else probe_item<kHash>(Q, I, idx, smem, &hdr->err);
+      } else if (threadIdx.x == 0) {
+        latch_error(&hdr->err, TQ_EHIP);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) signal(&ctr[1]);
+    } else {
+      if (type != kItFinWrite) {
+        if (threadIdx.x == 0) s_ok = wait_at_least(&ctr[1], I.n_probe_items, &hdr->err);
+      } else {
+        if (threadIdx.x == 0) s_ok = wait_at_least(&ctr[2], I.nchunks, &hdr->err);
+      }
+      __syncthreads();
+      if (!s_ok) {
+        if (threadIdx.x == 0) latch_error(&hdr->err, TQ_EHIP);
+      } else if (type == kItFinOne) {
+        int64_t g = fin_write(I, Q.nsum, 0, I.domain, 0, ws);
+        if (threadIdx.x == 0) *I.ngroups = g;
+      } else if (type == kItFinCount) {
+        int64_t c = fin_count(I, Q.nsum, idx * kFinChunk, min(I.domain, (idx + 1) * kFinChunk), ws);
+        if (threadIdx.x == 0) {
+          ctr[8 + idx] = c;
+          signal(&ctr[2]);
+        }
+      } else {
+        if (threadIdx.x == 0) {
+          int64_t b = 0;
+          for (int64_t c = 0; c < idx; c++) b += __hip_atomic_load(&ctr[8 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_base = b;
+        }
+        __syncthreads();
+        int64_t g = fin_write(I, Q.nsum, idx * kFinChunk, min(I.domain, (idx + 1) * kFinChunk), s_base, ws);
+        if (threadIdx.x == 0 && idx == I.nchunks - 1) *I.ngroups = g;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+tq_status make_query(const tq_batch_query* q, BQuery* Q) {
+  memset(Q, 0, sizeof *Q);
+  if (!q) return fail(TQ_EINVAL, "query is NULL");
+  if (q->ndim < 2 || q->ndim > 4 || q->nfact < 1 || q->nfact > 4) return fail(TQ_EINVAL, "column counts");
+  if (q->np < 0 || q->np > 2 || q->nsum < 0 || q->nsum > 2) return fail(TQ_EINVAL, "predicate or sum count");
+  if (q->dim_types[0] != TQ_I64 || q->fact_types[0] != TQ_I64) return fail(TQ_EINVAL, "keys must be int64");
+  for (int c = 0; c < 4; c++) {
+    if (c < q->ndim && q->dim_types[c] != TQ_U8 && q->dim_types[c] != TQ_I32 && q->dim_types[c] != TQ_I64)
+      return fail(TQ_EINVAL, "dimension column %d type", c);
+    if (c < q->nfact && q->fact_types[c] != TQ_U8 && q->fact_types[c] != TQ_I32 && q->fact_types[c] != TQ_I64)
+      return fail(TQ_EINVAL, "fact column %d type", c);
+    Q->dtype[c] = c < q->ndim ? q->dim_types[c] : 0;
+    Q->ftype[c] = c < q->nfact ? q->fact_types[c] : 0;
+  }
+  Q->ndim = q->ndim;
+  Q->nfact = q->nfact;
+  Q->np = q->np;
+  for (int j = 0; j < q->np; j++) {
+    if (q->preds[j].col < 0 || q->preds[j].col >= q->ndim) return fail(TQ_EINVAL, "predicate column");
+    Q->pred[j] = DPred{1u << q->preds[j].col, q->preds[j].lo, q->preds[j].hi};
+  }
+  Q->nsum = q->nsum;
+  for (int j = 0; j < q->nsum; j++) {
+    if (q->sums[j].nf < 1 || q->sums[j].nf > 3) return fail(TQ_EINVAL, "sum factors");
+    Q->sums[j].nf = q->sums[j].nf;
+    for (int f = 0; f < q->sums[j].nf; f++) {
+      const tq_factor& F = q->sums[j].f[f];
+      if (F.col < -1 || F.col >= q->nfact) return fail(TQ_EINVAL, "sum column");
+      Q->sums[j].f[f] = DFactor{F.col < 0 ? 0u : 1u << F.col, F.sign, F.add};
+    }
+  }
+  Q->flags = q->join_flags;
+  return TQ_OK;
+}
+
+}  // namespace
+}  // namespace tq
+
+using namespace tq;
+
+extern "C" {
+
+size_t tq_batched_state_bytes(int64_t domain, int32_t nsum) {
+  if (domain <= 0 || nsum < 0 || nsum > 2) return 0;
+  size_t shared = kHeaderBytes + (size_t)domain * (1 + nsum) * 8;
+  return std::max(shared, tq_groupby_state_bytes(domain, nsum));  // also fits the stand-alone layout
+}
+
+size_t tq_batched_work_bytes(const tq_instance* h, int32_t n) {
+  if (!h || n <= 0) return 0;
+  for (int i = 0; i < n; i++)
+    if (h[i].build_tile <= 0 || h[i].probe_tile <= 0) return 0;
+  return layout(n, count_items(h, n)).bytes;
+}
+
+tq_status tq_batched_prepare(const tq_batch_query* q, const tq_instance* h, int32_t n, void* d_work, size_t work_bytes,
+                             hipStream_t stream) {
+  BQuery Q;
+  tq_status s = make_query(q, &Q);
+  if (s) return s;
+  if (!h || n <= 0 || n > (1 << 24) || !d_work) return fail(TQ_EINVAL, "instances");
+  std::vector<BInst> bi((size_t)n);
+  std::vector<uint64_t> items;
+  for (int i = 0; i < n; i++) {
+    const tq_instance& x = h[i];
+    if (x.n_dim < 0 || x.n_fact < 0 || x.domain <= 0 || x.domain > (int64_t)kFinChunk * kMaxChunks)
+      return fail(TQ_EINVAL, "instance %d: sizes or domain (<= 65536)", i);
+    if (x.build_tile < 64 || x.probe_tile < 64 || x.build_tile % 64 || x.probe_tile % 64)
+      return fail(TQ_EINVAL, "instance %d: tiles must be multiples of 64", i);
+    if (!(x.load_factor > 0 && x.load_factor <= 0.9)) return fail(TQ_EINVAL, "instance %d: load factor", i);
+    for (int c = 0; c < 4; c++) {
+      if (c < q->ndim && ((!x.dim_cols[c] && x.n_dim) || ((uintptr_t)x.dim_cols[c] & 15)))
+        return fail(TQ_EINVAL, "instance %d: dimension column %d", i, c);
+      if (c < q->nfact && ((!x.fact_cols[c] && x.n_fact) || ((uintptr_t)x.fact_cols[c] & 15)))
+        return fail(TQ_EINVAL, "instance %d: fact column %d", i, c);
+    }
+    if (!x.d_table || !x.d_state || !x.d_keys || !x.d_count || !x.d_sums || !x.d_avg || !x.d_ngroups)
+      return fail(TQ_EINVAL, "instance %d: NULL buffer", i);
+    if (x.state_bytes < tq_batched_state_bytes(x.domain, q->nsum)) return fail(TQ_EINVAL, "instance %d: state size", i);
+    BInst& b = bi[(size_t)i];
+    memset(&b, 0, sizeof b);
+    for (int c = 0; c < 4; c++) {
+      b.dcol[c] = c < q->ndim ? x.dim_cols[c] : nullptr;
+      b.fcol[c] = c < q->nfact ? x.fact_cols[c] : nullptr;
+    }
+    b.n_dim = x.n_dim;
+    b.n_fact = x.n_fact;
+    b.domain = x.domain;
+    b.table = x.d_table;
+    b.cap_max = cap_max_for(x.table_bytes);
+    b.log2cap = log2cap_for_rows(x.n_dim, x.load_factor);
+    if (b.cap_max == 0 || ((int64_t)1 << b.log2cap) > b.cap_max) return fail(TQ_EINVAL, "instance %d: table too small", i);
+    b.build_tile = x.build_tile;
+    b.probe_tile = x.probe_tile;
+    b.nchunks = (int32_t)((x.domain + kFinChunk - 1) / kFinChunk);
+    b.n_build_items = (x.n_dim + x.build_tile - 1) / x.build_tile;
+    b.n_probe_items = (x.n_fact + x.probe_tile - 1) / x.probe_tile;
+    b.state = x.d_state;
+    b.keys = x.d_keys;
+    b.count = x.d_count;
+    b.sums = x.d_sums;
+    b.avg = x.d_avg;
+    b.ngroups = x.d_ngroups;
+  }
+  for (int i = 0; i < n; i++)
+    for (int64_t t = 0; t < bi[(size_t)i].n_build_items; t++) items.push_back(make_item(kItBuild, i, t));
+  for (int i = 0; i < n; i++)
+    for (int64_t t = 0; t < bi[(size_t)i].n_probe_items; t++) items.push_back(make_item(kItProbe, i, t));
+  for (int i = 0; i < n; i++) {
+    if (bi[(size_t)i].nchunks == 1) items.push_back(make_item(kItFinOne, i, 0));
+    else
+      for (int c = 0; c < bi[(size_t)i].nchunks; c++) items.push_back(make_item(kItFinCount, i, c));
+  }
+  for (int i = 0; i < n; i++)
+    if (bi[(size_t)i].nchunks > 1)
+      for (int c = 0; c < bi[(size_t)i].nchunks; c++) items.push_back(make_item(kItFinWrite, i, c));
+  Layout L = layout(n, (int64_t)items.size());
+  if (work_bytes < L.bytes) return fail(TQ_EINVAL, "work area has %zu bytes, needs %zu", work_bytes, L.bytes);
+  WorkHeader wh;
+  memset(&wh, 0, sizeof wh);
+  wh.n_items = (int64_t)items.size();
+  wh.n_inst = n;
+  char* w = static_cast<char*>(d_work);
+  TQ_HIP(hipMemcpyAsync(w, &wh, sizeof wh, hipMemcpyHostToDevice, stream));
+  TQ_HIP(hipMemcpyAsync(w + L.inst_off, bi.data(), bi.size() * sizeof(BInst), hipMemcpyHostToDevice, stream));
+  TQ_HIP(hipMemcpyAsync(w + L.item_off, items.data(), items.size() * 8, hipMemcpyHostToDevice, stream));
+  TQ_HIP(hipStreamSynchronize(stream));
+  return TQ_OK;
+}
+
+tq_status tq_batched_run(const tq_batch_query* q, void* d_work, int32_t n, hipStream_t stream) {
+  BQuery Q;
+  tq_status s = make_query(q, &Q);
+  if (s) return s;
+  if (!d_work || n <= 0) return fail(TQ_EINVAL, "work area or instance count");
+  Layout L = layout(n, 0);  // the item list is last; the kernel reads its length from the header
+  char* w = static_cast<char*>(d_work);
+  auto* hdr = reinterpret_cast<WorkHeader*>(w);
+  auto* insts = reinterpret_cast<const BInst*>(w + L.inst_off);
+  auto* items = reinterpret_cast<const uint64_t*>(w + L.item_off);
+  auto* ctrs = reinterpret_cast<int64_t*>(w + L.ctr_off);
+  hipLaunchKernelGGL(k_batched_prep, dim3(std::min(n, 8192)), dim3(256), 0, stream, hdr, insts, ctrs, n, Q.nsum,
+                     Q.flags);
+  TQ_HIP(hipGetLastError());
+  int per_cu = 0;
+  TQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched, kBBlock, kLdsAggBytes));
+  per_cu = std::max(1, std::min(per_cu, 4));
+  hipLaunchKernelGGL(k_batched, dim3(device_cu_count() * per_cu), dim3(kBBlock), kLdsAggBytes, stream, Q, hdr, insts,
+                     items, ctrs);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+tq_status tq_batched_check(const void* d_work, hipStream_t stream) {
+  if (!d_work) return fail(TQ_EINVAL, "work area is NULL");
+  TQ_HIP(hipStreamSynchronize(stream));
+  WorkHeader wh;
+  TQ_HIP(hipMemcpy(&wh, d_work, sizeof wh, hipMemcpyDeviceToHost));
+  if (wh.err) return fail(wh.err, "a batched work item timed out waiting for its dependencies");
+  return TQ_OK;
+}
+
+tq_status tq_batched_run_per_instance(const tq_batch_query* q, const tq_instance* h, int32_t n, hipStream_t stream) {
+  BQuery Q;
+  tq_status s = make_query(q, &Q);
+  if (s) return s;
+  for (int i = 0; i < n; i++) {
+    const tq_instance& x = h[i];
+    tq_col dcols[4], fcols[4];
+    for (int c = 0; c < 4; c++) {
+      dcols[c] = tq_col{x.dim_cols[c], q->dim_types[c]};
+      fcols[c] = tq_col{x.fact_cols[c], q->fact_types[c]};
+    }
+    if ((s = tq_join_table_init(x.d_table, x.table_bytes, stream))) return s;
+    if ((s = tq_join_build(x.d_table, x.table_bytes, static_cast<const int64_t*>(x.dim_cols[0]), dcols[1], x.n_dim,
+                           dcols, q->ndim, q->preds, q->np, x.load_factor, 0, q->join_flags, stream)))
+      return s;
+    if ((s = tq_groupby_init(x.d_state, x.state_bytes, x.domain, q->nsum, stream))) return s;
+    tq_agg agg{x.d_state, x.domain, q->sums, q->nsum};
+    if ((s = tq_join_probe(x.d_table, static_cast<const int64_t*>(x.fact_cols[0]), x.n_fact, fcols, q->nfact, nullptr, 0,
+                           nullptr, nullptr, 0, nullptr, &agg, stream)))
+      return s;
+    if ((s = tq_groupby_finalize(x.d_state, x.d_keys, x.d_count, x.d_sums, x.d_avg, x.d_ngroups, stream))) return s;
+  }
+  return TQ_OK;
+}
+
+}  // extern "C"

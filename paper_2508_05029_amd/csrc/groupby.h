@@ -46,7 +46,7 @@ inline int state_rows(int64_t domain, int stride) {
 }
 
 // Host: pick the LDS mode and its dynamic LDS size.
-inline AggMode agg_mode(int64_t domain, int stride, int* log2hcap, size_t* lds_bytes) {
+__host__ __device__ inline AggMode agg_mode(int64_t domain, int stride, int* log2hcap, size_t* lds_bytes) {
   if (domain * stride * 8 <= kLdsAggBytes) {
     *log2hcap = 0;
     *lds_bytes = (size_t)domain * stride * 8;

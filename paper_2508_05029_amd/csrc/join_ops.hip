@@ -18,6 +18,7 @@
 
 #include "common.h"
 #include "groupby.h"
+#include "table.h"
 
 namespace tq {
 
@@ -126,206 +127,30 @@ __global__ __launch_bounds__(kBlock) void k_build_clear(TableHeader* h, int64_t 
     tags[i] = z;
 }
 
-// Bits j (0..7) of the result: tag j of the bucket equals t.
-__device__ __forceinline__ uint32_t tag_match(const v4i32& w, uint32_t t) {
-  uint32_t m = 0;
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    uint32_t x = (uint32_t)w[q];
-    m |= (uint32_t)((x & 0xffffu) == t) << (2 * q);
-    m |= (uint32_t)((x >> 16) == t) << (2 * q + 1);
-  }
-  return m;
-}
-
-__device__ __forceinline__ uint32_t word_of(const v4i32& w, int q) {
-  uint32_t r = (uint32_t)w[0];
-  r = q == 1 ? (uint32_t)w[1] : r;
-  r = q == 2 ? (uint32_t)w[2] : r;
-  r = q == 3 ? (uint32_t)w[3] : r;
-  return r;
-}
-
-__device__ __forceinline__ void set_word(v4i32& w, int q, uint32_t v) {
-  w[0] = q == 0 ? (int)v : w[0];
-  w[1] = q == 1 ? (int)v : w[1];
-  w[2] = q == 2 ? (int)v : w[2];
-  w[3] = q == 3 ? (int)v : w[3];
-}
-
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
                                                          TableHeader* h) {
   if (h->magic != kTableMagic) return;
   const int l = h->log2cap, skip = h->skip;
-  const int64_t cap = (int64_t)1 << l, bmask = (cap >> kLog2Bucket) - 1;
-  if (h->n > cap) return;  // does not fit: TQ_EFULL is latched, nothing is inserted
+  if (h->n > ((int64_t)1 << l)) return;  // does not fit: TQ_EFULL is latched, nothing is inserted
   uint32_t* words = table_tags(h);
   v2i64* slots = reinterpret_cast<v2i64*>(table_slots(h, h->cap_max));
   const DCol kc = {keys, 8};
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
     const bool full = r0 + kRows <= n;
-    int64_t v[NC][kRows], k[kRows], pay[kRows], b[kRows];
-    uint32_t tg[kRows];
+    int64_t v[NC][kRows], k[kRows], pay[kRows];
     bool pend[kRows];
-    int st[kRows];
-    v4i32 w[kRows];
     load_rows<NC>(P, r0, full, n, v);
     load4(kc, r0, full, n, k);
     load4(payload, r0, full, n, pay);
 #pragma unroll
-    for (int i = 0; i < kRows; i++) {
-      pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
-      uint64_t hh = mulhash(k[i]);
-      b[i] = (int64_t)bucket_of(hh, skip, l - kLog2Bucket);
-      tg[i] = hash_tag(hh);
-      st[i] = (int)(hh >> 16) & (kBucket - 1);
-      w[i] = v4i32{0, 0, 0, 0};
-    }
-    // Each round issues at most one CAS per row, for the first free slot at or
-    // after the row's start slot (hash bits, so that inserters into one bucket
-    // spread over its slots) in the row's view of its bucket. The view starts
-    // as "empty" and is corrected by the word a failed CAS returns, so every
-    // round claims a slot, learns of a newly taken one, or moves on.
-    for (int64_t round = 0; round < 2 * cap + 8; round++) {
-      uint32_t expect[kRows], prev[kRows];
-      int slot[kRows];
-      bool tried[kRows];
-#pragma unroll
-      for (int i = 0; i < kRows; i++) {
-        tried[i] = false;
-        slot[i] = 0;
-        expect[i] = 0;
-        prev[i] = 0;
-        if (!pend[i]) continue;
-        uint32_t zero = tag_match(w[i], 0u);
-        if (zero == 0u) {  // bucket full: linear probing moves to the next bucket
-          b[i] = (b[i] + 1) & bmask;
-          w[i] = v4i32{0, 0, 0, 0};
-          continue;
-        }
-        uint32_t rot = ((zero >> st[i]) | (zero << (kBucket - st[i]))) & 0xffu;
-        slot[i] = (__builtin_ctz(rot) + st[i]) & (kBucket - 1);
-        int q = slot[i] >> 1;
-        expect[i] = word_of(w[i], q);
-        uint32_t desired = expect[i] | (tg[i] << ((slot[i] & 1) * 16));
-        prev[i] = atomicCAS(&words[b[i] * 4 + q], expect[i], desired);
-        tried[i] = true;
-      }
-      bool more = false;
-#pragma unroll
-      for (int i = 0; i < kRows; i++) {
-        if (tried[i]) {
-          if (prev[i] == expect[i]) {
-            v2i64 kv = {k[i], pay[i]};
-            slots[b[i] * kBucket + slot[i]] = kv;
-            pend[i] = false;
-          } else {
-            set_word(w[i], slot[i] >> 1, prev[i]);
-          }
-        }
-        more = more || pend[i];
-      }
-      if (!more) break;
-    }
+    for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
+    table_insert<kRows>(words, slots, l, skip, pend, k, pay);
   }
 }
 
 // ------------------------------------------------------------------ probe
-
-struct Probe {
-  const v4i32* groups;
-  const v2i64* slots;
-  int64_t bmask, cap;
-  int log2b, skip;
-  bool unique;
-
-  __device__ __forceinline__ void setup(const TableHeader* h) {
-    log2b = h->log2cap - kLog2Bucket;
-    skip = h->skip;
-    unique = (h->flags & TQ_UNIQUE_KEYS) != 0;
-    cap = (int64_t)1 << h->log2cap;
-    bmask = ((int64_t)1 << log2b) - 1;
-    groups = reinterpret_cast<const v4i32*>(table_tags(const_cast<TableHeader*>(h)));
-    slots = reinterpret_cast<const v2i64*>(table_slots(const_cast<TableHeader*>(h), h->cap_max));
-  }
-
-  // Walks the chains of one lane's rows in lockstep. Each round checks one
-  // tag-matching slot per row (or moves the row to its next bucket) and calls
-  // on_round(hit, payload): hit[i] is set when row i matched in this round (a
-  // row can match again in later rounds unless the build keys are unique).
-  template <int R, typename F>
-  __device__ __forceinline__ void walk(const bool (&ok)[R], const int64_t (&k)[R], F&& on_round) const {
-    walk(ok, k, on_round, [] {});
-  }
-
-  // As above; `issued()` runs once, right after the first tag loads are issued
-  // (a caller prefetches its next rows there, so that the wait for the tags
-  // does not also wait for the prefetch).
-  template <int R, typename F, typename G>
-  __device__ __forceinline__ void walk(const bool (&ok)[R], const int64_t (&k)[R], F&& on_round, G&& issued) const {
-    int64_t b[R];
-    uint32_t tg[R], m[R];
-    bool act[R], empty[R], load[R];
-#pragma unroll
-    for (int i = 0; i < R; i++) {
-      uint64_t hh = mulhash(k[i]);
-      b[i] = (int64_t)bucket_of(hh, skip, log2b);
-      tg[i] = hash_tag(hh);
-      act[i] = ok[i];
-      load[i] = true;
-      m[i] = 0;
-      empty[i] = false;
-    }
-    for (int64_t round = 0; round < 2 * cap + 8; round++) {
-      v4i32 w[R];
-#pragma unroll
-      for (int i = 0; i < R; i++)
-        if (act[i] && load[i]) w[i] = groups[b[i]];
-      if (round == 0) issued();
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        if (act[i] && load[i]) {
-          m[i] = tag_match(w[i], tg[i]);
-          empty[i] = tag_match(w[i], 0u) != 0u;
-          load[i] = false;
-        }
-      }
-      v2i64 kv[R];
-      bool cand[R], hit[R];
-      int64_t pay[R];
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        cand[i] = act[i] && m[i] != 0u;
-        int j = cand[i] ? __builtin_ctz(m[i]) : 0;
-        kv[i] = cand[i] ? slots[b[i] * kBucket + j] : v2i64{0, 0};
-        m[i] &= m[i] - 1u;
-      }
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        hit[i] = cand[i] && kv[i].x == k[i];
-        pay[i] = kv[i].y;
-      }
-      on_round(hit, pay);
-      bool more = false;
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        if (!act[i]) continue;
-        if (hit[i] && unique) act[i] = false;
-        else if (m[i] == 0u) {
-          if (empty[i]) act[i] = false;  // an empty slot ends the chain
-          else {
-            b[i] = (b[i] + 1) & bmask;
-            load[i] = true;
-          }
-        }
-        more = more || act[i];
-      }
-      if (!more) break;
-    }
-  }
-};
 
 template <int MODE, int NC, int NE>
 __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const TableHeader* h, const int64_t* pkeys, int64_t n, RowPlan P,

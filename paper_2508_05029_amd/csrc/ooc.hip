@@ -56,6 +56,7 @@ struct ChunkRef {
   int64_t dev = -1;  // arena chunk id, or -1 when not resident
   int32_t page = -1, sub = -1;  // spill location
   int64_t rows = 0;
+  bool pinned = false;  // an append that is being assembled writes into it
 };
 
 struct Holder {
@@ -192,7 +193,7 @@ class Driver {
 
   bool spillable(int p, const Holder& h, size_t idx) const {
     const ChunkRef& c = h.chunks[idx];
-    if (c.dev < 0) return false;
+    if (c.dev < 0 || c.pinned) return false;
     if (phase == 1) return idx + 1 < h.chunks.size();  // the tail chunk still receives appends
     return p < pin_lo || p > pin_hi;
   }
@@ -228,12 +229,16 @@ class Driver {
       cur_sub = 0;
     }
     // the spill copy follows everything already enqueued on the compute stream
-    hipEvent_t fence;
-    hipError_t e = hipEventCreateWithFlags(&fence, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(fence, compute)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(spill, fence, 0)) != hipSuccess) return e;
-    (void)hipEventDestroy(fence);
+    // (appends) and on the copy stream (a reload into this chunk)
+    for (hipStream_t src : {compute, copy}) {
+      hipEvent_t fence;
+      hipError_t e = hipEventCreateWithFlags(&fence, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+      if ((e = hipEventRecord(fence, src)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(spill, fence, 0)) != hipSuccess) return e;
+      (void)hipEventDestroy(fence);
+    }
+    hipError_t e;
     char* host = static_cast<char*>(tq_pagepool_page(pool, cur_page)) + (size_t)cur_sub * chunk_bytes;
     if ((e = hipMemcpyAsync(host, chunk_ptr(c.dev), chunk_bytes, hipMemcpyDeviceToHost, spill)) != hipSuccess) return e;
     st.bytes_d2h += (int64_t)chunk_bytes;
@@ -293,18 +298,28 @@ class Driver {
   // columns `src` (side column j at src[j]) to the holders.
   tq_status append(Side& s, char* const* src, const int64_t* off) {
     descs.clear();
-    for (int p = 0; p < nparts; p++) {
+    // every chunk this batch writes into stays pinned (not spillable) until the
+    // copy kernel that fills it has been enqueued
+    std::vector<std::pair<int, size_t>> touched;
+    for (int p = 0; p < nparts; p++)
+      if (!s.parts[p].chunks.empty()) {
+        s.parts[p].chunks.back().pinned = true;
+        touched.emplace_back(p, s.parts[p].chunks.size() - 1);
+      }
+    tq_status e = TQ_OK;
+    for (int p = 0; p < nparts && e == TQ_OK; p++) {
       int64_t at = off[p], left = off[p + 1] - off[p];
       Holder& h = s.parts[p];
       h.rows += left;
       while (left > 0) {
         if (h.chunks.empty() || h.chunks.back().rows == s.rows_per_chunk) {
           int64_t id;
-          tq_status e = take_chunk(&id);
-          if (e) return e;
+          if ((e = take_chunk(&id))) break;
           ChunkRef c;
           c.dev = id;
+          c.pinned = true;
           h.chunks.push_back(c);
+          touched.emplace_back(p, h.chunks.size() - 1);
         }
         ChunkRef& c = h.chunks.back();
         int64_t m = std::min(left, s.rows_per_chunk - c.rows);
@@ -317,7 +332,9 @@ class Driver {
         left -= m;
       }
     }
-    return launch_copies();
+    if (e == TQ_OK) e = launch_copies();
+    for (auto& t : touched) s.parts[t.first].chunks[t.second].pinned = false;
+    return e;
   }
 
   tq_status launch_copies() {
@@ -478,18 +495,14 @@ class Driver {
     if (n_chunks < 4) return fail(TQ_ENOMEM, "budget leaves room for %lld chunks", (long long)n_chunks);
     for (int64_t i = n_chunks - 1; i >= 0; i--) free_chunks.push_back(i);
 
-    // ---- pass 1
+    // ---- pass 1, dimension side
     phase = 1;
     if ((s = tq_pagepool_stream(pool, dimb, nd, staging, max_batch * plan.nslots, plan.nslots, on_dim, this, copy, compute)))
       return s;
     for (int64_t i = 0; i < nd; i++) st.bytes_h2d += batch_bytes(dimb[i]);
-    if ((s = tq_pagepool_stream(pool, factb, nf, staging, max_batch * plan.nslots, plan.nslots, on_fact, this, copy, compute)))
-      return s;
-    for (int64_t i = 0; i < nf; i++) st.bytes_h2d += batch_bytes(factb[i]);
-    TQ_HIP(hipStreamSynchronize(compute));
-    auto t1 = std::chrono::steady_clock::now();
 
-    // ---- pass 2 buffers: the largest dimension partition, gathered, and its table
+    // ---- pass 2 buffers, sized by the largest dimension partition and taken
+    // now, while the arena is still mostly free: the gathered partition and its table
     int64_t max_part = 1;
     for (int q = 0; q < nparts; q++) max_part = std::max(max_part, dim.parts[q].rows);
     size_t gather_bytes = 2 * align_up((size_t)max_part * 8, kAlign);
@@ -500,6 +513,14 @@ class Driver {
     int64_t* g_pay = reinterpret_cast<int64_t*>(region + align_up((size_t)max_part * 8, kAlign));
     void* table = region + gather_bytes;
     if ((s = tq_join_table_init(table, table_bytes, compute))) return s;
+    phase = 1;
+
+    // ---- pass 1, fact side
+    if ((s = tq_pagepool_stream(pool, factb, nf, staging, max_batch * plan.nslots, plan.nslots, on_fact, this, copy, compute)))
+      return s;
+    for (int64_t i = 0; i < nf; i++) st.bytes_h2d += batch_bytes(factb[i]);
+    TQ_HIP(hipStreamSynchronize(compute));
+    auto t1 = std::chrono::steady_clock::now();
 
     // ---- pass 2
     phase = 2;

@@ -1,0 +1,320 @@
+// The serving loop: admission by device-memory budget, worker threads with
+// their own streams, per-request latency stamps.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+
+namespace tq {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// First-fit allocator over the device arena (offsets only; host side).
+class Arena {
+ public:
+  explicit Arena(size_t bytes) { free_[0] = bytes; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = al(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        size_t left = it->second - bytes;
+        size_t next = it->first + bytes;
+        free_.erase(it);
+        if (left) free_[next] = left;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = al(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+struct Plan {  // device memory of one request, as offsets into its region
+  size_t state, table, keys, count, sums, avg, ngroups, staging, scratch, total;
+  size_t state_bytes, table_bytes, staging_bytes;
+  int64_t domain;
+  int nsum;
+};
+
+tq_col window(const tq_col& c, int64_t first) {
+  tq_col w = c;
+  w.data = static_cast<const char*>(c.data) + (size_t)first * c.type;
+  return w;
+}
+
+struct Server {
+  const tq_serve_tables& T;
+  const tq_request* reqs;
+  int64_t n;
+  tq_budget* budget;
+  char* arena_base;
+  Arena arena;
+  int64_t max_groups;
+  int64_t *h_keys, *h_count, *h_sums;
+  tq_request_result* res;
+  Clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv;
+  struct Slot {
+    int64_t job = -1;
+    size_t off = 0, bytes = 0;
+    bool busy = false;
+  };
+  std::vector<Slot> slots;
+  bool shutdown = false;
+  int64_t completed = 0;
+
+  Server(const tq_serve_tables& t, const tq_request* r, int64_t nr, tq_budget* b, void* d_arena, size_t arena_bytes,
+         int64_t mg, int64_t* k, int64_t* c, int64_t* s, tq_request_result* out)
+      : T(t), reqs(r), n(nr), budget(b), arena_base(static_cast<char*>(d_arena)), arena(arena_bytes), max_groups(mg),
+        h_keys(k), h_count(c), h_sums(s), res(out) {}
+
+  double now_s() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+  Plan plan_of(const tq_request& q) const {
+    Plan p{};
+    p.domain = q.shape == 0 ? T.fg_domain : T.join_domain;
+    p.nsum = q.shape == 0 ? T.fg_nsum : T.join_nsum;
+    p.state_bytes = tq_groupby_state_bytes(p.domain, p.nsum);
+    p.table_bytes = q.shape == 0 ? 0 : tq_join_table_bytes(q.n_dim, T.load_factor);
+    size_t staging = 0;
+    if (q.shape == 2) {
+      size_t mx = 0;
+      for (int64_t b = q.fact_first; b < q.fact_first + q.n_fact; b++)
+        mx = std::max(mx, (size_t)T.fact_batches[b].npages * tq_pagepool_page_bytes(T.pool));
+      staging = mx * (size_t)T.nslots;
+    }
+    p.staging_bytes = staging;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      size_t at = o;
+      o += al(std::max<size_t>(b, 8));
+      return at;
+    };
+    p.state = take(p.state_bytes);
+    p.table = take(p.table_bytes);
+    p.keys = take(p.domain * 8);
+    p.count = take(p.domain * 8);
+    p.sums = take(p.domain * p.nsum * 8);
+    p.avg = take(p.domain * p.nsum * 8);
+    p.ngroups = take(8);
+    p.staging = take(staging);
+    p.scratch = take(64);
+    p.total = o;
+    return p;
+  }
+
+  struct ProbeCtx {
+    const Server* s;
+    void* table;
+    tq_agg agg;
+  };
+
+  static tq_status on_batch(void* user, int64_t, const tq_col* cols, int32_t, int64_t nrows, hipStream_t compute) {
+    auto* c = static_cast<ProbeCtx*>(user);
+    const tq_serve_tables& T = c->s->T;
+    tq_col fc[4];
+    for (int j = 0; j < T.fact_ncol; j++) fc[j] = cols[T.fact_map[j]];
+    return tq_join_probe(c->table, static_cast<const int64_t*>(fc[0].data), nrows, fc, T.fact_ncol, nullptr, 0, nullptr,
+                         nullptr, 0, nullptr, &c->agg, compute);
+  }
+
+  tq_status execute(const tq_request& q, char* base, hipStream_t compute, hipStream_t copy, int64_t idx) {
+    Plan p = plan_of(q);
+    void* state = base + p.state;
+    int64_t* keys = reinterpret_cast<int64_t*>(base + p.keys);
+    int64_t* count = reinterpret_cast<int64_t*>(base + p.count);
+    int64_t* sums = reinterpret_cast<int64_t*>(base + p.sums);
+    double* avg = reinterpret_cast<double*>(base + p.avg);
+    int64_t* ng = reinterpret_cast<int64_t*>(base + p.ngroups);
+    tq_status s;
+    if ((s = tq_groupby_init(state, p.state_bytes, p.domain, p.nsum, compute))) return s;
+    if (q.shape == 0) {
+      tq_col w[TQ_MAX_COLS];
+      for (int c = 0; c < T.fg_ncol; c++) w[c] = window(T.fg_cols[c], q.fact_first);
+      if ((s = tq_groupby_agg(state, p.domain, w, T.fg_ncol, q.n_fact, T.fg_preds, T.fg_np, &T.fg_key, T.fg_sums,
+                              T.fg_nsum, compute)))
+        return s;
+    } else {
+      void* table = base + p.table;
+      tq_col dw[4];
+      for (int c = 0; c < T.dim_ncol; c++) dw[c] = window(T.dim_cols[c], q.dim_first);
+      if ((s = tq_join_table_init(table, p.table_bytes, compute))) return s;
+      if ((s = tq_join_build(table, p.table_bytes, static_cast<const int64_t*>(dw[0].data), dw[1], q.n_dim, dw,
+                             T.dim_ncol, T.dim_preds, T.dim_np, T.load_factor, 0, TQ_UNIQUE_KEYS, compute)))
+        return s;
+      tq_agg agg{state, p.domain, T.join_sums, T.join_nsum};
+      if (q.shape == 1) {
+        tq_col fw[4];
+        for (int c = 0; c < T.fact_ncol; c++) fw[c] = window(T.fact_cols[c], q.fact_first);
+        if ((s = tq_join_probe(table, static_cast<const int64_t*>(fw[0].data), q.n_fact, fw, T.fact_ncol, nullptr, 0,
+                               nullptr, nullptr, 0, nullptr, &agg, compute)))
+          return s;
+      } else {
+        ProbeCtx ctx{this, table, agg};
+        if ((s = tq_pagepool_stream(T.pool, T.fact_batches + q.fact_first, q.n_fact, base + p.staging, p.staging_bytes,
+                                    T.nslots, on_batch, &ctx, copy, compute)))
+          return s;
+      }
+    }
+    if ((s = tq_groupby_finalize(state, keys, count, sums, avg, ng, compute))) return s;
+    if ((s = tq_check(state, compute))) return s;
+    int64_t g = 0;
+    TQ_HIP(hipMemcpyAsync(&g, ng, 8, hipMemcpyDeviceToHost, compute));
+    TQ_HIP(hipStreamSynchronize(compute));
+    g = std::min(g, max_groups);
+    res[idx].ngroups = g;
+    if (g > 0) {
+      TQ_HIP(hipMemcpyAsync(h_keys + idx * max_groups, keys, (size_t)g * 8, hipMemcpyDeviceToHost, compute));
+      TQ_HIP(hipMemcpyAsync(h_count + idx * max_groups, count, (size_t)g * 8, hipMemcpyDeviceToHost, compute));
+      if (p.nsum)
+        TQ_HIP(hipMemcpyAsync(h_sums + idx * max_groups * TQ_MAX_SUMS, sums, (size_t)g * p.nsum * 8,
+                              hipMemcpyDeviceToHost, compute));
+      TQ_HIP(hipStreamSynchronize(compute));
+    }
+    return TQ_OK;
+  }
+
+  void worker(int w) {
+    hipStream_t compute = nullptr, copy = nullptr;
+    bool ok = hipStreamCreateWithFlags(&compute, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&copy, hipStreamNonBlocking) == hipSuccess;
+    for (;;) {
+      int64_t job;
+      size_t off, bytes;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return shutdown || slots[w].job >= 0; });
+        if (slots[w].job < 0) break;
+        job = slots[w].job;
+        off = slots[w].off;
+        bytes = slots[w].bytes;
+      }
+      res[job].start_s = now_s();
+      res[job].worker = w;
+      tq_status s = ok ? execute(reqs[job], arena_base + off, compute, copy, job) : TQ_EHIP;
+      if (s) {
+        (void)hipStreamSynchronize(compute);
+        (void)hipStreamSynchronize(copy);
+      }
+      res[job].status = s;
+      res[job].end_s = now_s();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        arena.release(off, bytes);
+        tq_budget_release(budget, bytes);
+        slots[w].job = -1;
+        slots[w].busy = false;
+        completed++;
+      }
+      cv.notify_all();
+    }
+    if (compute) (void)hipStreamDestroy(compute);
+    if (copy) (void)hipStreamDestroy(copy);
+  }
+
+  tq_status run(int workers) {
+    slots.assign(workers, Slot());
+    for (int64_t i = 0; i < n; i++) {
+      res[i] = tq_request_result{};
+      res[i].status = TQ_OK;
+    }
+    t0 = Clock::now();
+    std::vector<std::thread> th;
+    for (int w = 0; w < workers; w++) th.emplace_back([this, w] { worker(w); });
+    int64_t next = 0;
+    std::unique_lock<std::mutex> lk(mu);
+    while (completed < n) {
+      if (next < n) {
+        double wait = reqs[next].arrival_s - now_s();
+        if (wait > 0) {
+          cv.wait_for(lk, std::chrono::duration<double>(wait));
+          continue;
+        }
+        int idle = -1;
+        for (int w = 0; w < workers && idle < 0; w++)
+          if (!slots[w].busy) idle = w;
+        if (idle >= 0) {
+          Plan p = plan_of(reqs[next]);
+          size_t off;
+          if (p.total > tq_budget_cap(budget)) {  // can never fit: fail it rather than block the queue
+            res[next].status = TQ_ENOMEM;
+            res[next].start_s = res[next].end_s = now_s();
+            next++;
+            completed++;
+            continue;
+          }
+          if (tq_budget_reserve(budget, p.total) == TQ_OK) {
+            if (arena.alloc(p.total, &off)) {
+              slots[idle] = Slot{next, off, p.total, true};
+              next++;
+              cv.notify_all();
+              continue;
+            }
+            tq_budget_release(budget, p.total);
+          }
+        }
+      }
+      cv.wait_for(lk, std::chrono::milliseconds(1));  // a completion frees a worker or memory
+    }
+    shutdown = true;
+    lk.unlock();
+    cv.notify_all();
+    for (auto& t : th) t.join();
+    return TQ_OK;
+  }
+};
+
+}  // namespace
+}  // namespace tq
+
+extern "C" tq_status tq_serve_run(const tq_serve_tables* t, const tq_request* reqs, int64_t n, int32_t workers,
+                                  tq_budget* budget, void* d_arena, size_t arena_bytes, int64_t max_groups,
+                                  int64_t* h_keys, int64_t* h_count, int64_t* h_sums, tq_request_result* res) {
+  using tq::fail;
+  if (!t || (n > 0 && (!reqs || !res || !h_keys || !h_count || !h_sums)) || !budget || !d_arena)
+    return fail(TQ_EINVAL, "NULL argument");
+  if (workers < 1 || workers > 64) return fail(TQ_EINVAL, "workers outside [1, 64]");
+  if (max_groups < 1) return fail(TQ_EINVAL, "max_groups");
+  for (int64_t i = 0; i < n; i++) {
+    const tq_request& q = reqs[i];
+    if (i > 0 && q.arrival_s < reqs[i - 1].arrival_s) return fail(TQ_EINVAL, "requests must be in arrival order");
+    if (q.shape < 0 || q.shape > 2 || q.n_fact < 0 || q.fact_first < 0) return fail(TQ_EINVAL, "request %lld", (long long)i);
+    if (q.shape != 2 && q.fact_first % 16) return fail(TQ_EINVAL, "request %lld: window start not a multiple of 16", (long long)i);
+    if (q.shape != 0 && (q.dim_first % 16 || q.n_dim < 0)) return fail(TQ_EINVAL, "request %lld: dimension window", (long long)i);
+    if (q.shape == 2 && (!t->pool || q.fact_first + q.n_fact > t->n_fact_batches))
+      return fail(TQ_EINVAL, "request %lld: batch window", (long long)i);
+  }
+  tq::Server s(*t, reqs, n, budget, d_arena, arena_bytes, max_groups, h_keys, h_count, h_sums, res);
+  return s.run(workers);
+}

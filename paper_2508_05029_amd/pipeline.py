@@ -195,3 +195,201 @@ class OocJoinAgg:
         r["keys"] = r["keys"].reshape(-1, 1)
         r["join_rows"] = int(r["count"].sum())
         return r
+
+
+def _align(x: int, a: int = 256) -> int:
+    return (x + a - 1) // a * a
+
+
+class BatchedJoinAgg:
+    """Many join + group-by instances of one query shape (tq_batched_*).
+
+    instances: list of (dim table, fact table, domain) as numpy dicts;
+    params: per instance (load_factor, build_tile, probe_tile), e.g. from the
+    autotuner. All device memory is one torch allocation carved into columns,
+    tables, states and outputs."""
+
+    def __init__(self, query, instances, params, device="cuda", unique: bool = True):
+        self.q = query
+        self.dnames = referenced(query.build_preds, [], [query.build_key, query.build_payload])
+        self.fnames = referenced([], query.sums, [query.probe_key])
+        assert len(self.dnames) <= 4 and len(self.fnames) <= 4
+        Q = tq.BatchQuery()
+        d0, f0, _ = instances[0]
+        for i, c in enumerate(self.dnames):
+            Q.dim_types[i] = tq._TYPE[torch.from_numpy(d0[c][:0]).dtype]
+        Q.ndim = len(self.dnames)
+        for j, p in enumerate(query.build_preds):
+            Q.preds[j] = tq.PredS(self.dnames.index(p.col), p.lo, p.hi)
+        Q.np = len(query.build_preds)
+        for i, c in enumerate(self.fnames):
+            Q.fact_types[i] = tq._TYPE[torch.from_numpy(f0[c][:0]).dtype]
+        Q.nfact = len(self.fnames)
+        for j, e in enumerate(query.sums):
+            Q.sums[j].nf = len(e)
+            for k, f in enumerate(e):
+                Q.sums[j].f[k] = tq.FactorS(-1 if f.col is None else self.fnames.index(f.col), f.sign, f.add)
+        Q.nsum = len(query.sums)
+        Q.join_flags = tq.TQ_UNIQUE_KEYS if unique else 0
+        self.Q = Q
+        nsum = Q.nsum
+        # carve one allocation
+        plan, total = [], 0
+
+        def take(nbytes):
+            nonlocal total
+            off = total
+            total = _align(total + max(int(nbytes), 1))
+            return off
+
+        for (d, f, domain), (lf, bt, pt) in zip(instances, params):
+            nd, nf = len(d[self.dnames[0]]), len(f[self.fnames[0]])
+            e = {"dcols": [take(d[c].nbytes) for c in self.dnames], "fcols": [take(f[c].nbytes) for c in self.fnames],
+                 "table": take(tq.join_table_bytes(nd, lf)), "tbytes": tq.join_table_bytes(nd, lf),
+                 "state": take(tq.batched_state_bytes(domain, nsum)), "sbytes": tq.batched_state_bytes(domain, nsum),
+                 "keys": take(domain * 8), "count": take(domain * 8), "sums": take(domain * nsum * 8),
+                 "avg": take(domain * nsum * 8), "ng": take(8), "nd": nd, "nf": nf, "domain": domain,
+                 "lf": lf, "bt": bt, "pt": pt}
+            plan.append(e)
+        self.arena = torch.empty(total, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        self.insts = (tq.Instance * len(instances))()
+        host = torch.empty(total, dtype=torch.uint8, pin_memory=True)
+        hb = host.data_ptr()
+        for i, ((d, f, domain), e) in enumerate(zip(instances, plan)):
+            I = self.insts[i]
+            for j, c in enumerate(self.dnames):
+                a = np.ascontiguousarray(d[c])
+                ctypes.memmove(hb + e["dcols"][j], a.ctypes.data, a.nbytes)
+                I.dim_cols[j] = base + e["dcols"][j]
+            for j, c in enumerate(self.fnames):
+                a = np.ascontiguousarray(f[c])
+                ctypes.memmove(hb + e["fcols"][j], a.ctypes.data, a.nbytes)
+                I.fact_cols[j] = base + e["fcols"][j]
+            I.n_dim, I.n_fact, I.domain = e["nd"], e["nf"], domain
+            I.d_table, I.table_bytes = base + e["table"], e["tbytes"]
+            I.d_state, I.state_bytes = base + e["state"], e["sbytes"]
+            I.d_keys, I.d_count, I.d_sums = base + e["keys"], base + e["count"], base + e["sums"]
+            I.d_avg, I.d_ngroups = base + e["avg"], base + e["ng"]
+            I.load_factor, I.build_tile, I.probe_tile = e["lf"], e["bt"], e["pt"]
+        self.arena.copy_(host)
+        del host
+        self.plan = plan
+        self.n = len(instances)
+        self.nsum = nsum
+        self.input_bytes = sum(len(self.dnames) * 8 * e["nd"] + len(self.fnames) * 8 * e["nf"] for e in plan)
+        self.work = torch.empty(max(1, tq.batched_work_bytes(self.insts)), dtype=torch.uint8, device=device)
+        tq.batched_prepare(self.Q, self.insts, self.work)
+
+    def run(self, stream=None):
+        tq.batched_run(self.Q, self.work, self.n, stream)
+
+    def run_per_instance(self, stream=None):
+        tq.batched_run_per_instance(self.Q, self.insts, stream)
+
+    def check(self, stream=None):
+        tq.batched_check(self.work, stream)
+
+    def results(self, which=None):
+        """Outputs of the instances in `which` (default all), copied per instance."""
+        torch.cuda.synchronize()
+        out = []
+        for i in (range(self.n) if which is None else which):
+            e = self.plan[i]
+            g = int(self.arena[e["ng"]:e["ng"] + 8].cpu().numpy().view(np.int64)[0])
+            ns = self.nsum
+
+            def grab(off, nbytes, dt):
+                return self.arena[off:off + nbytes].cpu().numpy().view(dt)
+            out.append({"keys": grab(e["keys"], 8 * g, np.int64).reshape(-1, 1),
+                        "count": grab(e["count"], 8 * g, np.int64),
+                        "sums": grab(e["sums"], 8 * g * ns, np.int64).reshape(g, ns),
+                        "avg": grab(e["avg"], 8 * g * ns, np.float64).reshape(g, ns)})
+        return out
+
+
+class ServingSetup:
+    """Base tables for the three request shapes and the request -> window mapping.
+
+    shape 0: a filter + group-by table in device memory (n0 rows)
+    shape 1: a dimension (n_dim rows) and a fact table (n1 rows) in device memory
+    shape 2: the same dimension, and a fact table in page-pool batches (n2 rows)
+    A request of n fact rows reads a seeded window of its shape's base tables;
+    join requests read a dimension window of n / 4 rows."""
+
+    def __init__(self, n0, n_dim, n1, n2, batch_rows, pool, seed=None, device="cuda", load_factor=0.5, nslots=3):
+        from .datagen import workloads as wl
+        from .hosttable import HostTable
+        seed = wl.SERVE_SEED if seed is None else seed
+        self.wl = wl
+        self.fg = wl.filter_groupby_tables(n0, seed=seed + 10)
+        self.dim, self.fact = wl.join_agg_tables(n_dim, n1, seed=seed + 11)
+        self.hdim, self.hfact = wl.ooc_tables_numpy(n2, n_dim, seed=seed + 12)
+        self.fg_dev = to_device(self.fg, device)
+        self.dim_dev = to_device(self.dim, device)
+        self.fact_dev = to_device(self.fact, device)
+        self.batch_rows = batch_rows
+        self.host = HostTable(pool, wl.OOC_FACT_COLS, n2, batch_rows)
+        self.host.fill_numpy(self.hfact)
+        self.n0, self.n_dim, self.n1, self.n2 = n0, n_dim, n1, n2
+        q0, q1 = wl.FILTER_GROUPBY_QUERY, wl.JOIN_AGG_QUERY
+        self.q0, self.q1 = q0, q1
+        T = tq.ServeTables()
+        names0 = referenced(q0.preds, q0.sums, q0.key.cols)
+        for i, c in enumerate(names0):
+            T.fg_cols[i] = tq.col(self.fg_dev[c])
+        T.fg_ncol = len(names0)
+        for j, (c, lo, hi) in enumerate(plan_preds(names0, q0.preds)):
+            T.fg_preds[j] = tq.PredS(c, lo, hi)
+        T.fg_np = len(q0.preds)
+        T.fg_key = tq.gkey([names0.index(c) for c in q0.key.cols], q0.key.mult)
+        for j, e in enumerate(plan_exprs(names0, q0.sums)):
+            T.fg_sums[j].nf = len(e)
+            for k, (c, s, a) in enumerate(e):
+                T.fg_sums[j].f[k] = tq.FactorS(c, s, a)
+        T.fg_nsum, T.fg_domain = len(q0.sums), q0.key.domain
+        dnames = referenced(q1.build_preds, [], [q1.build_key, q1.build_payload])
+        for i, c in enumerate(dnames):
+            T.dim_cols[i] = tq.col(self.dim_dev[c])
+        T.dim_ncol = len(dnames)
+        for j, p in enumerate(q1.build_preds):
+            T.dim_preds[j] = tq.PredS(dnames.index(p.col), p.lo, p.hi)
+        T.dim_np = len(q1.build_preds)
+        fnames = referenced([], q1.sums, [q1.probe_key])
+        for i, c in enumerate(fnames):
+            T.fact_cols[i] = tq.col(self.fact_dev[c])
+            T.fact_map[i] = self.host.col_index(c)
+        T.fact_ncol = len(fnames)
+        for j, e in enumerate(plan_exprs(fnames, q1.sums)):
+            T.join_sums[j].nf = len(e)
+            for k, (c, s, a) in enumerate(e):
+                T.join_sums[j].f[k] = tq.FactorS(c, s, a)
+        T.join_nsum, T.join_domain, T.load_factor = len(q1.sums), q1.domain, load_factor
+        self._batches = self.host.c_batches()
+        T.pool = pool.h
+        T.fact_batches = ctypes.cast(self._batches[0], ctypes.c_void_p)
+        T.n_fact_batches = len(self.host.batches)
+        T.nslots = nslots
+        self.T = T
+
+    def requests(self, reqs, time_scale=1.0):
+        """tq_request array for workload Request objects (shape, n_fact, arrival)."""
+        out = (tq.Request * max(1, len(reqs)))()
+        rng = np.random.default_rng(12345)
+        for i, r in enumerate(reqs):
+            q = out[i]
+            q.shape, q.arrival_s = r.shape, r.arrival_s * time_scale
+            if r.shape == 0:
+                n = min(r.n_fact, self.n0)
+                q.fact_first, q.n_fact = int(rng.integers(0, self.n0 - n + 1)) // 16 * 16, n
+            elif r.shape == 1:
+                n = min(r.n_fact, self.n1)
+                q.fact_first, q.n_fact = int(rng.integers(0, self.n1 - n + 1)) // 16 * 16, n
+            else:
+                nb = min(max(1, -(-r.n_fact // self.batch_rows)), len(self.host.batches))
+                q.fact_first, q.n_fact = int(rng.integers(0, len(self.host.batches) - nb + 1)), nb
+                n = nb * self.batch_rows
+            if r.shape != 0:
+                nd = max(1, min(n // 4, self.n_dim))
+                q.dim_first, q.n_dim = int(rng.integers(0, self.n_dim - nd + 1)) // 16 * 16, nd
+        return out

@@ -419,3 +419,108 @@ def ooc_join_agg(pool, dim_batches, fact_batches, plan: OocPlan, budget: Budget,
                                         work.data_ptr(), _nbytes(work), state.data_ptr(), ctypes.byref(st),
                                         _stream(copy_stream), _stream(compute_stream)))
     return st
+
+
+# ------------------------------------------------------------------ batched instances
+
+class BatchQuery(ctypes.Structure):
+    _fields_ = [("dim_types", ctypes.c_int32 * 4), ("ndim", ctypes.c_int32), ("preds", PredS * 2),
+                ("np", ctypes.c_int32), ("fact_types", ctypes.c_int32 * 4), ("nfact", ctypes.c_int32),
+                ("sums", ExprS * 2), ("nsum", ctypes.c_int32), ("join_flags", ctypes.c_uint32)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("dim_cols", ctypes.c_void_p * 4), ("n_dim", ctypes.c_int64), ("fact_cols", ctypes.c_void_p * 4),
+                ("n_fact", ctypes.c_int64), ("domain", ctypes.c_int64), ("d_table", ctypes.c_void_p),
+                ("table_bytes", ctypes.c_size_t), ("d_state", ctypes.c_void_p), ("state_bytes", ctypes.c_size_t),
+                ("d_keys", ctypes.c_void_p), ("d_count", ctypes.c_void_p), ("d_sums", ctypes.c_void_p),
+                ("d_avg", ctypes.c_void_p), ("d_ngroups", ctypes.c_void_p), ("load_factor", ctypes.c_double),
+                ("build_tile", ctypes.c_int32), ("probe_tile", ctypes.c_int32)]
+
+
+_batched_sig = {
+    "tq_batched_state_bytes": (_sz, [_i64, _i32]),
+    "tq_batched_work_bytes": (_sz, [_vp, _i32]),
+    "tq_batched_prepare": (_i32, [ctypes.POINTER(BatchQuery), _vp, _i32, _vp, _sz, _vp]),
+    "tq_batched_run": (_i32, [ctypes.POINTER(BatchQuery), _vp, _i32, _vp]),
+    "tq_batched_check": (_i32, [_vp, _vp]),
+    "tq_batched_run_per_instance": (_i32, [ctypes.POINTER(BatchQuery), _vp, _i32, _vp]),
+}
+
+
+def _bind_batched():
+    L = lib()
+    if getattr(L, "_batched_bound", False):
+        return L
+    for name, (res, args) in _batched_sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    L._batched_bound = True
+    return L
+
+
+def batched_state_bytes(domain: int, nsum: int) -> int:
+    return _bind_batched().tq_batched_state_bytes(domain, nsum)
+
+
+def batched_work_bytes(insts) -> int:
+    return _bind_batched().tq_batched_work_bytes(insts, len(insts))
+
+
+def batched_prepare(q: BatchQuery, insts, work, stream=None):
+    _check(_bind_batched().tq_batched_prepare(ctypes.byref(q), insts, len(insts), work.data_ptr(), _nbytes(work),
+                                              _stream(stream)))
+
+
+def batched_run(q: BatchQuery, work, n: int, stream=None):
+    _check(_bind_batched().tq_batched_run(ctypes.byref(q), work.data_ptr(), n, _stream(stream)))
+
+
+def batched_check(work, stream=None):
+    _check(_bind_batched().tq_batched_check(work.data_ptr(), _stream(stream)))
+
+
+def batched_run_per_instance(q: BatchQuery, insts, stream=None):
+    _check(_bind_batched().tq_batched_run_per_instance(ctypes.byref(q), insts, len(insts), _stream(stream)))
+
+
+# ------------------------------------------------------------------ serving
+
+class ServeTables(ctypes.Structure):
+    _fields_ = [("fg_cols", Col * MAX_COLS), ("fg_ncol", ctypes.c_int32), ("fg_preds", PredS * MAX_PREDS),
+                ("fg_np", ctypes.c_int32), ("fg_key", GKey), ("fg_sums", ExprS * MAX_SUMS), ("fg_nsum", ctypes.c_int32),
+                ("fg_domain", ctypes.c_int64), ("dim_cols", Col * 4), ("dim_ncol", ctypes.c_int32),
+                ("dim_preds", PredS * 2), ("dim_np", ctypes.c_int32), ("fact_cols", Col * 4),
+                ("fact_ncol", ctypes.c_int32), ("join_sums", ExprS * 2), ("join_nsum", ctypes.c_int32),
+                ("join_domain", ctypes.c_int64), ("load_factor", ctypes.c_double), ("pool", ctypes.c_void_p),
+                ("fact_batches", ctypes.c_void_p), ("n_fact_batches", ctypes.c_int64), ("fact_map", ctypes.c_int32 * 4),
+                ("nslots", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("fact_first", ctypes.c_int64), ("n_fact", ctypes.c_int64),
+                ("dim_first", ctypes.c_int64), ("n_dim", ctypes.c_int64), ("arrival_s", ctypes.c_double)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("start_s", ctypes.c_double), ("end_s", ctypes.c_double), ("status", ctypes.c_int32),
+                ("worker", ctypes.c_int32), ("ngroups", ctypes.c_int64)]
+
+
+def serve_run(tables: ServeTables, reqs, workers: int, budget: Budget, arena, max_groups: int):
+    import numpy as np
+    L = lib()
+    if not getattr(L, "_serve_bound", False):
+        L.tq_serve_run.restype = _i32
+        L.tq_serve_run.argtypes = [ctypes.POINTER(ServeTables), _vp, _i64, _i32, _vp, _vp, _sz, _i64, _vp, _vp, _vp,
+                                   _vp]
+        L._serve_bound = True
+    n = len(reqs)
+    keys = np.zeros((max(n, 1), max_groups), np.int64)
+    count = np.zeros((max(n, 1), max_groups), np.int64)
+    sums = np.zeros((max(n, 1), max_groups, MAX_SUMS), np.int64)
+    res = (RequestResult * max(n, 1))()
+    _check(L.tq_serve_run(ctypes.byref(tables), reqs, n, workers, budget.h, arena.data_ptr(), _nbytes(arena), max_groups,
+                          keys.ctypes.data, count.ctypes.data, sums.ctypes.data, res))
+    return res, keys, count, sums

@@ -1,0 +1,94 @@
+"""GPU: the serving loop. Every request's result is the same alone (one
+worker, one request at a time) and in the mix (several workers, requests
+overlapping on the device), and equals the oracle; admission respects the
+budget."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2508_05029_amd import pipeline, tq  # noqa: E402
+from paper_2508_05029_amd.datagen import workloads as wl  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def expected(setup, q):
+    if q.shape == 0:
+        t = {k: v[q.fact_first:q.fact_first + q.n_fact] for k, v in setup.fg.items()}
+        return oracle.filter_groupby(t, setup.q0)
+    d = {k: v[q.dim_first:q.dim_first + q.n_dim] for k, v in setup.dim.items()}
+    if q.shape == 1:
+        f = {k: v[q.fact_first:q.fact_first + q.n_fact] for k, v in setup.fact.items()}
+    else:
+        lo = setup.host.batches[q.fact_first][0]
+        last = setup.host.batches[q.fact_first + q.n_fact - 1]
+        f = {k: v[lo:last[0] + last[1]] for k, v in setup.hfact.items()}
+    return oracle.join_agg(d, f, setup.q1)
+
+
+def packed(setup, q, res, keys, count, sums, i):
+    g = res[i].ngroups
+    nsum = 5 if q.shape == 0 else 1
+    k = keys[i, :g]
+    if q.shape == 0:  # the packed key flagA * 2 + flagB
+        k = np.stack([k // 2, k % 2], axis=1)
+    else:
+        k = k.reshape(-1, 1)
+    return k, count[i, :g], sums[i, :g, :nsum]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    pool = tq.PagePool(1 << 20, 200, pinned=True)
+    s = pipeline.ServingSetup(n0=300_000, n_dim=120_000, n1=400_000, n2=400_000, batch_rows=16_384, pool=pool)
+    yield s
+    s.host.free()
+    pool.close()
+
+
+def test_alone_equals_mix_equals_oracle(setup):
+    reqs = wl.serving_requests(40, qps=2000.0, fact_lo=3.0, fact_hi=5.5, seed=wl.SERVE_SEED + 1)
+    R = setup.requests(reqs)
+    budget = tq.Budget(256 << 20)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    alone = tq.serve_run(setup.T, R, 1, budget, arena, 25)
+    mixed = tq.serve_run(setup.T, R, 6, budget, arena, 25)
+    assert budget.used == 0
+    workers_used = {mixed[0][i].worker for i in range(len(reqs))}
+    say(f"workers used in the mix: {sorted(workers_used)}")
+    assert len(workers_used) > 1
+    for i in range(len(reqs)):
+        q = R[i]
+        assert alone[0][i].status == 0 and mixed[0][i].status == 0, i
+        a = packed(setup, q, *alone, i)
+        m = packed(setup, q, *mixed, i)
+        w = expected(setup, q)
+        for x, y in zip(a, m):
+            assert x.tolist() == y.tolist(), (i, q.shape)
+        assert a[0].tolist() == w["keys"].tolist(), (i, q.shape)
+        assert a[1].tolist() == w["count"].tolist(), (i, q.shape)
+        assert a[2].tolist() == w["sums"].tolist(), (i, q.shape)
+
+
+def test_budget_admission_and_oversized_request(setup):
+    reqs = wl.serving_requests(12, qps=5000.0, fact_lo=4.0, fact_hi=5.0, seed=wl.SERVE_SEED + 2)
+    R = setup.requests(reqs)
+    # room for about one join request at a time: admission serialises, nothing deadlocks
+    budget = tq.Budget(24 << 20)
+    arena = torch.empty(24 << 20, dtype=torch.uint8, device="cuda")
+    res, keys, count, sums = tq.serve_run(setup.T, R, 4, budget, arena, 25)
+    ok = [res[i].status for i in range(len(reqs))]
+    assert all(s in (0, tq.TQ_ENOMEM) for s in ok)
+    for i in range(len(reqs)):
+        if res[i].status == 0:
+            w = expected(setup, R[i])
+            assert packed(setup, R[i], res, keys, count, sums, i)[1].tolist() == w["count"].tolist()
+    assert budget.used == 0
