@@ -166,9 +166,15 @@ def main():
     ap.add_argument("--event-steps", type=int, default=20)
     ap.add_argument("--load-factor", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ooc-scale", type=float, default=1.0, help="fraction of the 600M x 150M out-of-core tables")
+    ap.add_argument("--instances", type=int, default=4096, help="batched workload: number of instances")
+    ap.add_argument("--requests", type=int, default=400, help="serving workload: number of requests")
+    ap.add_argument("--workers", type=int, default=6, help="serving workload: concurrent workers")
+    ap.add_argument("--serve-base-rows", type=int, default=100_000_000,
+                    help="serving workload: rows of each base table")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch

@@ -1,0 +1,329 @@
+"""Benchmarks of the other workloads (bench.py --workload ...). Each returns one
+JSON-serialisable dict. Not imported by the library itself."""
+from __future__ import annotations
+
+import ctypes
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import autotune, pipeline, tq
+from .datagen import workloads as wl
+from .hosttable import HostTable
+
+HBM_PEAK_GBS = 8000.0
+PCIE_GBS = 63.0  # PCIe 5.0 x16, one direction
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _events():
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _base(metric, value, unit, args, ms, steps, workload, extra):
+    d = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": steps,
+         "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+         "vs_baseline": None, "dtype": "int64", "data": "synthetic (seeded generators; stands in for TPC-H/TPC-DS)",
+         "config": {"workload": workload}}
+    d.update(extra)
+    return d
+
+
+# ------------------------------------------------------------------ filter + group-by
+
+def bench_filter_groupby(args):
+    n = 1_000_000
+    t = wl.filter_groupby_tables(n)
+    q = wl.FILTER_GROUPBY_QUERY
+    copies = [pipeline.to_device(t) for _ in range(args.copies)]
+    fg = pipeline.FilterGroupBy(q)
+    in_bytes = n * 38
+    for i in range(max(3, args.warmup)):
+        fg.run(copies[i % len(copies)])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ks = []
+    for i in range(args.event_steps):
+        a, b = _events()
+        tq.groupby_init(fg.state, fg.domain, fg.nsum)
+        a.record(stream)
+        cols = [copies[i % len(copies)][c] for c in fg.names]
+        tq.groupby_agg(fg.state, fg.domain, cols, n, fg.preds, fg.key, fg.exprs)
+        b.record(stream)
+        ks.append((a, b))
+    torch.cuda.synchronize()
+    agg_ms = float(np.mean([a.elapsed_time(b) for a, b in ks]))
+    gs = args.graph_steps
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        for i in range(gs):
+            fg.run(copies[i % len(copies)])
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        for i in range(gs):
+            fg.run(copies[i % len(copies)])
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // gs)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / (reps * gs)
+    got = fg.result()
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ts = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            want = oracle.filter_groupby(t, q)
+            ts.append(time.perf_counter() - t1)
+        tc = float(np.median(ts))
+        parity = got["sums"].tolist() == want["sums"].tolist() and got["count"].tolist() == want["count"].tolist()
+        cpu = {"value": round(in_bytes / tc / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole 1M-row workload, median of 5 runs, {tc:.3f} s per run"}
+    gbs = in_bytes / (ms / 1e3) / 1e9
+    kgbs = in_bytes / (agg_ms / 1e3) / 1e9
+    return _base("input GB/s filter-group-by (% of HBM peak)", gbs, "GB/s", args, ms, reps * gs,
+                 "filter_groupby: 1M rows, date<=2436, group (flagA, flagB), 5 sums + COUNT + AVG",
+                 {"pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                  "roofline": {"bound": "hbm", "achieved": round(kgbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": None,
+                               "kernel": "k_groupby", "bytes_per_launch": in_bytes},
+                  "cpu_baseline": cpu, "parity_vs_oracle": parity})
+
+
+# ------------------------------------------------------------------ out of core
+
+def _pinned_copy_peak(pool_bytes=1 << 30):
+    h = torch.empty(pool_bytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+    d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    for _ in range(4):
+        d.copy_(h, non_blocking=True)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 4 * pool_bytes / (a.elapsed_time(b) / 1e3) / 1e9
+    del h, d
+    return gbs
+
+
+def bench_ooc(args):
+    scale = args.ooc_scale
+    n_fact, n_dim = int(wl.OOC_FACT_ROWS * scale), int(wl.OOC_DIM_ROWS * scale)
+    page = 64 << 20
+    rows_per_batch = 3 * page // 44 // 256 * 256  # about three pages per fact batch
+    budget = int(24e9 * scale) if scale < 1 else int(24e9)
+    fact_bytes = n_fact * 44
+    dim_bytes = n_dim * 16
+    # table pages (with per-batch alignment slack) plus room to spill the whole fact side
+    n_pages = int((fact_bytes + dim_bytes) / page * 1.08) + 64 + int(fact_bytes / page) + 32
+    log(f"ooc: fact {n_fact} rows, dim {n_dim} rows, {n_pages} pages of 64 MiB, budget {budget / 1e9:.1f} GB")
+    t0 = time.perf_counter()
+    pool = tq.PagePool(page, n_pages, pinned=True)
+    log(f"pinned pool: {time.perf_counter() - t0:.1f} s")
+    dt = HostTable(pool, wl.OOC_DIM_COLS, n_dim, rows_per_batch)
+    ft = HostTable(pool, wl.OOC_FACT_COLS, n_fact, rows_per_batch)
+    t0 = time.perf_counter()
+    dt.fill(lambda name, addr, first, count: wl.ooc_fill_dim(name, addr, first, count, n_dim))
+    ft.fill(lambda name, addr, first, count: wl.ooc_fill_fact(name, addr, first, count, n_dim))
+    log(f"generated into pages: {time.perf_counter() - t0:.1f} s")
+    q = wl.JOIN_AGG_QUERY
+    peak_link = _pinned_copy_peak()
+    results = {}
+    for label, keep_all in (("all_columns", True), ("projected", False)):
+        job = pipeline.OocJoinAgg(q, dt, ft, budget, log2_fanout=8, chunk_bytes=4 << 20, nslots=3, keep_all=keep_all)
+        st = job.run()
+        torch.cuda.synchronize()
+        r = job.result()
+        results[label] = (st.as_dict(), r)
+        log(label, st.as_dict())
+        del job
+        torch.cuda.empty_cache()
+    st, r = results["all_columns"]
+    ms = st["ms_total"]
+    in_bytes = fact_bytes + n_dim * 16
+    link_gbs = st["bytes_h2d"] / (ms / 1e3) / 1e9
+    # parity on a sample scale against the oracle
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sd, sf = wl.ooc_tables_numpy(2_000_000, 500_000)
+        spool = tq.PagePool(1 << 20, 200, pinned=True)
+        sdt = HostTable(spool, wl.OOC_DIM_COLS, len(sd["key"]), 250_000)
+        sdt.fill_numpy(sd)
+        sft = HostTable(spool, wl.OOC_FACT_COLS, len(sf["fk"]), 250_000)
+        sft.fill_numpy(sf)
+        sj = pipeline.OocJoinAgg(q, sdt, sft, 48 << 20, log2_fanout=6, chunk_bytes=256 << 10)
+        sj.run()
+        got = sj.result()
+        t1 = time.perf_counter()
+        want = oracle.join_agg(sd, sf, q)
+        tc = time.perf_counter() - t1
+        parity = {"sample": "2M fact x 500K dim rows, budget 48 MiB (spills)",
+                  "equal": got["sums"].tolist() == want["sums"].tolist() and got["count"].tolist() == want["count"].tolist(),
+                  "spilled_chunks": sj.stats.spilled_chunks}
+        cpu = {"value": round((2_000_000 * 44 + 500_000 * 16) / tc / 1e9, 4), "unit": "GB/s", "cores": 1,
+               "kind": "oracle", "sample": f"2M x 500K rows of the same tables, {tc:.2f} s"}
+        sdt.free()
+        sft.free()
+        spool.close()
+    else:
+        cpu = None
+    out = _base("host-link GB/s out-of-core join-aggregate (% of PCIe and of the measured pinned-copy peak)",
+                link_gbs, "GB/s", args, ms, 1,
+                f"ooc_join_agg: fact {n_fact} rows x 6 cols (44 B/row) in 64 MiB pinned pages, dim {n_dim} rows, "
+                f"256 partitions, budget {budget / 1e9:.1f} GB",
+                {"input_bytes": in_bytes, "input_gbs": round(in_bytes / (ms / 1e3) / 1e9, 3),
+                 "pct_pcie_theoretical": round(100 * link_gbs / PCIE_GBS, 2),
+                 "pct_measured_pinned_copy": round(100 * link_gbs / peak_link, 2),
+                 "measured_pinned_copy_gbs": round(peak_link, 2),
+                 "stats": st, "projected_variant": results["projected"][0],
+                 "groups": len(r["count"]), "join_rows": r["join_rows"],
+                 "roofline": {"bound": "host-link", "achieved": round(link_gbs, 3), "peak": PCIE_GBS, "unit": "GB/s",
+                              "frac": round(link_gbs / PCIE_GBS, 4), "traffic": None,
+                              "kernel": "tq_ooc_join_agg (whole pipeline)"},
+                 "cpu_baseline": cpu, "parity_vs_oracle": parity})
+    dt.free()
+    ft.free()
+    pool.close()
+    return out
+
+
+# ------------------------------------------------------------------ batched
+
+def bench_batched(args):
+    count = args.instances
+    shapes = wl.batched_shapes(count)
+    t0 = time.perf_counter()
+    insts = []
+    for i, s in enumerate(shapes):
+        d, f = wl.batched_instance_tables(i, s)
+        insts.append((d, f, s.groups))
+    log(f"batched: {count} instances generated in {time.perf_counter() - t0:.1f} s; "
+        f"fact rows {sum(s.n_fact for s in shapes)}, dim rows {sum(s.n_dim for s in shapes)}")
+    q = wl.batched_query(8)
+    table = autotune.tune_batched(q, insts, cache_path=None, sample=32, reps=2, log=log)
+    params = autotune.params_for(insts, table)
+    job = pipeline.BatchedJoinAgg(q, insts, params)
+    in_bytes = job.input_bytes
+    stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        job.run()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        job.run()
+    for _ in range(max(1, args.warmup // 4)):
+        g.replay()
+    torch.cuda.synchronize()
+    reps = max(3, args.steps // 40)
+    a, b = _events()
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    job.check()
+    # one launch per instance, for comparison
+    a, b = _events()
+    job.run_per_instance()
+    torch.cuda.synchronize()
+    a.record()
+    job.run_per_instance()
+    b.record()
+    torch.cuda.synchronize()
+    ms_per_inst = a.elapsed_time(b)
+    # parity on a sample of instances against the oracle
+    parity = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        job.run()
+        torch.cuda.synchronize()
+        which = list(range(0, count, max(1, count // 24)))
+        got = job.results(which)
+        ok = True
+        tc = 0.0
+        rows = 0
+        for k, i in enumerate(which):
+            d, f, G = insts[i]
+            t1 = time.perf_counter()
+            want = oracle.join_agg(d, f, wl.batched_query(G))
+            tc += time.perf_counter() - t1
+            rows += len(d["key"]) * 24 + len(f["fk"]) * 24
+            ok = ok and got[k]["sums"].tolist() == want["sums"].tolist() and \
+                got[k]["count"].tolist() == want["count"].tolist()
+        parity = {"instances_checked": len(which), "equal": ok}
+        cpu = {"value": round(rows / tc / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(which)} of the {count} instances, {tc:.2f} s"}
+    gbs = in_bytes / (ms / 1e3) / 1e9
+    return _base("input GB/s batched join-aggregate instances (% of HBM peak)", gbs, "GB/s", args, ms, reps,
+                 f"batched: {count} instances, fact log-uniform 1e3..1e6, dim = fact/4, groups log-uniform "
+                 f"4..65536 Zipf(1.1), int64 columns; one persistent launch in a hipGraph",
+                 {"input_bytes": in_bytes, "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                  "ms_one_launch_per_instance": round(ms_per_inst, 3),
+                  "speedup_vs_per_instance": round(ms_per_inst / ms, 2),
+                  "autotuned": {k: list(v) for k, v in table.items()},
+                  "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                               "kernel": "k_batched (+ k_batched_prep)", "bytes_per_launch": in_bytes},
+                  "cpu_baseline": cpu, "parity_vs_oracle": parity})
+
+
+# ------------------------------------------------------------------ serving
+
+def bench_serving(args):
+    pool = tq.PagePool(64 << 20, 160, pinned=True)
+    nbase = args.serve_base_rows
+    setup = pipeline.ServingSetup(n0=nbase, n_dim=nbase // 4, n1=nbase, n2=nbase, batch_rows=1 << 20, pool=pool)
+    budget_bytes = int(64e9)
+    arena = torch.empty(min(budget_bytes, 48 << 30), dtype=torch.uint8, device="cuda")
+    n = args.requests
+    # calibrate the FIFO service rate on the first requests
+    cal = wl.serving_requests(60, qps=1e9, seed=wl.SERVE_SEED + 7)
+    Rc = setup.requests(cal)
+    b = tq.Budget(budget_bytes)
+    res, *_ = tq.serve_run(setup.T, Rc, 1, b, arena, 25)
+    mu = len(cal) / max(res[i].end_s for i in range(len(cal)))
+    lam = 0.8 * mu
+    reqs = wl.serving_requests(n, qps=lam)
+    R = setup.requests(reqs)
+    out = {}
+    for label, workers in (("fifo", 1), ("continuous", args.workers)):
+        b = tq.Budget(budget_bytes)
+        res, *_ = tq.serve_run(setup.T, R, workers, b, arena, 25)
+        lat = np.array([res[i].end_s - R[i].arrival_s for i in range(n)])
+        bad = sum(res[i].status != 0 for i in range(n))
+        span = max(res[i].end_s for i in range(n)) - R[0].arrival_s
+        out[label] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                      "mean_ms": round(float(lat.mean()) * 1e3, 3), "qps": round(n / span, 2), "failed": bad,
+                      "workers": workers}
+        log(label, out[label])
+    setup.host.free()
+    pool.close()
+    c = out["continuous"]
+    return _base("p50/p99 served query latency (ms) and queries/s, continuous batching vs FIFO", c["qps"], "queries/s",
+                 args, c["mean_ms"], n,
+                 f"serving: {n} requests, shapes 0/1/2 uniform, fact rows log-uniform 1e4..1e8 (windows of "
+                 f"{nbase}-row base tables), Poisson arrivals at 0.8 x the FIFO rate ({lam:.1f}/s), 64 GB budget",
+                 {"p50_ms": c["p50_ms"], "p99_ms": c["p99_ms"], "fifo": out["fifo"], "continuous": c,
+                  "calibrated_fifo_qps": round(mu, 2), "roofline": None, "cpu_baseline": None})

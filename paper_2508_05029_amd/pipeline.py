@@ -281,6 +281,20 @@ class BatchedJoinAgg:
         self.work = torch.empty(max(1, tq.batched_work_bytes(self.insts)), dtype=torch.uint8, device=device)
         tq.batched_prepare(self.Q, self.insts, self.work)
 
+    def set_params(self, params, device="cuda"):
+        """New (load_factor, build_tile, probe_tile) per instance; the tables were
+        sized for the load factors given at construction, so a load factor may
+        only grow."""
+        for i, (lf, bt, pt) in enumerate(params):
+            I = self.insts[i]
+            if tq.join_table_bytes(I.n_dim, lf) > I.table_bytes:
+                raise ValueError("the table was sized for a larger load factor")
+            I.load_factor, I.build_tile, I.probe_tile = lf, bt, pt
+        need = tq.batched_work_bytes(self.insts)
+        if need > self.work.numel():
+            self.work = torch.empty(need, dtype=torch.uint8, device=device)
+        tq.batched_prepare(self.Q, self.insts, self.work)
+
     def run(self, stream=None):
         tq.batched_run(self.Q, self.work, self.n, stream)
 
