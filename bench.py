@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="join_agg",
-                    choices=["join_agg", "filter_groupby", "ooc", "batched", "serving"])
+                    choices=["join_agg", "filter_groupby", "ooc", "batched", "serving", "copy"])
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--graph-steps", type=int, default=8)
     ap.add_argument("--event-steps", type=int, default=20)

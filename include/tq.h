@@ -451,8 +451,9 @@ typedef struct {
 
 /* Runs all requests and blocks until they are done. d_arena / arena_bytes is
  * the device memory requests are carved from; the budget bounds it. Group
- * results go to h_keys / h_count / h_sums (max_groups and max_groups * 6
- * entries per request); per-request timing to `res`. */
+ * results of request i go to h_keys[i][max_groups], h_count[i][max_groups] and
+ * h_sums[i][max_groups][TQ_MAX_SUMS] (sum j of group g at g * TQ_MAX_SUMS + j),
+ * groups in key order, at most max_groups of them; per-request timing to `res`. */
 tq_status tq_serve_run(const tq_serve_tables* t, const tq_request* reqs, int64_t n, int32_t workers,
                        tq_budget* budget, void* d_arena, size_t arena_bytes, int64_t max_groups, int64_t* h_keys,
                        int64_t* h_count, int64_t* h_sums, tq_request_result* res);

@@ -327,3 +327,41 @@ def bench_serving(args):
                  f"{nbase}-row base tables), Poisson arrivals at 0.8 x the FIFO rate ({lam:.1f}/s), 64 GB budget",
                  {"p50_ms": c["p50_ms"], "p99_ms": c["p99_ms"], "fifo": out["fifo"], "continuous": c,
                   "calibrated_fifo_qps": round(mu, 2), "roofline": None, "cpu_baseline": None})
+
+
+# ------------------------------------------------------------------ plain copy kernels (calibration)
+
+def bench_copy(args):
+    """Read-only and write-only passes over 1 GiB: the measured HBM ceilings, and
+    the kernels whose FETCH_SIZE / WRITE_SIZE counters calibrate those of the
+    query kernels (k_read_peak reads exactly 1 GiB, k_fill writes exactly 1 GiB)."""
+    nbytes = 1 << 30
+    x = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
+    part = torch.zeros(max(1, tq.read_peak_scratch_bytes() // 8), dtype=torch.int64, device="cuda")
+    tq.fill(x, 0x01010101)
+    for _ in range(3):
+        tq.read_peak(x, part)
+    torch.cuda.synchronize()
+    reps = max(4, min(args.steps, 50))
+    a, b = _events()
+    a.record()
+    for _ in range(reps):
+        tq.read_peak(x, part)
+    b.record()
+    torch.cuda.synchronize()
+    ms_r = a.elapsed_time(b) / reps
+    a.record()
+    for _ in range(reps):
+        tq.fill(x, 7)
+    b.record()
+    torch.cuda.synchronize()
+    ms_w = a.elapsed_time(b) / reps
+    rd = nbytes / (ms_r / 1e3) / 1e9
+    wr = nbytes / (ms_w / 1e3) / 1e9
+    return _base("HBM GB/s of a plain read and a plain write of 1 GiB", rd, "GB/s", args, ms_r, reps,
+                 "copy: k_read_peak over 1 GiB, k_fill over 1 GiB",
+                 {"read_gbs": round(rd, 1), "write_gbs": round(wr, 1), "ms_read": round(ms_r, 4),
+                  "ms_write": round(ms_w, 4), "bytes_per_launch": nbytes,
+                  "roofline": {"bound": "hbm", "achieved": round(rd, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(rd / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_read_peak"},
+                  "cpu_baseline": None})

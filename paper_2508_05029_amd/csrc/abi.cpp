@@ -92,6 +92,30 @@ tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p
     P->key_mask[1] = key->ncol == 2 ? 1u << key->col[1] : 0u;
     P->key_mult = key->mult;
   }
+  // keep only the columns a predicate, expression or key reads, so that the
+  // kernels load nothing else; masks are renumbered to the kept columns
+  uint32_t used = P->key_mask[0] | P->key_mask[1];
+  for (int j = 0; j < P->np; j++) used |= P->pred[j].mask;
+  for (int j = 0; j < P->ne; j++)
+    for (int f = 0; f < P->expr[j].nf; f++) used |= P->expr[j].f[f].mask;
+  uint32_t remap[TQ_MAX_COLS];
+  int kept = 0;
+  for (int c = 0; c < ncol; c++) {
+    remap[c] = 0;
+    if ((used >> c) & 1u) {
+      P->col[kept] = P->col[c];
+      remap[c] = 1u << kept;
+      kept++;
+    }
+  }
+  for (int c = kept; c < ncol; c++) P->col[c] = DCol{nullptr, 0};
+  auto re = [&](uint32_t m) -> uint32_t { return m ? remap[__builtin_ctz(m)] : 0u; };
+  for (int j = 0; j < P->np; j++) P->pred[j].mask = re(P->pred[j].mask);
+  for (int j = 0; j < P->ne; j++)
+    for (int f = 0; f < P->expr[j].nf; f++) P->expr[j].f[f].mask = re(P->expr[j].f[f].mask);
+  P->key_mask[0] = re(P->key_mask[0]);
+  P->key_mask[1] = re(P->key_mask[1]);
+  P->ncol = kept;
   return TQ_OK;
 }
 

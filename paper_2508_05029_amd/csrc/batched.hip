@@ -153,6 +153,8 @@ __global__ __launch_bounds__(256) void k_batched_prep(WorkHeader* hdr, const BIn
       th->nblk = 0;
       th->flags = flags;
       th->lf = 0;
+      th->log2g = I.log2cap - kLog2Bucket;
+      th->ovf = 0;
       StateHeader* sh = static_cast<StateHeader*>(I.state);
       sh->magic = kStateMagic;
       sh->err = 0;

@@ -105,6 +105,8 @@ struct TableHeader {
   int32_t nblk;      // blocks that wrote partial counts
   uint32_t flags;
   double lf;
+  int32_t log2g;     // buckets per region (log2): linear probing wraps inside a region
+  int32_t ovf;       // a region build found a region with more rows than slots
 };
 static_assert(sizeof(TableHeader) <= kHeaderBytes, "header");
 

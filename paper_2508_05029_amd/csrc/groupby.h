@@ -80,6 +80,12 @@ template <int MODE>
 struct LdsAgg {
   int64_t* vals;   // LDS. kDense: [domain][stride]; kHash: [hcap][stride]
   uint32_t* keys;  // LDS. kHash: key + 1, 0 = empty
+  // Deferred mode: a key outside the domain is remembered here and latched by
+  // flush(), so that the adding loop issues no device-memory atomic (on this
+  // GPU a store or atomic shares the wait counter with loads, and its mere
+  // presence in a loop makes every wait for a load a wait for all of them).
+  bool defer = false;
+  bool bad = false;
 
   __device__ void init(const AggTarget& T, char* smem) {
     if (MODE == kDense) {
@@ -98,7 +104,8 @@ struct LdsAgg {
   template <int NE>
   __device__ __forceinline__ void add(const AggTarget& T, int64_t key, const int64_t (&v)[NE], int nsum) {
     if ((uint64_t)key >= (uint64_t)T.domain) {
-      latch_error(T.err, TQ_EDOMAIN);
+      if (defer) bad = true;
+      else latch_error(T.err, TQ_EDOMAIN);
       return;
     }
     if (MODE == kDense) {
@@ -142,6 +149,7 @@ struct LdsAgg {
 
   // Folds this workgroup's LDS partials into the global state.
   __device__ void flush(const AggTarget& T) {
+    if (bad) latch_error(T.err, TQ_EDOMAIN);
     __syncthreads();
     if (MODE == kDense) {
       const int64_t entries = T.domain * T.stride;

@@ -25,6 +25,7 @@ namespace tq {
 constexpr int kBlock = 256;
 constexpr int kChunk = kBlock * kRows;
 constexpr int kPR = 2;  // rows per lane in the aggregating probe (fewer registers, more waves)
+constexpr int kMaxCountBlocks = 1024;  // build count blocks (their partials are summed by every insert block)
 
 __host__ __device__ inline int log2cap_for(int64_t rows, double lf) {
   double need = ceil((double)rows / lf);
@@ -74,13 +75,26 @@ __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
   h->nblk = 0;
   h->flags = 0;
   h->lf = 0.5;
+  h->log2g = 6 - kLog2Bucket;
+  h->ovf = 0;
 }
 
 // ------------------------------------------------------------------ build
 
+// Pass 1: the filtered row count of each block's contiguous range (into the
+// table's partial area), and the whole tag array cleared (the capacity the
+// rows need is only known once every block has counted).
 template <int NC>
-__global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, int64_t per, TableHeader* h) {
+__global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, int64_t per, TableHeader* h,
+                                                        int64_t cap_max, int count) {
   __shared__ int64_t ws[kBlock / kWave];
+  if (h->magic != kTableMagic) return;  // never initialised: the insert kernel does nothing either
+  v4i32* tags = reinterpret_cast<v4i32*>(table_tags(h));
+  const v4i32 z = {0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (cap_max >> kLog2Bucket);
+       i += (int64_t)gridDim.x * blockDim.x)
+    tags[i] = z;
+  if (!count) return;
   const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
   int64_t c = 0;
   for (int64_t r0 = lo + threadIdx.x * kRows; r0 < hi; r0 += kChunk) {
@@ -93,12 +107,15 @@ __global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, in
   if (threadIdx.x == 0) table_partials(h)[blockIdx.x] = t;
 }
 
-// Fix the capacity from the row count (host-given, or the sum of the per-block
-// counts) and clear the tags it uses.
-__global__ __launch_bounds__(kBlock) void k_build_clear(TableHeader* h, int64_t cap_max, int64_t n_host, int nblk,
-                                                        double lf, int skip, uint32_t flags) {
+// Pass 2: every block fixes the capacity from the row count (host-given, or
+// the sum of the per-block counts; block 0 records it in the header) and
+// inserts its rows.
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
+                                                         TableHeader* h, int64_t cap_max, int64_t n_host, int nblk,
+                                                         double lf, int skip, uint32_t flags) {
   __shared__ int64_t ws[kBlock / kWave];
-  if (h->magic != kTableMagic) return;  // never initialised: the insert kernel does nothing either
+  if (h->magic != kTableMagic) return;
   int64_t rows = n_host;
   if (n_host < 0) {
     int64_t c = 0;
@@ -106,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_build_clear(TableHeader* h, int64_t 
     rows = block_sum(c, ws);
   }
   int l = log2cap_for(rows, lf);
-  bool full = ((int64_t)1 << l) > cap_max;
+  const bool full = ((int64_t)1 << l) > cap_max;
   if (full) {
     l = 6;
     while (((int64_t)1 << (l + 1)) <= cap_max) l++;
@@ -118,32 +135,21 @@ __global__ __launch_bounds__(kBlock) void k_build_clear(TableHeader* h, int64_t 
     h->skip = skip;
     h->flags = flags;
     h->lf = lf;
+    h->log2g = l - kLog2Bucket;
     if (full) latch_error(&h->err, TQ_EFULL);
   }
-  v4i32* tags = reinterpret_cast<v4i32*>(table_tags(h));
-  const int64_t nb = ((int64_t)1 << l) >> kLog2Bucket;  // one 16-byte tag group per bucket
-  const v4i32 z = {0, 0, 0, 0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x)
-    tags[i] = z;
-}
-
-template <int NC>
-__global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
-                                                         TableHeader* h) {
-  if (h->magic != kTableMagic) return;
-  const int l = h->log2cap, skip = h->skip;
-  if (h->n > ((int64_t)1 << l)) return;  // does not fit: TQ_EFULL is latched, nothing is inserted
+  if (full) return;  // does not fit: TQ_EFULL is latched, nothing is inserted
   uint32_t* words = table_tags(h);
-  v2i64* slots = reinterpret_cast<v2i64*>(table_slots(h, h->cap_max));
+  v2i64* slots = reinterpret_cast<v2i64*>(table_slots(h, cap_max));
   const DCol kc = {keys, 8};
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
-    const bool full = r0 + kRows <= n;
+    const bool fullrow = r0 + kRows <= n;
     int64_t v[NC][kRows], k[kRows], pay[kRows];
     bool pend[kRows];
-    load_rows<NC>(P, r0, full, n, v);
-    load4(kc, r0, full, n, k);
-    load4(payload, r0, full, n, pay);
+    load_rows<NC>(P, r0, fullrow, n, v);
+    load4(kc, r0, fullrow, n, k);
+    load4(payload, r0, fullrow, n, pay);
 #pragma unroll
     for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
     table_insert<kRows>(words, slots, l, skip, pend, k, pay);
@@ -197,6 +203,206 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const 
             load4(kc, r1, r1 + kPR <= n, n, kn);
           }
         });
+  }
+  agg.flush(T);
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined probe with the fused group-by (int64 columns, up to two sums).
+//
+// Each lane takes two consecutive rows per tile (one 16-byte load per column);
+// tiles are strided over the grid. Four tiles of a lane are in flight at
+// once, one per stage: in iteration j the candidate slots of tile j are
+// consumed, the tags of tile j+1 turn into slot loads, the columns of tile j+2
+// into tag loads, and the columns of tile j+3 are requested. Each load is
+// issued one iteration before its data is used, and the loads of an
+// iteration are issued in the order they are consumed, so every wait covers
+// only the oldest loads. Every load is issued unconditionally: a row with
+// nothing to read loads a fixed valid address instead (one line shared by the
+// wave), so the count of loads in flight is the same on every path. The row of
+// a partial last tile (at most one) is walked by one lane at the end.
+//
+// A row is finished from its home bucket alone when the bucket decides it: no
+// tag match and a free slot (a miss), exactly one candidate and a free slot
+// (hit or miss), or a hit on unique build keys. Any other row (a full home
+// bucket, further candidates) goes to a queue in LDS private to its wave; the
+// wave walks 64 queued rows at a time to the end of their chains. A queued row
+// starts again from its home bucket and nothing of it was aggregated before,
+// so every match is counted exactly once.
+#ifndef TQ_PIPE_BLOCKS_PER_CU
+#define TQ_PIPE_BLOCKS_PER_CU 2
+#endif
+constexpr int kPipeBlocksPerCU = TQ_PIPE_BLOCKS_PER_CU;
+constexpr int kPipeRows = 2;
+constexpr int kPipeQ = 256;  // queue entries per wave: holds 63 + 128 between drains
+constexpr size_t kMaxPipeLds = 64 * 1024;  // dynamic LDS of a launch without a per-kernel attribute
+
+template <int NE>
+struct PipeRows {
+  static constexpr int R = kPipeRows;
+  int64_t k[R], e[R][NE], b[R];
+  uint32_t tg[R];
+  bool live[R];
+};
+
+template <int MODE, int NC, int NE>
+__global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(const TableHeader* h, const int64_t* pkeys,
+                                                                            int64_t n, RowPlan P, AggTarget T,
+                                                                            int agg_lds) {
+  constexpr int R = kPipeRows;
+  extern __shared__ __align__(16) char smem[];
+  if (h->magic != kTableMagic) return;
+  if (!state_matches(T)) return;
+  LdsAgg<MODE> agg;
+  agg.defer = true;
+  agg.init(T, smem);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  int64_t* qk = reinterpret_cast<int64_t*>(smem + agg_lds) + (int64_t)wave * kPipeQ * (1 + NE);
+  int64_t* qe = qk + kPipeQ;  // sum j of entry x at qe[j * kPipeQ + x]
+  __syncthreads();
+  Probe pr;
+  pr.setup(h);
+  const int64_t n_main = n & ~(int64_t)(R - 1);  // rows in full tiles
+  const v2i64* kcol = reinterpret_cast<const v2i64*>(pkeys);
+  const v2i64* ccol[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) ccol[c] = c < P.ncol ? static_cast<const v2i64*>(P.col[c].p) : kcol;
+  int qh = 0, qn = 0;  // queue head and length (the same in every lane)
+
+  // Walks `cnt` (<= 64) queued rows from the head, one per lane.
+  auto drain = [&](int cnt) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int x = (qh + lane) & (kPipeQ - 1);
+    bool ok1[1] = {lane < cnt};
+    int64_t k1[1] = {0}, e1[NE];
+#pragma unroll
+    for (int j = 0; j < NE; j++) e1[j] = 0;
+    if (ok1[0]) {
+      k1[0] = qk[x];
+#pragma unroll
+      for (int j = 0; j < NE; j++) e1[j] = qe[j * kPipeQ + x];
+    }
+    pr.walk(ok1, k1, [&](const bool (&hit)[1], const int64_t (&pay)[1]) {
+      if (hit[0]) agg.add(T, pay[0], e1, P.ne);
+    });
+    qh = (qh + cnt) & (kPipeQ - 1);
+    qn -= cnt;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
+
+  if (n_main > 0) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * R;
+    const int64_t wbase = ((int64_t)blockIdx.x * blockDim.x + wave * kWave) * R;  // the wave's first row
+    int64_t r = wbase + lane * R;
+    v2i64 cv[NC], ck;       // columns of the tile 3 ahead
+    v4i32 tw[R];            // tags of the tile 1 ahead
+    v2i64 kv[R];            // candidate slots of the current tile
+    PipeRows<NE> tt, st;    // rows whose tags (tt) / slots (st) are in flight
+    uint32_t sm[R];         // st: candidate mask of the home bucket
+    bool sempty[R];         // st: the home bucket has a free slot
+
+    auto load_cols = [&](int64_t rt) {  // a tile beyond the full tiles reads tile 0 instead
+      const int64_t q = (rt < n_main ? rt : 0) / R;
+      ck = ntload(kcol + q);
+#pragma unroll
+      for (int c = 0; c < NC; c++) cv[c] = ntload(ccol[c] + q);
+    };
+    auto cols_to_tags = [&](int64_t rt) {  // cv, ck -> tt; tag loads
+      int64_t v[NC][R];
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        v[c][0] = cv[c].x;
+        v[c][1] = cv[c].y;
+      }
+      const int64_t kk[R] = {ck.x, ck.y};
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        tt.live[i] = (rt < n_main) && eval_preds<NC>(P, v, i);
+#pragma unroll
+        for (int j = 0; j < NE; j++) tt.e[i][j] = j < P.ne ? eval_expr<NC>(P.expr[j], v, i) : 0;
+        tt.k[i] = kk[i];
+        const uint64_t hh = mulhash(kk[i]);
+        tt.b[i] = (int64_t)bucket_of(hh, pr.skip, pr.log2b);
+        tt.tg[i] = hash_tag(hh);
+      }
+#pragma unroll
+      for (int i = 0; i < R; i++) tw[i] = pr.groups[tt.live[i] ? tt.b[i] : 0];
+    };
+    auto tags_to_slots = [&]() {  // tt, tw -> st; slot loads
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        sm[i] = tt.live[i] ? tag_match(tw[i], tt.tg[i]) : 0u;
+        sempty[i] = tt.live[i] ? tag_match(tw[i], 0u) != 0u : true;
+      }
+      st = tt;
+#pragma unroll
+      for (int i = 0; i < R; i++) kv[i] = pr.slots[sm[i] ? st.b[i] * kBucket + __builtin_ctz(sm[i]) : 0];
+    };
+
+    // prologue: tile 0 to its slot loads, tile 1 to its tag loads, tile 2's columns requested
+    load_cols(r);
+    cols_to_tags(r);
+    asm volatile("" ::: "memory");
+    load_cols(r + stride);
+    asm volatile("" ::: "memory");
+    tags_to_slots();
+    asm volatile("" ::: "memory");
+    cols_to_tags(r + stride);
+    asm volatile("" ::: "memory");
+    load_cols(r + 2 * stride);
+    asm volatile("" ::: "memory");
+    for (int64_t w0 = wbase; w0 < n_main; w0 += stride, r += stride) {
+      // (a) finish this tile from its slots (before any register they live in is reloaded)
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        const bool cand = sm[i] != 0u;
+        const bool hit = cand && kv[i].x == st.k[i];
+        const uint32_t rest = sm[i] & (sm[i] - 1u);
+        const bool done =
+            !st.live[i] || (sm[i] == 0u && sempty[i]) || (hit && pr.unique) || (rest == 0u && sempty[i]);
+        if (done && hit) agg.add(T, kv[i].y, st.e[i], P.ne);
+        const bool slow = !done;
+        const uint64_t bal = __ballot(slow);
+        if (bal) {
+          if (slow) {
+            const int rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            const int x = (qh + qn + rank) & (kPipeQ - 1);
+            qk[x] = st.k[i];
+#pragma unroll
+            for (int j = 0; j < NE; j++) qe[j * kPipeQ + x] = st.e[i][j];
+          }
+          qn += __popcll(bal);
+        }
+      }
+      // (b) tile j+1: tags -> slot loads; (c) tile j+2: columns -> tag loads; (d) tile j+3 columns.
+      // The empty asm statements keep each stage's loads where they are: the
+      // compiler would otherwise merge the last loads with the prologue's and
+      // issue them at the top of the next iteration, after the slot loads.
+      tags_to_slots();
+      asm volatile("" ::: "memory");
+      cols_to_tags(r + 2 * stride);
+      asm volatile("" ::: "memory");
+      load_cols(r + 3 * stride);
+      asm volatile("" ::: "memory");
+      // queued rows are walked here, after this iteration's loads are on their way
+      while (qn >= kWave) drain(kWave);
+    }
+  }
+  if (qn > 0) drain(qn);
+  if (n_main < n && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the row of the partial last tile
+    const int64_t rt = n_main;
+    int64_t v[NC][1];
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c][0] = c < P.ncol ? static_cast<const int64_t*>(P.col[c].p)[rt] : 0;
+    bool ok1[1] = {eval_preds<NC>(P, v, 0)};
+    int64_t k1[1] = {pkeys[rt]}, e1[NE];
+#pragma unroll
+    for (int j = 0; j < NE; j++) e1[j] = j < P.ne ? eval_expr<NC>(P.expr[j], v, 0) : 0;
+    pr.walk(ok1, k1, [&](const bool (&hit)[1], const int64_t (&pay)[1]) {
+      if (hit[0]) agg.add(T, pay[0], e1, P.ne);
+    });
   }
   agg.flush(T);
 }
@@ -343,23 +549,18 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   tq_status s = make_plan(&P, filt, nfilt, p, np, nullptr, 0, nullptr, n);
   if (s) return s;
   TableHeader* h = static_cast<TableHeader*>(d_table);
-  int nblk = 0;
-  if (np > 0 && n > 0) {
-    Range R = split_rows(n, kMaxPartBlocks);
-    nblk = R.nblk;
-    TQ_DISPATCH_NC(nfilt, NC, hipLaunchKernelGGL(k_build_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, n, R.per, h));
-    TQ_HIP(hipGetLastError());
-  }
-  int64_t clear_blocks = std::max<int64_t>(1, std::min<int64_t>(cap_max / 4 / kBlock, device_cu_count() * 4));
-  hipLaunchKernelGGL(k_build_clear, dim3((int)clear_blocks), dim3(kBlock), 0, stream, h, cap_max,
-                     np > 0 ? (int64_t)-1 : n, nblk, load_factor, skip, flags);
+  const bool count = np > 0 && n > 0;
+  Range R = split_rows(std::max<int64_t>(n, 1), kMaxCountBlocks);
+  // enough blocks to clear the tags quickly; blocks past the rows count zero
+  const int64_t clear_blocks = std::min<int64_t>((cap_max >> kLog2Bucket) / kBlock, kMaxCountBlocks);
+  const int count_grid = (int)std::max<int64_t>(R.nblk, clear_blocks);
+  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_count<NC>, dim3(count_grid), dim3(kBlock), 0, stream, P, n, R.per,
+                                                h, cap_max, (int)count));
+  DCol pc = {payload.data, payload.type};
+  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_insert<NC>, dim3(stream_grid(n, 8)), dim3(kBlock), 0, stream, P,
+                                                d_keys, pc, n, h, cap_max, count ? (int64_t)-1 : n, R.nblk, load_factor,
+                                                skip, flags));
   TQ_HIP(hipGetLastError());
-  if (n > 0) {
-    DCol pc = {payload.data, payload.type};
-    TQ_DISPATCH_NC(nfilt, NC, hipLaunchKernelGGL(k_build_insert<NC>, dim3(stream_grid(n, 8)), dim3(kBlock), 0, stream, P,
-                                                 d_keys, pc, n, h));
-    TQ_HIP(hipGetLastError());
-  }
   return TQ_OK;
 }
 
@@ -381,9 +582,25 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
     if ((s = make_target(agg->d_state, agg->domain, agg->nsum, &T, &mode, &lds))) return s;
     if (d_out_count) return fail(TQ_EINVAL, "the fused group-by counts matches in its COUNT column; pass d_out_count = NULL");
     if (n == 0) return TQ_OK;
-    dim3 grid(agg_grid(n)), block(kAggBlock);
-    TQ_DISPATCH_AGG(mode, ncol, agg->nsum, M, NC, NE,
-                    hipLaunchKernelGGL((k_probe_agg<M, NC, NE>), grid, block, lds, stream, h, d_probe_keys, n, P, T));
+    bool all64 = true;
+    for (int c = 0; c < P.ncol; c++) all64 = all64 && P.col[c].w == 8;
+    const int nq = ne_bucket(agg->nsum);
+    const size_t pipe_lds = (lds + 15) / 16 * 16 + (size_t)(kAggBlock / kWave) * kPipeQ * (1 + nq) * 8;
+    if (all64 && nq <= 2 && pipe_lds <= kMaxPipeLds) {
+      const int64_t want = (n + (int64_t)kAggBlock * kPipeRows - 1) / ((int64_t)kAggBlock * kPipeRows);
+      const int64_t cap = std::min<int64_t>(kAggRows, (int64_t)kPipeBlocksPerCU * device_cu_count());
+      dim3 grid((int)std::max<int64_t>(1, std::min(want, cap))), block(kAggBlock);
+      const int agg_lds = (int)((lds + 15) / 16 * 16);
+      TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE, if constexpr (NE <= 2) {
+        const size_t q = (size_t)(kAggBlock / kWave) * kPipeQ * (1 + NE) * 8;
+        hipLaunchKernelGGL((k_probe_pipe<M, NC, NE>), grid, block, agg_lds + q, stream, h, d_probe_keys, n, P, T,
+                           agg_lds);
+      });
+    } else {
+      dim3 grid(agg_grid(n)), block(kAggBlock);
+      TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE,
+                      hipLaunchKernelGGL((k_probe_agg<M, NC, NE>), grid, block, lds, stream, h, d_probe_keys, n, P, T));
+    }
     TQ_HIP(hipGetLastError());
     return TQ_OK;
   }
@@ -397,10 +614,10 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
   Range R = split_rows(n, kMaxPartBlocks);
   // the per-block counts live in the table's partial area: materialising probes of one table must not overlap
   int64_t* cnt = table_partials(const_cast<void*>(d_table));
-  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_probe_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, h, d_probe_keys, n,
+  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_probe_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, h, d_probe_keys, n,
                                               R.per, P, cnt));
   hipLaunchKernelGGL(k_scan_blocks<0>, dim3(1), dim3(1024), 0, stream, cnt, R.nblk, d_out_count);
-  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_probe_write<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, h, d_probe_keys, n,
+  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_probe_write<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, h, d_probe_keys, n,
                                               R.per, P, cnt, d_out_probe_row, d_out_payload, capacity));
   TQ_HIP(hipGetLastError());
   return TQ_OK;

@@ -191,10 +191,13 @@ class Driver {
     return TQ_OK;
   }
 
+  // Pass 1 may spill any resident chunk that no append being assembled writes
+  // into, a partly filled tail too: the next append to that partition starts a
+  // new chunk, and pass 2 reads every chunk by its own row count.
   bool spillable(int p, const Holder& h, size_t idx) const {
     const ChunkRef& c = h.chunks[idx];
     if (c.dev < 0 || c.pinned) return false;
-    if (phase == 1) return idx + 1 < h.chunks.size();  // the tail chunk still receives appends
+    if (phase == 1) return true;
     return p < pin_lo || p > pin_hi;
   }
 
@@ -243,6 +246,7 @@ class Driver {
     if ((e = hipMemcpyAsync(host, chunk_ptr(c.dev), chunk_bytes, hipMemcpyDeviceToHost, spill)) != hipSuccess) return e;
     st.bytes_d2h += (int64_t)chunk_bytes;
     st.spilled_chunks++;
+    spill_unwaited = true;
     hipEvent_t ev;
     if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev, spill)) != hipSuccess) return e;
@@ -272,16 +276,35 @@ class Driver {
       bool spilled = false;
       tq_status s = spill_one(&spilled);
       if (s) return s;
-      if (!spilled) return fail(TQ_ENOMEM, "device budget exhausted and nothing left to spill");
+      if (spilled) continue;
+      if (appending && !touched.empty()) {
+        // every resident chunk is pinned by the append being assembled: launch
+        // its copies so far, after which those chunks may be spilled
+        if ((s = launch_copies())) return s;
+        unpin_touched();
+        continue;
+      }
+      return fail(TQ_ENOMEM, "device budget exhausted and nothing left to spill");
     }
     return fail(TQ_ENOMEM, "chunk allocation did not converge");
   }
+
+  bool spill_unwaited = false;  // spill copies enqueued since the copy stream last waited for them
 
   tq_status reload(ChunkRef& c) {
     if (c.dev >= 0) return TQ_OK;
     int64_t id;
     tq_status s = take_chunk(&id);
     if (s) return s;
+    if (spill_unwaited) {
+      // the chunk's spill copy to the host page may still be in flight
+      hipEvent_t ev;
+      TQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      TQ_HIP(hipEventRecord(ev, spill));
+      TQ_HIP(hipStreamWaitEvent(copy, ev, 0));
+      TQ_HIP(hipEventDestroy(ev));
+      spill_unwaited = false;
+    }
     const char* host = static_cast<const char*>(tq_pagepool_page(pool, c.page)) + (size_t)c.sub * chunk_bytes;
     TQ_HIP(hipMemcpyAsync(chunk_ptr(id), host, chunk_bytes, hipMemcpyHostToDevice, copy));
     st.bytes_h2d += (int64_t)chunk_bytes;
@@ -293,35 +316,46 @@ class Driver {
   // -------------------------------------------------------------- appends
 
   std::vector<CopyDesc> descs;
+  size_t desc_used = 0;  // descriptor slots of h_desc / d_desc taken since the last sync of `compute`
+  bool appending = false;
+  Side* app_side = nullptr;
+  std::vector<std::pair<int, size_t>> touched;  // (partition, chunk index) pinned by the current append
+
+  void unpin_touched() {
+    for (auto& t : touched) app_side->parts[t.first].chunks[t.second].pinned = false;
+    touched.clear();
+  }
 
   // Append rows [off[p], off[p+1]) of every partition p from the partitioned
-  // columns `src` (side column j at src[j]) to the holders.
+  // columns `src` (side column j at src[j]) to the holders. The caller has
+  // synchronised `compute` since the previous append (its offsets were read
+  // back), so the descriptor buffers are free.
   tq_status append(Side& s, char* const* src, const int64_t* off) {
     descs.clear();
-    // every chunk this batch writes into stays pinned (not spillable) until the
-    // copy kernel that fills it has been enqueued
-    std::vector<std::pair<int, size_t>> touched;
-    for (int p = 0; p < nparts; p++)
-      if (!s.parts[p].chunks.empty()) {
-        s.parts[p].chunks.back().pinned = true;
-        touched.emplace_back(p, s.parts[p].chunks.size() - 1);
-      }
+    desc_used = 0;
+    appending = true;
+    app_side = &s;
+    // a chunk is pinned (not spillable) from the moment a descriptor of this
+    // batch targets it until the copy kernel that fills it has been enqueued
+    touched.clear();
     tq_status e = TQ_OK;
     for (int p = 0; p < nparts && e == TQ_OK; p++) {
       int64_t at = off[p], left = off[p + 1] - off[p];
       Holder& h = s.parts[p];
       h.rows += left;
       while (left > 0) {
-        if (h.chunks.empty() || h.chunks.back().rows == s.rows_per_chunk) {
+        if (h.chunks.empty() || h.chunks.back().rows == s.rows_per_chunk || h.chunks.back().dev < 0) {
           int64_t id;
           if ((e = take_chunk(&id))) break;
           ChunkRef c;
           c.dev = id;
-          c.pinned = true;
           h.chunks.push_back(c);
-          touched.emplace_back(p, h.chunks.size() - 1);
         }
         ChunkRef& c = h.chunks.back();
+        if (!c.pinned) {
+          c.pinned = true;
+          touched.emplace_back(p, h.chunks.size() - 1);
+        }
         int64_t m = std::min(left, s.rows_per_chunk - c.rows);
         for (int j = 0; j < s.ncol; j++) {
           int w = s.type[j];
@@ -333,19 +367,32 @@ class Driver {
       }
     }
     if (e == TQ_OK) e = launch_copies();
-    for (auto& t : touched) s.parts[t.first].chunks[t.second].pinned = false;
+    unpin_touched();
+    appending = false;
     return e;
   }
 
+  // Enqueues the copies described so far on `compute`, in descriptor slots not
+  // used since `compute` was last synchronised (an earlier copy of pinned host
+  // descriptors may still be in flight).
   tq_status launch_copies() {
-    if (descs.empty()) return TQ_OK;
-    if ((int)descs.size() > max_desc) return fail(TQ_EINVAL, "too many copy descriptors");
-    // the previous batch's descriptors were consumed before the host read this batch's offsets
-    memcpy(h_desc, descs.data(), descs.size() * sizeof(CopyDesc));
-    TQ_HIP(hipMemcpyAsync(d_desc, h_desc, descs.size() * sizeof(CopyDesc), hipMemcpyHostToDevice, compute));
-    int grid = (int)std::min<size_t>(descs.size(), 2048);
-    hipLaunchKernelGGL(k_gather_copy, dim3(grid), dim3(256), 0, compute, d_desc, (int)descs.size());
-    TQ_HIP(hipGetLastError());
+    size_t done = 0;
+    while (done < descs.size()) {
+      if (desc_used == (size_t)max_desc) {  // every slot is in use: wait until compute has read them
+        TQ_HIP(hipStreamSynchronize(compute));
+        desc_used = 0;
+      }
+      const size_t k = std::min(descs.size() - done, (size_t)max_desc - desc_used);
+      memcpy(h_desc + desc_used, descs.data() + done, k * sizeof(CopyDesc));
+      TQ_HIP(hipMemcpyAsync(d_desc + desc_used, h_desc + desc_used, k * sizeof(CopyDesc), hipMemcpyHostToDevice,
+                            compute));
+      const int grid = (int)std::min<size_t>(k, 2048);
+      hipLaunchKernelGGL(k_gather_copy, dim3(grid), dim3(256), 0, compute, d_desc + desc_used, (int)k);
+      TQ_HIP(hipGetLastError());
+      desc_used += k;
+      done += k;
+    }
+    descs.clear();
     return TQ_OK;
   }
 
@@ -533,8 +580,10 @@ class Driver {
       if ((s = make_resident(q))) return s;
       TQ_HIP(hipEventRecord(loaded, copy));
       TQ_HIP(hipStreamWaitEvent(compute, loaded, 0));
-      // gather the partition's dimension rows
+      // gather the partition's dimension rows (compute was synchronised at the
+      // end of the previous partition, so the descriptor slots are free)
       descs.clear();
+      desc_used = 0;
       int64_t at = 0;
       for (ChunkRef& c : dim.parts[q].chunks) {
         descs.push_back(CopyDesc{chunk_ptr(c.dev) + dim.off[0], g_key + at, c.rows, 8, 0});

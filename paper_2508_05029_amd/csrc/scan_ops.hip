@@ -165,14 +165,25 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, in
   if (rows > 1) {
     for (int e = threadIdx.x; e < entries; e += kFinBlock) fold[e] = 0;
     __syncthreads();
-    // thread t < lim always lands on entry t % entries: it sums its share of
-    // the used rows in a register, then one LDS atomic per thread folds them
+    // thread t < lim owns entry t % entries and every per-th used row from
+    // t / entries: it sums them in a register (eight independent loads in
+    // flight), then one LDS atomic per thread folds the sums
     const int per = kFinBlock / entries, lim = per * entries;
-    const int total = (int)min<int64_t>(h->used, rows) * entries;
+    const int nrow = (int)min<int64_t>(h->used, rows);
     if ((int)threadIdx.x < lim) {
+      const int e = threadIdx.x % entries;
       uint64_t acc = 0;
-      for (int i = threadIdx.x; i < total; i += lim) acc += (uint64_t)d[i];
-      if (acc) atomicAdd(reinterpret_cast<unsigned long long*>(&fold[threadIdx.x % entries]), (unsigned long long)acc);
+      for (int r = threadIdx.x / entries; r < nrow; r += 8 * per) {
+        uint64_t x[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int rr = r + u * per;
+          x[u] = rr < nrow ? (uint64_t)d[(int64_t)rr * entries + e] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc += x[u];
+      }
+      if (acc) atomicAdd(reinterpret_cast<unsigned long long*>(&fold[e]), (unsigned long long)acc);
     }
   }
   if (threadIdx.x == 0) base_s = 0;
@@ -288,9 +299,9 @@ tq_status tq_filter_project(const tq_col* in, int32_t ncol, int64_t nrows, const
   }
   Range R = split_rows(nrows);
   int64_t* cnt = static_cast<int64_t*>(d_scratch);
-  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_fp_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, nrows, R.per, cnt));
+  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_fp_count<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, nrows, R.per, cnt));
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, cnt, R.nblk, d_out_rows);
-  TQ_DISPATCH_NC(ncol, NC, hipLaunchKernelGGL(k_fp_write<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, nrows, R.per, cnt, out, d_sel));
+  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_fp_write<NC>, dim3(R.nblk), dim3(kBlock), 0, stream, P, nrows, R.per, cnt, out, d_sel));
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -330,7 +341,7 @@ tq_status tq_groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_
   if ((s = make_target(d_state, domain, nsum, &T, &mode, &lds))) return s;
   if (nrows == 0) return TQ_OK;
   dim3 grid(agg_grid(nrows)), block(kAggBlock);
-  TQ_DISPATCH_AGG(mode, ncol, nsum, M, NC, NE,
+  TQ_DISPATCH_AGG(mode, P.ncol, nsum, M, NC, NE,
                   hipLaunchKernelGGL((k_groupby<M, NC, NE>), grid, block, lds, stream, P, nrows, T));
   TQ_HIP(hipGetLastError());
   return TQ_OK;

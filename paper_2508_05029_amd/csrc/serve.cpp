@@ -195,12 +195,15 @@ struct Server {
     g = std::min(g, max_groups);
     res[idx].ngroups = g;
     if (g > 0) {
+      std::vector<int64_t> dense((size_t)g * p.nsum);
       TQ_HIP(hipMemcpyAsync(h_keys + idx * max_groups, keys, (size_t)g * 8, hipMemcpyDeviceToHost, compute));
       TQ_HIP(hipMemcpyAsync(h_count + idx * max_groups, count, (size_t)g * 8, hipMemcpyDeviceToHost, compute));
-      if (p.nsum)
-        TQ_HIP(hipMemcpyAsync(h_sums + idx * max_groups * TQ_MAX_SUMS, sums, (size_t)g * p.nsum * 8,
-                              hipMemcpyDeviceToHost, compute));
+      if (p.nsum) TQ_HIP(hipMemcpyAsync(dense.data(), sums, dense.size() * 8, hipMemcpyDeviceToHost, compute));
       TQ_HIP(hipStreamSynchronize(compute));
+      // the caller's layout: [max_groups][TQ_MAX_SUMS] per request
+      int64_t* out = h_sums + idx * max_groups * TQ_MAX_SUMS;
+      for (int64_t k = 0; k < g; k++)
+        for (int j = 0; j < p.nsum; j++) out[k * TQ_MAX_SUMS + j] = dense[(size_t)k * p.nsum + j];
     }
     return TQ_OK;
   }

@@ -104,25 +104,31 @@ __device__ __forceinline__ void table_insert(uint32_t* words, v2i64* slots, int 
   }
 }
 
+// Bucket after b in its chain: linear probing that wraps inside b's region of
+// 2^log2g buckets (the whole table when log2g = log2 of the bucket count).
+__device__ __forceinline__ int64_t next_bucket(int64_t b, int64_t gmask) { return (b & ~gmask) | ((b + 1) & gmask); }
+
 struct Probe {
   const v4i32* groups;
   const v2i64* slots;
-  int64_t bmask, cap;
+  int64_t bmask, gmask, cap;
   int log2b, skip;
   bool unique;
 
   __device__ __forceinline__ void setup(const TableHeader* h) {
     setup(table_tags(const_cast<TableHeader*>(h)), table_slots(const_cast<TableHeader*>(h), h->cap_max), h->log2cap,
-          h->skip, (h->flags & TQ_UNIQUE_KEYS) != 0);
+          h->skip, (h->flags & TQ_UNIQUE_KEYS) != 0, h->log2g);
   }
 
+  // log2g < 0: one region spanning the table
   __device__ __forceinline__ void setup(const uint32_t* words, const int64_t* slot_base, int log2cap, int skip_bits,
-                                        bool unique_keys) {
+                                        bool unique_keys, int log2g = -1) {
     log2b = log2cap - kLog2Bucket;
     skip = skip_bits;
     unique = unique_keys;
     cap = (int64_t)1 << log2cap;
     bmask = ((int64_t)1 << log2b) - 1;
+    gmask = (log2g < 0 || log2g > log2b) ? bmask : ((int64_t)1 << log2g) - 1;
     groups = reinterpret_cast<const v4i32*>(words);
     slots = reinterpret_cast<const v2i64*>(slot_base);
   }
@@ -192,7 +198,7 @@ struct Probe {
         else if (m[i] == 0u) {
           if (empty[i]) act[i] = false;  // an empty slot ends the chain
           else {
-            b[i] = (b[i] + 1) & bmask;
+            b[i] = next_bucket(b[i], gmask);
             load[i] = true;
           }
         }

@@ -67,7 +67,8 @@ def _ooc_tables(pool, n_dim, n_fact, rows_per_batch, seed):
     return d, f, dt, ft
 
 
-@pytest.mark.parametrize("budget_mb,bits,keep_all", [(64, 4, True), (16, 4, True), (14, 6, False), (64, 0, True)])
+@pytest.mark.parametrize("budget_mb,bits,keep_all", [(64, 4, True), (16, 4, True), (64, 6, False), (14, 6, False),
+                                                    (64, 0, True)])
 def test_ooc_join_agg_matches_oracle(budget_mb, bits, keep_all):
     say(f"ooc budget={budget_mb}MB bits={bits} keep_all={keep_all}")
     pool = tq.PagePool(256 << 10, 2000, pinned=True)

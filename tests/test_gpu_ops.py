@@ -164,6 +164,18 @@ def test_join_pairs_many_to_many(lf):
     assert got == list(zip(pr.tolist(), br.tolist()))
 
 
+def test_join_pairs_heavy_duplicates():
+    # one key repeated 6,000 times: its chain runs over some 750 buckets
+    rng = np.random.default_rng(5)
+    bk = np.concatenate([np.full(6000, 7, np.int64), rng.integers(10, 200_000, 30_000)])
+    rng.shuffle(bk)
+    pk = np.concatenate([np.array([7, 7, 8], np.int64), rng.integers(0, 210_000, 20_000)])
+    m, got = _pairs(bk, pk, 0.5)
+    total, pr, br = oracle.join_pairs(bk, pk)
+    assert m == total and m > 12_000
+    assert got == list(zip(pr.tolist(), br.tolist()))
+
+
 def test_join_pairs_extreme_keys_and_empty_sides():
     I64_MIN, I64_MAX = -(2 ** 63), 2 ** 63 - 1
     bk = [I64_MAX, I64_MIN, I64_MIN + 1, -1, 0, 5, 5]
@@ -200,7 +212,7 @@ def test_join_table_too_small_latches_full():
     assert e.value.status == tq.TQ_EFULL
 
 
-@pytest.mark.parametrize("lf,unique", [(0.5, True), (0.25, False), (0.9, True)])
+@pytest.mark.parametrize("lf,unique", [(0.5, True), (0.25, False), (0.9, True), (0.1, True)])
 def test_join_agg_full_size_matches_oracle(lf, unique):
     say(f"join_agg 1.5M x 6M lf={lf} unique={unique}")
     dim, fact = wl.join_agg_tables()
@@ -211,6 +223,52 @@ def test_join_agg_full_size_matches_oracle(lf, unique):
     want = oracle.join_agg(dim, fact, q)
     assert got["join_rows"] == want["join_rows"]
     assert_groups_equal(got, want, q.avg_of)
+
+
+def _join_agg_case(dim, fact, q, lf, unique):
+    ja = pipeline.JoinAgg(q, len(dim["key"]), lf, unique=unique)
+    ja.run(pipeline.to_device(dim), pipeline.to_device(fact))
+    got = ja.result()
+    want = oracle.join_agg(dim, fact, q)
+    assert got["join_rows"] == want["join_rows"]
+    assert_groups_equal(got, want, q.avg_of)
+    return want["join_rows"]
+
+
+@pytest.mark.parametrize("lf", [0.5, 0.9])
+def test_join_agg_duplicate_build_keys(lf):
+    # many-to-many: every build key appears several times; full buckets are common at 0.9
+    nd, nf = 60_000, 300_000
+    dim = {"key": uniform(nd, 0, 14_999, np.int64, 71, 0), "group": uniform(nd, 0, 24, np.int32, 71, 1),
+           "date": uniform(nd, 700, 1100, np.int32, 71, 2)}
+    fact = {"fk": uniform(nf, 0, 17_999, np.int64, 72, 0), "price": uniform(nf, 90_000, 10_500_000, np.int64, 72, 1),
+            "disc": uniform(nf, 0, 10, np.int64, 72, 2)}
+    say(f"duplicate build keys lf={lf}")
+    assert _join_agg_case(dim, fact, wl.JOIN_AGG_QUERY, lf, unique=False) > nf
+
+
+@pytest.mark.parametrize("unique", [True, False])
+def test_join_agg_equal_tags_and_long_chains(unique):
+    # keys whose low 40 bits are zero share one tag, so every probe of a bucket
+    # sees several candidates; at load factor 0.9 chains run over many buckets
+    nd = 3000
+    keys = (np.arange(nd, dtype=np.int64) + 1) << 40
+    dim = {"key": keys, "group": (np.arange(nd) % 25).astype(np.int32), "date": np.full(nd, 800, np.int32)}
+    nf = 50_003
+    pick = uniform(nf, 0, nd + 499, np.int64, 73, 0)  # about 1 in 7 misses
+    fact = {"fk": (pick + 1) << 40, "price": uniform(nf, 90_000, 10_500_000, np.int64, 73, 1),
+            "disc": uniform(nf, 0, 10, np.int64, 73, 2)}
+    say(f"equal tags unique={unique}")
+    _join_agg_case(dim, fact, wl.JOIN_AGG_QUERY, 0.9, unique)
+
+
+def test_join_agg_two_sums_and_probe_filter():
+    dim, fact = wl.join_agg_tables(200_000, 900_001, seed=74)
+    q0 = wl.JOIN_AGG_QUERY
+    q = wl.JoinAggQuery(build_key=q0.build_key, build_payload=q0.build_payload, build_preds=q0.build_preds,
+                        probe_key=q0.probe_key, probe_preds=[Pred("disc", 2, 8)],
+                        sums=[q0.sums[0], [Factor("price", 1, 0)]], domain=q0.domain, avg_of=[0, 1])
+    _join_agg_case(dim, fact, q, 0.5, True)
 
 
 @pytest.mark.parametrize("nd,nf", [(1, 1), (3, 10), (100, 5), (4097, 20_001)])

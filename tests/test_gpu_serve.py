@@ -65,6 +65,18 @@ def test_alone_equals_mix_equals_oracle(setup):
     workers_used = {mixed[0][i].worker for i in range(len(reqs))}
     say(f"workers used in the mix: {sorted(workers_used)}")
     assert len(workers_used) > 1
+    bad = []
+    for i in range(len(reqs)):
+        q = R[i]
+        w = expected(setup, q)
+        for name, run in (("alone", alone), ("mix", mixed)):
+            k, c, sm = packed(setup, q, *run, i)
+            if not (k.tolist() == w["keys"].tolist() and c.tolist() == w["count"].tolist()
+                    and sm.tolist() == w["sums"].tolist()):
+                bad.append((name, i, q.shape, q.fact_first, q.n_fact, q.dim_first, q.n_dim, int(c.sum()),
+                            int(w["count"].sum())))
+    for b in bad:
+        say("mismatch", b)
     for i in range(len(reqs)):
         q = R[i]
         assert alone[0][i].status == 0 and mixed[0][i].status == 0, i
