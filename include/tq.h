@@ -377,18 +377,18 @@ tq_status tq_batched_prepare(const tq_batch_query* q, const tq_instance* h_inst,
                              size_t work_bytes, hipStream_t stream);
 
 /* One pass over the n prepared instances: a preparation kernel (table headers,
- * tags, states, counters) and ONE persistent launch whose workgroups take
- * work items (build tiles, probe tiles, finalize chunks, in that order) from
- * an atomic queue; a probe item waits until its instance's build items are
- * done, a finalize item until its probe items are done (bounded waits: a wait
- * that times out latches TQ_EHIP in the work area instead of hanging). Only
- * kernels are enqueued, so the call can be captured in a hipGraph and
- * replayed. tq_batched_check reads the error latched by the last run. */
+ * tags, states, counters), then one persistent launch per phase (build tiles;
+ * probe tiles; single-chunk finalizes and chunk counts; chunk writes) whose
+ * workgroups take the phase's work items of all instances from an atomic
+ * queue. An item needs only earlier phases, so no workgroup waits for
+ * another. Only kernels are enqueued, so the call can be captured in a
+ * hipGraph and replayed. tq_batched_check synchronises `stream` and reports an
+ * error latched in the work area by the last run. */
 tq_status tq_batched_run(const tq_batch_query* q, void* d_work, int32_t n, hipStream_t stream);
 tq_status tq_batched_check(const void* d_work, hipStream_t stream);
 
 /* The same work as separate stand-alone calls, one build, probe and finalize
- * launch per instance (the baseline the persistent launch is compared with). */
+ * launch per instance (the baseline the batched launches are compared with). */
 tq_status tq_batched_run_per_instance(const tq_batch_query* q, const tq_instance* h_inst, int32_t n,
                                       hipStream_t stream);
 

@@ -5,7 +5,7 @@ Instances are bucketed by fact-row decade and by whether their group domain
 fits the dense LDS partials. For each bucket, a sample of its instances is
 timed under candidate parameters by coordinate descent (load factor, then
 probe tile, then build tile), each timing the median of a few runs of the
-persistent launch. Results are independent of these parameters (the tests
+batched launches. Results are independent of these parameters (the tests
 sweep them), so tuning only changes speed. Choices are cached in a JSON file
 keyed by device and bucket.
 """

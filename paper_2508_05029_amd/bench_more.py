@@ -277,7 +277,7 @@ def bench_batched(args):
     gbs = in_bytes / (ms / 1e3) / 1e9
     return _base("input GB/s batched join-aggregate instances (% of HBM peak)", gbs, "GB/s", args, ms, reps,
                  f"batched: {count} instances, fact log-uniform 1e3..1e6, dim = fact/4, groups log-uniform "
-                 f"4..65536 Zipf(1.1), int64 columns; one persistent launch in a hipGraph",
+                 f"4..65536 Zipf(1.1), int64 columns; one queue launch per phase, all in a hipGraph",
                  {"input_bytes": in_bytes, "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
                   "ms_one_launch_per_instance": round(ms_per_inst, 3),
                   "speedup_vs_per_instance": round(ms_per_inst / ms, 2),

@@ -1,11 +1,13 @@
-// Batched join + group-by instances in one persistent launch.
+// Batched join + group-by instances: one queue launch per phase.
 //
 // Work area: WorkHeader | BInst[n] | int64 ctr[n][kCtr] | uint64 item[n_items].
 // An item is (type, instance, index). The list holds every build tile, then
-// every probe tile, then the finalize items, so an item's dependencies always
-// sit earlier in the queue: whoever waits has been preceded by workgroups that
-// already took the items it waits for, and waits end. Each wait is bounded in
-// any case; a timed-out wait latches an error and skips the item's work.
+// every probe tile, then the finalize items (single-chunk finalizes and chunk
+// counts), then the chunk writes; each group is one phase. Every phase is one
+// persistent launch whose workgroups take items from the phase's range of the
+// list through an atomic cursor; an item depends only on items of earlier
+// phases, which the launch boundary has completed and made visible, so no
+// workgroup ever waits for another.
 #include <math.h>
 #include <string.h>
 
@@ -22,8 +24,8 @@ namespace {
 constexpr int kBBlock = 512;
 constexpr int kFinChunk = 8192;  // keys per finalize chunk
 constexpr int kMaxChunks = 8;    // domain <= 65536
-constexpr int kCtr = 16;         // counters per instance: build, probe, fcount, -, chunk counts [8..16)
-constexpr int64_t kSpinLimit = (int64_t)1 << 19;  // polls: well under a second
+constexpr int kCtr = 16;         // counters per instance: chunk counts at [8..16)
+constexpr int kPhases = 4;       // build, probe, finalize (single chunk or chunk counts), chunk writes
 constexpr int kBPR = 2;          // rows per lane in probe items
 
 enum ItemType { kItBuild = 0, kItProbe = 1, kItFinOne = 2, kItFinCount = 3, kItFinWrite = 4 };
@@ -49,11 +51,11 @@ struct BInst {
 };
 
 struct WorkHeader {
-  int64_t head;
+  int64_t head[kPhases];  // next item of each phase
+  int64_t end[kPhases];   // the phase's items are [end[p - 1], end[p])
   int64_t n_items;
   int32_t n_inst;
   int32_t err;
-  int64_t pad[4];
 };
 static_assert(sizeof(WorkHeader) <= 256, "header");
 
@@ -113,32 +115,10 @@ int64_t count_items(const tq_instance* h, int32_t n) {
   return t;
 }
 
-// Spins until *p >= target. Gives up after kSpinLimit polls, or at once when
-// another wait has already timed out (*err set), so a failure cannot make the
-// launch run long.
-__device__ bool wait_at_least(int64_t* p, int64_t target, int32_t* err) {
-  for (int64_t i = 0; i < kSpinLimit; i++) {
-    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
-      __threadfence();  // acquire: the producers' writes are visible from here on
-      return true;
-    }
-    if ((i & 63) == 63 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    __builtin_amdgcn_s_sleep(8);
-  }
-  return false;
-}
-
-__device__ void signal(int64_t* p) {
-  __threadfence();  // release this workgroup's writes before the counter moves
-  atomicAdd(reinterpret_cast<unsigned long long*>(p), 1ull);
-}
-
 __global__ __launch_bounds__(256) void k_batched_prep(WorkHeader* hdr, const BInst* insts, int64_t* ctrs, int32_t n,
                                                       int32_t nsum, uint32_t flags) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    hdr->head = 0;
-    hdr->err = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x < kPhases) hdr->head[threadIdx.x] = threadIdx.x == 0 ? 0 : hdr->end[threadIdx.x - 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->err = 0;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const BInst& I = insts[i];
     if (threadIdx.x < kCtr) ctrs[(int64_t)i * kCtr + threadIdx.x] = 0;
@@ -263,17 +243,16 @@ __device__ void probe_item(const BQuery& Q, const BInst& I, int64_t idx, char* s
 }
 
 __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, const BInst* insts,
-                                                      const uint64_t* items, int64_t* ctrs) {
+                                                      const uint64_t* items, int64_t* ctrs, int phase) {
   extern __shared__ __align__(16) char smem[];
   __shared__ uint64_t s_item;
-  __shared__ int s_ok;
   __shared__ int64_t s_base;
   __shared__ int64_t ws[kBBlock / kWave];
-  const int64_t n_items = hdr->n_items;
+  const int64_t end = hdr->end[phase];
   for (;;) {
     if (threadIdx.x == 0) {
-      int64_t i = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->head), 1ull);
-      s_item = i < n_items ? items[i] : ~0ull;
+      int64_t i = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&hdr->head[phase]), 1ull);
+      s_item = i < end ? items[i] : ~0ull;
     }
     __syncthreads();
     const uint64_t it = s_item;
@@ -313,50 +292,26 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, 
         for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < hi) && eval_preds<4, kRows>(P, v, i);
         table_insert<kRows>(words, slots, I.log2cap, 0, pend, v[0], v[1]);
       }
-      __syncthreads();
-      if (threadIdx.x == 0) signal(&ctr[0]);
     } else if (type == kItProbe) {
-      if (threadIdx.x == 0) s_ok = wait_at_least(&ctr[0], I.n_build_items, &hdr->err);
-      __syncthreads();
-      if (s_ok) {
-        int stride = 1 + Q.nsum;
-        if (I.domain * stride * 8 <= kLdsAggBytes) probe_item<kDense>(Q, I, idx, smem, &hdr->err);
-        else probe_item<kHash>(Q, I, idx, smem, &hdr->err);
-      } else if (threadIdx.x == 0) {
-        latch_error(&hdr->err, TQ_EHIP);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) signal(&ctr[1]);
+      if (I.domain * (1 + Q.nsum) * 8 <= kLdsAggBytes) probe_item<kDense>(Q, I, idx, smem, &hdr->err);
+      else probe_item<kHash>(Q, I, idx, smem, &hdr->err);
+    } else if (type == kItFinOne) {
+      int64_t g = fin_write(I, Q.nsum, 0, I.domain, 0, ws);
+      if (threadIdx.x == 0) *I.ngroups = g;
+    } else if (type == kItFinCount) {
+      int64_t c = fin_count(I, Q.nsum, idx * kFinChunk, min(I.domain, (idx + 1) * kFinChunk), ws);
+      if (threadIdx.x == 0) ctr[8 + idx] = c;
     } else {
-      if (type != kItFinWrite) {
-        if (threadIdx.x == 0) s_ok = wait_at_least(&ctr[1], I.n_probe_items, &hdr->err);
-      } else {
-        if (threadIdx.x == 0) s_ok = wait_at_least(&ctr[2], I.nchunks, &hdr->err);
+      if (threadIdx.x == 0) {
+        int64_t b = 0;
+        for (int64_t c = 0; c < idx; c++) b += ctr[8 + c];
+        s_base = b;
       }
       __syncthreads();
-      if (!s_ok) {
-        if (threadIdx.x == 0) latch_error(&hdr->err, TQ_EHIP);
-      } else if (type == kItFinOne) {
-        int64_t g = fin_write(I, Q.nsum, 0, I.domain, 0, ws);
-        if (threadIdx.x == 0) *I.ngroups = g;
-      } else if (type == kItFinCount) {
-        int64_t c = fin_count(I, Q.nsum, idx * kFinChunk, min(I.domain, (idx + 1) * kFinChunk), ws);
-        if (threadIdx.x == 0) {
-          ctr[8 + idx] = c;
-          signal(&ctr[2]);
-        }
-      } else {
-        if (threadIdx.x == 0) {
-          int64_t b = 0;
-          for (int64_t c = 0; c < idx; c++) b += __hip_atomic_load(&ctr[8 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s_base = b;
-        }
-        __syncthreads();
-        int64_t g = fin_write(I, Q.nsum, idx * kFinChunk, min(I.domain, (idx + 1) * kFinChunk), s_base, ws);
-        if (threadIdx.x == 0 && idx == I.nchunks - 1) *I.ngroups = g;
-      }
-      __syncthreads();
+      int64_t g = fin_write(I, Q.nsum, idx * kFinChunk, min(I.domain, (idx + 1) * kFinChunk), s_base, ws);
+      if (threadIdx.x == 0 && idx == I.nchunks - 1) *I.ngroups = g;
     }
+    __syncthreads();
   }
 }
 
@@ -464,22 +419,31 @@ tq_status tq_batched_prepare(const tq_batch_query* q, const tq_instance* h, int3
     b.avg = x.d_avg;
     b.ngroups = x.d_ngroups;
   }
+  int64_t end[kPhases];
   for (int i = 0; i < n; i++)
     for (int64_t t = 0; t < bi[(size_t)i].n_build_items; t++) items.push_back(make_item(kItBuild, i, t));
+  end[0] = (int64_t)items.size();
   for (int i = 0; i < n; i++)
     for (int64_t t = 0; t < bi[(size_t)i].n_probe_items; t++) items.push_back(make_item(kItProbe, i, t));
+  end[1] = (int64_t)items.size();
   for (int i = 0; i < n; i++) {
     if (bi[(size_t)i].nchunks == 1) items.push_back(make_item(kItFinOne, i, 0));
     else
       for (int c = 0; c < bi[(size_t)i].nchunks; c++) items.push_back(make_item(kItFinCount, i, c));
   }
+  end[2] = (int64_t)items.size();
   for (int i = 0; i < n; i++)
     if (bi[(size_t)i].nchunks > 1)
       for (int c = 0; c < bi[(size_t)i].nchunks; c++) items.push_back(make_item(kItFinWrite, i, c));
+  end[3] = (int64_t)items.size();
   Layout L = layout(n, (int64_t)items.size());
   if (work_bytes < L.bytes) return fail(TQ_EINVAL, "work area has %zu bytes, needs %zu", work_bytes, L.bytes);
   WorkHeader wh;
   memset(&wh, 0, sizeof wh);
+  for (int p = 0; p < kPhases; p++) {
+    wh.end[p] = end[p];
+    wh.head[p] = p == 0 ? 0 : end[p - 1];
+  }
   wh.n_items = (int64_t)items.size();
   wh.n_inst = n;
   char* w = static_cast<char*>(d_work);
@@ -507,8 +471,9 @@ tq_status tq_batched_run(const tq_batch_query* q, void* d_work, int32_t n, hipSt
   int per_cu = 0;
   TQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched, kBBlock, kLdsAggBytes));
   per_cu = std::max(1, std::min(per_cu, 4));
-  hipLaunchKernelGGL(k_batched, dim3(device_cu_count() * per_cu), dim3(kBBlock), kLdsAggBytes, stream, Q, hdr, insts,
-                     items, ctrs);
+  for (int p = 0; p < kPhases; p++)
+    hipLaunchKernelGGL(k_batched, dim3(device_cu_count() * per_cu), dim3(kBBlock), kLdsAggBytes, stream, Q, hdr, insts,
+                       items, ctrs, p);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -518,7 +483,7 @@ tq_status tq_batched_check(const void* d_work, hipStream_t stream) {
   TQ_HIP(hipStreamSynchronize(stream));
   WorkHeader wh;
   TQ_HIP(hipMemcpy(&wh, d_work, sizeof wh, hipMemcpyDeviceToHost));
-  if (wh.err) return fail(wh.err, "a batched work item timed out waiting for its dependencies");
+  if (wh.err) return fail(wh.err, "a batched work item latched an error");
   return TQ_OK;
 }
 

@@ -1,15 +1,13 @@
-"""GPU: thousands-of-instances batching. Every instance of the persistent
-launch equals the oracle and the one-launch-per-instance path; results do not
-depend on tile sizes or load factors; a captured hipGraph replays correctly."""
+"""GPU: thousands-of-instances batching. Every instance of the batched
+launches equals the oracle and the one-launch-per-instance path; results do
+not depend on tile sizes or load factors; a captured hipGraph replays
+correctly."""
 import sys
 
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
-# the persistent launch did not finish within 180 s on its first GPU run and no
-# cause has been found by reading the code yet: it stays off the GPU until one is
-HUNG = pytest.mark.skip(reason="persistent launch: unexplained 180 s stall on its first GPU run")
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
@@ -44,9 +42,8 @@ def check_all(job, insts, which=None):
         assert np.all(np.abs(g["avg"][:, 0] - want["avg"][:, 0]) <= 1e-12 * np.abs(want["avg"][:, 0])), i
 
 
-@HUNG
 @pytest.mark.parametrize("tiles", [(4096, 4096, 0.5), (1024, 65536, 0.25), (65536, 1024, 0.9)])
-def test_persistent_launch_matches_oracle(tiles):
+def test_batched_launches_match_oracle(tiles):
     bt, pt, lf = tiles
     say(f"batched tiles={tiles}")
     insts = make_instances(48)
@@ -64,7 +61,6 @@ def test_per_instance_path_matches_oracle():
     check_all(job, insts)
 
 
-@HUNG
 def test_mixed_per_instance_parameters_and_graph_replay():
     insts = make_instances(32, fact_hi=5.0, seed=wl.BATCH_SEED + 200)
     params = [((0.25, 0.5, 0.75)[i % 3], (1024, 8192)[i % 2], (2048, 16384, 65536)[i % 3]) for i in range(len(insts))]
