@@ -162,18 +162,18 @@ def bench_ooc(args):
     if not args.no_cpu_baseline:
         import oracle
         sd, sf = wl.ooc_tables_numpy(2_000_000, 500_000)
-        spool = tq.PagePool(1 << 20, 200, pinned=True)
-        sdt = HostTable(spool, wl.OOC_DIM_COLS, len(sd["key"]), 250_000)
+        spool = tq.PagePool(1 << 20, 400, pinned=True)
+        sdt = HostTable(spool, wl.OOC_DIM_COLS, len(sd["key"]), 100_000)
         sdt.fill_numpy(sd)
-        sft = HostTable(spool, wl.OOC_FACT_COLS, len(sf["fk"]), 250_000)
+        sft = HostTable(spool, wl.OOC_FACT_COLS, len(sf["fk"]), 100_000)
         sft.fill_numpy(sf)
-        sj = pipeline.OocJoinAgg(q, sdt, sft, 48 << 20, log2_fanout=6, chunk_bytes=256 << 10)
+        sj = pipeline.OocJoinAgg(q, sdt, sft, 64 << 20, log2_fanout=6, chunk_bytes=256 << 10)
         sj.run()
         got = sj.result()
         t1 = time.perf_counter()
         want = oracle.join_agg(sd, sf, q)
         tc = time.perf_counter() - t1
-        parity = {"sample": "2M fact x 500K dim rows, budget 48 MiB (spills)",
+        parity = {"sample": "2M fact x 500K dim rows, budget 64 MiB (spills)",
                   "equal": got["sums"].tolist() == want["sums"].tolist() and got["count"].tolist() == want["count"].tolist(),
                   "spilled_chunks": sj.stats.spilled_chunks}
         cpu = {"value": round((2_000_000 * 44 + 500_000 * 16) / tc / 1e9, 4), "unit": "GB/s", "cores": 1,
