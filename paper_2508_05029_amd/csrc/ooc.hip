@@ -26,6 +26,8 @@ namespace tq {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kSpillBatch = 8;     // chunks spilled per shortage
+constexpr int kPrefetchParts = 3;  // pass 2 reloads this many partitions ahead of the one it joins, waiting if needed
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct CopyDesc {
@@ -36,19 +38,37 @@ struct CopyDesc {
   int32_t pad;
 };
 
-__global__ __launch_bounds__(256) void k_gather_copy(const CopyDesc* d, int nd) {
-  for (int i = blockIdx.x; i < nd; i += gridDim.x) {
-    const CopyDesc c = d[i];
-    if (c.w == 8) {
-      for (int64_t j = threadIdx.x; j < c.n; j += blockDim.x)
-        static_cast<int64_t*>(c.dst)[j] = static_cast<const int64_t*>(c.src)[j];
-    } else if (c.w == 4) {
-      for (int64_t j = threadIdx.x; j < c.n; j += blockDim.x)
-        static_cast<int32_t*>(c.dst)[j] = static_cast<const int32_t*>(c.src)[j];
-    } else {
-      for (int64_t j = threadIdx.x; j < c.n; j += blockDim.x)
-        static_cast<uint8_t*>(c.dst)[j] = static_cast<const uint8_t*>(c.src)[j];
+// Copies a list of contiguous byte ranges: workgroup (x, y) copies the 16 KiB
+// tiles x, x + gridDim.x, ... of range y, with the widest access that both of
+// its pointers allow (tile starts keep the ranges' alignment).
+constexpr int64_t kCopyTile = 16384;
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_gather_copy(const CopyDesc* d) {
+  const CopyDesc c = d[blockIdx.y];
+  const int64_t bytes = c.n * c.w;
+  const uintptr_t al = reinterpret_cast<uintptr_t>(c.src) | reinterpret_cast<uintptr_t>(c.dst);
+  for (int64_t b0 = (int64_t)blockIdx.x * kCopyTile; b0 < bytes; b0 += (int64_t)gridDim.x * kCopyTile) {
+    const int64_t nb = std::min<int64_t>(bytes - b0, kCopyTile);
+    const char* s = static_cast<const char*>(c.src) + b0;
+    char* o = static_cast<char*>(c.dst) + b0;
+    int64_t j0 = 0;
+    if ((al & 15) == 0) {
+      const int64_t nv = nb >> 4;
+      for (int64_t j = threadIdx.x; j < nv; j += 256)
+        reinterpret_cast<v4i32*>(o)[j] = __builtin_nontemporal_load(reinterpret_cast<const v4i32*>(s) + j);
+      j0 = nv << 4;
+    } else if ((al & 7) == 0) {
+      const int64_t nv = nb >> 3;
+      for (int64_t j = threadIdx.x; j < nv; j += 256)
+        reinterpret_cast<int64_t*>(o)[j] = reinterpret_cast<const int64_t*>(s)[j];
+      j0 = nv << 3;
+    } else if ((al & 3) == 0) {
+      const int64_t nv = nb >> 2;
+      for (int64_t j = threadIdx.x; j < nv; j += 256)
+        reinterpret_cast<int32_t*>(o)[j] = reinterpret_cast<const int32_t*>(s)[j];
+      j0 = nv << 2;
     }
+    for (int64_t j = j0 + threadIdx.x; j < nb; j += 256) o[j] = s[j];
   }
 }
 
@@ -95,7 +115,7 @@ class Driver {
   std::vector<uint8_t> chunk_busy;  // taken for a contiguous region
   struct Pending {
     hipEvent_t ev;
-    int64_t chunk;
+    std::vector<int64_t> chunks;
   };
   std::deque<Pending> pending;  // chunks to return once an event completes
 
@@ -171,23 +191,26 @@ class Driver {
 
   tq_status reclaim_one(bool wait) {
     if (pending.empty()) return TQ_ENOMEM;
-    Pending q = pending.front();
+    Pending& q = pending.front();
     if (wait) TQ_HIP(hipEventSynchronize(q.ev));
     else if (hipEventQuery(q.ev) != hipSuccess) return TQ_ENOMEM;
-    pending.pop_front();
     (void)hipEventDestroy(q.ev);
-    free_chunks.push_back(q.chunk);
-    tq_budget_release(budget, chunk_bytes);
-    chunks_out--;
+    for (int64_t id : q.chunks) {
+      free_chunks.push_back(id);
+      tq_budget_release(budget, chunk_bytes);
+      chunks_out--;
+    }
+    pending.pop_front();
     return TQ_OK;
   }
 
-  // Returns chunk `id` to the arena once the work enqueued so far on `s` is done.
-  tq_status retire(int64_t id, hipStream_t s) {
+  // Returns the chunks `ids` to the arena once the work enqueued so far on `s` is done.
+  tq_status retire(std::vector<int64_t> ids, hipStream_t s) {
+    if (ids.empty()) return TQ_OK;
     hipEvent_t ev;
     TQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     TQ_HIP(hipEventRecord(ev, s));
-    pending.push_back(Pending{ev, id});
+    pending.push_back(Pending{ev, std::move(ids)});
     return TQ_OK;
   }
 
@@ -201,21 +224,25 @@ class Driver {
     return p < pin_lo || p > pin_hi;
   }
 
-  // Spill one resident chunk of the partition that pass 2 reaches last.
+  // Spill one resident chunk of the partition that pass 2 reaches last,
+  // preferring full chunks: a partly filled tail that is spilled costs a whole
+  // chunk's copy for its few rows, and the partition's next append opens yet
+  // another chunk.
   tq_status spill_one(bool* done) {
     *done = false;
-    for (int p = nparts - 1; p >= 0; p--) {
-      if (phase == 2 && p <= pin_hi) break;  // earlier partitions are done or pinned
-      for (Side* s : {&fact, &dim}) {
-        Holder& h = s->parts[p];
-        for (size_t i = h.chunks.size(); i-- > 0;) {
-          if (!spillable(p, h, i)) continue;
-          TQ_HIP(spill_chunk(h.chunks[i]));
-          *done = true;
-          return TQ_OK;
+    for (int full_only = 1; full_only >= 0; full_only--)
+      for (int p = nparts - 1; p >= 0; p--) {
+        if (phase == 2 && p <= pin_hi) break;  // earlier partitions are done or pinned
+        for (Side* s : {&fact, &dim}) {
+          Holder& h = s->parts[p];
+          for (size_t i = h.chunks.size(); i-- > 0;) {
+            if (!spillable(p, h, i) || (full_only && h.chunks[i].rows < s->rows_per_chunk)) continue;
+            TQ_HIP(spill_chunk(h.chunks[i]));
+            *done = true;
+            return TQ_OK;
+          }
         }
       }
-    }
     return TQ_OK;
   }
 
@@ -250,33 +277,45 @@ class Driver {
     hipEvent_t ev;
     if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev, spill)) != hipSuccess) return e;
-    pending.push_back(Pending{ev, c.dev});
+    pending.push_back(Pending{ev, {c.dev}});
     c.dev = -1;
     c.page = cur_page;
     c.sub = cur_sub++;
     return hipSuccess;
   }
 
+  // A free chunk, reserved from the budget, if one is free now (no wait, no spill).
+  bool try_take_chunk(int64_t* out) {
+    while (reclaim_one(false) == TQ_OK) {
+    }
+    if (free_chunks.empty() || tq_budget_reserve(budget, chunk_bytes) != TQ_OK) return false;
+    *out = free_chunks.back();
+    free_chunks.pop_back();
+    chunks_out++;
+    return true;
+  }
+
   // A free chunk, reserved from the budget; spills when none is available.
   tq_status take_chunk(int64_t* out) {
     for (int guard = 0; guard < (1 << 30); guard++) {
-      while (reclaim_one(false) == TQ_OK) {
-      }
-      if (!free_chunks.empty() && tq_budget_reserve(budget, chunk_bytes) == TQ_OK) {
-        *out = free_chunks.back();
-        free_chunks.pop_back();
-        chunks_out++;
-        return TQ_OK;
-      }
+      if (try_take_chunk(out)) return TQ_OK;
       if (!pending.empty()) {
         tq_status s = reclaim_one(true);
         if (s) return s;
         continue;
       }
+      // spill several chunks at once, so that their copies to the host run back
+      // to back and the wait below is for the first of them only
       bool spilled = false;
-      tq_status s = spill_one(&spilled);
-      if (s) return s;
+      for (int k = 0; k < kSpillBatch; k++) {
+        bool one = false;
+        tq_status s = spill_one(&one);
+        if (s) return s;
+        if (!one) break;
+        spilled = true;
+      }
       if (spilled) continue;
+      tq_status s;
       if (appending && !touched.empty()) {
         // every resident chunk is pinned by the append being assembled: launch
         // its copies so far, after which those chunks may be spilled
@@ -291,11 +330,17 @@ class Driver {
 
   bool spill_unwaited = false;  // spill copies enqueued since the copy stream last waited for them
 
-  tq_status reload(ChunkRef& c) {
+  // Copies a spilled chunk back into the arena; with `nowait`, only into a
+  // chunk that is free now, returning TQ_ENOMEM otherwise.
+  tq_status reload(ChunkRef& c, bool nowait = false) {
     if (c.dev >= 0) return TQ_OK;
     int64_t id;
-    tq_status s = take_chunk(&id);
-    if (s) return s;
+    if (nowait) {
+      if (!try_take_chunk(&id)) return TQ_ENOMEM;
+    } else {
+      tq_status s = take_chunk(&id);
+      if (s) return s;
+    }
     if (spill_unwaited) {
       // the chunk's spill copy to the host page may still be in flight
       hipEvent_t ev;
@@ -382,12 +427,15 @@ class Driver {
         TQ_HIP(hipStreamSynchronize(compute));
         desc_used = 0;
       }
-      const size_t k = std::min(descs.size() - done, (size_t)max_desc - desc_used);
+      const size_t k = std::min({descs.size() - done, (size_t)max_desc - desc_used, (size_t)65535});
       memcpy(h_desc + desc_used, descs.data() + done, k * sizeof(CopyDesc));
       TQ_HIP(hipMemcpyAsync(d_desc + desc_used, h_desc + desc_used, k * sizeof(CopyDesc), hipMemcpyHostToDevice,
                             compute));
-      const int grid = (int)std::min<size_t>(k, 2048);
-      hipLaunchKernelGGL(k_gather_copy, dim3(grid), dim3(256), 0, compute, d_desc + desc_used, (int)k);
+      int64_t tiles = 1;
+      for (size_t i = done; i < done + k; i++)
+        tiles = std::max<int64_t>(tiles, (descs[i].n * descs[i].w + kCopyTile - 1) / kCopyTile);
+      const int gx = (int)std::min<int64_t>(tiles, std::max<int64_t>(1, 4096 / (int64_t)k));
+      hipLaunchKernelGGL(k_gather_copy, dim3(gx, (unsigned)k), dim3(256), 0, compute, d_desc + desc_used);
       TQ_HIP(hipGetLastError());
       desc_used += k;
       done += k;
@@ -417,6 +465,12 @@ class Driver {
   int64_t max_dim_rows = 0, max_fact_rows = 0;
   int fact_map[TQ_MAX_COLS];  // fact column -> side column (or -1)
   int fact_src[TQ_MAX_COLS];  // side column -> fact column
+  // pass 2: contiguous copy of one partition's probe columns
+  char* fg_base = nullptr;
+  int64_t fg_rows = 0;
+  int fg_ncol = 0;
+  int fg_col[TQ_MAX_COLS];     // side column -> index among the copied columns (or -1)
+  size_t fg_off[TQ_MAX_COLS];  // side column -> byte offset of its copy
 
   static tq_status on_dim(void* user, int64_t, const tq_col* cols, int32_t ncol, int64_t nrows, hipStream_t) {
     return static_cast<Driver*>(user)->dim_batch(cols, ncol, nrows);
@@ -554,8 +608,36 @@ class Driver {
     for (int q = 0; q < nparts; q++) max_part = std::max(max_part, dim.parts[q].rows);
     size_t gather_bytes = 2 * align_up((size_t)max_part * 8, kAlign);
     size_t table_bytes = tq_join_table_bytes(max_part, plan.load_factor);
+    // a contiguous copy of one partition's probe columns (its key and the
+    // columns the sums read), so that a partition is probed with one launch;
+    // sized for 1.3x an even share of the fact rows (a larger partition is
+    // probed chunk by chunk instead)
+    int64_t fact_total = 0;
+    for (int64_t i = 0; i < nf; i++) fact_total += factb[i].nrows;
+    fg_rows = fact_total / nparts * 13 / 10 + fact.rows_per_chunk;
+    fg_ncol = 0;
+    size_t fg_bytes = 0;
+    for (int j = 0; j < fact.ncol; j++) {
+      const int fc = fact_src[j];
+      bool used = fc == plan.fact_key_col;
+      for (int e = 0; e < plan.nsum; e++)
+        for (int f = 0; f < plan.sums[e].nf; f++) used = used || plan.sums[e].f[f].col == fc;
+      fg_col[j] = -1;
+      if (used) {
+        fg_col[j] = fg_ncol++;
+        fg_off[j] = fg_bytes;
+        fg_bytes = align_up(fg_bytes + (size_t)fg_rows * fact.type[j], kAlign);
+      }
+    }
+    if (fg_bytes > tq_budget_cap(budget) / 8) fg_rows = 0;  // too large a share of the budget: probe by chunks
     char* region;
-    if ((s = take_region(gather_bytes + table_bytes, &region))) return s;
+    if (fg_rows > 0) {
+      s = take_region(gather_bytes + table_bytes + fg_bytes, &region);
+      if (s == TQ_ENOMEM) fg_rows = 0;
+      else if (s) return s;
+    }
+    if (fg_rows == 0 && (s = take_region(gather_bytes + table_bytes, &region))) return s;
+    fg_base = region + gather_bytes + table_bytes;
     int64_t* g_key = reinterpret_cast<int64_t*>(region);
     int64_t* g_pay = reinterpret_cast<int64_t*>(region + align_up((size_t)max_part * 8, kAlign));
     void* table = region + gather_bytes;
@@ -574,28 +656,60 @@ class Driver {
     tq_agg agg{d_state, plan.domain, plan.sums, plan.nsum};
     hipEvent_t loaded;
     TQ_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
+    int ahead = 0;
     for (int q = 0; q < nparts; q++) {
       pin_lo = q;
       pin_hi = q;  // chunks prefetched for later partitions may be spilled again if q needs the room
       if ((s = make_resident(q))) return s;
       TQ_HIP(hipEventRecord(loaded, copy));
       TQ_HIP(hipStreamWaitEvent(compute, loaded, 0));
-      // gather the partition's dimension rows (compute was synchronised at the
-      // end of the previous partition, so the descriptor slots are free)
+      // gather the partition's dimension rows (launch_copies waits for compute
+      // only when every descriptor slot has been used since it last did)
       descs.clear();
-      desc_used = 0;
       int64_t at = 0;
       for (ChunkRef& c : dim.parts[q].chunks) {
         descs.push_back(CopyDesc{chunk_ptr(c.dev) + dim.off[0], g_key + at, c.rows, 8, 0});
         descs.push_back(CopyDesc{chunk_ptr(c.dev) + dim.off[1], g_pay + at, c.rows, 8, 0});
         at += c.rows;
       }
+      // and its probe columns, when they fit the contiguous copy
+      const bool whole = fact.parts[q].rows <= fg_rows;
+      int64_t fat = 0;
+      if (whole) {
+        for (ChunkRef& c : fact.parts[q].chunks) {
+          for (int j = 0; j < fact.ncol; j++)
+            if (fg_col[j] >= 0)
+              descs.push_back(CopyDesc{chunk_ptr(c.dev) + fact.off[j], fg_base + fg_off[j] + (size_t)fat * fact.type[j],
+                                       c.rows, fact.type[j], 0});
+          fat += c.rows;
+        }
+      }
       if ((s = launch_copies())) return s;
       tq_col pc = {g_pay, TQ_I64};
       if ((s = tq_join_build(table, table_bytes, g_key, pc, at, nullptr, 0, nullptr, 0, plan.load_factor,
                              plan.log2_fanout, plan.join_flags, compute)))
         return s;
+      if (whole && fat > 0) {
+        tq_col cols[TQ_MAX_COLS];
+        int ncols = 0;
+        const int jk = fact_map[plan.fact_key_col];
+        for (int fc = 0; fc < TQ_MAX_COLS; fc++) {
+          int j = fact_map[fc];
+          if (j >= 0 && fg_col[j] >= 0) {
+            ncols = fc + 1;
+            cols[fc].data = fg_base + fg_off[j];
+            cols[fc].type = fact.type[j];
+          } else {  // a column no sum reads: any valid pointer (the plan never loads it)
+            cols[fc].data = fg_base + fg_off[jk];
+            cols[fc].type = fact.type[jk];
+          }
+        }
+        if ((s = tq_join_probe(table, reinterpret_cast<const int64_t*>(fg_base + fg_off[jk]), fat, cols, ncols, nullptr, 0,
+                               nullptr, nullptr, 0, nullptr, &agg, compute)))
+          return s;
+      }
       for (ChunkRef& c : fact.parts[q].chunks) {
+        if (whole) break;
         tq_col cols[TQ_MAX_COLS];
         int ncols = 0;
         for (int fc = 0; fc < TQ_MAX_COLS; fc++) {
@@ -609,22 +723,39 @@ class Driver {
           return s;
       }
       // partition q is done once the compute stream passes this point
+      std::vector<int64_t> done;
       for (Side* sd : {&dim, &fact})
         for (ChunkRef& c : sd->parts[q].chunks) {
-          if ((s = retire(c.dev, compute))) return s;
+          done.push_back(c.dev);
           c.dev = -1;
         }
-      if (q + 1 < nparts) {
-        // reload ahead of use, overlapping q's compute; if the budget cannot
-        // hold both partitions, the rest of q + 1 is loaded when it is reached
-        pin_lo = q;
-        pin_hi = q + 1;
-        s = make_resident(q + 1);
-        if (s == TQ_ENOMEM) s = TQ_OK;
+      if ((s = retire(std::move(done), compute))) return s;
+      // reload the next partitions ahead of use, overlapping q's compute; what
+      // the budget cannot hold now is loaded when its partition is reached
+      pin_lo = q;
+      int a = 1;
+      for (; a <= kPrefetchParts && q + a < nparts; a++) {
+        pin_hi = q + a;
+        s = make_resident(q + a);
+        if (s == TQ_ENOMEM) {
+          s = TQ_OK;
+          break;
+        }
         if (s) return s;
       }
-      // the next gather reuses the descriptor buffers
-      TQ_HIP(hipStreamSynchronize(compute));
+      // and, in partition order, as many later ones as the chunks free now
+      // hold, so that the copy engine is busy from the start of the pass
+      if (a > kPrefetchParts) {
+        for (int r = std::max(q + a, ahead); r < nparts; r++) {
+          s = make_resident(r, true);
+          if (s == TQ_ENOMEM) {
+            s = TQ_OK;
+            break;
+          }
+          if (s) return s;
+          ahead = r + 1;  // partitions before `ahead` are resident
+        }
+      }
     }
     (void)hipEventDestroy(loaded);
     TQ_HIP(hipStreamSynchronize(compute));
@@ -642,10 +773,10 @@ class Driver {
     return end;
   }
 
-  tq_status make_resident(int q) {
+  tq_status make_resident(int q, bool nowait = false) {
     for (Side* sd : {&dim, &fact})
       for (ChunkRef& c : sd->parts[q].chunks) {
-        tq_status s = reload(c);
+        tq_status s = reload(c, nowait);
         if (s) return s;
       }
     return TQ_OK;
