@@ -134,6 +134,8 @@ __global__ __launch_bounds__(256) void k_batched_prep(WorkHeader* hdr, const BIn
       th->flags = flags;
       th->lf = 0;
       th->log2g = I.log2cap - kLog2Bucket;
+      th->regions = 0;
+      th->alt = 0;
       th->ovf = 0;
       StateHeader* sh = static_cast<StateHeader*>(I.state);
       sh->magic = kStateMagic;

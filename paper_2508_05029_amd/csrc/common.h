@@ -106,7 +106,9 @@ struct TableHeader {
   uint32_t flags;
   double lf;
   int32_t log2g;     // buckets per region (log2): linear probing wraps inside a region
-  int32_t ovf;       // a region build found a region with more rows than slots
+  int32_t regions;   // 1: the last build filled each region in LDS; 0: it inserted with global CAS
+  int32_t alt;       // 1: the tags and slots in use are the build scratch's (see scratch_alt_tags)
+  int32_t ovf;       // set during a build when a region's rows do not fit it
 };
 static_assert(sizeof(TableHeader) <= kHeaderBytes, "header");
 
@@ -120,7 +122,9 @@ struct StateHeader {
 };
 static_assert(sizeof(StateHeader) <= kHeaderBytes, "header");
 
-// Table: header | int64 partial[kMaxPartBlocks] | uint16 tag[cap_max] | {key, payload}[cap_max].
+// Table: header | int64 partial[kMaxPartBlocks] | uint16 tag[cap_max] |
+// {key, payload}[cap_max] | build scratch (the region build's tickets, bin
+// counts and row segments; see table_scratch).
 // Slots form buckets of kBucket; the 16-bit tags of one bucket are one 16-byte
 // word group, read with a single load.
 constexpr int kBucket = 8;
@@ -139,6 +143,42 @@ __host__ __device__ inline uint32_t* table_tags(void* t) {
 __host__ __device__ inline int64_t* table_slots(void* t, int64_t cap_max) {
   return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(t) + kHeaderBytes + kMaxPartBlocks * 8 +
                                     table_tag_bytes(cap_max));
+}
+// Region build scratch, after the slots, sized by the capacity: int32
+// block_rows[max_grid] | uint32 meta[max_grid][kRegionBins] ((offset << 16) |
+// count of one block's rows in each region) | {key, payload}[cap_max] (each
+// block's passing rows, grouped by region, at block * kPartRows) | uint16
+// alt_tags[cap_max], where max_grid = part_grid_max(cap_max). When a region
+// overflows, the fallback insert builds the whole table into alt_tags and
+// the row area (which then serves as the slots).
+constexpr int kRegionBins = 256;  // the top 8 bits of a bucket index select its region
+constexpr int kLog2Bins = 8;
+constexpr int kPartBlock = 512;
+constexpr int kPartRows = kPartBlock * kRows;  // rows per partitioning block
+__host__ __device__ inline int64_t part_grid_max(int64_t cap_max) {
+  return cap_max / kPartRows > 1 ? cap_max / kPartRows : 1;
+}
+__host__ __device__ inline size_t block_rows_bytes(int64_t cap_max) {
+  return ((size_t)part_grid_max(cap_max) * 4 + 255) & ~(size_t)255;
+}
+__host__ __device__ inline size_t scratch_bytes(int64_t cap_max) {
+  return block_rows_bytes(cap_max) + (size_t)part_grid_max(cap_max) * kRegionBins * 4 + (size_t)cap_max * 16 +
+         table_tag_bytes(cap_max);
+}
+__host__ __device__ inline char* table_scratch(void* t, int64_t cap_max) {
+  return reinterpret_cast<char*>(table_slots(t, cap_max)) + (size_t)cap_max * 16;
+}
+__host__ __device__ inline int32_t* scratch_block_rows(void* t, int64_t cap_max) {
+  return reinterpret_cast<int32_t*>(table_scratch(t, cap_max));
+}
+__host__ __device__ inline uint32_t* scratch_meta(void* t, int64_t cap_max) {
+  return reinterpret_cast<uint32_t*>(table_scratch(t, cap_max) + block_rows_bytes(cap_max));
+}
+__host__ __device__ inline int64_t* scratch_rows(void* t, int64_t cap_max) {
+  return reinterpret_cast<int64_t*>(scratch_meta(t, cap_max) + (size_t)part_grid_max(cap_max) * kRegionBins);
+}
+__host__ __device__ inline uint32_t* scratch_alt_tags(void* t, int64_t cap_max) {
+  return reinterpret_cast<uint32_t*>(scratch_rows(t, cap_max) + (size_t)cap_max * 2);
 }
 __host__ __device__ inline int64_t* state_data(void* s) {
   return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(s) + kHeaderBytes);
@@ -312,6 +352,48 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t* excl, int
 __device__ __forceinline__ int64_t block_sum(int64_t x, int64_t* wave_sums) {
   int64_t e;
   return block_excl_scan(x, &e, wave_sums);
+}
+
+// Block-wide sum and maximum of one int64 per thread, both valid in every
+// thread. Contains two barriers.
+__device__ __forceinline__ int64_t block_sum_max(int64_t x, int64_t* mx, int64_t* wave_vals) {
+  const int lane = __lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  int64_t s = x, m = x;
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    s += __shfl_xor(s, d, kWave);
+    const int64_t y = __shfl_xor(m, d, kWave);
+    m = y > m ? y : m;
+  }
+  if (lane == 0) {
+    wave_vals[2 * wid] = s;
+    wave_vals[2 * wid + 1] = m;
+  }
+  __syncthreads();
+  int64_t ts = 0, tm = wave_vals[1];
+  for (int w = 0; w < nw; w++) {
+    ts += wave_vals[2 * w];
+    tm = wave_vals[2 * w + 1] > tm ? wave_vals[2 * w + 1] : tm;
+  }
+  __syncthreads();
+  *mx = tm;
+  return ts;
+}
+
+// Block-wide maximum of one int64 per thread, valid in every thread. Contains two barriers.
+__device__ __forceinline__ int64_t block_max(int64_t x, int64_t* wave_vals) {
+  const int lane = __lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    int64_t y = __shfl_xor(x, d, kWave);
+    x = y > x ? y : x;
+  }
+  if (lane == 0) wave_vals[wid] = x;
+  __syncthreads();
+  int64_t m = wave_vals[0];
+  for (int w = 1; w < nw; w++) m = wave_vals[w] > m ? wave_vals[w] : m;
+  __syncthreads();
+  return m;
 }
 
 }  // namespace tq

@@ -35,7 +35,7 @@ __host__ __device__ inline int log2cap_for(int64_t rows, double lf) {
 }
 
 __host__ __device__ inline size_t table_bytes_for(int64_t cap) {
-  return kHeaderBytes + (size_t)kMaxPartBlocks * 8 + table_tag_bytes(cap) + (size_t)cap * 16;
+  return kHeaderBytes + (size_t)kMaxPartBlocks * 8 + table_tag_bytes(cap) + (size_t)cap * 16 + scratch_bytes(cap);
 }
 
 static int64_t cap_max_for_bytes(size_t bytes) {
@@ -76,6 +76,8 @@ __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
   h->flags = 0;
   h->lf = 0.5;
   h->log2g = 6 - kLog2Bucket;
+  h->regions = 0;
+  h->alt = 0;
   h->ovf = 0;
 }
 
@@ -136,11 +138,231 @@ __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_
     h->flags = flags;
     h->lf = lf;
     h->log2g = l - kLog2Bucket;
+    h->regions = 0;
+    h->alt = 0;
     if (full) latch_error(&h->err, TQ_EFULL);
   }
   if (full) return;  // does not fit: TQ_EFULL is latched, nothing is inserted
   uint32_t* words = table_tags(h);
   v2i64* slots = reinterpret_cast<v2i64*>(table_slots(h, cap_max));
+  const DCol kc = {keys, 8};
+  const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
+  for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
+    const bool fullrow = r0 + kRows <= n;
+    int64_t v[NC][kRows], k[kRows], pay[kRows];
+    bool pend[kRows];
+    load_rows<NC>(P, r0, fullrow, n, v);
+    load4(kc, r0, fullrow, n, k);
+    load4(payload, r0, fullrow, n, pay);
+#pragma unroll
+    for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
+    table_insert<kRows>(words, slots, l, skip, pend, k, pay);
+  }
+}
+
+// ------------------------------------------------------------------ region build
+//
+// The common case of a build that fits: no global atomics per row. Each table
+// region (the buckets that share the top kLog2Bins bits of their index, with
+// linear probing wrapping inside the region) is filled in LDS by one
+// workgroup and written out whole. Three launches, so that each reads what
+// the previous one wrote without any wait between workgroups:
+//   k_build_part     each block filters and hashes its kPartRows rows and
+//                    groups the passing ones by region in its own segment of
+//                    the scratch area, recording (offset, count) per region.
+//   k_build_regions  every workgroup sums the block counts and fixes the
+//                    capacity; workgroup j gathers region j's rows from every
+//                    segment, inserts them into an LDS copy of the region and
+//                    stores its tags and slots. A region whose rows would not
+//                    leave it a free slot (a probe's walk ends at one), or a
+//                    capacity outside the LDS range, sets the overflow flag.
+//   k_build_fallback nothing unless the flag is set; then the global CAS
+//                    insert of every row into the scratch's alternate tags and
+//                    slots (cleared by the previous launch), which the header
+//                    then names as the arrays in use.
+
+constexpr int kFinBlock = 1024;
+constexpr int kMaxRegionSlots = 2048;  // LDS region: 4 KiB of tags + 32 KiB of slots
+constexpr int kMinRegionLog2Cap = kLog2Bucket + kLog2Bins;  // a region of at least one bucket
+constexpr int kMaxRegionLog2Cap = 11 + kLog2Bins;            // at most kMaxRegionSlots slots
+
+template <int NC>
+__global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
+                                                          TableHeader* h, int64_t cap_max, int skip) {
+  __shared__ uint32_t hist[kRegionBins];
+  __shared__ uint32_t loc[kRegionBins];
+  __shared__ int64_t ws[kPartBlock / kWave];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kPartRows + (int64_t)tid * kRows;
+  const bool full = r0 + kRows <= n;
+  int64_t v[NC][kRows], k[kRows], pay[kRows];
+  const DCol kc = {keys, 8};
+  load_rows<NC>(P, r0, full, n, v);
+  load4(kc, r0, full, n, k);
+  load4(payload, r0, full, n, pay);
+  if (h->magic != kTableMagic) return;
+  if (blockIdx.x == 0 && tid == 0) h->ovf = 0;  // the previous build's fallback has finished with it
+  if (tid < kRegionBins) hist[tid] = 0;
+  __syncthreads();
+  bool ok[kRows];
+  uint32_t bin[kRows], rank[kRows];
+#pragma unroll
+  for (int i = 0; i < kRows; i++) {
+    ok[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
+    bin[i] = (uint32_t)((mulhash(k[i]) << skip) >> (64 - kLog2Bins));
+    rank[i] = ok[i] ? atomicAdd(&hist[bin[i]], 1u) : 0u;
+  }
+  __syncthreads();
+  const uint32_t cnt = tid < kRegionBins ? hist[tid] : 0u;
+  int64_t excl;
+  const int64_t total = block_excl_scan((int64_t)cnt, &excl, ws);
+  if (tid < kRegionBins) {
+    loc[tid] = (uint32_t)excl;
+    scratch_meta(h, cap_max)[(size_t)blockIdx.x * kRegionBins + tid] = ((uint32_t)excl << 16) | cnt;
+  }
+  if (tid == 0) scratch_block_rows(h, cap_max)[blockIdx.x] = (int32_t)total;
+  __syncthreads();
+  v2i64* seg = reinterpret_cast<v2i64*>(scratch_rows(h, cap_max)) + (size_t)blockIdx.x * kPartRows;
+#pragma unroll
+  for (int i = 0; i < kRows; i++)
+    if (ok[i]) seg[loc[bin[i]] + rank[i]] = v2i64{k[i], pay[i]};
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int64_t cap_max, int nblk, double lf,
+                                                            int skip, uint32_t flags) {
+  __shared__ uint32_t ltag[kMaxRegionSlots / 2];
+  __shared__ v2i64 lslot[kMaxRegionSlots];
+  __shared__ uint32_t lpos[kFinBlock];
+  __shared__ int64_t lsrc[kFinBlock];
+  __shared__ int64_t ws[2 * kFinBlock / kWave];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const uint32_t* meta = scratch_meta(h, cap_max);
+  // the first loads go out before the header check so that they overlap (the
+  // scratch lies inside the caller's buffer either way)
+  const int32_t* brows = scratch_block_rows(h, cap_max);
+  int64_t rb = 0, cj = 0;
+  uint32_t m0 = 0;
+  for (int b = tid; b < nblk; b += kFinBlock) {
+    const uint32_t m = meta[(size_t)b * kRegionBins + j];
+    rb += brows[b];
+    cj += m & 0xffffu;
+    if (b == tid) m0 = m;
+  }
+  if (h->magic != kTableMagic) return;
+  const int64_t rows = block_sum(rb, ws);
+  const int64_t mine = block_sum(cj, ws);  // rows of region j
+  int l = log2cap_for(rows, lf);
+  const bool too_big = ((int64_t)1 << l) > cap_max;
+  if (too_big) {
+    l = 6;
+    while (((int64_t)1 << (l + 1)) <= cap_max) l++;
+  }
+  const bool in_range = l >= kMinRegionLog2Cap && l <= kMaxRegionLog2Cap;
+  const int64_t region_slots = in_range ? (int64_t)1 << (l - kLog2Bins) : 0;
+  const bool fits = in_range && mine <= region_slots - std::max<int64_t>(1, region_slots / 8);
+  if (j == 0 && tid == 0) {
+    h->cap_max = cap_max;
+    h->n = rows;
+    h->log2cap = l;
+    h->skip = skip;
+    h->flags = flags;
+    h->lf = lf;
+    h->log2g = l - kLog2Bucket - kLog2Bins;
+    h->regions = 1;
+    h->alt = 0;
+    if (too_big) latch_error(&h->err, TQ_EFULL);
+  }
+  if (too_big) return;  // TQ_EFULL is latched: nothing is inserted
+  // the alternate tags, for a fallback insert (its launch decides)
+  {
+    v4i32* at = reinterpret_cast<v4i32*>(scratch_alt_tags(h, cap_max));
+    const v4i32 z = {0, 0, 0, 0};
+    const int64_t groups = (int64_t)1 << (l - kLog2Bucket);
+    for (int64_t i = (int64_t)j * kFinBlock + tid; i < groups; i += (int64_t)gridDim.x * kFinBlock) at[i] = z;
+  }
+  if (!fits) {
+    if (tid == 0) atomicOr(&h->ovf, 1);
+    return;
+  }
+  const int log2g = l - kLog2Bucket - kLog2Bins;
+  const int gmask = (1 << log2g) - 1, nslot = kBucket << log2g;
+  for (int i = tid; i < nslot / 2; i += kFinBlock) ltag[i] = 0u;
+  __syncthreads();
+  const v2i64* seg = reinterpret_cast<const v2i64*>(scratch_rows(h, cap_max));
+  bool stuck = false;
+  // kFinBlock source blocks per round: their counts are scanned in LDS, so that
+  // thread i fetches the round's rows i, i + kFinBlock, ... (each found by a
+  // binary search over the scan) with all loads in flight at once
+  for (int base = 0; base < nblk; base += kFinBlock) {
+    const int b = base + tid;
+    const uint32_t m = base == 0 ? m0 : (b < nblk ? meta[(size_t)b * kRegionBins + j] : 0u);
+    int64_t excl;
+    const int64_t total = block_excl_scan((int64_t)(m & 0xffffu), &excl, ws);
+    lpos[tid] = (uint32_t)excl;
+    lsrc[tid] = (int64_t)b * kPartRows + (m >> 16);
+    __syncthreads();
+    for (int64_t i = tid; i < total; i += kFinBlock) {
+      int lo = 0, hi = kFinBlock - 1;  // the last source whose first row is at or before i
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)lpos[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      const v2i64 kv = seg[lsrc[lo] + (i - (int64_t)lpos[lo])];
+      const uint64_t hh = mulhash(kv.x);
+      int bl = (int)(bucket_of(hh, skip, l - kLog2Bucket) & (uint64_t)gmask);
+      const uint32_t tg = hash_tag(hh);
+      const int st = (int)(hh >> 16) & (kBucket - 1);
+      // the region keeps a free slot, so the walk finds one; the bound only
+      // guards against a broken invariant
+      bool done = false;
+      for (int it = 0; it < 4 * nslot + 64 && !done; it++) {
+        uint32_t w[4], zero = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          w[q] = ltag[bl * 4 + q];
+          zero |= (uint32_t)((w[q] & 0xffffu) == 0u) << (2 * q);
+          zero |= (uint32_t)((w[q] >> 16) == 0u) << (2 * q + 1);
+        }
+        if (zero == 0u) {
+          bl = (bl + 1) & gmask;
+          continue;
+        }
+        const uint32_t rot = ((zero >> st) | (zero << (kBucket - st))) & 0xffu;
+        const int slot = (__builtin_ctz(rot) + st) & (kBucket - 1);
+        const int q = slot >> 1;
+        uint32_t cur = w[0];
+        cur = q == 1 ? w[1] : cur;
+        cur = q == 2 ? w[2] : cur;
+        cur = q == 3 ? w[3] : cur;
+        if (atomicCAS(&ltag[bl * 4 + q], cur, cur | (tg << ((slot & 1) * 16))) == cur) {
+          lslot[bl * kBucket + slot] = kv;
+          done = true;
+        }
+      }
+      stuck = stuck || !done;
+    }
+    __syncthreads();
+  }
+  if (stuck) latch_error(&h->err, TQ_EFULL);
+  uint32_t* gw = table_tags(h) + ((size_t)j << log2g) * 4;
+  for (int i = tid; i < nslot / 2; i += kFinBlock) gw[i] = ltag[i];
+  v2i64* gs = reinterpret_cast<v2i64*>(table_slots(h, cap_max)) + ((size_t)j << log2g) * kBucket;
+  for (int i = tid; i < nslot; i += kFinBlock) gs[i] = lslot[i];
+}
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_build_fallback(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
+                                                          TableHeader* h, int64_t cap_max) {
+  if (h->magic != kTableMagic || !h->ovf) return;
+  const int l = h->log2cap, skip = h->skip;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    h->regions = 0;
+    h->alt = 1;
+    h->log2g = l - kLog2Bucket;
+  }
+  uint32_t* words = scratch_alt_tags(h, cap_max);
+  v2i64* slots = reinterpret_cast<v2i64*>(scratch_rows(h, cap_max));
   const DCol kc = {keys, 8};
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
@@ -549,6 +771,19 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   tq_status s = make_plan(&P, filt, nfilt, p, np, nullptr, 0, nullptr, n);
   if (s) return s;
   TableHeader* h = static_cast<TableHeader*>(d_table);
+  DCol pc = {payload.data, payload.type};
+  const int64_t part_grid = std::max<int64_t>(1, (n + kPartRows - 1) / kPartRows);
+  if (part_grid <= part_grid_max(cap_max)) {
+    // the rows' segments fit the scratch area: partition, count, then fill regions (or CAS)
+    TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_part<NC>, dim3((int)part_grid), dim3(kPartBlock), 0, stream,
+                                                  P, d_keys, pc, n, h, cap_max, skip));
+    hipLaunchKernelGGL(k_build_regions, dim3(kRegionBins), dim3(kFinBlock), 0, stream, h, cap_max, (int)part_grid,
+                       load_factor, skip, flags);
+    TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_fallback<NC>, dim3(stream_grid(n, 2)), dim3(kBlock), 0,
+                                                  stream, P, d_keys, pc, n, h, cap_max));
+    TQ_HIP(hipGetLastError());
+    return TQ_OK;
+  }
   const bool count = np > 0 && n > 0;
   Range R = split_rows(std::max<int64_t>(n, 1), kMaxCountBlocks);
   // enough blocks to clear the tags quickly; blocks past the rows count zero
@@ -556,7 +791,6 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   const int count_grid = (int)std::max<int64_t>(R.nblk, clear_blocks);
   TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_count<NC>, dim3(count_grid), dim3(kBlock), 0, stream, P, n, R.per,
                                                 h, cap_max, (int)count));
-  DCol pc = {payload.data, payload.type};
   TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_insert<NC>, dim3(stream_grid(n, 8)), dim3(kBlock), 0, stream, P,
                                                 d_keys, pc, n, h, cap_max, count ? (int64_t)-1 : n, R.nblk, load_factor,
                                                 skip, flags));

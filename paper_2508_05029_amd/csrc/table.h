@@ -116,8 +116,11 @@ struct Probe {
   bool unique;
 
   __device__ __forceinline__ void setup(const TableHeader* h) {
-    setup(table_tags(const_cast<TableHeader*>(h)), table_slots(const_cast<TableHeader*>(h), h->cap_max), h->log2cap,
-          h->skip, (h->flags & TQ_UNIQUE_KEYS) != 0, h->log2g);
+    TableHeader* t = const_cast<TableHeader*>(h);
+    const bool alt = h->alt != 0;  // a fallback build used the scratch arrays
+    setup(alt ? scratch_alt_tags(t, h->cap_max) : table_tags(t),
+          alt ? scratch_rows(t, h->cap_max) : table_slots(t, h->cap_max), h->log2cap, h->skip,
+          (h->flags & TQ_UNIQUE_KEYS) != 0, h->log2g);
   }
 
   // log2g < 0: one region spanning the table

@@ -41,9 +41,17 @@ def test_status_strings_and_version():
 
 def test_buffer_sizes():
     # 227,600 filtered dimension rows at load factor 0.5 -> 2^19 slots
+    # header | partial counts | tags | slots | build scratch: rows per
+    # partitioning block (one block per 2048 slots), each block's (offset,
+    # count) per region, one row segment per slot, and alternate tags
     part = 2048 * 8
-    assert tq.join_table_bytes(227_600, 0.5) == 256 + part + (1 << 19) * 2 + (1 << 19) * 16
-    assert tq.join_table_bytes(0, 0.5) == 256 + part + 256 + 64 * 16
+
+    def scratch(cap):
+        g = max(1, cap // 2048)
+        return (g * 4 + 255) // 256 * 256 + g * 256 * 4 + cap * 16 + (cap * 2 + 255) // 256 * 256
+
+    assert tq.join_table_bytes(227_600, 0.5) == 256 + part + (1 << 19) * 2 + (1 << 19) * 16 + scratch(1 << 19)
+    assert tq.join_table_bytes(0, 0.5) == 256 + part + 256 + 64 * 16 + scratch(64)
     assert tq.join_table_bytes(10, 0.95) == 0  # load factor above 0.9 is refused
     assert tq.groupby_state_bytes(25, 1) == 256 + 1024 * 25 * 2 * 8  # one private row per workgroup slot
     assert tq.groupby_state_bytes(65536, 1) == 256 + 65536 * 2 * 8

@@ -202,6 +202,99 @@ def test_join_same_slot_collisions():
     assert m == total == 2000 and got == list(zip(pr.tolist(), br.tolist()))
 
 
+def _table_header(table):
+    """(regions, alt, log2g, log2cap) from the table header: whether the last
+    build filled the table region by region in LDS, whether a fallback insert
+    built it into the scratch's alternate arrays, and the probe's wrap span."""
+    h = table[:64].cpu().numpy()
+    i32 = lambda o: int(h[o:o + 4].view(np.int32)[0])  # noqa: E731
+    return i32(52), i32(56), i32(48), i32(16)
+
+
+@pytest.mark.parametrize("case", ["regions", "cas_large_table", "cas_region_overflow", "host_fallback"])
+def test_join_build_paths(case):
+    """Each build path gives the oracle's pairs, and the header says which ran:
+    regions (filled in LDS, probing wraps inside a region of 2^(log2cap-11)
+    buckets), or the global CAS insert (wrapping over the whole table): into
+    the alternate arrays when the table is too large for an LDS region or some
+    region receives more rows than it can hold with a free slot, or into the
+    main arrays (with a counting pass first) when the rows' segments do not
+    fit the scratch area."""
+    rng = np.random.default_rng(11)
+    filt = ()
+    if case == "regions":
+        bk = rng.permutation(100_000).astype(np.int64)
+        nb_table, want_regions = len(bk), 1
+    elif case == "cas_large_table":
+        bk = rng.permutation(600_000).astype(np.int64)  # 2^21 slots at 0.5
+        nb_table, want_regions = len(bk), 0
+    elif case == "cas_region_overflow":
+        bk = np.concatenate([np.full(3000, 7, np.int64), rng.integers(10, 400_000, 17_000)])
+        rng.shuffle(bk)
+        nb_table, want_regions = len(bk), 0
+    else:
+        # a selective filter over many rows into a table sized for the survivors
+        bk = rng.permutation(40_000).astype(np.int64)
+        filt = (bk % 40 == 0)
+        nb_table, want_regions = int(filt.sum()), 0
+    pk = np.concatenate([bk[:5000], rng.integers(-1000, 700_000, 30_000)])
+    n = len(bk)
+    say(f"build path {case} n={n}")
+    d_bk = torch.from_numpy(bk).to(DEV)
+    pay = torch.arange(n, dtype=torch.int64, device=DEV)
+    table = torch.empty(tq.join_table_bytes(nb_table, 0.5), dtype=torch.uint8, device=DEV)
+    tq.join_table_init(table)
+    if len(filt):
+        f = torch.from_numpy(filt.astype(np.int32)).to(DEV)
+        tq.join_build(table, d_bk, pay, n, filt_cols=[f], ps=[(0, 1, 1)], load_factor=0.5)
+        keep = np.nonzero(filt)[0]
+    else:
+        tq.join_build(table, d_bk, pay, n, load_factor=0.5)
+        keep = np.arange(n)
+    tq.check(table)
+    regions, alt, log2g, log2cap = _table_header(table)
+    assert regions == want_regions
+    assert alt == (1 if case.startswith("cas") else 0)  # the fallback insert uses the alternate arrays
+    assert log2g == (log2cap - 11 if regions else log2cap - 3)
+    total, pr, br = oracle.join_pairs(bk[keep], pk)
+    cap = max(total, 1)
+    rows = torch.empty(cap, dtype=torch.int64, device=DEV)
+    bro = torch.empty(cap, dtype=torch.int64, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+    tq.join_probe(table, torch.from_numpy(pk).to(DEV), len(pk), out_row=rows, out_payload=bro, capacity=cap,
+                  out_count=cnt)
+    tq.check(table)
+    assert int(cnt.item()) == total
+    got = sorted(zip(rows[:total].cpu().tolist(), bro[:total].cpu().tolist()))
+    # the oracle's build rows are indices into bk[keep]; the payload is the row of bk
+    assert got == sorted(zip(pr.tolist(), keep[br].tolist()))
+
+
+def test_join_build_repeated_into_one_table():
+    """Builds of different sizes into one buffer, each probed: the build's
+    tickets and counts start clean every time, whichever path ran before."""
+    rng = np.random.default_rng(12)
+    table = torch.empty(tq.join_table_bytes(600_000, 0.5), dtype=torch.uint8, device=DEV)
+    tq.join_table_init(table)
+    for n in (50_000, 600_000, 3, 0, 200_000, 1):
+        bk = rng.permutation(max(n, 1) * 2)[:n].astype(np.int64)
+        pk = rng.integers(0, max(n, 1) * 2, 20_000).astype(np.int64)
+        say(f"repeated build n={n}")
+        pay = torch.arange(max(n, 1), dtype=torch.int64, device=DEV)
+        tq.join_build(table, torch.from_numpy(bk).to(DEV) if n else pay, pay, n, load_factor=0.5)
+        total, pr, br = oracle.join_pairs(bk, pk)
+        cap = max(total, 1)
+        rows = torch.empty(cap, dtype=torch.int64, device=DEV)
+        bro = torch.empty(cap, dtype=torch.int64, device=DEV)
+        cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+        tq.join_probe(table, torch.from_numpy(pk).to(DEV), len(pk), out_row=rows, out_payload=bro, capacity=cap,
+                      out_count=cnt)
+        tq.check(table)
+        assert int(cnt.item()) == total
+        got = sorted(zip(rows[:total].cpu().tolist(), bro[:total].cpu().tolist()))
+        assert got == sorted(zip(pr.tolist(), br.tolist()))
+
+
 def test_join_table_too_small_latches_full():
     table = torch.empty(tq.join_table_bytes(100, 0.5), dtype=torch.uint8, device=DEV)
     tq.join_table_init(table)
