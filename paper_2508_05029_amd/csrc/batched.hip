@@ -137,6 +137,7 @@ __global__ __launch_bounds__(256) void k_batched_prep(WorkHeader* hdr, const BIn
       th->regions = 0;
       th->alt = 0;
       th->ovf = 0;
+      th->bloom_log2w = 0;
       StateHeader* sh = static_cast<StateHeader*>(I.state);
       sh->magic = kStateMagic;
       sh->err = 0;

@@ -109,6 +109,7 @@ struct TableHeader {
   int32_t regions;   // 1: the last build filled each region in LDS; 0: it inserted with global CAS
   int32_t alt;       // 1: the tags and slots in use are the build scratch's (see scratch_alt_tags)
   int32_t ovf;       // set during a build when a region's rows do not fit it
+  int32_t bloom_log2w;  // the build's Bloom filter has 2^bloom_log2w 64-bit words; 0: none
 };
 static_assert(sizeof(TableHeader) <= kHeaderBytes, "header");
 
@@ -150,7 +151,9 @@ __host__ __device__ inline int64_t* table_slots(void* t, int64_t cap_max) {
 // block's passing rows, grouped by region, at block * kPartRows) | uint16
 // alt_tags[cap_max], where max_grid = part_grid_max(cap_max). When a region
 // overflows, the fallback insert builds the whole table into alt_tags and
-// the row area (which then serves as the slots).
+// the row area (which then serves as the slots). Then uint64
+// bloom[bloom_words_max(cap_max)]: a region build's Bloom filter, one block of
+// 2^bloom_log2w / kRegionBins words per region.
 constexpr int kRegionBins = 256;  // the top 8 bits of a bucket index select its region
 constexpr int kLog2Bins = 8;
 constexpr int kPartBlock = 512;
@@ -161,9 +164,16 @@ __host__ __device__ inline int64_t part_grid_max(int64_t cap_max) {
 __host__ __device__ inline size_t block_rows_bytes(int64_t cap_max) {
   return ((size_t)part_grid_max(cap_max) * 4 + 255) & ~(size_t)255;
 }
+// Bloom words for a table of `cap` slots: two bits per slot, between one word
+// per region and 128 KiB (the LDS a probe workgroup gives it).
+constexpr int kBloomWordsMax = 16384;
+__host__ __device__ inline int64_t bloom_words_max(int64_t cap) {
+  const int64_t w = cap / 32;
+  return w < kRegionBins ? kRegionBins : (w > kBloomWordsMax ? kBloomWordsMax : w);
+}
 __host__ __device__ inline size_t scratch_bytes(int64_t cap_max) {
   return block_rows_bytes(cap_max) + (size_t)part_grid_max(cap_max) * kRegionBins * 4 + (size_t)cap_max * 16 +
-         table_tag_bytes(cap_max);
+         table_tag_bytes(cap_max) + (size_t)bloom_words_max(cap_max) * 8;
 }
 __host__ __device__ inline char* table_scratch(void* t, int64_t cap_max) {
   return reinterpret_cast<char*>(table_slots(t, cap_max)) + (size_t)cap_max * 16;
@@ -179,6 +189,9 @@ __host__ __device__ inline int64_t* scratch_rows(void* t, int64_t cap_max) {
 }
 __host__ __device__ inline uint32_t* scratch_alt_tags(void* t, int64_t cap_max) {
   return reinterpret_cast<uint32_t*>(scratch_rows(t, cap_max) + (size_t)cap_max * 2);
+}
+__host__ __device__ inline uint64_t* scratch_bloom(void* t, int64_t cap_max) {
+  return reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(scratch_alt_tags(t, cap_max)) + table_tag_bytes(cap_max));
 }
 __host__ __device__ inline int64_t* state_data(void* s) {
   return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(s) + kHeaderBytes);
@@ -199,6 +212,22 @@ __device__ __forceinline__ uint32_t hash_tag(uint64_t h) {
 // Home bucket: the high bits of the hash below the `skip` partition bits.
 __device__ __forceinline__ uint64_t bucket_of(uint64_t h, int skip, int log2buckets) {
   return (h << skip) >> (64 - log2buckets);
+}
+
+// Bloom filter of a region-built table: the key's region (as for its bucket)
+// selects a block of 2^(log2w - kLog2Bins) words; a second multiplicative
+// hash picks the word in the block (its top bits) and three bits of it.
+constexpr uint64_t kFib2 = 0xD6E8FEB86659FD93ull;
+__device__ __forceinline__ uint32_t bloom_word(uint64_t h, int64_t k, int skip, int log2w) {
+  const uint32_t region = (uint32_t)((h << skip) >> (64 - kLog2Bins));
+  const int sub_bits = log2w - kLog2Bins;
+  const uint64_t h2 = (uint64_t)k * kFib2;
+  const uint32_t sub = sub_bits ? (uint32_t)(h2 >> (64 - sub_bits)) : 0u;
+  return (region << sub_bits) | sub;
+}
+__device__ __forceinline__ uint64_t bloom_bits(int64_t k) {
+  const uint64_t h2 = (uint64_t)k * kFib2;
+  return (1ull << ((h2 >> 52) & 63)) | (1ull << ((h2 >> 46) & 63)) | (1ull << ((h2 >> 40) & 63));
 }
 
 template <typename T>
@@ -269,6 +298,28 @@ __device__ __forceinline__ void load_rows(const RowPlan& P, int64_t r0, bool ful
   }
 }
 
+// As load_rows for plan columns that are all 8 bytes wide and rows that all
+// exist: one 16-byte load per column and row pair, with no branch between the
+// loads (a branch on the width puts a wait for each load inside it).
+template <int NC, int R = kRows>
+__device__ __forceinline__ void load_rows64(const RowPlan& P, int64_t r0, int64_t (&v)[NC][R]) {
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    if (c < P.ncol) {
+      const v2i64* q = reinterpret_cast<const v2i64*>(static_cast<const int64_t*>(P.col[c].p) + r0);
+#pragma unroll
+      for (int h = 0; h < R / 2; h++) {
+        const v2i64 a = ntload(q + h);
+        v[c][2 * h] = a.x;
+        v[c][2 * h + 1] = a.y;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < R; i++) v[c][i] = 0;
+    }
+  }
+}
+
 // Value of the column selected by `mask` (one bit, uniform) for row i; 0 if mask is 0.
 template <int NC, int R>
 __device__ __forceinline__ int64_t pick(const int64_t (&v)[NC][R], int i, uint32_t mask) {
@@ -278,15 +329,16 @@ __device__ __forceinline__ int64_t pick(const int64_t (&v)[NC][R], int i, uint32
   return r;
 }
 
+// A rolled loop over the plan's predicates: unrolled over TQ_MAX_PREDS, the
+// bounds of all of them stay live in scalar registers across a kernel's main
+// loop and spill into vector lanes that every row then reads back.
 template <int NC, int R>
 __device__ __forceinline__ bool eval_preds(const RowPlan& P, const int64_t (&v)[NC][R], int i) {
   bool ok = true;
-#pragma unroll
-  for (int j = 0; j < TQ_MAX_PREDS; j++) {
-    if (j < P.np) {
-      int64_t x = pick<NC, R>(v, i, P.pred[j].mask);
-      ok = ok && (x >= P.pred[j].lo) && (x <= P.pred[j].hi);
-    }
+#pragma unroll 1
+  for (int j = 0; j < P.np; j++) {
+    int64_t x = pick<NC, R>(v, i, P.pred[j].mask);
+    ok = ok && (x >= P.pred[j].lo) && (x <= P.pred[j].hi);
   }
   return ok;
 }

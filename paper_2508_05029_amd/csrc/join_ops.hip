@@ -79,6 +79,7 @@ __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
   h->regions = 0;
   h->alt = 0;
   h->ovf = 0;
+  h->bloom_log2w = 0;
 }
 
 // ------------------------------------------------------------------ build
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_
     h->log2g = l - kLog2Bucket;
     h->regions = 0;
     h->alt = 0;
+    h->bloom_log2w = 0;
     if (full) latch_error(&h->err, TQ_EFULL);
   }
   if (full) return;  // does not fit: TQ_EFULL is latched, nothing is inserted
@@ -235,6 +237,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   __shared__ uint32_t lpos[kFinBlock];
   __shared__ int64_t lsrc[kFinBlock];
   __shared__ int64_t ws[2 * kFinBlock / kWave];
+  __shared__ unsigned long long lbloom[kBloomWordsMax / kRegionBins];
   const int j = blockIdx.x, tid = threadIdx.x;
   const uint32_t* meta = scratch_meta(h, cap_max);
   // the first loads go out before the header check so that they overlap (the
@@ -260,6 +263,8 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   const bool in_range = l >= kMinRegionLog2Cap && l <= kMaxRegionLog2Cap;
   const int64_t region_slots = in_range ? (int64_t)1 << (l - kLog2Bins) : 0;
   const bool fits = in_range && mine <= region_slots - std::max<int64_t>(1, region_slots / 8);
+  int log2w = 0;  // Bloom words (log2) for this capacity
+  while (((int64_t)1 << (log2w + 1)) <= bloom_words_max((int64_t)1 << l)) log2w++;
   if (j == 0 && tid == 0) {
     h->cap_max = cap_max;
     h->n = rows;
@@ -270,6 +275,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     h->log2g = l - kLog2Bucket - kLog2Bins;
     h->regions = 1;
     h->alt = 0;
+    h->bloom_log2w = log2w;
     if (too_big) latch_error(&h->err, TQ_EFULL);
   }
   if (too_big) return;  // TQ_EFULL is latched: nothing is inserted
@@ -286,7 +292,9 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   }
   const int log2g = l - kLog2Bucket - kLog2Bins;
   const int gmask = (1 << log2g) - 1, nslot = kBucket << log2g;
+  const int nbw = 1 << (log2w - kLog2Bins);  // Bloom words of this region
   for (int i = tid; i < nslot / 2; i += kFinBlock) ltag[i] = 0u;
+  if (tid < nbw) lbloom[tid] = 0ull;
   __syncthreads();
   const v2i64* seg = reinterpret_cast<const v2i64*>(scratch_rows(h, cap_max));
   bool stuck = false;
@@ -310,6 +318,8 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
       }
       const v2i64 kv = seg[lsrc[lo] + (i - (int64_t)lpos[lo])];
       const uint64_t hh = mulhash(kv.x);
+      atomicOr(&lbloom[bloom_word(hh, kv.x, skip, log2w) & (uint32_t)(nbw - 1)],
+               (unsigned long long)bloom_bits(kv.x));
       int bl = (int)(bucket_of(hh, skip, l - kLog2Bucket) & (uint64_t)gmask);
       const uint32_t tg = hash_tag(hh);
       const int st = (int)(hh >> 16) & (kBucket - 1);
@@ -349,6 +359,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   for (int i = tid; i < nslot / 2; i += kFinBlock) gw[i] = ltag[i];
   v2i64* gs = reinterpret_cast<v2i64*>(table_slots(h, cap_max)) + ((size_t)j << log2g) * kBucket;
   for (int i = tid; i < nslot; i += kFinBlock) gs[i] = lslot[i];
+  if (tid < nbw) scratch_bloom(h, cap_max)[(size_t)j * nbw + tid] = lbloom[tid];
 }
 
 template <int NC>
@@ -360,6 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_build_fallback(RowPlan P, const int6
     h->regions = 0;
     h->alt = 1;
     h->log2g = l - kLog2Bucket;
+    h->bloom_log2w = 0;
   }
   uint32_t* words = scratch_alt_tags(h, cap_max);
   v2i64* slots = reinterpret_cast<v2i64*>(scratch_rows(h, cap_max));
@@ -451,36 +463,53 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const 
 // wave walks 64 queued rows at a time to the end of their chains. A queued row
 // starts again from its home bucket and nothing of it was aggregated before,
 // so every match is counted exactly once.
+//
+// With BLOOM, the workgroup holds the build's Bloom filter in LDS (one
+// workgroup per CU, for its 128 KiB) and a row the filter rejects is not live:
+// its tag load goes to the shared dummy line, so a probe key the build does
+// not hold costs no table traffic. A table without a filter (a fallback
+// build) passes every row.
 #ifndef TQ_PIPE_BLOCKS_PER_CU
 #define TQ_PIPE_BLOCKS_PER_CU 2
 #endif
 constexpr int kPipeBlocksPerCU = TQ_PIPE_BLOCKS_PER_CU;
 constexpr int kPipeRows = 2;
-constexpr int kPipeQ = 256;  // queue entries per wave: holds 63 + 128 between drains
+constexpr int kPipeQ = 128;  // queue entries per wave: below 64 at a tile's start, each row adds at most 64
+constexpr int kBloomPipeBlock = 1024;  // one workgroup per CU beside the filter: 16 waves
 constexpr size_t kMaxPipeLds = 64 * 1024;  // dynamic LDS of a launch without a per-kernel attribute
+constexpr size_t kCuLds = 160 * 1024;
+constexpr size_t kMaxBloomPipeLds = kCuLds - (size_t)kBloomWordsMax * 8;  // dynamic LDS beside the filter
 
 template <int NE>
 struct PipeRows {
   static constexpr int R = kPipeRows;
   int64_t k[R], e[R][NE], b[R];
+  int64_t row;  // the tile's first row
   uint32_t tg[R];
   bool live[R];
 };
 
-template <int MODE, int NC, int NE>
-__global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(const TableHeader* h, const int64_t* pkeys,
-                                                                            int64_t n, RowPlan P, AggTarget T,
-                                                                            int agg_lds) {
+template <int MODE, int NC, int NE, bool BLOOM>
+__global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kPipeBlocksPerCU) void k_probe_pipe(const TableHeader* h,
+                                                                                        const int64_t* pkeys, int64_t n,
+                                                                                        RowPlan P, AggTarget T,
+                                                                                        int agg_lds) {
   constexpr int R = kPipeRows;
+  __shared__ uint64_t bloom[BLOOM ? kBloomWordsMax : 1];
   extern __shared__ __align__(16) char smem[];
   if (h->magic != kTableMagic) return;
   if (!state_matches(T)) return;
+  const int log2w = BLOOM ? h->bloom_log2w : 0;
+  const int nbw = log2w ? 1 << log2w : 0;
+  if (BLOOM) {
+    const uint64_t* gb = scratch_bloom(const_cast<TableHeader*>(h), h->cap_max);
+    for (int i = threadIdx.x; i < nbw; i += blockDim.x) bloom[i] = gb[i];
+  }
   LdsAgg<MODE> agg;
   agg.defer = true;
   agg.init(T, smem);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  int64_t* qk = reinterpret_cast<int64_t*>(smem + agg_lds) + (int64_t)wave * kPipeQ * (1 + NE);
-  int64_t* qe = qk + kPipeQ;  // sum j of entry x at qe[j * kPipeQ + x]
+  int64_t* qrow = reinterpret_cast<int64_t*>(smem + agg_lds) + (int64_t)wave * kPipeQ;  // queued row numbers
   __syncthreads();
   Probe pr;
   pr.setup(h);
@@ -491,7 +520,8 @@ __global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(cons
   for (int c = 0; c < NC; c++) ccol[c] = c < P.ncol ? static_cast<const v2i64*>(P.col[c].p) : kcol;
   int qh = 0, qn = 0;  // queue head and length (the same in every lane)
 
-  // Walks `cnt` (<= 64) queued rows from the head, one per lane.
+  // Walks `cnt` (<= 64) queued rows from the head, one per lane (their key and
+  // columns are read again: queued rows are rare).
   auto drain = [&](int cnt) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int x = (qh + lane) & (kPipeQ - 1);
@@ -500,9 +530,13 @@ __global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(cons
 #pragma unroll
     for (int j = 0; j < NE; j++) e1[j] = 0;
     if (ok1[0]) {
-      k1[0] = qk[x];
+      const int64_t row = qrow[x];
+      int64_t v1[NC][1];
 #pragma unroll
-      for (int j = 0; j < NE; j++) e1[j] = qe[j * kPipeQ + x];
+      for (int c = 0; c < NC; c++) v1[c][0] = c < P.ncol ? reinterpret_cast<const int64_t*>(ccol[c])[row] : 0;
+      k1[0] = pkeys[row];
+#pragma unroll
+      for (int j = 0; j < NE; j++) e1[j] = j < P.ne ? eval_expr<NC>(P.expr[j], v1, 0) : 0;
     }
     pr.walk(ok1, k1, [&](const bool (&hit)[1], const int64_t (&pay)[1]) {
       if (hit[0]) agg.add(T, pay[0], e1, P.ne);
@@ -516,20 +550,20 @@ __global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(cons
     const int64_t stride = (int64_t)gridDim.x * blockDim.x * R;
     const int64_t wbase = ((int64_t)blockIdx.x * blockDim.x + wave * kWave) * R;  // the wave's first row
     int64_t r = wbase + lane * R;
-    v2i64 cv[NC], ck;       // columns of the tile 3 ahead
+    v2i64 cva[NC], cka, cvb[NC], ckb;  // columns of two tiles ahead (alternating sets)
     v4i32 tw[R];            // tags of the tile 1 ahead
     v2i64 kv[R];            // candidate slots of the current tile
     PipeRows<NE> tt, st;    // rows whose tags (tt) / slots (st) are in flight
     uint32_t sm[R];         // st: candidate mask of the home bucket
     bool sempty[R];         // st: the home bucket has a free slot
 
-    auto load_cols = [&](int64_t rt) {  // a tile beyond the full tiles reads tile 0 instead
+    auto load_cols = [&](v2i64 (&cv)[NC], v2i64& ck, int64_t rt) {  // a tile past the last reads tile 0
       const int64_t q = (rt < n_main ? rt : 0) / R;
       ck = ntload(kcol + q);
 #pragma unroll
       for (int c = 0; c < NC; c++) cv[c] = ntload(ccol[c] + q);
     };
-    auto cols_to_tags = [&](int64_t rt) {  // cv, ck -> tt; tag loads
+    auto cols_to_tags = [&](const v2i64 (&cv)[NC], const v2i64& ck, int64_t rt) {  // cv, ck -> tt; tag loads
       int64_t v[NC][R];
 #pragma unroll
       for (int c = 0; c < NC; c++) {
@@ -537,6 +571,7 @@ __global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(cons
         v[c][1] = cv[c].y;
       }
       const int64_t kk[R] = {ck.x, ck.y};
+      tt.row = rt;
 #pragma unroll
       for (int i = 0; i < R; i++) {
         tt.live[i] = (rt < n_main) && eval_preds<NC>(P, v, i);
@@ -546,6 +581,10 @@ __global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(cons
         const uint64_t hh = mulhash(kk[i]);
         tt.b[i] = (int64_t)bucket_of(hh, pr.skip, pr.log2b);
         tt.tg[i] = hash_tag(hh);
+        if (BLOOM && nbw) {  // a key the filter rejects is not in the build
+          const uint64_t m = bloom_bits(kk[i]);
+          tt.live[i] = tt.live[i] && (bloom[bloom_word(hh, kk[i], pr.skip, log2w)] & m) == m;
+        }
       }
 #pragma unroll
       for (int i = 0; i < R; i++) tw[i] = pr.groups[tt.live[i] ? tt.b[i] : 0];
@@ -560,21 +599,8 @@ __global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(cons
 #pragma unroll
       for (int i = 0; i < R; i++) kv[i] = pr.slots[sm[i] ? st.b[i] * kBucket + __builtin_ctz(sm[i]) : 0];
     };
-
-    // prologue: tile 0 to its slot loads, tile 1 to its tag loads, tile 2's columns requested
-    load_cols(r);
-    cols_to_tags(r);
-    asm volatile("" ::: "memory");
-    load_cols(r + stride);
-    asm volatile("" ::: "memory");
-    tags_to_slots();
-    asm volatile("" ::: "memory");
-    cols_to_tags(r + stride);
-    asm volatile("" ::: "memory");
-    load_cols(r + 2 * stride);
-    asm volatile("" ::: "memory");
-    for (int64_t w0 = wbase; w0 < n_main; w0 += stride, r += stride) {
-      // (a) finish this tile from its slots (before any register they live in is reloaded)
+    // (a) finish the current tile from its slots (before any register they live in is reloaded)
+    auto finish = [&]() {
 #pragma unroll
       for (int i = 0; i < R; i++) {
         const bool cand = sm[i] != 0u;
@@ -590,24 +616,53 @@ __global__ __launch_bounds__(kAggBlock, kPipeBlocksPerCU) void k_probe_pipe(cons
             const int rank =
                 __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             const int x = (qh + qn + rank) & (kPipeQ - 1);
-            qk[x] = st.k[i];
-#pragma unroll
-            for (int j = 0; j < NE; j++) qe[j * kPipeQ + x] = st.e[i][j];
+            qrow[x] = st.row + i;
           }
           qn += __popcll(bal);
+          // keep room for the next row's 64 (rare: the loads of later tiles wait with it)
+          if (i + 1 < R && qn >= kWave) drain(kWave);
         }
       }
-      // (b) tile j+1: tags -> slot loads; (c) tile j+2: columns -> tag loads; (d) tile j+3 columns.
-      // The empty asm statements keep each stage's loads where they are: the
-      // compiler would otherwise merge the last loads with the prologue's and
-      // issue them at the top of the next iteration, after the slot loads.
+    };
+
+    // prologue: tile 0 to its slot loads, tile 1 to its tag loads, tiles 2
+    // and 3's columns requested
+    load_cols(cva, cka, r);
+    cols_to_tags(cva, cka, r);
+    asm volatile("" ::: "memory");
+    load_cols(cvb, ckb, r + stride);
+    asm volatile("" ::: "memory");
+    tags_to_slots();
+    asm volatile("" ::: "memory");
+    cols_to_tags(cvb, ckb, r + stride);
+    asm volatile("" ::: "memory");
+    load_cols(cva, cka, r + 2 * stride);
+    asm volatile("" ::: "memory");
+    load_cols(cvb, ckb, r + 3 * stride);
+    asm volatile("" ::: "memory");
+    // Two tiles per pass, one per column set, so that each set's loads have
+    // two tiles' time to arrive. Per tile: (a) finish it; (b) the next tile's
+    // tags -> slot loads; (c) the tile two ahead: columns -> tag loads; (d)
+    // request the columns four ahead. The empty asm statements keep each
+    // stage's loads where they are: the compiler would otherwise merge them
+    // with later ones, after the loads they must precede. A second tile past
+    // the wave's last reads tile 0 and is not live.
+    for (int64_t w0 = wbase; w0 < n_main; w0 += 2 * stride, r += 2 * stride) {
+      finish();
       tags_to_slots();
       asm volatile("" ::: "memory");
-      cols_to_tags(r + 2 * stride);
+      cols_to_tags(cva, cka, r + 2 * stride);
       asm volatile("" ::: "memory");
-      load_cols(r + 3 * stride);
+      load_cols(cva, cka, r + 4 * stride);
       asm volatile("" ::: "memory");
-      // queued rows are walked here, after this iteration's loads are on their way
+      while (qn >= kWave) drain(kWave);  // queued rows are walked after this tile's loads are on their way
+      finish();
+      tags_to_slots();
+      asm volatile("" ::: "memory");
+      cols_to_tags(cvb, ckb, r + 3 * stride);
+      asm volatile("" ::: "memory");
+      load_cols(cvb, ckb, r + 5 * stride);
+      asm volatile("" ::: "memory");
       while (qn >= kWave) drain(kWave);
     }
   }
@@ -819,16 +874,26 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
     bool all64 = true;
     for (int c = 0; c < P.ncol; c++) all64 = all64 && P.col[c].w == 8;
     const int nq = ne_bucket(agg->nsum);
-    const size_t pipe_lds = (lds + 15) / 16 * 16 + (size_t)(kAggBlock / kWave) * kPipeQ * (1 + nq) * 8;
+    const size_t agg_lds16 = (lds + 15) / 16 * 16;
+    const size_t pipe_lds = agg_lds16 + (size_t)(kAggBlock / kWave) * kPipeQ * 8;
+    const size_t bloom_lds = agg_lds16 + (size_t)(kBloomPipeBlock / kWave) * kPipeQ * 8;
     if (all64 && nq <= 2 && pipe_lds <= kMaxPipeLds) {
-      const int64_t want = (n + (int64_t)kAggBlock * kPipeRows - 1) / ((int64_t)kAggBlock * kPipeRows);
-      const int64_t cap = std::min<int64_t>(kAggRows, (int64_t)kPipeBlocksPerCU * device_cu_count());
-      dim3 grid((int)std::max<int64_t>(1, std::min(want, cap))), block(kAggBlock);
-      const int agg_lds = (int)((lds + 15) / 16 * 16);
+      // with the build's Bloom filter in LDS when it fits beside the queues and
+      // the group-by (one workgroup of 16 waves per CU), else without (two of 8)
+      const bool bloom = bloom_lds <= kMaxBloomPipeLds;
+      const int threads = bloom ? kBloomPipeBlock : kAggBlock;
+      const int64_t want = (n + (int64_t)threads * kPipeRows - 1) / ((int64_t)threads * kPipeRows);
+      const int64_t cap = std::min<int64_t>(kAggRows, (int64_t)(bloom ? 1 : kPipeBlocksPerCU) * device_cu_count());
+      dim3 grid((int)std::max<int64_t>(1, std::min(want, cap))), block(threads);
+      const int agg_lds = (int)agg_lds16;
       TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE, if constexpr (NE <= 2) {
-        const size_t q = (size_t)(kAggBlock / kWave) * kPipeQ * (1 + NE) * 8;
-        hipLaunchKernelGGL((k_probe_pipe<M, NC, NE>), grid, block, agg_lds + q, stream, h, d_probe_keys, n, P, T,
-                           agg_lds);
+        const size_t q = (size_t)(threads / kWave) * kPipeQ * 8;
+        if (bloom)
+          hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, true>), grid, block, agg_lds + q, stream, h, d_probe_keys, n,
+                             P, T, agg_lds);
+        else
+          hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, false>), grid, block, agg_lds + q, stream, h, d_probe_keys, n,
+                             P, T, agg_lds);
       });
     } else {
       dim3 grid(agg_grid(n)), block(kAggBlock);

@@ -43,12 +43,14 @@ def test_buffer_sizes():
     # 227,600 filtered dimension rows at load factor 0.5 -> 2^19 slots
     # header | partial counts | tags | slots | build scratch: rows per
     # partitioning block (one block per 2048 slots), each block's (offset,
-    # count) per region, one row segment per slot, and alternate tags
+    # count) per region, one row segment per slot, alternate tags, and the
+    # Bloom filter
     part = 2048 * 8
 
     def scratch(cap):
         g = max(1, cap // 2048)
-        return (g * 4 + 255) // 256 * 256 + g * 256 * 4 + cap * 16 + (cap * 2 + 255) // 256 * 256
+        bloom_words = min(max(cap // 32, 256), 16384)  # two bits per slot, at most 128 KiB
+        return (g * 4 + 255) // 256 * 256 + g * 256 * 4 + cap * 16 + (cap * 2 + 255) // 256 * 256 + bloom_words * 8
 
     assert tq.join_table_bytes(227_600, 0.5) == 256 + part + (1 << 19) * 2 + (1 << 19) * 16 + scratch(1 << 19)
     assert tq.join_table_bytes(0, 0.5) == 256 + part + 256 + 64 * 16 + scratch(64)

@@ -203,12 +203,13 @@ def test_join_same_slot_collisions():
 
 
 def _table_header(table):
-    """(regions, alt, log2g, log2cap) from the table header: whether the last
-    build filled the table region by region in LDS, whether a fallback insert
-    built it into the scratch's alternate arrays, and the probe's wrap span."""
-    h = table[:64].cpu().numpy()
+    """(regions, alt, log2g, log2cap, bloom_log2w) from the table header:
+    whether the last build filled the table region by region in LDS, whether a
+    fallback insert built it into the scratch's alternate arrays, the probe's
+    wrap span, and the size of the Bloom filter a region build leaves."""
+    h = table[:72].cpu().numpy()
     i32 = lambda o: int(h[o:o + 4].view(np.int32)[0])  # noqa: E731
-    return i32(52), i32(56), i32(48), i32(16)
+    return i32(52), i32(56), i32(48), i32(16), i32(64)
 
 
 @pytest.mark.parametrize("case", ["regions", "cas_large_table", "cas_region_overflow", "host_fallback"])
@@ -252,10 +253,12 @@ def test_join_build_paths(case):
         tq.join_build(table, d_bk, pay, n, load_factor=0.5)
         keep = np.arange(n)
     tq.check(table)
-    regions, alt, log2g, log2cap = _table_header(table)
+    regions, alt, log2g, log2cap, bloom_log2w = _table_header(table)
     assert regions == want_regions
     assert alt == (1 if case.startswith("cas") else 0)  # the fallback insert uses the alternate arrays
     assert log2g == (log2cap - 11 if regions else log2cap - 3)
+    # two filter bits per slot, 256 to 16384 words; only a region build has one
+    assert bloom_log2w == (min(max(log2cap - 5, 8), 14) if regions else 0)
     total, pr, br = oracle.join_pairs(bk[keep], pk)
     cap = max(total, 1)
     rows = torch.empty(cap, dtype=torch.int64, device=DEV)
