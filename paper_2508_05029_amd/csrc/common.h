@@ -146,8 +146,9 @@ __host__ __device__ inline int64_t* table_slots(void* t, int64_t cap_max) {
                                     table_tag_bytes(cap_max));
 }
 // Region build scratch, after the slots, sized by the capacity: int32
-// block_rows[max_grid] | uint32 meta[max_grid][kRegionBins] ((offset << 16) |
-// count of one block's rows in each region) | {key, payload}[cap_max] (each
+// block_rows[max_grid] | uint32 meta[kRegionBins][max_grid] ((offset << 16) |
+// count of one block's rows in each region, region-major so that a region's
+// counts over the blocks are contiguous) | {key, payload}[cap_max] (each
 // block's passing rows, grouped by region, at block * kPartRows) | uint16
 // alt_tags[cap_max], where max_grid = part_grid_max(cap_max). When a region
 // overflows, the fallback insert builds the whole table into alt_tags and
@@ -164,16 +165,17 @@ __host__ __device__ inline int64_t part_grid_max(int64_t cap_max) {
 __host__ __device__ inline size_t block_rows_bytes(int64_t cap_max) {
   return ((size_t)part_grid_max(cap_max) * 4 + 255) & ~(size_t)255;
 }
-// Bloom words for a table of `cap` slots: two bits per slot, between one word
-// per region and 128 KiB (the LDS a probe workgroup gives it).
-constexpr int kBloomWordsMax = 16384;
+// Bloom words (32-bit) for a table of `cap` slots: two bits per slot, between
+// two words per region and 128 KiB (the LDS a probe workgroup gives it).
+constexpr int kBloomWordsMax = 32768;
+constexpr int kLog2BloomWordsMax = 15;
 __host__ __device__ inline int64_t bloom_words_max(int64_t cap) {
-  const int64_t w = cap / 32;
-  return w < kRegionBins ? kRegionBins : (w > kBloomWordsMax ? kBloomWordsMax : w);
+  const int64_t w = cap / 16;
+  return w < 2 * kRegionBins ? 2 * kRegionBins : (w > kBloomWordsMax ? kBloomWordsMax : w);
 }
 __host__ __device__ inline size_t scratch_bytes(int64_t cap_max) {
   return block_rows_bytes(cap_max) + (size_t)part_grid_max(cap_max) * kRegionBins * 4 + (size_t)cap_max * 16 +
-         table_tag_bytes(cap_max) + (size_t)bloom_words_max(cap_max) * 8;
+         table_tag_bytes(cap_max) + (size_t)bloom_words_max(cap_max) * 4;
 }
 __host__ __device__ inline char* table_scratch(void* t, int64_t cap_max) {
   return reinterpret_cast<char*>(table_slots(t, cap_max)) + (size_t)cap_max * 16;
@@ -190,8 +192,8 @@ __host__ __device__ inline int64_t* scratch_rows(void* t, int64_t cap_max) {
 __host__ __device__ inline uint32_t* scratch_alt_tags(void* t, int64_t cap_max) {
   return reinterpret_cast<uint32_t*>(scratch_rows(t, cap_max) + (size_t)cap_max * 2);
 }
-__host__ __device__ inline uint64_t* scratch_bloom(void* t, int64_t cap_max) {
-  return reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(scratch_alt_tags(t, cap_max)) + table_tag_bytes(cap_max));
+__host__ __device__ inline uint32_t* scratch_bloom(void* t, int64_t cap_max) {
+  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(scratch_alt_tags(t, cap_max)) + table_tag_bytes(cap_max));
 }
 __host__ __device__ inline int64_t* state_data(void* s) {
   return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(s) + kHeaderBytes);
@@ -214,20 +216,20 @@ __device__ __forceinline__ uint64_t bucket_of(uint64_t h, int skip, int log2buck
   return (h << skip) >> (64 - log2buckets);
 }
 
-// Bloom filter of a region-built table: the key's region (as for its bucket)
-// selects a block of 2^(log2w - kLog2Bins) words; a second multiplicative
-// hash picks the word in the block (its top bits) and three bits of it.
-constexpr uint64_t kFib2 = 0xD6E8FEB86659FD93ull;
-__device__ __forceinline__ uint32_t bloom_word(uint64_t h, int64_t k, int skip, int log2w) {
+// Bloom filter of a region-built table, from the key's multiplicative hash h:
+// the key's region (as for its bucket) selects a block of 2^(log2w -
+// kLog2Bins) 32-bit words, bits 19.. of h the word in the block and three bit
+// positions in it (bits that the tag, the slot start and the bucket index of
+// tables up to 2^(23 - skip) buckets leave unused).
+__device__ __forceinline__ uint32_t bloom_word(uint64_t h, int skip, int log2w) {
   const uint32_t region = (uint32_t)((h << skip) >> (64 - kLog2Bins));
   const int sub_bits = log2w - kLog2Bins;
-  const uint64_t h2 = (uint64_t)k * kFib2;
-  const uint32_t sub = sub_bits ? (uint32_t)(h2 >> (64 - sub_bits)) : 0u;
+  const uint32_t sub = (uint32_t)(h >> 19) & ((1u << sub_bits) - 1u);
   return (region << sub_bits) | sub;
 }
-__device__ __forceinline__ uint64_t bloom_bits(int64_t k) {
-  const uint64_t h2 = (uint64_t)k * kFib2;
-  return (1ull << ((h2 >> 52) & 63)) | (1ull << ((h2 >> 46) & 63)) | (1ull << ((h2 >> 40) & 63));
+__device__ __forceinline__ uint32_t bloom_bits(uint64_t h) {
+  const uint32_t x = (uint32_t)(h >> 26);
+  return (1u << (x & 31u)) | (1u << ((x >> 5) & 31u)) | (1u << ((x >> 10) & 31u));
 }
 
 template <typename T>
@@ -404,6 +406,32 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t* excl, int
 __device__ __forceinline__ int64_t block_sum(int64_t x, int64_t* wave_sums) {
   int64_t e;
   return block_excl_scan(x, &e, wave_sums);
+}
+
+// Block-wide sums of two int64 per thread, both valid in every thread.
+// Contains two barriers.
+__device__ __forceinline__ void block_sum2(int64_t* a, int64_t* b, int64_t* wave_vals) {
+  const int lane = __lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  int64_t x = *a, y = *b;
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    x += __shfl_xor(x, d, kWave);
+    y += __shfl_xor(y, d, kWave);
+  }
+  if (lane == 0) {
+    wave_vals[2 * wid] = x;
+    wave_vals[2 * wid + 1] = y;
+  }
+  __syncthreads();
+  x = 0;
+  y = 0;
+  for (int w = 0; w < nw; w++) {
+    x += wave_vals[2 * w];
+    y += wave_vals[2 * w + 1];
+  }
+  __syncthreads();
+  *a = x;
+  *b = y;
 }
 
 // Block-wide sum and maximum of one int64 per thread, both valid in every

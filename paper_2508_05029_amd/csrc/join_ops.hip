@@ -38,6 +38,30 @@ __host__ __device__ inline size_t table_bytes_for(int64_t cap) {
   return kHeaderBytes + (size_t)kMaxPartBlocks * 8 + table_tag_bytes(cap) + (size_t)cap * 16 + scratch_bytes(cap);
 }
 
+// The capacity rule as integer thresholds, for kernels that apply it to a
+// device-side count: t[l] is the largest row count whose capacity
+// (log2cap_for) is at most 2^l, found with the same double arithmetic.
+struct CapRule {
+  int64_t t[62];
+};
+static CapRule cap_rule(double lf) {
+  CapRule R;
+  for (int l = 0; l < 62; l++) {
+    int64_t lo = -1, hi = (int64_t)1 << 61;  // log2cap_for(lo) <= l < log2cap_for(hi)
+    if (l < 6) {
+      R.t[l] = -1;
+      continue;
+    }
+    while (hi - lo > 1) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (log2cap_for(mid, lf) <= l) lo = mid;
+      else hi = mid;
+    }
+    R.t[l] = lo;
+  }
+  return R;
+}
+
 static int64_t cap_max_for_bytes(size_t bytes) {
   int64_t cap = 0;
   for (int l = 6; l < 62; l++) {
@@ -185,6 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_
 
 constexpr int kFinBlock = 1024;
 constexpr int kMaxRegionSlots = 2048;  // LDS region: 4 KiB of tags + 32 KiB of slots
+static_assert(kFinBlock == kMaxRegionSlots / 2, "one thread clears one LDS tag word");
 constexpr int kMinRegionLog2Cap = kLog2Bucket + kLog2Bins;  // a region of at least one bucket
 constexpr int kMaxRegionLog2Cap = 11 + kLog2Bins;            // at most kMaxRegionSlots slots
 
@@ -220,7 +245,7 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   const int64_t total = block_excl_scan((int64_t)cnt, &excl, ws);
   if (tid < kRegionBins) {
     loc[tid] = (uint32_t)excl;
-    scratch_meta(h, cap_max)[(size_t)blockIdx.x * kRegionBins + tid] = ((uint32_t)excl << 16) | cnt;
+    scratch_meta(h, cap_max)[(size_t)tid * part_grid_max(cap_max) + blockIdx.x] = ((uint32_t)excl << 16) | cnt;
   }
   if (tid == 0) scratch_block_rows(h, cap_max)[blockIdx.x] = (int32_t)total;
   __syncthreads();
@@ -231,30 +256,33 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int64_t cap_max, int nblk, double lf,
-                                                            int skip, uint32_t flags) {
+                                                            int skip, uint32_t flags, CapRule rule) {
   __shared__ uint32_t ltag[kMaxRegionSlots / 2];
   __shared__ v2i64 lslot[kMaxRegionSlots];
-  __shared__ uint32_t lpos[kFinBlock];
-  __shared__ int64_t lsrc[kFinBlock];
   __shared__ int64_t ws[2 * kFinBlock / kWave];
-  __shared__ unsigned long long lbloom[kBloomWordsMax / kRegionBins];
+  __shared__ uint32_t lbloom[kBloomWordsMax / kRegionBins];
   const int j = blockIdx.x, tid = threadIdx.x;
-  const uint32_t* meta = scratch_meta(h, cap_max);
-  // the first loads go out before the header check so that they overlap (the
-  // scratch lies inside the caller's buffer either way)
+  const uint32_t* meta = scratch_meta(h, cap_max) + (size_t)j * part_grid_max(cap_max);  // region j's counts
+  // the loads go out first (the scratch lies inside the caller's buffer
+  // whatever the header holds), then the LDS copy is cleared while they fly
   const int32_t* brows = scratch_block_rows(h, cap_max);
   int64_t rb = 0, cj = 0;
   uint32_t m0 = 0;
   for (int b = tid; b < nblk; b += kFinBlock) {
-    const uint32_t m = meta[(size_t)b * kRegionBins + j];
+    const uint32_t m = meta[b];
     rb += brows[b];
     cj += m & 0xffffu;
     if (b == tid) m0 = m;
   }
+  ltag[tid] = 0u;  // kFinBlock == kMaxRegionSlots / 2
+  if (tid < kBloomWordsMax / kRegionBins) lbloom[tid] = 0u;
   if (h->magic != kTableMagic) return;
-  const int64_t rows = block_sum(rb, ws);
-  const int64_t mine = block_sum(cj, ws);  // rows of region j
-  int l = log2cap_for(rows, lf);
+  int64_t rows = rb, mine = cj;  // all rows; rows of region j
+  block_sum2(&rows, &mine, ws);
+  rows = ((int64_t)__builtin_amdgcn_readfirstlane((int)(rows >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)rows);  // uniform: scalar from here
+  int l = 6;  // log2cap_for(rows, lf)
+  while (l < 62 && rows > rule.t[l]) l++;
   const bool too_big = ((int64_t)1 << l) > cap_max;
   if (too_big) {
     l = 6;
@@ -263,8 +291,9 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   const bool in_range = l >= kMinRegionLog2Cap && l <= kMaxRegionLog2Cap;
   const int64_t region_slots = in_range ? (int64_t)1 << (l - kLog2Bins) : 0;
   const bool fits = in_range && mine <= region_slots - std::max<int64_t>(1, region_slots / 8);
-  int log2w = 0;  // Bloom words (log2) for this capacity
-  while (((int64_t)1 << (log2w + 1)) <= bloom_words_max((int64_t)1 << l)) log2w++;
+  // Bloom words (log2) for this capacity: bloom_words_max(2^l)
+  const int log2w = std::min(std::max(l - 4, kLog2Bins + 1), kLog2BloomWordsMax);
+  static_assert(kBloomWordsMax == 1 << kLog2BloomWordsMax && kRegionBins == 1 << kLog2Bins, "bloom size rule");
   if (j == 0 && tid == 0) {
     h->cap_max = cap_max;
     h->n = rows;
@@ -293,33 +322,32 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   const int log2g = l - kLog2Bucket - kLog2Bins;
   const int gmask = (1 << log2g) - 1, nslot = kBucket << log2g;
   const int nbw = 1 << (log2w - kLog2Bins);  // Bloom words of this region
-  for (int i = tid; i < nslot / 2; i += kFinBlock) ltag[i] = 0u;
-  if (tid < nbw) lbloom[tid] = 0ull;
-  __syncthreads();
   const v2i64* seg = reinterpret_cast<const v2i64*>(scratch_rows(h, cap_max));
   bool stuck = false;
-  // kFinBlock source blocks per round: their counts are scanned in LDS, so that
-  // thread i fetches the round's rows i, i + kFinBlock, ... (each found by a
-  // binary search over the scan) with all loads in flight at once
-  for (int base = 0; base < nblk; base += kFinBlock) {
-    const int b = base + tid;
-    const uint32_t m = base == 0 ? m0 : (b < nblk ? meta[(size_t)b * kRegionBins + j] : 0u);
-    int64_t excl;
-    const int64_t total = block_excl_scan((int64_t)(m & 0xffffu), &excl, ws);
-    lpos[tid] = (uint32_t)excl;
-    lsrc[tid] = (int64_t)b * kPartRows + (m >> 16);
-    __syncthreads();
-    for (int64_t i = tid; i < total; i += kFinBlock) {
-      int lo = 0, hi = kFinBlock - 1;  // the last source whose first row is at or before i
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((int64_t)lpos[mid] <= i) lo = mid;
-        else hi = mid - 1;
-      }
-      const v2i64 kv = seg[lsrc[lo] + (i - (int64_t)lpos[lo])];
+  // each wave takes 64 source blocks at a time and spreads their rows of
+  // region j over its lanes (a wave scan of the counts, then a search over
+  // the lanes by shuffles), so that every lane loads one row at a time
+  const int lane = tid & (kWave - 1);
+  for (int b0 = tid - lane; b0 < nblk; b0 += kFinBlock) {
+    const int b = b0 + lane;
+    const uint32_t m = b < nblk ? (b0 == tid - lane && b == tid ? m0 : meta[b]) : 0u;
+    uint32_t total;
+    const uint32_t excl = wave_excl_scan(m & 0xffffu, &total);
+    const int64_t first = (int64_t)b * kPartRows + (m >> 16);  // this lane's first row in the segments
+    // (every lane stays in the loop for the shuffles; only the row work is guarded)
+    for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+      const uint32_t i = i0 + lane;
+      int s = 0;  // the last lane whose rows start at or before i
+#pragma unroll
+      for (int step = kWave / 2; step >= 1; step >>= 1)
+        if ((uint32_t)__shfl(excl, s + step, kWave) <= i) s += step;
+      const int64_t at = ((int64_t)__shfl((int)(first >> 32), s, kWave) << 32) |
+                         (uint32_t)__shfl((int)(uint32_t)first, s, kWave);
+      const uint32_t e_s = (uint32_t)__shfl(excl, s, kWave);
+      if (i >= total) continue;
+      const v2i64 kv = seg[at + (i - e_s)];
       const uint64_t hh = mulhash(kv.x);
-      atomicOr(&lbloom[bloom_word(hh, kv.x, skip, log2w) & (uint32_t)(nbw - 1)],
-               (unsigned long long)bloom_bits(kv.x));
+      atomicOr(&lbloom[bloom_word(hh, skip, log2w) & (uint32_t)(nbw - 1)], bloom_bits(hh));
       int bl = (int)(bucket_of(hh, skip, l - kLog2Bucket) & (uint64_t)gmask);
       const uint32_t tg = hash_tag(hh);
       const int st = (int)(hh >> 16) & (kBucket - 1);
@@ -352,8 +380,8 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
       }
       stuck = stuck || !done;
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (stuck) latch_error(&h->err, TQ_EFULL);
   uint32_t* gw = table_tags(h) + ((size_t)j << log2g) * 4;
   for (int i = tid; i < nslot / 2; i += kFinBlock) gw[i] = ltag[i];
@@ -478,7 +506,7 @@ constexpr int kPipeQ = 128;  // queue entries per wave: below 64 at a tile's sta
 constexpr int kBloomPipeBlock = 1024;  // one workgroup per CU beside the filter: 16 waves
 constexpr size_t kMaxPipeLds = 64 * 1024;  // dynamic LDS of a launch without a per-kernel attribute
 constexpr size_t kCuLds = 160 * 1024;
-constexpr size_t kMaxBloomPipeLds = kCuLds - (size_t)kBloomWordsMax * 8;  // dynamic LDS beside the filter
+constexpr size_t kMaxBloomPipeLds = kCuLds - (size_t)kBloomWordsMax * 4;  // dynamic LDS beside the filter
 
 template <int NE>
 struct PipeRows {
@@ -495,15 +523,15 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
                                                                                         RowPlan P, AggTarget T,
                                                                                         int agg_lds) {
   constexpr int R = kPipeRows;
-  __shared__ uint64_t bloom[BLOOM ? kBloomWordsMax : 1];
+  __shared__ uint32_t bloom[BLOOM ? kBloomWordsMax : 1];
   extern __shared__ __align__(16) char smem[];
   if (h->magic != kTableMagic) return;
   if (!state_matches(T)) return;
   const int log2w = BLOOM ? h->bloom_log2w : 0;
   const int nbw = log2w ? 1 << log2w : 0;
   if (BLOOM) {
-    const uint64_t* gb = scratch_bloom(const_cast<TableHeader*>(h), h->cap_max);
-    for (int i = threadIdx.x; i < nbw; i += blockDim.x) bloom[i] = gb[i];
+    const v4i32* gb = reinterpret_cast<const v4i32*>(scratch_bloom(const_cast<TableHeader*>(h), h->cap_max));
+    for (int i = threadIdx.x; i < nbw / 4; i += blockDim.x) reinterpret_cast<v4i32*>(bloom)[i] = gb[i];
   }
   LdsAgg<MODE> agg;
   agg.defer = true;
@@ -582,8 +610,8 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
         tt.b[i] = (int64_t)bucket_of(hh, pr.skip, pr.log2b);
         tt.tg[i] = hash_tag(hh);
         if (BLOOM && nbw) {  // a key the filter rejects is not in the build
-          const uint64_t m = bloom_bits(kk[i]);
-          tt.live[i] = tt.live[i] && (bloom[bloom_word(hh, kk[i], pr.skip, log2w)] & m) == m;
+          const uint32_t m = bloom_bits(hh);
+          tt.live[i] = tt.live[i] && (bloom[bloom_word(hh, pr.skip, log2w)] & m) == m;
         }
       }
 #pragma unroll
@@ -833,7 +861,7 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
     TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_part<NC>, dim3((int)part_grid), dim3(kPartBlock), 0, stream,
                                                   P, d_keys, pc, n, h, cap_max, skip));
     hipLaunchKernelGGL(k_build_regions, dim3(kRegionBins), dim3(kFinBlock), 0, stream, h, cap_max, (int)part_grid,
-                       load_factor, skip, flags);
+                       load_factor, skip, flags, cap_rule(load_factor));
     TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_fallback<NC>, dim3(stream_grid(n, 2)), dim3(kBlock), 0,
                                                   stream, P, d_keys, pc, n, h, cap_max));
     TQ_HIP(hipGetLastError());

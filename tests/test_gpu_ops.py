@@ -257,8 +257,8 @@ def test_join_build_paths(case):
     assert regions == want_regions
     assert alt == (1 if case.startswith("cas") else 0)  # the fallback insert uses the alternate arrays
     assert log2g == (log2cap - 11 if regions else log2cap - 3)
-    # two filter bits per slot, 256 to 16384 words; only a region build has one
-    assert bloom_log2w == (min(max(log2cap - 5, 8), 14) if regions else 0)
+    # two filter bits per slot, 512 to 32768 words of 32 bits; only a region build has one
+    assert bloom_log2w == (min(max(log2cap - 4, 9), 15) if regions else 0)
     total, pr, br = oracle.join_pairs(bk[keep], pk)
     cap = max(total, 1)
     rows = torch.empty(cap, dtype=torch.int64, device=DEV)
