@@ -146,9 +146,10 @@ __host__ __device__ inline int64_t* table_slots(void* t, int64_t cap_max) {
                                     table_tag_bytes(cap_max));
 }
 // Region build scratch, after the slots, sized by the capacity: int32
-// block_rows[max_grid] | uint32 meta[kRegionBins][max_grid] ((offset << 16) |
-// count of one block's rows in each region, region-major so that a region's
-// counts over the blocks are contiguous) | {key, payload}[cap_max] (each
+// block_rows[max_grid] | uint32 meta[max_grid][kMetaStride] ((offset << 16) |
+// count of one block's rows in each region; rows padded past kRegionBins so
+// that one region's counts over the blocks do not all fall in the same cache
+// channels) | {key, payload}[cap_max] (each
 // block's passing rows, grouped by region, at block * kPartRows) | uint16
 // alt_tags[cap_max], where max_grid = part_grid_max(cap_max). When a region
 // overflows, the fallback insert builds the whole table into alt_tags and
@@ -159,6 +160,7 @@ constexpr int kRegionBins = 256;  // the top 8 bits of a bucket index select its
 constexpr int kLog2Bins = 8;
 constexpr int kPartBlock = 512;
 constexpr int kPartRows = kPartBlock * kRows;  // rows per partitioning block
+constexpr int kMetaStride = kRegionBins + 8;
 __host__ __device__ inline int64_t part_grid_max(int64_t cap_max) {
   return cap_max / kPartRows > 1 ? cap_max / kPartRows : 1;
 }
@@ -174,7 +176,7 @@ __host__ __device__ inline int64_t bloom_words_max(int64_t cap) {
   return w < 2 * kRegionBins ? 2 * kRegionBins : (w > kBloomWordsMax ? kBloomWordsMax : w);
 }
 __host__ __device__ inline size_t scratch_bytes(int64_t cap_max) {
-  return block_rows_bytes(cap_max) + (size_t)part_grid_max(cap_max) * kRegionBins * 4 + (size_t)cap_max * 16 +
+  return block_rows_bytes(cap_max) + (size_t)part_grid_max(cap_max) * kMetaStride * 4 + (size_t)cap_max * 16 +
          table_tag_bytes(cap_max) + (size_t)bloom_words_max(cap_max) * 4;
 }
 __host__ __device__ inline char* table_scratch(void* t, int64_t cap_max) {
@@ -187,7 +189,7 @@ __host__ __device__ inline uint32_t* scratch_meta(void* t, int64_t cap_max) {
   return reinterpret_cast<uint32_t*>(table_scratch(t, cap_max) + block_rows_bytes(cap_max));
 }
 __host__ __device__ inline int64_t* scratch_rows(void* t, int64_t cap_max) {
-  return reinterpret_cast<int64_t*>(scratch_meta(t, cap_max) + (size_t)part_grid_max(cap_max) * kRegionBins);
+  return reinterpret_cast<int64_t*>(scratch_meta(t, cap_max) + (size_t)part_grid_max(cap_max) * kMetaStride);
 }
 __host__ __device__ inline uint32_t* scratch_alt_tags(void* t, int64_t cap_max) {
   return reinterpret_cast<uint32_t*>(scratch_rows(t, cap_max) + (size_t)cap_max * 2);

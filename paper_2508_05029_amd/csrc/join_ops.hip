@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   const int64_t total = block_excl_scan((int64_t)cnt, &excl, ws);
   if (tid < kRegionBins) {
     loc[tid] = (uint32_t)excl;
-    scratch_meta(h, cap_max)[(size_t)tid * part_grid_max(cap_max) + blockIdx.x] = ((uint32_t)excl << 16) | cnt;
+    scratch_meta(h, cap_max)[(size_t)blockIdx.x * kMetaStride + tid] = ((uint32_t)excl << 16) | cnt;
   }
   if (tid == 0) scratch_block_rows(h, cap_max)[blockIdx.x] = (int32_t)total;
   __syncthreads();
@@ -262,14 +262,14 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   __shared__ int64_t ws[2 * kFinBlock / kWave];
   __shared__ uint32_t lbloom[kBloomWordsMax / kRegionBins];
   const int j = blockIdx.x, tid = threadIdx.x;
-  const uint32_t* meta = scratch_meta(h, cap_max) + (size_t)j * part_grid_max(cap_max);  // region j's counts
+  const uint32_t* meta = scratch_meta(h, cap_max) + j;  // region j's counts, block b at meta[b * kMetaStride]
   // the loads go out first (the scratch lies inside the caller's buffer
   // whatever the header holds), then the LDS copy is cleared while they fly
   const int32_t* brows = scratch_block_rows(h, cap_max);
   int64_t rb = 0, cj = 0;
   uint32_t m0 = 0;
   for (int b = tid; b < nblk; b += kFinBlock) {
-    const uint32_t m = meta[b];
+    const uint32_t m = meta[(size_t)b * kMetaStride];
     rb += brows[b];
     cj += m & 0xffffu;
     if (b == tid) m0 = m;
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   const int lane = tid & (kWave - 1);
   for (int b0 = tid - lane; b0 < nblk; b0 += kFinBlock) {
     const int b = b0 + lane;
-    const uint32_t m = b < nblk ? (b0 == tid - lane && b == tid ? m0 : meta[b]) : 0u;
+    const uint32_t m = b < nblk ? (b0 == tid - lane && b == tid ? m0 : meta[(size_t)b * kMetaStride]) : 0u;
     uint32_t total;
     const uint32_t excl = wave_excl_scan(m & 0xffffu, &total);
     const int64_t first = (int64_t)b * kPartRows + (m >> 16);  // this lane's first row in the segments

@@ -50,7 +50,7 @@ def test_buffer_sizes():
     def scratch(cap):
         g = max(1, cap // 2048)
         bloom_words = min(max(cap // 16, 512), 32768)  # 32-bit words: two bits per slot, at most 128 KiB
-        return (g * 4 + 255) // 256 * 256 + g * 256 * 4 + cap * 16 + (cap * 2 + 255) // 256 * 256 + bloom_words * 4
+        return (g * 4 + 255) // 256 * 256 + g * 264 * 4 + cap * 16 + (cap * 2 + 255) // 256 * 256 + bloom_words * 4
 
     assert tq.join_table_bytes(227_600, 0.5) == 256 + part + (1 << 19) * 2 + (1 << 19) * 16 + scratch(1 << 19)
     assert tq.join_table_bytes(0, 0.5) == 256 + part + 256 + 64 * 16 + scratch(64)
