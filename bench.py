@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 PROBE_COUNTERS = {
     "sources": ["paper_2508_05029_amd/csrc/join_ops.hip", "paper_2508_05029_amd/csrc/table.h",
                 "paper_2508_05029_amd/csrc/groupby.h", "paper_2508_05029_amd/csrc/common.h"],
-    "sha1": "75beeb8aa1c7a84197487e5c6c9c5ed8d9458509",
-    "fetch_kib": 111556.6, "fetch_scale": 2.000,
-    "write_kib": 208.0, "write_scale": 0.995,
+    "sha1": "6adcc0707dcfb4a872538d298c4782cec263c838",
+    "fetch_kib": 115234.5, "fetch_scale": 2.000,
+    "write_kib": 104.0, "write_scale": 0.995,
 }
 
 
@@ -115,6 +115,16 @@ def bench_join_agg(args):
         for j, k in enumerate(ev):
             ev[k].append((marks[j], marks[j + 1]))
     kern_ms = {k: float(np.mean(events_ms(v))) for k, v in ev.items()}
+    # the probe alone: back-to-back launches between two events on its stream
+    # (its state just accumulates; every timed step below starts from a fresh one)
+    k_probe = 20
+    f = copies[0][1]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(k_probe):
+        ja.probe(f)
+    e1.record(stream)
+    kern_ms["probe"] = events_ms([(e0, e1)])[0] / k_probe
 
     # graph: args.graph_steps consecutive steps per replay, rotating the copies
     gs = args.graph_steps

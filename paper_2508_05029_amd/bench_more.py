@@ -218,7 +218,9 @@ def bench_batched(args):
     q = wl.batched_query(8)
     table = autotune.tune_batched(q, insts, cache_path=None, sample=32, reps=2, log=log)
     params = autotune.params_for(insts, table)
+    log(f"batched: tuned; laying out {count} instances on the device")
     job = pipeline.BatchedJoinAgg(q, insts, params)
+    log("batched: instances uploaded and prepared")
     in_bytes = job.input_bytes
     stream = torch.cuda.current_stream()
     side = torch.cuda.Stream()
@@ -242,6 +244,7 @@ def bench_batched(args):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
     job.check()
+    log(f"batched: graph replays done, {ms:.2f} ms per pass")
     # one launch per instance, for comparison
     a, b = _events()
     job.run_per_instance()
@@ -251,6 +254,7 @@ def bench_batched(args):
     b.record()
     torch.cuda.synchronize()
     ms_per_inst = a.elapsed_time(b)
+    log(f"batched: one launch per instance, {ms_per_inst:.2f} ms per pass")
     # parity on a sample of instances against the oracle
     parity = None
     cpu = None

@@ -254,17 +254,15 @@ class BatchedJoinAgg:
         self.arena = torch.empty(total, dtype=torch.uint8, device=device)
         base = self.arena.data_ptr()
         self.insts = (tq.Instance * len(instances))()
-        host = torch.empty(total, dtype=torch.uint8, pin_memory=True)
-        hb = host.data_ptr()
+        uploads = []  # (arena offset, column): only the columns come from the host;
+        # tables, states and outputs are set up on the device
         for i, ((d, f, domain), e) in enumerate(zip(instances, plan)):
             I = self.insts[i]
             for j, c in enumerate(self.dnames):
-                a = np.ascontiguousarray(d[c])
-                ctypes.memmove(hb + e["dcols"][j], a.ctypes.data, a.nbytes)
+                uploads.append((e["dcols"][j], d[c]))
                 I.dim_cols[j] = base + e["dcols"][j]
             for j, c in enumerate(self.fnames):
-                a = np.ascontiguousarray(f[c])
-                ctypes.memmove(hb + e["fcols"][j], a.ctypes.data, a.nbytes)
+                uploads.append((e["fcols"][j], f[c]))
                 I.fact_cols[j] = base + e["fcols"][j]
             I.n_dim, I.n_fact, I.domain = e["nd"], e["nf"], domain
             I.d_table, I.table_bytes = base + e["table"], e["tbytes"]
@@ -272,14 +270,40 @@ class BatchedJoinAgg:
             I.d_keys, I.d_count, I.d_sums = base + e["keys"], base + e["count"], base + e["sums"]
             I.d_avg, I.d_ngroups = base + e["avg"], base + e["ng"]
             I.load_factor, I.build_tile, I.probe_tile = e["lf"], e["bt"], e["pt"]
-        self.arena.copy_(host)
-        del host
+        self._upload(uploads)
         self.plan = plan
         self.n = len(instances)
         self.nsum = nsum
         self.input_bytes = sum(len(self.dnames) * 8 * e["nd"] + len(self.fnames) * 8 * e["nf"] for e in plan)
         self.work = torch.empty(max(1, tq.batched_work_bytes(self.insts)), dtype=torch.uint8, device=device)
         tq.batched_prepare(self.Q, self.insts, self.work)
+
+    def _upload(self, uploads, stage_bytes=64 << 20):
+        """Copies the columns into the arena through one reusable pinned
+        buffer (a pinned copy of the whole arena would be tens of GB)."""
+        stage = torch.empty(stage_bytes, dtype=torch.uint8, pin_memory=True)
+        sb = stage.data_ptr()
+        batch, fill = [], 0
+
+        def flush():
+            for off, n, at in batch:
+                self.arena[off:off + n].copy_(stage[at:at + n], non_blocking=True)
+            torch.cuda.synchronize()  # the buffer is refilled next
+            batch.clear()
+
+        for off, col in uploads:
+            a = np.ascontiguousarray(col)
+            n, pos = a.nbytes, 0
+            while pos < n:
+                k = min(n - pos, stage_bytes - fill)
+                ctypes.memmove(sb + fill, a.ctypes.data + pos, k)
+                batch.append((off + pos, k, fill))
+                fill, pos = fill + k, pos + k
+                if fill == stage_bytes:
+                    flush()
+                    fill = 0
+        if batch:
+            flush()
 
     def set_params(self, params, device="cuda"):
         """New (load_factor, build_tile, probe_tile) per instance; the tables were
