@@ -120,10 +120,13 @@ tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_
 
 /* ------------------------------------------------------------- hash join */
 
-/* An open-addressing hash table (linear probing) for the build side of an
- * equi-join (the Adaptive Join of Section 3.2). Layout: a 256-byte header, a
- * 16 KiB area of per-workgroup partial counts, a 32-bit tag per slot
- * (0 = empty) and a 16-byte {key, payload} slot array.
+/* An open-addressing hash table (linear probing over buckets of 8 slots) for
+ * the build side of an equi-join (the Adaptive Join of Section 3.2). Layout: a
+ * 256-byte header, a 16 KiB area of per-workgroup partial counts, a 16-bit tag
+ * per slot (0 = empty), a 16-byte {key, payload} slot array, and a build
+ * scratch area of about the slot array's size (the rows grouped by table
+ * region, alternate tags for a fallback build, and a Bloom filter of the keys
+ * that probes use to skip rows with no partner).
  * Any int64 key is allowed; duplicate build keys are kept (many-to-many).
  * tq_join_table_bytes gives the size for at most n_build_max rows at the given
  * load factor (0 < load_factor <= 0.9). The capacity actually used by a build
@@ -140,7 +143,8 @@ tq_status tq_join_table_init(void* d_table, size_t bytes, hipStream_t stream);
  * optional predicates over `filt` (the dimension filter fused into the build).
  * `skip` high hash bits are ignored by the slot index (set it to the partition
  * bits when the input is one hash partition). Latches TQ_EFULL if the rows do
- * not fit in the buffer. */
+ * not fit in the buffer. Three or four kernel launches on `stream`, none of
+ * which allocates; builds into one buffer must not overlap. */
 tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_col payload, int64_t n,
                         const tq_col* filt, int32_t nfilt, const tq_pred* p, int32_t np, double load_factor,
                         int32_t skip, uint32_t flags, hipStream_t stream);
