@@ -581,9 +581,9 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
     v2i64 cva[NC], cka, cvb[NC], ckb;  // columns of two tiles ahead (alternating sets)
     v4i32 tw[R];            // tags of the tile 1 ahead
     v2i64 kv[R];            // candidate slots of the current tile
-    PipeRows<NE> tt, st;    // rows whose tags (tt) / slots (st) are in flight
-    uint32_t sm[R];         // st: candidate mask of the home bucket
-    bool sempty[R];         // st: the home bucket has a free slot
+    PipeRows<NE> ra, rb;    // row state of two consecutive tiles (alternating sets, never copied)
+    uint32_t sm[R];         // candidate masks of the home buckets (slot loads in flight)
+    bool sempty[R];         // the home bucket has a free slot
 
     auto load_cols = [&](v2i64 (&cv)[NC], v2i64& ck, int64_t rt) {  // a tile past the last reads tile 0
       const int64_t q = (rt < n_main ? rt : 0) / R;
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
 #pragma unroll
       for (int c = 0; c < NC; c++) cv[c] = ntload(ccol[c] + q);
     };
-    auto cols_to_tags = [&](const v2i64 (&cv)[NC], const v2i64& ck, int64_t rt) {  // cv, ck -> tt; tag loads
+    auto cols_to_tags = [&](const v2i64 (&cv)[NC], const v2i64& ck, int64_t rt, PipeRows<NE>& t) {  // -> t; tag loads
       int64_t v[NC][R];
 #pragma unroll
       for (int c = 0; c < NC; c++) {
@@ -599,44 +599,43 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
         v[c][1] = cv[c].y;
       }
       const int64_t kk[R] = {ck.x, ck.y};
-      tt.row = rt;
+      t.row = rt;
 #pragma unroll
       for (int i = 0; i < R; i++) {
-        tt.live[i] = (rt < n_main) && eval_preds<NC>(P, v, i);
+        t.live[i] = (rt < n_main) && eval_preds<NC>(P, v, i);
 #pragma unroll
-        for (int j = 0; j < NE; j++) tt.e[i][j] = j < P.ne ? eval_expr<NC>(P.expr[j], v, i) : 0;
-        tt.k[i] = kk[i];
+        for (int j = 0; j < NE; j++) t.e[i][j] = j < P.ne ? eval_expr<NC>(P.expr[j], v, i) : 0;
+        t.k[i] = kk[i];
         const uint64_t hh = mulhash(kk[i]);
-        tt.b[i] = (int64_t)bucket_of(hh, pr.skip, pr.log2b);
-        tt.tg[i] = hash_tag(hh);
+        t.b[i] = (int64_t)bucket_of(hh, pr.skip, pr.log2b);
+        t.tg[i] = hash_tag(hh);
         if (BLOOM && nbw) {  // a key the filter rejects is not in the build
           const uint32_t m = bloom_bits(hh);
-          tt.live[i] = tt.live[i] && (bloom[bloom_word(hh, pr.skip, log2w)] & m) == m;
+          t.live[i] = t.live[i] && (bloom[bloom_word(hh, pr.skip, log2w)] & m) == m;
         }
       }
 #pragma unroll
-      for (int i = 0; i < R; i++) tw[i] = pr.groups[tt.live[i] ? tt.b[i] : 0];
+      for (int i = 0; i < R; i++) tw[i] = pr.groups[t.live[i] ? t.b[i] : 0];
     };
-    auto tags_to_slots = [&]() {  // tt, tw -> st; slot loads
+    auto tags_to_slots = [&](const PipeRows<NE>& t) {  // tw -> candidate masks; slot loads
 #pragma unroll
       for (int i = 0; i < R; i++) {
-        sm[i] = tt.live[i] ? tag_match(tw[i], tt.tg[i]) : 0u;
-        sempty[i] = tt.live[i] ? tag_match(tw[i], 0u) != 0u : true;
+        sm[i] = t.live[i] ? tag_match(tw[i], t.tg[i]) : 0u;
+        sempty[i] = t.live[i] ? tag_match(tw[i], 0u) != 0u : true;
       }
-      st = tt;
 #pragma unroll
-      for (int i = 0; i < R; i++) kv[i] = pr.slots[sm[i] ? st.b[i] * kBucket + __builtin_ctz(sm[i]) : 0];
+      for (int i = 0; i < R; i++) kv[i] = pr.slots[sm[i] ? t.b[i] * kBucket + __builtin_ctz(sm[i]) : 0];
     };
-    // (a) finish the current tile from its slots (before any register they live in is reloaded)
-    auto finish = [&]() {
+    // (a) finish a tile from its slots (before any register they live in is reloaded)
+    auto finish = [&](const PipeRows<NE>& t) {
 #pragma unroll
       for (int i = 0; i < R; i++) {
         const bool cand = sm[i] != 0u;
-        const bool hit = cand && kv[i].x == st.k[i];
+        const bool hit = cand && kv[i].x == t.k[i];
         const uint32_t rest = sm[i] & (sm[i] - 1u);
         const bool done =
-            !st.live[i] || (sm[i] == 0u && sempty[i]) || (hit && pr.unique) || (rest == 0u && sempty[i]);
-        if (done && hit) agg.add(T, kv[i].y, st.e[i], P.ne);
+            !t.live[i] || (sm[i] == 0u && sempty[i]) || (hit && pr.unique) || (rest == 0u && sempty[i]);
+        if (done && hit) agg.add(T, kv[i].y, t.e[i], P.ne);
         const bool slow = !done;
         const uint64_t bal = __ballot(slow);
         if (bal) {
@@ -644,7 +643,7 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
             const int rank =
                 __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             const int x = (qh + qn + rank) & (kPipeQ - 1);
-            qrow[x] = st.row + i;
+            qrow[x] = t.row + i;
           }
           qn += __popcll(bal);
           // keep room for the next row's 64 (rare: the loads of later tiles wait with it)
@@ -653,41 +652,42 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
       }
     };
 
-    // prologue: tile 0 to its slot loads, tile 1 to its tag loads, tiles 2
-    // and 3's columns requested
+    // prologue: tile 0 to its slot loads (row state ra), tile 1 to its tag
+    // loads (rb), tiles 2 and 3's columns requested
     load_cols(cva, cka, r);
-    cols_to_tags(cva, cka, r);
+    cols_to_tags(cva, cka, r, ra);
     asm volatile("" ::: "memory");
     load_cols(cvb, ckb, r + stride);
     asm volatile("" ::: "memory");
-    tags_to_slots();
+    tags_to_slots(ra);
     asm volatile("" ::: "memory");
-    cols_to_tags(cvb, ckb, r + stride);
+    cols_to_tags(cvb, ckb, r + stride, rb);
     asm volatile("" ::: "memory");
     load_cols(cva, cka, r + 2 * stride);
     asm volatile("" ::: "memory");
     load_cols(cvb, ckb, r + 3 * stride);
     asm volatile("" ::: "memory");
-    // Two tiles per pass, one per column set, so that each set's loads have
-    // two tiles' time to arrive. Per tile: (a) finish it; (b) the next tile's
-    // tags -> slot loads; (c) the tile two ahead: columns -> tag loads; (d)
-    // request the columns four ahead. The empty asm statements keep each
-    // stage's loads where they are: the compiler would otherwise merge them
-    // with later ones, after the loads they must precede. A second tile past
-    // the wave's last reads tile 0 and is not live.
+    // Two tiles per pass, one per column set and row-state set, so that each
+    // set's loads have two tiles' time to arrive. Per tile: (a) finish it; (b)
+    // the next tile's tags -> slot loads; (c) the tile two ahead: columns ->
+    // tag loads, into the row state just finished; (d) request the columns
+    // four ahead. The empty asm statements keep each stage's loads where they
+    // are: the compiler would otherwise merge them with later ones, after the
+    // loads they must precede. A second tile past the wave's last reads tile 0
+    // and is not live.
     for (int64_t w0 = wbase; w0 < n_main; w0 += 2 * stride, r += 2 * stride) {
-      finish();
-      tags_to_slots();
+      finish(ra);
+      tags_to_slots(rb);
       asm volatile("" ::: "memory");
-      cols_to_tags(cva, cka, r + 2 * stride);
+      cols_to_tags(cva, cka, r + 2 * stride, ra);
       asm volatile("" ::: "memory");
       load_cols(cva, cka, r + 4 * stride);
       asm volatile("" ::: "memory");
       while (qn >= kWave) drain(kWave);  // queued rows are walked after this tile's loads are on their way
-      finish();
-      tags_to_slots();
+      finish(rb);
+      tags_to_slots(ra);
       asm volatile("" ::: "memory");
-      cols_to_tags(cvb, ckb, r + 3 * stride);
+      cols_to_tags(cvb, ckb, r + 3 * stride, rb);
       asm volatile("" ::: "memory");
       load_cols(cvb, ckb, r + 5 * stride);
       asm volatile("" ::: "memory");
