@@ -289,12 +289,79 @@ __device__ __forceinline__ void load4(const DCol& c, int64_t r0, bool full, int6
   }
 }
 
+// Raw bytes of R (2 or 4) consecutive values of one column, loaded but not
+// yet widened, with the same instructions for every width: the 16-byte block
+// that holds row r0 (for R = 4 and 8-byte values, also the next one; for
+// other widths that load repeats the first). A column's width is only known
+// at run time, and a load in a branch of the width puts a wait inside the
+// branch, one memory latency per column; so every column is loaded before
+// any is widened. The caller makes sure rows r0 .. r0 + 15 exist, so that
+// the blocks lie inside the column (columns are 16-byte aligned).
+struct RawCol {
+  v4i32 a, b;
+  uint32_t off;  // byte offset of row r0 in block a
+};
+
+template <int R>
+__device__ __forceinline__ void load_raw(const DCol& c, int64_t r0, RawCol& x) {
+  // pointer arithmetic on the column pointer (an integer round trip would
+  // lose its address space and turn the loads into flat loads)
+  const char* at = static_cast<const char*>(c.p) + r0 * c.w;
+  x.off = (uint32_t)(reinterpret_cast<uintptr_t>(at) & 15);
+  const v4i32* blk = reinterpret_cast<const v4i32*>(at - x.off);
+  x.a = ntload(blk);
+  if (R == 4) x.b = ntload(blk + (c.w == 8 ? 1 : 0));
+}
+
+__device__ __forceinline__ uint32_t word_at(const v4i32& a, uint32_t q) {
+  uint32_t r = (uint32_t)a.x;
+  r = q == 1 ? (uint32_t)a.y : r;
+  r = q == 2 ? (uint32_t)a.z : r;
+  r = q == 3 ? (uint32_t)a.w : r;
+  return r;
+}
+
+template <int R>
+__device__ __forceinline__ void widen_raw(const DCol& c, const RawCol& x, int64_t (&v)[R]) {
+  if (c.w == 8) {  // block-aligned: R = 2 fills a, R = 4 fills a and b
+    v[0] = (int64_t)(((uint64_t)(uint32_t)x.a.y << 32) | (uint32_t)x.a.x);
+    v[1] = (int64_t)(((uint64_t)(uint32_t)x.a.w << 32) | (uint32_t)x.a.z);
+    if (R == 4) {
+      v[R > 2 ? 2 : 0] = (int64_t)(((uint64_t)(uint32_t)x.b.y << 32) | (uint32_t)x.b.x);
+      v[R > 2 ? 3 : 1] = (int64_t)(((uint64_t)(uint32_t)x.b.w << 32) | (uint32_t)x.b.z);
+    }
+  } else if (c.w == 4) {  // R = 4: block-aligned; R = 2: at word 0 or 2
+    const uint32_t q = x.off >> 2;
+#pragma unroll
+    for (int i = 0; i < R; i++) v[i] = (int32_t)word_at(x.a, q + i);
+  } else {  // 1 byte: R bytes inside one word of the block
+    const uint32_t wv = word_at(x.a, x.off >> 2) >> (8 * (x.off & 3));
+#pragma unroll
+    for (int i = 0; i < R; i++) v[i] = (wv >> (8 * i)) & 0xff;
+  }
+}
+
 // The rows r0..r0+R-1 of the first NC plan columns: v[c][i].
 template <int NC, int R = kRows>
 __device__ __forceinline__ void load_rows(const RowPlan& P, int64_t r0, bool full, int64_t n, int64_t (&v)[NC][R]) {
+  if (r0 + 16 <= n) {
+    RawCol raw[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+      if (c < P.ncol) load_raw<R>(P.col[c], r0, raw[c]);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      if (c < P.ncol) widen_raw<R>(P.col[c], raw[c], v[c]);
+      else {
+#pragma unroll
+        for (int i = 0; i < R; i++) v[c][i] = 0;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < NC; c++) {
-    if (c < P.ncol) load4<R>(P.col[c], r0, full, n, v[c]);
+    if (c < P.ncol) load4<R>(P.col[c], r0, false, n, v[c]);
     else {
 #pragma unroll
       for (int i = 0; i < R; i++) v[c][i] = 0;
