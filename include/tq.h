@@ -280,18 +280,40 @@ size_t tq_budget_cap(const tq_budget* b);
 
 /* ------------------------------------------------------------ out-of-core join */
 
-/* The partitioned out-of-core join + aggregate (Section 3.2's exchange in
- * front of a join, run on one GPU): both sides stream from page-pool batches
- * (tq_pagepool_stream); the dimension is filtered and both sides are hash
- * partitioned into 2^log2_fanout partitions whose rows are appended to
- * per-partition holders of fixed-size device chunks reserved from `budget`.
- * When a reservation fails, the resident chunks of the partition scheduled
- * latest are copied to pool pages (device -> host, on a stream of their own)
- * and released (Section 3.3.2: spill the data whose compute is furthest
- * away). Pass 2 joins partition by partition in order, reloading spilled
- * chunks one partition ahead of use, and aggregates into `agg` (group key =
- * dimension payload column). All library device memory counts against the
+/* The out-of-core join + aggregate (Section 3.2's exchange in front of a
+ * join, run on one GPU). Both sides stream from page-pool batches
+ * (tq_pagepool_stream); the dimension is filtered first, then the fact side
+ * follows.
+ *
+ * Adaptive Exchange (Section 3.2): the exchange in front of the join does not
+ * wait for its whole input before it chooses how to move it. Once the first
+ * dimension batches holding at least an eighth of the dimension's rows have
+ * been filtered, the kept fraction of those rows estimates the filtered
+ * dimension's size, and the exchange chooses one of two modes (plan.exchange
+ * may force either):
+ *  - single: one join table over every kept dimension row fits the budget, so
+ *    the fact side is not exchanged at all. Each staged fact batch probes that
+ *    table straight from its staging slot, aggregating as it goes: no fact
+ *    partitioning, no holders, no spills, no second pass. (On one GPU this is
+ *    what broadcasting the build side amounts to.)
+ *  - partitioned: both sides are hash partitioned into 2^log2_fanout
+ *    partitions whose rows are appended to per-partition holders of
+ *    fixed-size device chunks reserved from `budget`. When a reservation
+ *    fails, the resident chunks of the partition scheduled latest are copied
+ *    to pool pages (device -> host, on a stream of their own) and released
+ *    (Section 3.3.2: spill the data whose compute is furthest away). Pass 2
+ *    joins partition by partition in order, reloading spilled chunks one
+ *    partition ahead of use, and aggregates into `agg`.
+ * Dimension rows filtered before the choice are hash partitioned, so either
+ * mode can use them. When the exact kept count at the end of the dimension
+ * side shows that an automatic single choice no longer fits, the dimension's
+ * holders are released and the dimension side is streamed again,
+ * partitioned (stats.dim_restreams counts this). The group key is the
+ * dimension payload column. All library device memory counts against the
  * budget. */
+#define TQ_EXCHANGE_AUTO 0        /* choose from the estimate */
+#define TQ_EXCHANGE_PARTITIONED 1 /* always hash partition both sides */
+#define TQ_EXCHANGE_SINGLE 2      /* always one table (TQ_ENOMEM if it does not fit) */
 typedef struct {
   int32_t dim_key_col;     /* int64 */
   int32_t dim_payload_col; /* group id */
@@ -308,6 +330,7 @@ typedef struct {
   uint32_t join_flags;     /* TQ_UNIQUE_KEYS when the dimension keys are unique */
   size_t chunk_bytes;      /* device holder chunk size, a divisor of the pool's page size */
   int32_t nslots;          /* staging slots of the streaming passes (>= 2) */
+  int32_t exchange;        /* TQ_EXCHANGE_AUTO, _PARTITIONED or _SINGLE */
 } tq_ooc_plan;
 
 typedef struct {
@@ -315,7 +338,12 @@ typedef struct {
   int64_t spilled_chunks, reloaded_chunks;
   int64_t dim_rows_kept, fact_rows;
   int64_t peak_budget_bytes;
-  double ms_pass1, ms_pass2, ms_total; /* host wall clock */
+  double ms_pass1, ms_pass2, ms_total; /* host wall clock; single mode: pass 1 = dimension side and
+                                          table build, pass 2 = fact side */
+  int32_t exchange;                    /* the mode used: TQ_EXCHANGE_PARTITIONED or TQ_EXCHANGE_SINGLE */
+  int32_t dim_restreams;               /* times the dimension side was streamed again */
+  int64_t est_dim_rows;                /* the estimate of kept dimension rows (0 when the mode was forced) */
+  int64_t est_from_rows;               /* dimension rows filtered when the estimate was taken */
 } tq_ooc_stats;
 
 /* d_work: the device memory the call may use (work_bytes >= the budget's
@@ -324,7 +352,8 @@ typedef struct {
  * (domain, nsum); the call accumulates into it and leaves finalization to the
  * caller. Spilled chunks use free pool pages. Blocks until the work is done.
  * Returns TQ_ENOMEM if the budget cannot hold the fixed buffers plus one
- * partition's working set, or the pool has no page left to spill to. */
+ * partition's working set, or the pool has no page left to spill to, or a
+ * forced single table does not fit. */
 tq_status tq_ooc_join_agg(tq_pagepool* pool, const tq_batch* dim, int64_t n_dim_batches, const tq_batch* fact,
                           int64_t n_fact_batches, const tq_ooc_plan* plan, tq_budget* budget, void* d_work,
                           size_t work_bytes, void* d_state, tq_ooc_stats* stats, hipStream_t copy,

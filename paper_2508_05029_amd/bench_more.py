@@ -144,8 +144,12 @@ def bench_ooc(args):
     q = wl.JOIN_AGG_QUERY
     peak_link = _pinned_copy_peak()
     results = {}
-    for label, keep_all in (("all_columns", True), ("projected", False)):
-        job = pipeline.OocJoinAgg(q, dt, ft, budget, log2_fanout=8, chunk_bytes=4 << 20, nslots=3, keep_all=keep_all)
+    # the Adaptive Exchange as a caller gets it, then the partitioned exchange forced,
+    # carrying every fact column or only the ones the join reads
+    for label, keep_all, exchange in (("adaptive", True, "auto"), ("partitioned_all_columns", True, "partitioned"),
+                                      ("partitioned_projected", False, "partitioned")):
+        job = pipeline.OocJoinAgg(q, dt, ft, budget, log2_fanout=8, chunk_bytes=4 << 20, nslots=3, keep_all=keep_all,
+                                  exchange=exchange)
         st = job.run()
         torch.cuda.synchronize()
         r = job.result()
@@ -153,7 +157,7 @@ def bench_ooc(args):
         log(label, st.as_dict())
         del job
         torch.cuda.empty_cache()
-    st, r = results["all_columns"]
+    st, r = results["adaptive"]
     ms = st["ms_total"]
     in_bytes = fact_bytes + n_dim * 16
     link_gbs = st["bytes_h2d"] / (ms / 1e3) / 1e9
@@ -167,15 +171,21 @@ def bench_ooc(args):
         sdt.fill_numpy(sd)
         sft = HostTable(spool, wl.OOC_FACT_COLS, len(sf["fk"]), 100_000)
         sft.fill_numpy(sf)
-        sj = pipeline.OocJoinAgg(q, sdt, sft, 64 << 20, log2_fanout=6, chunk_bytes=256 << 10)
-        sj.run()
-        got = sj.result()
+        gots = {}
+        for exchange in ("auto", "partitioned"):
+            sj = pipeline.OocJoinAgg(q, sdt, sft, 64 << 20, log2_fanout=6, chunk_bytes=256 << 10, exchange=exchange)
+            sj.run()
+            gots[exchange] = (sj.result(), sj.stats)
+            del sj
         t1 = time.perf_counter()
         want = oracle.join_agg(sd, sf, q)
         tc = time.perf_counter() - t1
-        parity = {"sample": "2M fact x 500K dim rows, budget 64 MiB (spills)",
-                  "equal": got["sums"].tolist() == want["sums"].tolist() and got["count"].tolist() == want["count"].tolist(),
-                  "spilled_chunks": sj.stats.spilled_chunks}
+        parity = {"sample": "2M fact x 500K dim rows, budget 64 MiB: adaptive (one table) and forced partitioned "
+                            "(spills)",
+                  "equal": all(g["sums"].tolist() == want["sums"].tolist() and g["count"].tolist() == want["count"].tolist()
+                               for g, _ in gots.values()),
+                  "exchange_auto": gots["auto"][1].exchange,
+                  "spilled_chunks_partitioned": gots["partitioned"][1].spilled_chunks}
         cpu = {"value": round((2_000_000 * 44 + 500_000 * 16) / tc / 1e9, 4), "unit": "GB/s", "cores": 1,
                "kind": "oracle", "sample": f"2M x 500K rows of the same tables, {tc:.2f} s"}
         sdt.free()
@@ -186,12 +196,13 @@ def bench_ooc(args):
     out = _base("host-link GB/s out-of-core join-aggregate (% of PCIe and of the measured pinned-copy peak)",
                 link_gbs, "GB/s", args, ms, 1,
                 f"ooc_join_agg: fact {n_fact} rows x 6 cols (44 B/row) in 64 MiB pinned pages, dim {n_dim} rows, "
-                f"256 partitions, budget {budget / 1e9:.1f} GB",
+                f"Adaptive Exchange (one table when it fits, else 256 partitions), budget {budget / 1e9:.1f} GB",
                 {"input_bytes": in_bytes, "input_gbs": round(in_bytes / (ms / 1e3) / 1e9, 3),
                  "pct_pcie_theoretical": round(100 * link_gbs / PCIE_GBS, 2),
                  "pct_measured_pinned_copy": round(100 * link_gbs / peak_link, 2),
                  "measured_pinned_copy_gbs": round(peak_link, 2),
-                 "stats": st, "projected_variant": results["projected"][0],
+                 "stats": st, "partitioned_all_columns": results["partitioned_all_columns"][0],
+                 "partitioned_projected": results["partitioned_projected"][0],
                  "groups": len(r["count"]), "join_rows": r["join_rows"],
                  "roofline": {"bound": "host-link", "achieved": round(link_gbs, 3), "peak": PCIE_GBS, "unit": "GB/s",
                               "frac": round(link_gbs / PCIE_GBS, 4), "traffic": None,

@@ -125,6 +125,12 @@ class Driver {
 
   Side dim, fact;
   int phase = 1;     // 1: partitioning, 2: joining
+
+  // Adaptive Exchange: 0 while undecided, then TQ_EXCHANGE_PARTITIONED or TQ_EXCHANGE_SINGLE
+  int xmode = 0;
+  int64_t dim_total = 0, dim_seen = 0;  // dimension rows in all batches / filtered so far
+  void* s_table = nullptr;              // single mode: the one join table
+  tq_agg s_agg{};
   int pin_lo = 0, pin_hi = -1;  // partitions that must stay resident in pass 2
 
   // descriptors
@@ -495,6 +501,13 @@ class Driver {
     if ((s = read_back(d_count, 1))) return s;
     const int64_t kept = h_counts[0];
     st.dim_rows_kept += kept;
+    dim_seen += nrows;
+    if (xmode == TQ_EXCHANGE_SINGLE) {
+      // one table: the kept rows need no partitioning, they all go to the first holder
+      for (int q = 0; q <= nparts; q++) h_counts[q] = q == 0 ? 0 : kept;
+      char* src[2] = {reinterpret_cast<char*>(outs[0]), reinterpret_cast<char*>(outs[1])};
+      return append(dim, src, h_counts);
+    }
     char* out_key = tmp_b;
     char* out_pay = tmp_b + align_up((size_t)kept * 8, kAlign);
     tq_col pay = {outs[1], TQ_I64};
@@ -504,12 +517,88 @@ class Driver {
     if (s) return s;
     if ((s = read_back(d_off, nparts + 1))) return s;
     char* src[2] = {out_key, out_pay};
-    return append(dim, src, h_counts);
+    if ((s = append(dim, src, h_counts))) return s;
+    if (xmode == 0 && dim_seen * 8 >= dim_total) decide();
+    return TQ_OK;
+  }
+
+  // Adaptive Exchange, first phase (Section 3.2): the kept fraction of the
+  // dimension rows filtered so far, applied to all of them, estimates the
+  // filtered dimension; one table is chosen when that estimate, with a quarter
+  // more for its error, fits the arena beside the holders of its rows. On one
+  // GPU the host link bounds this path, so the budget is the only criterion:
+  // a single table saves the fact side's exchange whatever the table's size
+  // relative to the caches.
+  void decide() {
+    const int64_t est = dim_seen > 0 ? (int64_t)((double)st.dim_rows_kept * (double)dim_total / (double)dim_seen + 0.5) : 0;
+    st.est_dim_rows = est;
+    st.est_from_rows = dim_seen;
+    const int64_t rows = est + est / 4 + 1024;
+    const int64_t holder_chunks = (rows + dim.rows_per_chunk - 1) / dim.rows_per_chunk + nparts;
+    const size_t region = single_region_bytes(rows);
+    const int64_t region_chunks = (int64_t)((region + chunk_bytes - 1) / chunk_bytes);
+    xmode = holder_chunks + region_chunks <= n_chunks ? TQ_EXCHANGE_SINGLE : TQ_EXCHANGE_PARTITIONED;
+  }
+
+  static size_t gather_bytes_for(int64_t rows) { return 2 * align_up((size_t)std::max<int64_t>(rows, 1) * 8, kAlign); }
+  size_t single_region_bytes(int64_t rows) const {
+    return gather_bytes_for(rows) + tq_join_table_bytes(std::max<int64_t>(rows, 1), plan.load_factor);
+  }
+
+  // Single mode: gathers every kept dimension row into one contiguous copy and
+  // builds one table over it, then releases the holders. *fits is false (and
+  // nothing is enqueued) when the budget cannot hold the table and the copy
+  // beside the holders, or when holders were spilled.
+  tq_status single_table(bool* fits) {
+    *fits = false;
+    for (Holder& h : dim.parts)
+      for (ChunkRef& c : h.chunks)
+        if (c.dev < 0) return TQ_OK;
+    const int64_t n = st.dim_rows_kept;
+    const size_t table_bytes = tq_join_table_bytes(std::max<int64_t>(n, 1), plan.load_factor);
+    char* region;
+    tq_status s = take_region(single_region_bytes(n), &region, false);
+    if (s == TQ_ENOMEM) return TQ_OK;
+    if (s) return s;
+    *fits = true;
+    int64_t* g_key = reinterpret_cast<int64_t*>(region);
+    int64_t* g_pay = reinterpret_cast<int64_t*>(region + align_up((size_t)std::max<int64_t>(n, 1) * 8, kAlign));
+    s_table = region + gather_bytes_for(n);
+    if ((s = tq_join_table_init(s_table, table_bytes, compute))) return s;
+    descs.clear();
+    int64_t at = 0;
+    for (Holder& h : dim.parts)
+      for (ChunkRef& c : h.chunks) {
+        descs.push_back(CopyDesc{chunk_ptr(c.dev) + dim.off[0], g_key + at, c.rows, 8, 0});
+        descs.push_back(CopyDesc{chunk_ptr(c.dev) + dim.off[1], g_pay + at, c.rows, 8, 0});
+        at += c.rows;
+      }
+    if ((s = launch_copies())) return s;
+    tq_col pc = {g_pay, TQ_I64};
+    if ((s = tq_join_build(s_table, table_bytes, g_key, pc, at, nullptr, 0, nullptr, 0, plan.load_factor, 0,
+                           plan.join_flags, compute)))
+      return s;
+    return release_dim();
+  }
+
+  // Drops the dimension's holders: resident chunks return to the arena once
+  // `compute` has passed this point; spilled ones keep their pool pages until
+  // the call ends.
+  tq_status release_dim() {
+    std::vector<int64_t> ids;
+    for (Holder& h : dim.parts)
+      for (ChunkRef& c : h.chunks)
+        if (c.dev >= 0) ids.push_back(c.dev);
+    dim.parts.assign(nparts, Holder());
+    return retire(std::move(ids), compute);
   }
 
   tq_status fact_batch(const tq_col* cols, int32_t ncol, int64_t nrows) {
     if (nrows == 0) return TQ_OK;
     st.fact_rows += nrows;
+    if (xmode == TQ_EXCHANGE_SINGLE)  // no exchange: probe the staged batch where it lies
+      return tq_join_probe(s_table, static_cast<const int64_t*>(cols[plan.fact_key_col].data), nrows, cols, ncol, nullptr,
+                           0, nullptr, nullptr, 0, nullptr, &s_agg, compute);
     char* src[TQ_MAX_COLS];
     tq_col pay[TQ_MAX_COLS];
     void* outp[TQ_MAX_COLS];
@@ -598,9 +687,38 @@ class Driver {
 
     // ---- pass 1, dimension side
     phase = 1;
-    if ((s = tq_pagepool_stream(pool, dimb, nd, staging, max_batch * plan.nslots, plan.nslots, on_dim, this, copy, compute)))
-      return s;
-    for (int64_t i = 0; i < nd; i++) st.bytes_h2d += batch_bytes(dimb[i]);
+    for (int64_t i = 0; i < nd; i++) dim_total += dimb[i].nrows;
+    xmode = plan.exchange;  // TQ_EXCHANGE_AUTO (0) decides after the first batches
+    if ((s = stream_dim(dimb, nd, staging, max_batch))) return s;
+    if (xmode == 0) decide();
+    if (xmode == TQ_EXCHANGE_SINGLE) {
+      bool fits = false;
+      if ((s = single_table(&fits))) return s;
+      if (!fits) {
+        if (plan.exchange == TQ_EXCHANGE_SINGLE)
+          return fail(TQ_ENOMEM, "one table over %lld dimension rows does not fit the budget", (long long)st.dim_rows_kept);
+        // the estimate was too low: stream the dimension side again, partitioned
+        if ((s = release_dim())) return s;
+        xmode = TQ_EXCHANGE_PARTITIONED;
+        st.dim_restreams++;
+        st.dim_rows_kept = 0;
+        dim_seen = 0;
+        if ((s = stream_dim(dimb, nd, staging, max_batch))) return s;
+      }
+    }
+    st.exchange = xmode;
+    if (xmode == TQ_EXCHANGE_SINGLE) {
+      // ---- the fact side, probing the one table batch by batch
+      TQ_HIP(hipStreamSynchronize(compute));
+      auto t1 = std::chrono::steady_clock::now();
+      s_agg = tq_agg{d_state, plan.domain, plan.sums, plan.nsum};
+      if ((s = tq_pagepool_stream(pool, factb, nf, staging, max_batch * plan.nslots, plan.nslots, on_fact, this, copy,
+                                  compute)))
+        return s;
+      for (int64_t i = 0; i < nf; i++) st.bytes_h2d += batch_bytes(factb[i]);
+      TQ_HIP(hipStreamSynchronize(compute));
+      return finish_stats(t0, t1, std::chrono::steady_clock::now());
+    }
 
     // ---- pass 2 buffers, sized by the largest dimension partition and taken
     // now, while the arena is still mostly free: the gathered partition and its table
@@ -759,7 +877,19 @@ class Driver {
     }
     (void)hipEventDestroy(loaded);
     TQ_HIP(hipStreamSynchronize(compute));
-    auto t2 = std::chrono::steady_clock::now();
+    return finish_stats(t0, t1, std::chrono::steady_clock::now());
+  }
+
+  tq_status stream_dim(const tq_batch* dimb, int64_t nd, void* staging, size_t max_batch) {
+    tq_status s = tq_pagepool_stream(pool, dimb, nd, staging, max_batch * plan.nslots, plan.nslots, on_dim, this, copy,
+                                     compute);
+    if (s) return s;
+    for (int64_t i = 0; i < nd; i++) st.bytes_h2d += batch_bytes(dimb[i]);
+    return TQ_OK;
+  }
+
+  using Clock = std::chrono::steady_clock;
+  tq_status finish_stats(Clock::time_point t0, Clock::time_point t1, Clock::time_point t2) {
     st.ms_pass1 = std::chrono::duration<double, std::milli>(t1 - t0).count();
     st.ms_pass2 = std::chrono::duration<double, std::milli>(t2 - t1).count();
     st.ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
@@ -783,10 +913,12 @@ class Driver {
   }
 
   // A contiguous run of arena chunks (reserved from the budget) for pass-2 buffers.
-  tq_status take_region(size_t bytes, char** out) {
+  // Without `may_spill`, only the arena's free chunks are searched (after every
+  // pending release has completed) and TQ_ENOMEM is returned quietly.
+  tq_status take_region(size_t bytes, char** out, bool may_spill = true) {
     int64_t need = (int64_t)((bytes + chunk_bytes - 1) / chunk_bytes);
     for (int attempt = 0; attempt < 4; attempt++) {
-      while (reclaim_one(false) == TQ_OK) {
+      while (reclaim_one(!may_spill) == TQ_OK) {
       }
       std::vector<uint8_t> is_free((size_t)n_chunks, 0);
       for (int64_t id : free_chunks) is_free[(size_t)id] = 1;
@@ -807,6 +939,7 @@ class Driver {
           return TQ_OK;
         }
       }
+      if (!may_spill) return TQ_ENOMEM;
       // make room: spill pass-1 data of the last partitions, then retry
       phase = 2;
       pin_lo = 0;
@@ -834,6 +967,7 @@ extern "C" tq_status tq_ooc_join_agg(tq_pagepool* pool, const tq_batch* dim, int
   if (nd < 0 || nf < 1 || (nd > 0 && !dim) || !fact) return fail(TQ_EINVAL, "batch lists");
   if (plan->log2_fanout < 0 || plan->log2_fanout > 10) return fail(TQ_EINVAL, "log2_fanout outside [0, 10]");
   if (plan->nslots < 2 || plan->nslots > 8) return fail(TQ_EINVAL, "nslots outside [2, 8]");
+  if (plan->exchange < TQ_EXCHANGE_AUTO || plan->exchange > TQ_EXCHANGE_SINGLE) return fail(TQ_EINVAL, "exchange mode");
   size_t pb = tq_pagepool_page_bytes(pool);
   if (plan->chunk_bytes < 65536 || plan->chunk_bytes % 256 || pb % plan->chunk_bytes)
     return fail(TQ_EINVAL, "chunk_bytes must be a multiple of 256, at least 64 KiB, and divide the page size");

@@ -149,11 +149,13 @@ class OocJoinAgg:
 
     keep_all: carry every fact column through the exchange (as a generic
     exchange that does not know which columns the join needs would); else only
-    the key and the columns the sums read."""
+    the key and the columns the sums read. exchange: "auto" (the Adaptive
+    Exchange chooses one table or hash partitioning from an estimate taken on
+    the first dimension batches), "partitioned" or "single"."""
 
     def __init__(self, query, dim_table, fact_table, budget_bytes: int, log2_fanout: int = 8,
                  load_factor: float = 0.5, chunk_bytes: int = 4 << 20, nslots: int = 3, keep_all: bool = True,
-                 unique: bool = True, device="cuda"):
+                 unique: bool = True, exchange: str = "auto", device="cuda"):
         self.q = query
         self.dim, self.fact = dim_table, fact_table
         dn, fn = dim_table.names, fact_table.names
@@ -170,7 +172,8 @@ class OocJoinAgg:
                                ctypes.cast(self._preds, ctypes.POINTER(tq.PredS)), len(query.build_preds),
                                fn.index(query.probe_key), keep, ctypes.cast(self._sums, ctypes.POINTER(tq.ExprS)),
                                len(query.sums), query.domain, log2_fanout, load_factor,
-                               tq.TQ_UNIQUE_KEYS if unique else 0, chunk_bytes, nslots)
+                               tq.TQ_UNIQUE_KEYS if unique else 0, chunk_bytes, nslots,
+                               tq.EXCHANGE_MODES[exchange])
         self.budget = tq.Budget(budget_bytes)
         self.domain, self.nsum = query.domain, len(query.sums)
         # the group-by state and its outputs live outside the budgeted workspace

@@ -259,14 +259,15 @@ class OocPlan(ctypes.Structure):
                 ("fact_key_col", ctypes.c_int32), ("fact_keep_mask", ctypes.c_int32),
                 ("sums", ctypes.POINTER(ExprS)), ("nsum", ctypes.c_int32), ("domain", ctypes.c_int64),
                 ("log2_fanout", ctypes.c_int32), ("load_factor", ctypes.c_double), ("join_flags", ctypes.c_uint32),
-                ("chunk_bytes", ctypes.c_size_t), ("nslots", ctypes.c_int32)]
+                ("chunk_bytes", ctypes.c_size_t), ("nslots", ctypes.c_int32), ("exchange", ctypes.c_int32)]
 
 
 class OocStats(ctypes.Structure):
     _fields_ = [("bytes_h2d", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64), ("spilled_chunks", ctypes.c_int64),
                 ("reloaded_chunks", ctypes.c_int64), ("dim_rows_kept", ctypes.c_int64), ("fact_rows", ctypes.c_int64),
                 ("peak_budget_bytes", ctypes.c_int64), ("ms_pass1", ctypes.c_double), ("ms_pass2", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("exchange", ctypes.c_int32), ("dim_restreams", ctypes.c_int32),
+                ("est_dim_rows", ctypes.c_int64), ("est_from_rows", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -275,6 +276,8 @@ class OocStats(ctypes.Structure):
 BATCH_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Col), ctypes.c_int32,
                             ctypes.c_int64, ctypes.c_void_p)
 TQ_POOL_PAGEABLE = 1
+TQ_EXCHANGE_AUTO, TQ_EXCHANGE_PARTITIONED, TQ_EXCHANGE_SINGLE = 0, 1, 2
+EXCHANGE_MODES = {"auto": TQ_EXCHANGE_AUTO, "partitioned": TQ_EXCHANGE_PARTITIONED, "single": TQ_EXCHANGE_SINGLE}
 
 _more_sig = {
     "tq_pagepool_create": (_i32, [_sz, _i64, _u32, ctypes.POINTER(ctypes.c_void_p)]),

@@ -75,7 +75,8 @@ def test_ooc_join_agg_matches_oracle(budget_mb, bits, keep_all):
     d, f, dt, ft = _ooc_tables(pool, 100_000, 600_000, 50_000, seed=31)
     q = wl.JOIN_AGG_QUERY
     want = oracle.join_agg(d, f, q)
-    job = pipeline.OocJoinAgg(q, dt, ft, budget_mb << 20, log2_fanout=bits, chunk_bytes=64 << 10, keep_all=keep_all)
+    job = pipeline.OocJoinAgg(q, dt, ft, budget_mb << 20, log2_fanout=bits, chunk_bytes=64 << 10, keep_all=keep_all,
+                              exchange="partitioned")
     st = job.run()
     got = job.result()
     say(st.as_dict())
@@ -86,6 +87,7 @@ def test_ooc_join_agg_matches_oracle(budget_mb, bits, keep_all):
     assert st.fact_rows == 600_000
     assert st.dim_rows_kept == int(((d["date"] >= 730) & (d["date"] <= 1094)).sum())
     assert st.peak_budget_bytes <= budget_mb << 20
+    assert st.exchange == tq.TQ_EXCHANGE_PARTITIONED and st.dim_restreams == 0 and st.est_dim_rows == 0
     if budget_mb <= 16:
         assert st.spilled_chunks > 0 and st.reloaded_chunks > 0  # the budget forced spilling
     else:
@@ -108,4 +110,106 @@ def test_ooc_budget_too_small_fails_cleanly():
     dt.free()
     ft.free()
     assert pool.free_pages() == 600
+    pool.close()
+
+
+def _check_result(job, d, f, q):
+    want = oracle.join_agg(d, f, q)
+    got = job.result()
+    assert got["join_rows"] == want["join_rows"]
+    assert got["keys"].tolist() == want["keys"].tolist()
+    assert got["count"].tolist() == want["count"].tolist()
+    assert got["sums"].tolist() == want["sums"].tolist()
+
+
+def _kept(d):
+    return int(((d["date"] >= 730) & (d["date"] <= 1094)).sum())
+
+
+@pytest.mark.parametrize("bits,keep_all", [(4, True), (0, False)])
+def test_ooc_adaptive_exchange_chooses_one_table(bits, keep_all):
+    """A filtered dimension that fits the budget: the Adaptive Exchange takes
+    one table, the fact side is probed as it streams (nothing spilled or
+    reloaded), and the estimate from the first batches is close."""
+    say(f"ooc adaptive single bits={bits} keep_all={keep_all}")
+    pool = tq.PagePool(256 << 10, 2000, pinned=True)
+    d, f, dt, ft = _ooc_tables(pool, 100_000, 600_000, 10_000, seed=37)
+    q = wl.JOIN_AGG_QUERY
+    job = pipeline.OocJoinAgg(q, dt, ft, 64 << 20, log2_fanout=bits, chunk_bytes=64 << 10, keep_all=keep_all)
+    st = job.run()
+    say(st.as_dict())
+    _check_result(job, d, f, q)
+    assert st.exchange == tq.TQ_EXCHANGE_SINGLE and st.dim_restreams == 0
+    assert st.spilled_chunks == 0 and st.reloaded_chunks == 0 and st.bytes_d2h == 0
+    assert st.dim_rows_kept == _kept(d) and st.fact_rows == 600_000
+    # decided after the first batches holding an eighth of the rows (10K-row batches: two of ten)
+    assert st.est_from_rows == 20_000
+    assert abs(st.est_dim_rows - _kept(d)) <= 0.1 * _kept(d)
+    assert st.peak_budget_bytes <= 64 << 20
+    assert job.budget.used == 0
+    dt.free()
+    ft.free()
+    assert pool.free_pages() == 2000
+    pool.close()
+
+
+def test_ooc_adaptive_exchange_partitions_when_one_table_does_not_fit():
+    say("ooc adaptive partitioned")
+    pool = tq.PagePool(256 << 10, 3000, pinned=True)
+    d, f, dt, ft = _ooc_tables(pool, 1_000_000, 600_000, 50_000, seed=41)
+    q = wl.JOIN_AGG_QUERY
+    job = pipeline.OocJoinAgg(q, dt, ft, 16 << 20, log2_fanout=4, chunk_bytes=64 << 10)
+    st = job.run()
+    say(st.as_dict())
+    _check_result(job, d, f, q)
+    assert st.exchange == tq.TQ_EXCHANGE_PARTITIONED and st.dim_restreams == 0
+    assert st.est_from_rows == 150_000 and abs(st.est_dim_rows - _kept(d)) <= 0.1 * _kept(d)
+    assert st.spilled_chunks > 0 and st.peak_budget_bytes <= 16 << 20
+    assert job.budget.used == 0
+    dt.free()
+    ft.free()
+    assert pool.free_pages() == 3000
+    pool.close()
+
+
+def test_ooc_adaptive_exchange_restreams_after_a_low_estimate():
+    """Dimension rows sorted by date: the first batches keep nothing, the
+    estimate says one table, and the exact count at the end of the dimension
+    side does not fit, so the dimension is streamed again and partitioned."""
+    say("ooc adaptive restream")
+    pool = tq.PagePool(256 << 10, 3000, pinned=True)
+    d, f = wl.ooc_tables_numpy(600_000, 1_000_000, 43)
+    order = np.argsort(d["date"], kind="stable")
+    d = {k: v[order] for k, v in d.items()}
+    dt = HostTable(pool, wl.OOC_DIM_COLS, 1_000_000, 50_000)
+    dt.fill_numpy(d)
+    ft = HostTable(pool, wl.OOC_FACT_COLS, 600_000, 50_000)
+    ft.fill_numpy(f)
+    q = wl.JOIN_AGG_QUERY
+    job = pipeline.OocJoinAgg(q, dt, ft, 16 << 20, log2_fanout=4, chunk_bytes=64 << 10)
+    st = job.run()
+    say(st.as_dict())
+    _check_result(job, d, f, q)
+    assert st.est_dim_rows == 0 and st.est_from_rows == 150_000
+    assert st.exchange == tq.TQ_EXCHANGE_PARTITIONED and st.dim_restreams == 1
+    assert st.dim_rows_kept == _kept(d)
+    assert st.peak_budget_bytes <= 16 << 20
+    assert job.budget.used == 0
+    dt.free()
+    ft.free()
+    assert pool.free_pages() == 3000
+    pool.close()
+
+
+def test_ooc_forced_single_table_that_does_not_fit_fails_cleanly():
+    pool = tq.PagePool(256 << 10, 3000, pinned=True)
+    d, f, dt, ft = _ooc_tables(pool, 1_000_000, 100_000, 50_000, seed=47)
+    job = pipeline.OocJoinAgg(wl.JOIN_AGG_QUERY, dt, ft, 16 << 20, log2_fanout=4, chunk_bytes=64 << 10, exchange="single")
+    with pytest.raises(tq.TqError) as e:
+        job.run()
+    assert e.value.status == tq.TQ_ENOMEM
+    assert job.budget.used == 0
+    dt.free()
+    ft.free()
+    assert pool.free_pages() == 3000
     pool.close()
