@@ -143,11 +143,18 @@ tq_status tq_join_table_init(void* d_table, size_t bytes, hipStream_t stream);
  * optional predicates over `filt` (the dimension filter fused into the build).
  * `skip` high hash bits are ignored by the slot index (set it to the partition
  * bits when the input is one hash partition). Latches TQ_EFULL if the rows do
- * not fit in the buffer. Three or four kernel launches on `stream`, none of
- * which allocates; builds into one buffer must not overlap. */
+ * not fit in the buffer; the header still records how many rows passed the
+ * filter (tq_join_table_rows), and nothing is inserted. Three or four kernel
+ * launches on `stream`, none of which allocates; builds into one buffer must
+ * not overlap. */
 tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_col payload, int64_t n,
                         const tq_col* filt, int32_t nfilt, const tq_pred* p, int32_t np, double load_factor,
                         int32_t skip, uint32_t flags, hipStream_t stream);
+
+/* Rows that passed the last build's filter, read from a table's header after
+ * the build has completed (synchronises `stream`); set even when the build
+ * latched TQ_EFULL. */
+tq_status tq_join_table_rows(const void* d_table, int64_t* rows, hipStream_t stream);
 
 /* Fused group-by applied to probe matches: group key = the matched build
  * payload, sums = expressions over the probe-side columns passed to
@@ -170,7 +177,8 @@ typedef struct {
  *                of one table must not overlap.
  *   agg != NULL  aggregate the matches into agg->d_state instead (the
  *                state's COUNT column counts them); the pair outputs and
- *                d_out_count must be NULL. */
+ *                d_out_count must be NULL.
+ * A table whose build latched an error matches nothing. */
 tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_t n, const tq_col* cols,
                         int32_t ncol, const tq_pred* p, int32_t np, int64_t* d_out_probe_row,
                         int64_t* d_out_payload, int64_t capacity, int64_t* d_out_count, const tq_agg* agg,
@@ -436,7 +444,18 @@ tq_status tq_batched_run_per_instance(const tq_batch_query* q, const tq_instance
  * of `workers` worker threads, each with its own HIP streams, so requests
  * that arrive while others run overlap on the device; their tables and
  * partial aggregates stay resident until they complete. workers = 1 is the
- * one-at-a-time FIFO baseline. */
+ * one-at-a-time FIFO baseline.
+ *
+ * Reservations (Section 3.3.2): a join request's table is sized for the rows
+ * its dimension window keeps after the filter. With estimate = 0 that is the
+ * whole window (the worst case). With estimate = 1 each shape keeps a history
+ * of the kept fraction of its last 16 completed joins, and a request reserves
+ * a table for its window times the largest of those fractions, plus a quarter
+ * and 1024 rows (the worst case while the history is empty). A request whose
+ * table then proves too small (the build latches TQ_EFULL and has recorded
+ * the exact kept count) releases its reservation and is queued again ahead
+ * of new arrivals, reserving for that exact count; its result counts the
+ * retry. Work is not split into smaller tasks. */
 typedef struct {
   int32_t shape;     /* 0, 1 or 2 */
   int64_t fact_first; /* shapes 0, 1: first row (a multiple of 16); shape 2: first batch */
@@ -473,6 +492,7 @@ typedef struct {
   int64_t n_fact_batches;
   int32_t fact_map[4];
   int32_t nslots;
+  int32_t estimate; /* 1: reserve join tables from the memory-use history; 0: for the whole window */
 } tq_serve_tables;
 
 typedef struct {
@@ -480,6 +500,9 @@ typedef struct {
   int32_t status;        /* TQ_OK or the error of the request */
   int32_t worker;
   int64_t ngroups;
+  int64_t reserved_bytes; /* the device memory of the run that completed it */
+  int32_t retries;        /* runs that ended with a table too small for the kept rows */
+  int32_t pad;
 } tq_request_result;
 
 /* Runs all requests and blocks until they are done. d_arena / arena_bytes is

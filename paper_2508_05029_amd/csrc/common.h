@@ -109,7 +109,7 @@ struct TableHeader {
   int32_t regions;   // 1: the last build filled each region in LDS; 0: it inserted with global CAS
   int32_t alt;       // 1: the tags and slots in use are the build scratch's (see scratch_alt_tags)
   int32_t ovf;       // set during a build when a region's rows do not fit it
-  int32_t bloom_log2w;  // the build's Bloom filter has 2^bloom_log2w 64-bit words; 0: none
+  int32_t bloom_log2w;  // the build's Bloom filter has 2^bloom_log2w 32-bit words; 0: none
 };
 static_assert(sizeof(TableHeader) <= kHeaderBytes, "header");
 

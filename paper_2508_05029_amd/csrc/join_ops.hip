@@ -424,7 +424,7 @@ template <int MODE, int NC, int NE>
 __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const TableHeader* h, const int64_t* pkeys, int64_t n, RowPlan P,
                                                          AggTarget T) {
   extern __shared__ __align__(16) char smem[];
-  if (h->magic != kTableMagic) return;
+  if (h->magic != kTableMagic || h->err) return;  // a failed build inserted nothing: no row can match
   if (!state_matches(T)) return;
   LdsAgg<MODE> agg;
   agg.init(T, smem);
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   constexpr int R = kPipeRows;
   __shared__ uint32_t bloom[BLOOM ? kBloomWordsMax : 1];
   extern __shared__ __align__(16) char smem[];
-  if (h->magic != kTableMagic) return;
+  if (h->magic != kTableMagic || h->err) return;  // a failed build inserted nothing: no row can match
   if (!state_matches(T)) return;
   const int log2w = BLOOM ? h->bloom_log2w : 0;
   const int nbw = log2w ? 1 << log2w : 0;
@@ -721,7 +721,8 @@ __global__ __launch_bounds__(kBlock) void k_probe_count(const TableHeader* h, co
   Probe pr;
   pr.setup(h);
   const DCol kc = {pkeys, 8};
-  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
+  // a failed build inserted nothing: its rows count no match (and its tags are not cleared)
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = h->err ? lo : min(n, lo + per);
   int64_t c = 0;
   for (int64_t r0 = lo + threadIdx.x * kRows; r0 < hi; r0 += kChunk) {
     const bool full = r0 + kRows <= hi;
@@ -746,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_write(const TableHeader* h, co
                                                         int64_t per, RowPlan P, const int64_t* base, int64_t* out_row,
                                                         int64_t* out_pay, int64_t capacity) {
   __shared__ int64_t ws[kBlock / kWave];
-  if (h->magic != kTableMagic) return;
+  if (h->magic != kTableMagic || h->err) return;  // a failed build: every block counted no match
   Probe pr;
   pr.setup(h);
   const DCol kc = {pkeys, 8};
@@ -835,6 +836,16 @@ tq_status tq_join_table_init(void* d_table, size_t bytes, hipStream_t stream) {
   if (cap_max == 0) return fail(TQ_EINVAL, "table buffer of %zu bytes is too small", bytes);
   hipLaunchKernelGGL(k_table_init, dim3(1), dim3(1), 0, stream, static_cast<TableHeader*>(d_table), cap_max);
   TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+tq_status tq_join_table_rows(const void* d_table, int64_t* rows, hipStream_t stream) {
+  if (!d_table || !rows) return fail(TQ_EINVAL, "NULL argument");
+  TableHeader hdr;
+  TQ_HIP(hipMemcpyAsync(&hdr, d_table, sizeof hdr, hipMemcpyDeviceToHost, stream));
+  TQ_HIP(hipStreamSynchronize(stream));
+  if (hdr.magic != kTableMagic) return fail(TQ_EINVAL, "not a join table");
+  *rows = hdr.n;
   return TQ_OK;
 }
 

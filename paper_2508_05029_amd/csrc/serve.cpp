@@ -1,10 +1,12 @@
-// The serving loop: admission by device-memory budget, worker threads with
-// their own streams, per-request latency stamps.
+// The serving loop: admission by device-memory budget (join tables reserved
+// from a history of the kept fraction, with a retry when that proves too
+// small), worker threads with their own streams, per-request latency stamps.
 #include <string.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -86,7 +88,7 @@ struct Server {
   std::mutex mu;
   std::condition_variable cv;
   struct Slot {
-    int64_t job = -1;
+    int64_t job = -1, rows = 0;
     size_t off = 0, bytes = 0;
     bool busy = false;
   };
@@ -101,12 +103,42 @@ struct Server {
 
   double now_s() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
-  Plan plan_of(const tq_request& q) const {
+  // Memory-use history (Section 3.3.2): the kept fraction of the dimension
+  // window of the last kHist completed joins of each shape.
+  static constexpr int kHist = 16;
+  struct History {
+    double f[kHist];
+    int n = 0, at = 0;
+    void add(double x) {
+      f[at] = x;
+      at = (at + 1) % kHist;
+      n = std::min(n + 1, kHist);
+    }
+  } hist[3];
+  std::vector<int64_t> exact;  // per request: kept rows recorded by a build that did not fit, else -1
+  std::vector<int32_t> retries;
+  std::vector<double> first_start;  // per request: when its first run started (-1 before)
+  std::deque<int64_t> again;   // requests to run again, ahead of new arrivals
+
+  // The rows a request's table is sized for (called with `mu` held).
+  int64_t table_rows(int64_t i) const {
+    const tq_request& q = reqs[i];
+    if (q.shape == 0) return 0;
+    if (exact[(size_t)i] >= 0) return exact[(size_t)i];
+    const History& h = hist[q.shape];
+    if (!T.estimate || h.n == 0) return q.n_dim;
+    double fmax = 0;
+    for (int j = 0; j < h.n; j++) fmax = std::max(fmax, h.f[j]);
+    const double est = (double)q.n_dim * fmax * 1.25 + 1024.0;
+    return est >= (double)q.n_dim ? q.n_dim : (int64_t)est;
+  }
+
+  Plan plan_of(const tq_request& q, int64_t table_rows) const {
     Plan p{};
     p.domain = q.shape == 0 ? T.fg_domain : T.join_domain;
     p.nsum = q.shape == 0 ? T.fg_nsum : T.join_nsum;
     p.state_bytes = tq_groupby_state_bytes(p.domain, p.nsum);
-    p.table_bytes = q.shape == 0 ? 0 : tq_join_table_bytes(q.n_dim, T.load_factor);
+    p.table_bytes = q.shape == 0 ? 0 : tq_join_table_bytes(table_rows, T.load_factor);
     size_t staging = 0;
     if (q.shape == 2) {
       size_t mx = 0;
@@ -149,8 +181,13 @@ struct Server {
                          nullptr, 0, nullptr, &c->agg, compute);
   }
 
-  tq_status execute(const tq_request& q, char* base, hipStream_t compute, hipStream_t copy, int64_t idx) {
-    Plan p = plan_of(q);
+  // Runs request idx in the region at `base` (planned for `rows` table rows).
+  // *kept gets the rows its dimension window kept (-1 for shape 0). Returns
+  // TQ_EFULL, with no result written, when the table was too small for them.
+  tq_status execute(const tq_request& q, char* base, int64_t rows, hipStream_t compute, hipStream_t copy, int64_t idx,
+                    int64_t* kept) {
+    *kept = -1;
+    Plan p = plan_of(q, rows);
     void* state = base + p.state;
     int64_t* keys = reinterpret_cast<int64_t*>(base + p.keys);
     int64_t* count = reinterpret_cast<int64_t*>(base + p.count);
@@ -188,6 +225,12 @@ struct Server {
       }
     }
     if ((s = tq_groupby_finalize(state, keys, count, sums, avg, ng, compute))) return s;
+    if (q.shape != 0) {
+      if ((s = tq_join_table_rows(base + p.table, kept, compute))) return s;
+      const tq_status t = tq_check(base + p.table, compute);
+      if (t == TQ_EFULL) return t;  // nothing was inserted; the probe matched nothing
+      if (t) return t;
+    }
     if ((s = tq_check(state, compute))) return s;
     int64_t g = 0;
     TQ_HIP(hipMemcpyAsync(&g, ng, 8, hipMemcpyDeviceToHost, compute));
@@ -213,7 +256,7 @@ struct Server {
     bool ok = hipStreamCreateWithFlags(&compute, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&copy, hipStreamNonBlocking) == hipSuccess;
     for (;;) {
-      int64_t job;
+      int64_t job, rows;
       size_t off, bytes;
       {
         std::unique_lock<std::mutex> lk(mu);
@@ -222,23 +265,39 @@ struct Server {
         job = slots[w].job;
         off = slots[w].off;
         bytes = slots[w].bytes;
+        rows = slots[w].rows;
       }
-      res[job].start_s = now_s();
-      res[job].worker = w;
-      tq_status s = ok ? execute(reqs[job], arena_base + off, compute, copy, job) : TQ_EHIP;
+      const double start = now_s();
+      int64_t kept = -1;
+      tq_status s = ok ? execute(reqs[job], arena_base + off, rows, compute, copy, job, &kept) : TQ_EHIP;
       if (s) {
         (void)hipStreamSynchronize(compute);
         (void)hipStreamSynchronize(copy);
       }
-      res[job].status = s;
-      res[job].end_s = now_s();
+      // a table too small for the kept rows, sized from the history: run again for the exact count
+      const bool retry = s == TQ_EFULL && kept > rows && exact[(size_t)job] < 0;
       {
         std::lock_guard<std::mutex> lk(mu);
         arena.release(off, bytes);
         tq_budget_release(budget, bytes);
         slots[w].job = -1;
         slots[w].busy = false;
-        completed++;
+        if (first_start[(size_t)job] < 0) first_start[(size_t)job] = start;
+        if (retry) {
+          exact[(size_t)job] = kept;
+          retries[(size_t)job]++;
+          again.push_back(job);
+        } else {
+          const tq_request& q = reqs[job];
+          if (s == TQ_OK && q.shape != 0 && q.n_dim > 0 && kept >= 0) hist[q.shape].add((double)kept / (double)q.n_dim);
+          res[job].start_s = first_start[(size_t)job];
+          res[job].worker = w;
+          res[job].status = s;
+          res[job].reserved_bytes = (int64_t)bytes;
+          res[job].retries = retries[(size_t)job];
+          res[job].end_s = now_s();
+          completed++;
+        }
       }
       cv.notify_all();
     }
@@ -248,6 +307,9 @@ struct Server {
 
   tq_status run(int workers) {
     slots.assign(workers, Slot());
+    exact.assign((size_t)n, -1);
+    retries.assign((size_t)n, 0);
+    first_start.assign((size_t)n, -1.0);
     for (int64_t i = 0; i < n; i++) {
       res[i] = tq_request_result{};
       res[i].status = TQ_OK;
@@ -258,8 +320,11 @@ struct Server {
     int64_t next = 0;
     std::unique_lock<std::mutex> lk(mu);
     while (completed < n) {
-      if (next < n) {
-        double wait = reqs[next].arrival_s - now_s();
+      // requests to run again come first, then arrivals in order
+      const bool rerun = !again.empty();
+      if (rerun || next < n) {
+        const int64_t job = rerun ? again.front() : next;
+        double wait = rerun ? 0.0 : reqs[job].arrival_s - now_s();
         if (wait > 0) {
           cv.wait_for(lk, std::chrono::duration<double>(wait));
           continue;
@@ -268,19 +333,26 @@ struct Server {
         for (int w = 0; w < workers && idle < 0; w++)
           if (!slots[w].busy) idle = w;
         if (idle >= 0) {
-          Plan p = plan_of(reqs[next]);
+          const int64_t rows = table_rows(job);
+          Plan p = plan_of(reqs[job], rows);
           size_t off;
+          auto taken = [&] {
+            if (rerun) again.pop_front();
+            else next++;
+          };
           if (p.total > tq_budget_cap(budget)) {  // can never fit: fail it rather than block the queue
-            res[next].status = TQ_ENOMEM;
-            res[next].start_s = res[next].end_s = now_s();
-            next++;
+            res[job].status = TQ_ENOMEM;
+            res[job].retries = retries[(size_t)job];
+            res[job].start_s = first_start[(size_t)job] >= 0 ? first_start[(size_t)job] : now_s();
+            res[job].end_s = now_s();
+            taken();
             completed++;
             continue;
           }
           if (tq_budget_reserve(budget, p.total) == TQ_OK) {
             if (arena.alloc(p.total, &off)) {
-              slots[idle] = Slot{next, off, p.total, true};
-              next++;
+              slots[idle] = Slot{job, rows, off, p.total, true};
+              taken();
               cv.notify_all();
               continue;
             }

@@ -358,13 +358,17 @@ class ServingSetup:
     A request of n fact rows reads a seeded window of its shape's base tables;
     join requests read a dimension window of n / 4 rows."""
 
-    def __init__(self, n0, n_dim, n1, n2, batch_rows, pool, seed=None, device="cuda", load_factor=0.5, nslots=3):
+    def __init__(self, n0, n_dim, n1, n2, batch_rows, pool, seed=None, device="cuda", load_factor=0.5, nslots=3,
+                 estimate=True, dim_sorted_by=None):
         from .datagen import workloads as wl
         from .hosttable import HostTable
         seed = wl.SERVE_SEED if seed is None else seed
         self.wl = wl
         self.fg = wl.filter_groupby_tables(n0, seed=seed + 10)
         self.dim, self.fact = wl.join_agg_tables(n_dim, n1, seed=seed + 11)
+        if dim_sorted_by is not None:  # a dimension whose windows keep very different fractions
+            order = np.argsort(self.dim[dim_sorted_by], kind="stable")
+            self.dim = {k: v[order] for k, v in self.dim.items()}
         self.hdim, self.hfact = wl.ooc_tables_numpy(n2, n_dim, seed=seed + 12)
         self.fg_dev = to_device(self.fg, device)
         self.dim_dev = to_device(self.dim, device)
@@ -411,6 +415,7 @@ class ServingSetup:
         T.fact_batches = ctypes.cast(self._batches[0], ctypes.c_void_p)
         T.n_fact_batches = len(self.host.batches)
         T.nslots = nslots
+        T.estimate = 1 if estimate else 0
         self.T = T
 
     def requests(self, reqs, time_scale=1.0):

@@ -75,6 +75,7 @@ def lib():
             "tq_hash_partition": (_i32, [_vp, _vp, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
             "tq_join_table_bytes": (_sz, [_i64, _f64]),
             "tq_join_table_init": (_i32, [_vp, _sz, _vp]),
+            "tq_join_table_rows": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64), _vp]),
             "tq_join_build": (_i32, [_vp, _sz, _vp, Col, _i64, _vp, _i32, _vp, _i32, _f64, _i32, _u32, _vp]),
             "tq_join_probe": (_i32, [_vp, _vp, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp]),
             "tq_groupby_state_bytes": (_sz, [_i64, _i32]),
@@ -191,6 +192,12 @@ def _nbytes(t: torch.Tensor) -> int:
 
 def join_table_init(table, stream=None):
     _check(lib().tq_join_table_init(table.data_ptr(), _nbytes(table), _stream(stream)))
+
+
+def join_table_rows(table, stream=None) -> int:
+    r = ctypes.c_int64()
+    _check(lib().tq_join_table_rows(table.data_ptr(), ctypes.byref(r), _stream(stream)))
+    return r.value
 
 
 def join_build(table, keys, payload, n, filt_cols=(), ps=(), load_factor=0.5, skip=0, flags=0, stream=None):
@@ -498,7 +505,7 @@ class ServeTables(ctypes.Structure):
                 ("fact_ncol", ctypes.c_int32), ("join_sums", ExprS * 2), ("join_nsum", ctypes.c_int32),
                 ("join_domain", ctypes.c_int64), ("load_factor", ctypes.c_double), ("pool", ctypes.c_void_p),
                 ("fact_batches", ctypes.c_void_p), ("n_fact_batches", ctypes.c_int64), ("fact_map", ctypes.c_int32 * 4),
-                ("nslots", ctypes.c_int32)]
+                ("nslots", ctypes.c_int32), ("estimate", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -508,7 +515,8 @@ class Request(ctypes.Structure):
 
 class RequestResult(ctypes.Structure):
     _fields_ = [("start_s", ctypes.c_double), ("end_s", ctypes.c_double), ("status", ctypes.c_int32),
-                ("worker", ctypes.c_int32), ("ngroups", ctypes.c_int64)]
+                ("worker", ctypes.c_int32), ("ngroups", ctypes.c_int64), ("reserved_bytes", ctypes.c_int64),
+                ("retries", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def serve_run(tables: ServeTables, reqs, workers: int, budget: Budget, arena, max_groups: int):
