@@ -331,7 +331,9 @@ def bench_serving(args):
         out[label] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                       "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                       "mean_ms": round(float(lat.mean()) * 1e3, 3), "qps": round(n / span, 2), "failed": bad,
-                      "workers": workers}
+                      "workers": workers,
+                      "mean_reserved_mib": round(float(np.mean([res[i].reserved_bytes for i in range(n)])) / 2**20, 2),
+                      "retries": int(sum(res[i].retries for i in range(n)))}
         log(label, out[label])
     setup.host.free()
     pool.close()
