@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 PROBE_COUNTERS = {
     "sources": ["paper_2508_05029_amd/csrc/join_ops.hip", "paper_2508_05029_amd/csrc/table.h",
                 "paper_2508_05029_amd/csrc/groupby.h", "paper_2508_05029_amd/csrc/common.h"],
-    "sha1": "6adcc0707dcfb4a872538d298c4782cec263c838",
-    "fetch_kib": 115234.5, "fetch_scale": 2.000,
+    "sha1": "60969f08d57fb98ce04129c81218f47ed21579a6",
+    "fetch_kib": 115298.7, "fetch_scale": 2.000,
     "write_kib": 104.0, "write_scale": 0.995,
 }
 
@@ -115,14 +115,14 @@ def bench_join_agg(args):
         for j, k in enumerate(ev):
             ev[k].append((marks[j], marks[j + 1]))
     kern_ms = {k: float(np.mean(events_ms(v))) for k, v in ev.items()}
-    # the probe alone: back-to-back launches between two events on its stream
-    # (its state just accumulates; every timed step below starts from a fresh one)
+    # the probe alone: back-to-back launches between two events on its stream, over the
+    # rotating copies so that no launch finds its columns in the Infinity Cache (its state
+    # just accumulates; every timed step below starts from a fresh one)
     k_probe = 20
-    f = copies[0][1]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(k_probe):
-        ja.probe(f)
+    for i in range(k_probe):
+        ja.probe(copies[i % len(copies)][1])
     e1.record(stream)
     kern_ms["probe"] = events_ms([(e0, e1)])[0] / k_probe
 

@@ -322,8 +322,11 @@ def bench_serving(args):
     reqs = wl.serving_requests(n, qps=lam)
     R = setup.requests(reqs)
     out = {}
-    for label, workers in (("fifo", 1), ("continuous", args.workers)):
+    # the third run reserves every join table for its whole window (no memory-use history)
+    for label, workers, est in (("fifo", 1, 1), ("continuous", args.workers, 1),
+                                ("continuous_whole_window_reservations", args.workers, 0)):
         b = tq.Budget(budget_bytes)
+        setup.T.estimate = est
         res, *_ = tq.serve_run(setup.T, R, workers, b, arena, 25)
         lat = np.array([res[i].end_s - R[i].arrival_s for i in range(n)])
         bad = sum(res[i].status != 0 for i in range(n))
@@ -343,6 +346,7 @@ def bench_serving(args):
                  f"serving: {n} requests, shapes 0/1/2 uniform, fact rows log-uniform 1e4..1e8 (windows of "
                  f"{nbase}-row base tables), Poisson arrivals at 0.8 x the FIFO rate ({lam:.1f}/s), 64 GB budget",
                  {"p50_ms": c["p50_ms"], "p99_ms": c["p99_ms"], "fifo": out["fifo"], "continuous": c,
+                  "continuous_whole_window_reservations": out["continuous_whole_window_reservations"],
                   "calibrated_fifo_qps": round(mu, 2), "roofline": None, "cpu_baseline": None})
 
 
