@@ -10,9 +10,12 @@ consecutive steps do not find their input in the 256 MiB Infinity Cache.
 
 value = input bytes the query must read (16 B per dimension row + 24 B per fact
 row = 168 MB) / wall time per step, in GB/s. Steps are replayed from HIP graphs
-(several steps per graph) so that host launch cost does not set the pace.
+(several steps per graph) so that host launch cost does not set the pace, and
+consecutive steps alternate between --streams streams, each with its own table
+and group-by state (several compute streams, each running whole tasks, as the
+paper's executor does), so that one step's short kernels overlap another's.
 
-Prints ONE JSON line. Other workloads: --workload filter_groupby | ooc | batched | serving.
+Prints ONE JSON line. Other workloads: --workload filter_groupby | ooc | batched | serving | scaling | copy.
 """
 import argparse
 import json
@@ -87,6 +90,9 @@ def bench_join_agg(args):
     copies = [(pipeline.to_device(dim), pipeline.to_device(fact)) for _ in range(args.copies)]
     ja = pipeline.JoinAgg(q, n_dim, args.load_factor)
     stream = torch.cuda.current_stream()
+    nstreams = max(1, args.streams)
+    jas = [ja] + [pipeline.JoinAgg(q, n_dim, args.load_factor) for _ in range(nstreams - 1)]
+    extra_streams = [torch.cuda.Stream() for _ in range(nstreams - 1)]
 
     def step(i):
         d, f = copies[i % len(copies)]
@@ -126,46 +132,65 @@ def bench_join_agg(args):
     e1.record(stream)
     kern_ms["probe"] = events_ms([(e0, e1)])[0] / k_probe
 
-    # graph: args.graph_steps consecutive steps per replay, rotating the copies
+    # graph: args.graph_steps consecutive steps per replay, rotating the copies; step i
+    # runs on stream i % nstreams with that stream's table and state
     gs = args.graph_steps
-    side = torch.cuda.Stream()
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
+
+    def steps_on_streams(ns):
+        cur = torch.cuda.current_stream()
+        for s in extra_streams[:ns - 1]:
+            s.wait_stream(cur)
         for i in range(gs):
-            step(i)
-    stream.wait_stream(side)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        for i in range(gs):
-            step(i)
-    torch.cuda.synchronize()
-    for _ in range(max(1, args.warmup // gs)):
-        graph.replay()
-    torch.cuda.synchronize()
-    reps = max(1, args.steps // gs)
-    steps = reps * gs
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        graph.replay()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / steps
+            k = i % ns
+            d, f = copies[i % len(copies)]
+            with torch.cuda.stream(cur if k == 0 else extra_streams[k - 1]):
+                jas[k].init_state()
+                jas[k].build(d)
+                jas[k].probe(f)
+                jas[k].finalize()
+        for s in extra_streams[:ns - 1]:
+            cur.wait_stream(s)
+
+    def timed(ns):
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            steps_on_streams(ns)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            steps_on_streams(ns)
+        torch.cuda.synchronize()
+        for _ in range(max(1, args.warmup // gs)):
+            graph.replay()
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // gs)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / (reps * gs), reps * gs
+
+    ms_one_stream = timed(1)[0] if nstreams > 1 else None
+    ms_step, steps = timed(nstreams)
 
     # timed probe launches inside graph replays are measured by the eager events above;
-    # the result of the last replay is checked against the oracle below
-    got = ja.result()
+    # the result of each stream's last replayed step is checked against the oracle below
+    gots = [j.result() for j in jas[:min(nstreams, gs)]]
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
         want, t_cpu, runs = cpu_baseline_join_agg(dim, fact, q)
-        parity = (got["keys"].tolist() == want["keys"].tolist() and got["count"].tolist() == want["count"].tolist()
-                  and got["sums"].tolist() == want["sums"].tolist())
+        parity = all(got["keys"].tolist() == want["keys"].tolist() and got["count"].tolist() == want["count"].tolist()
+                     and got["sums"].tolist() == want["sums"].tolist() for got in gots)
         cpu = {"value": round(in_bytes / t_cpu / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"the whole workload (1.5M x 6M rows), median of {runs} runs of the sort-based C oracle, "
                          f"{t_cpu:.2f} s per run"}
     gbs = in_bytes / (ms_step / 1e3) / 1e9
     probe_gbs = probe_bytes / (kern_ms["probe"] / 1e3) / 1e9
+    from paper_2508_05029_amd.bench_more import measured_read_peak
+    read_peak = measured_read_peak()
     line = {
         "metric": "input GB/s filter-join-aggregate (% of HBM peak)",
         "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
@@ -175,8 +200,11 @@ def bench_join_agg(args):
                                "(fk U over dim keys, price, discount); date window [730,1094]; "
                                "SUM(price*(100-disc)), COUNT by group",
                    "input_bytes": in_bytes, "load_factor": args.load_factor, "copies": args.copies,
-                   "graph_steps": gs},
+                   "graph_steps": gs, "streams": nstreams},
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "ms_per_step_one_stream": None if ms_one_stream is None else round(ms_one_stream, 5),
+        "measured_read_peak_gbs": round(read_peak, 1),
+        "pct_measured_read_peak": round(100 * gbs / read_peak, 2),
         "rows_per_s": round((n_dim + n_fact) / (ms_step / 1e3), 1),
         "kernel_ms": {k: round(v, 5) for k, v in kern_ms.items()},
         "roofline": {"bound": "hbm", "achieved": round(probe_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -194,9 +222,10 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="join_agg",
-                    choices=["join_agg", "filter_groupby", "ooc", "batched", "serving", "copy"])
+                    choices=["join_agg", "filter_groupby", "ooc", "batched", "serving", "copy", "scaling"])
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--graph-steps", type=int, default=8)
+    ap.add_argument("--streams", type=int, default=2, help="join_agg: compute streams the steps alternate between")
     ap.add_argument("--event-steps", type=int, default=20)
     ap.add_argument("--load-factor", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -350,6 +350,115 @@ def bench_serving(args):
                   "calibrated_fifo_qps": round(mu, 2), "roofline": None, "cpu_baseline": None})
 
 
+# ------------------------------------------------------------------ steady state at growing row counts
+
+def measured_read_peak(nbytes=1 << 30, reps=5):
+    """GB/s of k_read_peak over nbytes (the device's streaming-read ceiling, measured in the same run)."""
+    x = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda")
+    part = torch.zeros(max(1, tq.read_peak_scratch_bytes() // 8), dtype=torch.int64, device="cuda")
+    tq.fill(x, 0x01010101)
+    tq.read_peak(x, part)
+    torch.cuda.synchronize()
+    a, b = _events()
+    a.record()
+    for _ in range(reps):
+        tq.read_peak(x, part)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = nbytes / (a.elapsed_time(b) / reps / 1e3) / 1e9
+    del x, part
+    return gbs
+
+
+def _replay_ms(step, ncopies, graph_steps, steps):
+    """ms per step of `step(i)` (i picks the input copy), replayed from a HIP graph."""
+    stream = torch.cuda.current_stream()
+    for i in range(3):
+        step(i % ncopies)
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        for i in range(graph_steps):
+            step(i % ncopies)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for i in range(graph_steps):
+            step(i % ncopies)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, steps // graph_steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / (reps * graph_steps), g
+
+
+def bench_scaling(args):
+    """The join+aggregate and filter+group-by steps at growing row counts (same value
+    distributions), so that fixed per-launch costs fade and the steady state shows; each
+    point is checked against the oracle."""
+    import oracle
+    peak = measured_read_peak()
+    log(f"measured read peak {peak:.0f} GB/s")
+    points = []
+    jq = wl.JOIN_AGG_QUERY
+    for n_dim, n_fact in ((1_500_000, 6_000_000), (6_000_000, 24_000_000), (25_000_000, 100_000_000)):
+        dim, fact = wl.join_agg_tables(n_dim, n_fact)
+        in_bytes = n_dim * 16 + n_fact * 24
+        ncopies = max(2, min(4, (1 << 30) // in_bytes + 1))
+        copies = [(pipeline.to_device(dim), pipeline.to_device(fact)) for _ in range(ncopies)]
+        ja = pipeline.JoinAgg(jq, n_dim, args.load_factor)
+
+        def step(i):
+            d, f = copies[i]
+            ja.init_state()
+            ja.build(d)
+            ja.probe(f)
+            ja.finalize()
+
+        steps = max(16, min(args.steps, int(4e9 // in_bytes) * 8))
+        ms, g = _replay_ms(step, ncopies, 8, steps)
+        got = ja.result()
+        want = oracle.join_agg(dim, fact, jq)
+        ok = (got["keys"].tolist() == want["keys"].tolist() and got["count"].tolist() == want["count"].tolist()
+              and got["sums"].tolist() == want["sums"].tolist())
+        gbs = in_bytes / (ms / 1e3) / 1e9
+        points.append({"workload": "join_agg", "dim_rows": n_dim, "fact_rows": n_fact, "ms_per_step": round(ms, 4),
+                       "gbs": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                       "pct_measured_read_peak": round(100 * gbs / peak, 2), "parity_vs_oracle": ok})
+        log(points[-1])
+        del copies, ja, g
+        torch.cuda.empty_cache()
+    fq = wl.FILTER_GROUPBY_QUERY
+    for n in (1_000_000, 10_000_000, 100_000_000):
+        t = wl.filter_groupby_tables(n)
+        in_bytes = n * 38
+        ncopies = max(2, min(4, (1 << 30) // in_bytes + 1))
+        copies = [pipeline.to_device(t) for _ in range(ncopies)]
+        fg = pipeline.FilterGroupBy(fq)
+        steps = max(16, min(args.steps, int(4e9 // in_bytes) * 8))
+        ms, g = _replay_ms(lambda i: fg.run(copies[i]), ncopies, 8, steps)
+        got = fg.result()
+        want = oracle.filter_groupby(t, fq)
+        ok = got["sums"].tolist() == want["sums"].tolist() and got["count"].tolist() == want["count"].tolist()
+        gbs = in_bytes / (ms / 1e3) / 1e9
+        points.append({"workload": "filter_groupby", "rows": n, "ms_per_step": round(ms, 4), "gbs": round(gbs, 1),
+                       "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+                       "pct_measured_read_peak": round(100 * gbs / peak, 2), "parity_vs_oracle": ok})
+        log(points[-1])
+        del copies, fg, g
+        torch.cuda.empty_cache()
+    big = points[2]
+    return _base("input GB/s filter-join-aggregate at growing row counts (steady state)", big["gbs"], "GB/s", args,
+                 big["ms_per_step"], 0,
+                 "scaling: join_agg at 1.5Mx6M, 6Mx24M, 25Mx100M rows; filter_groupby at 1M, 10M, 100M rows; "
+                 "value = the largest join",
+                 {"measured_read_peak_gbs": round(peak, 1), "points": points, "roofline": None, "cpu_baseline": None})
+
+
 # ------------------------------------------------------------------ plain copy kernels (calibration)
 
 def bench_copy(args):
