@@ -225,7 +225,7 @@ def main():
                     choices=["join_agg", "filter_groupby", "ooc", "batched", "serving", "copy", "scaling"])
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--graph-steps", type=int, default=8)
-    ap.add_argument("--streams", type=int, default=2, help="join_agg: compute streams the steps alternate between")
+    ap.add_argument("--streams", type=int, default=2, help="join_agg, filter_groupby: compute streams the steps alternate between")
     ap.add_argument("--event-steps", type=int, default=20)
     ap.add_argument("--load-factor", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
