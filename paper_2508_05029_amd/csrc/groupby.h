@@ -147,6 +147,45 @@ struct LdsAgg {
     }
   }
 
+  // The COUNT of group `key` (for add() split in two: the caller then adds sum
+  // j at at[1 + j]). Returns false for a key outside the domain (remembered or
+  // latched as in add()). *lds tells whether `at` is in LDS (else the
+  // group's global entry, where adds must be device atomics).
+  __device__ __forceinline__ bool count(const AggTarget& T, int64_t key, unsigned long long** at, bool* lds) {
+    if ((uint64_t)key >= (uint64_t)T.domain) {
+      if (defer) bad = true;
+      else latch_error(T.err, TQ_EDOMAIN);
+      return false;
+    }
+    *lds = true;
+    if (MODE == kDense) {
+      *at = reinterpret_cast<unsigned long long*>(vals + key * T.stride);
+    } else {
+      uint32_t k1 = (uint32_t)key + 1u;
+      uint32_t mask = (1u << T.log2hcap) - 1u;
+      uint32_t s = ((uint32_t)key * 0x9E3779B1u) >> (32 - T.log2hcap);
+      int found = -1;
+      for (int i = 0; i < kHashProbes; i++) {
+        uint32_t cur = keys[s];
+        if (cur == 0) {
+          uint32_t prev = atomicCAS(&keys[s], 0u, k1);
+          cur = prev == 0 ? k1 : prev;
+        }
+        if (cur == k1) {
+          found = (int)s;
+          break;
+        }
+        s = (s + 1) & mask;
+      }
+      *lds = found >= 0;
+      *at = *lds ? reinterpret_cast<unsigned long long*>(vals + (int64_t)found * T.stride)
+                 : reinterpret_cast<unsigned long long*>(T.data + key * T.stride);
+    }
+    if (*lds) atomicAdd(*at, 1ull);
+    else global_add(*at, 1);
+    return true;
+  }
+
   // Folds this workgroup's LDS partials into the global state.
   __device__ void flush(const AggTarget& T) {
     if (bad) latch_error(T.err, TQ_EDOMAIN);

@@ -122,13 +122,24 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_groupby(RowPlan 
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
     int64_t v[NC][kRows];
     load_rows<NC>(P, r0, r0 + kRows <= n, n, v);
+    bool ok[kRows], lds[kRows];
+    unsigned long long* at[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; i++) {
-      if (r0 + i < n && eval_preds<NC>(P, v, i)) {
-        int64_t s[NE];
+      ok[i] = r0 + i < n && eval_preds<NC>(P, v, i) && agg.count(T, eval_key<NC>(P, v, i), &at[i], &lds[i]);
+    }
+    // sums one at a time over the tile's rows, so that only one sum's plan
+    // constants are live (all of them at once spill into vector lanes)
+#pragma unroll 1
+    for (int e = 0; e < P.ne; e++) {
+      const DExpr E = P.expr[e];
 #pragma unroll
-        for (int e = 0; e < NE; e++) s[e] = e < P.ne ? eval_expr<NC>(P.expr[e], v, i) : 0;
-        agg.add(T, eval_key<NC>(P, v, i), s, P.ne);
+      for (int i = 0; i < kRows; i++) {
+        if (ok[i]) {
+          const int64_t x = eval_expr<NC>(E, v, i);
+          if (lds[i]) atomicAdd(at[i] + 1 + e, (unsigned long long)x);
+          else global_add(at[i] + 1 + e, x);
+        }
       }
     }
   }
