@@ -78,9 +78,7 @@ tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p
     for (int f = 0; f < e[j].nf; f++) {
       const tq_factor& F = e[j].f[f];
       if (F.col < -1 || F.col >= ncol) return fail(TQ_EINVAL, "expression %d factor %d: column %d", j, f, F.col);
-      P->expr[j].f[f].mask = F.col < 0 ? 0u : 1u << F.col;
-      P->expr[j].f[f].sign = F.sign;
-      P->expr[j].f[f].add = F.add;
+      P->expr[j].f[f] = make_factor(F.col, F.sign, F.add);
     }
   }
   if (key) {

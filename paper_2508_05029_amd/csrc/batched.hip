@@ -346,7 +346,7 @@ tq_status make_query(const tq_batch_query* q, BQuery* Q) {
     for (int f = 0; f < q->sums[j].nf; f++) {
       const tq_factor& F = q->sums[j].f[f];
       if (F.col < -1 || F.col >= q->nfact) return fail(TQ_EINVAL, "sum column");
-      Q->sums[j].f[f] = DFactor{F.col < 0 ? 0u : 1u << F.col, F.sign, F.add};
+      Q->sums[j].f[f] = make_factor(F.col, F.sign, F.add);
     }
   }
   Q->flags = q->join_flags;
