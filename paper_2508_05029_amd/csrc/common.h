@@ -400,31 +400,26 @@ __device__ __forceinline__ void load_rows64(const RowPlan& P, int64_t r0, int64_
 // Value of the column selected by `mask` (one bit, uniform) for row i; 0 if mask is 0.
 template <int NC, int R>
 __device__ __forceinline__ int64_t pick(const int64_t (&v)[NC][R], int i, uint32_t mask) {
-  // The column index is the same in every lane: select down a binary tree on
-  // its bits, so that a reference needs log2(NC) lane masks rather than NC
-  // (kept live across a kernel's loop, those spill). A zero mask (a constant
-  // factor, whose sign is zero) reads the last column or zero.
+  // The column index is the same in every lane, so a wider row is indexed
+  // directly (the compiler moves the row's registers by the index held in a
+  // scalar register) instead of through one select per column, whose lane
+  // masks, kept live across a kernel's loop, spill. A zero mask (a constant
+  // factor, whose sign is zero) reads the last column.
   // (Up to two columns the plain chain is kept: in the pipelined probe the
-  // tree's form raised register pressure into scratch spills.)
+  // other forms raised register pressure into scratch spills.)
+  static_assert(NC <= 8, "pick: at most 8 columns");
   if constexpr (NC <= 2) {
     int64_t r = 0;
 #pragma unroll
     for (int c = 0; c < NC; c++) r = ((mask >> c) & 1u) ? v[c][i] : r;
     return r;
+  } else {
+    const uint32_t c = min((uint32_t)__builtin_ctz(mask | 0x80000000u), (uint32_t)NC - 1);
+    int64_t t[NC];
+#pragma unroll
+    for (int k = 0; k < NC; k++) t[k] = v[k][i];
+    return t[c];
   }
-  constexpr int W = NC <= 1 ? 1 : NC <= 2 ? 2 : NC <= 4 ? 4 : 8;
-  static_assert(NC <= 8, "pick: at most 8 columns");
-  const uint32_t c = (uint32_t)__builtin_ctz(mask | 0x80000000u);
-  int64_t t[W];
-#pragma unroll
-  for (int k = 0; k < W; k++) t[k] = k < NC ? v[k < NC ? k : 0][i] : 0;
-#pragma unroll
-  for (int s = 0, w = W; w > 1; s++, w >>= 1) {
-    const bool b = (c >> s) & 1u;
-#pragma unroll
-    for (int k = 0; k < w / 2; k++) t[k] = b ? t[2 * k + 1] : t[2 * k];
-  }
-  return t[0];
 }
 
 // A rolled loop over the plan's predicates: unrolled over TQ_MAX_PREDS, the
