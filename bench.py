@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 PROBE_COUNTERS = {
     "sources": ["paper_2508_05029_amd/csrc/join_ops.hip", "paper_2508_05029_amd/csrc/table.h",
                 "paper_2508_05029_amd/csrc/groupby.h", "paper_2508_05029_amd/csrc/common.h"],
-    "sha1": "60969f08d57fb98ce04129c81218f47ed21579a6",
-    "fetch_kib": 115298.7, "fetch_scale": 2.000,
+    "sha1": "33fb0f81fa27de547dbea82345169c9d2045b383",
+    "fetch_kib": 115220.4, "fetch_scale": 2.000,
     "write_kib": 104.0, "write_scale": 0.995,
 }
 
