@@ -212,6 +212,9 @@ constexpr int kMaxRegionSlots = 2048;  // LDS region: 4 KiB of tags + 32 KiB of 
 static_assert(kFinBlock == kMaxRegionSlots / 2, "one thread clears one LDS tag word");
 constexpr int kMinRegionLog2Cap = kLog2Bucket + kLog2Bins;  // a region of at least one bucket
 constexpr int kMaxRegionLog2Cap = 11 + kLog2Bins;            // at most kMaxRegionSlots slots
+constexpr int kMaxPassLog2Cap = kMaxRegionLog2Cap + 4;        // regions of up to 16 LDS domains
+constexpr int kMaxSubs = 1 << (kMaxPassLog2Cap - kMaxRegionLog2Cap);
+constexpr int kMaxBloomLog2Cap = kMaxRegionLog2Cap + 1;       // the largest filter's 2^20 bits: >= 2 per key
 
 template <int NC>
 __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   __shared__ v2i64 lslot[kMaxRegionSlots];
   __shared__ int64_t ws[2 * kFinBlock / kWave];
   __shared__ uint32_t lbloom[kBloomWordsMax / kRegionBins];
+  __shared__ uint32_t sub_cnt[kMaxSubs], sub_fill[kMaxSubs], sub_off[kMaxSubs + 1];
   const int j = blockIdx.x, tid = threadIdx.x;
   const uint32_t* meta = scratch_meta(h, cap_max) + j;  // region j's counts, block b at meta[b * kMetaStride]
   // the loads go out first (the scratch lies inside the caller's buffer
@@ -276,6 +280,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   }
   ltag[tid] = 0u;  // kFinBlock == kMaxRegionSlots / 2
   if (tid < kBloomWordsMax / kRegionBins) lbloom[tid] = 0u;
+  if (tid < kMaxSubs) sub_cnt[tid] = sub_fill[tid] = 0u;
   if (h->magic != kTableMagic) return;
   int64_t rows = rb, mine = cj;  // all rows; rows of region j
   block_sum2(&rows, &mine, ws);
@@ -288,12 +293,20 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     l = 6;
     while (((int64_t)1 << (l + 1)) <= cap_max) l++;
   }
-  const bool in_range = l >= kMinRegionLog2Cap && l <= kMaxRegionLog2Cap;
+  // Up to kMaxRegionLog2Cap a region is one LDS domain, filled in one pass.
+  // Up to kMaxPassLog2Cap it is 2^(l - kMaxRegionLog2Cap) domains of
+  // kMaxRegionSlots slots, filled one after the other (linear probing wraps
+  // inside a domain either way).
+  const bool in_range = l >= kMinRegionLog2Cap && l <= kMaxPassLog2Cap;
+  const bool multi = l > kMaxRegionLog2Cap;
+  const int sub_log2 = multi ? l - kMaxRegionLog2Cap : 0;
   const int64_t region_slots = in_range ? (int64_t)1 << (l - kLog2Bins) : 0;
-  const bool fits = in_range && mine <= region_slots - std::max<int64_t>(1, region_slots / 8);
-  // Bloom words (log2) for this capacity: bloom_words_max(2^l)
-  const int log2w = std::min(std::max(l - 4, kLog2Bins + 1), kLog2BloomWordsMax);
+  const bool fits = in_range && (multi || mine <= region_slots - std::max<int64_t>(1, region_slots / 8));
+  // Bloom words (log2) for this capacity: bloom_words_max(2^l); none where the
+  // filter's fixed size would leave too few bits per key to reject much
+  const int log2w = l <= kMaxBloomLog2Cap ? std::min(std::max(l - 4, kLog2Bins + 1), kLog2BloomWordsMax) : 0;
   static_assert(kBloomWordsMax == 1 << kLog2BloomWordsMax && kRegionBins == 1 << kLog2Bins, "bloom size rule");
+  const int log2g = std::min(l, kMaxRegionLog2Cap) - kLog2Bucket - kLog2Bins;  // buckets per domain
   if (j == 0 && tid == 0) {
     h->cap_max = cap_max;
     h->n = rows;
@@ -301,7 +314,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     h->skip = skip;
     h->flags = flags;
     h->lf = lf;
-    h->log2g = l - kLog2Bucket - kLog2Bins;
+    h->log2g = log2g;
     h->regions = 1;
     h->alt = 0;
     h->bloom_log2w = log2w;
@@ -319,74 +332,135 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     if (tid == 0) atomicOr(&h->ovf, 1);
     return;
   }
-  const int log2g = l - kLog2Bucket - kLog2Bins;
   const int gmask = (1 << log2g) - 1, nslot = kBucket << log2g;
-  const int nbw = 1 << (log2w - kLog2Bins);  // Bloom words of this region
+  const int nbw = log2w ? 1 << (log2w - kLog2Bins) : 0;  // Bloom words of this region
   const v2i64* seg = reinterpret_cast<const v2i64*>(scratch_rows(h, cap_max));
   bool stuck = false;
-  // each wave takes 64 source blocks at a time and spreads their rows of
-  // region j over its lanes (a wave scan of the counts, then a search over
-  // the lanes by shuffles), so that every lane loads one row at a time
   const int lane = tid & (kWave - 1);
-  for (int b0 = tid - lane; b0 < nblk; b0 += kFinBlock) {
-    const int b = b0 + lane;
-    const uint32_t m = b < nblk ? (b0 == tid - lane && b == tid ? m0 : meta[(size_t)b * kMetaStride]) : 0u;
-    uint32_t total;
-    const uint32_t excl = wave_excl_scan(m & 0xffffu, &total);
-    const int64_t first = (int64_t)b * kPartRows + (m >> 16);  // this lane's first row in the segments
-    // (every lane stays in the loop for the shuffles; only the row work is guarded)
-    for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
-      const uint32_t i = i0 + lane;
-      int s = 0;  // the last lane whose rows start at or before i
+  // Calls body(kv) for every row of region j: each wave takes 64 source
+  // blocks at a time and spreads their rows of region j over its lanes (a wave
+  // scan of the counts, then a search over the lanes by shuffles), so that
+  // every lane loads one row at a time.
+  auto each_row = [&](auto&& body) {
+    for (int b0 = tid - lane; b0 < nblk; b0 += kFinBlock) {
+      const int b = b0 + lane;
+      const uint32_t m = b < nblk ? (b0 == tid - lane && b == tid ? m0 : meta[(size_t)b * kMetaStride]) : 0u;
+      uint32_t total;
+      const uint32_t excl = wave_excl_scan(m & 0xffffu, &total);
+      const int64_t first = (int64_t)b * kPartRows + (m >> 16);  // this lane's first row in the segments
+      // (every lane stays in the loop for the shuffles; only the row work is guarded)
+      for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+        const uint32_t i = i0 + lane;
+        int s = 0;  // the last lane whose rows start at or before i
 #pragma unroll
-      for (int step = kWave / 2; step >= 1; step >>= 1)
-        if ((uint32_t)__shfl(excl, s + step, kWave) <= i) s += step;
-      const int64_t at = ((int64_t)__shfl((int)(first >> 32), s, kWave) << 32) |
-                         (uint32_t)__shfl((int)(uint32_t)first, s, kWave);
-      const uint32_t e_s = (uint32_t)__shfl(excl, s, kWave);
-      if (i >= total) continue;
-      const v2i64 kv = seg[at + (i - e_s)];
-      const uint64_t hh = mulhash(kv.x);
-      atomicOr(&lbloom[bloom_word(hh, skip, log2w) & (uint32_t)(nbw - 1)], bloom_bits(hh));
-      int bl = (int)(bucket_of(hh, skip, l - kLog2Bucket) & (uint64_t)gmask);
-      const uint32_t tg = hash_tag(hh);
-      const int st = (int)(hh >> 16) & (kBucket - 1);
-      // the region keeps a free slot, so the walk finds one; the bound only
-      // guards against a broken invariant
-      bool done = false;
-      for (int it = 0; it < 4 * nslot + 64 && !done; it++) {
-        uint32_t w[4], zero = 0;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          w[q] = ltag[bl * 4 + q];
-          zero |= (uint32_t)((w[q] & 0xffffu) == 0u) << (2 * q);
-          zero |= (uint32_t)((w[q] >> 16) == 0u) << (2 * q + 1);
-        }
-        if (zero == 0u) {
-          bl = (bl + 1) & gmask;
-          continue;
-        }
-        const uint32_t rot = ((zero >> st) | (zero << (kBucket - st))) & 0xffu;
-        const int slot = (__builtin_ctz(rot) + st) & (kBucket - 1);
-        const int q = slot >> 1;
-        uint32_t cur = w[0];
-        cur = q == 1 ? w[1] : cur;
-        cur = q == 2 ? w[2] : cur;
-        cur = q == 3 ? w[3] : cur;
-        if (atomicCAS(&ltag[bl * 4 + q], cur, cur | (tg << ((slot & 1) * 16))) == cur) {
-          lslot[bl * kBucket + slot] = kv;
-          done = true;
-        }
+        for (int step = kWave / 2; step >= 1; step >>= 1)
+          if ((uint32_t)__shfl(excl, s + step, kWave) <= i) s += step;
+        const int64_t at = ((int64_t)__shfl((int)(first >> 32), s, kWave) << 32) |
+                           (uint32_t)__shfl((int)(uint32_t)first, s, kWave);
+        const uint32_t e_s = (uint32_t)__shfl(excl, s, kWave);
+        if (i >= total) continue;
+        body(seg[at + (i - e_s)]);
       }
-      stuck = stuck || !done;
+    }
+  };
+  // Inserts a row into the LDS domain (its bucket's low log2g bits).
+  auto insert = [&](const v2i64& kv, uint64_t hh) {
+    int bl = (int)(bucket_of(hh, skip, l - kLog2Bucket) & (uint64_t)gmask);
+    const uint32_t tg = hash_tag(hh);
+    const int st = (int)(hh >> 16) & (kBucket - 1);
+    // the domain keeps a free slot, so the walk finds one; the bound only
+    // guards against a broken invariant
+    bool done = false;
+    for (int it = 0; it < 4 * nslot + 64 && !done; it++) {
+      uint32_t w[4], zero = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        w[q] = ltag[bl * 4 + q];
+        zero |= (uint32_t)((w[q] & 0xffffu) == 0u) << (2 * q);
+        zero |= (uint32_t)((w[q] >> 16) == 0u) << (2 * q + 1);
+      }
+      if (zero == 0u) {
+        bl = (bl + 1) & gmask;
+        continue;
+      }
+      const uint32_t rot = ((zero >> st) | (zero << (kBucket - st))) & 0xffu;
+      const int slot = (__builtin_ctz(rot) + st) & (kBucket - 1);
+      const int q = slot >> 1;
+      uint32_t cur = w[0];
+      cur = q == 1 ? w[1] : cur;
+      cur = q == 2 ? w[2] : cur;
+      cur = q == 3 ? w[3] : cur;
+      if (atomicCAS(&ltag[bl * 4 + q], cur, cur | (tg << ((slot & 1) * 16))) == cur) {
+        lslot[bl * kBucket + slot] = kv;
+        done = true;
+      }
+    }
+    stuck = stuck || !done;
+  };
+  auto add_bloom = [&](uint64_t hh) {
+    if (nbw) atomicOr(&lbloom[bloom_word(hh, skip, log2w) & (uint32_t)(nbw - 1)], bloom_bits(hh));
+  };
+  // Writes LDS domain d (of the whole table) out.
+  auto write_domain = [&](int64_t d) {
+    uint32_t* gw = table_tags(h) + ((size_t)d << log2g) * 4;
+    for (int i = tid; i < nslot / 2; i += kFinBlock) gw[i] = ltag[i];
+    v2i64* gs = reinterpret_cast<v2i64*>(table_slots(h, cap_max)) + ((size_t)d << log2g) * kBucket;
+    for (int i = tid; i < nslot; i += kFinBlock) gs[i] = lslot[i];
+  };
+  if (!multi) {
+    each_row([&](const v2i64& kv) {
+      const uint64_t hh = mulhash(kv.x);
+      add_bloom(hh);
+      insert(kv, hh);
+    });
+    __syncthreads();
+    write_domain(j);
+  } else {
+    const int nsub = 1 << sub_log2;
+    auto sub_of = [&](uint64_t hh) {
+      return (int)((bucket_of(hh, skip, l - kLog2Bucket) >> log2g) & (uint64_t)(nsub - 1));
+    };
+    // count the rows of each domain; each must keep an eighth of its slots free
+    each_row([&](const v2i64& kv) {
+      const uint64_t hh = mulhash(kv.x);
+      add_bloom(hh);
+      atomicAdd(&sub_cnt[sub_of(hh)], 1u);
+    });
+    __syncthreads();
+    bool ok = true;
+    for (int d = 0; d < nsub; d++) ok = ok && sub_cnt[d] <= (uint32_t)(kMaxRegionSlots - kMaxRegionSlots / 8);
+    if (!ok) {
+      if (tid == 0) atomicOr(&h->ovf, 1);
+      return;
+    }
+    if (tid == 0) {
+      sub_off[0] = 0;
+      for (int d = 0; d < nsub; d++) sub_off[d + 1] = sub_off[d] + sub_cnt[d];
+    }
+    __syncthreads();
+    // stage the rows grouped by domain at the front of the region's own slot
+    // area: domain d's rows end below d * kMaxRegionSlots (each domain holds
+    // fewer), so filling the domains from the last one down never overwrites
+    // rows not yet read
+    v2i64* stage = reinterpret_cast<v2i64*>(table_slots(h, cap_max)) + ((size_t)j << (l - kLog2Bins));
+    each_row([&](const v2i64& kv) {
+      const int d = sub_of(mulhash(kv.x));
+      stage[sub_off[d] + atomicAdd(&sub_fill[d], 1u)] = kv;
+    });
+    __syncthreads();
+    for (int d = nsub - 1; d >= 0; d--) {
+      ltag[tid] = 0u;
+      __syncthreads();
+      for (uint32_t r = sub_off[d] + tid; r < sub_off[d + 1]; r += kFinBlock) {
+        const v2i64 kv = stage[r];
+        insert(kv, mulhash(kv.x));
+      }
+      __syncthreads();
+      write_domain(((int64_t)j << sub_log2) + d);
+      __syncthreads();
     }
   }
-  __syncthreads();
   if (stuck) latch_error(&h->err, TQ_EFULL);
-  uint32_t* gw = table_tags(h) + ((size_t)j << log2g) * 4;
-  for (int i = tid; i < nslot / 2; i += kFinBlock) gw[i] = ltag[i];
-  v2i64* gs = reinterpret_cast<v2i64*>(table_slots(h, cap_max)) + ((size_t)j << log2g) * kBucket;
-  for (int i = tid; i < nslot; i += kFinBlock) gs[i] = lslot[i];
   if (tid < nbw) scratch_bloom(h, cap_max)[(size_t)j * nbw + tid] = lbloom[tid];
 }
 

@@ -212,22 +212,32 @@ def _table_header(table):
     return i32(52), i32(56), i32(48), i32(16), i32(64)
 
 
-@pytest.mark.parametrize("case", ["regions", "cas_large_table", "cas_region_overflow", "host_fallback"])
+@pytest.mark.parametrize("case", ["regions", "multipass", "cas_large_table", "cas_region_overflow",
+                                  "cas_domain_overflow", "host_fallback"])
 def test_join_build_paths(case):
     """Each build path gives the oracle's pairs, and the header says which ran:
-    regions (filled in LDS, probing wraps inside a region of 2^(log2cap-11)
-    buckets), or the global CAS insert (wrapping over the whole table): into
-    the alternate arrays when the table is too large for an LDS region or some
-    region receives more rows than it can hold with a free slot, or into the
-    main arrays (with a counting pass first) when the rows' segments do not
-    fit the scratch area."""
+    regions (filled in LDS; up to 2^19 slots one domain per region, up to 2^23
+    several domains of 2048 slots filled one after the other; probing wraps
+    inside a domain), or the global CAS insert (wrapping over the whole
+    table): into the alternate arrays when the table is too large for LDS
+    domains or some domain receives more rows than it can hold with a free
+    slot, or into the main arrays (with a counting pass first) when the rows'
+    segments do not fit the scratch area."""
     rng = np.random.default_rng(11)
     filt = ()
     if case == "regions":
         bk = rng.permutation(100_000).astype(np.int64)
         nb_table, want_regions = len(bk), 1
+    elif case == "multipass":
+        bk = rng.permutation(600_000).astype(np.int64)  # 2^21 slots at 0.5: four domains per region
+        nb_table, want_regions = len(bk), 1
     elif case == "cas_large_table":
-        bk = rng.permutation(600_000).astype(np.int64)  # 2^21 slots at 0.5
+        bk = rng.permutation(5_000_000).astype(np.int64)  # 2^24 slots at 0.5
+        nb_table, want_regions = len(bk), 0
+    elif case == "cas_domain_overflow":
+        # one key 3000 times: its domain cannot hold them
+        bk = np.concatenate([np.full(3000, 7, np.int64), rng.permutation(600_000).astype(np.int64) + 10])
+        rng.shuffle(bk)
         nb_table, want_regions = len(bk), 0
     elif case == "cas_region_overflow":
         bk = np.concatenate([np.full(3000, 7, np.int64), rng.integers(10, 400_000, 17_000)])
@@ -256,9 +266,11 @@ def test_join_build_paths(case):
     regions, alt, log2g, log2cap, bloom_log2w = _table_header(table)
     assert regions == want_regions
     assert alt == (1 if case.startswith("cas") else 0)  # the fallback insert uses the alternate arrays
-    assert log2g == (log2cap - 11 if regions else log2cap - 3)
-    # two filter bits per slot, 512 to 32768 words of 32 bits; only a region build has one
-    assert bloom_log2w == (min(max(log2cap - 4, 9), 15) if regions else 0)
+    assert log2cap == {"multipass": 21, "cas_large_table": 24, "cas_domain_overflow": 21}.get(case, log2cap)
+    assert log2g == (min(log2cap, 19) - 11 if regions else log2cap - 3)
+    # two filter bits per slot, 512 to 32768 words of 32 bits; only a region build has one, and
+    # only up to 2^20 slots (past that the largest filter has under two bits per key)
+    assert bloom_log2w == (min(max(log2cap - 4, 9), 15) if regions and log2cap <= 20 else 0)
     total, pr, br = oracle.join_pairs(bk[keep], pk)
     cap = max(total, 1)
     rows = torch.empty(cap, dtype=torch.int64, device=DEV)
