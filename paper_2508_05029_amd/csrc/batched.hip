@@ -245,8 +245,13 @@ __device__ void probe_item(const BQuery& Q, const BInst& I, int64_t idx, char* s
   (void)err;
 }
 
+// One launch per phase, instantiated per phase so that each holds only the
+// code of its own items: a kernel with every phase's code is allocated the
+// registers of the largest (148 VGPRs, one workgroup per CU).
+template <int PHASE>
 __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, const BInst* insts,
-                                                      const uint64_t* items, int64_t* ctrs, int phase) {
+                                                      const uint64_t* items, int64_t* ctrs) {
+  constexpr int phase = PHASE;
   extern __shared__ __align__(16) char smem[];
   __shared__ uint64_t s_item;
   __shared__ int64_t s_base;
@@ -267,7 +272,7 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, 
     const BInst& I = insts[inst];
     int64_t* ctr = ctrs + inst * kCtr;
 
-    if (type == kItBuild) {
+    if (PHASE == 0 && type == kItBuild) {
       const TableHeader* th = static_cast<const TableHeader*>(I.table);
       uint32_t* words = table_tags(const_cast<TableHeader*>(th));
       v2i64* slots = reinterpret_cast<v2i64*>(table_slots(const_cast<TableHeader*>(th), I.cap_max));
@@ -275,10 +280,6 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, 
       DCol dc[4];
 #pragma unroll
       for (int c = 0; c < 4; c++) dc[c] = DCol{I.dcol[c] ? I.dcol[c] : I.dcol[0], Q.dtype[c] ? Q.dtype[c] : 8};
-      RowPlan P;
-      P.np = Q.np;
-      P.pred[0] = Q.pred[0];
-      P.pred[1] = Q.pred[1];
       for (int64_t r0 = lo + (int64_t)threadIdx.x * kRows; r0 < hi; r0 += (int64_t)blockDim.x * kRows) {
         const bool full = r0 + kRows <= hi;
         int64_t v[4][kRows];
@@ -292,19 +293,31 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, 
           }
         }
 #pragma unroll
-        for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < hi) && eval_preds<4, kRows>(P, v, i);
+        for (int i = 0; i < kRows; i++) {
+          // at most two predicates, read from the query directly (a plan copied
+          // into a local structure and indexed in a loop lives in scratch memory)
+          bool ok = r0 + i < hi;
+#pragma unroll
+          for (int j = 0; j < 2; j++) {
+            if (j < Q.np) {
+              const int64_t x = pick<4, kRows>(v, i, Q.pred[j].mask);
+              ok = ok && x >= Q.pred[j].lo && x <= Q.pred[j].hi;
+            }
+          }
+          pend[i] = ok;
+        }
         table_insert<kRows>(words, slots, I.log2cap, 0, pend, v[0], v[1]);
       }
-    } else if (type == kItProbe) {
+    } else if (PHASE == 1 && type == kItProbe) {
       if (I.domain * (1 + Q.nsum) * 8 <= kLdsAggBytes) probe_item<kDense>(Q, I, idx, smem, &hdr->err);
       else probe_item<kHash>(Q, I, idx, smem, &hdr->err);
-    } else if (type == kItFinOne) {
+    } else if (PHASE == 2 && type == kItFinOne) {
       int64_t g = fin_write(I, Q.nsum, 0, I.domain, 0, ws);
       if (threadIdx.x == 0) *I.ngroups = g;
-    } else if (type == kItFinCount) {
+    } else if (PHASE == 2 && type == kItFinCount) {
       int64_t c = fin_count(I, Q.nsum, idx * kFinChunk, min(I.domain, (idx + 1) * kFinChunk), ws);
       if (threadIdx.x == 0) ctr[8 + idx] = c;
-    } else {
+    } else if (PHASE == 3 && type == kItFinWrite) {
       if (threadIdx.x == 0) {
         int64_t b = 0;
         for (int64_t c = 0; c < idx; c++) b += ctr[8 + c];
@@ -471,12 +484,16 @@ tq_status tq_batched_run(const tq_batch_query* q, void* d_work, int32_t n, hipSt
   hipLaunchKernelGGL(k_batched_prep, dim3(std::min(n, 8192)), dim3(256), 0, stream, hdr, insts, ctrs, n, Q.nsum,
                      Q.flags);
   TQ_HIP(hipGetLastError());
-  int per_cu = 0;
-  TQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched, kBBlock, kLdsAggBytes));
-  per_cu = std::max(1, std::min(per_cu, 4));
-  for (int p = 0; p < kPhases; p++)
-    hipLaunchKernelGGL(k_batched, dim3(device_cu_count() * per_cu), dim3(kBBlock), kLdsAggBytes, stream, Q, hdr, insts,
-                       items, ctrs, p);
+  static_assert(kPhases == 4, "one kernel per phase");
+  void (*kern[kPhases])(BQuery, WorkHeader*, const BInst*, const uint64_t*, int64_t*) = {
+      k_batched<0>, k_batched<1>, k_batched<2>, k_batched<3>};
+  for (int p = 0; p < kPhases; p++) {
+    int per_cu = 0;
+    TQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern[p], kBBlock, kLdsAggBytes));
+    per_cu = std::max(1, std::min(per_cu, 4));
+    hipLaunchKernelGGL(kern[p], dim3(device_cu_count() * per_cu), dim3(kBBlock), kLdsAggBytes, stream, Q, hdr, insts,
+                       items, ctrs);
+  }
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
