@@ -111,7 +111,7 @@ int agg_grid(int64_t n) {
   return (int)std::max<int64_t>(1, std::min(want, cap));
 }
 
-template <int MODE, int NC, int NE>
+template <int MODE, int NC>
 __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_groupby(RowPlan P, int64_t n, AggTarget T) {
   extern __shared__ __align__(16) char smem[];
   if (!state_matches(T)) return;
@@ -352,8 +352,9 @@ tq_status tq_groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_
   if ((s = make_target(d_state, domain, nsum, &T, &mode, &lds))) return s;
   if (nrows == 0) return TQ_OK;
   dim3 grid(agg_grid(nrows)), block(kAggBlock);
-  TQ_DISPATCH_AGG(mode, P.ncol, nsum, M, NC, NE,
-                  hipLaunchKernelGGL((k_groupby<M, NC, NE>), grid, block, lds, stream, P, nrows, T));
+  // (the sums are evaluated one at a time: the kernel does not depend on their count)
+  TQ_DISPATCH_AGG(mode, P.ncol, nsum, M, NC, NE, (void)NE;
+                  hipLaunchKernelGGL((k_groupby<M, NC>), grid, block, lds, stream, P, nrows, T));
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
