@@ -93,6 +93,10 @@ def test_invalid_arguments_are_rejected_synchronously():
     assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 40, 0, None) == tq.TQ_EINVAL
     # a table buffer too small for even 64 slots
     assert L.tq_join_table_init(FAKE, 100, None) == tq.TQ_EINVAL
+    # the kept-row count needs a table and somewhere to write it
+    r = ctypes.c_int64()
+    assert L.tq_join_table_rows(None, ctypes.byref(r), None) == tq.TQ_EINVAL
+    assert L.tq_join_table_rows(FAKE, None, None) == tq.TQ_EINVAL
     # group-by state: nsum, domain, size
     assert L.tq_groupby_init(FAKE, 1 << 20, 10, 7, None) == tq.TQ_EINVAL
     assert L.tq_groupby_init(FAKE, 1 << 20, 0, 1, None) == tq.TQ_EINVAL

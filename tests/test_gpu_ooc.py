@@ -213,3 +213,28 @@ def test_ooc_forced_single_table_that_does_not_fit_fails_cleanly():
     ft.free()
     assert pool.free_pages() == 3000
     pool.close()
+
+
+@pytest.mark.parametrize("exchange", ["auto", "partitioned"])
+def test_ooc_dimension_filter_keeps_nothing(exchange):
+    """No dimension row passes the filter: both exchanges produce no group."""
+    say(f"ooc empty dimension side, exchange={exchange}")
+    pool = tq.PagePool(256 << 10, 1000, pinned=True)
+    d, f = wl.ooc_tables_numpy(200_000, 50_000, 53)
+    d["date"][:] = 5  # outside the query's window
+    dt = HostTable(pool, wl.OOC_DIM_COLS, 50_000, 20_000)
+    dt.fill_numpy(d)
+    ft = HostTable(pool, wl.OOC_FACT_COLS, 200_000, 20_000)
+    ft.fill_numpy(f)
+    q = wl.JOIN_AGG_QUERY
+    job = pipeline.OocJoinAgg(q, dt, ft, 32 << 20, log2_fanout=4, chunk_bytes=64 << 10, exchange=exchange)
+    st = job.run()
+    got = job.result()
+    assert st.dim_rows_kept == 0 and st.fact_rows == 200_000
+    assert got["join_rows"] == 0 and len(got["count"]) == 0
+    assert st.exchange == (tq.TQ_EXCHANGE_SINGLE if exchange == "auto" else tq.TQ_EXCHANGE_PARTITIONED)
+    assert job.budget.used == 0
+    dt.free()
+    ft.free()
+    assert pool.free_pages() == 1000
+    pool.close()

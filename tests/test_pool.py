@@ -71,3 +71,43 @@ def test_budget_reservations():
     assert b.used == 300 and b.peak == 1000
     b.release(10_000)  # never below zero
     assert b.used == 0 and b.cap == 1000
+
+
+def test_ooc_rejects_bad_plans_before_any_work():
+    """tq_ooc_join_agg validates the plan before it touches a device: an
+    unknown exchange mode, a fan-out past 2^10 and a single staging slot all
+    return TQ_EINVAL (the work and state pointers are never dereferenced)."""
+    import ctypes
+    fake = 0x100000
+    pool = tq.PagePool(1 << 16, 16, pinned=False)
+    rng = np.random.default_rng(3)
+    dt = HostTable(pool, [("key", np.int64), ("group", np.int32), ("date", np.int32)], 100, 50)
+    dt.fill_numpy({"key": np.arange(100, dtype=np.int64), "group": rng.integers(0, 5, 100).astype(np.int32),
+                   "date": rng.integers(0, 2000, 100).astype(np.int32)})
+    ft = HostTable(pool, [("fk", np.int64), ("price", np.int64)], 100, 50)
+    ft.fill_numpy({"fk": rng.integers(0, 100, 100).astype(np.int64), "price": np.arange(100, dtype=np.int64)})
+    preds = tq.preds([(2, 730, 1094)])
+    sums = tq.exprs([[(1, 1, 0)]])
+    d_arr, d_keep = dt.c_batches()
+    f_arr, f_keep = ft.c_batches()
+    budget = tq.Budget(1 << 24)
+    L = tq._bind_more()
+
+    def run(**over):
+        kw = dict(log2_fanout=2, nslots=2, exchange=tq.TQ_EXCHANGE_AUTO)
+        kw.update(over)
+        plan = tq.OocPlan(0, 1, ctypes.cast(preds, ctypes.POINTER(tq.PredS)), 1, 0, 3,
+                          ctypes.cast(sums, ctypes.POINTER(tq.ExprS)), 1, 5, kw["log2_fanout"], 0.5, 0, 1 << 16,
+                          kw["nslots"], kw["exchange"])
+        st = tq.OocStats()
+        return L.tq_ooc_join_agg(pool.h, d_arr, len(dt.batches), f_arr, len(ft.batches), ctypes.byref(plan),
+                                 budget.h, fake, 1 << 24, fake, ctypes.byref(st), None, None)
+
+    assert run(exchange=3) == tq.TQ_EINVAL
+    assert run(exchange=-1) == tq.TQ_EINVAL
+    assert run(log2_fanout=11) == tq.TQ_EINVAL
+    assert run(nslots=1) == tq.TQ_EINVAL
+    assert budget.used == 0
+    dt.free()
+    ft.free()
+    pool.close()
