@@ -695,7 +695,7 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
 #pragma unroll
       for (int i = 0; i < R; i++) {
         sm[i] = t.live[i] ? tag_match(tw[i], t.tg[i]) : 0u;
-        sempty[i] = t.live[i] ? tag_match(tw[i], 0u) != 0u : true;
+        sempty[i] = t.live[i] ? has_empty(tw[i]) : true;
       }
 #pragma unroll
       for (int i = 0; i < R; i++) kv[i] = pr.slots[sm[i] ? t.b[i] * kBucket + __builtin_ctz(sm[i]) : 0];

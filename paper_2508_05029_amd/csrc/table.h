@@ -24,6 +24,20 @@ __device__ __forceinline__ uint32_t tag_match(const v4i32& w, uint32_t t) {
   return m;
 }
 
+// Whether some tag of the bucket is 0 (a free slot). Per 32-bit word of two
+// tags, (x - 0x00010001) & ~x has a lane's top bit set exactly when that lane
+// is the lowest zero one (a borrow leaves only a zero lane); as a yes/no over
+// the word the test is exact, in two instructions instead of a mask's eight.
+__device__ __forceinline__ bool has_empty(const v4i32& w) {
+  uint32_t a = 0;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const uint32_t x = (uint32_t)w[q];
+    a |= (x - 0x00010001u) & ~x;
+  }
+  return (a & 0x80008000u) != 0u;
+}
+
 __device__ __forceinline__ uint32_t word_of(const v4i32& w, int q) {
   uint32_t r = (uint32_t)w[0];
   r = q == 1 ? (uint32_t)w[1] : r;
@@ -173,7 +187,7 @@ struct Probe {
       for (int i = 0; i < R; i++) {
         if (act[i] && load[i]) {
           m[i] = tag_match(w[i], tg[i]);
-          empty[i] = tag_match(w[i], 0u) != 0u;
+          empty[i] = has_empty(w[i]);
           load[i] = false;
         }
       }
