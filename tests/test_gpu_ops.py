@@ -212,7 +212,7 @@ def _table_header(table):
     return i32(52), i32(56), i32(48), i32(16), i32(64)
 
 
-@pytest.mark.parametrize("case", ["regions", "multipass", "cas_large_table", "cas_region_overflow",
+@pytest.mark.parametrize("case", ["regions", "multipass", "multipass_16", "cas_large_table", "cas_region_overflow",
                                   "cas_domain_overflow", "host_fallback"])
 def test_join_build_paths(case):
     """Each build path gives the oracle's pairs, and the header says which ran:
@@ -230,6 +230,9 @@ def test_join_build_paths(case):
         nb_table, want_regions = len(bk), 1
     elif case == "multipass":
         bk = rng.permutation(600_000).astype(np.int64)  # 2^21 slots at 0.5: four domains per region
+        nb_table, want_regions = len(bk), 1
+    elif case == "multipass_16":
+        bk = rng.permutation(3_000_000).astype(np.int64)  # 2^23 slots: sixteen domains per region
         nb_table, want_regions = len(bk), 1
     elif case == "cas_large_table":
         bk = rng.permutation(5_000_000).astype(np.int64)  # 2^24 slots at 0.5
@@ -266,7 +269,8 @@ def test_join_build_paths(case):
     regions, alt, log2g, log2cap, bloom_log2w = _table_header(table)
     assert regions == want_regions
     assert alt == (1 if case.startswith("cas") else 0)  # the fallback insert uses the alternate arrays
-    assert log2cap == {"multipass": 21, "cas_large_table": 24, "cas_domain_overflow": 21}.get(case, log2cap)
+    assert log2cap == {"multipass": 21, "multipass_16": 23, "cas_large_table": 24,
+                       "cas_domain_overflow": 21}.get(case, log2cap)
     assert log2g == (min(log2cap, 19) - 11 if regions else log2cap - 3)
     # two filter bits per slot, 512 to 32768 words of 32 bits; only a region build has one, and
     # only up to 2^20 slots (past that the largest filter has under two bits per key)
