@@ -612,7 +612,8 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   agg.init(T, smem);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   int64_t* qrow = reinterpret_cast<int64_t*>(smem + agg_lds) + (int64_t)wave * kPipeQ;  // queued row numbers
-  __syncthreads();
+  // (the barrier after which the filter, the partials and the queues may be
+  // used comes after the first tiles' column loads, which it overlaps)
   Probe pr;
   pr.setup(h);
   const int64_t n_main = n & ~(int64_t)(R - 1);  // rows in full tiles
@@ -729,9 +730,10 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
     // prologue: tile 0 to its slot loads (row state ra), tile 1 to its tag
     // loads (rb), tiles 2 and 3's columns requested
     load_cols(cva, cka, r);
-    cols_to_tags(cva, cka, r, ra);
-    asm volatile("" ::: "memory");
     load_cols(cvb, ckb, r + stride);
+    asm volatile("" ::: "memory");
+    __syncthreads();
+    cols_to_tags(cva, cka, r, ra);
     asm volatile("" ::: "memory");
     tags_to_slots(ra);
     asm volatile("" ::: "memory");
@@ -767,6 +769,8 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
       asm volatile("" ::: "memory");
       while (qn >= kWave) drain(kWave);
     }
+  } else {
+    __syncthreads();
   }
   if (qn > 0) drain(qn);
   if (n_main < n && blockIdx.x == 0 && threadIdx.x == 0) {
