@@ -604,8 +604,22 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   const int log2w = BLOOM ? h->bloom_log2w : 0;
   const int nbw = log2w ? 1 << log2w : 0;
   if (BLOOM) {
+    // every load of the copy first, then every LDS store: one round trip to
+    // memory instead of one per 16 bytes a thread copies
+    constexpr int kU = kBloomWordsMax / 4 / kBloomPipeBlock;
+    static_assert(kU * 4 * kBloomPipeBlock == kBloomWordsMax, "filter copy");
     const v4i32* gb = reinterpret_cast<const v4i32*>(scratch_bloom(const_cast<TableHeader*>(h), h->cap_max));
-    for (int i = threadIdx.x; i < nbw / 4; i += blockDim.x) reinterpret_cast<v4i32*>(bloom)[i] = gb[i];
+    v4i32 t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int i = (int)threadIdx.x + u * kBloomPipeBlock;
+      if (i < nbw / 4) t[u] = gb[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int i = (int)threadIdx.x + u * kBloomPipeBlock;
+      if (i < nbw / 4) reinterpret_cast<v4i32*>(bloom)[i] = t[u];
+    }
   }
   LdsAgg<MODE> agg;
   agg.defer = true;
