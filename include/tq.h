@@ -148,7 +148,8 @@ tq_status tq_join_table_init(void* d_table, size_t bytes, hipStream_t stream);
  * `skip` high hash bits are ignored by the slot index (set it to the partition
  * bits when the input is one hash partition). Latches TQ_EFULL if the rows do
  * not fit in the buffer; the header still records how many rows passed the
- * filter (tq_join_table_rows), and nothing is inserted. Three or four kernel
+ * filter (tq_join_table_rows), and nothing is inserted. Every build replaces
+ * the previous one, an error it latched included. Three or four kernel
  * launches on `stream`, none of which allocates; builds into one buffer must
  * not overlap. */
 tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_col payload, int64_t n,
@@ -270,8 +271,9 @@ typedef tq_status (*tq_batch_fn)(void* user, int64_t batch_idx, const tq_col* d_
  * contiguous on the device) while earlier batches compute on `compute`; a
  * slot is refilled only after the compute work of the batch it held is done.
  * d_staging holds nslots slots of staging_bytes / nslots bytes each (a slot
- * must hold the largest batch, rounded to whole pages). Returns after
- * enqueueing everything; synchronise `compute` to wait for the last batch. */
+ * must hold the largest batch, rounded to whole pages). Blocks until every
+ * copy and every callback's compute work has completed (both streams are
+ * synchronised before it returns). */
 tq_status tq_pagepool_stream(tq_pagepool* pool, const tq_batch* batches, int64_t nb, void* d_staging,
                              size_t staging_bytes, int32_t nslots, tq_batch_fn on_resident, void* user,
                              hipStream_t copy, hipStream_t compute);
@@ -497,6 +499,10 @@ typedef struct {
   int32_t fact_map[4];
   int32_t nslots;
   int32_t estimate; /* 1: reserve join tables from the memory-use history; 0: for the whole window */
+  /* rows of the base tables: every request window must lie inside them (else TQ_EINVAL) */
+  int64_t fg_rows;   /* shape 0 table */
+  int64_t dim_rows;  /* dimension (shapes 1, 2) */
+  int64_t fact_rows; /* shape 1 fact table */
 } tq_serve_tables;
 
 typedef struct {
@@ -511,12 +517,25 @@ typedef struct {
 
 /* Runs all requests and blocks until they are done. d_arena / arena_bytes is
  * the device memory requests are carved from; the budget bounds it. Group
- * results of request i go to h_keys[i][max_groups], h_count[i][max_groups] and
- * h_sums[i][max_groups][TQ_MAX_SUMS] (sum j of group g at g * TQ_MAX_SUMS + j),
- * groups in key order, at most max_groups of them; per-request timing to `res`. */
+ * results of request i go to h_keys[i][max_groups], h_count[i][max_groups],
+ * h_sums[i][max_groups][TQ_MAX_SUMS] (sum j of group g at g * TQ_MAX_SUMS + j)
+ * and h_avg (same layout: (double)SUM_j / (double)COUNT, rounded to nearest
+ * even), groups in key order, at most max_groups of them; per-request timing
+ * to `res`.
+ *
+ * What a request reserves: the sum, each rounded up to 256 bytes (and at
+ * least 8), of tq_groupby_state_bytes(domain, nsum), the join table
+ * (tq_join_table_bytes(rows, load_factor), shapes 1 and 2; 0 for shape 0),
+ * keys and COUNT (8 * domain each), SUMs and AVGs (8 * domain * nsum each),
+ * the group count (8), the staging slots of shape 2 (nslots times the largest
+ * batch of its window in whole pages; 0 otherwise) and 64 bytes of scratch. A
+ * request whose reservation exceeds the budget's capacity can never run and
+ * completes at once with status TQ_ENOMEM; the others wait for room.
+ * Every window is checked against the base tables' row counts before any
+ * request runs (TQ_EINVAL). */
 tq_status tq_serve_run(const tq_serve_tables* t, const tq_request* reqs, int64_t n, int32_t workers,
                        tq_budget* budget, void* d_arena, size_t arena_bytes, int64_t max_groups, int64_t* h_keys,
-                       int64_t* h_count, int64_t* h_sums, tq_request_result* res);
+                       int64_t* h_count, int64_t* h_sums, double* h_avg, tq_request_result* res);
 
 /* ------------------------------------------------------- measurement kernels */
 

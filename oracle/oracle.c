@@ -17,10 +17,12 @@
  *               COUNT, SUM_j (mod 2^64), AVG_j = (double)SUM_j / (double)COUNT
  *   equi-join   sort both sides by key, every (probe, build) pair with equal
  *               keys (inner join), reported in (probe_row, build_row) order
- *   partition   p(k) = (k * 0x9E3779B97F4A7C15 mod 2^64) >> (64 - b): the
- *               64-bit multiplicative hash that Section 3.2 (Example
- *               Execution) uses to hash-partition both sides of a join;
- *               a stable counting sort yields the partitions in row order
+ *   partition   p(k) = (k * 0x9E3779B97F4A7C15 mod 2^64) >> (64 - b).
+ *               Section 3.2 (Example Execution) hash-partitions both sides
+ *               of a join but names no hash function; this 64-bit
+ *               multiplicative hash with Knuth's constant (floor(2^64 /
+ *               golden ratio)) is the workload's choice. A stable counting
+ *               sort yields the partitions in row order
  *
  * Values are widened to int64 before any comparison: uint8 by zero extension,
  * int32 by sign extension. An __int128 shadow of every product and sum flags

@@ -207,6 +207,7 @@ __device__ void probe_item(const BQuery& Q, const BInst& I, int64_t idx, char* s
   size_t lds;
   agg_mode(I.domain, T.stride, &T.log2hcap, &lds);
   LdsAgg<MODE> agg;
+  agg.defer = true;  // a key outside the domain is remembered and latched below
   agg.init(T, smem);
   __syncthreads();
   const TableHeader* th = static_cast<const TableHeader*>(I.table);
@@ -241,8 +242,10 @@ __device__ void probe_item(const BQuery& Q, const BInst& I, int64_t idx, char* s
         if (hit[i]) agg.add(T, pay[i], e[i], Q.nsum);
     });
   }
+  // a group key outside the instance's domain: latched in the instance's state
+  // (by flush) and in the work area, where tq_batched_check finds it
+  if (__syncthreads_or(agg.bad) && threadIdx.x == 0) latch_error(err, TQ_EDOMAIN);
   agg.flush(T);
-  (void)err;
 }
 
 // One launch per phase, instantiated per phase so that each holds only the

@@ -116,6 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, in
                                                         int64_t cap_max, int count) {
   __shared__ int64_t ws[kBlock / kWave];
   if (h->magic != kTableMagic) return;  // never initialised: the insert kernel does nothing either
+  // a new build: an error latched by an earlier build into this buffer no longer applies
+  if (blockIdx.x == 0 && threadIdx.x == 0) h->err = 0;
   v4i32* tags = reinterpret_cast<v4i32*>(table_tags(h));
   const v4i32 z = {0, 0, 0, 0};
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (cap_max >> kLog2Bucket);
@@ -231,7 +233,10 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   load4(kc, r0, full, n, k);
   load4(payload, r0, full, n, pay);
   if (h->magic != kTableMagic) return;
-  if (blockIdx.x == 0 && tid == 0) h->ovf = 0;  // the previous build's fallback has finished with it
+  if (blockIdx.x == 0 && tid == 0) {
+    h->ovf = 0;  // the previous build's fallback has finished with it
+    h->err = 0;  // and an error it latched no longer applies
+  }
   if (tid < kRegionBins) hist[tid] = 0;
   __syncthreads();
   bool ok[kRows];

@@ -82,6 +82,7 @@ struct Server {
   Arena arena;
   int64_t max_groups;
   int64_t *h_keys, *h_count, *h_sums;
+  double* h_avg;
   tq_request_result* res;
   Clock::time_point t0;
 
@@ -97,9 +98,9 @@ struct Server {
   int64_t completed = 0;
 
   Server(const tq_serve_tables& t, const tq_request* r, int64_t nr, tq_budget* b, void* d_arena, size_t arena_bytes,
-         int64_t mg, int64_t* k, int64_t* c, int64_t* s, tq_request_result* out)
+         int64_t mg, int64_t* k, int64_t* c, int64_t* s, double* a, tq_request_result* out)
       : T(t), reqs(r), n(nr), budget(b), arena_base(static_cast<char*>(d_arena)), arena(arena_bytes), max_groups(mg),
-        h_keys(k), h_count(c), h_sums(s), res(out) {}
+        h_keys(k), h_count(c), h_sums(s), h_avg(a), res(out) {}
 
   double now_s() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
@@ -239,14 +240,22 @@ struct Server {
     res[idx].ngroups = g;
     if (g > 0) {
       std::vector<int64_t> dense((size_t)g * p.nsum);
+      std::vector<double> dense_avg((size_t)g * p.nsum);
       TQ_HIP(hipMemcpyAsync(h_keys + idx * max_groups, keys, (size_t)g * 8, hipMemcpyDeviceToHost, compute));
       TQ_HIP(hipMemcpyAsync(h_count + idx * max_groups, count, (size_t)g * 8, hipMemcpyDeviceToHost, compute));
-      if (p.nsum) TQ_HIP(hipMemcpyAsync(dense.data(), sums, dense.size() * 8, hipMemcpyDeviceToHost, compute));
+      if (p.nsum) {
+        TQ_HIP(hipMemcpyAsync(dense.data(), sums, dense.size() * 8, hipMemcpyDeviceToHost, compute));
+        TQ_HIP(hipMemcpyAsync(dense_avg.data(), avg, dense_avg.size() * 8, hipMemcpyDeviceToHost, compute));
+      }
       TQ_HIP(hipStreamSynchronize(compute));
       // the caller's layout: [max_groups][TQ_MAX_SUMS] per request
       int64_t* out = h_sums + idx * max_groups * TQ_MAX_SUMS;
+      double* out_avg = h_avg + idx * max_groups * TQ_MAX_SUMS;
       for (int64_t k = 0; k < g; k++)
-        for (int j = 0; j < p.nsum; j++) out[k * TQ_MAX_SUMS + j] = dense[(size_t)k * p.nsum + j];
+        for (int j = 0; j < p.nsum; j++) {
+          out[k * TQ_MAX_SUMS + j] = dense[(size_t)k * p.nsum + j];
+          out_avg[k * TQ_MAX_SUMS + j] = dense_avg[(size_t)k * p.nsum + j];
+        }
     }
     return TQ_OK;
   }
@@ -375,10 +384,12 @@ struct Server {
 
 extern "C" tq_status tq_serve_run(const tq_serve_tables* t, const tq_request* reqs, int64_t n, int32_t workers,
                                   tq_budget* budget, void* d_arena, size_t arena_bytes, int64_t max_groups,
-                                  int64_t* h_keys, int64_t* h_count, int64_t* h_sums, tq_request_result* res) {
+                                  int64_t* h_keys, int64_t* h_count, int64_t* h_sums, double* h_avg,
+                                  tq_request_result* res) {
   using tq::fail;
-  if (!t || (n > 0 && (!reqs || !res || !h_keys || !h_count || !h_sums)) || !budget || !d_arena)
+  if (!t || (n > 0 && (!reqs || !res || !h_keys || !h_count || !h_sums || !h_avg)) || !budget || !d_arena)
     return fail(TQ_EINVAL, "NULL argument");
+  if (t->fg_rows < 0 || t->dim_rows < 0 || t->fact_rows < 0) return fail(TQ_EINVAL, "negative base table row count");
   if (workers < 1 || workers > 64) return fail(TQ_EINVAL, "workers outside [1, 64]");
   if (max_groups < 1) return fail(TQ_EINVAL, "max_groups");
   for (int64_t i = 0; i < n; i++) {
@@ -389,7 +400,17 @@ extern "C" tq_status tq_serve_run(const tq_serve_tables* t, const tq_request* re
     if (q.shape != 0 && (q.dim_first % 16 || q.n_dim < 0)) return fail(TQ_EINVAL, "request %lld: dimension window", (long long)i);
     if (q.shape == 2 && (!t->pool || q.fact_first + q.n_fact > t->n_fact_batches))
       return fail(TQ_EINVAL, "request %lld: batch window", (long long)i);
+    // every window lies inside its base table (a window past the end would make the kernels read past the columns)
+    if (q.shape == 0 && q.fact_first + q.n_fact > t->fg_rows)
+      return fail(TQ_EINVAL, "request %lld: rows [%lld, %lld) outside the %lld-row filter table", (long long)i,
+                  (long long)q.fact_first, (long long)(q.fact_first + q.n_fact), (long long)t->fg_rows);
+    if (q.shape == 1 && q.fact_first + q.n_fact > t->fact_rows)
+      return fail(TQ_EINVAL, "request %lld: rows [%lld, %lld) outside the %lld-row fact table", (long long)i,
+                  (long long)q.fact_first, (long long)(q.fact_first + q.n_fact), (long long)t->fact_rows);
+    if (q.shape != 0 && (q.dim_first < 0 || q.dim_first + q.n_dim > t->dim_rows))
+      return fail(TQ_EINVAL, "request %lld: rows [%lld, %lld) outside the %lld-row dimension table", (long long)i,
+                  (long long)q.dim_first, (long long)(q.dim_first + q.n_dim), (long long)t->dim_rows);
   }
-  tq::Server s(*t, reqs, n, budget, d_arena, arena_bytes, max_groups, h_keys, h_count, h_sums, res);
+  tq::Server s(*t, reqs, n, budget, d_arena, arena_bytes, max_groups, h_keys, h_count, h_sums, h_avg, res);
   return s.run(workers);
 }

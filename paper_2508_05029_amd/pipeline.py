@@ -416,6 +416,7 @@ class ServingSetup:
         T.n_fact_batches = len(self.host.batches)
         T.nslots = nslots
         T.estimate = 1 if estimate else 0
+        T.fg_rows, T.dim_rows, T.fact_rows = n0, n_dim, n1
         self.T = T
 
     def requests(self, reqs, time_scale=1.0):

@@ -505,7 +505,8 @@ class ServeTables(ctypes.Structure):
                 ("fact_ncol", ctypes.c_int32), ("join_sums", ExprS * 2), ("join_nsum", ctypes.c_int32),
                 ("join_domain", ctypes.c_int64), ("load_factor", ctypes.c_double), ("pool", ctypes.c_void_p),
                 ("fact_batches", ctypes.c_void_p), ("n_fact_batches", ctypes.c_int64), ("fact_map", ctypes.c_int32 * 4),
-                ("nslots", ctypes.c_int32), ("estimate", ctypes.c_int32)]
+                ("nslots", ctypes.c_int32), ("estimate", ctypes.c_int32), ("fg_rows", ctypes.c_int64),
+                ("dim_rows", ctypes.c_int64), ("fact_rows", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -525,13 +526,14 @@ def serve_run(tables: ServeTables, reqs, workers: int, budget: Budget, arena, ma
     if not getattr(L, "_serve_bound", False):
         L.tq_serve_run.restype = _i32
         L.tq_serve_run.argtypes = [ctypes.POINTER(ServeTables), _vp, _i64, _i32, _vp, _vp, _sz, _i64, _vp, _vp, _vp,
-                                   _vp]
+                                   _vp, _vp]
         L._serve_bound = True
     n = len(reqs)
     keys = np.zeros((max(n, 1), max_groups), np.int64)
     count = np.zeros((max(n, 1), max_groups), np.int64)
     sums = np.zeros((max(n, 1), max_groups, MAX_SUMS), np.int64)
+    avg = np.zeros((max(n, 1), max_groups, MAX_SUMS), np.float64)
     res = (RequestResult * max(n, 1))()
     _check(L.tq_serve_run(ctypes.byref(tables), reqs, n, workers, budget.h, arena.data_ptr(), _nbytes(arena), max_groups,
-                          keys.ctypes.data, count.ctypes.data, sums.ctypes.data, res))
-    return res, keys, count, sums
+                          keys.ctypes.data, count.ctypes.data, sums.ctypes.data, avg.ctypes.data, res))
+    return res, keys, count, sums, avg

@@ -111,3 +111,29 @@ def test_invalid_arguments_are_rejected_synchronously():
     c = (tq.Col * 1)(tq.Col(FAKE, tq.TQ_I64))
     assert L.tq_join_probe(FAKE, FAKE, 10, c, 1, None, 0, None, None, 0, None, ctypes.byref(agg), None) == tq.TQ_EINVAL
     assert L.tq_read_peak(FAKE, 15, FAKE, None) == tq.TQ_EINVAL
+
+
+def test_serving_rejects_windows_outside_the_base_tables():
+    """A request window past the end of its base table is refused before any
+    request runs (the kernels would otherwise read past the device columns)."""
+    import torch
+    T = tq.ServeTables()
+    T.fg_rows, T.dim_rows, T.fact_rows = 1000, 500, 2000
+    arena = torch.empty(1 << 16, dtype=torch.uint8)
+    budget = tq.Budget(1 << 16)
+    cases = [(0, 992, 16, 0, 0),      # filter table: rows [992, 1008) of 1000
+             (1, 0, 2016, 0, 100),    # fact table: rows [0, 2016) of 2000
+             (1, 0, 100, 496, 16),    # dimension: rows [496, 512) of 500
+             (2, 0, 1, 496, 16)]      # the same dimension window for a streamed request
+    try:
+        for shape, ff, nf, df, nd in cases:
+            R = (tq.Request * 1)()
+            R[0].shape, R[0].fact_first, R[0].n_fact, R[0].dim_first, R[0].n_dim = shape, ff, nf, df, nd
+            if shape == 2:
+                T.pool, T.n_fact_batches = FAKE, 4  # a batch window that fits; never read
+            with pytest.raises(tq.TqError) as e:
+                tq.serve_run(T, R, 1, budget, arena, 25)
+            assert e.value.status == tq.TQ_EINVAL
+            assert b"outside" in tq.lib().tq_last_error(), (shape, tq.lib().tq_last_error())
+    finally:
+        budget.close()

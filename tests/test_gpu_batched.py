@@ -82,3 +82,40 @@ def test_mixed_per_instance_parameters_and_graph_replay():
         torch.cuda.synchronize()
         job.check()
         check_all(job, insts)
+
+
+def test_group_key_outside_domain_is_reported():
+    """One instance whose dimension payloads (the group keys) all lie outside
+    its domain: tq_batched_check reports TQ_EDOMAIN, as the stand-alone path's
+    tq_check would, and every other instance still equals the oracle."""
+    from paper_2508_05029_amd import tq
+    insts = make_instances(12)
+    bad = 5
+    d, f, G = insts[bad]
+    d = dict(d)
+    d["group"] = np.full_like(d["group"], G)
+    insts[bad] = (d, f, G)
+    want_bad = oracle.join_agg(d, f, wl.batched_query(G))
+    assert want_bad["join_rows"] > 0  # some probe row matches, so the bad key is reached
+    job = pipeline.BatchedJoinAgg(wl.batched_query(8), insts, [(0.5, 4096, 4096)] * len(insts))
+    job.run()
+    with pytest.raises(tq.TqError) as e:
+        job.check()
+    assert e.value.status == tq.TQ_EDOMAIN
+    check_all(job, insts, [i for i in range(len(insts)) if i != bad])
+
+
+def test_batched_sums_wrap_mod_2_64_like_the_oracle():
+    """Prices near 2^62 in every instance: products and per-group sums wrap mod
+    2^64 in the batched launches exactly as in the oracle."""
+    from paper_2508_05029_amd.datagen import uniform
+    insts = []
+    for i, (d, f, G) in enumerate(make_instances(24, seed=wl.BATCH_SEED + 300)):
+        f = dict(f)
+        f["price"] = uniform(len(f["price"]), 2 ** 61, 2 ** 62, np.int64, 83 + i, 0)
+        insts.append((d, f, G))
+    assert any(oracle.join_agg(d, f, wl.batched_query(G))["overflow"].any() for d, f, G in insts)
+    job = pipeline.BatchedJoinAgg(wl.batched_query(8), insts, [(0.5, 4096, 8192)] * len(insts))
+    job.run()
+    job.check()
+    check_all(job, insts)

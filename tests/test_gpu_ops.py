@@ -92,6 +92,30 @@ def test_groupby_lds_modes_match_oracle(domain, skew):
     assert_groups_equal(got, want)
 
 
+@pytest.mark.parametrize("domain", [25, 4000, 100_000])
+def test_groupby_wraps_mod_2_64_like_the_oracle(domain):
+    """Values near +-2^62: the products and the per-group sums leave the int64
+    range and wrap mod 2^64, on the GPU exactly as in the oracle (dense LDS
+    partials, the LDS hot-key table, and global atomics)."""
+    say(f"groupby wrap domain={domain}")
+    n = 200_003
+    t = {"g": uniform(n, 0, domain - 1, np.int64, 81, 0),
+         "v": uniform(n, 2 ** 62 - 2 ** 40, 2 ** 62, np.int64, 81, 1),
+         "u": uniform(n, -(2 ** 62), 2 ** 62, np.int64, 81, 2),
+         "w": uniform(n, 0, 100, np.int32, 81, 3)}
+    sums = [(Factor("v"),), (Factor("v"), Factor("w", -1, 7)), (Factor("u"), Factor("v"), Factor("w", 1, 3))]
+    q = wl.FilterGroupByQuery(preds=[Pred("w", 1, 99)], key=wl.GroupKey(("g",), 1, domain), sums=sums,
+                              avg_of=[0, 1, 2])
+    fg = pipeline.FilterGroupBy(q)
+    fg.run(pipeline.to_device(t))
+    got = fg.result()
+    want = oracle.filter_groupby(t, q)
+    assert oracle.project(t, sums[1])[1].any() and oracle.project(t, sums[2])[1].any()  # products wrap
+    # the exact sums leave the int64 range: SUM(v) of every group with 3 rows or more (v >= 2^62 - 2^40)
+    assert want["overflow"].any() and want["overflow"][want["count"] >= 3, 0].all()
+    assert_groups_equal(got, want)
+
+
 def test_groupby_key_outside_domain_is_latched():
     t = {"g": np.array([0, 1, 7, 2], np.int64), "v": np.arange(4, dtype=np.int64)}
     q = wl.FilterGroupByQuery(preds=[], key=wl.GroupKey(("g",), 1, 4), sums=[(Factor("v"),)], avg_of=[])
@@ -314,6 +338,44 @@ def test_join_build_repeated_into_one_table():
         assert got == sorted(zip(pr.tolist(), br.tolist()))
 
 
+def test_build_after_a_failed_build_starts_clean():
+    """A build that latches TQ_EFULL, then one that fits, into the same buffer:
+    the second build clears the error and its table matches the oracle. Both
+    build paths fail and recover: the region build (rows that fit the scratch
+    segments, too many of them passing the filter) and the counting CAS build
+    (more rows than the scratch holds)."""
+    rng = np.random.default_rng(31)
+    table = torch.empty(tq.join_table_bytes(1000, 0.5), dtype=torch.uint8, device=DEV)  # 2048 slots
+    tq.join_table_init(table)
+    pk = rng.integers(0, 20_000, 30_000).astype(np.int64)
+    # (rows, kept by the filter): region path too full; CAS path that fits; CAS path too full; region path that fits
+    for n, keep_every, fits in ((2000, 1, False), (3000, 6, True), (10_000, 1, False), (500, 1, True)):
+        bk = rng.permutation(20_000)[:n].astype(np.int64)
+        f = (np.arange(n) % keep_every == 0).astype(np.int32)
+        say(f"build n={n} kept={int(f.sum())} fits={fits}")
+        pay = torch.arange(n, dtype=torch.int64, device=DEV)
+        tq.join_build(table, torch.from_numpy(bk).to(DEV), pay, n, filt_cols=[torch.from_numpy(f).to(DEV)],
+                      ps=[(0, 1, 1)], load_factor=0.5)
+        if not fits:
+            with pytest.raises(tq.TqError) as e:
+                tq.check(table)
+            assert e.value.status == tq.TQ_EFULL
+            continue
+        tq.check(table)
+        keep = np.nonzero(f)[0]
+        total, pr, br = oracle.join_pairs(bk[keep], pk)
+        cap = max(total, 1)
+        rows = torch.empty(cap, dtype=torch.int64, device=DEV)
+        bro = torch.empty(cap, dtype=torch.int64, device=DEV)
+        cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+        tq.join_probe(table, torch.from_numpy(pk).to(DEV), len(pk), out_row=rows, out_payload=bro, capacity=cap,
+                      out_count=cnt)
+        tq.check(table)
+        assert int(cnt.item()) == total > 0
+        got = sorted(zip(rows[:total].cpu().tolist(), bro[:total].cpu().tolist()))
+        assert got == sorted(zip(pr.tolist(), keep[br].tolist()))
+
+
 def test_join_table_too_small_latches_full():
     table = torch.empty(tq.join_table_bytes(100, 0.5), dtype=torch.uint8, device=DEV)
     tq.join_table_init(table)
@@ -381,6 +443,24 @@ def test_join_agg_two_sums_and_probe_filter():
                         probe_key=q0.probe_key, probe_preds=[Pred("disc", 2, 8)],
                         sums=[q0.sums[0], [Factor("price", 1, 0)]], domain=q0.domain, avg_of=[0, 1])
     _join_agg_case(dim, fact, q, 0.5, True)
+
+
+@pytest.mark.parametrize("n_fact", [400_000, 6_000_000])
+def test_join_agg_wraps_mod_2_64_like_the_oracle(n_fact):
+    """Prices near 2^62: price * (100 - discount) and the per-group sums wrap
+    mod 2^64 in the fused probe exactly as in the oracle."""
+    say(f"join_agg wrap n_fact={n_fact}")
+    dim, fact = wl.join_agg_tables(n_fact // 4, n_fact, seed=82)
+    fact["price"] = uniform(n_fact, 2 ** 61, 2 ** 62, np.int64, 82, 5)
+    q0 = wl.JOIN_AGG_QUERY
+    q = wl.JoinAggQuery(build_key=q0.build_key, build_payload=q0.build_payload, build_preds=q0.build_preds,
+                        probe_key=q0.probe_key, probe_preds=[], sums=[q0.sums[0], [Factor("price", 1, 0)]],
+                        domain=q0.domain, avg_of=[0, 1])
+    want_rows = _join_agg_case(dim, fact, q, 0.5, True)
+    assert want_rows > 0
+    assert oracle.project(fact, q.sums[0])[1].any()  # the product wraps
+    want = oracle.join_agg(dim, fact, q)
+    assert want["overflow"][:, 1].all()  # so does every group's SUM(price) (prices >= 2^61, thousands of rows)
 
 
 @pytest.mark.parametrize("nd,nf", [(1, 1), (3, 10), (100, 5), (4097, 20_001)])
@@ -474,5 +554,6 @@ def test_read_peak_and_fill():
     assert int(x[123].item()) == 0x0101010101010101
     part = torch.zeros(tq.read_peak_scratch_bytes() // 8, dtype=torch.int64, device=DEV)
     tq.read_peak(x, part)
-    assert int(part.sum().item()) == (1 << 20) * 0x0101010101010101 % (1 << 64) - (1 << 64) * 0 or True
-    torch.cuda.synchronize()
+    # the partial checksums wrap mod 2^64 (int64 adds), so compare modulo 2^64
+    got = sum(int(x) for x in part.cpu().tolist()) % (1 << 64)
+    assert got == ((1 << 20) * 0x0101010101010101) % (1 << 64)

@@ -34,7 +34,8 @@ def expected(setup, q):
     return oracle.join_agg(d, f, setup.q1)
 
 
-def packed(setup, q, res, keys, count, sums, i):
+def packed(setup, q, res, keys, count, sums, avg, i):
+    """(keys, COUNT, SUMs, AVGs) of request i in the oracle's layout."""
     g = res[i].ngroups
     nsum = 5 if q.shape == 0 else 1
     k = keys[i, :g]
@@ -42,7 +43,32 @@ def packed(setup, q, res, keys, count, sums, i):
         k = np.stack([k // 2, k % 2], axis=1)
     else:
         k = k.reshape(-1, 1)
-    return k, count[i, :g], sums[i, :g, :nsum]
+    return k, count[i, :g], sums[i, :g, :nsum], avg[i, :g, :nsum]
+
+
+def same_as_oracle(got, want):
+    """Integers bit-exact; AVG within 1e-12 relative (both sides divide once in IEEE double)."""
+    k, c, sm, av = got
+    if not (k.tolist() == want["keys"].tolist() and c.tolist() == want["count"].tolist()
+            and sm.tolist() == want["sums"].tolist()):
+        return False
+    return bool(np.all(np.abs(av - want["avg"]) <= 1e-12 * np.abs(want["avg"])))
+
+
+def reservation(setup, q, rows=None):
+    """The device bytes a request reserves, by the rule tq_serve_run documents
+    (each piece rounded up to 256 bytes, at least 8), with the join table sized
+    for the whole dimension window (no memory-use history)."""
+    al = lambda b: (max(b, 8) + 255) // 256 * 256  # noqa: E731
+    T = setup.T
+    domain, nsum = (T.fg_domain, T.fg_nsum) if q.shape == 0 else (T.join_domain, T.join_nsum)
+    table = 0 if q.shape == 0 else tq.join_table_bytes(q.n_dim if rows is None else rows, T.load_factor)
+    staging = 0
+    if q.shape == 2:
+        pages = max(len(setup.host.batches[b][3]) for b in range(q.fact_first, q.fact_first + q.n_fact))
+        staging = pages * setup.host.pool.page_bytes * T.nslots
+    return sum(al(b) for b in (tq.groupby_state_bytes(domain, nsum), table, 8 * domain, 8 * domain,
+                               8 * domain * nsum, 8 * domain * nsum, 8, staging, 64))
 
 
 @pytest.fixture(scope="module")
@@ -70,10 +96,9 @@ def test_alone_equals_mix_equals_oracle(setup):
         q = R[i]
         w = expected(setup, q)
         for name, run in (("alone", alone), ("mix", mixed)):
-            k, c, sm = packed(setup, q, *run, i)
-            if not (k.tolist() == w["keys"].tolist() and c.tolist() == w["count"].tolist()
-                    and sm.tolist() == w["sums"].tolist()):
-                bad.append((name, i, q.shape, q.fact_first, q.n_fact, q.dim_first, q.n_dim, int(c.sum()),
+            got = packed(setup, q, *run, i)
+            if not same_as_oracle(got, w):
+                bad.append((name, i, q.shape, q.fact_first, q.n_fact, q.dim_first, q.n_dim, int(got[1].sum()),
                             int(w["count"].sum())))
     for b in bad:
         say("mismatch", b)
@@ -82,27 +107,49 @@ def test_alone_equals_mix_equals_oracle(setup):
         assert alone[0][i].status == 0 and mixed[0][i].status == 0, i
         a = packed(setup, q, *alone, i)
         m = packed(setup, q, *mixed, i)
-        w = expected(setup, q)
+        # alone and in the mix: the same bits, AVG included (one division of the same integers)
         for x, y in zip(a, m):
             assert x.tolist() == y.tolist(), (i, q.shape)
-        assert a[0].tolist() == w["keys"].tolist(), (i, q.shape)
-        assert a[1].tolist() == w["count"].tolist(), (i, q.shape)
-        assert a[2].tolist() == w["sums"].tolist(), (i, q.shape)
+        assert same_as_oracle(a, expected(setup, q)), (i, q.shape)
+    assert not bad
 
 
 def test_budget_admission_and_oversized_request(setup):
+    """A budget with room for about one join request at a time: admission
+    serialises and nothing deadlocks; exactly the requests whose documented
+    reservation exceeds the cap fail with TQ_ENOMEM, and every other result
+    equals the oracle."""
     reqs = wl.serving_requests(12, qps=5000.0, fact_lo=4.0, fact_hi=5.0, seed=wl.SERVE_SEED + 2)
-    R = setup.requests(reqs)
-    # room for about one join request at a time: admission serialises, nothing deadlocks
-    budget = tq.Budget(24 << 20)
-    arena = torch.empty(24 << 20, dtype=torch.uint8, device="cuda")
-    res, keys, count, sums = tq.serve_run(setup.T, R, 4, budget, arena, 25)
-    ok = [res[i].status for i in range(len(reqs))]
-    assert all(s in (0, tq.TQ_ENOMEM) for s in ok)
+    base = setup.requests(reqs)
+    rows = [(base[i].shape, base[i].fact_first, base[i].n_fact, base[i].dim_first, base[i].n_dim, base[i].arrival_s)
+            for i in range(len(reqs))]
+    # two requests that can never fit: joins over the whole dimension (a 2^18-slot table, 9.7 MB), one
+    # in the middle of the queue and one at its end; they must fail without holding up the others
+    rows.insert(4, (1, 0, 50_000, 0, setup.n_dim, rows[3][5]))
+    rows.append((2, 0, 2, 0, setup.n_dim, rows[-1][5]))
+    R = (tq.Request * len(rows))()
+    for i, (shape, ff, nf, df, nd, at) in enumerate(rows):
+        R[i].shape, R[i].fact_first, R[i].n_fact, R[i].dim_first, R[i].n_dim, R[i].arrival_s = shape, ff, nf, df, nd, at
+    reqs = rows
+    setup.T.estimate = 0  # tables for whole windows, so each reservation is known in advance
+    cap = 8 << 20
+    try:
+        budget = tq.Budget(cap)
+        arena = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        run = tq.serve_run(setup.T, R, 4, budget, arena, 25)
+    finally:
+        setup.T.estimate = 1
+    res = run[0]
+    need = [reservation(setup, R[i]) for i in range(len(reqs))]
+    say(f"reservations (MiB): {[round(b / 2**20, 1) for b in need]}, cap {cap / 2**20:.0f}")
+    assert [i for i in range(len(reqs)) if need[i] > cap] == [4, len(reqs) - 1]
     for i in range(len(reqs)):
-        if res[i].status == 0:
-            w = expected(setup, R[i])
-            assert packed(setup, R[i], res, keys, count, sums, i)[1].tolist() == w["count"].tolist()
+        if need[i] > cap:
+            assert res[i].status == tq.TQ_ENOMEM, i
+        else:
+            assert res[i].status == 0, i
+            assert res[i].reserved_bytes == need[i], i
+            assert same_as_oracle(packed(setup, R[i], *run, i), expected(setup, R[i])), i
     assert budget.used == 0
 
 
@@ -113,9 +160,7 @@ def _join_requests(setup, n, seed):
 
 
 def _equal_oracle(setup, R, run, i):
-    k, c, sm = packed(setup, R[i], *run, i)
-    w = expected(setup, R[i])
-    return k.tolist() == w["keys"].tolist() and c.tolist() == w["count"].tolist() and sm.tolist() == w["sums"].tolist()
+    return same_as_oracle(packed(setup, R[i], *run, i), expected(setup, R[i]))
 
 
 def test_history_reservations_are_smaller_and_results_unchanged(setup):
