@@ -59,6 +59,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def graph_steps_for(steps, want):
+    """Steps per graph: the largest divisor of `steps` not above `want`, so that whole
+    replays time exactly `steps` steps."""
+    for g in range(max(1, min(want, steps)), 0, -1):
+        if steps % g == 0:
+            return g
+    return 1
+
+
+def host_cpu():
+    """(model name, logical CPUs this process may run on, os.cpu_count())."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable, os.cpu_count()
+
+
+# threads of the all-cores oracle run: the host share a single-GPU job is given (16 cores
+# per GPU), whatever larger count the machine itself reports
+HOST_THREADS_MAX = 16
+
+
 def events_ms(pairs):
     import torch
     torch.cuda.synchronize()
@@ -161,7 +193,7 @@ def bench_join_agg(args):
 
     # graph: args.graph_steps consecutive steps per replay, rotating the copies; step i
     # runs on stream i % nstreams with that stream's table and state
-    gs = args.graph_steps
+    gs = graph_steps_for(args.steps, args.graph_steps)
 
     def steps_on_streams(ns):
         cur = torch.cuda.current_stream()
@@ -178,7 +210,9 @@ def bench_join_agg(args):
         for s in extra_streams[:ns - 1]:
             cur.wait_stream(s)
 
-    def timed(ns):
+    def timed(ns, k_steps):
+        """Exactly k_steps steps (k_steps / gs replays); wall time of the whole run, and
+        each replay's device time from HIP events around it on the replay stream."""
         side = torch.cuda.Stream()
         side.wait_stream(stream)
         with torch.cuda.stream(side):
@@ -189,18 +223,23 @@ def bench_join_agg(args):
         with torch.cuda.graph(graph):
             steps_on_streams(ns)
         torch.cuda.synchronize()
-        for _ in range(max(1, args.warmup // gs)):
+        for _ in range(max(1, -(-args.warmup // gs))):
             graph.replay()
         torch.cuda.synchronize()
-        reps = max(1, args.steps // gs)
+        reps = k_steps // gs
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
         t0 = time.perf_counter()
-        for _ in range(reps):
+        marks[0].record(stream)
+        for r in range(reps):
             graph.replay()
+            marks[r + 1].record(stream)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / (reps * gs), reps * gs
+        wall = (time.perf_counter() - t0) * 1e3 / (reps * gs)
+        per = [marks[r].elapsed_time(marks[r + 1]) / gs for r in range(reps)]
+        return wall, reps * gs, per
 
-    ms_one_stream = timed(1)[0] if nstreams > 1 else None
-    ms_step, steps = timed(nstreams)
+    ms_one_stream = timed(1, args.steps)[0] if nstreams > 1 else None
+    ms_step, steps, per_replay = timed(nstreams, args.steps)
 
     # timed probe launches inside graph replays are measured by the eager events above;
     # the result of each stream's last replayed step is checked against the oracle below
@@ -214,14 +253,16 @@ def bench_join_agg(args):
         cpu = {"value": round(in_bytes / t_cpu / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"the whole workload (1.5M x 6M rows), median of {runs} runs of the sort-based C oracle, "
                          f"{t_cpu:.2f} s per run"}
-        threads = max(1, min(16, os.cpu_count() or 1))
+        model, usable, total = host_cpu()
+        threads = max(1, min(HOST_THREADS_MAX, usable))
         t_all, ok_all = cpu_all_cores_join_agg(dim, fact, q, want, threads)
         cpu_all = {"value": round(in_bytes / t_all / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
                    "sample": f"the whole workload, the fact table in {threads} slices run at once, {t_all:.2f} s",
-                   "equal_to_one_thread": ok_all}
+                   "equal_to_one_thread": ok_all, "host_cpu": model, "host_cpus_usable": usable,
+                   "host_cpus_reported": total}
     gbs = in_bytes / (ms_step / 1e3) / 1e9
     probe_gbs = probe_bytes / (kern_ms["probe"] / 1e3) / 1e9
-    from paper_2508_05029_amd.bench_more import measured_read_peak
+    from bench_workloads import measured_read_peak
     read_peak = measured_read_peak()
     line = {
         "metric": "input GB/s filter-join-aggregate (% of HBM peak)",
@@ -235,6 +276,9 @@ def bench_join_agg(args):
                    "graph_steps": gs, "streams": nstreams},
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "ms_per_step_one_stream": None if ms_one_stream is None else round(ms_one_stream, 5),
+        "ms_per_step_device": {"replays": len(per_replay), "steps_per_replay": gs,
+                               "median": round(float(np.median(per_replay)), 5),
+                               "min": round(float(np.min(per_replay)), 5), "max": round(float(np.max(per_replay)), 5)},
         "measured_read_peak_gbs": round(read_peak, 1),
         "pct_measured_read_peak": round(100 * gbs / read_peak, 2),
         "rows_per_s": round((n_dim + n_fact) / (ms_step / 1e3), 1),
@@ -269,6 +313,8 @@ def main():
     ap.add_argument("--serve-base-rows", type=int, default=100_000_000,
                     help="serving workload: rows of each base table")
     args = ap.parse_args()
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be at least 1 and --warmup at least 0")
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}), flush=True)
@@ -279,8 +325,8 @@ def main():
         sys.exit(1)
     fn = {"join_agg": bench_join_agg}.get(args.workload)
     if fn is None:
-        from paper_2508_05029_amd import bench_more
-        fn = getattr(bench_more, "bench_" + args.workload)
+        import bench_workloads
+        fn = getattr(bench_workloads, "bench_" + args.workload)
     line = fn(args)
     print(json.dumps(line), flush=True)
 

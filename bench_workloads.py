@@ -9,9 +9,9 @@ import time
 import numpy as np
 import torch
 
-from . import autotune, pipeline, tq
-from .datagen import workloads as wl
-from .hosttable import HostTable
+from paper_2508_05029_amd import autotune, pipeline, tq
+from paper_2508_05029_amd.datagen import workloads as wl
+from paper_2508_05029_amd.hosttable import HostTable
 
 HBM_PEAK_GBS = 8000.0
 PCIE_GBS = 63.0  # PCIe 5.0 x16, one direction
@@ -60,7 +60,8 @@ def bench_filter_groupby(args):
     torch.cuda.synchronize()
     agg_ms = a.elapsed_time(b) / k_agg
     # steps alternate between args.streams compute streams, each with its own state
-    gs = args.graph_steps
+    from bench import graph_steps_for
+    gs = graph_steps_for(args.steps, args.graph_steps)
     nstreams = max(1, args.streams)
     fgs = [fg] + [pipeline.FilterGroupBy(q) for _ in range(nstreams - 1)]
     extra = [torch.cuda.Stream() for _ in range(nstreams - 1)]
@@ -77,6 +78,8 @@ def bench_filter_groupby(args):
             cur.wait_stream(s)
 
     def timed(ns):
+        """Exactly args.steps steps (whole replays of gs steps); wall time, and each
+        replay's device time from HIP events around it."""
         g = torch.cuda.CUDAGraph()
         side = torch.cuda.Stream()
         side.wait_stream(stream)
@@ -88,15 +91,19 @@ def bench_filter_groupby(args):
             steps_on_streams(ns)
         g.replay()
         torch.cuda.synchronize()
-        reps = max(1, args.steps // gs)
+        reps = args.steps // gs
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
         t0 = time.perf_counter()
-        for _ in range(reps):
+        marks[0].record(stream)
+        for r in range(reps):
             g.replay()
+            marks[r + 1].record(stream)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / (reps * gs), reps
+        per = [marks[r].elapsed_time(marks[r + 1]) / gs for r in range(reps)]
+        return (time.perf_counter() - t0) * 1e3 / (reps * gs), reps, per
 
     ms_one = timed(1)[0] if nstreams > 1 else None
-    ms, reps = timed(nstreams)
+    ms, reps, per_replay = timed(nstreams)
     got = fgs[min(nstreams, gs) - 1].result()
     cpu = None
     parity = None
@@ -118,6 +125,10 @@ def bench_filter_groupby(args):
                  "filter_groupby: 1M rows, date<=2436, group (flagA, flagB), 5 sums + COUNT + AVG",
                  {"pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2), "streams": nstreams,
                   "ms_per_step_one_stream": None if ms_one is None else round(ms_one, 5),
+                  "ms_per_step_device": {"replays": len(per_replay), "steps_per_replay": gs,
+                                         "median": round(float(np.median(per_replay)), 5),
+                                         "min": round(float(np.min(per_replay)), 5),
+                                         "max": round(float(np.max(per_replay)), 5)},
                   "roofline": {"bound": "hbm", "achieved": round(kgbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": None,
                                "kernel": "k_groupby", "bytes_per_launch": in_bytes},

@@ -29,6 +29,13 @@ tq_status fail(tq_status s, const char* fmt, ...);
 tq_status hip_fail(hipError_t e, const char* what);
 int device_cu_count();
 
+// A run of `npages` consecutive free pages of the pool (one contiguous host
+// range, pinned when the pool is): *first gets the first page's id. The
+// library's own host staging (descriptor uploads, counts read back) comes from
+// here, so that no call pins memory of its own. TQ_ENOMEM if no run is free.
+tq_status pool_take_run(tq_pagepool* pool, int64_t npages, int32_t* first);
+void pool_give_run(tq_pagepool* pool, int32_t first, int64_t npages);
+
 #define TQ_HIP(call)                                        \
   do {                                                      \
     hipError_t e_ = (call);                                 \

@@ -138,6 +138,8 @@ class Driver {
   CopyDesc* d_desc = nullptr;
   int max_desc = 0;
   int64_t* h_counts = nullptr;  // pinned: offsets or counts read back per batch
+  int32_t host_run = -1;        // pool pages holding h_desc and h_counts
+  int64_t host_run_pages = 0;
 
   Driver(tq_pagepool* p, tq_budget* b, const tq_ooc_plan& pl, hipStream_t c, hipStream_t k, void* w, size_t wb)
       : pool(p), budget(b), plan(pl), copy(c), compute(k), work(static_cast<char*>(w)), work_cap(wb) {
@@ -154,8 +156,7 @@ class Driver {
     (void)hipStreamSynchronize(copy);
     for (auto& q : pending) (void)hipEventDestroy(q.ev);
     if (!spill_pages.empty()) tq_pagepool_free(pool, spill_pages.data(), (int64_t)spill_pages.size());
-    if (h_desc) (void)hipHostFree(h_desc);
-    if (h_counts) (void)hipHostFree(h_counts);
+    if (host_run >= 0) pool_give_run(pool, host_run, host_run_pages);
     if (reserved_fixed) tq_budget_release(budget, reserved_fixed);
     if (chunks_out) tq_budget_release(budget, (size_t)chunks_out * chunk_bytes);
   }
@@ -674,8 +675,18 @@ class Driver {
     max_desc = nparts * (TQ_MAX_COLS + 1) * 4 + 64;
     if ((s = carve((size_t)max_desc * sizeof(CopyDesc), &p))) return s;
     d_desc = static_cast<CopyDesc*>(p);
-    TQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc), (size_t)max_desc * sizeof(CopyDesc), hipHostMallocDefault));
-    TQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_counts), (size_t)(nparts + 8) * 8, hipHostMallocDefault));
+    {
+      // host staging from consecutive pool pages (pinned once with the pool), not pinned per call
+      const size_t desc_bytes = align_up((size_t)max_desc * sizeof(CopyDesc), kAlign);
+      const size_t page = tq_pagepool_page_bytes(pool);
+      const int64_t np = (int64_t)((desc_bytes + (size_t)(nparts + 8) * 8 + page - 1) / page);
+      if ((s = pool_take_run(pool, np, &host_run)))
+        return fail(TQ_ENOMEM, "the page pool has no %lld consecutive free pages for the copy descriptors", (long long)np);
+      host_run_pages = np;
+      char* hb = static_cast<char*>(tq_pagepool_page(pool, host_run));
+      h_desc = reinterpret_cast<CopyDesc*>(hb);
+      h_counts = reinterpret_cast<int64_t*>(hb + desc_bytes);
+    }
 
     // ---- arena: the rest of the workspace, within the budget
     size_t cap_left = tq_budget_cap(budget) > tq_budget_used(budget) ? tq_budget_cap(budget) - tq_budget_used(budget) : 0;

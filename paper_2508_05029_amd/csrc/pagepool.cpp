@@ -108,6 +108,43 @@ int64_t tq_pagepool_free_pages(tq_pagepool* p) {
 
 size_t tq_pagepool_page_bytes(tq_pagepool* p) { return p ? p->page_bytes : 0; }
 
+}  // extern "C"
+
+namespace tq {
+
+tq_status pool_take_run(tq_pagepool* p, int64_t npages, int32_t* first) {
+  if (!p || npages <= 0 || !first) return fail(TQ_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> g(p->mu);
+  // rare (once per out-of-core call): a scan over a map of the free ids
+  std::vector<char> is_free((size_t)p->n_pages, 0);
+  for (int32_t id : p->free_ids) is_free[(size_t)id] = 1;
+  int64_t run = 0, at = -1;
+  for (int64_t i = 0; i < p->n_pages; i++) {
+    run = is_free[(size_t)i] ? run + 1 : 0;
+    if (run == npages) {
+      at = i - npages + 1;
+      break;
+    }
+  }
+  if (at < 0) return fail(TQ_ENOMEM, "no run of %lld free consecutive pages", (long long)npages);
+  p->free_ids.erase(std::remove_if(p->free_ids.begin(), p->free_ids.end(),
+                                   [&](int32_t id) { return id >= at && id < at + npages; }),
+                    p->free_ids.end());
+  *first = (int32_t)at;
+  return TQ_OK;
+}
+
+void pool_give_run(tq_pagepool* p, int32_t first, int64_t npages) {
+  if (!p || first < 0) return;
+  std::lock_guard<std::mutex> g(p->mu);
+  for (int64_t i = 0; i < npages; i++)
+    if (first + i < p->n_pages) p->free_ids.push_back((int32_t)(first + i));
+}
+
+}  // namespace tq
+
+extern "C" {
+
 tq_status tq_batch_layout(int64_t nrows, int32_t ncol, const int32_t* types, size_t page_bytes, int64_t* col_offset,
                           size_t* bytes, int64_t* npages) {
   if (nrows < 0 || ncol < 0 || ncol > 64 || (ncol > 0 && (!types || !col_offset)) || page_bytes == 0)
