@@ -118,6 +118,23 @@ tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_
                             int32_t log2_fanout, int32_t skip, int64_t* d_out_keys, void* const* d_out_payload,
                             int64_t* d_offsets, void* d_scratch, size_t scratch_bytes, hipStream_t stream);
 
+/* tq_hash_partition for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc): the
+ * same partitioning and outputs, with the scratch taken from a fixed array in
+ * the library's device image (TQ_PARTITION_STATIC_SCRATCH_BYTES per GPU, held
+ * until the process ends) instead of a caller buffer. The call allocates
+ * nothing; it looks the array's address up on its first call on each device
+ * (the calling thread's current device must be the one `stream` belongs to).
+ * A size whose scratch (tq_hash_partition_scratch_bytes(n, log2_fanout))
+ * exceeds the array returns TQ_EINVAL before anything is enqueued. Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be serialised by
+ * the caller. */
+#define TQ_PARTITION_STATIC_SCRATCH_BYTES (8u << 20)
+tq_status tq_hash_partition_noalloc(const int64_t* d_keys, const tq_col* payload, int32_t npay, int64_t n,
+                                    int32_t log2_fanout, int32_t skip, int64_t* d_out_keys,
+                                    void* const* d_out_payload, int64_t* d_offsets, hipStream_t stream);
+
 /* ------------------------------------------------------------- hash join */
 
 /* An open-addressing hash table (linear probing over buckets of 8 slots) for

@@ -1,6 +1,8 @@
 // Hash partitioning: per-tile histogram -> exclusive scan over (partition, tile)
 // -> per-tile scatter staged through LDS, so that each partition's run of a
 // tile leaves the workgroup as one contiguous, coalesced write.
+#include <mutex>
+
 #include "common.h"
 
 namespace tq {
@@ -200,9 +202,41 @@ size_t tq_hash_partition_scratch_bytes(int64_t n, int32_t log2_fanout) {
   return part_scratch(n, log2_fanout).bytes;
 }
 
-tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_t npay, int64_t n, int32_t log2_fanout,
-                            int32_t skip, int64_t* d_out_keys, void* const* d_out_payload, int64_t* d_offsets,
-                            void* d_scratch, size_t scratch_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace tq {
+
+// The scratch of tq_hash_partition_noalloc: a fixed device array, one copy per
+// GPU, held until the process ends. Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device (the array's name
+// on the host is a stand-in, not a device address).
+constexpr size_t kStaticScratchBytes = (size_t)TQ_PARTITION_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) int64_t scratch[kStaticScratchBytes / 8];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up on the first call on each device.
+static tq_status static_scratch(void** out) {
+  int dev = -1;
+  TQ_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TQ_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(TQ_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TQ_OK;
+}
+
+static tq_status partition(const int64_t* d_keys, const tq_col* payload, int32_t npay, int64_t n, int32_t log2_fanout,
+                           int32_t skip, int64_t* d_out_keys, void* const* d_out_payload, int64_t* d_offsets,
+                           void* d_scratch, size_t scratch_bytes, bool static_scratch_area, hipStream_t stream) {
   if (n < 0) return fail(TQ_EINVAL, "n < 0");
   if (log2_fanout < 0 || log2_fanout > kMaxFanoutBits)
     return fail(TQ_EINVAL, "log2_fanout %d outside [0, %d]", log2_fanout, kMaxFanoutBits);
@@ -211,8 +245,13 @@ tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_
   if (!d_offsets) return fail(TQ_EINVAL, "offsets are NULL");
   if (n > 0 && (!d_keys || !d_out_keys)) return fail(TQ_EINVAL, "NULL keys");
   PartScratch ps = part_scratch(n, log2_fanout);
-  if (scratch_bytes < ps.bytes || (n > 0 && !d_scratch))
+  if (static_scratch_area) {
+    if (ps.bytes > kStaticScratchBytes)
+      return fail(TQ_EINVAL, "%lld rows at %d partition bits need %zu bytes of scratch; the fixed area holds %zu",
+                  (long long)n, log2_fanout, ps.bytes, kStaticScratchBytes);
+  } else if (scratch_bytes < ps.bytes || (n > 0 && !d_scratch)) {
     return fail(TQ_EINVAL, "scratch has %zu bytes, needs %zu", scratch_bytes, ps.bytes);
+  }
   PayCols pc{};
   pc.n = npay;
   for (int c = 0; c < npay; c++) {
@@ -223,7 +262,13 @@ tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_
     pc.out[c] = d_out_payload[c];
     pc.w[c] = payload[c].type;
   }
+  if (static_scratch_area) {  // arguments are valid: only now look the area up
+    tq_status s = static_scratch(&d_scratch);
+    if (s) return s;
+  }
   const int nb = 1 << log2_fanout;
+  // every word of the scratch that a kernel reads was written by an earlier kernel of
+  // this call (the histogram fills all (partition, tile) counts), so nothing is cleared
   int64_t* counts = static_cast<int64_t*>(d_scratch);
   int64_t* bsum = counts + ps.L;
   if (n > 0) {
@@ -239,6 +284,24 @@ tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_
                      d_offsets);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
+}
+
+}  // namespace tq
+
+extern "C" {
+
+tq_status tq_hash_partition(const int64_t* d_keys, const tq_col* payload, int32_t npay, int64_t n, int32_t log2_fanout,
+                            int32_t skip, int64_t* d_out_keys, void* const* d_out_payload, int64_t* d_offsets,
+                            void* d_scratch, size_t scratch_bytes, hipStream_t stream) {
+  return partition(d_keys, payload, npay, n, log2_fanout, skip, d_out_keys, d_out_payload, d_offsets, d_scratch,
+                   scratch_bytes, false, stream);
+}
+
+tq_status tq_hash_partition_noalloc(const int64_t* d_keys, const tq_col* payload, int32_t npay, int64_t n,
+                                    int32_t log2_fanout, int32_t skip, int64_t* d_out_keys,
+                                    void* const* d_out_payload, int64_t* d_offsets, hipStream_t stream) {
+  return partition(d_keys, payload, npay, n, log2_fanout, skip, d_out_keys, d_out_payload, d_offsets, nullptr, 0, true,
+                   stream);
 }
 
 }  // extern "C"

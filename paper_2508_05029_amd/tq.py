@@ -73,6 +73,7 @@ def lib():
             "tq_filter_project": (_i32, [_vp, _i32, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
             "tq_hash_partition_scratch_bytes": (_sz, [_i64, _i32]),
             "tq_hash_partition": (_i32, [_vp, _vp, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+            "tq_hash_partition_noalloc": (_i32, [_vp, _vp, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp]),
             "tq_join_table_bytes": (_sz, [_i64, _f64]),
             "tq_join_table_init": (_i32, [_vp, _sz, _vp]),
             "tq_join_table_rows": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64), _vp]),
@@ -180,6 +181,16 @@ def hash_partition(keys, payload, n, log2_fanout, skip, out_keys, out_payload, o
                                    outp, offsets.data_ptr(), _ptr(scratch),
                                    0 if scratch is None else scratch.numel() * scratch.element_size(),
                                    _stream(stream)))
+
+
+def hash_partition_noalloc(keys, payload, n, log2_fanout, skip, out_keys, out_payload, offsets, stream=None):
+    """tq_hash_partition with the library's fixed scratch area (no scratch argument)."""
+    outp = (ctypes.c_void_p * max(1, len(out_payload)))(*[t.data_ptr() for t in out_payload])
+    _check(lib().tq_hash_partition_noalloc(_ptr(keys), cols(payload), len(payload), n, log2_fanout, skip,
+                                           _ptr(out_keys), outp, offsets.data_ptr(), _stream(stream)))
+
+
+PARTITION_STATIC_SCRATCH_BYTES = 8 << 20  # TQ_PARTITION_STATIC_SCRATCH_BYTES
 
 
 def join_table_bytes(n_build_max: int, load_factor: float) -> int:

@@ -104,6 +104,11 @@ def test_invalid_arguments_are_rejected_synchronously():
     # partition fan-out and scratch
     assert L.tq_hash_partition(FAKE, None, 0, 10, 11, 0, FAKE, None, FAKE, FAKE, 1 << 20, None) == tq.TQ_EINVAL
     assert L.tq_hash_partition(FAKE, None, 0, 100000, 8, 0, FAKE, None, FAKE, FAKE, 16, None) == tq.TQ_EINVAL
+    # the variant with the fixed scratch area: sizes beyond the area, bad fan-out
+    assert tq.hash_partition_scratch_bytes(5_000_000, 10) > tq.PARTITION_STATIC_SCRATCH_BYTES
+    assert L.tq_hash_partition_noalloc(FAKE, None, 0, 5_000_000, 10, 0, FAKE, None, FAKE, None) == tq.TQ_EINVAL
+    assert b"fixed area" in L.tq_last_error()
+    assert L.tq_hash_partition_noalloc(FAKE, None, 0, 10, 11, 0, FAKE, None, FAKE, None) == tq.TQ_EINVAL
     # probe: expression factor count
     e = tq.exprs([[(0, 1, 0)] * 3])
     e[0].nf = 4
