@@ -566,10 +566,16 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const 
 // A row is finished from its home bucket alone when the bucket decides it: no
 // tag match and a free slot (a miss), exactly one candidate and a free slot
 // (hit or miss), or a hit on unique build keys. Any other row (a full home
-// bucket, further candidates) goes to a queue in LDS private to its wave; the
-// wave walks 64 queued rows at a time to the end of their chains. A queued row
-// starts again from its home bucket and nothing of it was aggregated before,
-// so every match is counted exactly once.
+// bucket, further candidates) goes to a queue in LDS private to its wave. A
+// queued row starts again from its home bucket and nothing of it was
+// aggregated before, so every match is counted exactly once. The queue is
+// walked (64 rows at a time, each to the end of its chain) only outside the
+// pipelined loop: at its end, or when the queue could not take another
+// iteration's rows, in which case the loop stops before finishing anything of
+// the tiles in flight, the queue is walked, and the loop starts again at the
+// first unfinished tile. (A walk inside the loop would wait for every load in
+// flight, and the compiler then also waits for all of them on the loop's own
+// path, as a register the walk loads into is one the loop reuses.)
 //
 // With BLOOM, the workgroup holds the build's Bloom filter in LDS (one
 // workgroup per CU, for its 128 KiB) and a row the filter rejects is not live:
@@ -581,7 +587,12 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const 
 #endif
 constexpr int kPipeBlocksPerCU = TQ_PIPE_BLOCKS_PER_CU;
 constexpr int kPipeRows = 2;
-constexpr int kPipeQ = 128;  // queue entries per wave: below 64 at a tile's start, each row adds at most 64
+constexpr int kPipeQ = 320;  // queue entries per wave (row offsets from the wave's first row, 4 bytes)
+// the loop goes on only while the queue can take the two tiles an iteration finishes
+constexpr int kPipeQLimit = kPipeQ - 2 * kWave * kPipeRows;
+static_assert(kPipeQLimit >= 0, "queue");
+// rows per launch of the pipelined probe: queued rows are kept as 32-bit offsets
+constexpr int64_t kPipeMaxRows = (int64_t)1 << 31;
 constexpr int kBloomPipeBlock = 1024;  // one workgroup per CU beside the filter: 16 waves
 constexpr size_t kMaxPipeLds = 64 * 1024;  // dynamic LDS of a launch without a per-kernel attribute
 constexpr size_t kCuLds = 160 * 1024;
@@ -630,7 +641,7 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   agg.defer = true;
   agg.init(T, smem);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  int64_t* qrow = reinterpret_cast<int64_t*>(smem + agg_lds) + (int64_t)wave * kPipeQ;  // queued row numbers
+  uint32_t* qrow = reinterpret_cast<uint32_t*>(smem + agg_lds) + (int64_t)wave * kPipeQ;  // queued rows
   // (the barrier after which the filter, the partials and the queues may be
   // used comes after the first tiles' column loads, which it overlaps)
   Probe pr;
@@ -640,38 +651,41 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   const v2i64* ccol[NC];
 #pragma unroll
   for (int c = 0; c < NC; c++) ccol[c] = c < P.ncol ? static_cast<const v2i64*>(P.col[c].p) : kcol;
-  int qh = 0, qn = 0;  // queue head and length (the same in every lane)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * R;
+  const int64_t wbase = ((int64_t)blockIdx.x * blockDim.x + wave * kWave) * R;  // the wave's first row
+  int qn = 0;  // queued rows (the same in every lane); the queue is only appended to inside the loop
 
-  // Walks `cnt` (<= 64) queued rows from the head, one per lane (their key and
-  // columns are read again: queued rows are rare).
-  auto drain = [&](int cnt) {
+  // Walks every queued row to the end of its chain, 64 at a time, one per lane
+  // (their key and columns are read again: queued rows are rare), and empties
+  // the queue.
+  auto drain_all = [&] {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int x = (qh + lane) & (kPipeQ - 1);
-    bool ok1[1] = {lane < cnt};
-    int64_t k1[1] = {0}, e1[NE];
+    for (int q0 = 0; q0 < qn; q0 += kWave) {
+      bool ok1[1] = {q0 + lane < qn};
+      int64_t k1[1] = {0}, e1[NE];
 #pragma unroll
-    for (int j = 0; j < NE; j++) e1[j] = 0;
-    if (ok1[0]) {
-      const int64_t row = qrow[x];
-      int64_t v1[NC][1];
+      for (int j = 0; j < NE; j++) e1[j] = 0;
+      if (ok1[0]) {
+        const int64_t row = wbase + qrow[q0 + lane];
+        int64_t v1[NC][1];
 #pragma unroll
-      for (int c = 0; c < NC; c++) v1[c][0] = c < P.ncol ? reinterpret_cast<const int64_t*>(ccol[c])[row] : 0;
-      k1[0] = pkeys[row];
+        for (int c = 0; c < NC; c++) v1[c][0] = c < P.ncol ? reinterpret_cast<const int64_t*>(ccol[c])[row] : 0;
+        k1[0] = pkeys[row];
 #pragma unroll
-      for (int j = 0; j < NE; j++) e1[j] = j < P.ne ? eval_expr<NC>(P.expr[j], v1, 0) : 0;
+        for (int j = 0; j < NE; j++) e1[j] = j < P.ne ? eval_expr<NC>(P.expr[j], v1, 0) : 0;
+      }
+      pr.walk(ok1, k1, [&](const bool (&hit)[1], const int64_t (&pay)[1]) {
+        if (hit[0]) agg.add(T, pay[0], e1, P.ne);
+      });
     }
-    pr.walk(ok1, k1, [&](const bool (&hit)[1], const int64_t (&pay)[1]) {
-      if (hit[0]) agg.add(T, pay[0], e1, P.ne);
-    });
-    qh = (qh + cnt) & (kPipeQ - 1);
-    qn -= cnt;
+    qn = 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   };
 
-  if (n_main > 0) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x * R;
-    const int64_t wbase = ((int64_t)blockIdx.x * blockDim.x + wave * kWave) * R;  // the wave's first row
-    int64_t r = wbase + lane * R;
+  bool first = true;  // the one workgroup barrier comes in the first prologue (or below)
+  int64_t pos = wbase;  // this wave's first tile not yet finished
+  while (pos < n_main) {
+    int64_t r = pos + lane * R;
     v2i64 cva[NC], cka, cvb[NC], ckb;  // columns of two tiles ahead (alternating sets)
     v4i32 tw[R];            // tags of the tile 1 ahead
     v2i64 kv[R];            // candidate slots of the current tile
@@ -720,7 +734,8 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
 #pragma unroll
       for (int i = 0; i < R; i++) kv[i] = pr.slots[sm[i] ? t.b[i] * kBucket + __builtin_ctz(sm[i]) : 0];
     };
-    // (a) finish a tile from its slots (before any register they live in is reloaded)
+    // (a) finish a tile from its slots (before any register they live in is
+    // reloaded); rows the home bucket does not decide go to the queue
     auto finish = [&](const PipeRows<NE>& t) {
 #pragma unroll
       for (int i = 0; i < R; i++) {
@@ -736,12 +751,9 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
           if (slow) {
             const int rank =
                 __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            const int x = (qh + qn + rank) & (kPipeQ - 1);
-            qrow[x] = t.row + i;
+            qrow[qn + rank] = (uint32_t)(t.row + i - wbase);
           }
           qn += __popcll(bal);
-          // keep room for the next row's 64 (rare: the loads of later tiles wait with it)
-          if (i + 1 < R && qn >= kWave) drain(kWave);
         }
       }
     };
@@ -751,7 +763,8 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
     load_cols(cva, cka, r);
     load_cols(cvb, ckb, r + stride);
     asm volatile("" ::: "memory");
-    __syncthreads();
+    if (first) __syncthreads();
+    first = false;
     cols_to_tags(cva, cka, r, ra);
     asm volatile("" ::: "memory");
     tags_to_slots(ra);
@@ -769,8 +782,11 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
     // four ahead. The empty asm statements keep each stage's loads where they
     // are: the compiler would otherwise merge them with later ones, after the
     // loads they must precede. A second tile past the wave's last reads tile 0
-    // and is not live.
-    for (int64_t w0 = wbase; w0 < n_main; w0 += 2 * stride, r += 2 * stride) {
+    // and is not live. The pass stops early, finishing nothing of the tiles in
+    // flight, when the queue could not take its rows.
+    int64_t w0 = pos;
+    for (; w0 < n_main; w0 += 2 * stride, r += 2 * stride) {
+      if (qn > kPipeQLimit) break;
       finish(ra);
       tags_to_slots(rb);
       asm volatile("" ::: "memory");
@@ -778,7 +794,6 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
       asm volatile("" ::: "memory");
       load_cols(cva, cka, r + 4 * stride);
       asm volatile("" ::: "memory");
-      while (qn >= kWave) drain(kWave);  // queued rows are walked after this tile's loads are on their way
       finish(rb);
       tags_to_slots(ra);
       asm volatile("" ::: "memory");
@@ -786,12 +801,12 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
       asm volatile("" ::: "memory");
       load_cols(cvb, ckb, r + 5 * stride);
       asm volatile("" ::: "memory");
-      while (qn >= kWave) drain(kWave);
     }
-  } else {
-    __syncthreads();
+    pos = w0;  // every tile before w0 is finished (its queued rows are in the queue)
+    if (qn > 0) drain_all();
   }
-  if (qn > 0) drain(qn);
+  if (first) __syncthreads();  // a wave with no full tile still takes part in the barrier
+  if (qn > 0) drain_all();
   if (n_main < n && blockIdx.x == 0 && threadIdx.x == 0) {
     // the row of the partial last tile
     const int64_t rt = n_main;
@@ -1011,26 +1026,32 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
     for (int c = 0; c < P.ncol; c++) all64 = all64 && P.col[c].w == 8;
     const int nq = ne_bucket(agg->nsum);
     const size_t agg_lds16 = (lds + 15) / 16 * 16;
-    const size_t pipe_lds = agg_lds16 + (size_t)(kAggBlock / kWave) * kPipeQ * 8;
-    const size_t bloom_lds = agg_lds16 + (size_t)(kBloomPipeBlock / kWave) * kPipeQ * 8;
+    const size_t pipe_lds = agg_lds16 + (size_t)(kAggBlock / kWave) * kPipeQ * 4;
+    const size_t bloom_lds = agg_lds16 + (size_t)(kBloomPipeBlock / kWave) * kPipeQ * 4;
     if (all64 && nq <= 2 && pipe_lds <= kMaxPipeLds) {
       // with the build's Bloom filter in LDS when it fits beside the queues and
       // the group-by (one workgroup of 16 waves per CU), else without (two of 8)
       const bool bloom = bloom_lds <= kMaxBloomPipeLds;
       const int threads = bloom ? kBloomPipeBlock : kAggBlock;
-      const int64_t want = (n + (int64_t)threads * kPipeRows - 1) / ((int64_t)threads * kPipeRows);
-      const int64_t cap = std::min<int64_t>(kAggRows, (int64_t)(bloom ? 1 : kPipeBlocksPerCU) * device_cu_count());
-      dim3 grid((int)std::max<int64_t>(1, std::min(want, cap))), block(threads);
       const int agg_lds = (int)agg_lds16;
-      TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE, if constexpr (NE <= 2) {
-        const size_t q = (size_t)(threads / kWave) * kPipeQ * 8;
-        if (bloom)
-          hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, true>), grid, block, agg_lds + q, stream, h, d_probe_keys, n,
-                             P, T, agg_lds);
-        else
-          hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, false>), grid, block, agg_lds + q, stream, h, d_probe_keys, n,
-                             P, T, agg_lds);
-      });
+      // one launch per kPipeMaxRows rows (an even count: the 16-byte column loads stay aligned)
+      for (int64_t c0 = 0; c0 < n; c0 += kPipeMaxRows) {
+        const int64_t nc = std::min<int64_t>(kPipeMaxRows, n - c0);
+        RowPlan Pc = P;
+        for (int c = 0; c < Pc.ncol; c++) Pc.col[c].p = static_cast<const int64_t*>(P.col[c].p) + c0;
+        const int64_t want = (nc + (int64_t)threads * kPipeRows - 1) / ((int64_t)threads * kPipeRows);
+        const int64_t cap = std::min<int64_t>(kAggRows, (int64_t)(bloom ? 1 : kPipeBlocksPerCU) * device_cu_count());
+        dim3 grid((int)std::max<int64_t>(1, std::min(want, cap))), block(threads);
+        TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE, if constexpr (NE <= 2) {
+          const size_t q = (size_t)(threads / kWave) * kPipeQ * 4;
+          if (bloom)
+            hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, true>), grid, block, agg_lds + q, stream, h, d_probe_keys + c0,
+                               nc, Pc, T, agg_lds);
+          else
+            hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, false>), grid, block, agg_lds + q, stream, h, d_probe_keys + c0,
+                               nc, Pc, T, agg_lds);
+        });
+      }
     } else {
       dim3 grid(agg_grid(n)), block(kAggBlock);
       TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE,
