@@ -5,7 +5,8 @@ Default workload (join_agg): dimension 1.5M rows (key, group, date), fact 6M
 rows (fk, price, discount). One step = filter the dimension to a 365-day
 window, build the open-addressing table, probe it with every fact row while
 aggregating SUM(price * (100 - discount)) and COUNT per group, and finalize the
-25 groups in key order. Inputs are device resident; four copies rotate so that
+25 groups in key order (the finalize also empties the group-by state for the
+next step). Inputs are device resident; four copies rotate so that
 consecutive steps do not find their input in the 256 MiB Infinity Cache.
 
 value = input bytes the query must read (16 B per dimension row + 24 B per fact
@@ -153,36 +154,39 @@ def bench_join_agg(args):
     jas = [ja] + [pipeline.JoinAgg(q, n_dim, args.load_factor) for _ in range(nstreams - 1)]
     extra_streams = [torch.cuda.Stream() for _ in range(nstreams - 1)]
 
+    # A step: build, probe with the fused group-by, finalize. The finalize leaves the
+    # group-by state empty (tq_groupby_finalize_reset), so the state is set up once here
+    # and each step starts from zero without a launch of its own.
+    for j in jas:
+        j.init_state()
+
     def step(i):
         d, f = copies[i % len(copies)]
-        ja.init_state()
         ja.build(d)
         ja.probe(f)
-        ja.finalize()
+        ja.finalize(reset=True)
 
     # eager warmup, then per-kernel timing with HIP events on the launch stream
     for i in range(max(args.warmup, 3)):
         step(i)
     torch.cuda.synchronize()
-    ev = {k: [] for k in ("init", "build", "probe", "finalize")}
+    ev = {k: [] for k in ("build", "probe", "finalize")}
     for i in range(args.event_steps):
         d, f = copies[i % len(copies)]
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         marks[0].record(stream)
-        ja.init_state()
-        marks[1].record(stream)
         ja.build(d)
-        marks[2].record(stream)
+        marks[1].record(stream)
         ja.probe(f)
+        marks[2].record(stream)
+        ja.finalize(reset=True)
         marks[3].record(stream)
-        ja.finalize()
-        marks[4].record(stream)
         for j, k in enumerate(ev):
             ev[k].append((marks[j], marks[j + 1]))
     kern_ms = {k: float(np.mean(events_ms(v))) for k, v in ev.items()}
     # the probe alone: back-to-back launches between two events on its stream, over the
     # rotating copies so that no launch finds its columns in the Infinity Cache (its state
-    # just accumulates; every timed step below starts from a fresh one)
+    # just accumulates, and is set up afresh below)
     k_probe = 20
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -190,6 +194,7 @@ def bench_join_agg(args):
         ja.probe(copies[i % len(copies)][1])
     e1.record(stream)
     kern_ms["probe"] = events_ms([(e0, e1)])[0] / k_probe
+    ja.init_state()
 
     # graph: args.graph_steps consecutive steps per replay, rotating the copies; step i
     # runs on stream i % nstreams with that stream's table and state
@@ -203,10 +208,9 @@ def bench_join_agg(args):
             k = i % ns
             d, f = copies[i % len(copies)]
             with torch.cuda.stream(cur if k == 0 else extra_streams[k - 1]):
-                jas[k].init_state()
                 jas[k].build(d)
                 jas[k].probe(f)
-                jas[k].finalize()
+                jas[k].finalize(reset=True)
         for s in extra_streams[:ns - 1]:
             cur.wait_stream(s)
 
@@ -308,7 +312,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ooc-scale", type=float, default=1.0, help="fraction of the 600M x 150M out-of-core tables")
     ap.add_argument("--instances", type=int, default=4096, help="batched workload: number of instances")
-    ap.add_argument("--requests", type=int, default=400, help="serving workload: number of requests")
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="serving workload: measured requests (after 100 warm-up requests)")
     ap.add_argument("--workers", type=int, default=6, help="serving workload: concurrent workers")
     ap.add_argument("--serve-base-rows", type=int, default=100_000_000,
                     help="serving workload: rows of each base table")

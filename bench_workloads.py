@@ -137,6 +137,53 @@ def bench_filter_groupby(args):
 
 # ------------------------------------------------------------------ out of core
 
+def merge_groups(parts):
+    """Groups of several partial results merged: COUNT and SUM added (int64, wrapping
+    mod 2^64), in ascending key order. Returns (keys, count, sums) as lists."""
+    count, sums = {}, {}
+    for r in parts:
+        for g, k in enumerate(r["keys"].reshape(-1).tolist()):
+            count[k] = count.get(k, 0) + int(r["count"][g])
+            s_ = sums.setdefault(k, [0] * r["sums"].shape[1])
+            for j in range(r["sums"].shape[1]):
+                s_[j] = (s_[j] + int(r["sums"][g, j]) + 2**63) % 2**64 - 2**63
+    keys = sorted(count)
+    return keys, [count[k] for k in keys], [sums[k] for k in keys]
+
+
+def ooc_oracle_full(n_fact, n_dim, q, threads):
+    """The oracle over the whole out-of-core workload: the dimension generated once, the
+    fact table in `threads` row slices generated and joined at once (each slice's C calls
+    release the interpreter lock), the slices' groups merged mod 2^64. Only the fact
+    columns the query reads are generated. Returns ((keys, count, sums), seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    t0 = time.perf_counter()
+    dim = {}
+    for name, dt in wl.OOC_DIM_COLS:
+        a = np.empty(n_dim, dtype=dt)
+        wl.ooc_fill_dim(name, a.ctypes.data, 0, n_dim, n_dim)
+        dim[name] = a
+    need = {q.probe_key} | {f.col for e in q.sums for f in e if f.col is not None}
+    cuts = [n_fact * i // threads for i in range(threads + 1)]
+
+    def one(i):
+        a, b = cuts[i], cuts[i + 1]
+        f = {}
+        for name, dt in wl.OOC_FACT_COLS:
+            if name in need:
+                arr = np.empty(b - a, dtype=dt)
+                wl.ooc_fill_fact(name, arr.ctypes.data, a, b - a, n_dim)
+                f[name] = arr
+        r = oracle.join_agg(dim, f, q)
+        del f
+        return r
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(one, range(threads)))
+    return merge_groups(parts), time.perf_counter() - t0
+
+
 def _pinned_copy_peak(pool_bytes=1 << 30):
     h = torch.empty(pool_bytes, dtype=torch.uint8, pin_memory=True)
     d = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
@@ -191,6 +238,19 @@ def bench_ooc(args):
         torch.cuda.empty_cache()
     st, r = results["adaptive"]
     ms = st["ms_total"]
+    # every group of every full-size run against the oracle over the whole workload
+    full = None
+    if not args.no_cpu_baseline:
+        from bench import HOST_THREADS_MAX, host_cpu
+        _, usable, _ = host_cpu()
+        threads = max(1, min(HOST_THREADS_MAX, usable))
+        (wk, wc, ws), t_full = ooc_oracle_full(n_fact, n_dim, q, threads)
+        full = {"rows": f"{n_fact} fact x {n_dim} dim (the whole workload)", "threads": threads,
+                "oracle_s": round(t_full, 1), "groups": len(wk)}
+        for label, (_, rr) in results.items():
+            full["equal_" + label] = (rr["keys"].reshape(-1).tolist() == wk and rr["count"].tolist() == wc
+                                      and rr["sums"].tolist() == ws)
+        log("ooc full-size oracle", full)
     in_bytes = fact_bytes + n_dim * 16
     link_gbs = st["bytes_h2d"] / (ms / 1e3) / 1e9
     # parity on a sample scale against the oracle
@@ -239,7 +299,7 @@ def bench_ooc(args):
                  "roofline": {"bound": "host-link", "achieved": round(link_gbs, 3), "peak": PCIE_GBS, "unit": "GB/s",
                               "frac": round(link_gbs / PCIE_GBS, 4), "traffic": None,
                               "kernel": "tq_ooc_join_agg (whole pipeline)"},
-                 "cpu_baseline": cpu, "parity_vs_oracle": parity})
+                 "cpu_baseline": cpu, "parity_vs_oracle": parity, "parity_full_size": full})
     dt.free()
     ft.free()
     pool.close()
@@ -305,22 +365,40 @@ def bench_batched(args):
         import oracle
         job.run()
         torch.cuda.synchronize()
-        which = list(range(0, count, max(1, count // 24)))
-        got = job.results(which)
-        ok = True
+        # every instance against the oracle (on the host's cores at once); the single-core
+        # baseline is timed on an evenly spaced sample of them
+        from concurrent.futures import ThreadPoolExecutor
+        from bench import HOST_THREADS_MAX, host_cpu
+        got = job.results(list(range(count)))
+        sample = set(range(0, count, max(1, count // 24)))
+
+        def check(i):
+            d, f, G = insts[i]
+            want = oracle.join_agg(d, f, wl.batched_query(G))
+            return (got[i]["keys"].reshape(-1).tolist() == want["keys"].reshape(-1).tolist()
+                    and got[i]["sums"].tolist() == want["sums"].tolist()
+                    and got[i]["count"].tolist() == want["count"].tolist()
+                    and bool(np.all(np.abs(got[i]["avg"] - want["avg"]) <= 1e-12 * np.abs(want["avg"]))))
+
+        _, usable, _ = host_cpu()
+        threads = max(1, min(HOST_THREADS_MAX, usable))
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            oks = list(ex.map(check, range(count)))
+        t_all = time.perf_counter() - t1
+        bad = [i for i, o in enumerate(oks) if not o]
         tc = 0.0
         rows = 0
-        for k, i in enumerate(which):
+        for i in sorted(sample):
             d, f, G = insts[i]
             t1 = time.perf_counter()
-            want = oracle.join_agg(d, f, wl.batched_query(G))
+            oracle.join_agg(d, f, wl.batched_query(G))
             tc += time.perf_counter() - t1
             rows += len(d["key"]) * 24 + len(f["fk"]) * 24
-            ok = ok and got[k]["sums"].tolist() == want["sums"].tolist() and \
-                got[k]["count"].tolist() == want["count"].tolist()
-        parity = {"instances_checked": len(which), "equal": ok}
+        parity = {"instances_checked": count, "equal": not bad, "unequal_instances": bad[:20],
+                  "oracle_threads": threads, "oracle_s": round(t_all, 1)}
         cpu = {"value": round(rows / tc / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(which)} of the {count} instances, {tc:.2f} s"}
+               "sample": f"{len(sample)} evenly spaced of the {count} instances, {tc:.2f} s"}
     gbs = in_bytes / (ms / 1e3) / 1e9
     return _base("input GB/s batched join-aggregate instances (% of HBM peak)", gbs, "GB/s", args, ms, reps,
                  f"batched: {count} instances, fact log-uniform 1e3..1e6, dim = fact/4, groups log-uniform "
@@ -337,49 +415,107 @@ def bench_batched(args):
 
 # ------------------------------------------------------------------ serving
 
+def _serve_expected(setup, q):
+    """The oracle's result for one served request (its windows of the base tables)."""
+    import oracle
+    if q.shape == 0:
+        t = {k: v[q.fact_first:q.fact_first + q.n_fact] for k, v in setup.fg.items()}
+        return oracle.filter_groupby(t, setup.q0)
+    d = {k: v[q.dim_first:q.dim_first + q.n_dim] for k, v in setup.dim.items()}
+    if q.shape == 1:
+        f = {k: v[q.fact_first:q.fact_first + q.n_fact] for k, v in setup.fact.items()}
+    else:
+        lo = setup.host.batches[q.fact_first][0]
+        last = setup.host.batches[q.fact_first + q.n_fact - 1]
+        f = {k: v[lo:last[0] + last[1]] for k, v in setup.hfact.items()}
+    return oracle.join_agg(d, f, setup.q1)
+
+
+def _serve_result(q, out, i):
+    """(keys, COUNT, SUMs, AVGs) of served request i in the oracle's layout."""
+    res, keys, count, sums, avg = out
+    g = res[i].ngroups
+    nsum = 5 if q.shape == 0 else 1
+    k = keys[i, :g]
+    k = np.stack([k // 2, k % 2], axis=1) if q.shape == 0 else k.reshape(-1, 1)
+    return k, count[i, :g], sums[i, :g, :nsum], avg[i, :g, :nsum]
+
+
+def _same(a, b):
+    """Integer parts bit-equal, AVG within 1e-12 relative."""
+    (ka, ca, sa, aa), (kb, cb, sb, ab) = a, b
+    if not (ka.tolist() == kb.tolist() and ca.tolist() == cb.tolist() and sa.tolist() == sb.tolist()):
+        return False
+    return bool(np.all(np.abs(aa - ab) <= 1e-12 * np.abs(ab)))
+
+
 def bench_serving(args):
+    """Poisson arrivals of mixed requests at 0.5, 0.8, 1.0 and 1.2 times the FIFO service
+    rate (measured first), each served one at a time (FIFO) and by concurrent workers;
+    latency percentiles over the requests after a warm-up; every request's result alone
+    (FIFO) equal to its result in the mix, and a sample against the oracle."""
     pool = tq.PagePool(64 << 20, 160, pinned=True)
     nbase = args.serve_base_rows
     setup = pipeline.ServingSetup(n0=nbase, n_dim=nbase // 4, n1=nbase, n2=nbase, batch_rows=1 << 20, pool=pool)
     budget_bytes = int(64e9)
     arena = torch.empty(min(budget_bytes, 48 << 30), dtype=torch.uint8, device="cuda")
-    n = args.requests
-    # calibrate the FIFO service rate on the first requests
-    cal = wl.serving_requests(60, qps=1e9, seed=wl.SERVE_SEED + 7)
+    warm, n_meas = 100, args.requests
+    n = warm + n_meas
+    # the FIFO service rate, from calibration requests that all arrive at once
+    cal = wl.serving_requests(200, qps=1e9, seed=wl.SERVE_SEED + 7)
     Rc = setup.requests(cal)
-    b = tq.Budget(budget_bytes)
-    res, *_ = tq.serve_run(setup.T, Rc, 1, b, arena, 25)
+    res, *_ = tq.serve_run(setup.T, Rc, 1, tq.Budget(budget_bytes), arena, 25)
     mu = len(cal) / max(res[i].end_s for i in range(len(cal)))
-    lam = 0.8 * mu
-    reqs = wl.serving_requests(n, qps=lam)
-    R = setup.requests(reqs)
-    out = {}
-    # the third run reserves every join table for its whole window (no memory-use history)
-    for label, workers, est in (("fifo", 1, 1), ("continuous", args.workers, 1),
-                                ("continuous_whole_window_reservations", args.workers, 0)):
-        b = tq.Budget(budget_bytes)
-        setup.T.estimate = est
-        res, *_ = tq.serve_run(setup.T, R, workers, b, arena, 25)
-        lat = np.array([res[i].end_s - R[i].arrival_s for i in range(n)])
-        bad = sum(res[i].status != 0 for i in range(n))
-        span = max(res[i].end_s for i in range(n)) - R[0].arrival_s
-        out[label] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                      "mean_ms": round(float(lat.mean()) * 1e3, 3), "qps": round(n / span, 2), "failed": bad,
-                      "workers": workers,
-                      "mean_reserved_mib": round(float(np.mean([res[i].reserved_bytes for i in range(n)])) / 2**20, 2),
-                      "retries": int(sum(res[i].retries for i in range(n)))}
-        log(label, out[label])
+    log(f"serving: FIFO service rate {mu:.1f} requests/s")
+    base = wl.serving_requests(n, qps=1.0)  # arrival times at rate 1; scaled to each rate below
+    sweep, kept = [], {}
+    for f in (0.5, 0.8, 1.0, 1.2):
+        lam = f * mu
+        R = setup.requests(base, time_scale=1.0 / lam)
+        for label, workers in (("fifo", 1), ("continuous", args.workers)):
+            out = tq.serve_run(setup.T, R, workers, tq.Budget(budget_bytes), arena, 25)
+            res = out[0]
+            idx = range(warm, n)
+            lat = np.array([res[i].end_s - R[i].arrival_s for i in idx])
+            span = max(res[i].end_s for i in idx) - R[warm].arrival_s
+            row = {"rate_x_fifo": f, "arrivals_per_s": round(lam, 2), "mode": label, "workers": workers,
+                   "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                   "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                   "mean_ms": round(float(lat.mean()) * 1e3, 3), "qps": round(n_meas / span, 2),
+                   "failed": int(sum(res[i].status != 0 for i in range(n))),
+                   "retries": int(sum(res[i].retries for i in range(n))),
+                   "mean_reserved_mib": round(float(np.mean([res[i].reserved_bytes for i in idx])) / 2**20, 2)}
+            sweep.append(row)
+            log(row)
+            if f == 0.8:
+                kept[label] = (R, out)
+    # every request: alone (FIFO, one at a time) == in the mix (concurrent workers)
+    R, fifo = kept["fifo"]
+    _, mix = kept["continuous"]
+    unequal = [i for i in range(n) if not _same(_serve_result(R[i], fifo, i), _serve_result(R[i], mix, i))]
+    # a sample against the oracle: the smallest requests of each shape
+    sizes = sorted(range(n), key=lambda i: (R[i].shape, R[i].n_fact))
+    sample = []
+    for shape in (0, 1, 2):
+        sample += [i for i in sizes if R[i].shape == shape][:8]
+    oracle_bad = [i for i in sample if not _same(_serve_result(R[i], mix, i), _packed_want(_serve_expected(setup, R[i])))]
     setup.host.free()
     pool.close()
-    c = out["continuous"]
-    return _base("p50/p99 served query latency (ms) and queries/s, continuous batching vs FIFO", c["qps"], "queries/s",
-                 args, c["mean_ms"], n,
-                 f"serving: {n} requests, shapes 0/1/2 uniform, fact rows log-uniform 1e4..1e8 (windows of "
-                 f"{nbase}-row base tables), Poisson arrivals at 0.8 x the FIFO rate ({lam:.1f}/s), 64 GB budget",
-                 {"p50_ms": c["p50_ms"], "p99_ms": c["p99_ms"], "fifo": out["fifo"], "continuous": c,
-                  "continuous_whole_window_reservations": out["continuous_whole_window_reservations"],
-                  "calibrated_fifo_qps": round(mu, 2), "roofline": None, "cpu_baseline": None})
+    head = [r for r in sweep if r["rate_x_fifo"] == 0.8 and r["mode"] == "continuous"][0]
+    return _base("p50/p99 served query latency (ms) and queries/s, continuous batching vs FIFO", head["qps"],
+                 "queries/s", args, head["mean_ms"], n_meas,
+                 f"serving: {n_meas} requests after {warm} warm-up, shapes 0/1/2 uniform, fact rows log-uniform "
+                 f"1e4..1e8 (windows of {nbase}-row base tables), Poisson arrivals at 0.5/0.8/1.0/1.2 x the FIFO "
+                 f"rate ({mu:.1f}/s), 64 GB budget, {args.workers} workers",
+                 {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "calibrated_fifo_qps": round(mu, 2),
+                  "sweep": sweep,
+                  "alone_equals_mix": {"requests": n, "unequal": unequal[:20], "equal": not unequal},
+                  "oracle_sample": {"requests": sample, "unequal": oracle_bad, "equal": not oracle_bad},
+                  "roofline": None, "cpu_baseline": None})
+
+
+def _packed_want(w):
+    return w["keys"], w["count"], w["sums"], w["avg"]
 
 
 # ------------------------------------------------------------------ steady state at growing row counts

@@ -159,6 +159,16 @@ size_t tq_join_table_bytes(int64_t n_build_max, double load_factor);
 tq_status tq_join_table_init(void* d_table, size_t bytes, hipStream_t stream);
 
 #define TQ_UNIQUE_KEYS 1u /* build keys are unique: a probe stops at its first match */
+/* One hash partition of a join (the split of a task that does not fit its
+ * memory, Section 3.3.2): with TQ_SELECT_PARTITION | TQ_PARTITION(id) in the
+ * build's flags and 1 <= skip <= 16, the build keeps only the rows whose key
+ * hash (key * 0x9E3779B97F4A7C15 mod 2^64) has `id` in its top `skip` bits,
+ * and every probe of the table then takes only the probe rows of that
+ * partition (the others match nothing). Running the 2^skip partitions one after
+ * another into one group-by state gives the whole join's result, each with a
+ * table sized for its share of the rows. */
+#define TQ_SELECT_PARTITION 2u
+#define TQ_PARTITION(id) ((uint32_t)(id) << 16)
 
 /* Build: insert (keys[r], payload[r]) for every row r < n that satisfies the
  * optional predicates over `filt` (the dimension filter fused into the build).
@@ -232,6 +242,14 @@ tq_status tq_groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_
  * even). Outputs must hold `domain` groups; *d_ngroups gets the count. */
 tq_status tq_groupby_finalize(const void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums,
                               double* d_avg, int64_t* d_ngroups, hipStream_t stream);
+
+/* tq_groupby_finalize that also leaves the state empty, as tq_groupby_init
+ * does (every partial it read is zeroed in the same pass), so that a caller
+ * running one query after another on a state skips the separate set-up: the
+ * next aggregation starts from zero. A latched error stays latched (it is
+ * reported by tq_check and cleared by tq_groupby_init). */
+tq_status tq_groupby_finalize_reset(void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums, double* d_avg,
+                                    int64_t* d_ngroups, hipStream_t stream);
 
 /* Synchronise `stream`, then return the error latched in a join table or a
  * group-by state (TQ_OK if none). */
@@ -529,7 +547,7 @@ typedef struct {
   int64_t ngroups;
   int64_t reserved_bytes; /* the device memory of the run that completed it */
   int32_t retries;        /* runs that ended with a table too small for the kept rows */
-  int32_t pad;
+  int32_t splits;         /* hash partitions its join ran as, one after another (1: whole) */
 } tq_request_result;
 
 /* Runs all requests and blocks until they are done. d_arena / arena_bytes is
@@ -545,8 +563,15 @@ typedef struct {
  * (tq_join_table_bytes(rows, load_factor), shapes 1 and 2; 0 for shape 0),
  * keys and COUNT (8 * domain each), SUMs and AVGs (8 * domain * nsum each),
  * the group count (8), the staging slots of shape 2 (nslots times the largest
- * batch of its window in whole pages; 0 otherwise) and 64 bytes of scratch. A
- * request whose reservation exceeds the budget's capacity can never run and
+ * batch of its window in whole pages; 0 otherwise) and 64 bytes of scratch.
+ * A join request whose reservation exceeds the budget's capacity is split
+ * (the third remedy of Section 3.3.2): it runs as 2^b hash partitions one
+ * after another (TQ_SELECT_PARTITION builds over its whole windows, each
+ * followed by the probe of the whole fact window, all into one group-by
+ * state), with the smallest b <= 8 whose table, sized for a 2^-b share of the
+ * rows plus a quarter and 1024 rows, fits; a partition that proves larger than
+ * its table runs the request again with one more split bit. A request that
+ * cannot fit even so (or a filter + group-by request over the capacity)
  * completes at once with status TQ_ENOMEM; the others wait for room.
  * Every window is checked against the base tables' row counts before any
  * request runs (TQ_EINVAL). */

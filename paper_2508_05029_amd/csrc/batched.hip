@@ -365,6 +365,7 @@ tq_status make_query(const tq_batch_query* q, BQuery* Q) {
       Q->sums[j].f[f] = make_factor(F.col, F.sign, F.add);
     }
   }
+  if (q->join_flags & ~TQ_UNIQUE_KEYS) return fail(TQ_EINVAL, "join_flags: only TQ_UNIQUE_KEYS applies to batched instances");
   Q->flags = q->join_flags;
   return TQ_OK;
 }

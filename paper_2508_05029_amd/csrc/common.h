@@ -231,6 +231,12 @@ __device__ __forceinline__ uint64_t bucket_of(uint64_t h, int skip, int log2buck
   return (h << skip) >> (64 - log2buckets);
 }
 
+// Whether hash h belongs to the partition a table was built for
+// (TQ_SELECT_PARTITION: partition id = flags >> 16 in the top `skip` bits).
+__device__ __forceinline__ bool in_partition(uint64_t h, int skip, uint32_t flags) {
+  return !(flags & TQ_SELECT_PARTITION) || (uint32_t)(h >> (64 - skip)) == (flags >> 16);
+}
+
 // Bloom filter of a region-built table, from the key's multiplicative hash h:
 // the key's region (as for its bucket) selects a block of 2^(log2w -
 // kLog2Bins) 32-bit words, bits 19.. of h the word in the block and three bit

@@ -112,8 +112,9 @@ __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
 // table's partial area), and the whole tag array cleared (the capacity the
 // rows need is only known once every block has counted).
 template <int NC>
-__global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, int64_t per, TableHeader* h,
-                                                        int64_t cap_max, int count) {
+__global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, const int64_t* keys, int64_t n, int64_t per,
+                                                        TableHeader* h, int64_t cap_max, int count, int skip,
+                                                        uint32_t flags) {
   __shared__ int64_t ws[kBlock / kWave];
   if (h->magic != kTableMagic) return;  // never initialised: the insert kernel does nothing either
   // a new build: an error latched by an earlier build into this buffer no longer applies
@@ -126,11 +127,15 @@ __global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, int64_t n, in
   if (!count) return;
   const int64_t lo = (int64_t)blockIdx.x * per, hi = min(n, lo + per);
   int64_t c = 0;
+  const DCol kc = {keys, 8};
+  const bool sel = (flags & TQ_SELECT_PARTITION) != 0;
   for (int64_t r0 = lo + threadIdx.x * kRows; r0 < hi; r0 += kChunk) {
-    int64_t v[NC][kRows];
+    int64_t v[NC][kRows], k[kRows];
     load_rows<NC>(P, r0, r0 + kRows <= hi, hi, v);
+    if (sel) load4(kc, r0, r0 + kRows <= hi, hi, k);
 #pragma unroll
-    for (int i = 0; i < kRows; i++) c += (r0 + i < hi) && eval_preds<NC>(P, v, i);
+    for (int i = 0; i < kRows; i++)
+      c += (r0 + i < hi) && eval_preds<NC>(P, v, i) && (!sel || in_partition(mulhash(k[i]), skip, flags));
   }
   int64_t t = block_sum(c, ws);
   if (threadIdx.x == 0) table_partials(h)[blockIdx.x] = t;
@@ -183,7 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_
     load4(kc, r0, fullrow, n, k);
     load4(payload, r0, fullrow, n, pay);
 #pragma unroll
-    for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
+    for (int i = 0; i < kRows; i++)
+      pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i) && in_partition(mulhash(k[i]), skip, flags);
     table_insert<kRows>(words, slots, l, skip, pend, k, pay);
   }
 }
@@ -220,7 +226,7 @@ constexpr int kMaxBloomLog2Cap = kMaxRegionLog2Cap + 1;       // the largest fil
 
 template <int NC>
 __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
-                                                          TableHeader* h, int64_t cap_max, int skip) {
+                                                          TableHeader* h, int64_t cap_max, int skip, uint32_t flags) {
   __shared__ uint32_t hist[kRegionBins];
   __shared__ uint32_t loc[kRegionBins];
   __shared__ int64_t ws[kPartBlock / kWave];
@@ -243,8 +249,9 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   uint32_t bin[kRows], rank[kRows];
 #pragma unroll
   for (int i = 0; i < kRows; i++) {
-    ok[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
-    bin[i] = (uint32_t)((mulhash(k[i]) << skip) >> (64 - kLog2Bins));
+    const uint64_t hh = mulhash(k[i]);
+    ok[i] = (r0 + i < n) && eval_preds<NC>(P, v, i) && in_partition(hh, skip, flags);
+    bin[i] = (uint32_t)((hh << skip) >> (64 - kLog2Bins));
     rank[i] = ok[i] ? atomicAdd(&hist[bin[i]], 1u) : 0u;
   }
   __syncthreads();
@@ -469,11 +476,14 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   if (tid < nbw) scratch_bloom(h, cap_max)[(size_t)j * nbw + tid] = lbloom[tid];
 }
 
+constexpr int kFallbackBlocks = 16;  // two per XCD; the global-CAS insert, when needed, strides over every row
+
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_build_fallback(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
                                                           TableHeader* h, int64_t cap_max) {
   if (h->magic != kTableMagic || !h->ovf) return;
   const int l = h->log2cap, skip = h->skip;
+  const uint32_t flags = h->flags;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     h->regions = 0;
     h->alt = 1;
@@ -492,7 +502,8 @@ __global__ __launch_bounds__(kBlock) void k_build_fallback(RowPlan P, const int6
     load4(kc, r0, fullrow, n, k);
     load4(payload, r0, fullrow, n, pay);
 #pragma unroll
-    for (int i = 0; i < kRows; i++) pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i);
+    for (int i = 0; i < kRows; i++)
+      pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i) && in_partition(mulhash(k[i]), skip, flags);
     table_insert<kRows>(words, slots, l, skip, pend, k, pay);
   }
 }
@@ -607,11 +618,66 @@ struct PipeRows {
   bool live[R];
 };
 
-template <int MODE, int NC, int NE, bool BLOOM>
+// A sum as a product of up to three (column + constant) factors, negated when
+// `neg` is set: the form of every expression whose coefficients are 1, -1 or 0
+// (add - x = -(x + (-add)) mod 2^64; a constant factor has a zero column mask,
+// which picks 0 from at most two columns). It needs no 64-bit multiply by a
+// coefficient (three quarter-rate instructions each on this GPU).
+struct UnitSum {
+  int32_t nf;
+  int32_t neg;
+  uint32_t mask[3];
+  int64_t add[3];
+};
+struct UnitPlan {
+  UnitSum s[2];
+};
+
+// The unit form of the plan's sums; false if some coefficient is not 1, -1 or 0.
+static bool unit_plan(const RowPlan& P, UnitPlan* U) {
+  *U = UnitPlan{};
+  for (int j = 0; j < P.ne; j++) {
+    if (j >= 2) return false;
+    UnitSum& S = U->s[j];
+    S.nf = P.expr[j].nf;
+    for (int f = 0; f < S.nf; f++) {
+      const DFactor& F = P.expr[j].f[f];
+      if (F.sign == 0) {
+        S.mask[f] = 0u;
+        S.add[f] = F.add;
+      } else if (F.sign == 1 || F.sign == -1) {
+        S.mask[f] = F.mask;
+        S.add[f] = F.sign == 1 ? F.add : (int64_t)(0ull - (uint64_t)F.add);
+        S.neg ^= F.sign == -1;
+      } else {
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+template <int NC, int R>
+__device__ __forceinline__ int64_t eval_unit(const UnitSum& S, const int64_t (&v)[NC][R], int i) {
+  static_assert(NC <= 2, "a zero mask must pick 0");
+  uint64_t acc = (uint64_t)pick<NC, R>(v, i, S.mask[0]) + (uint64_t)S.add[0];
+#pragma unroll
+  for (int f = 1; f < 3; f++)
+    if (f < S.nf) acc *= (uint64_t)pick<NC, R>(v, i, S.mask[f]) + (uint64_t)S.add[f];
+  return (int64_t)(S.neg ? 0ull - acc : acc);
+}
+
+// FAST: the common plan (group-by partials dense in LDS, at most two columns,
+// no probe-side predicate, sums of unit coefficients; U holds them): no
+// predicate loop, sums without multiplies by a coefficient, and the LDS adds
+// of a match in one branch with no call into the generic group-by code, so
+// that the few values they need stay in scalar registers.
+template <int MODE, int NC, int NE, bool BLOOM, bool FAST>
 __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kPipeBlocksPerCU) void k_probe_pipe(const TableHeader* h,
                                                                                         const int64_t* pkeys, int64_t n,
                                                                                         RowPlan P, AggTarget T,
-                                                                                        int agg_lds) {
+                                                                                        UnitPlan U, int agg_lds) {
+  static_assert(!FAST || (MODE == kDense && NC <= 2), "fast plan");
   constexpr int R = kPipeRows;
   __shared__ uint32_t bloom[BLOOM ? kBloomWordsMax : 1];
   extern __shared__ __align__(16) char smem[];
@@ -654,6 +720,10 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * R;
   const int64_t wbase = ((int64_t)blockIdx.x * blockDim.x + wave * kWave) * R;  // the wave's first row
   int qn = 0;  // queued rows (the same in every lane); the queue is only appended to inside the loop
+  const int ne = P.ne;
+  const uint64_t udomain = (uint64_t)T.domain;
+  const uint32_t gstride = (uint32_t)T.stride;  // entries per group: COUNT and the sums
+  bool bad = false;  // FAST: a group key outside the domain was met
 
   // Walks every queued row to the end of its chain, 64 at a time, one per lane
   // (their key and columns are read again: queued rows are rare), and empties
@@ -710,11 +780,18 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
       t.row = rt;
 #pragma unroll
       for (int i = 0; i < R; i++) {
-        t.live[i] = (rt < n_main) && eval_preds<NC>(P, v, i);
+        if constexpr (FAST) {
+          t.live[i] = rt < n_main;
 #pragma unroll
-        for (int j = 0; j < NE; j++) t.e[i][j] = j < P.ne ? eval_expr<NC>(P.expr[j], v, i) : 0;
+          for (int j = 0; j < NE; j++) t.e[i][j] = j < ne ? eval_unit<NC>(U.s[j], v, i) : 0;
+        } else {
+          t.live[i] = (rt < n_main) && eval_preds<NC>(P, v, i);
+#pragma unroll
+          for (int j = 0; j < NE; j++) t.e[i][j] = j < ne ? eval_expr<NC>(P.expr[j], v, i) : 0;
+        }
         t.k[i] = kk[i];
         const uint64_t hh = mulhash(kk[i]);
+        t.live[i] = t.live[i] && pr.selected(hh);
         t.b[i] = (int64_t)bucket_of(hh, pr.skip, pr.log2b);
         t.tg[i] = hash_tag(hh);
         if (BLOOM && nbw) {  // a key the filter rejects is not in the build
@@ -744,7 +821,21 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
         const uint32_t rest = sm[i] & (sm[i] - 1u);
         const bool done =
             !t.live[i] || (sm[i] == 0u && sempty[i]) || (hit && pr.unique) || (rest == 0u && sempty[i]);
-        if (done && hit) agg.add(T, kv[i].y, t.e[i], P.ne);
+        if constexpr (FAST) {
+          const bool addit = done && hit;
+          const uint64_t key = (uint64_t)kv[i].y;
+          const bool in = key < udomain;
+          bad = bad || (addit && !in);  // latched after the loop
+          if (addit && in) {  // key < domain <= 4096 (dense partials): a 24-bit multiply
+            unsigned long long* d = reinterpret_cast<unsigned long long*>(agg.vals) + __umul24((uint32_t)key, gstride);
+            atomicAdd(d, 1ull);
+#pragma unroll
+            for (int j = 0; j < NE; j++)
+              if (j < ne) atomicAdd(d + 1 + j, (unsigned long long)t.e[i][j]);
+          }
+        } else {
+          if (done && hit) agg.add(T, kv[i].y, t.e[i], ne);
+        }
         const bool slow = !done;
         const uint64_t bal = __ballot(slow);
         if (bal) {
@@ -821,6 +912,7 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
       if (hit[0]) agg.add(T, pay[0], e1, P.ne);
     });
   }
+  agg.bad = agg.bad || bad;
   agg.flush(T);
 }
 
@@ -967,6 +1059,14 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   if (!d_table) return fail(TQ_EINVAL, "table is NULL");
   if (!(load_factor > 0.0 && load_factor <= 0.9)) return fail(TQ_EINVAL, "load factor %g outside (0, 0.9]", load_factor);
   if (skip < 0 || skip > 32) return fail(TQ_EINVAL, "skip %d outside [0, 32]", skip);
+  if (flags & ~(TQ_UNIQUE_KEYS | TQ_SELECT_PARTITION | TQ_PARTITION(0xffffu)))
+    return fail(TQ_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & TQ_SELECT_PARTITION) {
+    if (skip < 1 || skip > 16) return fail(TQ_EINVAL, "a partition build needs 1 <= skip <= 16 (got %d)", skip);
+    if ((flags >> 16) >= (1u << skip)) return fail(TQ_EINVAL, "partition %u outside [0, 2^%d)", flags >> 16, skip);
+  } else if (flags >> 16) {
+    return fail(TQ_EINVAL, "a partition id without TQ_SELECT_PARTITION");
+  }
   if (n < 0) return fail(TQ_EINVAL, "n < 0");
   if (n > 0 && (!d_keys || !payload.data)) return fail(TQ_EINVAL, "NULL keys or payload");
   if (((uintptr_t)d_keys & 15) || ((uintptr_t)payload.data & 15)) return fail(TQ_EINVAL, "keys/payload not 16-byte aligned");
@@ -982,21 +1082,24 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   if (part_grid <= part_grid_max(cap_max)) {
     // the rows' segments fit the scratch area: partition, count, then fill regions (or CAS)
     TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_part<NC>, dim3((int)part_grid), dim3(kPartBlock), 0, stream,
-                                                  P, d_keys, pc, n, h, cap_max, skip));
+                                                  P, d_keys, pc, n, h, cap_max, skip, flags));
     hipLaunchKernelGGL(k_build_regions, dim3(kRegionBins), dim3(kFinBlock), 0, stream, h, cap_max, (int)part_grid,
                        load_factor, skip, flags, cap_rule(load_factor));
-    TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_fallback<NC>, dim3(stream_grid(n, 2)), dim3(kBlock), 0,
+    // the fallback does nothing unless a region overflowed (rare: keys whose hashes
+    // crowd one region); a small grid keeps the launch that finds nothing to do cheap
+    // (dispatching hundreds of workgroups that return at once took about 4 us)
+    TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_fallback<NC>, dim3(kFallbackBlocks), dim3(kBlock), 0,
                                                   stream, P, d_keys, pc, n, h, cap_max));
     TQ_HIP(hipGetLastError());
     return TQ_OK;
   }
-  const bool count = np > 0 && n > 0;
+  const bool count = (np > 0 || (flags & TQ_SELECT_PARTITION)) && n > 0;
   Range R = split_rows(std::max<int64_t>(n, 1), kMaxCountBlocks);
   // enough blocks to clear the tags quickly; blocks past the rows count zero
   const int64_t clear_blocks = std::min<int64_t>((cap_max >> kLog2Bucket) / kBlock, kMaxCountBlocks);
   const int count_grid = (int)std::max<int64_t>(R.nblk, clear_blocks);
-  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_count<NC>, dim3(count_grid), dim3(kBlock), 0, stream, P, n, R.per,
-                                                h, cap_max, (int)count));
+  TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_count<NC>, dim3(count_grid), dim3(kBlock), 0, stream, P, d_keys, n,
+                                                R.per, h, cap_max, (int)count, skip, flags));
   TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_insert<NC>, dim3(stream_grid(n, 8)), dim3(kBlock), 0, stream, P,
                                                 d_keys, pc, n, h, cap_max, count ? (int64_t)-1 : n, R.nblk, load_factor,
                                                 skip, flags));
@@ -1034,6 +1137,8 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
       const bool bloom = bloom_lds <= kMaxBloomPipeLds;
       const int threads = bloom ? kBloomPipeBlock : kAggBlock;
       const int agg_lds = (int)agg_lds16;
+      UnitPlan U;
+      const bool fast = mode == kDense && P.np == 0 && P.ncol <= 2 && unit_plan(P, &U);
       // one launch per kPipeMaxRows rows (an even count: the 16-byte column loads stay aligned)
       for (int64_t c0 = 0; c0 < n; c0 += kPipeMaxRows) {
         const int64_t nc = std::min<int64_t>(kPipeMaxRows, n - c0);
@@ -1044,12 +1149,26 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
         dim3 grid((int)std::max<int64_t>(1, std::min(want, cap))), block(threads);
         TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE, if constexpr (NE <= 2) {
           const size_t q = (size_t)(threads / kWave) * kPipeQ * 4;
-          if (bloom)
-            hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, true>), grid, block, agg_lds + q, stream, h, d_probe_keys + c0,
-                               nc, Pc, T, agg_lds);
-          else
-            hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, false>), grid, block, agg_lds + q, stream, h, d_probe_keys + c0,
-                               nc, Pc, T, agg_lds);
+          bool launched = false;
+          if constexpr (M == kDense && NC <= 2 && NE == 1) {  // (two sums would spill registers to memory)
+            if (fast) {
+              if (bloom)
+                hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, true, true>), grid, block, agg_lds + q, stream, h,
+                                   d_probe_keys + c0, nc, Pc, T, U, agg_lds);
+              else
+                hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, false, true>), grid, block, agg_lds + q, stream, h,
+                                   d_probe_keys + c0, nc, Pc, T, U, agg_lds);
+              launched = true;
+            }
+          }
+          if (!launched) {
+            if (bloom)
+              hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, true, false>), grid, block, agg_lds + q, stream, h,
+                                 d_probe_keys + c0, nc, Pc, T, U, agg_lds);
+            else
+              hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, false, false>), grid, block, agg_lds + q, stream, h,
+                                 d_probe_keys + c0, nc, Pc, T, U, agg_lds);
+          }
         });
       }
     } else {

@@ -977,6 +977,7 @@ extern "C" tq_status tq_ooc_join_agg(tq_pagepool* pool, const tq_batch* dim, int
   if (!pool || !plan || !budget || !d_work || !d_state) return fail(TQ_EINVAL, "NULL argument");
   if (nd < 0 || nf < 1 || (nd > 0 && !dim) || !fact) return fail(TQ_EINVAL, "batch lists");
   if (plan->log2_fanout < 0 || plan->log2_fanout > 10) return fail(TQ_EINVAL, "log2_fanout outside [0, 10]");
+  if (plan->join_flags & ~TQ_UNIQUE_KEYS) return fail(TQ_EINVAL, "join_flags: only TQ_UNIQUE_KEYS applies here");
   if (plan->nslots < 2 || plan->nslots > 8) return fail(TQ_EINVAL, "nslots outside [2, 8]");
   if (plan->exchange < TQ_EXCHANGE_AUTO || plan->exchange > TQ_EXCHANGE_SINGLE) return fail(TQ_EINVAL, "exchange mode");
   size_t pb = tq_pagepool_page_bytes(pool);

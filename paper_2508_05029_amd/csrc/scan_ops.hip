@@ -163,15 +163,18 @@ __global__ void k_state_init(StateHeader* h, int64_t domain, int32_t nsum, int32
 // One workgroup: fold the private rows (if any), keep COUNT > 0, emit in key order.
 constexpr int kFinBlock = 1024;
 
-__global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, int64_t* keys, int64_t* count,
-                                                        int64_t* sums, double* avg, int64_t* ngroups) {
+// With `reset`, every partial read is zeroed right after (the same thread, so
+// the store follows its load) and the count of used private rows goes to 0:
+// the state is then as tq_groupby_init leaves it, its error word aside.
+__global__ __launch_bounds__(kFinBlock) void k_finalize(StateHeader* h, int64_t* keys, int64_t* count,
+                                                        int64_t* sums, double* avg, int64_t* ngroups, int reset) {
   __shared__ uint32_t wave_tot[kFinBlock / kWave];
   __shared__ int64_t fold[kPrivateRowsMaxEntries];
   __shared__ int64_t base_s;
   if (h->magic != kStateMagic) return;
   const int64_t domain = h->domain;
   const int nsum = h->nsum, stride = 1 + nsum, rows = h->rows;
-  const int64_t* d = state_data(const_cast<StateHeader*>(h));
+  int64_t* d = state_data(h);
   const int entries = (int)(domain * stride);
   if (rows > 1) {
     for (int e = threadIdx.x; e < entries; e += kFinBlock) fold[e] = 0;
@@ -193,6 +196,13 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, in
         }
 #pragma unroll
         for (int u = 0; u < 8; u++) acc += x[u];
+        if (reset) {
+#pragma unroll
+          for (int u = 0; u < 8; u++) {
+            const int rr = r + u * per;
+            if (rr < nrow) d[(int64_t)rr * entries + e] = 0;
+          }
+        }
       }
       if (acc) atomicAdd(reinterpret_cast<unsigned long long*>(&fold[e]), (unsigned long long)acc);
     }
@@ -208,6 +218,11 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, in
 #pragma unroll
       for (int j = 0; j < 1 + TQ_MAX_SUMS; j++)
         if (j < stride) e[j] = rows > 1 ? fold[k * stride + j] : d[k * stride + j];
+      if (reset && rows == 1) {
+#pragma unroll
+        for (int j = 0; j < 1 + TQ_MAX_SUMS; j++)
+          if (j < stride) d[k * stride + j] = 0;
+      }
       live = e[0] != 0;
     }
     uint64_t m = __ballot(live);
@@ -236,7 +251,10 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const StateHeader* h, in
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *ngroups = base_s;
+  if (threadIdx.x == 0) {
+    *ngroups = base_s;
+    if (reset) h->used = 0;  // (read above by every thread, before the loop's barriers)
+  }
 }
 
 // ------------------------------------------------------------ measurement
@@ -363,8 +381,19 @@ tq_status tq_groupby_finalize(const void* d_state, int64_t* d_keys, int64_t* d_c
                               int64_t* d_ngroups, hipStream_t stream) {
   if (!d_state) return fail(TQ_EINVAL, "group-by state is NULL");
   if (!d_keys || !d_count || !d_ngroups || !d_sums) return fail(TQ_EINVAL, "NULL output");
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, stream, static_cast<const StateHeader*>(d_state),
-                     d_keys, d_count, d_sums, d_avg, d_ngroups);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, stream,
+                     static_cast<StateHeader*>(const_cast<void*>(d_state)), d_keys, d_count, d_sums, d_avg, d_ngroups,
+                     0);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+tq_status tq_groupby_finalize_reset(void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums, double* d_avg,
+                                    int64_t* d_ngroups, hipStream_t stream) {
+  if (!d_state) return fail(TQ_EINVAL, "group-by state is NULL");
+  if (!d_keys || !d_count || !d_ngroups || !d_sums) return fail(TQ_EINVAL, "NULL output");
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, stream, static_cast<StateHeader*>(d_state), d_keys,
+                     d_count, d_sums, d_avg, d_ngroups, 1);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }

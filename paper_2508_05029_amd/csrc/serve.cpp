@@ -91,8 +91,10 @@ struct Server {
   struct Slot {
     int64_t job = -1, rows = 0;
     size_t off = 0, bytes = 0;
+    int split = 0;  // the join runs as 2^split hash partitions (0: whole)
     bool busy = false;
   };
+  static constexpr int kMaxSplitBits = 8;
   std::vector<Slot> slots;
   bool shutdown = false;
   int64_t completed = 0;
@@ -117,6 +119,7 @@ struct Server {
     }
   } hist[3];
   std::vector<int64_t> exact;  // per request: kept rows recorded by a build that did not fit, else -1
+  std::vector<int32_t> split_min;  // per request: split bits at least (raised when a partition did not fit)
   std::vector<int32_t> retries;
   std::vector<double> first_start;  // per request: when its first run started (-1 before)
   std::deque<int64_t> again;   // requests to run again, ahead of new arrivals
@@ -132,6 +135,14 @@ struct Server {
     for (int j = 0; j < h.n; j++) fmax = std::max(fmax, h.f[j]);
     const double est = (double)q.n_dim * fmax * 1.25 + 1024.0;
     return est >= (double)q.n_dim ? q.n_dim : (int64_t)est;
+  }
+
+  // Table rows of one of 2^b partitions of `rows` kept rows: its share, plus a
+  // quarter and 1024 rows for the spread of the hash.
+  static int64_t part_rows(int64_t rows, int b) {
+    if (b == 0) return rows;
+    const double share = (double)rows / (double)(1 << b);
+    return std::min<int64_t>(rows, (int64_t)(share * 1.25) + 1024);
   }
 
   Plan plan_of(const tq_request& q, int64_t table_rows) const {
@@ -185,8 +196,8 @@ struct Server {
   // Runs request idx in the region at `base` (planned for `rows` table rows).
   // *kept gets the rows its dimension window kept (-1 for shape 0). Returns
   // TQ_EFULL, with no result written, when the table was too small for them.
-  tq_status execute(const tq_request& q, char* base, int64_t rows, hipStream_t compute, hipStream_t copy, int64_t idx,
-                    int64_t* kept) {
+  tq_status execute(const tq_request& q, char* base, int64_t rows, int split, hipStream_t compute, hipStream_t copy,
+                    int64_t idx, int64_t* kept) {
     *kept = -1;
     Plan p = plan_of(q, rows);
     void* state = base + p.state;
@@ -208,25 +219,42 @@ struct Server {
       tq_col dw[4];
       for (int c = 0; c < T.dim_ncol; c++) dw[c] = window(T.dim_cols[c], q.dim_first);
       if ((s = tq_join_table_init(table, p.table_bytes, compute))) return s;
-      if ((s = tq_join_build(table, p.table_bytes, static_cast<const int64_t*>(dw[0].data), dw[1], q.n_dim, dw,
-                             T.dim_ncol, T.dim_preds, T.dim_np, T.load_factor, 0, TQ_UNIQUE_KEYS, compute)))
-        return s;
       tq_agg agg{state, p.domain, T.join_sums, T.join_nsum};
-      if (q.shape == 1) {
-        tq_col fw[4];
-        for (int c = 0; c < T.fact_ncol; c++) fw[c] = window(T.fact_cols[c], q.fact_first);
-        if ((s = tq_join_probe(table, static_cast<const int64_t*>(fw[0].data), q.n_fact, fw, T.fact_ncol, nullptr, 0,
-                               nullptr, nullptr, 0, nullptr, &agg, compute)))
+      int64_t kept_all = 0;
+      // whole, or one hash partition after another into the one state (a split)
+      for (int part = 0; part < (1 << split); part++) {
+        const uint32_t flags = TQ_UNIQUE_KEYS | (split ? TQ_SELECT_PARTITION | TQ_PARTITION(part) : 0u);
+        if ((s = tq_join_build(table, p.table_bytes, static_cast<const int64_t*>(dw[0].data), dw[1], q.n_dim, dw,
+                               T.dim_ncol, T.dim_preds, T.dim_np, T.load_factor, split, flags, compute)))
           return s;
-      } else {
-        ProbeCtx ctx{this, table, agg};
-        if ((s = tq_pagepool_stream(T.pool, T.fact_batches + q.fact_first, q.n_fact, base + p.staging, p.staging_bytes,
-                                    T.nslots, on_batch, &ctx, copy, compute)))
-          return s;
+        if (split) {  // each partition's build is checked before its probe
+          int64_t k = 0;
+          if ((s = tq_join_table_rows(table, &k, compute))) return s;
+          kept_all += k;
+          const tq_status t = tq_check(table, compute);
+          if (t == TQ_EFULL) {
+            *kept = k;
+            return t;  // this partition's rows do not fit its table: run again with more partitions
+          }
+          if (t) return t;
+        }
+        if (q.shape == 1) {
+          tq_col fw[4];
+          for (int c = 0; c < T.fact_ncol; c++) fw[c] = window(T.fact_cols[c], q.fact_first);
+          if ((s = tq_join_probe(table, static_cast<const int64_t*>(fw[0].data), q.n_fact, fw, T.fact_ncol, nullptr, 0,
+                                 nullptr, nullptr, 0, nullptr, &agg, compute)))
+            return s;
+        } else {
+          ProbeCtx ctx{this, table, agg};
+          if ((s = tq_pagepool_stream(T.pool, T.fact_batches + q.fact_first, q.n_fact, base + p.staging,
+                                      p.staging_bytes, T.nslots, on_batch, &ctx, copy, compute)))
+            return s;
+        }
       }
+      if (split) *kept = kept_all;
     }
     if ((s = tq_groupby_finalize(state, keys, count, sums, avg, ng, compute))) return s;
-    if (q.shape != 0) {
+    if (q.shape != 0 && !split) {
       if ((s = tq_join_table_rows(base + p.table, kept, compute))) return s;
       const tq_status t = tq_check(base + p.table, compute);
       if (t == TQ_EFULL) return t;  // nothing was inserted; the probe matched nothing
@@ -267,6 +295,7 @@ struct Server {
     for (;;) {
       int64_t job, rows;
       size_t off, bytes;
+      int split;
       {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait(lk, [&] { return shutdown || slots[w].job >= 0; });
@@ -275,16 +304,19 @@ struct Server {
         off = slots[w].off;
         bytes = slots[w].bytes;
         rows = slots[w].rows;
+        split = slots[w].split;
       }
       const double start = now_s();
       int64_t kept = -1;
-      tq_status s = ok ? execute(reqs[job], arena_base + off, rows, compute, copy, job, &kept) : TQ_EHIP;
+      tq_status s = ok ? execute(reqs[job], arena_base + off, rows, split, compute, copy, job, &kept) : TQ_EHIP;
       if (s) {
         (void)hipStreamSynchronize(compute);
         (void)hipStreamSynchronize(copy);
       }
-      // a table too small for the kept rows, sized from the history: run again for the exact count
-      const bool retry = s == TQ_EFULL && kept > rows && exact[(size_t)job] < 0;
+      // a table too small for the kept rows, sized from the history: run again for the exact
+      // count; a partition of a split too large for its table: again with one more split bit
+      const bool refit = s == TQ_EFULL && !split && kept > rows && exact[(size_t)job] < 0;
+      const bool resplit = s == TQ_EFULL && split && split < kMaxSplitBits;
       {
         std::lock_guard<std::mutex> lk(mu);
         arena.release(off, bytes);
@@ -292,8 +324,9 @@ struct Server {
         slots[w].job = -1;
         slots[w].busy = false;
         if (first_start[(size_t)job] < 0) first_start[(size_t)job] = start;
-        if (retry) {
-          exact[(size_t)job] = kept;
+        if (refit || resplit) {
+          if (refit) exact[(size_t)job] = kept;
+          else split_min[(size_t)job] = split + 1;
           retries[(size_t)job]++;
           again.push_back(job);
         } else {
@@ -304,6 +337,7 @@ struct Server {
           res[job].status = s;
           res[job].reserved_bytes = (int64_t)bytes;
           res[job].retries = retries[(size_t)job];
+          res[job].splits = 1 << split;
           res[job].end_s = now_s();
           completed++;
         }
@@ -317,6 +351,7 @@ struct Server {
   tq_status run(int workers) {
     slots.assign(workers, Slot());
     exact.assign((size_t)n, -1);
+    split_min.assign((size_t)n, 0);
     retries.assign((size_t)n, 0);
     first_start.assign((size_t)n, -1.0);
     for (int64_t i = 0; i < n; i++) {
@@ -342,8 +377,22 @@ struct Server {
         for (int w = 0; w < workers && idle < 0; w++)
           if (!slots[w].busy) idle = w;
         if (idle >= 0) {
-          const int64_t rows = table_rows(job);
+          int64_t rows = table_rows(job);
           Plan p = plan_of(reqs[job], rows);
+          // a join over the capacity (or one whose partition proved too large) runs split:
+          // the fewest hash partitions whose table fits
+          int split = 0;
+          if (reqs[job].shape != 0 && (p.total > tq_budget_cap(budget) || split_min[(size_t)job] > 0)) {
+            for (int b = std::max(1, (int)split_min[(size_t)job]); b <= kMaxSplitBits; b++) {
+              const Plan pb = plan_of(reqs[job], part_rows(rows, b));
+              if (pb.total <= tq_budget_cap(budget)) {
+                split = b;
+                rows = part_rows(rows, b);
+                p = pb;
+                break;
+              }
+            }
+          }
           size_t off;
           auto taken = [&] {
             if (rerun) again.pop_front();
@@ -352,6 +401,7 @@ struct Server {
           if (p.total > tq_budget_cap(budget)) {  // can never fit: fail it rather than block the queue
             res[job].status = TQ_ENOMEM;
             res[job].retries = retries[(size_t)job];
+            res[job].splits = 0;
             res[job].start_s = first_start[(size_t)job] >= 0 ? first_start[(size_t)job] : now_s();
             res[job].end_s = now_s();
             taken();
@@ -360,7 +410,7 @@ struct Server {
           }
           if (tq_budget_reserve(budget, p.total) == TQ_OK) {
             if (arena.alloc(p.total, &off)) {
-              slots[idle] = Slot{job, rows, off, p.total, true};
+              slots[idle] = Slot{job, rows, off, p.total, split, true};
               taken();
               cv.notify_all();
               continue;

@@ -128,6 +128,7 @@ struct Probe {
   int64_t bmask, gmask, cap;
   int log2b, skip;
   bool unique;
+  uint32_t sel = 0;  // the build's flags when it kept one hash partition (a probe row of another matches nothing)
 
   __device__ __forceinline__ void setup(const TableHeader* h) {
     TableHeader* t = const_cast<TableHeader*>(h);
@@ -135,7 +136,10 @@ struct Probe {
     setup(alt ? scratch_alt_tags(t, h->cap_max) : table_tags(t),
           alt ? scratch_rows(t, h->cap_max) : table_slots(t, h->cap_max), h->log2cap, h->skip,
           (h->flags & TQ_UNIQUE_KEYS) != 0, h->log2g);
+    sel = h->flags & TQ_SELECT_PARTITION ? h->flags : 0u;
   }
+
+  __device__ __forceinline__ bool selected(uint64_t hh) const { return in_partition(hh, skip, sel); }
 
   // log2g < 0: one region spanning the table
   __device__ __forceinline__ void setup(const uint32_t* words, const int64_t* slot_base, int log2cap, int skip_bits,
@@ -172,7 +176,7 @@ struct Probe {
       uint64_t hh = mulhash(k[i]);
       b[i] = (int64_t)bucket_of(hh, skip, log2b);
       tg[i] = hash_tag(hh);
-      act[i] = ok[i];
+      act[i] = ok[i] && selected(hh);
       load[i] = true;
       m[i] = 0;
       empty[i] = false;

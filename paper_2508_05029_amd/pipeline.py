@@ -125,9 +125,10 @@ class JoinAgg:
     def init_state(self, stream=None):
         tq.groupby_init(self.state, self.domain, self.nsum, stream)
 
-    def finalize(self, stream=None):
+    def finalize(self, stream=None, reset=False):
+        """reset=True leaves the state empty, so the next query needs no init_state()."""
         tq.groupby_finalize(self.state, self.out.keys, self.out.count, self.out.sums, self.out.avg,
-                            self.out.ngroups, stream)
+                            self.out.ngroups, stream, reset=reset)
 
     def run(self, dim, fact, stream=None):
         self.init_state(stream)

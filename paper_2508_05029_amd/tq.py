@@ -19,6 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libtq.so")
 TQ_OK, TQ_EINVAL, TQ_ENOMEM, TQ_EFULL, TQ_EDOMAIN, TQ_EHIP = 0, -1, -2, -3, -4, -5
 TQ_U8, TQ_I32, TQ_I64 = 1, 4, 8
 TQ_UNIQUE_KEYS = 1
+TQ_SELECT_PARTITION = 2
+
+
+def TQ_PARTITION(i: int) -> int:
+    return i << 16
+
+
 MAX_COLS, MAX_PREDS, MAX_SUMS = 8, 4, 6
 
 
@@ -83,6 +90,7 @@ def lib():
             "tq_groupby_init": (_i32, [_vp, _sz, _i64, _i32, _vp]),
             "tq_groupby_agg": (_i32, [_vp, _i64, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp]),
             "tq_groupby_finalize": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tq_groupby_finalize_reset": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tq_check": (_i32, [_vp, _vp]),
             "tq_read_peak_scratch_bytes": (_sz, []),
             "tq_read_peak": (_i32, [_vp, _sz, _vp, _vp]),
@@ -242,9 +250,11 @@ def groupby_agg(state, domain, in_cols, nrows, ps, key: GKey, es, stream=None):
                                 ctypes.byref(key), exprs(es), len(es), _stream(stream)))
 
 
-def groupby_finalize(state, keys, count, sums, avg, ngroups, stream=None):
-    _check(lib().tq_groupby_finalize(state.data_ptr(), keys.data_ptr(), count.data_ptr(), sums.data_ptr(),
-                                     _ptr(avg), ngroups.data_ptr(), _stream(stream)))
+def groupby_finalize(state, keys, count, sums, avg, ngroups, stream=None, reset=False):
+    """reset=True: tq_groupby_finalize_reset (the state is left empty for the next query)."""
+    fn = lib().tq_groupby_finalize_reset if reset else lib().tq_groupby_finalize
+    _check(fn(state.data_ptr(), keys.data_ptr(), count.data_ptr(), sums.data_ptr(), _ptr(avg), ngroups.data_ptr(),
+              _stream(stream)))
 
 
 def check(obj, stream=None):
@@ -528,7 +538,7 @@ class Request(ctypes.Structure):
 class RequestResult(ctypes.Structure):
     _fields_ = [("start_s", ctypes.c_double), ("end_s", ctypes.c_double), ("status", ctypes.c_int32),
                 ("worker", ctypes.c_int32), ("ngroups", ctypes.c_int64), ("reserved_bytes", ctypes.c_int64),
-                ("retries", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("retries", ctypes.c_int32), ("splits", ctypes.c_int32)]
 
 
 def serve_run(tables: ServeTables, reqs, workers: int, budget: Budget, arena, max_groups: int):

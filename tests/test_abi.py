@@ -91,6 +91,15 @@ def test_invalid_arguments_are_rejected_synchronously():
     pay = tq.Col(FAKE, tq.TQ_I64)
     assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.0, 0, 0, None) == tq.TQ_EINVAL
     assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 40, 0, None) == tq.TQ_EINVAL
+    # one hash partition: 1 <= skip <= 16, id < 2^skip, and no id without the flag
+    sel = tq.TQ_SELECT_PARTITION
+    assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 0, sel, None) == tq.TQ_EINVAL
+    assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 17, sel, None) == tq.TQ_EINVAL
+    assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 2, sel | tq.TQ_PARTITION(4),
+                           None) == tq.TQ_EINVAL
+    assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 2, tq.TQ_PARTITION(1),
+                           None) == tq.TQ_EINVAL
+    assert L.tq_join_build(FAKE, 1 << 20, FAKE, pay, 10, None, 0, None, 0, 0.5, 0, 0x80, None) == tq.TQ_EINVAL
     # a table buffer too small for even 64 slots
     assert L.tq_join_table_init(FAKE, 100, None) == tq.TQ_EINVAL
     # the kept-row count needs a table and somewhere to write it

@@ -92,6 +92,42 @@ def test_groupby_lds_modes_match_oracle(domain, skew):
     assert_groups_equal(got, want)
 
 
+@pytest.mark.parametrize("domain", [6, 4000, 100_000])
+def test_finalize_reset_leaves_the_state_empty(domain):
+    """tq_groupby_finalize_reset: queries one after another on one state, with no
+    tq_groupby_init between them, each equal to the oracle (private rows for the small
+    domain, one shared table for the larger ones)."""
+    say(f"finalize_reset domain={domain}")
+    q = wl.FilterGroupByQuery(preds=[Pred("w", 5, 95)], key=wl.GroupKey(("g",), 1, domain),
+                              sums=[(Factor("v"),), (Factor("v"), Factor("w", -1, 7))], avg_of=[0, 1])
+    fg = pipeline.FilterGroupBy(q)
+    tq.groupby_init(fg.state, fg.domain, fg.nsum)
+    for rep, n in enumerate((300_000, 70_001, 5)):
+        g = uniform(n, 0, domain - 1, np.int64, 40 + rep, 0)
+        v = uniform(n, -10**12, 10**12, np.int64, 40 + rep, 1)
+        w = uniform(n, 0, 100, np.int32, 40 + rep, 2)
+        t = {"g": g, "v": v, "w": w}
+        d = pipeline.to_device(t)
+        tq.groupby_agg(fg.state, fg.domain, [d[c] for c in fg.names], n, fg.preds, fg.key, fg.exprs)
+        out = fg.out
+        tq.groupby_finalize(fg.state, out.keys, out.count, out.sums, out.avg, out.ngroups, reset=True)
+        assert_groups_equal(fg.result(), oracle.filter_groupby(t, q))
+    # and for the fused join probe: two steps on one table and state, reset between them
+    dim, fact = wl.join_agg_tables(150_000, 600_000, seed=47)
+    q = wl.JOIN_AGG_QUERY
+    want = oracle.join_agg(dim, fact, q)
+    ja = pipeline.JoinAgg(q, 150_000, 0.5)
+    ja.init_state()
+    dd, fd = pipeline.to_device(dim), pipeline.to_device(fact)
+    for _ in range(2):
+        ja.build(dd)
+        ja.probe(fd)
+        ja.finalize(reset=True)
+        got = ja.result()
+        assert got["join_rows"] == want["join_rows"]
+        assert_groups_equal(got, want, q.avg_of)
+
+
 @pytest.mark.parametrize("domain", [25, 4000, 100_000])
 def test_groupby_wraps_mod_2_64_like_the_oracle(domain):
     """Values near +-2^62: the products and the per-group sums leave the int64
@@ -419,6 +455,58 @@ def test_join_agg_duplicate_build_keys(lf):
             "disc": uniform(nf, 0, 10, np.int64, 72, 2)}
     say(f"duplicate build keys lf={lf}")
     assert _join_agg_case(dim, fact, wl.JOIN_AGG_QUERY, lf, unique=False) > nf
+
+
+@pytest.mark.parametrize("bits,unique,n_dim,share", [(1, True, 150_000, False), (3, True, 150_000, False),
+                                                     (4, False, 40_000, False), (2, True, 1_000_000, False),
+                                                     (3, True, 400_000, True)])
+def test_join_partitions_one_after_another_equal_the_whole_join(bits, unique, n_dim, share):
+    """TQ_SELECT_PARTITION: 2^bits builds, each keeping one hash partition of the
+    dimension rows, each followed by a probe of the whole fact table into one
+    group-by state, give the whole join's result (the split of a join too large
+    for its memory). share: the table holds only a partition's share of the rows
+    (its build then takes the global-atomic path)."""
+    say(f"partition builds bits={bits} unique={unique} n_dim={n_dim} share={share}")
+    q = wl.JOIN_AGG_QUERY
+    dim, fact = wl.join_agg_tables(n_dim, 4 * n_dim, seed=91 + bits)
+    if not unique:
+        dim["key"] = dim["key"] % (n_dim // 3)
+    want = oracle.join_agg(dim, fact, q)
+    dd, fd = pipeline.to_device(dim), pipeline.to_device(fact)
+    # (about 15% of the dimension rows pass the date filter; a share is an eighth of those, with room)
+    rows = n_dim if not share else int(n_dim * 0.16 / (1 << bits) * 1.5) + 1024
+    ja = pipeline.JoinAgg(q, rows, 0.5, unique=unique)
+    ja.init_state()
+    for part in range(1 << bits):
+        tq.join_build(ja.table, dd[q.build_key], dd[q.build_payload], n_dim, [dd[c] for c in ja.bnames], ja.bpreds,
+                      0.5, bits, ja.flags | tq.TQ_SELECT_PARTITION | tq.TQ_PARTITION(part))
+        ja.probe(fd)
+    ja.finalize()
+    got = ja.result()
+    assert got["join_rows"] == want["join_rows"]
+    assert_groups_equal(got, want, q.avg_of)
+    # materialised pairs: the union over the partitions equals the join
+    bk = dim["key"][:20_000]
+    pk = fact["fk"][:50_000]
+    total, pr, br = oracle.join_pairs(bk, pk)
+    bkd, pkd = torch.from_numpy(bk).to(DEV), torch.from_numpy(pk).to(DEV)
+    pay = torch.arange(len(bk), dtype=torch.int64, device=DEV)
+    table = torch.empty(tq.join_table_bytes(len(bk), 0.5), dtype=torch.uint8, device=DEV)
+    tq.join_table_init(table)
+    pairs = []
+    for part in range(1 << bits):
+        tq.join_build(table, bkd, pay, len(bk), skip=bits,
+                      flags=(tq.TQ_UNIQUE_KEYS if unique else 0) | tq.TQ_SELECT_PARTITION | tq.TQ_PARTITION(part))
+        cap = max(total, 1)
+        rws = torch.empty(cap, dtype=torch.int64, device=DEV)
+        bro = torch.empty(cap, dtype=torch.int64, device=DEV)
+        cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+        tq.join_probe(table, pkd, len(pk), out_row=rws, out_payload=bro, capacity=cap, out_count=cnt)
+        tq.check(table)
+        m = int(cnt.item())
+        assert m <= cap
+        pairs += list(zip(rws[:m].cpu().tolist(), bro[:m].cpu().tolist()))
+    assert sorted(pairs) == list(zip(pr.tolist(), br.tolist()))
 
 
 @pytest.mark.parametrize("unique", [True, False])

@@ -116,15 +116,16 @@ def test_alone_equals_mix_equals_oracle(setup):
 
 def test_budget_admission_and_oversized_request(setup):
     """A budget with room for about one join request at a time: admission
-    serialises and nothing deadlocks; exactly the requests whose documented
-    reservation exceeds the cap fail with TQ_ENOMEM, and every other result
-    equals the oracle."""
+    serialises and nothing deadlocks; exactly the join requests whose documented
+    reservation exceeds the cap run split into hash partitions (one after
+    another, each table within the cap), and every result, split or not, equals
+    the oracle."""
     reqs = wl.serving_requests(12, qps=5000.0, fact_lo=4.0, fact_hi=5.0, seed=wl.SERVE_SEED + 2)
     base = setup.requests(reqs)
     rows = [(base[i].shape, base[i].fact_first, base[i].n_fact, base[i].dim_first, base[i].n_dim, base[i].arrival_s)
             for i in range(len(reqs))]
-    # two requests that can never fit: joins over the whole dimension (a 2^18-slot table, 9.7 MB), one
-    # in the middle of the queue and one at its end; they must fail without holding up the others
+    # two requests that do not fit whole: joins over the whole dimension (a 2^18-slot table, 9.7 MB), one
+    # in the middle of the queue and one at its end; they must run split without holding up the others
     rows.insert(4, (1, 0, 50_000, 0, setup.n_dim, rows[3][5]))
     rows.append((2, 0, 2, 0, setup.n_dim, rows[-1][5]))
     R = (tq.Request * len(rows))()
@@ -144,13 +145,73 @@ def test_budget_admission_and_oversized_request(setup):
     say(f"reservations (MiB): {[round(b / 2**20, 1) for b in need]}, cap {cap / 2**20:.0f}")
     assert [i for i in range(len(reqs)) if need[i] > cap] == [4, len(reqs) - 1]
     for i in range(len(reqs)):
+        assert res[i].status == 0, i
         if need[i] > cap:
-            assert res[i].status == tq.TQ_ENOMEM, i
+            say(f"request {i}: split into {res[i].splits} partitions, reserved {res[i].reserved_bytes / 2**20:.1f} MiB")
+            assert res[i].splits > 1 and res[i].reserved_bytes <= cap, i
         else:
-            assert res[i].status == 0, i
+            assert res[i].splits == 1, i
             assert res[i].reserved_bytes == need[i], i
-            assert same_as_oracle(packed(setup, R[i], *run, i), expected(setup, R[i])), i
+        assert same_as_oracle(packed(setup, R[i], *run, i), expected(setup, R[i])), i
     assert budget.used == 0
+
+
+def test_requests_that_cannot_fit_even_split_fail_alone(setup):
+    """A budget that holds a filter + group-by request but no join request, not
+    even split 256 ways (its group-by state alone is larger): the joins complete
+    at once with TQ_ENOMEM, the others run and equal the oracle, nothing waits
+    forever."""
+    reqs = wl.serving_requests(12, qps=5000.0, fact_lo=4.0, fact_hi=5.0, seed=wl.SERVE_SEED + 5)
+    R = setup.requests(reqs)
+    setup.T.estimate = 0
+    cap = 400 << 10
+    try:
+        budget = tq.Budget(cap)
+        arena = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        run = tq.serve_run(setup.T, R, 3, budget, arena, 25)
+    finally:
+        setup.T.estimate = 1
+    res = run[0]
+    shapes = [R[i].shape for i in range(len(reqs))]
+    assert 0 in shapes and any(x != 0 for x in shapes)
+    for i in range(len(reqs)):
+        if R[i].shape == 0:
+            assert res[i].status == 0, i
+            assert reservation(setup, R[i]) <= cap
+            assert same_as_oracle(packed(setup, R[i], *run, i), expected(setup, R[i])), i
+        else:
+            assert res[i].status == tq.TQ_ENOMEM, i
+    assert budget.used == 0
+
+
+def test_split_join_equals_whole_join(setup):
+    """The same join requests served whole (a large budget) and split into hash
+    partitions (a budget below each one's whole reservation): equal results,
+    equal to the oracle."""
+    # device-resident joins only (a streamed one reserves its staging slots whole, which no
+    # split makes smaller)
+    reqs = [r for r in wl.serving_requests(40, qps=1e9, fact_lo=4.5, fact_hi=5.3, seed=wl.SERVE_SEED + 6)
+            if r.shape == 1][:6]
+    R = setup.requests(reqs)
+    n = len(R)
+    setup.T.estimate = 0
+    try:
+        big = tq.Budget(256 << 20)
+        arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        whole = tq.serve_run(setup.T, R, 2, big, arena, 25)
+        cap = min(reservation(setup, R[i]) for i in range(n)) - 1
+        small = tq.Budget(cap)
+        split = tq.serve_run(setup.T, R, 2, small, arena, 25)
+    finally:
+        setup.T.estimate = 1
+    for i in range(n):
+        assert whole[0][i].status == 0 and split[0][i].status == 0, i
+        assert whole[0][i].splits == 1 and split[0][i].splits > 1, i
+        a = packed(setup, R[i], *whole, i)
+        b = packed(setup, R[i], *split, i)
+        for x, y in zip(a, b):
+            assert x.tolist() == y.tolist(), i
+        assert same_as_oracle(b, expected(setup, R[i])), i
 
 
 def _join_requests(setup, n, seed):
