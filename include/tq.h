@@ -53,8 +53,11 @@ int32_t tq_version(void);
 typedef enum { TQ_U8 = 1, TQ_I32 = 4, TQ_I64 = 8 } tq_type; /* values widen to int64 */
 
 typedef struct {
-  const void* data; /* d_ column values */
-  int32_t type;     /* tq_type */
+  const void* data;     /* d_ column values */
+  int32_t type;         /* tq_type */
+  const uint8_t* valid; /* d_ validity bitmap or NULL (no NULLs): bit r of byte r / 8, least significant
+                           bit first, 1 = value present (the Arrow layout, Section 3.4). Only the *_nullable
+                           entry points accept columns that carry one (the others return TQ_EINVAL). */
 } tq_col;
 
 /* lo <= col <= hi on the widened value; a list of predicates is a conjunction. */
@@ -193,9 +196,10 @@ tq_status tq_join_table_rows(const void* d_table, int64_t* rows, hipStream_t str
  * tq_join_probe. d_state comes from tq_groupby_init. */
 typedef struct {
   void* d_state;
-  int64_t domain; /* as passed to tq_groupby_init */
+  int64_t domain; /* as passed to tq_groupby_init (or tq_groupby_init_nullable) */
   const tq_expr* sums;
-  int32_t nsum;   /* as passed to tq_groupby_init */
+  int32_t nsum;   /* as passed to tq_groupby_init (or tq_groupby_init_nullable) */
+  int32_t nullable; /* 1: d_state comes from tq_groupby_init_nullable (tq_join_probe_nullable only) */
 } tq_agg;
 
 /* Probe: for every probe row r < n that satisfies the optional predicates over
@@ -215,6 +219,54 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
                         int32_t ncol, const tq_pred* p, int32_t np, int64_t* d_out_probe_row,
                         int64_t* d_out_payload, int64_t capacity, int64_t* d_out_count, const tq_agg* agg,
                         hipStream_t stream);
+
+/* The join under NULLs: a NULL key (d_key_valid, a bitmap or NULL; build or
+ * probe side) equals nothing; the build's filter columns and payload may carry
+ * bitmaps, and a NULL payload is stored as INT64_MIN (a payload column with
+ * NULLs must not hold INT64_MIN itself). The probe aggregates into a nullable
+ * group-by state (agg->nullable = 1, from tq_groupby_init_nullable): a match
+ * whose payload is NULL goes to the NULL group, and a probe value that is NULL
+ * makes the sums reading it skip the row. Arguments as tq_join_build and the
+ * fused tq_join_probe otherwise. */
+tq_status tq_join_build_nullable(void* d_table, size_t bytes, const int64_t* d_keys, const uint8_t* d_key_valid,
+                                 tq_col payload, int64_t n, const tq_col* filt, int32_t nfilt, const tq_pred* p,
+                                 int32_t np, double load_factor, int32_t skip, uint32_t flags, hipStream_t stream);
+tq_status tq_join_probe_nullable(const void* d_table, const int64_t* d_probe_keys, const uint8_t* d_key_valid,
+                                 int64_t n, const tq_col* cols, int32_t ncol, const tq_pred* p, int32_t np,
+                                 const tq_agg* agg, hipStream_t stream);
+
+/* --------------------------------------------- string keys (dictionaries) */
+
+/* A column of strings in Arrow's layout: string i is the bytes
+ * data[offsets[i] .. offsets[i + 1]) (offsets: n + 1 int32 entries). */
+typedef struct {
+  const int32_t* offsets; /* d_ */
+  const uint8_t* data;    /* d_ */
+  int64_t n;
+} tq_strings;
+
+/* String join and group keys are dictionary-encoded (the Arrow dictionary
+ * arrays of the columnar layout, Section 3.4): int32 codes into a dictionary of
+ * distinct strings. Grouping by a string column groups by its codes (domain =
+ * the dictionary size; the caller decodes the output keys). Joining two string
+ * columns encoded against different dictionaries maps the probe side's
+ * dictionary onto the build side's: tq_dict_unify sets d_remap[i] = the index
+ * j of the build dictionary entry equal byte for byte to probe dictionary
+ * entry i, or -1 if there is none. The build dictionary's entries must be
+ * distinct. d_table is a join table buffer for build.n rows
+ * (tq_join_table_bytes(build.n, 0.5)), d_scratch holds
+ * tq_dict_unify_scratch_bytes(build.n) bytes; both are overwritten. */
+size_t tq_dict_unify_scratch_bytes(int64_t n_build);
+tq_status tq_dict_unify(void* d_table, size_t table_bytes, tq_strings build, tq_strings probe, void* d_scratch,
+                        size_t scratch_bytes, int32_t* d_remap, hipStream_t stream);
+
+/* int64 join keys from dictionary codes: d_keys[r] = codes[r] (d_remap NULL)
+ * or d_remap[codes[r]], and -1 where the code is NULL (d_valid, a bitmap or
+ * NULL), outside [0, n_remap) or maps to no entry. Codes of the build side
+ * (>= 0) never equal -1, so a probe key of -1 matches nothing; build rows whose
+ * code is NULL are left out by tq_join_build_nullable with the same bitmap. */
+tq_status tq_dict_keys(const int32_t* d_codes, const uint8_t* d_valid, int64_t n, const int32_t* d_remap,
+                       int64_t n_remap, int64_t* d_keys, hipStream_t stream);
 
 /* ------------------------------------------------------------- group-by */
 
@@ -250,6 +302,27 @@ tq_status tq_groupby_finalize(const void* d_state, int64_t* d_keys, int64_t* d_c
  * reported by tq_check and cleared by tq_groupby_init). */
 tq_status tq_groupby_finalize_reset(void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums, double* d_avg,
                                     int64_t* d_ngroups, hipStream_t stream);
+
+/* NULLs (SQL's semantics over Arrow validity bitmaps, the columnar layout of
+ * Section 3.4): a predicate over a NULL value is not true, so the row is
+ * dropped; a sum whose expression reads a NULL value skips the row; COUNT(*)
+ * counts every row; rows whose group key is NULL form one group of their own.
+ * A nullable state for keys in [0, domain) keeps, per group and per sum j,
+ * SUM_j and COUNT_j (the rows where sum j is not NULL), and one more group for
+ * the NULL key; at most 3 sums. tq_groupby_agg_nullable takes the arguments of
+ * tq_groupby_agg; its group key has one column. tq_groupby_finalize_nullable
+ * emits the groups with COUNT(*) > 0 in ascending key order, the NULL group
+ * last with d_keys[g] = domain (the key that stands for NULL), d_sums[g * nsum
+ * + j] = SUM_j, d_nonnull[g * nsum + j] = COUNT_j (SUM_j and AVG_j are NULL when
+ * it is 0, and are then written as 0), d_avg = (double)SUM_j / (double)COUNT_j.
+ * Outputs must hold domain + 1 groups. */
+size_t tq_groupby_state_bytes_nullable(int64_t domain, int32_t nsum);
+tq_status tq_groupby_init_nullable(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream);
+tq_status tq_groupby_agg_nullable(void* d_state, int64_t domain, const tq_col* in, int32_t ncol, int64_t nrows,
+                                  const tq_pred* p, int32_t np, const tq_gkey* key, const tq_expr* sums, int32_t nsum,
+                                  hipStream_t stream);
+tq_status tq_groupby_finalize_nullable(const void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums,
+                                       int64_t* d_nonnull, double* d_avg, int64_t* d_ngroups, hipStream_t stream);
 
 /* Synchronise `stream`, then return the error latched in a join table or a
  * group-by state (TQ_OK if none). */

@@ -274,3 +274,180 @@ void oc_partition(const int64_t* keys, int64_t n, int32_t bits, int64_t* out_per
   free(cursor);
   free(pid);
 }
+
+/* ---- NULLs ----------------------------------------------------------------
+ * A column may carry a validity bitmap: bit r of byte r / 8, least significant
+ * bit first, 1 when the value is present (the Arrow layout of the device
+ * batches, Section 3.4); no bitmap means every value is present. SQL's
+ * semantics, written out:
+ *   selection   a predicate over a NULL value is not true, so the row does not
+ *               pass (a conjunction passes only if every predicate is true)
+ *   projection  a product with a NULL factor is NULL (a constant is never NULL)
+ *   group-by    the rows whose key is NULL form one group of their own,
+ *               emitted after every other group; COUNT(*) counts every row of
+ *               a group; SUM_j and COUNT_j take only the rows whose e_j is not
+ *               NULL; AVG_j = (double)SUM_j / (double)COUNT_j; SUM_j and AVG_j
+ *               are NULL when COUNT_j is 0
+ *   equi-join   a NULL key equals nothing, on either side
+ */
+static int valid_at(const uint8_t* v, int64_t r) { return v == NULL || ((v[r >> 3] >> (r & 7)) & 1); }
+
+/* Selection with validity bitmaps (valid[c] NULL: column c has no NULLs). */
+int64_t oc_filter_nullable(const oc_col* cols, const uint8_t* const* valid, int64_t n, int32_t np, const int32_t* pcol,
+                           const int64_t* plo, const int64_t* phi, uint8_t* pass) {
+  int64_t count = 0;
+  for (int64_t r = 0; r < n; r++) {
+    int ok = 1;
+    for (int32_t j = 0; j < np && ok; j++) {
+      if (!valid_at(valid[pcol[j]], r)) {
+        ok = 0;
+        break;
+      }
+      int64_t v = widen(&cols[pcol[j]], r);
+      if (v < plo[j] || v > phi[j]) ok = 0;
+    }
+    pass[r] = (uint8_t)ok;
+    count += ok;
+  }
+  return count;
+}
+
+/* Projection with validity: out_valid[r] (one byte per row) is 0 when a factor
+ * reads a NULL value, and out[r] is then 0. */
+void oc_project_nullable(const oc_col* cols, const uint8_t* const* valid, int64_t n, int32_t nf, const int32_t* fcol,
+                         const int64_t* fsign, const int64_t* fadd, int64_t* out, uint8_t* out_valid) {
+  for (int64_t r = 0; r < n; r++) {
+    uint64_t acc = 1;
+    int present = 1;
+    for (int32_t f = 0; f < nf; f++) {
+      int64_t x = 0;
+      if (fcol[f] >= 0) {
+        if (!valid_at(valid[fcol[f]], r)) present = 0;
+        x = widen(&cols[fcol[f]], r);
+      }
+      uint64_t fac = (uint64_t)fsign[f] * (uint64_t)x + (uint64_t)fadd[f];
+      acc = f == 0 ? fac : acc * fac;
+    }
+    out[r] = present ? (int64_t)acc : 0;
+    out_valid[r] = (uint8_t)present;
+  }
+}
+
+typedef struct {
+  int64_t isnull, key, row;
+} null_keyed_row;
+
+static int cmp_null_keyed_row(const void* a, const void* b) {
+  const null_keyed_row* x = (const null_keyed_row*)a;
+  const null_keyed_row* y = (const null_keyed_row*)b;
+  if (x->isnull != y->isnull) return x->isnull < y->isnull ? -1 : 1;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  if (x->row != y->row) return x->row < y->row ? -1 : 1;
+  return 0;
+}
+
+/* Group-by over one key column that may hold NULLs (key_valid: a bitmap, or
+ * NULL), with nval value arrays whose rows may be NULL (vals_valid[v]: one
+ * byte per row, or NULL for none). Outputs per group g: out_keys[g] (0 for the
+ * NULL group), out_key_null[g], out_count[g] = COUNT(*), and per value v at
+ * g * nval + v: out_sums (0 when NULL), out_nonnull = COUNT_v, out_avg (0 when
+ * NULL). Groups in ascending key order, the NULL group last. Returns the group
+ * count, or -1 if it exceeds max_groups. */
+int64_t oc_groupby_nullable(int64_t n, const uint8_t* pass, oc_col key, const uint8_t* key_valid, int32_t nval,
+                            const int64_t* const* vals, const uint8_t* const* vals_valid, int64_t* out_keys,
+                            uint8_t* out_key_null, int64_t* out_count, int64_t* out_sums, int64_t* out_nonnull,
+                            double* out_avg, int64_t max_groups) {
+  int64_t m = 0;
+  for (int64_t r = 0; r < n; r++) m += (pass == NULL || pass[r]);
+  null_keyed_row* rows = (null_keyed_row*)malloc((size_t)(m > 0 ? m : 1) * sizeof(null_keyed_row));
+  int64_t w = 0;
+  for (int64_t r = 0; r < n; r++) {
+    if (pass != NULL && !pass[r]) continue;
+    rows[w].isnull = !valid_at(key_valid, r);
+    rows[w].key = rows[w].isnull ? 0 : widen(&key, r);
+    rows[w].row = r;
+    w++;
+  }
+  qsort(rows, (size_t)m, sizeof(null_keyed_row), cmp_null_keyed_row);
+  int64_t g = 0;
+  for (int64_t i = 0; i < m;) {
+    int64_t j = i;
+    while (j < m && rows[j].isnull == rows[i].isnull && rows[j].key == rows[i].key) j++;
+    if (g >= max_groups) {
+      free(rows);
+      return -1;
+    }
+    out_keys[g] = rows[i].key;
+    out_key_null[g] = (uint8_t)rows[i].isnull;
+    out_count[g] = j - i;
+    for (int32_t v = 0; v < nval; v++) {
+      uint64_t s = 0;
+      int64_t c = 0;
+      for (int64_t t = i; t < j; t++) {
+        const int64_t row = rows[t].row;
+        if (vals_valid != NULL && vals_valid[v] != NULL && !vals_valid[v][row]) continue;
+        s += (uint64_t)vals[v][row];
+        c++;
+      }
+      out_sums[g * nval + v] = c ? (int64_t)s : 0;
+      out_nonnull[g * nval + v] = c;
+      out_avg[g * nval + v] = c ? (double)(int64_t)s / (double)c : 0.0;
+    }
+    g++;
+    i = j;
+  }
+  free(rows);
+  return g;
+}
+
+/* ---------------------------------------------------------------------------
+ * Dictionary-encoded strings (Arrow dictionary arrays, Section 3.4). Two
+ * string columns encoded against different dictionaries join on the strings
+ * themselves: remap[i] is the index of the build dictionary entry whose bytes
+ * equal probe dictionary entry i, or -1 when there is none. Definition
+ * written out: the build entries are sorted by (length, bytes) and each
+ * probe entry is looked up by binary search with the same order.
+ */
+typedef struct {
+  const int32_t* off;
+  const uint8_t* data;
+} str_col;
+
+static int cmp_str(const str_col* c, int64_t i, const uint8_t* s, int32_t len) {
+  const int32_t a = c->off[i], li = c->off[i + 1] - a;
+  if (li != len) return li < len ? -1 : 1;
+  return len ? memcmp(c->data + a, s, (size_t)len) : 0;
+}
+
+static const str_col* g_sort_col;
+static int cmp_str_idx(const void* x, const void* y) {
+  const int64_t j = *(const int64_t*)y;
+  const int32_t a = g_sort_col->off[j];
+  return cmp_str(g_sort_col, *(const int64_t*)x, g_sort_col->data + a, g_sort_col->off[j + 1] - a);
+}
+
+void oc_dict_unify(const int32_t* boff, const uint8_t* bdata, int64_t nb, const int32_t* poff, const uint8_t* pdata,
+                   int64_t np, int32_t* remap) {
+  str_col b = {boff, bdata};
+  int64_t* idx = (int64_t*)malloc((size_t)(nb > 0 ? nb : 1) * sizeof(int64_t));
+  for (int64_t i = 0; i < nb; i++) idx[i] = i;
+  g_sort_col = &b;
+  qsort(idx, (size_t)nb, sizeof(int64_t), cmp_str_idx);
+  for (int64_t i = 0; i < np; i++) {
+    const uint8_t* s = pdata + poff[i];
+    const int32_t len = poff[i + 1] - poff[i];
+    int64_t lo = 0, hi = nb;
+    remap[i] = -1;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      const int c = cmp_str(&b, idx[mid], s, len);
+      if (c == 0) {
+        remap[i] = (int32_t)idx[mid];
+        break;
+      }
+      if (c < 0) lo = mid + 1;
+      else hi = mid;
+    }
+  }
+  free(idx);
+}

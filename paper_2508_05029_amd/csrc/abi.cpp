@@ -47,8 +47,8 @@ int device_cu_count() {
 static bool valid_type(int32_t t) { return t == TQ_U8 || t == TQ_I32 || t == TQ_I64; }
 
 tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p, int32_t np, const tq_expr* e,
-                    int32_t ne, const tq_gkey* key, int64_t nrows) {
-  memset(P, 0, sizeof *P);
+                    int32_t ne, const tq_gkey* key, int64_t nrows, bool allow_nulls) {
+  *P = RowPlan{};
   if (nrows < 0) return fail(TQ_EINVAL, "nrows < 0");
   if (ncol < 0 || ncol > TQ_MAX_COLS) return fail(TQ_EINVAL, "ncol %d outside [0, %d]", ncol, TQ_MAX_COLS);
   if (np < 0 || np > TQ_MAX_PREDS) return fail(TQ_EINVAL, "np %d outside [0, %d]", np, TQ_MAX_PREDS);
@@ -61,8 +61,11 @@ tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p
     if (!valid_type(in[c].type)) return fail(TQ_EINVAL, "column %d: bad type %d", c, in[c].type);
     if (nrows > 0 && in[c].data == nullptr) return fail(TQ_EINVAL, "column %d: NULL data", c);
     if (((uintptr_t)in[c].data & 15) != 0) return fail(TQ_EINVAL, "column %d: not 16-byte aligned", c);
+    if (in[c].valid && !allow_nulls)
+      return fail(TQ_EINVAL, "column %d has a validity bitmap: use the _nullable entry point", c);
     P->col[c].p = in[c].data;
     P->col[c].w = in[c].type;
+    P->col[c].valid = in[c].valid;
   }
   P->np = np;
   for (int j = 0; j < np; j++) {
@@ -106,7 +109,9 @@ tq_status make_plan(RowPlan* P, const tq_col* in, int32_t ncol, const tq_pred* p
       kept++;
     }
   }
-  for (int c = kept; c < ncol; c++) P->col[c] = DCol{nullptr, 0};
+  for (int c = kept; c < ncol; c++) P->col[c] = DCol{nullptr, 0, nullptr};
+  P->null_cols = 0;
+  for (int c = 0; c < kept; c++) P->null_cols |= (P->col[c].valid ? 1u : 0u) << c;
   auto re = [&](uint32_t m) -> uint32_t { return m ? remap[__builtin_ctz(m)] : 0u; };
   for (int j = 0; j < P->np; j++) P->pred[j].mask = re(P->pred[j].mask);
   for (int j = 0; j < P->ne; j++)

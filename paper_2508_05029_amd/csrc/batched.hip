@@ -517,7 +517,7 @@ tq_status tq_batched_run_per_instance(const tq_batch_query* q, const tq_instance
   if (s) return s;
   for (int i = 0; i < n; i++) {
     const tq_instance& x = h[i];
-    tq_col dcols[4], fcols[4];
+    tq_col dcols[4] = {}, fcols[4] = {};
     for (int c = 0; c < 4; c++) {
       dcols[c] = tq_col{x.dim_cols[c], q->dim_types[c]};
       fcols[c] = tq_col{x.fact_cols[c], q->fact_types[c]};

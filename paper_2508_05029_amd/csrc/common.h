@@ -59,6 +59,7 @@ inline int nc_bucket(int ncol) { return ncol <= 1 ? 1 : ncol <= 2 ? 2 : ncol <= 
 struct DCol {
   const void* p;
   int32_t w;  // byte width 1, 4 or 8
+  const uint8_t* valid = nullptr;  // validity bitmap (bit r of byte r / 8), or none
 };
 
 // Columns are referenced through one-bit masks (bit c = plan column c; 0 = the
@@ -95,11 +96,13 @@ struct RowPlan {
   int32_t key_ncol;  // group key (0 when unused)
   uint32_t key_mask[2];
   int64_t key_mult;
+  uint32_t null_cols;  // bit c: plan column c carries a validity bitmap
 };
 
-// Validates and copies host descriptors into a RowPlan. Returns TQ_OK or TQ_EINVAL.
+// Validates and copies host descriptors into a RowPlan. Returns TQ_OK or
+// TQ_EINVAL (also for a column with a validity bitmap unless allow_nulls).
 tq_status make_plan(RowPlan* plan, const tq_col* in, int32_t ncol, const tq_pred* p, int32_t np,
-                    const tq_expr* e, int32_t ne, const tq_gkey* key, int64_t nrows);
+                    const tq_expr* e, int32_t ne, const tq_gkey* key, int64_t nrows, bool allow_nulls = false);
 
 // ------------------------------------------------------- object headers
 
@@ -133,6 +136,7 @@ struct StateHeader {
   int32_t nsum;
   int32_t rows;  // partial rows: > 1 for block-private partials, 1 for one shared table
   int64_t used;  // private rows written since init (the largest grid of an aggregating launch)
+  int32_t nullable;  // 1: groups [0, domain - 1) and the NULL group domain - 1; per sum SUM_j, COUNT_j
 };
 static_assert(sizeof(StateHeader) <= kHeaderBytes, "header");
 
@@ -468,6 +472,43 @@ __device__ __forceinline__ int64_t eval_key(const RowPlan& P, const int64_t (&v)
   int64_t k = pick<NC, R>(v, i, P.key_mask[0]);
   if (P.key_ncol == 2) k = (int64_t)((uint64_t)k * (uint64_t)P.key_mult + (uint64_t)pick<NC, R>(v, i, P.key_mask[1]));
   return k;
+}
+
+// ----------------------------------------------------------------- NULLs
+
+__device__ __forceinline__ bool bit_at(const uint8_t* v, int64_t r) { return (v[r >> 3] >> (r & 7)) & 1u; }
+
+// The plan columns present at row r, as a mask (bit c set: column c is not
+// NULL there).
+template <int NC>
+__device__ __forceinline__ uint32_t row_present(const RowPlan& P, int64_t r) {
+  uint32_t m = ~0u;
+#pragma unroll
+  for (int c = 0; c < NC; c++)
+    if ((P.null_cols >> c) & 1u) m &= ~((uint32_t)!bit_at(P.col[c].valid, r) << c);
+  return m;
+}
+
+// Every predicate true, none over a NULL value (a predicate over NULL is not true).
+template <int NC, int R>
+__device__ __forceinline__ bool eval_preds_present(const RowPlan& P, const int64_t (&v)[NC][R], int i,
+                                                   uint32_t present) {
+  bool ok = true;
+#pragma unroll 1
+  for (int j = 0; j < P.np; j++) {
+    const int64_t x = pick<NC, R>(v, i, P.pred[j].mask);
+    ok = ok && (present & P.pred[j].mask) && (x >= P.pred[j].lo) && (x <= P.pred[j].hi);
+  }
+  return ok;
+}
+
+// The columns an expression reads (a constant factor reads none).
+__device__ __forceinline__ uint32_t expr_cols(const DExpr& E) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int f = 0; f < 3; f++)
+    if (f < E.nf) m |= E.f[f].mask;
+  return m;
 }
 
 // Exclusive prefix over the wave of a 32-bit value; *total gets the wave sum.

@@ -30,15 +30,18 @@ constexpr int kAggRows = 1024;            // grid cap of the aggregating kernels
 constexpr int kPrivateRowsMaxEntries = 1024;
 constexpr int kAggBlock = 512;            // threads per aggregating workgroup
 constexpr int kAggBlocksPerCU = 3;
+constexpr int kMaxNullableSums = TQ_MAX_SUMS / 2;  // a nullable state keeps SUM_j and COUNT_j per sum
 
 struct AggTarget {
   const StateHeader* hdr;
   int64_t* data;
   int32_t* err;
   int64_t domain;
-  int32_t stride;   // 1 + nsum
+  int32_t stride;   // 1 + nsum (nullable: 1 + 2 * nsum)
   int32_t rows;     // kAggRows or 1
   int32_t log2hcap; // kHash: LDS slots = 1 << log2hcap
+  int32_t nullable; // 1: the state of tq_groupby_init_nullable
+  int64_t udomain;  // keys of the caller's domain (nullable: domain - 1, the last group being NULL)
 };
 
 inline int state_rows(int64_t domain, int stride) {
@@ -65,7 +68,7 @@ __host__ __device__ inline AggMode agg_mode(int64_t domain, int stride, int* log
 __device__ __forceinline__ bool state_matches(const AggTarget& T) {
   const StateHeader* h = T.hdr;
   if (h->magic != kStateMagic) return false;
-  if (h->domain != T.domain || h->nsum != T.stride - 1 || h->rows != T.rows) {
+  if (h->domain != T.domain || h->nsum != T.stride - 1 || h->rows != T.rows || h->nullable != T.nullable) {
     if (threadIdx.x == 0 && blockIdx.x == 0) latch_error(T.err, TQ_EINVAL);
     return false;
   }
@@ -186,6 +189,30 @@ struct LdsAgg {
     return true;
   }
 
+  // Nullable states: group `key` (T.udomain: the NULL group; a key outside
+  // [0, udomain] is remembered or latched as TQ_EDOMAIN), COUNT(*) += 1, and
+  // for each sum j present in the row (bit j of `present`) SUM_j += v[j] and
+  // COUNT_j += 1 (entries 1 + 2j and 2 + 2j).
+  template <int NE>
+  __device__ __forceinline__ void add_nullable(const AggTarget& T, int64_t key, const int64_t (&v)[NE],
+                                               uint32_t present, int nsum) {
+    unsigned long long* at;
+    bool in_lds;
+    if (!count(T, key, &at, &in_lds)) return;
+#pragma unroll
+    for (int j = 0; j < NE; j++) {
+      if (j < nsum && ((present >> j) & 1u)) {
+        if (in_lds) {
+          atomicAdd(at + 1 + 2 * j, (unsigned long long)v[j]);
+          atomicAdd(at + 2 + 2 * j, 1ull);
+        } else {
+          global_add(at + 1 + 2 * j, v[j]);
+          global_add(at + 2 + 2 * j, 1);
+        }
+      }
+    }
+  }
+
   // Folds this workgroup's LDS partials into the global state.
   __device__ void flush(const AggTarget& T) {
     if (bad) latch_error(T.err, TQ_EDOMAIN);
@@ -221,7 +248,9 @@ struct LdsAgg {
   }
 };
 
-tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T, AggMode* mode, size_t* lds);
+// nullable: the state of tq_groupby_init_nullable (domain + 1 groups, 1 + 2 * nsum entries each).
+tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T, AggMode* mode, size_t* lds,
+                      bool nullable = false);
 int agg_grid(int64_t n);
 
 // Smallest supported sum-count bucket >= ne (the aggregating kernels are

@@ -89,6 +89,21 @@ static int stream_grid(int64_t n, int per_cu) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)device_cu_count() * per_cu));
 }
 
+// A build row's admission under NULLs (nulls: some column carries a
+// validity bitmap): the filter (a predicate over NULL is not true) and a
+// present key. Without NULLs, the filter alone.
+template <int NC, int R>
+__device__ __forceinline__ bool build_row_ok(const RowPlan& P, const int64_t (&v)[NC][R], int i, int64_t r,
+                                             const uint8_t* key_valid, bool nulls) {
+  if (!nulls) return eval_preds<NC>(P, v, i);
+  return (!key_valid || bit_at(key_valid, r)) && eval_preds_present<NC>(P, v, i, row_present<NC>(P, r));
+}
+
+// The stored payload: INT64_MIN stands for a NULL one.
+__device__ __forceinline__ int64_t stored_payload(const DCol& pc, int64_t r, int64_t pay) {
+  return pc.valid && !bit_at(pc.valid, r) ? INT64_MIN : pay;
+}
+
 __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
   h->magic = kTableMagic;
   h->err = 0;
@@ -114,7 +129,7 @@ __global__ void k_table_init(TableHeader* h, int64_t cap_max) {
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, const int64_t* keys, int64_t n, int64_t per,
                                                         TableHeader* h, int64_t cap_max, int count, int skip,
-                                                        uint32_t flags) {
+                                                        uint32_t flags, const uint8_t* key_valid) {
   __shared__ int64_t ws[kBlock / kWave];
   if (h->magic != kTableMagic) return;  // never initialised: the insert kernel does nothing either
   // a new build: an error latched by an earlier build into this buffer no longer applies
@@ -129,13 +144,15 @@ __global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, const int64_t
   int64_t c = 0;
   const DCol kc = {keys, 8};
   const bool sel = (flags & TQ_SELECT_PARTITION) != 0;
+  const bool nulls = P.null_cols != 0 || key_valid != nullptr;
   for (int64_t r0 = lo + threadIdx.x * kRows; r0 < hi; r0 += kChunk) {
     int64_t v[NC][kRows], k[kRows];
     load_rows<NC>(P, r0, r0 + kRows <= hi, hi, v);
     if (sel) load4(kc, r0, r0 + kRows <= hi, hi, k);
 #pragma unroll
     for (int i = 0; i < kRows; i++)
-      c += (r0 + i < hi) && eval_preds<NC>(P, v, i) && (!sel || in_partition(mulhash(k[i]), skip, flags));
+      c += (r0 + i < hi) && build_row_ok<NC>(P, v, i, r0 + i, key_valid, nulls) &&
+           (!sel || in_partition(mulhash(k[i]), skip, flags));
   }
   int64_t t = block_sum(c, ws);
   if (threadIdx.x == 0) table_partials(h)[blockIdx.x] = t;
@@ -147,7 +164,8 @@ __global__ __launch_bounds__(kBlock) void k_build_count(RowPlan P, const int64_t
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
                                                          TableHeader* h, int64_t cap_max, int64_t n_host, int nblk,
-                                                         double lf, int skip, uint32_t flags) {
+                                                         double lf, int skip, uint32_t flags,
+                                                         const uint8_t* key_valid) {
   __shared__ int64_t ws[kBlock / kWave];
   if (h->magic != kTableMagic) return;
   int64_t rows = n_host;
@@ -179,6 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_
   uint32_t* words = table_tags(h);
   v2i64* slots = reinterpret_cast<v2i64*>(table_slots(h, cap_max));
   const DCol kc = {keys, 8};
+  const bool nulls = P.null_cols != 0 || key_valid != nullptr;
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
     const bool fullrow = r0 + kRows <= n;
@@ -188,8 +207,11 @@ __global__ __launch_bounds__(kBlock) void k_build_insert(RowPlan P, const int64_
     load4(kc, r0, fullrow, n, k);
     load4(payload, r0, fullrow, n, pay);
 #pragma unroll
-    for (int i = 0; i < kRows; i++)
-      pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i) && in_partition(mulhash(k[i]), skip, flags);
+    for (int i = 0; i < kRows; i++) {
+      pend[i] = (r0 + i < n) && build_row_ok<NC>(P, v, i, r0 + i, key_valid, nulls) &&
+                in_partition(mulhash(k[i]), skip, flags);
+      if (pend[i]) pay[i] = stored_payload(payload, r0 + i, pay[i]);
+    }
     table_insert<kRows>(words, slots, l, skip, pend, k, pay);
   }
 }
@@ -226,7 +248,8 @@ constexpr int kMaxBloomLog2Cap = kMaxRegionLog2Cap + 1;       // the largest fil
 
 template <int NC>
 __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
-                                                          TableHeader* h, int64_t cap_max, int skip, uint32_t flags) {
+                                                          TableHeader* h, int64_t cap_max, int skip, uint32_t flags,
+                                                          const uint8_t* key_valid) {
   __shared__ uint32_t hist[kRegionBins];
   __shared__ uint32_t loc[kRegionBins];
   __shared__ int64_t ws[kPartBlock / kWave];
@@ -245,12 +268,14 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   }
   if (tid < kRegionBins) hist[tid] = 0;
   __syncthreads();
+  const bool nulls = P.null_cols != 0 || key_valid != nullptr;
   bool ok[kRows];
   uint32_t bin[kRows], rank[kRows];
 #pragma unroll
   for (int i = 0; i < kRows; i++) {
     const uint64_t hh = mulhash(k[i]);
-    ok[i] = (r0 + i < n) && eval_preds<NC>(P, v, i) && in_partition(hh, skip, flags);
+    ok[i] = (r0 + i < n) && build_row_ok<NC>(P, v, i, r0 + i, key_valid, nulls) && in_partition(hh, skip, flags);
+    if (ok[i]) pay[i] = stored_payload(payload, r0 + i, pay[i]);
     bin[i] = (uint32_t)((hh << skip) >> (64 - kLog2Bins));
     rank[i] = ok[i] ? atomicAdd(&hist[bin[i]], 1u) : 0u;
   }
@@ -480,10 +505,11 @@ constexpr int kFallbackBlocks = 16;  // two per XCD; the global-CAS insert, when
 
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_build_fallback(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
-                                                          TableHeader* h, int64_t cap_max) {
+                                                          TableHeader* h, int64_t cap_max, const uint8_t* key_valid) {
   if (h->magic != kTableMagic || !h->ovf) return;
   const int l = h->log2cap, skip = h->skip;
   const uint32_t flags = h->flags;
+  const bool nulls = P.null_cols != 0 || key_valid != nullptr;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     h->regions = 0;
     h->alt = 1;
@@ -502,17 +528,24 @@ __global__ __launch_bounds__(kBlock) void k_build_fallback(RowPlan P, const int6
     load4(kc, r0, fullrow, n, k);
     load4(payload, r0, fullrow, n, pay);
 #pragma unroll
-    for (int i = 0; i < kRows; i++)
-      pend[i] = (r0 + i < n) && eval_preds<NC>(P, v, i) && in_partition(mulhash(k[i]), skip, flags);
+    for (int i = 0; i < kRows; i++) {
+      pend[i] = (r0 + i < n) && build_row_ok<NC>(P, v, i, r0 + i, key_valid, nulls) &&
+                in_partition(mulhash(k[i]), skip, flags);
+      if (pend[i]) pay[i] = stored_payload(payload, r0 + i, pay[i]);
+    }
     table_insert<kRows>(words, slots, l, skip, pend, k, pay);
   }
 }
 
 // ------------------------------------------------------------------ probe
 
+// With NULLs (a validity bitmap on the probe key, on a plan column, or a
+// nullable state): a NULL probe key matches nothing, a predicate over NULL
+// drops the row, a match whose stored payload is INT64_MIN (a NULL build
+// payload) goes to the NULL group, and a sum reading a NULL value skips it.
 template <int MODE, int NC, int NE>
 __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const TableHeader* h, const int64_t* pkeys, int64_t n, RowPlan P,
-                                                         AggTarget T) {
+                                                         AggTarget T, const uint8_t* key_valid) {
   extern __shared__ __align__(16) char smem[];
   if (h->magic != kTableMagic || h->err) return;  // a failed build inserted nothing: no row can match
   if (!state_matches(T)) return;
@@ -531,12 +564,26 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const 
     load_rows<NC>(P, r0, r0 + kPR <= n, n, vn);
     load4(kc, r0, r0 + kPR <= n, n, kn);
   }
+  const bool nulls = P.null_cols != 0 || key_valid != nullptr;
   for (; r0 < n; r0 += step) {
     int64_t k[kPR], e[kPR][NE];
     bool ok[kPR];
+    uint32_t epresent[kPR];  // bit j: sum j reads no NULL value in the row
 #pragma unroll
     for (int i = 0; i < kPR; i++) {
-      ok[i] = (r0 + i < n) && eval_preds<NC>(P, vn, i);
+      epresent[i] = ~0u;
+      if (!nulls) {
+        ok[i] = (r0 + i < n) && eval_preds<NC>(P, vn, i);
+      } else {
+        const uint32_t present = r0 + i < n ? row_present<NC>(P, r0 + i) : 0u;
+        ok[i] = (r0 + i < n) && (!key_valid || bit_at(key_valid, r0 + i)) &&
+                eval_preds_present<NC>(P, vn, i, present);
+#pragma unroll
+        for (int j = 0; j < NE; j++) {
+          const uint32_t ec = j < P.ne ? expr_cols(P.expr[j]) : 0u;
+          if ((present & ec) != ec) epresent[i] &= ~(1u << j);
+        }
+      }
 #pragma unroll
       for (int j = 0; j < NE; j++) e[i][j] = j < P.ne ? eval_expr<NC>(P.expr[j], vn, i) : 0;
       k[i] = kn[i];
@@ -546,8 +593,17 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_probe_agg(const 
         ok, k,
         [&](const bool (&hit)[kPR], const int64_t (&pay)[kPR]) {
 #pragma unroll
-          for (int i = 0; i < kPR; i++)
-            if (hit[i]) agg.add(T, pay[i], e[i], P.ne);
+          for (int i = 0; i < kPR; i++) {
+            if (!hit[i]) continue;
+            if (T.nullable) {
+              // INT64_MIN: a NULL build payload (the NULL group); a present one outside the domain: an error
+              const int64_t g = pay[i] == INT64_MIN ? T.udomain
+                                                    : ((uint64_t)pay[i] < (uint64_t)T.udomain ? pay[i] : -1);
+              agg.add_nullable(T, g, e[i], epresent[i], P.ne);
+            } else {
+              agg.add(T, pay[i], e[i], P.ne);
+            }
+          }
         },
         [&] {
           if (r1 < n) {
@@ -1053,9 +1109,11 @@ tq_status tq_join_table_rows(const void* d_table, int64_t* rows, hipStream_t str
   return TQ_OK;
 }
 
-tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_col payload, int64_t n,
-                        const tq_col* filt, int32_t nfilt, const tq_pred* p, int32_t np, double load_factor,
-                        int32_t skip, uint32_t flags, hipStream_t stream) {
+}  // extern "C"
+
+static tq_status join_build(void* d_table, size_t bytes, const int64_t* d_keys, const uint8_t* key_valid,
+                            tq_col payload, int64_t n, const tq_col* filt, int32_t nfilt, const tq_pred* p, int32_t np,
+                            double load_factor, int32_t skip, uint32_t flags, bool nullable, hipStream_t stream) {
   if (!d_table) return fail(TQ_EINVAL, "table is NULL");
   if (!(load_factor > 0.0 && load_factor <= 0.9)) return fail(TQ_EINVAL, "load factor %g outside (0, 0.9]", load_factor);
   if (skip < 0 || skip > 32) return fail(TQ_EINVAL, "skip %d outside [0, 32]", skip);
@@ -1071,38 +1129,80 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
   if (n > 0 && (!d_keys || !payload.data)) return fail(TQ_EINVAL, "NULL keys or payload");
   if (((uintptr_t)d_keys & 15) || ((uintptr_t)payload.data & 15)) return fail(TQ_EINVAL, "keys/payload not 16-byte aligned");
   if (payload.type != TQ_U8 && payload.type != TQ_I32 && payload.type != TQ_I64) return fail(TQ_EINVAL, "payload type");
+  if (!nullable && (key_valid || payload.valid))
+    return fail(TQ_EINVAL, "validity bitmaps on the key or payload: use tq_join_build_nullable");
   int64_t cap_max = cap_max_for_bytes(bytes);
   if (cap_max == 0) return fail(TQ_EINVAL, "table buffer of %zu bytes is too small", bytes);
   RowPlan P;
-  tq_status s = make_plan(&P, filt, nfilt, p, np, nullptr, 0, nullptr, n);
+  tq_status s = make_plan(&P, filt, nfilt, p, np, nullptr, 0, nullptr, n, nullable);
   if (s) return s;
   TableHeader* h = static_cast<TableHeader*>(d_table);
-  DCol pc = {payload.data, payload.type};
+  DCol pc = {payload.data, payload.type, payload.valid};
   const int64_t part_grid = std::max<int64_t>(1, (n + kPartRows - 1) / kPartRows);
   if (part_grid <= part_grid_max(cap_max)) {
     // the rows' segments fit the scratch area: partition, count, then fill regions (or CAS)
     TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_part<NC>, dim3((int)part_grid), dim3(kPartBlock), 0, stream,
-                                                  P, d_keys, pc, n, h, cap_max, skip, flags));
+                                                  P, d_keys, pc, n, h, cap_max, skip, flags, key_valid));
     hipLaunchKernelGGL(k_build_regions, dim3(kRegionBins), dim3(kFinBlock), 0, stream, h, cap_max, (int)part_grid,
                        load_factor, skip, flags, cap_rule(load_factor));
     // the fallback does nothing unless a region overflowed (rare: keys whose hashes
     // crowd one region); a small grid keeps the launch that finds nothing to do cheap
     // (dispatching hundreds of workgroups that return at once took about 4 us)
     TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_fallback<NC>, dim3(kFallbackBlocks), dim3(kBlock), 0,
-                                                  stream, P, d_keys, pc, n, h, cap_max));
+                                                  stream, P, d_keys, pc, n, h, cap_max, key_valid));
     TQ_HIP(hipGetLastError());
     return TQ_OK;
   }
-  const bool count = (np > 0 || (flags & TQ_SELECT_PARTITION)) && n > 0;
+  const bool count = (np > 0 || (flags & TQ_SELECT_PARTITION) || key_valid) && n > 0;
   Range R = split_rows(std::max<int64_t>(n, 1), kMaxCountBlocks);
   // enough blocks to clear the tags quickly; blocks past the rows count zero
   const int64_t clear_blocks = std::min<int64_t>((cap_max >> kLog2Bucket) / kBlock, kMaxCountBlocks);
   const int count_grid = (int)std::max<int64_t>(R.nblk, clear_blocks);
   TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_count<NC>, dim3(count_grid), dim3(kBlock), 0, stream, P, d_keys, n,
-                                                R.per, h, cap_max, (int)count, skip, flags));
+                                                R.per, h, cap_max, (int)count, skip, flags, key_valid));
   TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_insert<NC>, dim3(stream_grid(n, 8)), dim3(kBlock), 0, stream, P,
                                                 d_keys, pc, n, h, cap_max, count ? (int64_t)-1 : n, R.nblk, load_factor,
-                                                skip, flags));
+                                                skip, flags, key_valid));
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+extern "C" {
+
+tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_col payload, int64_t n,
+                        const tq_col* filt, int32_t nfilt, const tq_pred* p, int32_t np, double load_factor,
+                        int32_t skip, uint32_t flags, hipStream_t stream) {
+  return join_build(d_table, bytes, d_keys, nullptr, payload, n, filt, nfilt, p, np, load_factor, skip, flags, false,
+                    stream);
+}
+
+tq_status tq_join_build_nullable(void* d_table, size_t bytes, const int64_t* d_keys, const uint8_t* d_key_valid,
+                                 tq_col payload, int64_t n, const tq_col* filt, int32_t nfilt, const tq_pred* p,
+                                 int32_t np, double load_factor, int32_t skip, uint32_t flags, hipStream_t stream) {
+  return join_build(d_table, bytes, d_keys, d_key_valid, payload, n, filt, nfilt, p, np, load_factor, skip, flags, true,
+                    stream);
+}
+
+tq_status tq_join_probe_nullable(const void* d_table, const int64_t* d_probe_keys, const uint8_t* d_key_valid,
+                                 int64_t n, const tq_col* cols, int32_t ncol, const tq_pred* p, int32_t np,
+                                 const tq_agg* agg, hipStream_t stream) {
+  if (!d_table) return fail(TQ_EINVAL, "table is NULL");
+  if (!agg) return fail(TQ_EINVAL, "the probe under NULLs aggregates: agg is NULL");
+  if (n < 0) return fail(TQ_EINVAL, "n < 0");
+  if (n > 0 && !d_probe_keys) return fail(TQ_EINVAL, "probe keys are NULL");
+  if ((uintptr_t)d_probe_keys & 15) return fail(TQ_EINVAL, "probe keys not 16-byte aligned");
+  RowPlan P;
+  tq_status s = make_plan(&P, cols, ncol, p, np, agg->sums, agg->nsum, nullptr, n, true);
+  if (s) return s;
+  AggTarget T{};
+  AggMode mode;
+  size_t lds = 0;
+  if ((s = make_target(agg->d_state, agg->domain, agg->nsum, &T, &mode, &lds, agg->nullable != 0))) return s;
+  if (n == 0) return TQ_OK;
+  dim3 grid(agg_grid(n)), block(kAggBlock);
+  TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE,
+                  hipLaunchKernelGGL((k_probe_agg<M, NC, NE>), grid, block, lds, stream,
+                                     static_cast<const TableHeader*>(d_table), d_probe_keys, n, P, T, d_key_valid));
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -1110,6 +1210,7 @@ tq_status tq_join_build(void* d_table, size_t bytes, const int64_t* d_keys, tq_c
 tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_t n, const tq_col* cols, int32_t ncol,
                         const tq_pred* p, int32_t np, int64_t* d_out_probe_row, int64_t* d_out_payload,
                         int64_t capacity, int64_t* d_out_count, const tq_agg* agg, hipStream_t stream) {
+  if (agg && agg->nullable) return fail(TQ_EINVAL, "a nullable group-by state: use tq_join_probe_nullable");
   if (!d_table) return fail(TQ_EINVAL, "table is NULL");
   if (n < 0) return fail(TQ_EINVAL, "n < 0");
   if (n > 0 && !d_probe_keys) return fail(TQ_EINVAL, "probe keys are NULL");
@@ -1174,7 +1275,8 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
     } else {
       dim3 grid(agg_grid(n)), block(kAggBlock);
       TQ_DISPATCH_AGG(mode, P.ncol, agg->nsum, M, NC, NE,
-                      hipLaunchKernelGGL((k_probe_agg<M, NC, NE>), grid, block, lds, stream, h, d_probe_keys, n, P, T));
+                      hipLaunchKernelGGL((k_probe_agg<M, NC, NE>), grid, block, lds, stream, h, d_probe_keys, n, P, T,
+                                         nullptr));
     }
     TQ_HIP(hipGetLastError());
     return TQ_OK;

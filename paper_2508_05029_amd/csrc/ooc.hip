@@ -601,7 +601,7 @@ class Driver {
       return tq_join_probe(s_table, static_cast<const int64_t*>(cols[plan.fact_key_col].data), nrows, cols, ncol, nullptr,
                            0, nullptr, nullptr, 0, nullptr, &s_agg, compute);
     char* src[TQ_MAX_COLS];
-    tq_col pay[TQ_MAX_COLS];
+    tq_col pay[TQ_MAX_COLS] = {};
     void* outp[TQ_MAX_COLS];
     size_t off = 0;
     for (int j = 0; j < fact.ncol; j++) {
@@ -819,7 +819,7 @@ class Driver {
                              plan.log2_fanout, plan.join_flags, compute)))
         return s;
       if (whole && fat > 0) {
-        tq_col cols[TQ_MAX_COLS];
+        tq_col cols[TQ_MAX_COLS] = {};
         int ncols = 0;
         const int jk = fact_map[plan.fact_key_col];
         for (int fc = 0; fc < TQ_MAX_COLS; fc++) {
@@ -839,7 +839,7 @@ class Driver {
       }
       for (ChunkRef& c : fact.parts[q].chunks) {
         if (whole) break;
-        tq_col cols[TQ_MAX_COLS];
+        tq_col cols[TQ_MAX_COLS] = {};
         int ncols = 0;
         for (int fc = 0; fc < TQ_MAX_COLS; fc++) {
           int j = fact_map[fc];

@@ -221,7 +221,7 @@ tq_status tq_pagepool_stream(tq_pagepool* pool, const tq_batch* batches, int64_t
     const int s = (int)(i % nslots);
     char* slot = staging + (size_t)s * slot_bytes;
     TQ_HIP(hipStreamWaitEvent(compute, copied[s], 0));
-    tq_col cols[TQ_MAX_COLS];
+    tq_col cols[TQ_MAX_COLS] = {};
     for (int c = 0; c < b.ncol; c++) {
       cols[c].data = slot + b.col_offset[c];
       cols[c].type = b.col_type[c];

@@ -111,7 +111,11 @@ int agg_grid(int64_t n) {
   return (int)std::max<int64_t>(1, std::min(want, cap));
 }
 
-template <int MODE, int NC>
+// NULLS: a nullable state (T.nullable) and columns that may carry validity
+// bitmaps: a predicate over NULL drops the row, a NULL key goes to the NULL
+// group (key T.udomain), and a sum whose expression reads a NULL value skips
+// the row (entries 1 + 2e and 2 + 2e hold SUM_e and COUNT_e).
+template <int MODE, int NC, bool NULLS>
 __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_groupby(RowPlan P, int64_t n, AggTarget T) {
   extern __shared__ __align__(16) char smem[];
   if (!state_matches(T)) return;
@@ -119,26 +123,54 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_groupby(RowPlan 
   agg.init(T, smem);
   __syncthreads();
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kRows;
+  const uint32_t key_cols = P.key_mask[0] | P.key_mask[1];
   for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRows; r0 < n; r0 += step) {
     int64_t v[NC][kRows];
     load_rows<NC>(P, r0, r0 + kRows <= n, n, v);
     bool ok[kRows], lds[kRows];
     unsigned long long* at[kRows];
+    uint32_t present[kRows];
 #pragma unroll
     for (int i = 0; i < kRows; i++) {
-      ok[i] = r0 + i < n && eval_preds<NC>(P, v, i) && agg.count(T, eval_key<NC>(P, v, i), &at[i], &lds[i]);
+      if constexpr (NULLS) {
+        present[i] = r0 + i < n ? row_present<NC>(P, r0 + i) : 0u;
+        int64_t key = eval_key<NC>(P, v, i);
+        // a NULL key is the NULL group; a present key outside [0, udomain) is an error (-1)
+        key = (present[i] & key_cols) != key_cols ? T.udomain : ((uint64_t)key < (uint64_t)T.udomain ? key : -1);
+        ok[i] = r0 + i < n && eval_preds_present<NC>(P, v, i, present[i]) && agg.count(T, key, &at[i], &lds[i]);
+      } else {
+        present[i] = ~0u;
+        ok[i] = r0 + i < n && eval_preds<NC>(P, v, i) && agg.count(T, eval_key<NC>(P, v, i), &at[i], &lds[i]);
+      }
     }
     // sums one at a time over the tile's rows, so that only one sum's plan
     // constants are live (all of them at once spill into vector lanes)
 #pragma unroll 1
     for (int e = 0; e < P.ne; e++) {
       const DExpr E = P.expr[e];
+      if constexpr (NULLS) {
+        const uint32_t ec = expr_cols(E);
 #pragma unroll
-      for (int i = 0; i < kRows; i++) {
-        if (ok[i]) {
-          const int64_t x = eval_expr<NC>(E, v, i);
-          if (lds[i]) atomicAdd(at[i] + 1 + e, (unsigned long long)x);
-          else global_add(at[i] + 1 + e, x);
+        for (int i = 0; i < kRows; i++) {
+          if (ok[i] && (present[i] & ec) == ec) {
+            const int64_t x = eval_expr<NC>(E, v, i);
+            if (lds[i]) {
+              atomicAdd(at[i] + 1 + 2 * e, (unsigned long long)x);
+              atomicAdd(at[i] + 2 + 2 * e, 1ull);
+            } else {
+              global_add(at[i] + 1 + 2 * e, x);
+              global_add(at[i] + 2 + 2 * e, 1);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kRows; i++) {
+          if (ok[i]) {
+            const int64_t x = eval_expr<NC>(E, v, i);
+            if (lds[i]) atomicAdd(at[i] + 1 + e, (unsigned long long)x);
+            else global_add(at[i] + 1 + e, x);
+          }
         }
       }
     }
@@ -146,7 +178,8 @@ __global__ __launch_bounds__(kAggBlock, kAggBlocksPerCU) void k_groupby(RowPlan 
   agg.flush(T);
 }
 
-__global__ void k_state_init(StateHeader* h, int64_t domain, int32_t nsum, int32_t rows, int64_t entries) {
+__global__ void k_state_init(StateHeader* h, int64_t domain, int32_t nsum, int32_t rows, int64_t entries,
+                             int32_t nullable) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     h->magic = kStateMagic;
     h->err = 0;
@@ -154,6 +187,7 @@ __global__ void k_state_init(StateHeader* h, int64_t domain, int32_t nsum, int32
     h->nsum = nsum;
     h->rows = rows;
     h->used = 0;
+    h->nullable = nullable;
   }
   int64_t* d = state_data(h);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < entries; i += (int64_t)gridDim.x * blockDim.x)
@@ -166,14 +200,27 @@ constexpr int kFinBlock = 1024;
 // With `reset`, every partial read is zeroed right after (the same thread, so
 // the store follows its load) and the count of used private rows goes to 0:
 // the state is then as tq_groupby_init leaves it, its error word aside.
+// With a nullable state, sum j of a group is SUM_j over COUNT_j rows (entries
+// 1 + 2j and 2 + 2j): d_sums gets SUM_j, d_nonnull COUNT_j, d_avg SUM_j /
+// COUNT_j (0 when COUNT_j is 0), and the last group is the NULL key's.
 __global__ __launch_bounds__(kFinBlock) void k_finalize(StateHeader* h, int64_t* keys, int64_t* count,
-                                                        int64_t* sums, double* avg, int64_t* ngroups, int reset) {
+                                                        int64_t* sums, double* avg, int64_t* ngroups, int reset,
+                                                        int64_t* nonnull) {
   __shared__ uint32_t wave_tot[kFinBlock / kWave];
   __shared__ int64_t fold[kPrivateRowsMaxEntries];
   __shared__ int64_t base_s;
   if (h->magic != kStateMagic) return;
+  if ((h->nullable != 0) != (nonnull != nullptr)) {  // the finalize call does not fit the state
+    if (threadIdx.x == 0) {
+      latch_error(&h->err, TQ_EINVAL);
+      *ngroups = 0;
+    }
+    return;
+  }
   const int64_t domain = h->domain;
-  const int nsum = h->nsum, stride = 1 + nsum, rows = h->rows;
+  const int stride = 1 + h->nsum, rows = h->rows;
+  const bool nl = h->nullable != 0;
+  const int nsum = nl ? h->nsum / 2 : h->nsum;  // the caller's sums
   int64_t* d = state_data(h);
   const int entries = (int)(domain * stride);
   if (rows > 1) {
@@ -235,11 +282,23 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(StateHeader* h, int64_t*
       int64_t g = off + pre;
       keys[g] = k;
       count[g] = e[0];
+      if (nl) {
 #pragma unroll
-      for (int j = 0; j < TQ_MAX_SUMS; j++) {
-        if (j < nsum) {
-          sums[g * nsum + j] = e[1 + j];
-          if (avg) avg[g * nsum + j] = (double)e[1 + j] / (double)e[0];
+        for (int j = 0; j < kMaxNullableSums; j++) {
+          if (j < nsum) {
+            const int64_t sj = e[1 + 2 * j], cj = e[2 + 2 * j];
+            sums[g * nsum + j] = cj ? sj : 0;
+            nonnull[g * nsum + j] = cj;
+            if (avg) avg[g * nsum + j] = cj ? (double)sj / (double)cj : 0.0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < TQ_MAX_SUMS; j++) {
+          if (j < nsum) {
+            sums[g * nsum + j] = e[1 + j];
+            if (avg) avg[g * nsum + j] = (double)e[1 + j] / (double)e[0];
+          }
         }
       }
     }
@@ -282,17 +341,21 @@ __global__ __launch_bounds__(kBlock) void k_fill(v4i32* dst, int64_t n16, uint32
     __builtin_nontemporal_store(v, dst + i);
 }
 
-tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T, AggMode* mode, size_t* lds) {
+tq_status make_target(void* d_state, int64_t domain, int32_t nsum, AggTarget* T, AggMode* mode, size_t* lds,
+                      bool nullable) {
   if (!d_state) return fail(TQ_EINVAL, "group-by state is NULL");
   if (domain <= 0 || domain > ((int64_t)1 << 31)) return fail(TQ_EINVAL, "domain %lld outside [1, 2^31]", (long long)domain);
-  if (nsum < 0 || nsum > TQ_MAX_SUMS) return fail(TQ_EINVAL, "nsum %d outside [0, %d]", nsum, TQ_MAX_SUMS);
+  const int max_sums = nullable ? kMaxNullableSums : TQ_MAX_SUMS;
+  if (nsum < 0 || nsum > max_sums) return fail(TQ_EINVAL, "nsum %d outside [0, %d]", nsum, max_sums);
   T->hdr = static_cast<const StateHeader*>(d_state);
   T->data = state_data(d_state);
   T->err = &static_cast<StateHeader*>(d_state)->err;
-  T->domain = domain;
-  T->stride = 1 + nsum;
-  T->rows = state_rows(domain, 1 + nsum);
-  *mode = agg_mode(domain, 1 + nsum, &T->log2hcap, lds);
+  T->nullable = nullable ? 1 : 0;
+  T->udomain = domain;
+  T->domain = nullable ? domain + 1 : domain;  // the NULL group follows the keys
+  T->stride = nullable ? 1 + 2 * nsum : 1 + nsum;
+  T->rows = state_rows(T->domain, T->stride);
+  *mode = agg_mode(T->domain, T->stride, &T->log2hcap, lds);
   return TQ_OK;
 }
 
@@ -341,18 +404,61 @@ size_t tq_groupby_state_bytes(int64_t domain, int32_t nsum) {
   return kHeaderBytes + (size_t)state_rows(domain, stride) * (size_t)domain * stride * 8;
 }
 
-tq_status tq_groupby_init(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream) {
+static tq_status init_state(void* d_state, size_t bytes, int64_t domain, int32_t nsum, bool nullable,
+                            hipStream_t stream) {
   if (!d_state) return fail(TQ_EINVAL, "state is NULL");
   if (domain <= 0 || domain > (int64_t)1 << 31) return fail(TQ_EINVAL, "domain %lld outside [1, 2^31]", (long long)domain);
-  if (nsum < 0 || nsum > TQ_MAX_SUMS) return fail(TQ_EINVAL, "nsum %d outside [0, %d]", nsum, TQ_MAX_SUMS);
-  size_t need = tq_groupby_state_bytes(domain, nsum);
+  const int max_sums = nullable ? kMaxNullableSums : TQ_MAX_SUMS;
+  if (nsum < 0 || nsum > max_sums) return fail(TQ_EINVAL, "nsum %d outside [0, %d]", nsum, max_sums);
+  size_t need = nullable ? tq_groupby_state_bytes_nullable(domain, nsum) : tq_groupby_state_bytes(domain, nsum);
   if (bytes < need) return fail(TQ_EINVAL, "state buffer has %zu bytes, needs %zu", bytes, need);
-  int stride = 1 + nsum;
-  int rows = state_rows(domain, stride);
-  int64_t entries = (int64_t)rows * domain * stride;
+  const int64_t groups = nullable ? domain + 1 : domain;  // the NULL group follows the keys
+  const int32_t entry_sums = nullable ? 2 * nsum : nsum;   // SUM_j and COUNT_j per sum
+  int stride = 1 + entry_sums;
+  int rows = state_rows(groups, stride);
+  int64_t entries = (int64_t)rows * groups * stride;
   int blocks = (int)std::min<int64_t>((entries + kBlock - 1) / kBlock, 1024);
-  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(kBlock), 0, stream, static_cast<StateHeader*>(d_state), domain,
-                     nsum, rows, entries);
+  hipLaunchKernelGGL(k_state_init, dim3(blocks), dim3(kBlock), 0, stream, static_cast<StateHeader*>(d_state), groups,
+                     entry_sums, rows, entries, nullable ? 1 : 0);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+tq_status tq_groupby_init(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream) {
+  return init_state(d_state, bytes, domain, nsum, false, stream);
+}
+
+size_t tq_groupby_state_bytes_nullable(int64_t domain, int32_t nsum) {
+  if (domain <= 0 || domain >= ((int64_t)1 << 31) || nsum < 0 || nsum > kMaxNullableSums) return 0;
+  const int stride = 1 + 2 * nsum;
+  return kHeaderBytes + (size_t)state_rows(domain + 1, stride) * (size_t)(domain + 1) * stride * 8;
+}
+
+tq_status tq_groupby_init_nullable(void* d_state, size_t bytes, int64_t domain, int32_t nsum, hipStream_t stream) {
+  return init_state(d_state, bytes, domain, nsum, true, stream);
+}
+
+static tq_status groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_t ncol, int64_t nrows,
+                             const tq_pred* p, int32_t np, const tq_gkey* key, const tq_expr* sums, int32_t nsum,
+                             bool nullable, hipStream_t stream) {
+  if (!key) return fail(TQ_EINVAL, "group key is NULL");
+  if (nullable && key->ncol != 1) return fail(TQ_EINVAL, "a group key that may be NULL has one column");
+  RowPlan P;
+  tq_status s = make_plan(&P, in, ncol, p, np, sums, nsum, key, nrows, nullable);
+  if (s) return s;
+  AggTarget T;
+  AggMode mode;
+  size_t lds;
+  if ((s = make_target(d_state, domain, nsum, &T, &mode, &lds, nullable))) return s;
+  if (nrows == 0) return TQ_OK;
+  dim3 grid(agg_grid(nrows)), block(kAggBlock);
+  // (the sums are evaluated one at a time: the kernel does not depend on their count)
+  if (nullable)
+    TQ_DISPATCH_AGG(mode, P.ncol, nsum, M, NC, NE, (void)NE;
+                    hipLaunchKernelGGL((k_groupby<M, NC, true>), grid, block, lds, stream, P, nrows, T));
+  else
+    TQ_DISPATCH_AGG(mode, P.ncol, nsum, M, NC, NE, (void)NE;
+                    hipLaunchKernelGGL((k_groupby<M, NC, false>), grid, block, lds, stream, P, nrows, T));
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -360,19 +466,22 @@ tq_status tq_groupby_init(void* d_state, size_t bytes, int64_t domain, int32_t n
 tq_status tq_groupby_agg(void* d_state, int64_t domain, const tq_col* in, int32_t ncol, int64_t nrows,
                          const tq_pred* p, int32_t np, const tq_gkey* key, const tq_expr* sums, int32_t nsum,
                          hipStream_t stream) {
-  if (!key) return fail(TQ_EINVAL, "group key is NULL");
-  RowPlan P;
-  tq_status s = make_plan(&P, in, ncol, p, np, sums, nsum, key, nrows);
-  if (s) return s;
-  AggTarget T;
-  AggMode mode;
-  size_t lds;
-  if ((s = make_target(d_state, domain, nsum, &T, &mode, &lds))) return s;
-  if (nrows == 0) return TQ_OK;
-  dim3 grid(agg_grid(nrows)), block(kAggBlock);
-  // (the sums are evaluated one at a time: the kernel does not depend on their count)
-  TQ_DISPATCH_AGG(mode, P.ncol, nsum, M, NC, NE, (void)NE;
-                  hipLaunchKernelGGL((k_groupby<M, NC>), grid, block, lds, stream, P, nrows, T));
+  return groupby_agg(d_state, domain, in, ncol, nrows, p, np, key, sums, nsum, false, stream);
+}
+
+tq_status tq_groupby_agg_nullable(void* d_state, int64_t domain, const tq_col* in, int32_t ncol, int64_t nrows,
+                                  const tq_pred* p, int32_t np, const tq_gkey* key, const tq_expr* sums, int32_t nsum,
+                                  hipStream_t stream) {
+  return groupby_agg(d_state, domain, in, ncol, nrows, p, np, key, sums, nsum, true, stream);
+}
+
+tq_status tq_groupby_finalize_nullable(const void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums,
+                                       int64_t* d_nonnull, double* d_avg, int64_t* d_ngroups, hipStream_t stream) {
+  if (!d_state) return fail(TQ_EINVAL, "group-by state is NULL");
+  if (!d_keys || !d_count || !d_ngroups || !d_sums || !d_nonnull) return fail(TQ_EINVAL, "NULL output");
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, stream,
+                     static_cast<StateHeader*>(const_cast<void*>(d_state)), d_keys, d_count, d_sums, d_avg, d_ngroups,
+                     0, d_nonnull);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -383,7 +492,7 @@ tq_status tq_groupby_finalize(const void* d_state, int64_t* d_keys, int64_t* d_c
   if (!d_keys || !d_count || !d_ngroups || !d_sums) return fail(TQ_EINVAL, "NULL output");
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, stream,
                      static_cast<StateHeader*>(const_cast<void*>(d_state)), d_keys, d_count, d_sums, d_avg, d_ngroups,
-                     0);
+                     0, nullptr);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -393,7 +502,7 @@ tq_status tq_groupby_finalize_reset(void* d_state, int64_t* d_keys, int64_t* d_c
   if (!d_state) return fail(TQ_EINVAL, "group-by state is NULL");
   if (!d_keys || !d_count || !d_ngroups || !d_sums) return fail(TQ_EINVAL, "NULL output");
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, stream, static_cast<StateHeader*>(d_state), d_keys,
-                     d_count, d_sums, d_avg, d_ngroups, 1);
+                     d_count, d_sums, d_avg, d_ngroups, 1, nullptr);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }

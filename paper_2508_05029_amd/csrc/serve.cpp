@@ -187,7 +187,7 @@ struct Server {
   static tq_status on_batch(void* user, int64_t, const tq_col* cols, int32_t, int64_t nrows, hipStream_t compute) {
     auto* c = static_cast<ProbeCtx*>(user);
     const tq_serve_tables& T = c->s->T;
-    tq_col fc[4];
+    tq_col fc[4] = {};
     for (int j = 0; j < T.fact_ncol; j++) fc[j] = cols[T.fact_map[j]];
     return tq_join_probe(c->table, static_cast<const int64_t*>(fc[0].data), nrows, fc, T.fact_ncol, nullptr, 0, nullptr,
                          nullptr, 0, nullptr, &c->agg, compute);
@@ -209,14 +209,14 @@ struct Server {
     tq_status s;
     if ((s = tq_groupby_init(state, p.state_bytes, p.domain, p.nsum, compute))) return s;
     if (q.shape == 0) {
-      tq_col w[TQ_MAX_COLS];
+      tq_col w[TQ_MAX_COLS] = {};
       for (int c = 0; c < T.fg_ncol; c++) w[c] = window(T.fg_cols[c], q.fact_first);
       if ((s = tq_groupby_agg(state, p.domain, w, T.fg_ncol, q.n_fact, T.fg_preds, T.fg_np, &T.fg_key, T.fg_sums,
                               T.fg_nsum, compute)))
         return s;
     } else {
       void* table = base + p.table;
-      tq_col dw[4];
+      tq_col dw[4] = {};
       for (int c = 0; c < T.dim_ncol; c++) dw[c] = window(T.dim_cols[c], q.dim_first);
       if ((s = tq_join_table_init(table, p.table_bytes, compute))) return s;
       tq_agg agg{state, p.domain, T.join_sums, T.join_nsum};
@@ -239,7 +239,7 @@ struct Server {
           if (t) return t;
         }
         if (q.shape == 1) {
-          tq_col fw[4];
+          tq_col fw[4] = {};
           for (int c = 0; c < T.fact_ncol; c++) fw[c] = window(T.fact_cols[c], q.fact_first);
           if ((s = tq_join_probe(table, static_cast<const int64_t*>(fw[0].data), q.n_fact, fw, T.fact_ncol, nullptr, 0,
                                  nullptr, nullptr, 0, nullptr, &agg, compute)))

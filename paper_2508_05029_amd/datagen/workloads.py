@@ -9,6 +9,7 @@ value ranges and join shapes that the five workload descriptions fix:
   ooc_join_agg     600M-row fact / 150M-row dimension streamed from pinned pages
   batched          4,096 uneven join+group-by instances, Zipf(1.1) group skew
   serving          Poisson arrivals of requests of the three shapes above
+  string keys      dictionary-encoded string join keys (two dictionaries)
 
 A query is described by predicates (inclusive integer ranges, conjunctive),
 product expressions of affine factors, and a group key. The descriptions are
@@ -265,3 +266,52 @@ def serving_requests(count: int, qps: float, seed: int = SERVE_SEED, fact_lo: fl
     gaps = exponential(count, qps, seed, 2)
     t = np.cumsum(gaps)
     return [Request(i, int(shapes[i]), int(nf[i]), float(t[i])) for i in range(count)]
+
+
+# ---------------------------------------------------------------------------
+# dictionary-encoded string keys
+
+def strings_of(ids: np.ndarray, seed: int, stream: int, max_prefix: int = 20) -> Tuple[np.ndarray, np.ndarray]:
+    """Arrow string column (int32 offsets, uint8 bytes) for entity ids: a
+    lower-case prefix of 0..max_prefix letters drawn per id, '#', then the id
+    in decimal. Distinct ids give distinct strings (the text after the last
+    '#' is the id); equal ids give equal strings. Lengths 2..max_prefix + 20."""
+    ids = np.asarray(ids, dtype=np.int64)
+    n = len(ids)
+    # draws indexed by id (not by position), so one id always spells one string
+    top = int(ids.max()) + 1 if n else 1
+    plen = uniform(top, 0, max_prefix, np.int64, seed, stream)
+    letters = uniform(top * max_prefix, 97, 122, np.uint8, seed, stream + 1).reshape(top, max_prefix) \
+        if max_prefix else np.zeros((top, 0), np.uint8)
+    parts = [letters[x, :plen[x]].tobytes() + b"#" + str(x).encode() for x in ids.tolist()]
+    offsets = np.zeros(n + 1, np.int32)
+    offsets[1:] = np.cumsum([len(b) for b in parts], dtype=np.int64)
+    data = np.frombuffer(b"".join(parts), dtype=np.uint8).copy() if n else np.zeros(0, np.uint8)
+    return offsets, data
+
+
+@dataclass
+class StringJoinTables:
+    build_dict: Tuple[np.ndarray, np.ndarray]  # distinct strings
+    probe_dict: Tuple[np.ndarray, np.ndarray]  # distinct strings, a quarter of them absent from build_dict
+    dim: Dict[str, np.ndarray]                 # key: int32 codes into build_dict (one row per entry)
+    fact: Dict[str, np.ndarray]                # fk: int32 codes into probe_dict
+
+
+def string_join_tables(n_dim: int, n_fact: int, seed: int = SEED_BASE + 5,
+                       groups: int = 25) -> StringJoinTables:
+    """join_agg's shape with string keys encoded against two dictionaries. The
+    build dictionary spells entity ids [0, n_dim) in a keyed order, the probe
+    dictionary ids [n_dim / 4, n_dim * 5 / 4) in another, so a quarter of the
+    probe entries match nothing; the dimension's key codes are a permutation
+    of the build dictionary, the fact's uniform over the probe dictionary."""
+    q = n_dim // 4
+    bids = permutation(n_dim, seed, 0)
+    pids = permutation(n_dim, seed, 1) + q
+    d = {"key": permutation(n_dim, seed, 2).astype(np.int32),
+         "group": uniform(n_dim, 0, groups - 1, np.int32, seed, 3),
+         "date": uniform(n_dim, 0, 2405, np.int32, seed, 4)}
+    f = {"fk": uniform(n_fact, 0, max(n_dim - 1, 0), np.int32, seed, 5),
+         "price": uniform(n_fact, 90_000, 10_500_000, np.int64, seed, 6),
+         "disc": uniform(n_fact, 0, 10, np.int64, seed, 7)}
+    return StringJoinTables(strings_of(bids, seed, 8), strings_of(pids, seed, 8), d, f)

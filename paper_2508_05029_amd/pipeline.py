@@ -441,3 +441,141 @@ class ServingSetup:
                 nd = max(1, min(n // 4, self.n_dim))
                 q.dim_first, q.n_dim = int(rng.integers(0, self.n_dim - nd + 1)) // 16 * 16, nd
         return out
+
+
+class NullableGroupByResult:
+    """Outputs of tq_groupby_finalize_nullable: domain + 1 groups (the last key is NULL)."""
+
+    def __init__(self, domain: int, nsum: int, device):
+        g = domain + 1
+        self.domain = domain
+        self.keys = torch.empty(g, dtype=torch.int64, device=device)
+        self.count = torch.empty(g, dtype=torch.int64, device=device)
+        self.sums = torch.empty(g * max(nsum, 1), dtype=torch.int64, device=device)
+        self.nonnull = torch.empty(g * max(nsum, 1), dtype=torch.int64, device=device)
+        self.avg = torch.empty(g * max(nsum, 1), dtype=torch.float64, device=device)
+        self.ngroups = torch.zeros(1, dtype=torch.int64, device=device)
+        self.nsum = nsum
+
+    def host(self) -> dict:
+        g = int(self.ngroups.item())
+        k = self.keys[:g].cpu().numpy()
+        ns = self.nsum
+        return {"keys": np.where(k == self.domain, 0, k), "key_null": k == self.domain,
+                "count": self.count[:g].cpu().numpy(),
+                "sums": self.sums[: g * ns].cpu().numpy().reshape(g, ns),
+                "nonnull": self.nonnull[: g * ns].cpu().numpy().reshape(g, ns),
+                "avg": self.avg[: g * ns].cpu().numpy().reshape(g, ns)}
+
+
+class NullableFilterGroupBy:
+    """sigma + pi + gamma under NULL semantics (one key column). `valid` maps a
+    column name to a device validity bitmap (uint8 tensor); others have no NULLs."""
+
+    def __init__(self, query, device="cuda"):
+        assert len(query.key.cols) == 1
+        self.q = query
+        self.names = referenced(query.preds, query.sums, query.key.cols)
+        self.preds = plan_preds(self.names, query.preds)
+        self.exprs = plan_exprs(self.names, query.sums)
+        self.key = tq.gkey([_col_index(self.names, query.key.cols[0])], 1)
+        self.domain = query.key.domain
+        self.nsum = len(query.sums)
+        self.state = torch.empty(tq.groupby_state_bytes_nullable(self.domain, self.nsum), dtype=torch.uint8,
+                                 device=device)
+        self.out = NullableGroupByResult(self.domain, self.nsum, device)
+
+    def run(self, table, valid, nrows=None, stream=None):
+        cols = [table[c] for c in self.names]
+        vals = [valid.get(c) if valid else None for c in self.names]
+        n = cols[0].numel() if nrows is None else nrows
+        tq.groupby_init_nullable(self.state, self.domain, self.nsum, stream)
+        tq.groupby_agg_nullable(self.state, self.domain, cols, vals, n, self.preds, self.key, self.exprs, stream)
+        o = self.out
+        tq.groupby_finalize_nullable(self.state, o.keys, o.count, o.sums, o.nonnull, o.avg, o.ngroups, stream)
+
+    def result(self, stream=None) -> dict:
+        tq.check(self.state, stream)
+        return self.out.host()
+
+
+class NullableJoinAgg:
+    """join + aggregate under NULL semantics: NULL keys match nothing, a NULL
+    build payload is the NULL group, a NULL probe value skips the sums reading it."""
+
+    def __init__(self, query, n_build_max: int, load_factor: float = 0.5, device="cuda", unique: bool = True):
+        self.q = query
+        self.lf = load_factor
+        self.flags = tq.TQ_UNIQUE_KEYS if unique else 0
+        self.bnames = referenced(query.build_preds, [])
+        self.bpreds = plan_preds(self.bnames, query.build_preds)
+        self.pnames = referenced(query.probe_preds, query.sums)
+        self.ppreds = plan_preds(self.pnames, query.probe_preds)
+        self.exprs = plan_exprs(self.pnames, query.sums)
+        self.domain = query.domain
+        self.nsum = len(query.sums)
+        self.table = torch.empty(tq.join_table_bytes(n_build_max, load_factor), dtype=torch.uint8, device=device)
+        tq.join_table_init(self.table)
+        self.state = torch.empty(tq.groupby_state_bytes_nullable(self.domain, self.nsum), dtype=torch.uint8,
+                                 device=device)
+        self.out = NullableGroupByResult(self.domain, self.nsum, device)
+
+    def run(self, dim, dvalid, fact, fvalid, stream=None):
+        dv = dvalid or {}
+        fv = fvalid or {}
+        q = self.q
+        keys = dim[q.build_key]
+        tq.groupby_init_nullable(self.state, self.domain, self.nsum, stream)
+        tq.join_build_nullable(self.table, keys, dv.get(q.build_key), dim[q.build_payload], dv.get(q.build_payload),
+                               keys.numel(), [dim[c] for c in self.bnames], [dv.get(c) for c in self.bnames],
+                               self.bpreds, self.lf, 0, self.flags, stream)
+        pk = fact[q.probe_key]
+        tq.join_probe_nullable(self.table, pk, fv.get(q.probe_key), pk.numel(), [fact[c] for c in self.pnames],
+                               [fv.get(c) for c in self.pnames], self.ppreds, (self.state, self.domain, self.exprs),
+                               stream)
+        o = self.out
+        tq.groupby_finalize_nullable(self.state, o.keys, o.count, o.sums, o.nonnull, o.avg, o.ngroups, stream)
+
+    def result(self, stream=None) -> dict:
+        tq.check(self.table, stream)
+        tq.check(self.state, stream)
+        r = self.out.host()
+        r["join_rows"] = int(r["count"].sum())
+        return r
+
+
+class StringJoinAgg:
+    """join + aggregate on a dictionary-encoded string key. The dimension's key
+    column holds int32 codes into `build_dict`, the fact's into `probe_dict`
+    (each an (offsets, data) pair of device tensors; the build dictionary's
+    entries are distinct). tq_dict_unify maps the probe dictionary onto the
+    build one, tq_dict_keys turns both code columns into int64 join keys, and
+    the join runs as NullableJoinAgg (NULL codes match nothing)."""
+
+    def __init__(self, query, n_build_max: int, n_probe_max: int, n_build_dict_max: int, n_probe_dict_max: int,
+                 load_factor: float = 0.5, device="cuda"):
+        self.q = query
+        self.join = NullableJoinAgg(query, n_build_max, load_factor, device)
+        self.dtable = torch.empty(tq.join_table_bytes(max(n_build_dict_max, 1), 0.5), dtype=torch.uint8,
+                                  device=device)
+        self.scratch = torch.empty(tq.dict_unify_scratch_bytes(n_build_dict_max), dtype=torch.uint8, device=device)
+        self.remap = torch.empty(max(n_probe_dict_max, 1), dtype=torch.int32, device=device)
+        self.bkeys = torch.empty(max(n_build_max, 1), dtype=torch.int64, device=device)
+        self.pkeys = torch.empty(max(n_probe_max, 1), dtype=torch.int64, device=device)
+
+    def run(self, build_dict, probe_dict, dim, dvalid, fact, fvalid, stream=None):
+        q = self.q
+        dv, fv = dvalid or {}, fvalid or {}
+        npd = probe_dict[0].numel() - 1
+        remap = self.remap[:npd]
+        tq.dict_unify(self.dtable, build_dict, probe_dict, self.scratch, remap, stream)
+        nb = dim[q.build_key].numel()
+        nf = fact[q.probe_key].numel()
+        bk, pk = self.bkeys[:nb], self.pkeys[:nf]
+        tq.dict_keys(dim[q.build_key], dv.get(q.build_key), nb, None, bk, stream)
+        tq.dict_keys(fact[q.probe_key], fv.get(q.probe_key), nf, remap, pk, stream)
+        self.join.run(dict(dim, **{q.build_key: bk}), dv, dict(fact, **{q.probe_key: pk}), fv, stream)
+
+    def result(self, stream=None) -> dict:
+        tq.check(self.dtable, stream)
+        return self.join.result(stream)

@@ -36,7 +36,13 @@ class TqError(RuntimeError):
 
 
 class Col(ctypes.Structure):
-    _fields_ = [("data", ctypes.c_void_p), ("type", ctypes.c_int32)]
+    # valid: a validity bitmap (bit r of byte r // 8, least significant first; 1 = present) or None
+    _fields_ = [("data", ctypes.c_void_p), ("type", ctypes.c_int32), ("valid", ctypes.c_void_p)]
+
+
+class Strings(ctypes.Structure):
+    # Arrow string column: string i is data[offsets[i]:offsets[i + 1]] (int32 offsets, n + 1 of them)
+    _fields_ = [("offsets", ctypes.c_void_p), ("data", ctypes.c_void_p), ("n", ctypes.c_int64)]
 
 
 class PredS(ctypes.Structure):
@@ -57,7 +63,7 @@ class GKey(ctypes.Structure):
 
 class Agg(ctypes.Structure):
     _fields_ = [("d_state", ctypes.c_void_p), ("domain", ctypes.c_int64), ("sums", ctypes.POINTER(ExprS)),
-                ("nsum", ctypes.c_int32)]
+                ("nsum", ctypes.c_int32), ("nullable", ctypes.c_int32)]
 
 
 _vp, _i64, _i32, _u32, _sz, _f64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
@@ -91,6 +97,16 @@ def lib():
             "tq_groupby_agg": (_i32, [_vp, _i64, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp]),
             "tq_groupby_finalize": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tq_groupby_finalize_reset": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tq_groupby_state_bytes_nullable": (_sz, [_i64, _i32]),
+            "tq_groupby_init_nullable": (_i32, [_vp, _sz, _i64, _i32, _vp]),
+            "tq_groupby_agg_nullable": (_i32, [_vp, _i64, _vp, _i32, _i64, _vp, _i32, _vp, _vp, _i32, _vp]),
+            "tq_groupby_finalize_nullable": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tq_join_build_nullable": (_i32, [_vp, _sz, _vp, _vp, Col, _i64, _vp, _i32, _vp, _i32, _f64, _i32, _u32,
+                                              _vp]),
+            "tq_join_probe_nullable": (_i32, [_vp, _vp, _vp, _i64, _vp, _i32, _vp, _i32, _vp, _vp]),
+            "tq_dict_unify_scratch_bytes": (_sz, [_i64]),
+            "tq_dict_unify": (_i32, [_vp, _sz, Strings, Strings, _vp, _sz, _vp, _vp]),
+            "tq_dict_keys": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
             "tq_check": (_i32, [_vp, _vp]),
             "tq_read_peak_scratch_bytes": (_sz, []),
             "tq_read_peak": (_i32, [_vp, _sz, _vp, _vp]),
@@ -122,16 +138,19 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
 _TYPE = {torch.uint8: TQ_U8, torch.int32: TQ_I32, torch.int64: TQ_I64}
 
 
-def cols(tensors: Sequence[torch.Tensor]):
+def cols(tensors: Sequence[torch.Tensor], valid: Optional[Sequence[Optional[torch.Tensor]]] = None):
+    """Column descriptors; valid[i]: a uint8 validity bitmap tensor for column i, or None."""
     arr = (Col * max(1, len(tensors)))()
     for i, t in enumerate(tensors):
         arr[i].data = t.data_ptr()
         arr[i].type = _TYPE[t.dtype]
+        if valid is not None and valid[i] is not None:
+            arr[i].valid = valid[i].data_ptr()
     return arr
 
 
-def col(t: torch.Tensor) -> Col:
-    return Col(t.data_ptr(), _TYPE[t.dtype])
+def col(t: torch.Tensor, valid: Optional[torch.Tensor] = None) -> Col:
+    return Col(t.data_ptr(), _TYPE[t.dtype], None if valid is None else valid.data_ptr())
 
 
 def preds(ps: Sequence[tuple]):
@@ -255,6 +274,63 @@ def groupby_finalize(state, keys, count, sums, avg, ngroups, stream=None, reset=
     fn = lib().tq_groupby_finalize_reset if reset else lib().tq_groupby_finalize
     _check(fn(state.data_ptr(), keys.data_ptr(), count.data_ptr(), sums.data_ptr(), _ptr(avg), ngroups.data_ptr(),
               _stream(stream)))
+
+
+def groupby_state_bytes_nullable(domain: int, nsum: int) -> int:
+    return lib().tq_groupby_state_bytes_nullable(domain, nsum)
+
+
+def groupby_init_nullable(state, domain, nsum, stream=None):
+    _check(lib().tq_groupby_init_nullable(state.data_ptr(), _nbytes(state), domain, nsum, _stream(stream)))
+
+
+def groupby_agg_nullable(state, domain, in_cols, in_valid, nrows, ps, key: GKey, es, stream=None):
+    """in_valid[i]: validity bitmap tensor of column i or None."""
+    _check(lib().tq_groupby_agg_nullable(state.data_ptr(), domain, cols(in_cols, in_valid), len(in_cols), nrows,
+                                         preds(ps), len(ps), ctypes.byref(key), exprs(es), len(es), _stream(stream)))
+
+
+def groupby_finalize_nullable(state, keys, count, sums, nonnull, avg, ngroups, stream=None):
+    _check(lib().tq_groupby_finalize_nullable(state.data_ptr(), keys.data_ptr(), count.data_ptr(), sums.data_ptr(),
+                                              nonnull.data_ptr(), _ptr(avg), ngroups.data_ptr(), _stream(stream)))
+
+
+def join_build_nullable(table, keys, key_valid, payload, payload_valid, n, filt_cols=(), filt_valid=None, ps=(),
+                        load_factor=0.5, skip=0, flags=0, stream=None):
+    _check(lib().tq_join_build_nullable(table.data_ptr(), _nbytes(table), _ptr(keys), _ptr(key_valid),
+                                        col(payload, payload_valid), n, cols(filt_cols, filt_valid), len(filt_cols),
+                                        preds(ps), len(ps), load_factor, skip, flags, _stream(stream)))
+
+
+def join_probe_nullable(table, probe_keys, key_valid, n, probe_cols, probe_valid, ps, agg, stream=None):
+    """agg: (nullable state, domain, exprs)."""
+    state, domain, es = agg
+    E = exprs(es)
+    A = Agg(state.data_ptr(), domain, ctypes.cast(E, ctypes.POINTER(ExprS)), len(es), 1)
+    _check(lib().tq_join_probe_nullable(table.data_ptr(), _ptr(probe_keys), _ptr(key_valid), n,
+                                        cols(probe_cols, probe_valid), len(probe_cols), preds(ps), len(ps),
+                                        ctypes.byref(A), _stream(stream)))
+
+
+def strings(offsets: torch.Tensor, data: torch.Tensor) -> Strings:
+    assert offsets.dtype == torch.int32 and data.dtype == torch.uint8
+    return Strings(offsets.data_ptr(), data.data_ptr(), offsets.numel() - 1)
+
+
+def dict_unify_scratch_bytes(n_build: int) -> int:
+    return lib().tq_dict_unify_scratch_bytes(n_build)
+
+
+def dict_unify(table, build, probe, scratch, remap, stream=None):
+    """build/probe: (offsets, data) tensor pairs; remap: int32 tensor of probe.n entries."""
+    b, p = strings(*build), strings(*probe)
+    _check(lib().tq_dict_unify(table.data_ptr(), table.numel(), b, p, scratch.data_ptr(), scratch.numel(),
+                               _ptr(remap), _stream(stream)))
+
+
+def dict_keys(codes, valid, n, remap, keys, stream=None):
+    nr = 0 if remap is None else remap.numel()
+    _check(lib().tq_dict_keys(codes.data_ptr(), _ptr(valid), n, _ptr(remap), nr, keys.data_ptr(), _stream(stream)))
 
 
 def check(obj, stream=None):

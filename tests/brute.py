@@ -78,3 +78,82 @@ def brute_partition_id(key: int, bits: int) -> int:
     if bits == 0:
         return 0
     return ((int(key) % M64) * PHI % M64) >> (64 - bits)
+
+
+# ---------------------------------------------------------------- NULLs
+# Columns here are Python lists whose NULL entries are None (no bitmaps), and
+# SQL's rules are applied row by row: a predicate over None is not true, a
+# product with a None factor is None, SUM/COUNT(e)/AVG skip None, COUNT(*) does
+# not, None group keys form one group (sorted last), None join keys match
+# nothing.
+
+def brute_filter_nulls(cols, preds, n):
+    out = []
+    for r in range(n):
+        ok = True
+        for (name, lo, hi) in preds:
+            v = cols[name][r]
+            if v is None or not (lo <= int(v) <= hi):
+                ok = False
+        out.append(ok)
+    return out
+
+
+def brute_expr_nulls(cols, expr, r):
+    v = 1
+    for (name, sign, add) in expr:
+        if name is None:
+            x = 0
+        else:
+            x = cols[name][r]
+            if x is None:
+                return None
+            x = int(x)
+        v *= sign * x + add
+    return v
+
+
+def brute_groupby_nulls(cols, preds, key_name, exprs, n):
+    """[(key or None, COUNT(*), [SUM_j or None], [COUNT_j], [AVG_j as Fraction or None])],
+    non-NULL keys ascending, then the NULL key."""
+    passing = brute_filter_nulls(cols, preds, n)
+    groups = []  # [key, count, sums, counts]
+    for r in range(n):
+        if not passing[r]:
+            continue
+        k = cols[key_name][r]
+        k = None if k is None else int(k)
+        found = None
+        for g in groups:  # linear search; None equals None here (SQL GROUP BY)
+            if g[0] == k:
+                found = g
+                break
+        if found is None:
+            found = [k, 0, [0] * len(exprs), [0] * len(exprs)]
+            groups.append(found)
+        found[1] += 1
+        for j, e in enumerate(exprs):
+            v = brute_expr_nulls(cols, e, r)
+            if v is not None:
+                found[2][j] += v
+                found[3][j] += 1
+    groups.sort(key=lambda g: (g[0] is None, 0 if g[0] is None else g[0]))
+    out = []
+    for k, c, s, cn in groups:
+        sums = [to_i64(x) if m else None for x, m in zip(s, cn)]
+        avgs = [Fraction(to_i64(x), m) if m else None for x, m in zip(s, cn)]
+        out.append((k, c, sums, cn, avgs))
+    return out
+
+
+def brute_join_nulls(bkeys, pkeys, bpass=None, ppass=None):
+    pairs = []
+    for p in range(len(pkeys)):
+        if (ppass is not None and not ppass[p]) or pkeys[p] is None:
+            continue
+        for b in range(len(bkeys)):
+            if (bpass is not None and not bpass[b]) or bkeys[b] is None:
+                continue
+            if int(bkeys[b]) == int(pkeys[p]):
+                pairs.append((p, b))
+    return pairs

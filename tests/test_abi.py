@@ -118,6 +118,16 @@ def test_invalid_arguments_are_rejected_synchronously():
     assert L.tq_hash_partition_noalloc(FAKE, None, 0, 5_000_000, 10, 0, FAKE, None, FAKE, None) == tq.TQ_EINVAL
     assert b"fixed area" in L.tq_last_error()
     assert L.tq_hash_partition_noalloc(FAKE, None, 0, 10, 11, 0, FAKE, None, FAKE, None) == tq.TQ_EINVAL
+    # dictionary strings: table, counts, NULL columns, scratch size
+    S = tq.Strings
+    assert L.tq_dict_unify(None, 1 << 20, S(FAKE, FAKE, 2), S(FAKE, FAKE, 2), FAKE, 1 << 20, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_dict_unify(FAKE, 1 << 20, S(FAKE, FAKE, -1), S(FAKE, FAKE, 2), FAKE, 1 << 20, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_dict_unify(FAKE, 1 << 20, S(None, FAKE, 2), S(FAKE, FAKE, 2), FAKE, 1 << 20, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_dict_unify(FAKE, 1 << 20, S(FAKE, FAKE, 2), S(FAKE, FAKE, 2), FAKE, 1 << 20, None, None) == tq.TQ_EINVAL
+    assert L.tq_dict_unify(FAKE, 1 << 20, S(FAKE, FAKE, 2), S(FAKE, FAKE, 2), FAKE, 16, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_dict_keys(None, None, 5, None, 0, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_dict_keys(FAKE, None, 5, None, 3, FAKE, None) == tq.TQ_EINVAL
+    assert L.tq_dict_keys(FAKE, None, -1, None, 0, FAKE, None) == tq.TQ_EINVAL
     # probe: expression factor count
     e = tq.exprs([[(0, 1, 0)] * 3])
     e[0].nf = 4

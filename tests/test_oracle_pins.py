@@ -14,8 +14,10 @@ import pytest
 
 import oracle
 from paper_2508_05029_amd.datagen import uniform, permutation
-from paper_2508_05029_amd.datagen.workloads import (FILTER_GROUPBY_QUERY, JOIN_AGG_QUERY, Factor, Pred,
-                                                     filter_groupby_tables, join_agg_tables)
+from paper_2508_05029_amd.datagen import workloads as wl
+from paper_2508_05029_amd.datagen.workloads import (FILTER_GROUPBY_QUERY, JOIN_AGG_QUERY, Factor, FilterGroupByQuery,
+                                                     GroupKey, Pred, filter_groupby_tables, join_agg_tables)
+from tests import brute
 from tests.brute import (brute_expr_exact, brute_filter, brute_groupby, brute_join, brute_partition_id,
                          to_i64)
 
@@ -304,3 +306,229 @@ def test_golden_join_duplicate_keys():
     total, pr, br = oracle.join_pairs(np.array(fx["build_keys"]), np.array(fx["probe_keys"]))
     assert total == fx["expect"]["cardinality"]
     assert [list(x) for x in zip(pr.tolist(), br.tolist())] == fx["expect"]["pairs"]
+
+
+# ---------------------------------------------------------------- NULLs
+
+def _with_nulls(n, density, seed, lo=-50, hi=50):
+    """A column as (numpy int64 values, Arrow bitmap, Python list with None)."""
+    rng = np.random.default_rng(seed)
+    vals = rng.integers(lo, hi + 1, n).astype(np.int64)
+    present = rng.random(n) >= density
+    bits = np.packbits(present.astype(np.uint8), bitorder="little")
+    return vals, bits, [int(v) if p else None for v, p in zip(vals, present)]
+
+
+def _oracle_groups_nulls(got):
+    out = []
+    for g in range(len(got["count"])):
+        key = None if got["key_null"][g] else int(got["keys"][g])
+        sums = [int(s) if c else None for s, c in zip(got["sums"][g], got["nonnull"][g])]
+        out.append((key, int(got["count"][g]), sums, [int(c) for c in got["nonnull"][g]]))
+    return out
+
+
+@pytest.mark.parametrize("seed,density", [(1, 0.0), (2, 0.1), (3, 0.5), (4, 0.9), (5, 1.0)])
+def test_nullable_filter_groupby_matches_brute(seed, density):
+    n = 90
+    k, kb, kl = _with_nulls(n, density, seed * 10 + 1, 0, 6)
+    v, vb, vl = _with_nulls(n, density, seed * 10 + 2, -(2 ** 62), 2 ** 62)
+    w, wb, wl = _with_nulls(n, density, seed * 10 + 3, 0, 10)
+    t = {"k": k, "v": v, "w": w}
+    valid = {"k": kb, "v": vb, "w": wb}
+    sums = [(Factor("v"),), (Factor("v"), Factor("w", -1, 10)), (Factor(None, 0, 7),)]
+    q = FilterGroupByQuery(preds=[Pred("w", 2, 8)], key=GroupKey(("k",), 1, 7), sums=sums, avg_of=[])
+    got = oracle.filter_groupby_nullable(t, valid, q)
+    want = brute.brute_groupby_nulls({"k": kl, "v": vl, "w": wl}, [("w", 2, 8)], "k",
+                                     [[(f.col, f.sign, f.add) for f in e] for e in sums], n)
+    assert _oracle_groups_nulls(got) == [(key, c, s, cn) for key, c, s, cn, _ in want]
+    for g, (_, _, _, cn, avgs) in enumerate(want):
+        for j, a in enumerate(avgs):
+            if a is not None:
+                assert abs(got["avg"][g, j] - float(a)) <= 1e-12 * abs(float(a))
+
+
+def test_nullable_without_nulls_equals_the_plain_oracle():
+    t = wl.filter_groupby_tables(20_000, seed=77)
+    q = wl.FILTER_GROUPBY_QUERY
+    q1 = FilterGroupByQuery(preds=q.preds, key=GroupKey(("flagA",), 1, 3), sums=q.sums, avg_of=[])
+    plain = oracle.filter_groupby(t, q1)
+    n = 20_000
+    ones = np.packbits(np.ones(n, np.uint8), bitorder="little")
+    for valid in (None, {}, {c: ones for c in t}):
+        got = oracle.filter_groupby_nullable(t, valid, q1)
+        assert not got["key_null"].any()
+        assert got["keys"].tolist() == plain["keys"][:, 0].tolist()
+        assert got["count"].tolist() == plain["count"].tolist()
+        assert got["sums"].tolist() == plain["sums"].tolist()
+        assert (got["nonnull"] == got["count"][:, None]).all()
+        assert got["avg"].tolist() == plain["avg"].tolist()
+    dim, fact = wl.join_agg_tables(3_000, 12_000, seed=78)
+    jq = JOIN_AGG_QUERY
+    plain = oracle.join_agg(dim, fact, jq)
+    got = oracle.join_agg_nullable(dim, None, fact, None, jq)
+    assert got["join_rows"] == plain["join_rows"]
+    assert got["keys"].tolist() == plain["keys"][:, 0].tolist()
+    assert got["count"].tolist() == plain["count"].tolist() and got["sums"].tolist() == plain["sums"].tolist()
+
+
+def test_nullable_all_null_values_and_keys():
+    n = 40
+    t = {"k": np.arange(n, dtype=np.int64) % 3, "v": np.arange(n, dtype=np.int64)}
+    none = np.zeros((n + 7) // 8, np.uint8)
+    q = FilterGroupByQuery(preds=[], key=GroupKey(("k",), 1, 3), sums=[(Factor("v"),)], avg_of=[])
+    got = oracle.filter_groupby_nullable(t, {"v": none}, q)
+    assert got["count"].tolist() == [14, 13, 13] and got["nonnull"][:, 0].tolist() == [0, 0, 0]
+    assert got["sums"][:, 0].tolist() == [0, 0, 0]
+    got = oracle.filter_groupby_nullable(t, {"k": none}, q)  # every key NULL: one group, listed as NULL
+    assert got["key_null"].tolist() == [True] and got["count"].tolist() == [n]
+    assert got["sums"][:, 0].tolist() == [n * (n - 1) // 2]
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_nullable_join_agg_matches_brute(seed):
+    nd, nf = 30, 70
+    key, kb, kl = _with_nulls(nd, 0.2, seed, 0, 15)
+    grp, gb, gl = _with_nulls(nd, 0.2, seed + 100, 0, 3)
+    date, db, dl = _with_nulls(nd, 0.1, seed + 200, 700, 1200)
+    fk, fb, fl = _with_nulls(nf, 0.2, seed + 300, 0, 18)
+    price, pb, plist = _with_nulls(nf, 0.2, seed + 400, 90_000, 10_500_000)
+    disc, cb, cl = _with_nulls(nf, 0.2, seed + 500, 0, 10)
+    dim = {"key": key, "group": grp.astype(np.int32), "date": date.astype(np.int32)}
+    fact = {"fk": fk, "price": price, "disc": disc}
+    q = JOIN_AGG_QUERY
+    got = oracle.join_agg_nullable(dim, {"key": kb, "group": gb, "date": db}, fact,
+                                   {"fk": fb, "price": pb, "disc": cb}, q)
+    bpass = brute.brute_filter_nulls({"date": dl}, [(p.col, p.lo, p.hi) for p in q.build_preds], nd)
+    pairs = brute.brute_join_nulls(kl, fl, bpass)
+    assert got["join_rows"] == len(pairs)
+    # group by the build payload over the pairs, by brute force
+    rows = {"g": [gl[b] for _, b in pairs], "price": [plist[p] for p, _ in pairs], "disc": [cl[p] for p, _ in pairs]}
+    exprs = [[(f.col, f.sign, f.add) for f in e] for e in q.sums]
+    want = brute.brute_groupby_nulls(rows, [], "g", exprs, len(pairs))
+    assert _oracle_groups_nulls(got) == [(k_, c, s, cn) for k_, c, s, cn, _ in want]
+
+
+def test_golden_nulls():
+    fx = _load("nulls_small.json")
+
+    def col(values, dtype):
+        present = np.array([x is not None for x in values], np.uint8)
+        vals = np.array([0 if x is None else x for x in values], dtype=dtype)
+        return vals, np.packbits(present, bitorder="little")
+
+    g = fx["groupby"]
+    t, valid = {}, {}
+    for name, values in g["columns"].items():
+        t[name], valid[name] = col(values, np.int64)
+    sums = [tuple(Factor(*f) for f in e) for e in g["sums"]]
+    q = FilterGroupByQuery(preds=[Pred(*p) for p in g["preds"]], key=GroupKey((g["key"],), 1, 10), sums=sums,
+                           avg_of=[])
+    got = oracle.filter_groupby_nullable(t, valid, q)
+    e = g["expect"]
+    assert [None if nl else int(k) for k, nl in zip(got["keys"], got["key_null"])] == e["keys"]
+    assert got["count"].tolist() == e["count"]
+    assert got["nonnull"].tolist() == e["nonnull"]
+    assert [[int(s) if c else None for s, c in zip(r, cr)] for r, cr in zip(got["sums"], got["nonnull"])] == e["sums"]
+    j = fx["join"]
+    b, bv, p, pv = {}, {}, {}, {}
+    for name, values in j["build"].items():
+        b[name], bv[name] = col(values, np.int32 if name == "group" else np.int64)
+    b["date"], bv["date"] = col([800] * len(j["build"]["key"]), np.int32)
+    for name, values in j["probe"].items():
+        p[name], pv[name] = col(values, np.int64)
+    p["disc"], pv["disc"] = col([0] * len(j["probe"]["fk"]), np.int64)
+    q = JOIN_AGG_QUERY  # window [730, 1094] passes every build row here; SUM(price * (100 - 0)) / 100
+    got = oracle.join_agg_nullable(b, bv, p, pv, q)
+    e = j["expect"]
+    assert got["join_rows"] == e["join_rows"]
+    assert [None if nl else int(k) for k, nl in zip(got["keys"], got["key_null"])] == e["keys"]
+    assert got["count"].tolist() == e["count"]
+    assert [int(s) // 100 for s in got["sums"][:, 0]] == e["sums"]
+    assert got["nonnull"][:, 0].tolist() == e["nonnull"]
+
+
+# ---------------------------------------------------------------------------
+# dictionary-encoded strings
+
+def _arrow(strings):
+    off = np.zeros(len(strings) + 1, np.int32)
+    off[1:] = np.cumsum([len(s) for s in strings])
+    data = np.frombuffer(b"".join(strings), np.uint8).copy() if strings else np.zeros(0, np.uint8)
+    return off, data
+
+
+def _tricky_strings(n, seed):
+    """Distinct byte strings that stress an equality test: the empty string,
+    prefixes of one another, equal lengths that differ in one byte (first,
+    middle, last), bytes 0x00 and >= 0x80."""
+    rng = np.random.default_rng(seed)
+    out = {b"", b"a", b"ab", b"abc", b"abd", b"bbc", b"\x00", b"\x00\x00", b"\xff", b"\x80a"}
+    while len(out) < n:
+        L = int(rng.integers(0, 12))
+        out.add(bytes(rng.integers(0, 256, L).astype(np.uint8)) if rng.random() < 0.5
+                else bytes(rng.choice(list(b"ab\x00\xff"), L).astype(np.uint8)))
+    return sorted(out)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_dict_unify_matches_a_python_dict(seed):
+    pool = _tricky_strings(300, seed)
+    rng = np.random.default_rng(seed)
+    build = [pool[i] for i in rng.permutation(len(pool))[:200]]
+    probe = [pool[i] for i in rng.permutation(len(pool))[:250]]
+    where = {s: j for j, s in enumerate(build)}
+    want = [where.get(s, -1) for s in probe]
+    got = oracle.dict_unify(_arrow(build), _arrow(probe))
+    assert got.tolist() == want
+    assert (got == -1).sum() == len(set(probe) - set(build)) > 0
+
+
+def test_dict_unify_empty_sides():
+    assert oracle.dict_unify(_arrow([]), _arrow([b"x", b""])).tolist() == [-1, -1]
+    assert oracle.dict_unify(_arrow([b"x", b""]), _arrow([])).tolist() == []
+    assert oracle.dict_unify(_arrow([b"x", b""]), _arrow([b"", b"x", b"y"])).tolist() == [1, 0, -1]
+
+
+def test_string_workload_dictionaries_are_distinct_and_overlap_by_three_quarters():
+    T = wl.string_join_tables(4000, 100)
+    b = oracle.decode(T.build_dict, np.arange(4000))
+    p = oracle.decode(T.probe_dict, np.arange(4000))
+    assert len(set(b)) == 4000 and len(set(p)) == 4000
+    assert len(set(b) & set(p)) == 3000
+    # the id after the last '#' names the string
+    assert all(int(s.rsplit(b"#", 1)[1]) < 4000 for s in b)
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_join_agg_strings_matches_brute(seed):
+    """Nested loops over the decoded strings: a pair joins when its strings are
+    equal and neither key is NULL."""
+    nd, nf = 40, 90
+    T = wl.string_join_tables(nd, nf, seed=seed)
+    rng = np.random.default_rng(seed)
+    kvalid = rng.random(nd) >= 0.15
+    fvalid = rng.random(nf) >= 0.15
+    dv = {"key": np.packbits(kvalid.astype(np.uint8), bitorder="little")}
+    fv = {"fk": np.packbits(fvalid.astype(np.uint8), bitorder="little")}
+    q = JOIN_AGG_QUERY
+    got = oracle.join_agg_strings(T.build_dict, T.dim, dv, T.probe_dict, T.fact, fv, q)
+    bs = oracle.decode(T.build_dict, T.dim["key"], dv["key"])
+    ps = oracle.decode(T.probe_dict, T.fact["fk"], fv["fk"])
+    groups = {}
+    npairs = 0
+    for p in range(nf):
+        for b in range(nd):
+            if bs[b] is None or ps[p] is None or bs[b] != ps[p]:
+                continue
+            if not (q.build_preds[0].lo <= T.dim["date"][b] <= q.build_preds[0].hi):
+                continue
+            npairs += 1
+            g = int(T.dim["group"][b])
+            c, s = groups.get(g, (0, [0] * len(q.sums)))
+            vals = [brute_expr_exact(T.fact, [(f.col, f.sign, f.add) for f in e], p) for e in q.sums]
+            groups[g] = (c + 1, [to_i64(a + v) for a, v in zip(s, vals)])
+    assert got["join_rows"] == npairs > 0
+    assert got["keys"].tolist() == sorted(groups)
+    assert got["count"].tolist() == [groups[g][0] for g in sorted(groups)]
+    assert got["sums"].tolist() == [groups[g][1] for g in sorted(groups)]
