@@ -176,7 +176,8 @@ __host__ __device__ inline int64_t* table_slots(void* t, int64_t cap_max) {
 constexpr int kRegionBins = 256;  // the top 8 bits of a bucket index select its region
 constexpr int kLog2Bins = 8;
 constexpr int kPartBlock = 512;
-constexpr int kPartRows = kPartBlock * kRows;  // rows per partitioning block
+constexpr int kPartSub = 1;                              // groups of kRows rows per thread
+constexpr int kPartRows = kPartBlock * kRows * kPartSub;  // rows per partitioning block
 constexpr int kMetaStride = kRegionBins + 8;
 __host__ __device__ inline int64_t part_grid_max(int64_t cap_max) {
   return cap_max / kPartRows > 1 ? cap_max / kPartRows : 1;

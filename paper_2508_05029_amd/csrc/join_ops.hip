@@ -254,13 +254,18 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   __shared__ uint32_t loc[kRegionBins];
   __shared__ int64_t ws[kPartBlock / kWave];
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * kPartRows + (int64_t)tid * kRows;
-  const bool full = r0 + kRows <= n;
-  int64_t v[NC][kRows], k[kRows], pay[kRows];
+  // kPartSub groups of kRows consecutive rows per thread, the groups a block
+  // width apart: every load of a group is issued before any row is hashed
+  int64_t v[kPartSub][NC][kRows], k[kPartSub][kRows], pay[kPartSub][kRows];
   const DCol kc = {keys, 8};
-  load_rows<NC>(P, r0, full, n, v);
-  load4(kc, r0, full, n, k);
-  load4(payload, r0, full, n, pay);
+#pragma unroll
+  for (int c = 0; c < kPartSub; c++) {
+    const int64_t r0 = (int64_t)blockIdx.x * kPartRows + ((int64_t)c * kPartBlock + tid) * kRows;
+    const bool full = r0 + kRows <= n;
+    load_rows<NC>(P, r0, full, n, v[c]);
+    load4(kc, r0, full, n, k[c]);
+    load4(payload, r0, full, n, pay[c]);
+  }
   if (h->magic != kTableMagic) return;
   if (blockIdx.x == 0 && tid == 0) {
     h->ovf = 0;  // the previous build's fallback has finished with it
@@ -269,15 +274,20 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   if (tid < kRegionBins) hist[tid] = 0;
   __syncthreads();
   const bool nulls = P.null_cols != 0 || key_valid != nullptr;
-  bool ok[kRows];
-  uint32_t bin[kRows], rank[kRows];
+  bool ok[kPartSub][kRows];
+  uint32_t bin[kPartSub][kRows], rank[kPartSub][kRows];
 #pragma unroll
-  for (int i = 0; i < kRows; i++) {
-    const uint64_t hh = mulhash(k[i]);
-    ok[i] = (r0 + i < n) && build_row_ok<NC>(P, v, i, r0 + i, key_valid, nulls) && in_partition(hh, skip, flags);
-    if (ok[i]) pay[i] = stored_payload(payload, r0 + i, pay[i]);
-    bin[i] = (uint32_t)((hh << skip) >> (64 - kLog2Bins));
-    rank[i] = ok[i] ? atomicAdd(&hist[bin[i]], 1u) : 0u;
+  for (int c = 0; c < kPartSub; c++) {
+    const int64_t r0 = (int64_t)blockIdx.x * kPartRows + ((int64_t)c * kPartBlock + tid) * kRows;
+#pragma unroll
+    for (int i = 0; i < kRows; i++) {
+      const uint64_t hh = mulhash(k[c][i]);
+      ok[c][i] = (r0 + i < n) && build_row_ok<NC>(P, v[c], i, r0 + i, key_valid, nulls) &&
+                 in_partition(hh, skip, flags);
+      if (ok[c][i]) pay[c][i] = stored_payload(payload, r0 + i, pay[c][i]);
+      bin[c][i] = (uint32_t)((hh << skip) >> (64 - kLog2Bins));
+      rank[c][i] = ok[c][i] ? atomicAdd(&hist[bin[c][i]], 1u) : 0u;
+    }
   }
   __syncthreads();
   const uint32_t cnt = tid < kRegionBins ? hist[tid] : 0u;
@@ -291,8 +301,21 @@ __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int6
   __syncthreads();
   v2i64* seg = reinterpret_cast<v2i64*>(scratch_rows(h, cap_max)) + (size_t)blockIdx.x * kPartRows;
 #pragma unroll
-  for (int i = 0; i < kRows; i++)
-    if (ok[i]) seg[loc[bin[i]] + rank[i]] = v2i64{k[i], pay[i]};
+  for (int c = 0; c < kPartSub; c++)
+#pragma unroll
+    for (int i = 0; i < kRows; i++)
+      if (ok[c][i]) seg[loc[bin[c][i]] + rank[c][i]] = v2i64{k[c][i], pay[c][i]};
+}
+
+// The region a k_build_regions workgroup fills. Workgroups are dealt to the
+// eight XCDs in turn (workgroup i to XCD i mod 8), so workgroup i takes region
+// (i mod 8) * 32 + i / 8: each XCD fills 32 adjacent regions, whose counts in
+// a block's metadata row share one cache line and whose rows lie together in
+// each block's segment, so that each line is fetched into one XCD's L2, not
+// into up to eight.
+__device__ __forceinline__ int region_of_workgroup(int i) {
+  constexpr int kXcds = 8, kPer = kRegionBins / kXcds;
+  return (i % kXcds) * kPer + i / kXcds;
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int64_t cap_max, int nblk, double lf,
@@ -302,7 +325,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   __shared__ int64_t ws[2 * kFinBlock / kWave];
   __shared__ uint32_t lbloom[kBloomWordsMax / kRegionBins];
   __shared__ uint32_t sub_cnt[kMaxSubs], sub_fill[kMaxSubs], sub_off[kMaxSubs + 1];
-  const int j = blockIdx.x, tid = threadIdx.x;
+  const int j = region_of_workgroup(blockIdx.x), tid = threadIdx.x;
   const uint32_t* meta = scratch_meta(h, cap_max) + j;  // region j's counts, block b at meta[b * kMetaStride]
   // the loads go out first (the scratch lies inside the caller's buffer
   // whatever the header holds), then the LDS copy is cleared while they fly
@@ -344,7 +367,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   const int log2w = l <= kMaxBloomLog2Cap ? std::min(std::max(l - 4, kLog2Bins + 1), kLog2BloomWordsMax) : 0;
   static_assert(kBloomWordsMax == 1 << kLog2BloomWordsMax && kRegionBins == 1 << kLog2Bins, "bloom size rule");
   const int log2g = std::min(l, kMaxRegionLog2Cap) - kLog2Bucket - kLog2Bins;  // buckets per domain
-  if (j == 0 && tid == 0) {
+  if (blockIdx.x == 0 && tid == 0) {
     h->cap_max = cap_max;
     h->n = rows;
     h->log2cap = l;
@@ -363,7 +386,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     v4i32* at = reinterpret_cast<v4i32*>(scratch_alt_tags(h, cap_max));
     const v4i32 z = {0, 0, 0, 0};
     const int64_t groups = (int64_t)1 << (l - kLog2Bucket);
-    for (int64_t i = (int64_t)j * kFinBlock + tid; i < groups; i += (int64_t)gridDim.x * kFinBlock) at[i] = z;
+    for (int64_t i = (int64_t)blockIdx.x * kFinBlock + tid; i < groups; i += (int64_t)gridDim.x * kFinBlock) at[i] = z;
   }
   if (!fits) {
     if (tid == 0) atomicOr(&h->ovf, 1);
