@@ -324,8 +324,8 @@ tq_status tq_groupby_agg_nullable(void* d_state, int64_t domain, const tq_col* i
 tq_status tq_groupby_finalize_nullable(const void* d_state, int64_t* d_keys, int64_t* d_count, int64_t* d_sums,
                                        int64_t* d_nonnull, double* d_avg, int64_t* d_ngroups, hipStream_t stream);
 
-/* Synchronise `stream`, then return the error latched in a join table or a
- * group-by state (TQ_OK if none). */
+/* Synchronise `stream`, then return the error latched in a join table, a
+ * group-by state or a Parquet decode's work buffer (TQ_OK if none). */
 tq_status tq_check(const void* d_obj, hipStream_t stream);
 
 /* ------------------------------------------------------------ page pool */
@@ -661,6 +661,68 @@ size_t tq_read_peak_scratch_bytes(void);
 tq_status tq_read_peak(const void* d_src, size_t bytes, int64_t* d_partial, hipStream_t stream);
 /* Write `bytes` (multiple of 16) of a pattern; used to evict caches between timed repetitions. */
 tq_status tq_fill(void* d_dst, size_t bytes, uint32_t pattern, hipStream_t stream);
+
+/* ------------------------------------------------------------ Parquet scan */
+
+/* Scan-side decode of Parquet files (Section 3.3.3, Byte Range Pre-loading:
+ * the file's metadata gives the exact byte ranges a scan needs, close ranges
+ * are merged into one read, and the bytes land in pool pages ahead of the
+ * compute task, which is left with decoding; Section 4 reads Parquet inputs).
+ * Supported: flat schemas; INT32 and INT64 columns, required or optional;
+ * data pages v1 and v2 in PLAIN or dictionary encoding (RLE_DICTIONARY /
+ * PLAIN_DICTIONARY, dictionary pages PLAIN); uncompressed column chunks.
+ * Other codecs, encodings, types and nested columns are rejected with
+ * TQ_EINVAL when the file is opened or the preload is planned. */
+typedef struct tq_parquet tq_parquet;
+typedef struct tq_preload tq_preload;
+
+/* Open a file and read its footer (host). The handle owns the file
+ * descriptor; tq_parquet_close releases both. */
+tq_status tq_parquet_open(const char* path, tq_parquet** out);
+void tq_parquet_close(tq_parquet* pq);
+int64_t tq_parquet_num_rows(const tq_parquet* pq);
+int32_t tq_parquet_num_row_groups(const tq_parquet* pq);
+int64_t tq_parquet_row_group_rows(const tq_parquet* pq, int32_t rg);
+int32_t tq_parquet_num_columns(const tq_parquet* pq);
+/* Column c: its name (owned by the handle), output type (TQ_I32 / TQ_I64, 0
+ * if not decodable) and whether it may hold NULLs (an optional column). */
+tq_status tq_parquet_column(const tq_parquet* pq, int32_t c, const char** name, int32_t* type, int32_t* nullable);
+/* The byte range of column c's chunk in row group rg, and its codec. */
+tq_status tq_parquet_chunk(const tq_parquet* pq, int32_t rg, int32_t c, int64_t* file_off, int64_t* bytes,
+                           int32_t* codec);
+
+/* Byte Range Pre-loading: the chunks of columns h_cols[0..ncol) in row
+ * groups [rg0, rg1), sorted by offset, ranges at most merge_gap bytes apart
+ * merged into one read; pool pages are taken for every read (TQ_ENOMEM if the
+ * pool has too few) and a host thread starts reading into them; the call
+ * returns at once. */
+tq_status tq_parquet_preload(tq_parquet* pq, tq_pagepool* pool, int32_t rg0, int32_t rg1, const int32_t* h_cols,
+                             int32_t ncol, int64_t merge_gap, tq_preload** out);
+int32_t tq_preload_num_reads(const tq_preload* p);
+tq_status tq_preload_read(const tq_preload* p, int32_t i, int64_t* file_off, int64_t* bytes);
+int64_t tq_preload_rows(const tq_preload* p); /* rows of the row groups */
+/* Waits for the reads, walks the page headers (host) and returns the device
+ * work bytes tq_parquet_decode needs. */
+tq_status tq_preload_work_bytes(tq_preload* p, size_t* bytes);
+/* After tq_preload_work_bytes: the pages found, in file order (kind 0 data,
+ * 2 dictionary; encoding 0 PLAIN, 8 dictionary indices). */
+int64_t tq_preload_num_pages(const tq_preload* p);
+tq_status tq_preload_page(const tq_preload* p, int64_t i, int64_t* row0, int32_t* nrows, int32_t* col, int32_t* kind,
+                          int32_t* encoding);
+/* Decode into out[c] (c over the preload's columns): out[c].type = the
+ * column's type, out[c].data holds tq_preload_rows() values, out[c].valid a
+ * bitmap of as many bits, written as whole 32-bit words: it must hold
+ * ((rows + 31) / 32) * 4 bytes, 4-byte aligned (required for a nullable
+ * column, optional otherwise: all ones then). NULL rows get value 0. The bytes are copied from
+ * the pool pages into d_work (256-byte aligned, tq_preload_work_bytes bytes)
+ * and decoded there by kernels on `stream`; the call returns once the copies
+ * are done and the pages are back in the pool, with the kernels enqueued.
+ * Errors found by the kernels (a malformed stream, a dictionary index out of
+ * range) are latched in d_work: tq_check(d_work, stream) reports them. A
+ * preload is decoded once. */
+tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, const tq_col* out, hipStream_t stream);
+/* Waits for the reads, returns unused pages to the pool and frees the handle. */
+void tq_preload_free(tq_preload* p);
 
 #ifdef __cplusplus
 }

@@ -108,6 +108,7 @@ tq_status make_plan(RowPlan* plan, const tq_col* in, int32_t ncol, const tq_pred
 
 constexpr uint32_t kTableMagic = 0x54514A54u;
 constexpr uint32_t kStateMagic = 0x54514753u;
+constexpr uint32_t kScanMagic = 0x54515053u;  // a Parquet decode's work buffer
 constexpr size_t kHeaderBytes = 256;
 constexpr int kMaxPartBlocks = 2048;  // per-block partial counts kept in a table
 

@@ -1,0 +1,554 @@
+// Parquet scan, device side: decodes the pages of preloaded column chunks
+// into Arrow columns (values + validity bitmap). Section 3.3.3 leaves the
+// compute task only decompression and decoding once the byte ranges are in
+// memory; these kernels are that decoding, for uncompressed INT32 / INT64
+// pages in PLAIN or dictionary (RLE_DICTIONARY) encoding, flat columns,
+// required or optional (definition levels).
+//
+// The definition levels and the dictionary indices are RLE/bit-packed hybrid
+// streams, whose runs can only be found one after another. So:
+//   k_pq_dict   copies each dictionary page's values to an aligned array;
+//   k_pq_walk   one wave per (page, stream) walks the run headers out of an
+//               LDS window of the stream (one lane; the wave stages the bytes)
+//               and writes a run table, plus a checkpoint every kPqTile items
+//               (the run holding that item, and the present rows before it);
+//   k_pq_decode one workgroup per kPqTile rows of a page: from its checkpoint
+//               it stages the tile's runs in LDS, finds each row's level and
+//               value index (a workgroup scan of the present rows), decodes
+//               the value (PLAIN, or dictionary index then gather) and writes
+//               the values and the validity bits.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "parquet.h"
+
+namespace tq {
+
+constexpr int kWalkWin = 16384;  // bytes of a stream staged in LDS at a time
+constexpr int kDecBlock = 256;
+constexpr int kDecRows = kPqTile / kDecBlock;  // rows per thread
+constexpr int kTileRuns = 1024 + 1;           // runs of a tile's rows (each run holds at least one item)
+
+struct PqHeader {
+  uint32_t magic;
+  int32_t err;
+};
+
+__device__ __forceinline__ void pq_error(PqHeader* h, int32_t code) { atomicCAS(&h->err, 0, code); }
+
+// Little-endian bytes [p, p + width) of the raw area (width 4 or 8), from
+// aligned 32-bit loads; may read up to 8 bytes past the value (the raw area
+// is padded).
+__device__ __forceinline__ uint64_t ld_le(const uint8_t* raw, int64_t p, int width) {
+  const uint32_t* a = reinterpret_cast<const uint32_t*>(raw + (p & ~(int64_t)3));
+  const uint32_t sh = (uint32_t)(p & 3) * 8;
+  const uint32_t w0 = a[0], w1 = a[1];
+  const uint32_t lo = sh ? (w0 >> sh) | (w1 << (32 - sh)) : w0;
+  if (width == 4) return lo;
+  const uint32_t w2 = a[2];
+  const uint32_t hi = sh ? (w1 >> sh) | (w2 << (32 - sh)) : w1;
+  return (uint64_t)hi << 32 | lo;
+}
+
+__global__ void k_pq_init(PqHeader* h) {
+  h->magic = kScanMagic;
+  h->err = 0;
+}
+
+__global__ void k_pq_zero(uint32_t* words, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    words[i] = 0u;
+}
+
+// One workgroup per dictionary page.
+__global__ __launch_bounds__(kDecBlock) void k_pq_dict(const PqPage* pages, const int32_t* dict_pages,
+                                                       const uint8_t* raw, uint8_t* dict) {
+  const PqPage pg = pages[dict_pages[blockIdx.x]];
+  const int w = pg.width;
+  uint8_t* out = dict + pg.dict_off;
+  for (int64_t e = threadIdx.x; e < pg.dict_n; e += kDecBlock) {
+    const uint64_t v = ld_le(raw, pg.val_off + e * w, w);
+    if (w == 8) reinterpret_cast<uint64_t*>(out)[e] = v;
+    else reinterpret_cast<uint32_t*>(out)[e] = (uint32_t)v;
+  }
+}
+
+__device__ __forceinline__ uint32_t win_byte(const uint32_t* win, int64_t i) { return (win[i >> 2] >> ((i & 3) * 8)) & 0xffu; }
+
+// Items equal to 1 among the first n of a bit-packed run of bit width 1 at
+// raw byte `at` (window bytes when they are staged there).
+__device__ uint32_t ones_prefix(const uint32_t* win, int64_t wbase, int64_t wend, const uint8_t* raw, int64_t at,
+                                int64_t n) {
+  uint32_t c = 0;
+  int64_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    const int64_t b = at + i / 8;
+    c += __popc(b >= wbase && b < wend ? win_byte(win, b - wbase) : raw[b]);
+  }
+  if (i < n) {
+    const int64_t b = at + i / 8;
+    const uint32_t x = b >= wbase && b < wend ? win_byte(win, b - wbase) : raw[b];
+    c += __popc(x & ((1u << (n - i)) - 1u));
+  }
+  return c;
+}
+
+// One 64-lane workgroup per (data page, stream): stream 0 the definition
+// levels, stream 1 the dictionary indices.
+__global__ __launch_bounds__(64) void k_pq_walk(const PqPage* pages, int npages, const uint8_t* raw, PqRun* runs,
+                                                int32_t* nruns, PqCk* cks, PqHeader* hdr) {
+  __shared__ uint32_t win[kWalkWin / 4 + 4];
+  __shared__ int64_t s_pos, s_items, s_before;
+  __shared__ int32_t s_nr, s_ck, s_done;
+  const int pi = blockIdx.x >> 1, s = blockIdx.x & 1;
+  const PqPage pg = pages[pi];
+  if (pg.kind != kPqDataPage) return;
+  if (s == 0 && pg.def_off < 0) return;
+  if (s == 1 && pg.encoding != kPqRleDictionary) return;
+  const int64_t end = s == 0 ? pg.def_end : pg.val_end;
+  int bw = 1;
+  if (s == 1) {
+    if (pg.val_off >= pg.val_end) {
+      if (threadIdx.x == 0 && pg.nrows > 0) nruns[2 * pi + 1] = 0;
+      return;
+    }
+    bw = raw[pg.val_off];  // the index bit width leads the stream
+    if (bw > 32) {
+      if (threadIdx.x == 0) pq_error(hdr, TQ_EINVAL);
+      return;
+    }
+  }
+  const int64_t limit = pg.nrows;  // items: the page's rows (levels), at most that many values
+  PqRun* R = runs + (s ? pg.runs_val : pg.runs_def);
+  PqCk* C = cks + (s ? pg.ck_val : pg.ck_def);
+  const int64_t nck = ((int64_t)pg.nrows + kPqTile - 1) / kPqTile;
+  const int vbytes = (bw + 7) / 8;
+  if (threadIdx.x == 0) {
+    s_pos = s == 0 ? pg.def_off : pg.val_off + 1;
+    s_items = 0;
+    s_before = 0;
+    s_nr = 0;
+    s_ck = 0;
+    s_done = 0;
+  }
+  __syncthreads();
+  while (!s_done) {
+    const int64_t wbase = s_pos & ~(int64_t)3;
+    const int64_t wend = wbase + kWalkWin;
+    for (int i = threadIdx.x; i < kWalkWin / 4 + 4; i += 64) {
+      const int64_t a = wbase + 4 * (int64_t)i;
+      win[i] = a < end ? *reinterpret_cast<const uint32_t*>(raw + a) : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t pos = s_pos, items = s_items, before = s_before;
+      int32_t nr = s_nr, ck = s_ck;
+      bool done = false, bad = false;
+      // a run is walked here while its header and fixed bytes lie in the window
+      while (!done && !bad) {
+        if (items >= limit || pos >= end) {
+          done = true;
+          break;
+        }
+        if (pos + 16 > wend) break;  // refill the window from this header
+        uint64_t h = 0;
+        int sh = 0;
+        uint32_t b;
+        do {
+          b = win_byte(win, pos - wbase);
+          h |= (uint64_t)(b & 0x7f) << sh;
+          sh += 7;
+          pos++;
+        } while ((b & 0x80) && sh < 35);
+        if (b & 0x80) {
+          bad = true;
+          break;
+        }
+        PqRun r;
+        r.first = (int32_t)items;
+        r.before = (int32_t)before;
+        int64_t count, ones;
+        if (h & 1) {  // bit-packed: (h >> 1) groups of 8 items, bw bytes each
+          const int64_t groups = (int64_t)(h >> 1);
+          count = groups * 8;
+          r.meta = 0x80000000u | (uint32_t)bw;
+          r.arg = pos;
+          const int64_t bytes = groups * bw;
+          if (groups == 0 || pos + bytes > end) {
+            bad = true;
+            break;
+          }
+          const int64_t live = min(count, limit - items);  // the last run is padded to whole groups
+          ones = s == 0 ? ones_prefix(win, wbase, wend, raw, pos, live) : 0;
+          // checkpoints inside the run
+          while (ck < nck && (int64_t)ck * kPqTile < items + count) {
+            const int64_t k = (int64_t)ck * kPqTile - items;
+            C[ck] = PqCk{nr, (int32_t)(before + (s == 0 ? ones_prefix(win, wbase, wend, raw, pos, k) : 0))};
+            ck++;
+          }
+          pos += bytes;
+        } else {  // RLE: (h >> 1) copies of one value of vbytes bytes
+          count = (int64_t)(h >> 1);
+          if (count == 0 || pos + vbytes > end) {
+            bad = true;
+            break;
+          }
+          uint64_t v = 0;
+          for (int i = 0; i < vbytes; i++) v |= (uint64_t)win_byte(win, pos - wbase + i) << (8 * i);
+          r.meta = (uint32_t)bw;
+          r.arg = (int64_t)v;
+          ones = s == 0 && v ? min(count, limit - items) : 0;
+          while (ck < nck && (int64_t)ck * kPqTile < items + count) {
+            const int64_t k = (int64_t)ck * kPqTile - items;
+            C[ck] = PqCk{nr, (int32_t)(before + (s == 0 && v ? k : 0))};
+            ck++;
+          }
+          pos += vbytes;
+        }
+        if (nr >= (s ? pg.max_val : pg.max_def) || items + count > (int64_t)INT32_MAX) {
+          bad = true;
+          break;
+        }
+        r.count = (int32_t)count;
+        R[nr++] = r;
+        items += count;
+        before += ones;
+      }
+      if (bad) pq_error(hdr, TQ_EINVAL);
+      if (done || bad) {
+        nruns[2 * pi + s] = bad ? 0 : nr;
+        if (s == 0 && !bad && items < limit) pq_error(hdr, TQ_EINVAL);  // levels end early
+      }
+      s_pos = pos;
+      s_items = items;
+      s_before = before;
+      s_nr = nr;
+      s_ck = ck;
+      s_done = done || bad;
+    }
+    __syncthreads();
+  }
+}
+
+// The value of item i of a run (bit width <= 32).
+__device__ __forceinline__ uint32_t run_item(const PqRun& r, const uint8_t* raw, int64_t i) {
+  if (!(r.meta >> 31)) return (uint32_t)r.arg;
+  const uint32_t bw = r.meta & 0xffu;
+  const int64_t bit = i * bw;
+  const uint64_t x = ld_le(raw, r.arg + (bit >> 3), 8);
+  const uint64_t v = x >> (bit & 7);
+  return bw == 32 ? (uint32_t)v : (uint32_t)(v & ((1ull << bw) - 1ull));
+}
+
+// Index of the run (among n staged in LDS) holding item `item`.
+__device__ __forceinline__ int find_run(const PqRun* r, int n, int64_t item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (r[mid].first <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Stages in LDS the runs of a table (`total` runs) that hold items
+// [first_item, last_item], searching for the first of them from run
+// `from` on (a checkpoint's run, at or before it); returns how many, 0 if the
+// table does not hold those items.
+__device__ int stage_runs(PqRun* dst, const PqRun* src, int32_t from, int32_t total, int64_t first_item,
+                          int64_t last_item, int* s_at, int* s_n) {
+  if (from < 0 || from > total) from = 0;  // a checkpoint the walk never wrote (it stopped on an error)
+  if (threadIdx.x == 0) *s_at = -1;
+  __syncthreads();
+  int32_t at = -1;
+  for (int32_t base = from; base < total; base += kDecBlock) {
+    const int32_t i = base + (int32_t)threadIdx.x;
+    if (i < total && src[i].first <= first_item && first_item < (int64_t)src[i].first + src[i].count) *s_at = i;
+    __syncthreads();
+    at = *s_at;
+    __syncthreads();  // read by all before anyone writes it again
+    if (at >= 0) break;
+  }
+  if (at < 0) return 0;
+  int n = 0;
+  for (;;) {
+    const int take = min(kDecBlock, min(kTileRuns - n, total - at - n));
+    if (take <= 0) break;
+    if ((int)threadIdx.x < take) dst[n + threadIdx.x] = src[at + n + threadIdx.x];
+    __syncthreads();
+    n += take;
+    const PqRun& tail = dst[n - 1];
+    if ((int64_t)tail.first + tail.count > last_item) break;
+  }
+  if (threadIdx.x == 0) *s_n = n;
+  __syncthreads();
+  const int got = *s_n;
+  __syncthreads();  // every thread has read *s_at and *s_n before they are reused
+  return (int64_t)dst[got - 1].first + dst[got - 1].count > last_item ? got : 0;
+}
+
+struct PqOut {
+  void* data[TQ_MAX_COLS];
+  uint32_t* valid[TQ_MAX_COLS];
+};
+
+__global__ __launch_bounds__(kDecBlock) void k_pq_decode(const PqPage* pages, const int32_t* tile_page,
+                                                         const uint8_t* raw, const uint8_t* dict, const PqRun* runs,
+                                                         const int32_t* nruns, const PqCk* cks, PqOut out,
+                                                         PqHeader* hdr) {
+  __shared__ PqRun lr[kTileRuns];
+  __shared__ int64_t ws[kDecBlock / kWave];
+  __shared__ uint32_t bits[kPqTile / 32];
+  __shared__ int s_n, s_at;
+  const int pi = tile_page[blockIdx.x];
+  const PqPage pg = pages[pi];
+  const int64_t k = blockIdx.x - pg.tile0;
+  const int64_t t0 = k * kPqTile;  // first row of the tile in the page
+  const int tid = threadIdx.x;
+  const int rows = (int)min((int64_t)kPqTile, (int64_t)pg.nrows - t0);
+  const bool optional = pg.def_off >= 0;
+  // levels: present bits of this thread's rows
+  uint32_t present = 0;  // bit i: row tid * kDecRows + i
+  int64_t pres0 = t0;    // present rows of the page before the tile
+  if (optional) {
+    const PqCk c = cks[pg.ck_def + k];
+    pres0 = c.before;
+    const int n = stage_runs(lr, runs + pg.runs_def, c.run, nruns[2 * pi], t0, t0 + rows - 1, &s_at, &s_n);
+    if (n == 0) {
+      if (tid == 0) pq_error(hdr, TQ_EINVAL);
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < kDecRows; i++) {
+      const int j = tid * kDecRows + i;
+      if (j < rows) {
+        const int64_t item = t0 + j;
+        const PqRun& r = lr[find_run(lr, n, item)];
+        if (item < r.first || item >= (int64_t)r.first + r.count) pq_error(hdr, TQ_EINVAL);
+        else present |= (run_item(r, raw, item - r.first) & 1u) << i;
+      }
+    }
+    __syncthreads();  // the level runs are read; the table is staged anew below
+  } else {
+#pragma unroll
+    for (int i = 0; i < kDecRows; i++) present |= (uint32_t)(tid * kDecRows + i < rows) << i;
+  }
+  int64_t excl;
+  const int64_t tile_present = block_excl_scan((int64_t)__popc(present), &excl, ws);
+  const int64_t v0 = pres0 + excl;  // value index of this thread's first present row
+  // values
+  uint64_t val[kDecRows];
+#pragma unroll
+  for (int i = 0; i < kDecRows; i++) val[i] = 0;
+  const int w = pg.width;
+  if (pg.encoding == kPqPlain) {
+    int64_t v = v0;
+#pragma unroll
+    for (int i = 0; i < kDecRows; i++) {
+      if (present >> i & 1u) {
+        const int64_t at = pg.val_off + v * w;
+        if (at + w > pg.val_end) pq_error(hdr, TQ_EINVAL);
+        else val[i] = ld_le(raw, at, w);
+        v++;
+      }
+    }
+  } else if (tile_present > 0) {
+    const int64_t vfirst = pres0, vlast = pres0 + tile_present - 1;
+    const int32_t nv = nruns[2 * pi + 1];
+    const PqCk c = cks[pg.ck_val + vfirst / kPqTile];
+    // from the checkpoint's run to the one holding vfirst, then the tile's runs
+    const int n = stage_runs(lr, runs + pg.runs_val, c.run, nv, vfirst, vlast, &s_at, &s_n);
+    if (n == 0) {
+      if (tid == 0) pq_error(hdr, TQ_EINVAL);
+      return;
+    }
+    const int64_t* d64 = reinterpret_cast<const int64_t*>(dict + pg.dict_off);
+    const int32_t* d32 = reinterpret_cast<const int32_t*>(dict + pg.dict_off);
+    int64_t v = v0;
+#pragma unroll
+    for (int i = 0; i < kDecRows; i++) {
+      if (present >> i & 1u) {
+        const PqRun& r = lr[find_run(lr, n, v)];
+        const bool in_run = v >= r.first && v < (int64_t)r.first + r.count;
+        const uint32_t idx = in_run ? run_item(r, raw, v - r.first) : 0u;
+        if (!in_run || idx >= (uint32_t)pg.dict_n) pq_error(hdr, TQ_EINVAL);
+        else val[i] = w == 8 ? (uint64_t)d64[idx] : (uint64_t)(uint32_t)d32[idx];
+        v++;
+      }
+    }
+  }
+  // write the values (NULL rows: 0)
+  const int64_t row = pg.row0 + t0 + (int64_t)tid * kDecRows;
+#pragma unroll
+  for (int i = 0; i < kDecRows; i++) {
+    if (tid * kDecRows + i < rows) {
+      if (w == 8) static_cast<uint64_t*>(out.data[pg.col])[row + i] = val[i];
+      else static_cast<uint32_t*>(out.data[pg.col])[row + i] = (uint32_t)val[i];
+    }
+  }
+  // validity: the tile's bits gathered in LDS, then OR-ed into the output words
+  uint32_t* vout = out.valid[pg.col];
+  if (vout) {
+    if (tid < kPqTile / 32) bits[tid] = 0u;
+    __syncthreads();
+    if (present) atomicOr(&bits[(tid * kDecRows) / 32], present << ((tid * kDecRows) % 32));
+    __syncthreads();
+    const int64_t base = pg.row0 + t0;      // output bit of tile row 0
+    const int64_t w0 = base >> 5, sh = base & 31;
+    const int nw = (int)(((base + rows - 1) >> 5) - w0 + 1);
+    if (tid < nw) {
+      // output word w0 + tid holds tile bits [32 * tid - sh, 32 * tid - sh + 32)
+      const int64_t lo_bit = 32 * (int64_t)tid - sh;
+      uint32_t x = 0;
+      const int64_t i0 = lo_bit >> 5;  // may be -1
+      const uint32_t s2 = (uint32_t)(lo_bit & 31);
+      const uint32_t a = i0 >= 0 && i0 < kPqTile / 32 ? bits[i0] : 0u;
+      const uint32_t b = i0 + 1 >= 0 && i0 + 1 < kPqTile / 32 ? bits[i0 + 1] : 0u;
+      x = s2 ? (a >> s2) | (b << (32 - s2)) : a;
+      if (x) atomicOr(&vout[w0 + tid], x);
+    }
+  }
+}
+
+}  // namespace tq
+
+using namespace tq;
+
+extern "C" {
+
+tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, const tq_col* out, hipStream_t stream) {
+  if (!p || !d_work || !out) return fail(TQ_EINVAL, "preload, work buffer or outputs NULL");
+  if ((uintptr_t)d_work & 255) return fail(TQ_EINVAL, "work buffer not 256-byte aligned");
+  tq_status s;
+  if ((s = pq_join(p))) return s;
+  if ((s = pq_parse_pages(p))) return s;
+  if (p->reads.empty() && p->raw_bytes > 0) return fail(TQ_EINVAL, "the preload was decoded already");
+  const PqLayout L = pq_layout(p);
+  if (work_bytes < L.total) return fail(TQ_EINVAL, "work buffer needs %zu bytes", L.total);
+  const int32_t ncol = (int32_t)p->cols.size();
+  PqOut po{};
+  for (int32_t c = 0; c < ncol; c++) {
+    const char* name;
+    int32_t type, nullable;
+    tq_parquet_column(p->pq, p->cols[(size_t)c], &name, &type, &nullable);
+    if (out[c].type != type) return fail(TQ_EINVAL, "output %d (%s): type %d, the column is %d", c, name, out[c].type, type);
+    if (p->rows > 0 && !out[c].data) return fail(TQ_EINVAL, "output %d (%s): NULL data", c, name);
+    if ((uintptr_t)out[c].data & 7) return fail(TQ_EINVAL, "output %d: data not 8-byte aligned", c);
+    if (nullable && !out[c].valid && p->rows > 0)
+      return fail(TQ_EINVAL, "output %d (%s) may hold NULLs: it needs a validity bitmap", c, name);
+    if ((uintptr_t)out[c].valid & 3) return fail(TQ_EINVAL, "output %d: bitmap not 4-byte aligned", c);
+    po.data[c] = const_cast<void*>(out[c].data);
+    po.valid[c] = reinterpret_cast<uint32_t*>(const_cast<uint8_t*>(out[c].valid));
+  }
+  char* W = static_cast<char*>(d_work);
+  uint8_t* raw = reinterpret_cast<uint8_t*>(W + L.raw);
+  PqHeader* hdr = reinterpret_cast<PqHeader*>(W);
+  // host tables: descriptors with offsets made absolute where the kernels want
+  // them, the tile -> page map, the dictionary pages; staged through pool pages
+  std::vector<PqPage> pages = p->pages;
+  std::vector<int32_t> tile_page((size_t)p->tiles), dict_pages;
+  for (size_t i = 0; i < pages.size(); i++) {
+    const PqPage& d = pages[i];
+    if (d.kind == kPqDictionaryPage) dict_pages.push_back((int32_t)i);
+    else
+      for (int64_t t = 0; t < ((int64_t)d.nrows + kPqTile - 1) / kPqTile; t++) tile_page[(size_t)(d.tile0 + t)] = (int32_t)i;
+  }
+  const size_t pb = tq_pagepool_page_bytes(p->pool);
+  const size_t host_bytes = pages.size() * sizeof(PqPage) + tile_page.size() * 4 + dict_pages.size() * 4 + 64;
+  const int64_t hpages = (int64_t)((host_bytes + pb - 1) / pb);
+  std::vector<int32_t> staging((size_t)hpages);
+  if (hpages > 0 && tq_pagepool_alloc(p->pool, hpages, staging.data()) != TQ_OK)
+    return fail(TQ_ENOMEM, "no free pool page to stage %zu bytes of page tables", host_bytes);
+  const size_t tiles_at = L.tiles, dictl_at = L.dictl;
+  auto give_back = [&] {
+    if (hpages > 0) tq_pagepool_free(p->pool, staging.data(), hpages);
+  };
+  // copies: the raw bytes page by page, then the tables
+  hipError_t e = hipSuccess;
+  for (const tq_parquet_read& r : p->reads) {
+    int64_t done = 0;
+    for (int32_t id : r.pages) {
+      const int64_t n = std::min<int64_t>((int64_t)pb, r.bytes - done);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(raw + r.raw_off + done, tq_pagepool_page(p->pool, id), (size_t)n, hipMemcpyHostToDevice, stream);
+      done += n;
+    }
+  }
+  {
+    // pack the three tables into the staging pages back to back, then copy each table
+    std::vector<char> blob(host_bytes, 0);
+    size_t o = 0;
+    const size_t o_pages = o;
+    memcpy(blob.data() + o, pages.data(), pages.size() * sizeof(PqPage));
+    o += pages.size() * sizeof(PqPage);
+    const size_t o_tiles = o;
+    memcpy(blob.data() + o, tile_page.data(), tile_page.size() * 4);
+    o += tile_page.size() * 4;
+    const size_t o_dict = o;
+    memcpy(blob.data() + o, dict_pages.data(), dict_pages.size() * 4);
+    o += dict_pages.size() * 4;
+    for (int64_t i = 0; i < hpages; i++) {
+      const size_t at = (size_t)i * pb, n = std::min(pb, o > at ? o - at : 0);
+      if (n) memcpy(tq_pagepool_page(p->pool, staging[(size_t)i]), blob.data() + at, n);
+    }
+    // a host range [a, a + n) of the blob to device offset d
+    auto copy = [&](size_t a, size_t n, size_t d) {
+      while (n > 0 && e == hipSuccess) {
+        const size_t pg = a / pb, in = a % pb, take = std::min(n, pb - in);
+        e = hipMemcpyAsync(W + d, static_cast<char*>(tq_pagepool_page(p->pool, staging[pg])) + in, take,
+                           hipMemcpyHostToDevice, stream);
+        a += take;
+        d += take;
+        n -= take;
+      }
+    };
+    copy(o_pages, pages.size() * sizeof(PqPage), L.pages);
+    copy(o_tiles, tile_page.size() * 4, tiles_at);
+    copy(o_dict, dict_pages.size() * 4, dictl_at);
+  }
+  hipEvent_t copied = nullptr;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&copied, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(copied, stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_pq_init, dim3(1), dim3(1), 0, stream, hdr);
+    for (int32_t c = 0; c < ncol; c++)
+      if (po.valid[c]) {
+        const int64_t words = (p->rows + 31) / 32;
+        hipLaunchKernelGGL(k_pq_zero, dim3((int)std::max<int64_t>(1, std::min<int64_t>((words + 255) / 256, 1024))),
+                           dim3(256), 0, stream, po.valid[c], words);
+      }
+    // run counts and checkpoints start at zero: a walk that stops on an error leaves them so
+    const int64_t zwords = (int64_t)(L.runs - L.nruns) / 4;
+    hipLaunchKernelGGL(k_pq_zero, dim3((int)std::max<int64_t>(1, std::min<int64_t>((zwords + 255) / 256, 1024))),
+                       dim3(256), 0, stream, reinterpret_cast<uint32_t*>(W + L.nruns), zwords);
+    const PqPage* dp = reinterpret_cast<const PqPage*>(W + L.pages);
+    if (!dict_pages.empty())
+      hipLaunchKernelGGL(k_pq_dict, dim3((int)dict_pages.size()), dim3(kDecBlock), 0, stream, dp,
+                         reinterpret_cast<const int32_t*>(W + dictl_at), raw, reinterpret_cast<uint8_t*>(W + L.dict));
+    if (!pages.empty())
+      hipLaunchKernelGGL(k_pq_walk, dim3((int)(2 * pages.size())), dim3(64), 0, stream, dp, (int)pages.size(), raw,
+                         reinterpret_cast<PqRun*>(W + L.runs), reinterpret_cast<int32_t*>(W + L.nruns),
+                         reinterpret_cast<PqCk*>(W + L.cks), hdr);
+    if (p->tiles > 0)
+      hipLaunchKernelGGL(k_pq_decode, dim3((int)p->tiles), dim3(kDecBlock), 0, stream, dp,
+                         reinterpret_cast<const int32_t*>(W + tiles_at), raw, reinterpret_cast<const uint8_t*>(W + L.dict),
+                         reinterpret_cast<const PqRun*>(W + L.runs), reinterpret_cast<const int32_t*>(W + L.nruns),
+                         reinterpret_cast<const PqCk*>(W + L.cks), po, hdr);
+    e = hipGetLastError();
+  }
+  // the pool pages may be reused once the copies out of them have finished
+  hipError_t e2 = copied ? hipEventSynchronize(copied) : hipSuccess;
+  if (copied) (void)hipEventDestroy(copied);
+  if (e2 != hipSuccess && copied) {
+    // the copies' fate is unknown: keep the pages rather than hand them out again
+    return hip_fail(e2, "waiting for the page copies");
+  }
+  give_back();
+  pq_release_pages(p);
+  if (e != hipSuccess) return hip_fail(e, "parquet decode");
+  return TQ_OK;
+}
+
+}  // extern "C"

@@ -512,7 +512,8 @@ tq_status tq_check(const void* d_obj, hipStream_t stream) {
   TQ_HIP(hipStreamSynchronize(stream));
   uint32_t hdr[2];
   TQ_HIP(hipMemcpy(hdr, d_obj, sizeof hdr, hipMemcpyDeviceToHost));
-  if (hdr[0] != kTableMagic && hdr[0] != kStateMagic) return fail(TQ_EINVAL, "not a join table or group-by state");
+  if (hdr[0] != kTableMagic && hdr[0] != kStateMagic && hdr[0] != kScanMagic)
+    return fail(TQ_EINVAL, "not a join table, group-by state or Parquet work buffer");
   int32_t err = (int32_t)hdr[1];
   if (err) return fail(err, "%s latched by a kernel", tq_strerror(err));
   return TQ_OK;

@@ -107,6 +107,26 @@ def lib():
             "tq_dict_unify_scratch_bytes": (_sz, [_i64]),
             "tq_dict_unify": (_i32, [_vp, _sz, Strings, Strings, _vp, _sz, _vp, _vp]),
             "tq_dict_keys": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+            "tq_parquet_open": (_i32, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
+            "tq_parquet_close": (None, [_vp]),
+            "tq_parquet_num_rows": (_i64, [_vp]),
+            "tq_parquet_num_row_groups": (_i32, [_vp]),
+            "tq_parquet_row_group_rows": (_i64, [_vp, _i32]),
+            "tq_parquet_num_columns": (_i32, [_vp]),
+            "tq_parquet_column": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_i32),
+                                         ctypes.POINTER(_i32)]),
+            "tq_parquet_chunk": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                        ctypes.POINTER(_i32)]),
+            "tq_parquet_preload": (_i32, [_vp, _vp, _i32, _i32, _vp, _i32, _i64, ctypes.POINTER(_vp)]),
+            "tq_preload_num_reads": (_i32, [_vp]),
+            "tq_preload_read": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+            "tq_preload_rows": (_i64, [_vp]),
+            "tq_preload_work_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
+            "tq_preload_num_pages": (_i64, [_vp]),
+            "tq_preload_page": (_i32, [_vp, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+            "tq_parquet_decode": (_i32, [_vp, _vp, _sz, _vp, _vp]),
+            "tq_preload_free": (None, [_vp]),
             "tq_check": (_i32, [_vp, _vp]),
             "tq_read_peak_scratch_bytes": (_sz, []),
             "tq_read_peak": (_i32, [_vp, _sz, _vp, _vp]),
@@ -634,3 +654,108 @@ def serve_run(tables: ServeTables, reqs, workers: int, budget: Budget, arena, ma
     _check(L.tq_serve_run(ctypes.byref(tables), reqs, n, workers, budget.h, arena.data_ptr(), _nbytes(arena), max_groups,
                           keys.ctypes.data, count.ctypes.data, sums.ctypes.data, avg.ctypes.data, res))
     return res, keys, count, sums, avg
+
+
+# ----------------------------------------------------------------- Parquet scan
+
+class ParquetFile:
+    """tq_parquet_open and the metadata queries (host only)."""
+
+    def __init__(self, path: str):
+        h = ctypes.c_void_p()
+        _check(lib().tq_parquet_open(path.encode(), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().tq_parquet_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_rows(self) -> int:
+        return lib().tq_parquet_num_rows(self.h)
+
+    @property
+    def num_row_groups(self) -> int:
+        return lib().tq_parquet_num_row_groups(self.h)
+
+    def row_group_rows(self, rg: int) -> int:
+        return lib().tq_parquet_row_group_rows(self.h, rg)
+
+    def columns(self):
+        """[(name, type, nullable)] with type TQ_I32 / TQ_I64 (0: not decodable)."""
+        out = []
+        for c in range(lib().tq_parquet_num_columns(self.h)):
+            name, t, nl = ctypes.c_char_p(), _i32(), _i32()
+            _check(lib().tq_parquet_column(self.h, c, ctypes.byref(name), ctypes.byref(t), ctypes.byref(nl)))
+            out.append((name.value.decode(), t.value, bool(nl.value)))
+        return out
+
+    def chunk(self, rg: int, c: int):
+        off, n, codec = _i64(), _i64(), _i32()
+        _check(lib().tq_parquet_chunk(self.h, rg, c, ctypes.byref(off), ctypes.byref(n), ctypes.byref(codec)))
+        return off.value, n.value, codec.value
+
+    def preload(self, pool, rg0: int, rg1: int, cols: Sequence[int], merge_gap: int = 1 << 20) -> "Preload":
+        arr = (ctypes.c_int32 * max(1, len(cols)))(*cols)
+        h = ctypes.c_void_p()
+        _check(lib().tq_parquet_preload(self.h, getattr(pool, "h", pool), rg0, rg1, arr, len(cols), merge_gap,
+                                        ctypes.byref(h)))
+        return Preload(h, self)
+
+
+class Preload:
+    """tq_preload: the reads under way, the page walk, the decode."""
+
+    def __init__(self, h, owner):
+        self.h = h
+        self.owner = owner  # keeps the file open while the reads run
+
+    def reads(self):
+        out = []
+        for i in range(lib().tq_preload_num_reads(self.h)):
+            off, n = _i64(), _i64()
+            _check(lib().tq_preload_read(self.h, i, ctypes.byref(off), ctypes.byref(n)))
+            out.append((off.value, n.value))
+        return out
+
+    @property
+    def rows(self) -> int:
+        return lib().tq_preload_rows(self.h)
+
+    def work_bytes(self) -> int:
+        n = _sz()
+        _check(lib().tq_preload_work_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def pages(self):
+        """[(row0, nrows, col, kind, encoding)] after work_bytes()."""
+        out = []
+        for i in range(lib().tq_preload_num_pages(self.h)):
+            r0, nr, c, k, e = _i64(), _i32(), _i32(), _i32(), _i32()
+            _check(lib().tq_preload_page(self.h, i, ctypes.byref(r0), ctypes.byref(nr), ctypes.byref(c),
+                                         ctypes.byref(k), ctypes.byref(e)))
+            out.append((r0.value, nr.value, c.value, k.value, e.value))
+        return out
+
+    def decode(self, work, out_cols, stream=None):
+        """out_cols: [(data tensor, valid tensor or None)] in the preload's column order."""
+        arr = cols([d for d, _ in out_cols], [v for _, v in out_cols])
+        _check(lib().tq_parquet_decode(self.h, work.data_ptr(), _nbytes(work), arr, _stream(stream)))
+
+    def free(self):
+        if self.h:
+            lib().tq_preload_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,149 @@
+"""GPU: Parquet pages decoded by the scan kernels equal the columns pyarrow
+wrote (values bit-exact, NULL rows 0, validity bits exact): PLAIN and
+dictionary pages, a dictionary that falls back to PLAIN, data pages v1 and
+v2, optional columns with NULLs (none, some, all), several row groups and
+pages, column and row-group subsets; then a join + aggregate over decoded
+columns against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+pytest.importorskip("pyarrow")
+
+import oracle  # noqa: E402
+from paper_2508_05029_amd import pipeline, tq  # noqa: E402
+from paper_2508_05029_amd.datagen import workloads as wl  # noqa: E402
+from tests import pqfiles  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def decode(path, sel, rg0=None, rg1=None, page_bytes=1 << 20, merge_gap=1 << 20, valid_for_all=False):
+    f = tq.ParquetFile(path)
+    rg0 = 0 if rg0 is None else rg0
+    rg1 = f.num_row_groups if rg1 is None else rg1
+    pool = tq.PagePool(page_bytes, 512)
+    pl = f.preload(pool, rg0, rg1, sel, merge_gap=merge_gap)
+    n = pl.rows
+    work = torch.empty(pl.work_bytes(), dtype=torch.uint8, device=DEV)
+    meta = f.columns()
+    outs = []
+    for c in sel:
+        _, t, nullable = meta[c]
+        data = torch.full((max(n, 1),), -1, dtype=torch.int64 if t == 8 else torch.int32, device=DEV)
+        valid = (torch.full((((n + 31) // 32) * 4 or 4,), 0xAB, dtype=torch.uint8, device=DEV)
+                 if nullable or valid_for_all else None)
+        outs.append((data, valid))
+    pl.decode(work, outs)
+    tq.check(work)
+    pl.free()
+    assert pool.free_pages() == 512
+    res = []
+    for data, valid in outs:
+        v = data[:n].cpu().numpy()
+        bits = None if valid is None else np.unpackbits(valid.cpu().numpy(), bitorder="little")[:n].astype(bool)
+        res.append((v, bits))
+    return res, n
+
+
+def expect(cols, c, lo, hi):
+    name, vals, mask, _ = cols[c]
+    v = vals[lo:hi]
+    m = np.ones(hi - lo, bool) if mask is None else mask[lo:hi]
+    return np.where(m, v, 0), m
+
+
+def check(cols, sel, res, lo, hi):
+    for c, (v, bits) in zip(sel, res):
+        want, m = expect(cols, c, lo, hi)
+        assert v.tolist() == want.tolist(), cols[c][0]
+        if bits is not None:
+            assert bits.tolist() == m.tolist(), cols[c][0]
+
+
+@pytest.mark.parametrize("n,rg,page,version", [(50_000, 20_000, 16_384, "1.0"), (50_000, 20_000, 8_192, "2.0"),
+                                               (1, None, None, "1.0"), (1025, 1024, 512, "1.0"),
+                                               (300_000, None, 1 << 20, "1.0")])
+def test_decode_matches_written_columns(tmp_path, n, rg, page, version):
+    say(f"parquet decode n={n} rg={rg} page={page} v{version}")
+    cols = pqfiles.columns(n, 21)
+    path = pqfiles.write(str(tmp_path / "t.parquet"), cols, row_group_size=rg, data_page_size=page, version=version)
+    sel = list(range(len(cols)))
+    res, rows = decode(path, sel)
+    assert rows == n
+    check(cols, sel, res, 0, n)
+
+
+def test_dictionary_falling_back_to_plain(tmp_path):
+    cols = pqfiles.columns(400_000, 22)
+    path = pqfiles.write(str(tmp_path / "fb.parquet"), cols, dictionary_pagesize_limit=64 << 10,
+                         data_page_size=64 << 10)
+    res, n = decode(path, [2, 1])
+    check(cols, [2, 1], res, 0, n)
+
+
+def test_column_and_row_group_subsets(tmp_path):
+    cols = pqfiles.columns(100_000, 23)
+    path = pqfiles.write(str(tmp_path / "sub.parquet"), cols, row_group_size=30_000, data_page_size=32_768)
+    res, n = decode(path, [4, 0], rg0=1, rg1=3, merge_gap=0)
+    assert n == 60_000
+    check(cols, [4, 0], res, 30_000, 90_000)
+
+
+def test_required_column_with_a_bitmap_gets_all_ones(tmp_path):
+    cols = pqfiles.columns(5000, 24)
+    path = pqfiles.write(str(tmp_path / "req.parquet"), cols)
+    res, n = decode(path, [0, 3], valid_for_all=True)
+    for v, bits in res:
+        assert bits.all()
+    check(cols, [0, 3], res, 0, n)
+
+
+def test_scan_then_join_aggregate(tmp_path):
+    """The join + aggregate workload's tables, written to Parquet and scanned
+    back, feed the join: its result equals the oracle's on the original tables."""
+    nd, nf = 150_000, 600_000
+    dim, fact = wl.join_agg_tables(nd, nf, seed=25)
+    dcols = [(k, v, None, k == "group") for k, v in dim.items()]
+    fcols = [(k, v, None, k == "disc") for k, v in fact.items()]
+    dpath = pqfiles.write(str(tmp_path / "dim.parquet"), dcols, data_page_size=1 << 20)
+    fpath = pqfiles.write(str(tmp_path / "fact.parquet"), fcols, data_page_size=1 << 20)
+    dres, _ = decode(dpath, list(range(len(dcols))))
+    fres, _ = decode(fpath, list(range(len(fcols))))
+    ddev = {k: torch.from_numpy(v).to(DEV) for (k, _, _, _), (v, _) in zip(dcols, dres)}
+    fdev = {k: torch.from_numpy(v).to(DEV) for (k, _, _, _), (v, _) in zip(fcols, fres)}
+    q = wl.JOIN_AGG_QUERY
+    ja = pipeline.JoinAgg(q, nd, 0.5)
+    ja.run(ddev, fdev)
+    got = ja.result()
+    want = oracle.join_agg(dim, fact, q)
+    assert got["keys"].tolist() == want["keys"].tolist()
+    assert got["count"].tolist() == want["count"].tolist()
+    assert got["sums"].tolist() == want["sums"].tolist()
+
+
+def test_decode_rejects_bad_outputs(tmp_path):
+    cols = pqfiles.columns(1000, 26)
+    path = pqfiles.write(str(tmp_path / "o.parquet"), cols)
+    f = tq.ParquetFile(path)
+    pool = tq.PagePool(1 << 16, 64)
+    pl = f.preload(pool, 0, 1, [1], merge_gap=0)
+    work = torch.empty(pl.work_bytes(), dtype=torch.uint8, device=DEV)
+    data = torch.empty(1000, dtype=torch.int64, device=DEV)  # the column is INT32
+    with pytest.raises(tq.TqError):
+        pl.decode(work, [(data, torch.zeros(128, dtype=torch.uint8, device=DEV))])
+    data32 = torch.empty(1000, dtype=torch.int32, device=DEV)
+    with pytest.raises(tq.TqError, match="bitmap"):
+        pl.decode(work, [(data32, None)])  # nullable column without a bitmap
+    with pytest.raises(tq.TqError, match="work buffer"):
+        pl.decode(work[:256], [(data32, torch.zeros(128, dtype=torch.uint8, device=DEV))])
+    pl.free()
+    assert pool.free_pages() == 64
