@@ -670,7 +670,8 @@ tq_status tq_fill(void* d_dst, size_t bytes, uint32_t pattern, hipStream_t strea
  * compute task, which is left with decoding; Section 4 reads Parquet inputs).
  * Supported: flat schemas; INT32 and INT64 columns, required or optional;
  * data pages v1 and v2 in PLAIN or dictionary encoding (RLE_DICTIONARY /
- * PLAIN_DICTIONARY, dictionary pages PLAIN); uncompressed column chunks.
+ * PLAIN_DICTIONARY, dictionary pages PLAIN); column chunks uncompressed or
+ * Snappy-compressed (inflated on the GPU).
  * Other codecs, encodings, types and nested columns are rejected with
  * TQ_EINVAL when the file is opened or the preload is planned. */
 typedef struct tq_parquet tq_parquet;

@@ -338,7 +338,8 @@ tq_status pq_parse_pages(tq_preload* p) {
   if (p->parsed) return TQ_OK;
   const tq_parquet* pq = p->pq;
   std::vector<uint8_t> hdr;
-  int64_t row0 = 0, dict_bytes = 0, run_slots = 0, ck_slots = 0, tiles = 0;
+  int64_t row0 = 0, dict_bytes = 0, run_slots = 0, ck_slots = 0, tiles = 0, decomp_bytes = 0;
+  const int64_t decomp_base = align256(p->raw_bytes + 16);  // from the raw area's start
   std::vector<PqPage> pages;
   for (int32_t g = p->rg0; g < p->rg1; g++) {
     const PqRowGroup& rg = pq->rgs[(size_t)g];
@@ -363,18 +364,32 @@ tq_status pq_parse_pages(tq_preload* p) {
         if (t.bad || h.type < 0 || h.compressed < 0 || at + hbytes + h.compressed > end)
           return fail(TQ_EINVAL, "column %d: malformed page header at byte %lld", c, (long long)at);
         const int64_t data = raw + hbytes;  // the page body in the raw area
+        // a compressed body is inflated into the decompressed area (at
+        // decomp_base + decomp_bytes), which is where the kernels then read it
+        auto inflate = [&](PqPage& d, int64_t c_off, int64_t c_len, int64_t u_len) {
+          d.c_off = c_off;
+          d.c_len = c_len;
+          d.u_len = u_len;
+          d.u_off = decomp_base + decomp_bytes;
+          decomp_bytes += align256(u_len + 16);
+          return d.u_off;
+        };
+        const bool snappy = ch.codec == kPqSnappy;
+        if (h.uncompressed < 0 || (snappy && h.uncompressed > (1 << 30)))
+          return fail(TQ_EINVAL, "column %d: page size %d", c, h.uncompressed);
         if (h.type == kPqDictionaryPage) {
           if (h.dict_encoding != kPqPlain && h.dict_encoding != kPqPlainDictionary)
             return fail(TQ_EINVAL, "column %d: dictionary page encoding %d", c, h.dict_encoding);
-          if ((int64_t)h.dict_num_values * width > h.compressed)
+          const int64_t body_bytes = snappy ? h.uncompressed : h.compressed;
+          if ((int64_t)h.dict_num_values * width > body_bytes || h.dict_num_values < 0)
             return fail(TQ_EINVAL, "column %d: dictionary page too short", c);
           PqPage d{};
           d.kind = kPqDictionaryPage;
           d.col = (int32_t)ci;
-          d.val_off = data;
-          d.val_end = data + h.compressed;
+          d.val_off = snappy ? inflate(d, data, h.compressed, h.uncompressed) : data;
+          d.val_end = d.val_off + body_bytes;
           d.width = width;
-          d.dict_off = dict_bytes;  // relative to the dictionary area, fixed below
+          d.dict_off = dict_bytes;  // from the dictionary area's start
           d.dict_n = h.dict_num_values;
           d.def_off = -1;
           pages.push_back(d);
@@ -393,39 +408,38 @@ tq_status pq_parse_pages(tq_preload* p) {
             return fail(TQ_EINVAL, "column %d: page encoding %d is not supported", c, h.encoding);
           if (d.encoding == kPqRleDictionary && dict_off < 0)
             return fail(TQ_EINVAL, "column %d: dictionary-encoded page without a dictionary", c);
+          if (d.nrows < 0) return fail(TQ_EINVAL, "column %d: negative value count", c);
           d.dict_off = d.encoding == kPqRleDictionary ? dict_off : -1;
           d.dict_n = d.encoding == kPqRleDictionary ? dict_n : 0;
           const bool optional = col.repetition == kPqOptional;
-          int64_t body = data;
-          const int64_t body_end = data + h.compressed;
           if (h.type == kPqDataPage) {
-            if (optional) {
-              if (h.def_encoding != kPqRle) return fail(TQ_EINVAL, "column %d: level encoding %d", c, h.def_encoding);
-              uint8_t len4[4];
-              if (body + 4 > body_end || !copy_out(p, body, 4, len4))
-                return fail(TQ_EINVAL, "column %d: truncated page", c);
-              const int64_t len = (int64_t)len4[0] | (int64_t)len4[1] << 8 | (int64_t)len4[2] << 16 |
-                                  (int64_t)len4[3] << 24;
-              if (body + 4 + len > body_end) return fail(TQ_EINVAL, "column %d: levels past the page", c);
-              d.def_off = body + 4;
-              d.def_end = body + 4 + len;
-              body = d.def_end;
-            } else {
-              d.def_off = -1;
-            }
+            // levels and values are one body (compressed together); the
+            // levels' 4-byte length prefix is read on the device
+            if (optional && h.def_encoding != kPqRle)
+              return fail(TQ_EINVAL, "column %d: level encoding %d", c, h.def_encoding);
+            const int64_t body_bytes = snappy ? h.uncompressed : h.compressed;
+            d.val_off = snappy ? inflate(d, data, h.compressed, h.uncompressed) : data;
+            d.val_end = d.val_off + body_bytes;
+            d.def_off = optional ? kPqLevelsInBody : -1;
+            d.def_end = -1;
           } else {
             if (h.v2_rep_bytes != 0) return fail(TQ_EINVAL, "column %d: repetition levels", c);
             if (h.v2_def_bytes > 0 && !optional) return fail(TQ_EINVAL, "column %d: levels on a required column", c);
-            d.def_off = optional ? body : -1;
-            d.def_end = optional ? body + h.v2_def_bytes : -1;
-            body += h.v2_def_bytes;
+            if (h.v2_def_bytes < 0 || h.v2_def_bytes > h.compressed)
+              return fail(TQ_EINVAL, "column %d: level bytes %d", c, h.v2_def_bytes);
+            d.def_off = optional ? data : -1;  // the levels are never compressed
+            d.def_end = optional ? data + h.v2_def_bytes : -1;
+            const int64_t vc = h.compressed - h.v2_def_bytes;
+            const int64_t vu = h.uncompressed - h.v2_def_bytes;
+            const bool inflated = snappy && h.v2_compressed;
+            if (inflated && vu < 0) return fail(TQ_EINVAL, "column %d: page sizes", c);
+            d.val_off = inflated ? inflate(d, data + h.v2_def_bytes, vc, vu) : data + h.v2_def_bytes;
+            d.val_end = d.val_off + (inflated ? vu : vc);
           }
-          d.val_off = body;
-          d.val_end = body_end;
-          if (d.nrows < 0) return fail(TQ_EINVAL, "column %d: negative value count", c);
           // a run covers at least one item and takes at least one byte (its
           // header; levels, of bit width 1, also a value byte or a packed group)
-          d.max_def = optional ? std::min<int64_t>(d.nrows, (d.def_end - d.def_off) / 2) + 1 : 0;
+          const int64_t level_bytes = d.def_off == kPqLevelsInBody ? d.val_end - d.val_off : d.def_end - d.def_off;
+          d.max_def = optional ? std::min<int64_t>(d.nrows, level_bytes / 2) + 1 : 0;
           d.max_val = d.encoding == kPqRleDictionary ? std::min<int64_t>(d.nrows, d.val_end - d.val_off) + 1 : 0;
           d.runs_def = run_slots;
           d.runs_val = run_slots + d.max_def;
@@ -450,6 +464,7 @@ tq_status pq_parse_pages(tq_preload* p) {
     row0 += rg.num_rows;
   }
   p->pages = std::move(pages);
+  p->decomp_bytes = decomp_bytes;
   p->dict_bytes = dict_bytes;
   p->run_slots = run_slots;
   p->ck_slots = ck_slots;
@@ -463,10 +478,13 @@ PqLayout pq_layout(const tq_preload* p) {
   size_t at = 256;  // the header: magic, latched error
   L.raw = at;
   at += (size_t)align256(p->raw_bytes + 16);  // loads may read a few bytes past a stream's end
+  at += (size_t)p->decomp_bytes;               // inflated page bodies (each padded likewise)
   L.dict = at;
   at += (size_t)p->dict_bytes;
   L.pages = at;
   at += (size_t)align256((int64_t)(p->pages.size() * sizeof(PqPage)));
+  L.spans = at;
+  at += (size_t)align256((int64_t)(p->pages.size() * sizeof(PqSpan)));
   L.nruns = at;
   at += (size_t)align256((int64_t)p->pages.size() * 2 * 4);
   L.cks = at;
@@ -477,8 +495,12 @@ PqLayout pq_layout(const tq_preload* p) {
   for (const PqPage& d : p->pages) ndict += d.kind == kPqDictionaryPage;
   L.tiles = at;
   at += (size_t)align256(p->tiles * 4);
+  int64_t ncomp = 0;
+  for (const PqPage& d : p->pages) ncomp += d.c_len > 0;
   L.dictl = at;
   at += (size_t)align256(ndict * 4);
+  L.compl_ = at;
+  at += (size_t)align256(ncomp * 4);
   L.total = at;
   return L;
 }
@@ -653,8 +675,8 @@ tq_status tq_parquet_preload(tq_parquet* pq, tq_pagepool* pool, int32_t rg0, int
                   pq->cols[(size_t)c].type);
     for (int32_t g = rg0; g < rg1; g++) {
       const PqChunk& ch = pq->rgs[(size_t)g].chunks[(size_t)c];
-      if (ch.codec != 0)
-        return fail(TQ_EINVAL, "column %s: codec %d; the decoder takes uncompressed chunks",
+      if (ch.codec != 0 && ch.codec != kPqSnappy)
+        return fail(TQ_EINVAL, "column %s: codec %d; the decoder takes uncompressed or Snappy chunks",
                     pq->cols[(size_t)c].name.c_str(), ch.codec);
       if (ch.bytes > 0) ranges.push_back(Range{ch.start, ch.bytes});
     }

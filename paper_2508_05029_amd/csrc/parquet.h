@@ -17,6 +17,8 @@ enum PqType : int32_t { kPqBoolean = 0, kPqInt32 = 1, kPqInt64 = 2 };
 enum PqRepetition : int32_t { kPqRequired = 0, kPqOptional = 1, kPqRepeated = 2 };
 enum PqEncoding : int32_t { kPqPlain = 0, kPqPlainDictionary = 2, kPqRle = 3, kPqRleDictionary = 8 };
 enum PqPageType : int32_t { kPqDataPage = 0, kPqIndexPage = 1, kPqDictionaryPage = 2, kPqDataPageV2 = 3 };
+enum PqCodec : int32_t { kPqUncompressed = 0, kPqSnappy = 1 };
+constexpr int64_t kPqLevelsInBody = -2;  // def_off of a v1 page: the levels lead its body, after a 4-byte length
 
 struct PqColumn {
   std::string name;
@@ -37,15 +39,17 @@ struct PqRowGroup {
 };
 
 // One page as the kernels see it. Offsets are bytes from the start of the
-// raw area of the device work buffer.
+// raw area of the device work buffer (the decompressed area follows it).
 struct PqPage {
   int64_t row0;        // first output row (rows of all selected row groups, in order)
   int32_t nrows;       // rows (= level count of a flat column)
   int32_t col;         // output column (index into the call's column list)
-  int64_t def_off;     // definition levels (RLE/bit-packed hybrid, bit width 1); -1: none (a required column)
-  int64_t def_end;
-  int64_t val_off;     // values section
+  int64_t def_off;     // definition levels (RLE/bit-packed hybrid, bit width 1); -1: none (a required
+  int64_t def_end;     // column); kPqLevelsInBody: they lead the body [val_off, val_end)
+  int64_t val_off;     // values section (or the whole body, see def_off)
   int64_t val_end;
+  int64_t c_off, c_len;  // a Snappy-compressed body: its bytes in the raw area (c_len 0: not compressed)
+  int64_t u_off, u_len;  // and where it is inflated to (= val_off)
   int32_t encoding;    // kPqPlain, or dictionary indices (kPqRleDictionary)
   int32_t width;       // 4 or 8 bytes
   int64_t dict_off;    // dictionary values (aligned copy), from the dictionary area's start; -1 if none
@@ -61,6 +65,12 @@ struct PqPage {
 };
 
 constexpr int kPqTile = 1024;  // rows per decode workgroup, and the checkpoint spacing
+
+// A data page's level and value sections, fixed on the device once the page
+// is inflated (a v1 page's level length is inside its body).
+struct PqSpan {
+  int64_t def_off, def_end, val_off, val_end;
+};
 
 // Where item k * kPqTile of a stream lies: run `run`, with `before` items
 // equal to 1 ahead of it (definition levels: present rows before that row).
@@ -111,6 +121,7 @@ struct tq_preload {
   // page headers, parsed once the bytes are in host memory
   bool parsed = false;
   std::vector<tq::PqPage> pages;
+  int64_t decomp_bytes = 0;
   int64_t dict_bytes = 0;
   int64_t run_slots = 0;
   int64_t ck_slots = 0;
@@ -123,11 +134,12 @@ size_t pq_work_bytes(const tq_preload* p);
 tq_status pq_join(tq_preload* p);
 void pq_release_pages(tq_preload* p);
 
-// Device work buffer of a decode: header | raw bytes | dictionaries | page
-// descriptors | run counts | checkpoints | run tables | tile -> page map |
-// dictionary page list (each part 256-aligned).
+// Device work buffer of a decode: header | raw bytes | inflated page bodies |
+// dictionaries | page descriptors | spans | run counts | checkpoints | run
+// tables | tile -> page map | dictionary page list | compressed page list
+// (each part 256-aligned).
 struct PqLayout {
-  size_t raw, dict, pages, nruns, cks, runs, tiles, dictl, total;
+  size_t raw, dict, pages, spans, nruns, cks, runs, tiles, dictl, compl_, total;
 };
 PqLayout pq_layout(const tq_preload* p);
 }  // namespace tq

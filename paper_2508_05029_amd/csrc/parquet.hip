@@ -1,12 +1,14 @@
 // Parquet scan, device side: decodes the pages of preloaded column chunks
 // into Arrow columns (values + validity bitmap). Section 3.3.3 leaves the
 // compute task only decompression and decoding once the byte ranges are in
-// memory; these kernels are that decoding, for uncompressed INT32 / INT64
-// pages in PLAIN or dictionary (RLE_DICTIONARY) encoding, flat columns,
-// required or optional (definition levels).
+// memory; these kernels are that work, for INT32 / INT64 pages in PLAIN or
+// dictionary (RLE_DICTIONARY) encoding, flat columns, required or optional
+// (definition levels), uncompressed or Snappy-compressed.
 //
 // The definition levels and the dictionary indices are RLE/bit-packed hybrid
 // streams, whose runs can only be found one after another. So:
+//   k_pq_snappy inflates each compressed page body (one wave per page);
+//   k_pq_span   finds each page's level and value sections;
 //   k_pq_dict   copies each dictionary page's values to an aligned array;
 //   k_pq_walk   one wave per (page, stream) walks the run headers out of an
 //               LDS window of the stream (one lane; the wave stages the bytes)
@@ -62,6 +64,166 @@ __global__ void k_pq_zero(uint32_t* words, int64_t n) {
     words[i] = 0u;
 }
 
+// ------------------------------------------------------------------ Snappy
+//
+// One wave per compressed page body. The format (Snappy's raw block: the
+// uncompressed length as a varint, then elements: a literal of n bytes that
+// follow its tag, or a copy of n bytes from `offset` bytes back in the
+// output, which may overlap what it writes) is sequential, so every lane
+// parses the same element headers out of an LDS window of the input, and the
+// lanes then move the element's bytes in parallel. The output goes through
+// a 64 KiB LDS ring holding the last 64 KiB written (every copy offset below
+// 65536 reads from it) and is written to the device buffer 8 KiB at a time.
+// A wave's LDS accesses take effect in program order, so a lane reads the
+// bytes other lanes wrote for earlier elements without a barrier.
+constexpr int kRing = 65536;
+constexpr int kFlushBytes = 8192;
+constexpr int kInWin = 4096;
+
+__device__ __forceinline__ uint32_t in_byte(const uint32_t* w, int64_t i) { return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu; }
+
+__global__ __launch_bounds__(64) void k_pq_snappy(const PqPage* pages, const int32_t* cpages, uint8_t* raw,
+                                                  PqHeader* hdr) {
+  __shared__ uint32_t ring[kRing / 4];
+  __shared__ uint32_t win[kInWin / 4 + 4];
+  uint8_t* rb = reinterpret_cast<uint8_t*>(ring);
+  const PqPage pg = pages[cpages[blockIdx.x]];
+  const uint8_t* in = raw + pg.c_off;
+  const int64_t in_len = pg.c_len, out_len = pg.u_len;
+  uint8_t* out = raw + pg.u_off;
+  const int lane = threadIdx.x;
+  // the input window holds input bytes [wbase, wbase + kInWin), loaded as
+  // aligned dwords of the raw area (wbase may be up to 3 bytes before 0)
+  int64_t wbase = INT64_MIN / 2;
+  auto window = [&](int64_t at) {  // uniform: every lane asks for the same position
+    if (at >= wbase && at + 8 <= wbase + kInWin) return;
+    const int64_t abs0 = (pg.c_off + at) & ~(int64_t)3;
+    wbase = abs0 - pg.c_off;
+    for (int i = lane; i < kInWin / 4 + 4; i += 64) {
+      const int64_t a = abs0 + 4 * (int64_t)i;  // a dword starting before the input's end stays in the padded area
+      win[i] = a < pg.c_off + in_len ? *reinterpret_cast<const uint32_t*>(raw + a) : 0u;
+    }
+    __syncthreads();
+  };
+  auto ib = [&](int64_t at) { return in_byte(win, at - wbase); };
+  bool bad = false;
+  // the uncompressed length
+  window(0);
+  uint64_t ulen = 0;
+  int64_t ip = 0;
+  for (int sh = 0;; sh += 7) {
+    const uint32_t b = ip < in_len ? ib(ip) : 0x80u;
+    ip++;
+    ulen |= (uint64_t)(b & 0x7f) << sh;
+    if (!(b & 0x80)) break;
+    if (sh >= 28 || ip >= in_len) {
+      bad = true;
+      break;
+    }
+  }
+  if (ulen != (uint64_t)out_len) bad = true;
+  int64_t q = 0, flushed = 0;
+  // writes the ring's final bytes out in whole chunks below `upto` (a chunk
+  // boundary), or everything left once upto is the output's end
+  auto flush_to = [&](int64_t upto) {
+    while (flushed + kFlushBytes <= upto || (upto == out_len && flushed < out_len)) {
+      const int64_t n = min((int64_t)kFlushBytes, out_len - flushed);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(out + flushed);  // the output area is 256-aligned and padded
+      const int base = (int)((flushed & (kRing - 1)) >> 2);
+      for (int i = lane; i < (int)((n + 3) >> 2); i += 64) dst[i] = ring[base + i];
+      flushed += n;
+    }
+  };
+  while (!bad && q < out_len) {
+    window(ip);
+    if (ip >= in_len) {
+      bad = true;
+      break;
+    }
+    const uint32_t tag = ib(ip);
+    int64_t len, off = 0, src = 0;
+    const bool literal = (tag & 3) == 0;
+    if (literal) {
+      const uint32_t l6 = tag >> 2;
+      if (l6 < 60) {
+        len = (int64_t)l6 + 1;
+        ip += 1;
+      } else {
+        const int nb = (int)l6 - 59;
+        uint64_t v = 0;
+        for (int k = 0; k < nb; k++) v |= (uint64_t)ib(ip + 1 + k) << (8 * k);
+        len = (int64_t)v + 1;
+        ip += 1 + nb;
+      }
+      src = ip;
+      ip += len;
+      if (ip > in_len) bad = true;
+    } else if ((tag & 3) == 1) {
+      len = 4 + ((tag >> 2) & 7);
+      off = (int64_t)((tag >> 5) << 8) | ib(ip + 1);
+      ip += 2;
+    } else if ((tag & 3) == 2) {
+      len = (int64_t)(tag >> 2) + 1;
+      off = (int64_t)ib(ip + 1) | (int64_t)ib(ip + 2) << 8;
+      ip += 3;
+    } else {
+      len = (int64_t)(tag >> 2) + 1;
+      off = (int64_t)ib(ip + 1) | (int64_t)ib(ip + 2) << 8 | (int64_t)ib(ip + 3) << 16 | (int64_t)ib(ip + 4) << 24;
+      ip += 5;
+    }
+    if (!literal && (off <= 0 || off > q)) bad = true;
+    if (q + len > out_len || ip > in_len) bad = true;
+    if (bad) break;
+    const bool far = !literal && off >= kRing;  // the source has left the ring: read the output written
+    if (far) {
+      flush_to(q & ~(int64_t)(kFlushBytes - 1));  // every source byte lies below (q - off + 64 < q - 8 KiB)
+      __threadfence();  // those stores are visible before the loads below
+    }
+    for (int64_t s0 = 0; s0 < len; s0 += kFlushBytes) {
+      const int64_t pl = min((int64_t)kFlushBytes, len - s0);
+      // the ring slots about to be written must have been flushed
+      const int64_t need = q + s0 + pl - kRing;  // at most q + s0 - 56 KiB: those bytes are final
+      if (need > flushed) flush_to(((need + kFlushBytes - 1) / kFlushBytes) * kFlushBytes);
+      for (int64_t i = lane; i < pl; i += 64) {
+        const int64_t j = s0 + i;  // byte j of the element
+        uint8_t b;
+        if (literal) b = in[src + j];
+        else {
+          const int64_t sp = q - off + (j % off);
+          b = far ? out[sp] : rb[sp & (kRing - 1)];
+        }
+        rb[(q + j) & (kRing - 1)] = b;
+      }
+    }
+    q += len;
+  }
+  if (!bad) flush_to(out_len);
+  if (bad && lane == 0) pq_error(hdr, TQ_EINVAL);
+}
+
+// The level and value sections of every page, once bodies are inflated.
+__global__ void k_pq_span(const PqPage* pages, int npages, const uint8_t* raw, PqSpan* spans, PqHeader* hdr) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npages; i += gridDim.x * blockDim.x) {
+    const PqPage pg = pages[i];
+    PqSpan sp{pg.def_off, pg.def_end, pg.val_off, pg.val_end};
+    if (pg.def_off == kPqLevelsInBody) {
+      if (pg.val_off + 4 > pg.val_end) {
+        pq_error(hdr, TQ_EINVAL);
+        sp = PqSpan{-1, -1, pg.val_end, pg.val_end};
+      } else {
+        const int64_t len = (int64_t)(uint32_t)ld_le(raw, pg.val_off, 4);
+        if (pg.val_off + 4 + len > pg.val_end) {
+          pq_error(hdr, TQ_EINVAL);
+          sp = PqSpan{pg.val_off + 4, pg.val_off + 4, pg.val_end, pg.val_end};
+        } else {
+          sp = PqSpan{pg.val_off + 4, pg.val_off + 4 + len, pg.val_off + 4 + len, pg.val_end};
+        }
+      }
+    }
+    spans[i] = sp;
+  }
+}
+
 // One workgroup per dictionary page.
 __global__ __launch_bounds__(kDecBlock) void k_pq_dict(const PqPage* pages, const int32_t* dict_pages,
                                                        const uint8_t* raw, uint8_t* dict) {
@@ -97,24 +259,23 @@ __device__ uint32_t ones_prefix(const uint32_t* win, int64_t wbase, int64_t wend
 
 // One 64-lane workgroup per (data page, stream): stream 0 the definition
 // levels, stream 1 the dictionary indices.
-__global__ __launch_bounds__(64) void k_pq_walk(const PqPage* pages, int npages, const uint8_t* raw, PqRun* runs,
-                                                int32_t* nruns, PqCk* cks, PqHeader* hdr) {
+__global__ __launch_bounds__(64) void k_pq_walk(const PqPage* pages, const PqSpan* spans, int npages,
+                                                const uint8_t* raw, PqRun* runs, int32_t* nruns, PqCk* cks,
+                                                PqHeader* hdr) {
   __shared__ uint32_t win[kWalkWin / 4 + 4];
   __shared__ int64_t s_pos, s_items, s_before;
   __shared__ int32_t s_nr, s_ck, s_done;
   const int pi = blockIdx.x >> 1, s = blockIdx.x & 1;
   const PqPage pg = pages[pi];
+  const PqSpan sp = spans[pi];
   if (pg.kind != kPqDataPage) return;
-  if (s == 0 && pg.def_off < 0) return;
+  if (s == 0 && sp.def_off < 0) return;
   if (s == 1 && pg.encoding != kPqRleDictionary) return;
-  const int64_t end = s == 0 ? pg.def_end : pg.val_end;
+  const int64_t end = s == 0 ? sp.def_end : sp.val_end;
   int bw = 1;
   if (s == 1) {
-    if (pg.val_off >= pg.val_end) {
-      if (threadIdx.x == 0 && pg.nrows > 0) nruns[2 * pi + 1] = 0;
-      return;
-    }
-    bw = raw[pg.val_off];  // the index bit width leads the stream
+    if (sp.val_off >= sp.val_end) return;  // no values: the run count stays 0
+    bw = raw[sp.val_off];  // the index bit width leads the stream
     if (bw > 32) {
       if (threadIdx.x == 0) pq_error(hdr, TQ_EINVAL);
       return;
@@ -126,7 +287,7 @@ __global__ __launch_bounds__(64) void k_pq_walk(const PqPage* pages, int npages,
   const int64_t nck = ((int64_t)pg.nrows + kPqTile - 1) / kPqTile;
   const int vbytes = (bw + 7) / 8;
   if (threadIdx.x == 0) {
-    s_pos = s == 0 ? pg.def_off : pg.val_off + 1;
+    s_pos = s == 0 ? sp.def_off : sp.val_off + 1;
     s_items = 0;
     s_before = 0;
     s_nr = 0;
@@ -294,7 +455,8 @@ struct PqOut {
   uint32_t* valid[TQ_MAX_COLS];
 };
 
-__global__ __launch_bounds__(kDecBlock) void k_pq_decode(const PqPage* pages, const int32_t* tile_page,
+__global__ __launch_bounds__(kDecBlock) void k_pq_decode(const PqPage* pages, const PqSpan* spans,
+                                                         const int32_t* tile_page,
                                                          const uint8_t* raw, const uint8_t* dict, const PqRun* runs,
                                                          const int32_t* nruns, const PqCk* cks, PqOut out,
                                                          PqHeader* hdr) {
@@ -304,11 +466,12 @@ __global__ __launch_bounds__(kDecBlock) void k_pq_decode(const PqPage* pages, co
   __shared__ int s_n, s_at;
   const int pi = tile_page[blockIdx.x];
   const PqPage pg = pages[pi];
+  const PqSpan sp = spans[pi];
   const int64_t k = blockIdx.x - pg.tile0;
   const int64_t t0 = k * kPqTile;  // first row of the tile in the page
   const int tid = threadIdx.x;
   const int rows = (int)min((int64_t)kPqTile, (int64_t)pg.nrows - t0);
-  const bool optional = pg.def_off >= 0;
+  const bool optional = sp.def_off >= 0;
   // levels: present bits of this thread's rows
   uint32_t present = 0;  // bit i: row tid * kDecRows + i
   int64_t pres0 = t0;    // present rows of the page before the tile
@@ -348,8 +511,8 @@ __global__ __launch_bounds__(kDecBlock) void k_pq_decode(const PqPage* pages, co
 #pragma unroll
     for (int i = 0; i < kDecRows; i++) {
       if (present >> i & 1u) {
-        const int64_t at = pg.val_off + v * w;
-        if (at + w > pg.val_end) pq_error(hdr, TQ_EINVAL);
+        const int64_t at = sp.val_off + v * w;
+        if (at + w > sp.val_end) pq_error(hdr, TQ_EINVAL);
         else val[i] = ld_le(raw, at, w);
         v++;
       }
@@ -448,15 +611,17 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
   // host tables: descriptors with offsets made absolute where the kernels want
   // them, the tile -> page map, the dictionary pages; staged through pool pages
   std::vector<PqPage> pages = p->pages;
-  std::vector<int32_t> tile_page((size_t)p->tiles), dict_pages;
+  std::vector<int32_t> tile_page((size_t)p->tiles), dict_pages, comp_pages;
   for (size_t i = 0; i < pages.size(); i++) {
     const PqPage& d = pages[i];
+    if (d.c_len > 0) comp_pages.push_back((int32_t)i);
     if (d.kind == kPqDictionaryPage) dict_pages.push_back((int32_t)i);
     else
       for (int64_t t = 0; t < ((int64_t)d.nrows + kPqTile - 1) / kPqTile; t++) tile_page[(size_t)(d.tile0 + t)] = (int32_t)i;
   }
   const size_t pb = tq_pagepool_page_bytes(p->pool);
-  const size_t host_bytes = pages.size() * sizeof(PqPage) + tile_page.size() * 4 + dict_pages.size() * 4 + 64;
+  const size_t host_bytes =
+      pages.size() * sizeof(PqPage) + tile_page.size() * 4 + dict_pages.size() * 4 + comp_pages.size() * 4 + 64;
   const int64_t hpages = (int64_t)((host_bytes + pb - 1) / pb);
   std::vector<int32_t> staging((size_t)hpages);
   if (hpages > 0 && tq_pagepool_alloc(p->pool, hpages, staging.data()) != TQ_OK)
@@ -489,6 +654,9 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
     const size_t o_dict = o;
     memcpy(blob.data() + o, dict_pages.data(), dict_pages.size() * 4);
     o += dict_pages.size() * 4;
+    const size_t o_comp = o;
+    memcpy(blob.data() + o, comp_pages.data(), comp_pages.size() * 4);
+    o += comp_pages.size() * 4;
     for (int64_t i = 0; i < hpages; i++) {
       const size_t at = (size_t)i * pb, n = std::min(pb, o > at ? o - at : 0);
       if (n) memcpy(tq_pagepool_page(p->pool, staging[(size_t)i]), blob.data() + at, n);
@@ -507,6 +675,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
     copy(o_pages, pages.size() * sizeof(PqPage), L.pages);
     copy(o_tiles, tile_page.size() * 4, tiles_at);
     copy(o_dict, dict_pages.size() * 4, dictl_at);
+    copy(o_comp, comp_pages.size() * 4, L.compl_);
   }
   hipEvent_t copied = nullptr;
   if (e == hipSuccess) e = hipEventCreateWithFlags(&copied, hipEventDisableTiming);
@@ -524,15 +693,22 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
     hipLaunchKernelGGL(k_pq_zero, dim3((int)std::max<int64_t>(1, std::min<int64_t>((zwords + 255) / 256, 1024))),
                        dim3(256), 0, stream, reinterpret_cast<uint32_t*>(W + L.nruns), zwords);
     const PqPage* dp = reinterpret_cast<const PqPage*>(W + L.pages);
+    PqSpan* spans = reinterpret_cast<PqSpan*>(W + L.spans);
+    if (!comp_pages.empty())
+      hipLaunchKernelGGL(k_pq_snappy, dim3((int)comp_pages.size()), dim3(64), 0, stream, dp,
+                         reinterpret_cast<const int32_t*>(W + L.compl_), raw, hdr);
+    if (!pages.empty())
+      hipLaunchKernelGGL(k_pq_span, dim3((int)std::min<size_t>((pages.size() + 255) / 256, 1024)), dim3(256), 0,
+                         stream, dp, (int)pages.size(), raw, spans, hdr);
     if (!dict_pages.empty())
       hipLaunchKernelGGL(k_pq_dict, dim3((int)dict_pages.size()), dim3(kDecBlock), 0, stream, dp,
                          reinterpret_cast<const int32_t*>(W + dictl_at), raw, reinterpret_cast<uint8_t*>(W + L.dict));
     if (!pages.empty())
-      hipLaunchKernelGGL(k_pq_walk, dim3((int)(2 * pages.size())), dim3(64), 0, stream, dp, (int)pages.size(), raw,
+      hipLaunchKernelGGL(k_pq_walk, dim3((int)(2 * pages.size())), dim3(64), 0, stream, dp, spans, (int)pages.size(), raw,
                          reinterpret_cast<PqRun*>(W + L.runs), reinterpret_cast<int32_t*>(W + L.nruns),
                          reinterpret_cast<PqCk*>(W + L.cks), hdr);
     if (p->tiles > 0)
-      hipLaunchKernelGGL(k_pq_decode, dim3((int)p->tiles), dim3(kDecBlock), 0, stream, dp,
+      hipLaunchKernelGGL(k_pq_decode, dim3((int)p->tiles), dim3(kDecBlock), 0, stream, dp, spans,
                          reinterpret_cast<const int32_t*>(W + tiles_at), raw, reinterpret_cast<const uint8_t*>(W + L.dict),
                          reinterpret_cast<const PqRun*>(W + L.runs), reinterpret_cast<const int32_t*>(W + L.nruns),
                          reinterpret_cast<const PqCk*>(W + L.cks), po, hdr);

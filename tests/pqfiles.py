@@ -1,7 +1,7 @@
 """Parquet files for the scan tests, written by pyarrow from seeded columns."""
 import numpy as np
 
-from paper_2508_05029_amd.datagen import uniform
+from paper_2508_05029_amd.datagen import uniform  # noqa: F401 (also used by the tests)
 
 pa = None
 pq = None

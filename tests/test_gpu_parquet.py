@@ -69,13 +69,19 @@ def check(cols, sel, res, lo, hi):
             assert bits.tolist() == m.tolist(), cols[c][0]
 
 
-@pytest.mark.parametrize("n,rg,page,version", [(50_000, 20_000, 16_384, "1.0"), (50_000, 20_000, 8_192, "2.0"),
-                                               (1, None, None, "1.0"), (1025, 1024, 512, "1.0"),
-                                               (300_000, None, 1 << 20, "1.0")])
-def test_decode_matches_written_columns(tmp_path, n, rg, page, version):
-    say(f"parquet decode n={n} rg={rg} page={page} v{version}")
+@pytest.mark.parametrize("n,rg,page,version,codec", [(50_000, 20_000, 16_384, "1.0", "NONE"),
+                                                     (50_000, 20_000, 8_192, "2.0", "NONE"),
+                                                     (1, None, None, "1.0", "NONE"), (1025, 1024, 512, "1.0", "NONE"),
+                                                     (300_000, None, 1 << 20, "1.0", "NONE"),
+                                                     (50_000, 20_000, 16_384, "1.0", "snappy"),
+                                                     (50_000, 20_000, 8_192, "2.0", "snappy"),
+                                                     (1, None, None, "1.0", "snappy"),
+                                                     (300_000, None, 1 << 20, "1.0", "snappy")])
+def test_decode_matches_written_columns(tmp_path, n, rg, page, version, codec):
+    say(f"parquet decode n={n} rg={rg} page={page} v{version} {codec}")
     cols = pqfiles.columns(n, 21)
-    path = pqfiles.write(str(tmp_path / "t.parquet"), cols, row_group_size=rg, data_page_size=page, version=version)
+    path = pqfiles.write(str(tmp_path / "t.parquet"), cols, row_group_size=rg, data_page_size=page, version=version,
+                         compression=codec)
     sel = list(range(len(cols)))
     res, rows = decode(path, sel)
     assert rows == n
@@ -147,3 +153,20 @@ def test_decode_rejects_bad_outputs(tmp_path):
         pl.decode(work[:256], [(data32, torch.zeros(128, dtype=torch.uint8, device=DEV))])
     pl.free()
     assert pool.free_pages() == 64
+
+
+def test_snappy_repeats_and_runs(tmp_path):
+    """Snappy bodies of 4 MiB pages with copies of every length class and
+    overlapping copies (runs of one value): a column of repeated blocks with
+    short repeats, a long run, and a constant column. (The reference
+    compressor never copies from further back than 64 KiB, so the kernel's
+    path for such copies is not reached by files pyarrow writes.)"""
+    n = 400_000
+    block = pqfiles.uniform(20_000, -2 ** 62, 2 ** 62, np.int64, 27, 0)
+    vals = np.concatenate([block] * (n // 20_000))
+    vals[::7] = 5  # short repeats
+    vals[1000:9000] = 0  # a long run
+    cols = [("rep", vals, None, False), ("run", np.full(n, 3, np.int64), None, False)]
+    path = pqfiles.write(str(tmp_path / "rep.parquet"), cols, data_page_size=4 << 20, compression="snappy")
+    res, rows = decode(path, [0, 1])
+    check(cols, [0, 1], res, 0, rows)

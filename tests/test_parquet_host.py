@@ -101,11 +101,16 @@ def test_version_2_pages_walk(tmp_path):
 
 def test_refused_files(tmp_path):
     cols = pqfiles.columns(1000, 11)
-    snappy = pqfiles.write(str(tmp_path / "s.parquet"), cols, compression="snappy")
+    gz = pqfiles.write(str(tmp_path / "g.parquet"), cols, compression="gzip")
     pool = tq.PagePool(1 << 16, 16, pinned=False)
-    f = tq.ParquetFile(snappy)
+    f = tq.ParquetFile(gz)
     with pytest.raises(tq.TqError, match="codec"):
         f.preload(pool, 0, 1, [0], merge_gap=0)
+    # Snappy chunks are taken (inflated on the GPU)
+    sn = tq.ParquetFile(pqfiles.write(str(tmp_path / "s.parquet"), cols, compression="snappy"))
+    pl = sn.preload(pool, 0, 1, [0, 1], merge_gap=0)
+    assert pl.work_bytes() > 0
+    pl.free()
     # strings and nested columns
     pa = pyarrow
     pq.write_table(pa.table({"s": pa.array(["a", "b"])}), str(tmp_path / "str.parquet"), compression="NONE")
@@ -122,7 +127,7 @@ def test_refused_files(tmp_path):
     bad.write_bytes(b"PAR1" + b"\0" * 100)
     with pytest.raises(tq.TqError):
         tq.ParquetFile(str(bad))
-    raw = open(snappy, "rb").read()
+    raw = open(gz, "rb").read()
     (tmp_path / "cut.parquet").write_bytes(raw[: len(raw) // 2])
     with pytest.raises(tq.TqError):
         tq.ParquetFile(str(tmp_path / "cut.parquet"))
