@@ -16,7 +16,7 @@ consecutive steps alternate between --streams streams, each with its own table
 and group-by state (several compute streams, each running whole tasks, as the
 paper's executor does), so that one step's short kernels overlap another's.
 
-Prints ONE JSON line. Other workloads: --workload filter_groupby | ooc | batched | serving | scaling | copy.
+Prints ONE JSON line. Other workloads: --workload filter_groupby | ooc | batched | serving | scaling | copy | scan.
 """
 import argparse
 import json
@@ -303,7 +303,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="join_agg",
-                    choices=["join_agg", "filter_groupby", "ooc", "batched", "serving", "copy", "scaling"])
+                    choices=["join_agg", "filter_groupby", "ooc", "batched", "serving", "copy", "scaling", "scan"])
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--graph-steps", type=int, default=8)
     ap.add_argument("--streams", type=int, default=2, help="join_agg, filter_groupby: compute streams the steps alternate between")

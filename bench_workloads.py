@@ -663,3 +663,90 @@ def bench_copy(args):
                   "roofline": {"bound": "hbm", "achieved": round(rd, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(rd / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_read_peak"},
                   "cpu_baseline": None})
+
+
+# ------------------------------------------------------------------ Parquet scan
+
+def _write_parquet(path, table, codec, page_bytes=1 << 20, row_group_rows=None):
+    import pyarrow as pa
+    import pyarrow.parquet as pq
+    arrays = {k: pa.array(v) for k, v in table.items()}
+    schema = pa.schema([pa.field(k, a.type, nullable=False) for k, a in arrays.items()])
+    pq.write_table(pa.Table.from_pydict(arrays, schema=schema), path, compression=codec, data_page_size=page_bytes,
+                   row_group_size=row_group_rows)
+    import os
+    return os.path.getsize(path)
+
+
+def bench_scan(args):
+    """The join + aggregate tables (1.5M x 6M rows) as Parquet files with 1 MiB
+    pages, dictionary encoding where it fits (pyarrow's default), Snappy and
+    uncompressed. A step: preload both files' byte ranges into pool pages,
+    decode them on the GPU, run the join + aggregate on the decoded columns."""
+    import os
+    import shutil
+    import tempfile
+    import oracle
+    n_dim, n_fact = 1_500_000, 6_000_000
+    dim, fact = wl.join_agg_tables(n_dim, n_fact)
+    q = wl.JOIN_AGG_QUERY
+    want = oracle.join_agg(dim, fact, q)
+    tmp = tempfile.mkdtemp(prefix="tq_scan_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    out = {}
+    try:
+        pool = tq.PagePool(16 << 20, 64)  # 1 GiB of pinned pages
+        value_bytes = n_dim * 16 + n_fact * 24
+        for codec in ("snappy", "NONE"):
+            dpath, fpath = os.path.join(tmp, f"dim_{codec}.parquet"), os.path.join(tmp, f"fact_{codec}.parquet")
+            file_bytes = _write_parquet(dpath, dim, codec) + _write_parquet(fpath, fact, codec)
+            ds = pipeline.ParquetScan(dpath, list(dim), pool)
+            fs = pipeline.ParquetScan(fpath, list(fact), pool)
+            ja = pipeline.JoinAgg(q, n_dim, 0.5)
+            stream = torch.cuda.current_stream()
+
+            def step():
+                t0 = time.perf_counter()
+                dpl, fpl = ds.preload(), fs.preload()  # both files' reads start at once
+                dpl.work_bytes()
+                fpl.work_bytes()
+                t1 = time.perf_counter()
+                a, b = _events()
+                a.record(stream)
+                dd, _ = ds.decode(dpl)
+                ff, _ = fs.decode(fpl)
+                b.record(stream)
+                ja.run(dd, ff)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                dpl.free()
+                fpl.free()
+                return (t1 - t0) * 1e3, a.elapsed_time(b), (t2 - t0) * 1e3
+
+            for _ in range(max(2, args.warmup // 8)):
+                step()
+            ds.check()
+            fs.check()
+            got = ja.result()
+            equal = (got["keys"][:, 0].tolist() == want["keys"][:, 0].tolist() and
+                     got["count"].tolist() == want["count"].tolist() and got["sums"].tolist() == want["sums"].tolist())
+            k = min(args.steps, 10)
+            runs = [step() for _ in range(k)]
+            pre = float(np.median([r[0] for r in runs]))
+            dec = float(np.median([r[1] for r in runs]))
+            tot = float(np.median([r[2] for r in runs]))
+            out[codec] = {"file_bytes": file_bytes, "value_bytes": value_bytes, "ms_preload": round(pre, 3),
+                          "ms_copy_and_decode": round(dec, 3), "ms_step": round(tot, 3),
+                          "file_gbs_preload": round(file_bytes / pre / 1e6, 2),
+                          "decoded_gbs": round(value_bytes / dec / 1e6, 2),
+                          "result_equals_oracle": equal}
+            log(codec, out[codec])
+            pool_free = pool.free_pages()
+            assert pool_free == 64, pool_free
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    s = out["snappy"]
+    return _base("Parquet scan + join-aggregate: decoded GB/s (file bytes preloaded, copied, decoded on the GPU)",
+                 s["value_bytes"] / s["ms_step"] / 1e6, "GB/s", args, s["ms_step"], min(args.steps, 10),
+                 "scan: dim 1.5M + fact 6M rows as Parquet (1 MiB pages, pyarrow dictionary default), Snappy; "
+                 "preload -> decode -> join+aggregate per step",
+                 {"codecs": out, "roofline": None, "cpu_baseline": None})

@@ -338,7 +338,7 @@ tq_status pq_parse_pages(tq_preload* p) {
   if (p->parsed) return TQ_OK;
   const tq_parquet* pq = p->pq;
   std::vector<uint8_t> hdr;
-  int64_t row0 = 0, dict_bytes = 0, run_slots = 0, ck_slots = 0, tiles = 0, decomp_bytes = 0;
+  int64_t row0 = 0, dict_bytes = 0, run_slots = 0, ck_slots = 0, tiles = 0, decomp_bytes = 0, frags = 0;
   const int64_t decomp_base = align256(p->raw_bytes + 16);  // from the raw area's start
   std::vector<PqPage> pages;
   for (int32_t g = p->rg0; g < p->rg1; g++) {
@@ -372,6 +372,8 @@ tq_status pq_parse_pages(tq_preload* p) {
           d.u_len = u_len;
           d.u_off = decomp_base + decomp_bytes;
           decomp_bytes += align256(u_len + 16);
+          d.frag0 = frags;
+          frags += (u_len + 65535) / 65536;
           return d.u_off;
         };
         const bool snappy = ch.codec == kPqSnappy;
@@ -469,6 +471,7 @@ tq_status pq_parse_pages(tq_preload* p) {
   p->run_slots = run_slots;
   p->ck_slots = ck_slots;
   p->tiles = tiles;
+  p->frags = frags;
   p->parsed = true;
   return TQ_OK;
 }
@@ -501,6 +504,12 @@ PqLayout pq_layout(const tq_preload* p) {
   at += (size_t)align256(ndict * 4);
   L.compl_ = at;
   at += (size_t)align256(ncomp * 4);
+  L.cflags = at;
+  at += (size_t)align256(ncomp * 4);
+  L.frag_in = at;
+  at += (size_t)align256(p->frags * 4);
+  L.frag_cp = at;
+  at += (size_t)align256(p->frags * 4);
   L.total = at;
   return L;
 }

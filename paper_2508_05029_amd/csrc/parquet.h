@@ -50,6 +50,7 @@ struct PqPage {
   int64_t val_end;
   int64_t c_off, c_len;  // a Snappy-compressed body: its bytes in the raw area (c_len 0: not compressed)
   int64_t u_off, u_len;  // and where it is inflated to (= val_off)
+  int64_t frag0;         // its first 64 KiB output fragment (compressed bodies)
   int32_t encoding;    // kPqPlain, or dictionary indices (kPqRleDictionary)
   int32_t width;       // 4 or 8 bytes
   int64_t dict_off;    // dictionary values (aligned copy), from the dictionary area's start; -1 if none
@@ -126,6 +127,7 @@ struct tq_preload {
   int64_t run_slots = 0;
   int64_t ck_slots = 0;
   int64_t tiles = 0;
+  int64_t frags = 0;  // 64 KiB output fragments of the compressed bodies
 };
 
 namespace tq {
@@ -136,10 +138,11 @@ void pq_release_pages(tq_preload* p);
 
 // Device work buffer of a decode: header | raw bytes | inflated page bodies |
 // dictionaries | page descriptors | spans | run counts | checkpoints | run
-// tables | tile -> page map | dictionary page list | compressed page list
-// (each part 256-aligned).
+// tables | tile -> page map | dictionary page list | compressed page list |
+// their scan flags | fragment starts | fragment -> compressed page map (each
+// part 256-aligned).
 struct PqLayout {
-  size_t raw, dict, pages, spans, nruns, cks, runs, tiles, dictl, compl_, total;
+  size_t raw, dict, pages, spans, nruns, cks, runs, tiles, dictl, compl_, cflags, frag_in, frag_cp, total;
 };
 PqLayout pq_layout(const tq_preload* p);
 }  // namespace tq

@@ -69,133 +69,319 @@ __global__ void k_pq_zero(uint32_t* words, int64_t n) {
 // One wave per compressed page body. The format (Snappy's raw block: the
 // uncompressed length as a varint, then elements: a literal of n bytes that
 // follow its tag, or a copy of n bytes from `offset` bytes back in the
-// output, which may overlap what it writes) is sequential, so every lane
-// parses the same element headers out of an LDS window of the input, and the
-// lanes then move the element's bytes in parallel. The output goes through
+// output, which may overlap what it writes) is sequential. In a batch, lane i
+// decodes the element that would start at input byte ip + i; following the
+// chain of real elements from lane 0 then takes register reads only, and each
+// element's bytes are moved by the lanes in parallel. The output goes through
 // a 64 KiB LDS ring holding the last 64 KiB written (every copy offset below
 // 65536 reads from it) and is written to the device buffer 8 KiB at a time.
 // A wave's LDS accesses take effect in program order, so a lane reads the
 // bytes other lanes wrote for earlier elements without a barrier.
 constexpr int kRing = 65536;
 constexpr int kFlushBytes = 8192;
-constexpr int kInWin = 4096;
+constexpr int kInWin = 16384;
 
-__device__ __forceinline__ uint32_t in_byte(const uint32_t* w, int64_t i) { return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu; }
+__device__ __forceinline__ uint32_t in_byte(const uint32_t* w, int32_t i) { return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu; }
 
+// The Snappy element that would start at window byte i: the input bytes it
+// takes (tag, length or offset bytes, literal payload), the output bytes it
+// writes, and its copy offset (0 for a literal; -1 if 0 or impossibly far).
+__device__ __forceinline__ void snappy_candidate(const uint32_t* win, int32_t i, int32_t& c_adv, int32_t& c_len,
+                                                 int32_t& c_off) {
+  uint32_t cb[5];
+#pragma unroll
+  for (int k = 0; k < 5; k++) cb[k] = in_byte(win, i + k);
+  const uint32_t t = cb[0];
+  if ((t & 3) == 0) {
+    const uint32_t l6 = t >> 2;
+    uint32_t lit = l6 + 1, hb = 1;
+    if (l6 >= 60) {
+      const int nb = (int)l6 - 59;
+      uint32_t v = 0;
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (k < nb) v |= cb[1 + k] << (8 * k);
+      lit = v >= (1u << 30) ? (1u << 30) : v + 1;  // too long for any page: caught by the caller
+      hb = 1 + nb;
+    }
+    c_adv = (int32_t)(hb + lit);
+    c_len = (int32_t)lit;
+    c_off = 0;
+  } else if ((t & 3) == 1) {
+    c_adv = 2;
+    c_len = 4 + (int32_t)((t >> 2) & 7);
+    c_off = (int32_t)(((t >> 5) << 8) | cb[1]);
+  } else if ((t & 3) == 2) {
+    c_adv = 3;
+    c_len = (int32_t)(t >> 2) + 1;
+    c_off = (int32_t)(cb[1] | cb[2] << 8);
+  } else {
+    c_adv = 5;
+    c_len = (int32_t)(t >> 2) + 1;
+    const uint32_t o = cb[1] | cb[2] << 8 | cb[3] << 16 | cb[4] << 24;
+    c_off = o >= (1u << 30) ? -1 : (int32_t)o;
+  }
+  if ((t & 3) != 0 && c_off == 0) c_off = -1;  // c_off == 0 marks a literal and nothing else
+}
+
+// An LDS window of a compressed body: input bytes [wbase, wbase + kInWin),
+// loaded as aligned dwords of the raw area (wbase may be up to 3 bytes
+// before 0). ensure() is called alike by every lane of the wave.
+struct InWindow {
+  uint32_t* win;
+  const uint8_t* raw;
+  int64_t c_off;
+  int32_t in_len;
+  int32_t wbase;
+  __device__ void ensure(int32_t at, int32_t need) {
+    if (at >= wbase && at + need <= wbase + kInWin) return;
+    const int64_t abs0 = (c_off + at) & ~(int64_t)3;
+    wbase = (int32_t)(abs0 - c_off);
+    for (int i = threadIdx.x; i < kInWin / 4 + 4; i += 64) {
+      const int64_t a = abs0 + 4 * (int64_t)i;  // a dword starting before the input's end stays in the padded area
+      win[i] = a < c_off + in_len ? *reinterpret_cast<const uint32_t*>(raw + a) : 0u;
+    }
+    __syncthreads();
+  }
+  __device__ uint32_t byte(int32_t at) const { return in_byte(win, at - wbase); }
+};
+
+// The length preamble (a varint) of a Snappy body; its size in *ip, false
+// if malformed.
+__device__ bool snappy_preamble(InWindow& w, uint32_t* ulen, int32_t* ip) {
+  w.ensure(0, 8);
+  uint32_t v = 0;
+  int32_t i = 0;
+  for (int sh = 0;; sh += 7) {
+    const uint32_t b = i < w.in_len ? w.byte(i) : 0x80u;
+    i++;
+    v |= (b & 0x7f) << sh;
+    if (!(b & 0x80)) break;
+    if (sh >= 28 || i >= w.in_len) return false;
+  }
+  *ulen = v;
+  *ip = i;
+  return true;
+}
+
+constexpr int kFrag = 65536;  // the reference compressor's independent fragments
+
+// Pass 1, one wave per compressed body: follows the element chain (bounds
+// checked), records where each 64 KiB output fragment's first element starts,
+// and flags the body when an element crosses a fragment or copies from
+// before its fragment (then the body is inflated by one wave, in order).
+// flags: 0 fragments independent, 1 inflate in order, 2 malformed.
+__global__ __launch_bounds__(64) void k_pq_snappy_scan(const PqPage* pages, const int32_t* cpages, const uint8_t* raw,
+                                                       int32_t* frag_in, int32_t* flags, PqHeader* hdr) {
+  __shared__ uint32_t wbuf[kInWin / 4 + 4];
+  const PqPage pg = pages[cpages[blockIdx.x]];
+  InWindow w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
+  const int32_t out_len = (int32_t)pg.u_len;
+  int32_t* fi = frag_in + pg.frag0;
+  const int lane = threadIdx.x;
+  uint32_t ulen;
+  int32_t ip;
+  bool bad = !snappy_preamble(w, &ulen, &ip) || ulen != (uint32_t)out_len;
+  bool dep = false;
+  int32_t q = 0;
+  while (!bad && q < out_len) {
+    w.ensure(ip, 64 + 8);
+    int32_t c_adv, c_len, c_off;
+    snappy_candidate(w.win, ip + lane - w.wbase, c_adv, c_len, c_off);
+    // The chain is followed with as few instructions as possible (one wave
+    // issues one every few cycles): bounds are not checked per element, since
+    // nothing is read or written here but the fragment starts (below the
+    // output length); a malformed body ends its chain off the input's or
+    // the output's end, and the fragment pass checks every access itself.
+    int32_t rel = 0;
+    while (rel < 64 && q < out_len) {
+      const int32_t adv = __builtin_amdgcn_readlane(c_adv, rel);
+      const int32_t len = __builtin_amdgcn_readlane(c_len, rel);
+      const int32_t off = __builtin_amdgcn_readlane(c_off, rel);  // 0: a literal; -1: invalid
+      const int32_t fs = q & ~(kFrag - 1);
+      if (q == fs && lane == 0) fi[q >> 16] = ip + rel;
+      dep = dep || (q + len > fs + kFrag) || (q - off < fs) || off < 0;
+      q += len;
+      rel += adv;
+    }
+    ip += rel;
+    if (ip > w.in_len) bad = true;
+  }
+  if (!bad && (ip != w.in_len || q != out_len)) bad = true;  // the chain must end at both ends
+  if (lane == 0) {
+    flags[blockIdx.x] = bad ? 2 : dep ? 1 : 0;
+    if (bad) pq_error(hdr, TQ_EINVAL);
+  }
+}
+
+// Pass 2, one wave per 64 KiB fragment of a body whose fragments are
+// independent: its elements are executed in order into an LDS copy of the
+// fragment, which is then written out.
+__global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, const int32_t* cpages,
+                                                       const int32_t* frag_cpage, uint8_t* raw, const int32_t* frag_in,
+                                                       const int32_t* flags, PqHeader* hdr) {
+  __shared__ uint32_t buf[kFrag / 4];
+  __shared__ uint32_t wbuf[kInWin / 4 + 4];
+  uint8_t* fb = reinterpret_cast<uint8_t*>(buf);
+  const int32_t ci = frag_cpage[blockIdx.x];
+  if (flags[ci] != 0) return;
+  const PqPage pg = pages[cpages[ci]];
+  const int32_t f = (int32_t)(blockIdx.x - pg.frag0);
+  InWindow w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
+  const int32_t out_len = (int32_t)pg.u_len;
+  const int32_t fs = f * kFrag, fe = min(fs + kFrag, out_len);
+  const int lane = threadIdx.x;
+  const uint8_t* in = raw + pg.c_off;
+  int32_t ip = frag_in[pg.frag0 + f], q = fs;
+  bool bad = ip < 0 || ip >= w.in_len;
+  while (!bad && q < fe) {
+    w.ensure(ip, 64 + 8);
+    int32_t c_adv, c_len, c_off;
+    snappy_candidate(w.win, ip + lane - w.wbase, c_adv, c_len, c_off);
+    int32_t rel = 0;
+    while (rel < 64 && q < fe) {
+      const int32_t at = ip + rel;
+      const int32_t adv = __builtin_amdgcn_readlane(c_adv, rel);
+      const int32_t len = __builtin_amdgcn_readlane(c_len, rel);
+      const int32_t off = __builtin_amdgcn_readlane(c_off, rel);
+      const bool literal = off == 0;
+      // the scan checked the chain; these checks keep every access in bounds regardless
+      if (at >= w.in_len || len > fe - q || adv > w.in_len - at || (!literal && (off <= 0 || off > q - fs))) {
+        bad = true;
+        break;
+      }
+      const int32_t lq = q - fs;  // position in the fragment
+      if (literal) {
+        const int32_t src = at + adv - len;
+        const bool in_win = src >= w.wbase && src + len <= w.wbase + kInWin;
+        for (int32_t j = lane; j < len; j += 64) fb[lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
+      } else if (lane < len) {
+        fb[lq + lane] = fb[lq - off + (off >= len ? lane : lane % off)];
+      }
+      q += len;
+      rel += adv;
+    }
+    ip += rel;
+  }
+  if (bad) {
+    if (lane == 0) pq_error(hdr, TQ_EINVAL);
+    return;
+  }
+  uint32_t* dst = reinterpret_cast<uint32_t*>(raw + pg.u_off + fs);  // 256-aligned, padded past the body
+  for (int i = lane; i < ((fe - fs + 3) >> 2); i += 64) dst[i] = buf[i];
+}
+
+// A body the scan flagged (1), inflated by one wave in order through a 64 KiB
+// ring of the latest output.
 __global__ __launch_bounds__(64) void k_pq_snappy(const PqPage* pages, const int32_t* cpages, uint8_t* raw,
-                                                  PqHeader* hdr) {
+                                                  const int32_t* flags, PqHeader* hdr) {
   __shared__ uint32_t ring[kRing / 4];
   __shared__ uint32_t win[kInWin / 4 + 4];
   uint8_t* rb = reinterpret_cast<uint8_t*>(ring);
+  if (flags[blockIdx.x] != 1) return;
   const PqPage pg = pages[cpages[blockIdx.x]];
   const uint8_t* in = raw + pg.c_off;
-  const int64_t in_len = pg.c_len, out_len = pg.u_len;
+  // page bodies are at most 1 GiB (checked on the host): 32-bit positions
+  const int32_t in_len = (int32_t)pg.c_len, out_len = (int32_t)pg.u_len;
   uint8_t* out = raw + pg.u_off;
   const int lane = threadIdx.x;
   // the input window holds input bytes [wbase, wbase + kInWin), loaded as
   // aligned dwords of the raw area (wbase may be up to 3 bytes before 0)
-  int64_t wbase = INT64_MIN / 2;
-  auto window = [&](int64_t at) {  // uniform: every lane asks for the same position
-    if (at >= wbase && at + 8 <= wbase + kInWin) return;
+  int32_t wbase = INT32_MIN / 2;
+  auto window = [&](int32_t at, int32_t need) {  // uniform: every lane asks for the same bytes
+    if (at >= wbase && at + need <= wbase + kInWin) return;
     const int64_t abs0 = (pg.c_off + at) & ~(int64_t)3;
-    wbase = abs0 - pg.c_off;
+    wbase = (int32_t)(abs0 - pg.c_off);
     for (int i = lane; i < kInWin / 4 + 4; i += 64) {
       const int64_t a = abs0 + 4 * (int64_t)i;  // a dword starting before the input's end stays in the padded area
       win[i] = a < pg.c_off + in_len ? *reinterpret_cast<const uint32_t*>(raw + a) : 0u;
     }
     __syncthreads();
   };
-  auto ib = [&](int64_t at) { return in_byte(win, at - wbase); };
   bool bad = false;
   // the uncompressed length
-  window(0);
-  uint64_t ulen = 0;
-  int64_t ip = 0;
+  window(0, 8);
+  uint32_t ulen = 0;
+  int32_t ip = 0;
   for (int sh = 0;; sh += 7) {
-    const uint32_t b = ip < in_len ? ib(ip) : 0x80u;
+    const uint32_t b = ip < in_len ? in_byte(win, ip - wbase) : 0x80u;
     ip++;
-    ulen |= (uint64_t)(b & 0x7f) << sh;
+    ulen |= (b & 0x7f) << sh;
     if (!(b & 0x80)) break;
     if (sh >= 28 || ip >= in_len) {
       bad = true;
       break;
     }
   }
-  if (ulen != (uint64_t)out_len) bad = true;
-  int64_t q = 0, flushed = 0;
+  if (ulen != (uint32_t)out_len) bad = true;
+  int32_t q = 0, flushed = 0;
   // writes the ring's final bytes out in whole chunks below `upto` (a chunk
   // boundary), or everything left once upto is the output's end
-  auto flush_to = [&](int64_t upto) {
+  auto flush_to = [&](int32_t upto) {
     while (flushed + kFlushBytes <= upto || (upto == out_len && flushed < out_len)) {
-      const int64_t n = min((int64_t)kFlushBytes, out_len - flushed);
+      const int32_t n = min(kFlushBytes, out_len - flushed);
       uint32_t* dst = reinterpret_cast<uint32_t*>(out + flushed);  // the output area is 256-aligned and padded
-      const int base = (int)((flushed & (kRing - 1)) >> 2);
-      for (int i = lane; i < (int)((n + 3) >> 2); i += 64) dst[i] = ring[base + i];
+      const int base = (flushed & (kRing - 1)) >> 2;
+      for (int i = lane; i < ((n + 3) >> 2); i += 64) dst[i] = ring[base + i];
       flushed += n;
     }
   };
   while (!bad && q < out_len) {
-    window(ip);
-    if (ip >= in_len) {
-      bad = true;
-      break;
-    }
-    const uint32_t tag = ib(ip);
-    int64_t len, off = 0, src = 0;
-    const bool literal = (tag & 3) == 0;
-    if (literal) {
-      const uint32_t l6 = tag >> 2;
-      if (l6 < 60) {
-        len = (int64_t)l6 + 1;
-        ip += 1;
-      } else {
-        const int nb = (int)l6 - 59;
-        uint64_t v = 0;
-        for (int k = 0; k < nb; k++) v |= (uint64_t)ib(ip + 1 + k) << (8 * k);
-        len = (int64_t)v + 1;
-        ip += 1 + nb;
+    // Parse a batch: lane i decodes the element that would start at input
+    // byte ip + i; the chain of real elements is then followed from lane 0
+    // with register reads (the element after the one at lane r is at lane
+    // r + its byte length), and each element is executed as it is reached.
+    window(ip, 64 + 8);
+    int32_t c_adv, c_len, c_off;  // bytes the element takes, bytes it writes, copy offset (0: a literal)
+    snappy_candidate(win, ip + lane - wbase, c_adv, c_len, c_off);
+    int32_t rel = 0;
+    while (rel < 64 && !bad && q < out_len) {
+      const int32_t at = ip + rel;
+      if (at >= in_len) {
+        bad = true;
+        break;
       }
-      src = ip;
-      ip += len;
-      if (ip > in_len) bad = true;
-    } else if ((tag & 3) == 1) {
-      len = 4 + ((tag >> 2) & 7);
-      off = (int64_t)((tag >> 5) << 8) | ib(ip + 1);
-      ip += 2;
-    } else if ((tag & 3) == 2) {
-      len = (int64_t)(tag >> 2) + 1;
-      off = (int64_t)ib(ip + 1) | (int64_t)ib(ip + 2) << 8;
-      ip += 3;
-    } else {
-      len = (int64_t)(tag >> 2) + 1;
-      off = (int64_t)ib(ip + 1) | (int64_t)ib(ip + 2) << 8 | (int64_t)ib(ip + 3) << 16 | (int64_t)ib(ip + 4) << 24;
-      ip += 5;
-    }
-    if (!literal && (off <= 0 || off > q)) bad = true;
-    if (q + len > out_len || ip > in_len) bad = true;
-    if (bad) break;
-    const bool far = !literal && off >= kRing;  // the source has left the ring: read the output written
-    if (far) {
-      flush_to(q & ~(int64_t)(kFlushBytes - 1));  // every source byte lies below (q - off + 64 < q - 8 KiB)
-      __threadfence();  // those stores are visible before the loads below
-    }
-    for (int64_t s0 = 0; s0 < len; s0 += kFlushBytes) {
-      const int64_t pl = min((int64_t)kFlushBytes, len - s0);
-      // the ring slots about to be written must have been flushed
-      const int64_t need = q + s0 + pl - kRing;  // at most q + s0 - 56 KiB: those bytes are final
-      if (need > flushed) flush_to(((need + kFlushBytes - 1) / kFlushBytes) * kFlushBytes);
-      for (int64_t i = lane; i < pl; i += 64) {
-        const int64_t j = s0 + i;  // byte j of the element
-        uint8_t b;
-        if (literal) b = in[src + j];
-        else {
-          const int64_t sp = q - off + (j % off);
-          b = far ? out[sp] : rb[sp & (kRing - 1)];
+      const int32_t adv = __builtin_amdgcn_readlane(c_adv, rel);
+      const int32_t len = __builtin_amdgcn_readlane(c_len, rel);
+      const int32_t off = __builtin_amdgcn_readlane(c_off, rel);
+      const bool literal = off == 0;
+      const int32_t src = at + adv - len;                        // a literal's first payload byte
+      if (len > out_len - q || adv > in_len - at || (!literal && (off <= 0 || off > q))) {
+        bad = true;
+        break;
+      }
+      if (literal) {
+        // from the window when the payload lies in it, else straight from memory
+        const bool in_win = src >= wbase && src + len <= wbase + kInWin;
+        for (int32_t s0 = 0; s0 < len; s0 += kFlushBytes) {
+          const int32_t pl = min(kFlushBytes, len - s0);
+          const int32_t need = q + s0 + pl - kRing;  // ring slots about to be reused: those bytes are final
+          if (need > flushed) flush_to(((need + kFlushBytes - 1) / kFlushBytes) * kFlushBytes);
+          for (int32_t j = s0 + lane; j < s0 + pl; j += 64) {
+            const uint8_t b = in_win ? (uint8_t)in_byte(win, src + j - wbase) : in[src + j];
+            rb[(q + j) & (kRing - 1)] = b;
+          }
         }
-        rb[(q + j) & (kRing - 1)] = b;
+      } else {
+        // a copy is at most 64 bytes; its sources lie below q (final; in the
+        // ring when less than 64 KiB back)
+        const int32_t need = q + len - kRing;
+        if (need > flushed) flush_to(((need + kFlushBytes - 1) / kFlushBytes) * kFlushBytes);
+        const bool far = off >= kRing;
+        if (far) {
+          flush_to(q & ~(kFlushBytes - 1));  // every source byte lies below (q - off + 64 < q - 8 KiB)
+          __threadfence();                   // those stores are visible before the loads below
+        }
+        if (lane < len) {
+          const int32_t sp = q - off + (off >= len ? lane : lane % off);
+          const uint8_t b = far ? out[sp] : rb[sp & (kRing - 1)];
+          rb[(q + lane) & (kRing - 1)] = b;
+        }
       }
+      q += len;
+      rel += adv;
     }
-    q += len;
+    ip += rel;
   }
   if (!bad) flush_to(out_len);
   if (bad && lane == 0) pq_error(hdr, TQ_EINVAL);
@@ -611,17 +797,20 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
   // host tables: descriptors with offsets made absolute where the kernels want
   // them, the tile -> page map, the dictionary pages; staged through pool pages
   std::vector<PqPage> pages = p->pages;
-  std::vector<int32_t> tile_page((size_t)p->tiles), dict_pages, comp_pages;
+  std::vector<int32_t> tile_page((size_t)p->tiles), dict_pages, comp_pages, frag_cpage((size_t)p->frags);
   for (size_t i = 0; i < pages.size(); i++) {
     const PqPage& d = pages[i];
-    if (d.c_len > 0) comp_pages.push_back((int32_t)i);
+    if (d.c_len > 0) {
+      for (int64_t f = 0; f < (d.u_len + 65535) / 65536; f++) frag_cpage[(size_t)(d.frag0 + f)] = (int32_t)comp_pages.size();
+      comp_pages.push_back((int32_t)i);
+    }
     if (d.kind == kPqDictionaryPage) dict_pages.push_back((int32_t)i);
     else
       for (int64_t t = 0; t < ((int64_t)d.nrows + kPqTile - 1) / kPqTile; t++) tile_page[(size_t)(d.tile0 + t)] = (int32_t)i;
   }
   const size_t pb = tq_pagepool_page_bytes(p->pool);
-  const size_t host_bytes =
-      pages.size() * sizeof(PqPage) + tile_page.size() * 4 + dict_pages.size() * 4 + comp_pages.size() * 4 + 64;
+  const size_t host_bytes = pages.size() * sizeof(PqPage) + tile_page.size() * 4 + dict_pages.size() * 4 +
+                            comp_pages.size() * 4 + frag_cpage.size() * 4 + 64;
   const int64_t hpages = (int64_t)((host_bytes + pb - 1) / pb);
   std::vector<int32_t> staging((size_t)hpages);
   if (hpages > 0 && tq_pagepool_alloc(p->pool, hpages, staging.data()) != TQ_OK)
@@ -657,6 +846,9 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
     const size_t o_comp = o;
     memcpy(blob.data() + o, comp_pages.data(), comp_pages.size() * 4);
     o += comp_pages.size() * 4;
+    const size_t o_fcp = o;
+    memcpy(blob.data() + o, frag_cpage.data(), frag_cpage.size() * 4);
+    o += frag_cpage.size() * 4;
     for (int64_t i = 0; i < hpages; i++) {
       const size_t at = (size_t)i * pb, n = std::min(pb, o > at ? o - at : 0);
       if (n) memcpy(tq_pagepool_page(p->pool, staging[(size_t)i]), blob.data() + at, n);
@@ -676,6 +868,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
     copy(o_tiles, tile_page.size() * 4, tiles_at);
     copy(o_dict, dict_pages.size() * 4, dictl_at);
     copy(o_comp, comp_pages.size() * 4, L.compl_);
+    copy(o_fcp, frag_cpage.size() * 4, L.frag_cp);
   }
   hipEvent_t copied = nullptr;
   if (e == hipSuccess) e = hipEventCreateWithFlags(&copied, hipEventDisableTiming);
@@ -694,9 +887,17 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
                        dim3(256), 0, stream, reinterpret_cast<uint32_t*>(W + L.nruns), zwords);
     const PqPage* dp = reinterpret_cast<const PqPage*>(W + L.pages);
     PqSpan* spans = reinterpret_cast<PqSpan*>(W + L.spans);
-    if (!comp_pages.empty())
-      hipLaunchKernelGGL(k_pq_snappy, dim3((int)comp_pages.size()), dim3(64), 0, stream, dp,
-                         reinterpret_cast<const int32_t*>(W + L.compl_), raw, hdr);
+    if (!comp_pages.empty()) {
+      const int32_t* cl = reinterpret_cast<const int32_t*>(W + L.compl_);
+      int32_t* frag_in = reinterpret_cast<int32_t*>(W + L.frag_in);
+      int32_t* flags = reinterpret_cast<int32_t*>(W + L.cflags);
+      hipLaunchKernelGGL(k_pq_snappy_scan, dim3((int)comp_pages.size()), dim3(64), 0, stream, dp, cl, raw, frag_in,
+                         flags, hdr);
+      if (p->frags > 0)
+        hipLaunchKernelGGL(k_pq_snappy_frag, dim3((int)p->frags), dim3(64), 0, stream, dp, cl,
+                           reinterpret_cast<const int32_t*>(W + L.frag_cp), raw, frag_in, flags, hdr);
+      hipLaunchKernelGGL(k_pq_snappy, dim3((int)comp_pages.size()), dim3(64), 0, stream, dp, cl, raw, flags, hdr);
+    }
     if (!pages.empty())
       hipLaunchKernelGGL(k_pq_span, dim3((int)std::min<size_t>((pages.size() + 255) / 256, 1024)), dim3(256), 0,
                          stream, dp, (int)pages.size(), raw, spans, hdr);

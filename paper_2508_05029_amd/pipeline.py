@@ -579,3 +579,51 @@ class StringJoinAgg:
     def result(self, stream=None) -> dict:
         tq.check(self.dtable, stream)
         return self.join.result(stream)
+
+
+class ParquetScan:
+    """Scan of a Parquet file's columns into device tensors: tq_parquet_preload
+    (byte ranges merged and read into pool pages by a host thread), then
+    tq_parquet_decode (pages copied to the device and decoded there). The
+    work buffer grows to the largest preload seen; outputs are new tensors."""
+
+    def __init__(self, path: str, columns, pool, merge_gap: int = 1 << 20, device="cuda"):
+        self.file = tq.ParquetFile(path)
+        meta = self.file.columns()
+        names = [m[0] for m in meta]
+        self.cols = [names.index(c) for c in columns]
+        self.meta = [meta[c] for c in self.cols]
+        self.names = list(columns)
+        self.pool = pool
+        self.merge_gap = merge_gap
+        self.device = device
+        self.work = None
+
+    def preload(self, rg0: int = 0, rg1=None):
+        rg1 = self.file.num_row_groups if rg1 is None else rg1
+        return self.file.preload(self.pool, rg0, rg1, self.cols, self.merge_gap)
+
+    def decode(self, pl, stream=None):
+        """Decodes a preload; returns ({name: values}, {name: validity bitmap or None})."""
+        need = pl.work_bytes()
+        if self.work is None or self.work.numel() < need:
+            self.work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        n = pl.rows
+        data, valid, outs = {}, {}, []
+        for name, (_, t, nullable) in zip(self.names, self.meta):
+            d = torch.empty(max(n, 1), dtype=torch.int64 if t == tq.TQ_I64 else torch.int32, device=self.device)
+            v = torch.empty(max(((n + 31) // 32) * 4, 4), dtype=torch.uint8, device=self.device) if nullable else None
+            data[name], valid[name] = d[:n], v
+            outs.append((d, v))
+        pl.decode(self.work, outs, stream)
+        return data, valid
+
+    def read(self, rg0: int = 0, rg1=None, stream=None):
+        pl = self.preload(rg0, rg1)
+        try:
+            return self.decode(pl, stream)
+        finally:
+            pl.free()
+
+    def check(self, stream=None):
+        tq.check(self.work, stream)
