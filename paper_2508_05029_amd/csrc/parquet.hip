@@ -410,13 +410,16 @@ __global__ void k_pq_span(const PqPage* pages, int npages, const uint8_t* raw, P
   }
 }
 
-// One workgroup per dictionary page.
+constexpr int kDictBlocks = 16;  // workgroups per dictionary page
+
+// kDictBlocks workgroups per dictionary page.
 __global__ __launch_bounds__(kDecBlock) void k_pq_dict(const PqPage* pages, const int32_t* dict_pages,
                                                        const uint8_t* raw, uint8_t* dict) {
-  const PqPage pg = pages[dict_pages[blockIdx.x]];
+  const PqPage pg = pages[dict_pages[blockIdx.x / kDictBlocks]];
   const int w = pg.width;
   uint8_t* out = dict + pg.dict_off;
-  for (int64_t e = threadIdx.x; e < pg.dict_n; e += kDecBlock) {
+  const int part = blockIdx.x % kDictBlocks;
+  for (int64_t e = (int64_t)part * kDecBlock + threadIdx.x; e < pg.dict_n; e += (int64_t)kDictBlocks * kDecBlock) {
     const uint64_t v = ld_le(raw, pg.val_off + e * w, w);
     if (w == 8) reinterpret_cast<uint64_t*>(out)[e] = v;
     else reinterpret_cast<uint32_t*>(out)[e] = (uint32_t)v;
@@ -784,7 +787,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
     tq_parquet_column(p->pq, p->cols[(size_t)c], &name, &type, &nullable);
     if (out[c].type != type) return fail(TQ_EINVAL, "output %d (%s): type %d, the column is %d", c, name, out[c].type, type);
     if (p->rows > 0 && !out[c].data) return fail(TQ_EINVAL, "output %d (%s): NULL data", c, name);
-    if ((uintptr_t)out[c].data & 7) return fail(TQ_EINVAL, "output %d: data not 8-byte aligned", c);
+    if ((uintptr_t)out[c].data & (uintptr_t)(type - 1)) return fail(TQ_EINVAL, "output %d: data not aligned to its width", c);
     if (nullable && !out[c].valid && p->rows > 0)
       return fail(TQ_EINVAL, "output %d (%s) may hold NULLs: it needs a validity bitmap", c, name);
     if ((uintptr_t)out[c].valid & 3) return fail(TQ_EINVAL, "output %d: bitmap not 4-byte aligned", c);
@@ -902,7 +905,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
       hipLaunchKernelGGL(k_pq_span, dim3((int)std::min<size_t>((pages.size() + 255) / 256, 1024)), dim3(256), 0,
                          stream, dp, (int)pages.size(), raw, spans, hdr);
     if (!dict_pages.empty())
-      hipLaunchKernelGGL(k_pq_dict, dim3((int)dict_pages.size()), dim3(kDecBlock), 0, stream, dp,
+      hipLaunchKernelGGL(k_pq_dict, dim3((int)dict_pages.size() * kDictBlocks), dim3(kDecBlock), 0, stream, dp,
                          reinterpret_cast<const int32_t*>(W + dictl_at), raw, reinterpret_cast<uint8_t*>(W + L.dict));
     if (!pages.empty())
       hipLaunchKernelGGL(k_pq_walk, dim3((int)(2 * pages.size())), dim3(64), 0, stream, dp, spans, (int)pages.size(), raw,

@@ -618,6 +618,39 @@ class ParquetScan:
         pl.decode(self.work, outs, stream)
         return data, valid
 
+    def read_pipelined(self, stream=None):
+        """Every row group into one set of columns, the next row group's bytes
+        read ahead (its preload started) while the current one is decoded:
+        the host reads overlap the copies and kernels. Row groups must start
+        on multiples of 32 rows when a column is nullable (bitmap words)."""
+        nrg = self.file.num_row_groups
+        n = self.file.num_rows
+        data, valid = {}, {}
+        for name, (_, t, nullable) in zip(self.names, self.meta):
+            data[name] = torch.empty(max(n, 1), dtype=torch.int64 if t == tq.TQ_I64 else torch.int32,
+                                     device=self.device)
+            valid[name] = (torch.empty(max(((n + 31) // 32) * 4, 4), dtype=torch.uint8, device=self.device)
+                           if nullable else None)
+        if nrg == 0:
+            return {k: v[:0] for k, v in data.items()}, valid
+        nxt = self.preload(0, 1)
+        row = 0
+        for g in range(nrg):
+            cur = nxt
+            nxt = self.preload(g + 1, g + 2) if g + 1 < nrg else None
+            need = cur.work_bytes()
+            if self.work is None or self.work.numel() < need:
+                self.work = torch.empty(need, dtype=torch.uint8, device=self.device)
+            rows = cur.rows
+            if any(v is not None for v in valid.values()) and row % 32:
+                raise ValueError("a row group of a nullable column starts off a 32-row boundary")
+            outs = [(data[name][row:row + rows], None if valid[name] is None else valid[name][row // 8:])
+                    for name in self.names]
+            cur.decode(self.work, outs, stream)
+            cur.free()
+            row += rows
+        return {k: v[:n] for k, v in data.items()}, valid
+
     def read(self, rg0: int = 0, rg1=None, stream=None):
         pl = self.preload(rg0, rg1)
         try:

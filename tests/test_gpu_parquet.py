@@ -170,3 +170,24 @@ def test_snappy_repeats_and_runs(tmp_path):
     path = pqfiles.write(str(tmp_path / "rep.parquet"), cols, data_page_size=4 << 20, compression="snappy")
     res, rows = decode(path, [0, 1])
     check(cols, [0, 1], res, 0, rows)
+
+
+@pytest.mark.parametrize("codec", ["NONE", "snappy"])
+def test_pipelined_row_groups_equal_the_whole_read(tmp_path, codec):
+    """read_pipelined (each row group decoded into its slice of one set of
+    columns while the next one's bytes are read) equals what pyarrow wrote."""
+    cols = pqfiles.columns(100_000, 28)
+    path = pqfiles.write(str(tmp_path / "pipe.parquet"), cols, row_group_size=20_000, data_page_size=32_768,
+                         compression=codec)
+    pool = tq.PagePool(1 << 20, 64)
+    names = [c[0] for c in cols]
+    scan = pipeline.ParquetScan(path, names, pool)
+    data, valid = scan.read_pipelined()
+    scan.check()
+    for c, name in enumerate(names):
+        want, m = expect(cols, c, 0, 100_000)
+        assert data[name].cpu().numpy().tolist() == want.tolist(), name
+        if valid[name] is not None:
+            bits = np.unpackbits(valid[name].cpu().numpy(), bitorder="little")[:100_000].astype(bool)
+            assert bits.tolist() == m.tolist(), name
+    assert pool.free_pages() == 64
