@@ -523,7 +523,9 @@ typedef struct {
 } tq_instance;
 
 size_t tq_batched_state_bytes(int64_t domain, int32_t nsum);
-/* Device work area for n instances (descriptors, the work-item list, counters). */
+/* Device work area for n instances (descriptors, the work-item list, counters,
+ * and each instance's Bloom filter of its kept build keys: 2 bits per build
+ * row, 256 B to 32 KiB). */
 size_t tq_batched_work_bytes(const tq_instance* h_inst, int32_t n);
 
 /* Upload the descriptors and the work-item list for tq_batched_run (copies

@@ -1,6 +1,7 @@
 // Batched join + group-by instances: one queue launch per phase.
 //
-// Work area: WorkHeader | BInst[n] | int64 ctr[n][kCtr] | uint64 item[n_items].
+// Work area: WorkHeader | BInst[n] | int64 ctr[n][kCtr] | uint64 item[n_items] |
+// uint32 bloom[...] (each instance's Bloom filter of its kept build keys).
 // An item is (type, instance, index). The list holds every build tile, then
 // every probe tile, then the finalize items (single-chunk finalizes and chunk
 // counts), then the chunk writes; each group is one phase. Every phase is one
@@ -27,6 +28,8 @@ constexpr int kMaxChunks = 8;    // domain <= 65536
 constexpr int kCtr = 16;         // counters per instance: chunk counts at [8..16)
 constexpr int kPhases = 4;       // build, probe, finalize (single chunk or chunk counts), chunk writes
 constexpr int kBPR = 2;          // rows per lane in probe items
+constexpr int kMinBloomWords = 64;    // an instance's filter: 2 bits per build row, 256 B to 32 KiB
+constexpr int kMaxBloomWords = 8192;
 
 enum ItemType { kItBuild = 0, kItProbe = 1, kItFinOne = 2, kItFinCount = 3, kItFinWrite = 4 };
 
@@ -43,6 +46,8 @@ struct BInst {
   int32_t log2cap, build_tile, probe_tile, nchunks;
   int64_t n_build_items, n_probe_items;
   void* state;
+  uint32_t* bloom;  // the instance's filter (bloom_nw words, a power of two)
+  int32_t bloom_nw;
   int64_t* keys;
   int64_t* count;
   int64_t* sums;
@@ -74,16 +79,36 @@ struct BQuery {
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-  size_t inst_off, item_off, ctr_off, bytes;
+  size_t inst_off, item_off, ctr_off, bloom_off, bytes;
 };
 
-Layout layout(int32_t n, int64_t n_items) {
+Layout layout(int32_t n, int64_t n_items, int64_t bloom_words = 0) {
   Layout L;
   L.inst_off = 256;
   L.ctr_off = L.inst_off + al((size_t)n * sizeof(BInst));
   L.item_off = L.ctr_off + al((size_t)n * kCtr * 8);
-  L.bytes = L.item_off + al((size_t)n_items * 8);
+  L.bloom_off = L.item_off + al((size_t)n_items * 8);
+  L.bytes = L.bloom_off + al((size_t)bloom_words * 4);
   return L;
+}
+
+// Filter words of an instance with n_dim build rows.
+int32_t bloom_words_for(int64_t n_dim) {
+  int64_t w = kMinBloomWords;
+  while (w < kMaxBloomWords && w * 16 < n_dim) w *= 2;
+  return (int32_t)w;
+}
+
+int64_t count_bloom_words(const tq_instance* h, int32_t n) {
+  int64_t t = 0;
+  for (int i = 0; i < n; i++) t += bloom_words_for(h[i].n_dim);
+  return t;
+}
+
+// The filter's word (from hash bits 41.., above those of bloom_bits) for a
+// key's multiplicative hash.
+__device__ __forceinline__ uint32_t inst_bloom_word(uint64_t hh, int32_t nw) {
+  return (uint32_t)(hh >> 41) & (uint32_t)(nw - 1);
 }
 
 int log2cap_for_rows(int64_t rows, double lf) {
@@ -151,6 +176,7 @@ __global__ __launch_bounds__(256) void k_batched_prep(WorkHeader* hdr, const BIn
     for (int64_t g = threadIdx.x; g < ((int64_t)1 << I.log2cap) / kBucket; g += blockDim.x) tags[g] = z;
     int64_t* d = state_data(I.state);
     for (int64_t e = threadIdx.x; e < I.domain * (1 + nsum); e += blockDim.x) d[e] = 0;
+    for (int e = threadIdx.x; e < I.bloom_nw; e += blockDim.x) I.bloom[e] = 0u;
   }
 }
 
@@ -209,6 +235,11 @@ __device__ void probe_item(const BQuery& Q, const BInst& I, int64_t idx, char* s
   LdsAgg<MODE> agg;
   agg.defer = true;  // a key outside the domain is remembered and latched below
   agg.init(T, smem);
+  // the instance's filter, after the partials: most probe rows have no
+  // partner, and a row it rejects loads nothing from the table
+  uint32_t* bloom = reinterpret_cast<uint32_t*>(smem + kLdsAggBytes);
+  const int32_t nw = I.bloom_nw;
+  for (int e = threadIdx.x; e < nw; e += blockDim.x) bloom[e] = I.bloom[e];
   __syncthreads();
   const TableHeader* th = static_cast<const TableHeader*>(I.table);
   Probe pr;
@@ -217,30 +248,45 @@ __device__ void probe_item(const BQuery& Q, const BInst& I, int64_t idx, char* s
   DCol fc[4];
 #pragma unroll
   for (int c = 0; c < 4; c++) fc[c] = DCol{I.fcol[c] ? I.fcol[c] : I.fcol[0], Q.ftype[c] ? Q.ftype[c] : 8};
-  for (int64_t r0 = lo + (int64_t)threadIdx.x * kBPR; r0 < hi; r0 += (int64_t)blockDim.x * kBPR) {
-    const bool full = r0 + kBPR <= hi;
-    int64_t v[4][kBPR], k[kBPR], e[kBPR][2];
-    bool ok[kBPR];
+  // the columns of a lane's next rows are requested while its current rows
+  // walk the table (right after their first tag loads are issued)
+  int64_t vn[4][kBPR];
+  auto load = [&](int64_t r) {
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-      if (c < Q.nfact) load4<kBPR>(fc[c], r0, full, hi, v[c]);
+      if (c < Q.nfact) load4<kBPR>(fc[c], r, r + kBPR <= hi, hi, vn[c]);
       else {
 #pragma unroll
-        for (int i = 0; i < kBPR; i++) v[c][i] = 0;
+        for (int i = 0; i < kBPR; i++) vn[c][i] = 0;
       }
     }
+  };
+  const int64_t step = (int64_t)blockDim.x * kBPR;
+  int64_t r0 = lo + (int64_t)threadIdx.x * kBPR;
+  if (r0 < hi) load(r0);
+  for (; r0 < hi; r0 += step) {
+    int64_t k[kBPR], e[kBPR][2];
+    bool ok[kBPR];
 #pragma unroll
     for (int i = 0; i < kBPR; i++) {
-      ok[i] = r0 + i < hi;
-      k[i] = v[0][i];
+      k[i] = vn[0][i];
+      const uint64_t hh = mulhash(k[i]);
+      const uint32_t m = bloom_bits(hh);
+      ok[i] = r0 + i < hi && (bloom[inst_bloom_word(hh, nw)] & m) == m;
 #pragma unroll
-      for (int j = 0; j < 2; j++) e[i][j] = j < Q.nsum ? eval_expr<4, kBPR>(Q.sums[j], v, i) : 0;
+      for (int j = 0; j < 2; j++) e[i][j] = j < Q.nsum ? eval_expr<4, kBPR>(Q.sums[j], vn, i) : 0;
     }
-    pr.walk(ok, k, [&](const bool (&hit)[kBPR], const int64_t (&pay)[kBPR]) {
+    const int64_t r1 = r0 + step;
+    pr.walk(
+        ok, k,
+        [&](const bool (&hit)[kBPR], const int64_t (&pay)[kBPR]) {
 #pragma unroll
-      for (int i = 0; i < kBPR; i++)
-        if (hit[i]) agg.add(T, pay[i], e[i], Q.nsum);
-    });
+          for (int i = 0; i < kBPR; i++)
+            if (hit[i]) agg.add(T, pay[i], e[i], Q.nsum);
+        },
+        [&] {
+          if (r1 < hi) load(r1);
+        });
   }
   // a group key outside the instance's domain: latched in the instance's state
   // (by flush) and in the work area, where tq_batched_check finds it
@@ -308,6 +354,10 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, 
             }
           }
           pend[i] = ok;
+          if (ok) {
+            const uint64_t hh = mulhash(v[0][i]);
+            atomicOr(&I.bloom[inst_bloom_word(hh, I.bloom_nw)], bloom_bits(hh));
+          }
         }
         table_insert<kRows>(words, slots, I.log2cap, 0, pend, v[0], v[1]);
       }
@@ -387,7 +437,7 @@ size_t tq_batched_work_bytes(const tq_instance* h, int32_t n) {
   if (!h || n <= 0) return 0;
   for (int i = 0; i < n; i++)
     if (h[i].build_tile <= 0 || h[i].probe_tile <= 0) return 0;
-  return layout(n, count_items(h, n)).bytes;
+  return layout(n, count_items(h, n), count_bloom_words(h, n)).bytes;
 }
 
 tq_status tq_batched_prepare(const tq_batch_query* q, const tq_instance* h, int32_t n, void* d_work, size_t work_bytes,
@@ -456,7 +506,15 @@ tq_status tq_batched_prepare(const tq_batch_query* q, const tq_instance* h, int3
     if (bi[(size_t)i].nchunks > 1)
       for (int c = 0; c < bi[(size_t)i].nchunks; c++) items.push_back(make_item(kItFinWrite, i, c));
   end[3] = (int64_t)items.size();
-  Layout L = layout(n, (int64_t)items.size());
+  Layout L = layout(n, (int64_t)items.size(), count_bloom_words(h, n));
+  {
+    uint32_t* bw = reinterpret_cast<uint32_t*>(static_cast<char*>(d_work) + L.bloom_off);
+    for (int i = 0; i < n; i++) {
+      bi[(size_t)i].bloom = bw;
+      bi[(size_t)i].bloom_nw = bloom_words_for(h[i].n_dim);
+      bw += bi[(size_t)i].bloom_nw;
+    }
+  }
   if (work_bytes < L.bytes) return fail(TQ_EINVAL, "work area has %zu bytes, needs %zu", work_bytes, L.bytes);
   WorkHeader wh;
   memset(&wh, 0, sizeof wh);
@@ -493,9 +551,10 @@ tq_status tq_batched_run(const tq_batch_query* q, void* d_work, int32_t n, hipSt
       k_batched<0>, k_batched<1>, k_batched<2>, k_batched<3>};
   for (int p = 0; p < kPhases; p++) {
     int per_cu = 0;
-    TQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern[p], kBBlock, kLdsAggBytes));
+    const size_t lds = kLdsAggBytes + (p == 1 ? (size_t)kMaxBloomWords * 4 : 0);  // probe items: the filter too
+    TQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern[p], kBBlock, lds));
     per_cu = std::max(1, std::min(per_cu, 4));
-    hipLaunchKernelGGL(kern[p], dim3(device_cu_count() * per_cu), dim3(kBBlock), kLdsAggBytes, stream, Q, hdr, insts,
+    hipLaunchKernelGGL(kern[p], dim3(device_cu_count() * per_cu), dim3(kBBlock), lds, stream, Q, hdr, insts,
                        items, ctrs);
   }
   TQ_HIP(hipGetLastError());
