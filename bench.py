@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 PROBE_COUNTERS = {
     "sources": ["paper_2508_05029_amd/csrc/join_ops.hip", "paper_2508_05029_amd/csrc/table.h",
                 "paper_2508_05029_amd/csrc/groupby.h", "paper_2508_05029_amd/csrc/common.h"],
-    "sha1": "342a87547767e099ae785e5a22964b870d90a750",
-    "fetch_kib": 115183.6, "fetch_scale": 2.000,
+    "sha1": "4edc09dcced0011b0885e3dd8515b4ae4a86d035",
+    "fetch_kib": 115494.4, "fetch_scale": 2.000,
     "write_kib": 104.0, "write_scale": 0.995,
 }
 
