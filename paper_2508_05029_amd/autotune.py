@@ -1,5 +1,5 @@
 """Autotuner for the batched join + group-by: tile sizes and load factor per
-size bucket, and the partition fan-out of the out-of-core join.
+size bucket.
 
 Instances are bucketed by fact-row decade and by whether their group domain
 fits the dense LDS partials. For each bucket, a sample of its instances is
@@ -89,12 +89,3 @@ def tune_batched(query, instances: Sequence[Tuple[dict, dict, int]], cache_path:
 
 def params_for(instances: Sequence[Tuple[dict, dict, int]], table: Dict[str, tuple]) -> List[tuple]:
     return [table.get(bucket_of(len(f["fk"]), g), DEFAULT) for d, f, g in instances]
-
-
-def tune_ooc_fanout(run_with_fanout: Callable[[int], float], fanouts: Sequence[int] = (6, 7, 8, 9, 10),
-                    log: Callable[[str], None] = lambda s: None) -> int:
-    """The log2 fan-out of the out-of-core join with the smallest time;
-    run_with_fanout(bits) returns a time in ms (on a sample of the input)."""
-    scores = [(run_with_fanout(b), b) for b in fanouts]
-    log("ooc fan-out: " + ", ".join(f"2^{b}: {t:.1f} ms" for t, b in scores))
-    return min(scores)[1]
