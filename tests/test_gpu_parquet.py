@@ -159,8 +159,8 @@ def test_snappy_repeats_and_runs(tmp_path):
     """Snappy bodies of 4 MiB pages with copies of every length class and
     overlapping copies (runs of one value): a column of repeated blocks with
     short repeats, a long run, and a constant column. (The reference
-    compressor never copies from further back than 64 KiB, so the kernel's
-    path for such copies is not reached by files pyarrow writes.)"""
+    compressor never copies from further back than 64 KiB or across a 64 KiB
+    fragment; the hand-built pages below do.)"""
     n = 400_000
     block = pqfiles.uniform(20_000, -2 ** 62, 2 ** 62, np.int64, 27, 0)
     vals = np.concatenate([block] * (n // 20_000))
@@ -191,3 +191,80 @@ def test_pipelined_row_groups_equal_the_whole_read(tmp_path, codec):
             bits = np.unpackbits(valid[name].cpu().numpy(), bitorder="little")[:100_000].astype(bool)
             assert bits.tolist() == m.tolist(), name
     assert pool.free_pages() == 64
+
+
+# ---------------------------------------------------------------------------
+# Snappy bodies built element by element (tests/pqhand.py), for the paths the
+# reference compressor never takes; pyarrow reads every well-formed one back.
+
+def _hand_page(seed, plan):
+    """plan: a list of ('lit', n) / ('copy', offset, length); returns (body, values)."""
+    from tests import pqhand as H
+    rng = np.random.default_rng(seed)
+    out, els = bytearray(), []
+    for step in plan:
+        if step[0] == "lit":
+            b = rng.integers(0, 256, step[1]).astype(np.uint8).tobytes()
+            out += b
+            els.append(H.literal(b))
+        else:
+            _, off, ln = step
+            for _ in range(ln):
+                out.append(out[len(out) - off])
+            els.append(H.copy(off, ln))
+    pad = (-len(out)) % 8
+    if pad:
+        out += bytes(pad)
+        els.append(H.literal(bytes(pad)))
+    return H.snappy_block(els, len(out)), np.frombuffer(bytes(out), np.int64).copy()
+
+
+@pytest.mark.parametrize("name,plan", [
+    # many copies 4000 bytes back, some reaching over a 64 KiB boundary: the in-order pass
+    ("back_4000", [("lit", 70_000), ("copy", 9, 64), ("copy", 1, 50)] + [("lit", 30), ("copy", 4000, 64)] * 900),
+    # elements aligned with the 64 KiB fragments, copies inside them: the fragment pass
+    ("aligned", [("lit", 65_536), ("lit", 30), ("copy", 20, 64)] + [("lit", 34), ("copy", 100, 64)] * 1000),
+    # copies from further back than 64 KiB (4-byte offsets): the in-order pass, read from memory
+    ("far", [("lit", 70_000), ("copy", 68_000, 64), ("copy", 65_536, 40), ("copy", 1, 64), ("copy", 3, 17)]),
+    # a literal across the 64 KiB boundary, then copies reaching back over it
+    ("across", [("lit", 65_530), ("lit", 20), ("copy", 30, 64), ("lit", 80_000), ("copy", 70_000, 10)]),
+])
+def test_hand_built_snappy_pages(tmp_path, name, plan):
+    import pyarrow.parquet as pq
+    from tests import pqhand as H
+    say(f"hand-built snappy page: {name}")
+    body, vals = _hand_page(31, plan)
+    path = H.write(str(tmp_path / f"{name}.parquet"), [body], [len(vals)])
+    assert np.array(pq.read_table(path)["x"]).tolist() == vals.tolist()  # valid Parquet and Snappy
+    res, n = decode(path, [0])
+    assert n == len(vals)
+    assert res[0][0].tolist() == vals.tolist()
+
+
+@pytest.mark.parametrize("bad", ["offset_past_start", "length_mismatch", "truncated", "copy_past_end"])
+def test_malformed_snappy_bodies_are_reported(tmp_path, bad):
+    """A malformed body latches TQ_EINVAL in the work buffer (every access
+    stays inside the page's areas); the pool pages come back."""
+    from tests import pqhand as H
+    body, vals = _hand_page(32, [("lit", 1000), ("copy", 8, 64), ("lit", 2000)])
+    n = len(vals)
+    if bad == "offset_past_start":
+        body = H.snappy_block([H.literal(bytes(16)), H.copy(5000, 8)], n * 8)
+    elif bad == "length_mismatch":
+        body = H._varint(n * 8 + 8) + body[len(H._varint(n * 8)):]
+    elif bad == "truncated":
+        body = body[:-500]
+    else:
+        body = H.snappy_block([H.literal(bytes(16)), H.copy(8, 64)] * 200, n * 8)  # writes past the length
+    path = H.write(str(tmp_path / f"{bad}.parquet"), [body], [n])
+    f = tq.ParquetFile(path)
+    pool = tq.PagePool(1 << 20, 16)
+    pl = f.preload(pool, 0, 1, [0], merge_gap=0)
+    work = torch.empty(pl.work_bytes(), dtype=torch.uint8, device=DEV)
+    data = torch.empty(n, dtype=torch.int64, device=DEV)
+    pl.decode(work, [(data, None)])
+    with pytest.raises(tq.TqError) as e:
+        tq.check(work)
+    assert e.value.status == tq.TQ_EINVAL
+    pl.free()
+    assert pool.free_pages() == 16

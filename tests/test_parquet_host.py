@@ -147,3 +147,29 @@ def test_pool_too_small_is_refused(small):
         f.preload(pool, 0, 3, [0], merge_gap=0)
     assert e.value.status == tq.TQ_ENOMEM
     assert pool.free_pages() == 4
+
+
+def test_hand_written_file_is_valid_parquet_and_walks(tmp_path):
+    """The tests' own minimal writer (Snappy elements placed by hand): pyarrow
+    reads the file back, and the host side finds its one chunk and page."""
+    from tests import pqhand as H
+    rng = np.random.default_rng(5)
+    raw = rng.integers(0, 256, 70_000 + 8 * 10).astype(np.uint8).tobytes()[:70_000]
+    out = bytearray(raw)
+    els = [H.literal(raw)]
+    for off, ln in [(68_000, 64), (1, 16)]:
+        for _ in range(ln):
+            out.append(out[len(out) - off])
+        els.append(H.copy(off, ln))
+    n = len(out) // 8
+    body = H.snappy_block(els, len(out))
+    path = H.write(str(tmp_path / "h.parquet"), [body], [n])
+    assert np.array(pq.read_table(path)["x"]).tobytes() == bytes(out)
+    f = tq.ParquetFile(path)
+    assert f.columns() == [("x", 8, False)] and f.num_rows == n
+    assert f.chunk(0, 0)[2] == 1  # Snappy
+    pool = tq.PagePool(1 << 20, 8, pinned=False)
+    pl = f.preload(pool, 0, 1, [0], merge_gap=0)
+    pl.work_bytes()
+    assert pl.pages() == [(0, n, 0, 0, 0)]
+    pl.free()
