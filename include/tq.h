@@ -260,6 +260,20 @@ size_t tq_dict_unify_scratch_bytes(int64_t n_build);
 tq_status tq_dict_unify(void* d_table, size_t table_bytes, tq_strings build, tq_strings probe, void* d_scratch,
                         size_t scratch_bytes, int32_t* d_remap, hipStream_t stream);
 
+/* Dictionary encoding of a plain string column (its strings need not be
+ * distinct): d_codes[i] = the code of string i, equal codes exactly for equal
+ * strings; codes are 0 .. *d_ndict - 1 (numbered in the order of a 64-bit
+ * hash of the bytes, FNV-1a), and d_first_rows[c] = the smallest row holding
+ * code c, from which the dictionary's strings are read. A group-by or a join
+ * on strings then runs on the codes (both sides of a join encoded as one
+ * column). d_codes and d_first_rows hold n entries; d_scratch
+ * tq_dict_encode_scratch_bytes(n) bytes (temporary storage of a radix sort by
+ * hash, and run tables). *d_ndict is written on the device, -1 if more than 16
+ * distinct strings shared one hash. n < 2^31 - 1. */
+size_t tq_dict_encode_scratch_bytes(int64_t n);
+tq_status tq_dict_encode(tq_strings in, void* d_scratch, size_t scratch_bytes, int32_t* d_codes, int32_t* d_first_rows,
+                         int64_t* d_ndict, hipStream_t stream);
+
 /* int64 join keys from dictionary codes: d_keys[r] = codes[r] (d_remap NULL)
  * or d_remap[codes[r]], and -1 where the code is NULL (d_valid, a bitmap or
  * NULL), outside [0, n_remap) or maps to no entry. Codes of the build side

@@ -342,3 +342,16 @@ def join_agg_strings(build_dict, dim, dvalid, probe_dict, fact, fvalid, query) -
     pi = np.array([0 if s is None else ids[s] for s in pk], np.int64)
     return join_agg_nullable(dict(dim, **{query.build_key: bi}), dvalid, dict(fact, **{query.probe_key: pi}),
                              fvalid, query)
+
+
+def first_occurrence(strings) -> np.ndarray:
+    """first[i] = the smallest row whose string equals string i's (the plain
+    definition of "same dictionary entry"); strings: an (offsets, data) column."""
+    off, data = strings
+    n = len(off) - 1
+    seen: Dict[bytes, int] = {}
+    first = np.empty(n, np.int64)
+    for i in range(n):
+        s = bytes(data[off[i]:off[i + 1]])
+        first[i] = seen.setdefault(s, i)
+    return first

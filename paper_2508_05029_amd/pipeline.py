@@ -660,3 +660,35 @@ class ParquetScan:
 
     def check(self, stream=None):
         tq.check(self.work, stream)
+
+
+class StringGroupBy:
+    """GROUP BY a plain (not dictionary-encoded) string column: tq_dict_encode
+    gives every distinct string a code, the group-by runs on the codes, and
+    the result's keys are the first rows of their strings."""
+
+    def __init__(self, n_max: int, sums, device="cuda"):
+        self.scratch = torch.empty(tq.dict_encode_scratch_bytes(n_max), dtype=torch.uint8, device=device)
+        self.codes = torch.empty(max(n_max, 1), dtype=torch.int32, device=device)
+        self.first = torch.empty(max(n_max, 1), dtype=torch.int32, device=device)
+        self.ndict = torch.zeros(1, dtype=torch.int64, device=device)
+        self.sums = sums
+        self.device = device
+
+    def run(self, column, values: Dict[str, torch.Tensor], stream=None):
+        """column: (offsets, data); values: the columns the sums read. Returns
+        the group-by result with 'first_row' (the smallest row of each group's
+        string) in place of keys."""
+        from .datagen.workloads import FilterGroupByQuery, GroupKey
+        n = column[0].numel() - 1
+        tq.dict_encode(column, self.scratch, self.codes[:n], self.first[:n], self.ndict, stream)
+        nd = int(self.ndict.item())  # the domain of the codes
+        if nd < 0:
+            raise tq.TqError(tq.TQ_EINVAL, "more than 16 distinct strings share one hash")
+        q = FilterGroupByQuery(preds=[], key=GroupKey(("__code",), 1, max(nd, 1)), sums=self.sums,
+                               avg_of=list(range(len(self.sums))))
+        fg = FilterGroupBy(q, self.device)
+        fg.run(dict(values, __code=self.codes[:n]), n, stream)
+        r = fg.result(stream)
+        r["first_row"] = self.first[:max(nd, 1)].cpu().numpy()[r["keys"][:, 0]]
+        return r

@@ -107,6 +107,8 @@ def lib():
             "tq_dict_unify_scratch_bytes": (_sz, [_i64]),
             "tq_dict_unify": (_i32, [_vp, _sz, Strings, Strings, _vp, _sz, _vp, _vp]),
             "tq_dict_keys": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+            "tq_dict_encode_scratch_bytes": (_sz, [_i64]),
+            "tq_dict_encode": (_i32, [Strings, _vp, _sz, _vp, _vp, _vp, _vp]),
             "tq_parquet_open": (_i32, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
             "tq_parquet_close": (None, [_vp]),
             "tq_parquet_num_rows": (_i64, [_vp]),
@@ -346,6 +348,16 @@ def dict_unify(table, build, probe, scratch, remap, stream=None):
     b, p = strings(*build), strings(*probe)
     _check(lib().tq_dict_unify(table.data_ptr(), table.numel(), b, p, scratch.data_ptr(), scratch.numel(),
                                _ptr(remap), _stream(stream)))
+
+
+def dict_encode_scratch_bytes(n: int) -> int:
+    return lib().tq_dict_encode_scratch_bytes(n)
+
+
+def dict_encode(column, scratch, codes, first_rows, ndict, stream=None):
+    """column: (offsets, data) tensors; codes, first_rows: int32 tensors of n; ndict: int64 tensor of 1."""
+    _check(lib().tq_dict_encode(strings(*column), scratch.data_ptr(), scratch.numel(), _ptr(codes), _ptr(first_rows),
+                                ndict.data_ptr(), _stream(stream)))
 
 
 def dict_keys(codes, valid, n, remap, keys, stream=None):

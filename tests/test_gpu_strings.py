@@ -151,3 +151,63 @@ def test_join_on_plain_string_columns():
     assert got["join_rows"] == want["join_rows"] > 0
     for k in ("keys", "count", "sums"):
         assert got[k].tolist() == want[k].tolist(), k
+
+
+def gpu_encode(sc):
+    n = len(sc[0]) - 1
+    scratch = torch.empty(tq.dict_encode_scratch_bytes(n), dtype=torch.uint8, device=DEV)
+    codes = torch.full((max(n, 1),), -5, dtype=torch.int32, device=DEV)
+    first = torch.full((max(n, 1),), -5, dtype=torch.int32, device=DEV)
+    nd = torch.zeros(1, dtype=torch.int64, device=DEV)
+    tq.dict_encode(on_dev(sc), scratch, codes[:n], first[:n], nd)
+    torch.cuda.synchronize()
+    return codes[:n].cpu().numpy(), first.cpu().numpy(), int(nd.item())
+
+
+def check_encoding(sc):
+    codes, first, nd = gpu_encode(sc)
+    want = oracle.first_occurrence(sc)
+    assert nd == len(np.unique(want))
+    assert codes.min(initial=0) >= 0 and codes.max(initial=-1) < nd
+    # equal codes exactly for equal strings, and each code's first row is its smallest
+    assert first[codes].tolist() == want.tolist()
+
+
+@pytest.mark.parametrize("case", ["empty", "one", "all_equal", "all_distinct", "tricky", "zipf"])
+def test_dict_encode_matches_first_occurrence(case):
+    say(f"dict_encode {case}")
+    rng = np.random.default_rng(41)
+    if case == "empty":
+        strs = []
+    elif case == "one":
+        strs = [b"abc"]
+    elif case == "all_equal":
+        strs = [b"same string"] * 70_000
+    elif case == "all_distinct":
+        strs = tricky(5000, 42)
+    elif case == "tricky":
+        pool = tricky(300, 43)
+        strs = [pool[i] for i in rng.integers(0, len(pool), 20_000)]
+    else:
+        pool = [s for s in oracle.decode(wl.string_join_tables(2000, 1).build_dict, np.arange(2000))]
+        cdf = np.cumsum(1.0 / np.arange(1, 2001) ** 1.1)
+        idx = np.searchsorted(cdf / cdf[-1], rng.random(300_000))
+        strs = [pool[i] for i in idx]
+    check_encoding(arrow(strs))
+
+
+def test_group_by_a_plain_string_column():
+    """GROUP BY over strings that are not dictionary-encoded: encoded on the
+    GPU, grouped on the codes; the oracle groups the strings themselves."""
+    n = 200_000
+    T = wl.string_join_tables(20_000, n, seed=75)
+    strs = oracle.decode(T.probe_dict, T.fact["fk"])  # 200K strings, many repeated
+    col = arrow(strs)
+    sg = pipeline.StringGroupBy(n, [(Factor("price"),)])
+    got = sg.run(on_dev(col), {"price": torch.from_numpy(T.fact["price"]).to(DEV)})
+    by = {strs[int(r)]: (int(c), int(v)) for r, c, v in zip(got["first_row"], got["count"], got["sums"][:, 0])}
+    want = {}
+    for s, v in zip(strs, T.fact["price"].tolist()):
+        c, t = want.get(s, (0, 0))
+        want[s] = (c + 1, t + v)
+    assert by == want

@@ -532,3 +532,13 @@ def test_join_agg_strings_matches_brute(seed):
     assert got["keys"].tolist() == sorted(groups)
     assert got["count"].tolist() == [groups[g][0] for g in sorted(groups)]
     assert got["sums"].tolist() == [groups[g][1] for g in sorted(groups)]
+
+
+def test_first_occurrence_matches_nested_loops():
+    rng = np.random.default_rng(7)
+    pool = _tricky_strings(40, 8)
+    strs = [pool[i] for i in rng.integers(0, len(pool), 300)]
+    got = oracle.first_occurrence(_arrow(strs))
+    want = [min(j for j in range(len(strs)) if strs[j] == strs[i]) for i in range(len(strs))]
+    assert got.tolist() == want
+    assert oracle.first_occurrence(_arrow([])).tolist() == []
