@@ -712,7 +712,8 @@ tq_status tq_parquet_chunk(const tq_parquet* pq, int32_t rg, int32_t c, int64_t*
  * groups [rg0, rg1), sorted by offset, ranges at most merge_gap bytes apart
  * merged into one read; pool pages are taken for every read (TQ_ENOMEM if the
  * pool has too few) and a host thread starts reading into them; the call
- * returns at once. */
+ * returns at once. The file handle and the pool must outlive the preload
+ * (tq_preload_free waits for the reads). */
 tq_status tq_parquet_preload(tq_parquet* pq, tq_pagepool* pool, int32_t rg0, int32_t rg1, const int32_t* h_cols,
                              int32_t ncol, int64_t merge_gap, tq_preload** out);
 int32_t tq_preload_num_reads(const tq_preload* p);
@@ -736,7 +737,7 @@ tq_status tq_preload_page(const tq_preload* p, int64_t i, int64_t* row0, int32_t
  * are done and the pages are back in the pool, with the kernels enqueued.
  * Errors found by the kernels (a malformed stream, a dictionary index out of
  * range) are latched in d_work: tq_check(d_work, stream) reports them. A
- * preload is decoded once. */
+ * preload is decoded once (a second call returns TQ_EINVAL). */
 tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, const tq_col* out, hipStream_t stream);
 /* Waits for the reads, returns unused pages to the pool and frees the handle. */
 void tq_preload_free(tq_preload* p);

@@ -743,7 +743,6 @@ tq_status tq_preload_work_bytes(tq_preload* p, size_t* bytes) {
   if (!p || !bytes) return fail(TQ_EINVAL, "preload or bytes is NULL");
   tq_status s;
   if ((s = pq_join(p))) return s;
-  if (p->reads.empty() && !p->pages.empty()) return fail(TQ_EINVAL, "the preload was decoded already");
   if ((s = pq_parse_pages(p))) return s;
   *bytes = pq_work_bytes(p);
   return TQ_OK;

@@ -117,6 +117,7 @@ struct tq_preload {
   int64_t rows = 0;
   std::thread reader;
   bool joined = false;
+  bool decoded = false;  // a preload is decoded once: its pages go back to the pool
   tq_status read_status = TQ_OK;
   std::string read_error;
   // page headers, parsed once the bytes are in host memory

@@ -776,7 +776,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
   tq_status s;
   if ((s = pq_join(p))) return s;
   if ((s = pq_parse_pages(p))) return s;
-  if (p->reads.empty() && p->raw_bytes > 0) return fail(TQ_EINVAL, "the preload was decoded already");
+  if (p->decoded) return fail(TQ_EINVAL, "the preload was decoded already");
   const PqLayout L = pq_layout(p);
   if (work_bytes < L.total) return fail(TQ_EINVAL, "work buffer needs %zu bytes", L.total);
   const int32_t ncol = (int32_t)p->cols.size();
@@ -927,6 +927,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
   }
   give_back();
   pq_release_pages(p);
+  p->decoded = true;
   if (e != hipSuccess) return hip_fail(e, "parquet decode");
   return TQ_OK;
 }

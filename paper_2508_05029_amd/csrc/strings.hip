@@ -268,6 +268,7 @@ tq_status tq_dict_unify(void* d_table, size_t table_bytes, tq_strings build, tq_
                         size_t scratch_bytes, int32_t* d_remap, hipStream_t stream) {
   if (!d_table) return fail(TQ_EINVAL, "table is NULL");
   if (build.n < 0 || probe.n < 0) return fail(TQ_EINVAL, "negative string count");
+  if (build.n > INT32_MAX - 1) return fail(TQ_EINVAL, "build dictionary of %lld entries (int32 codes)", (long long)build.n);
   if ((build.n > 0 && (!build.offsets || !build.data)) || (probe.n > 0 && (!probe.offsets || !probe.data)))
     return fail(TQ_EINVAL, "NULL string column");
   if (probe.n > 0 && !d_remap) return fail(TQ_EINVAL, "d_remap is NULL");

@@ -268,3 +268,20 @@ def test_malformed_snappy_bodies_are_reported(tmp_path, bad):
     assert e.value.status == tq.TQ_EINVAL
     pl.free()
     assert pool.free_pages() == 16
+
+
+def test_a_preload_is_decoded_once(tmp_path):
+    cols = pqfiles.columns(2000, 29)
+    path = pqfiles.write(str(tmp_path / "once.parquet"), cols)
+    f = tq.ParquetFile(path)
+    pool = tq.PagePool(1 << 16, 32)
+    pl = f.preload(pool, 0, 1, [0], merge_gap=0)
+    work = torch.empty(pl.work_bytes(), dtype=torch.uint8, device=DEV)
+    data = torch.empty(2000, dtype=torch.int64, device=DEV)
+    pl.decode(work, [(data, None)])
+    tq.check(work)
+    assert pool.free_pages() == 32  # the pages are back already
+    with pytest.raises(tq.TqError, match="decoded already"):
+        pl.decode(work, [(data, None)])
+    pl.free()
+    assert data.cpu().numpy().tolist() == cols[0][1].tolist()
