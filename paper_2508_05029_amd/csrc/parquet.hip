@@ -135,11 +135,21 @@ struct InWindow {
   int32_t wbase;
   __device__ void ensure(int32_t at, int32_t need) {
     if (at >= wbase && at + need <= wbase + kInWin) return;
-    const int64_t abs0 = (c_off + at) & ~(int64_t)3;
+    // 16-byte loads, all issued before any is stored: one memory round trip
+    const int64_t abs0 = (c_off + at) & ~(int64_t)15;
     wbase = (int32_t)(abs0 - c_off);
-    for (int i = threadIdx.x; i < kInWin / 4 + 4; i += 64) {
-      const int64_t a = abs0 + 4 * (int64_t)i;  // a dword starting before the input's end stays in the padded area
-      win[i] = a < c_off + in_len ? *reinterpret_cast<const uint32_t*>(raw + a) : 0u;
+    constexpr int kV = (kInWin / 16 + 1 + 63) / 64;  // loads per lane
+    v4i32 t[kV];
+#pragma unroll
+    for (int u = 0; u < kV; u++) {
+      const int i = (int)threadIdx.x + 64 * u;
+      const int64_t a = abs0 + 16 * (int64_t)i;  // a load starting before the input's end stays in the padded area
+      t[u] = i < kInWin / 16 + 1 && a < c_off + in_len ? *reinterpret_cast<const v4i32*>(raw + a) : v4i32{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < kV; u++) {
+      const int i = (int)threadIdx.x + 64 * u;
+      if (i < kInWin / 16 + 1) reinterpret_cast<v4i32*>(win)[i] = t[u];
     }
     __syncthreads();
   }
@@ -166,6 +176,39 @@ __device__ bool snappy_preamble(InWindow& w, uint32_t* ulen, int32_t* ip) {
 
 constexpr int kFrag = 65536;  // the reference compressor's independent fragments
 
+// The elements that start among a batch's 64 candidates (lane i: the
+// element that would start at the batch's byte i, nxt = i + its input bytes),
+// found in parallel by pointer doubling: after step k every lane knows the
+// start 2^(k+1) elements after its own, and the set of starts reached from
+// lane 0 doubles; six steps reach every element that starts in the batch.
+// Returns them as a lane mask; *incl: the inclusive prefix sum of their
+// output lengths (0 for other lanes' own term).
+__device__ uint64_t snappy_elements(int32_t nxt, int32_t c_len, int32_t* mark, int64_t* incl) {
+  const int lane = threadIdx.x;
+  int32_t J = nxt;
+  uint64_t on = 1;
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    mark[lane] = 0;
+    if ((on >> lane & 1) && J < 64) mark[J] = 1;
+    // (a barrier, though the workgroup is one wave, so that the compiler
+    // reads the marks other lanes wrote instead of this lane's own zero)
+    __syncthreads();
+    on |= __ballot(mark[lane] != 0);
+    __syncthreads();
+    const int32_t jj = __shfl(J, J < 64 ? J : lane);
+    J = J < 64 ? jj : J;
+  }
+  int64_t x = (on >> lane & 1) ? (int64_t)c_len : 0;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  *incl = x;
+  return on;
+}
+
 // Pass 1, one wave per compressed body: follows the element chain (bounds
 // checked), records where each 64 KiB output fragment's first element starts,
 // and flags the body when an element crosses a fragment or copies from
@@ -173,7 +216,8 @@ constexpr int kFrag = 65536;  // the reference compressor's independent fragment
 // flags: 0 fragments independent, 1 inflate in order, 2 malformed.
 __global__ __launch_bounds__(64) void k_pq_snappy_scan(const PqPage* pages, const int32_t* cpages, const uint8_t* raw,
                                                        int32_t* frag_in, int32_t* flags, PqHeader* hdr) {
-  __shared__ uint32_t wbuf[kInWin / 4 + 4];
+  __shared__ __align__(16) uint32_t wbuf[kInWin / 4 + 4];
+  __shared__ int32_t mark[64];
   const PqPage pg = pages[cpages[blockIdx.x]];
   InWindow w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
   const int32_t out_len = (int32_t)pg.u_len;
@@ -188,24 +232,26 @@ __global__ __launch_bounds__(64) void k_pq_snappy_scan(const PqPage* pages, cons
     w.ensure(ip, 64 + 8);
     int32_t c_adv, c_len, c_off;
     snappy_candidate(w.win, ip + lane - w.wbase, c_adv, c_len, c_off);
-    // The chain is followed with as few instructions as possible (one wave
-    // issues one every few cycles): bounds are not checked per element, since
-    // nothing is read or written here but the fragment starts (below the
-    // output length); a malformed body ends its chain off the input's or
-    // the output's end, and the fragment pass checks every access itself.
-    int32_t rel = 0;
-    while (rel < 64 && q < out_len) {
-      const int32_t adv = __builtin_amdgcn_readlane(c_adv, rel);
-      const int32_t len = __builtin_amdgcn_readlane(c_len, rel);
-      const int32_t off = __builtin_amdgcn_readlane(c_off, rel);  // 0: a literal; -1: invalid
-      const int32_t fs = q & ~(kFrag - 1);
-      if (q == fs && lane == 0) fi[q >> 16] = ip + rel;
-      dep = dep || (q + len > fs + kFrag) || (q - off < fs) || off < 0;
-      q += len;
-      rel += adv;
+    const int32_t nxt = lane + c_adv;  // the next element's candidate (>= 64: past the batch)
+    int64_t x;
+    const uint64_t on = snappy_elements(nxt, c_len, mark, &x);
+    const bool el = (on >> lane) & 1;
+    const int64_t qs = (int64_t)q + x - (el ? c_len : 0);  // this element's first output byte
+    if (el && qs < out_len) {
+      const int64_t fs = qs & ~(int64_t)(kFrag - 1);
+      if (qs == fs) fi[qs >> 16] = ip + lane;
     }
-    ip += rel;
-    if (ip > w.in_len) bad = true;
+    dep = dep || __ballot(el && qs < out_len &&
+                          ((qs + c_len > (qs & ~(int64_t)(kFrag - 1)) + kFrag) ||
+                           qs - c_off < (qs & ~(int64_t)(kFrag - 1)) || c_off < 0)) != 0;
+    // the batch ends at its last element that starts below the output's end
+    // (past it, the candidates read beyond the input: no elements)
+    const uint64_t live = __ballot(el && qs < out_len);  // lane 0 is live: q < out_len here
+    const int last = 63 - __builtin_clzll(live);
+    const int64_t qn = (int64_t)q + __shfl(x, last);
+    q = qn > (int64_t)INT32_MAX ? INT32_MAX : (int32_t)qn;
+    ip += __shfl(nxt, last);
+    if (ip > w.in_len || ip < 0) bad = true;
   }
   if (!bad && (ip != w.in_len || q != out_len)) bad = true;  // the chain must end at both ends
   if (lane == 0) {
@@ -221,7 +267,8 @@ __global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, cons
                                                        const int32_t* frag_cpage, uint8_t* raw, const int32_t* frag_in,
                                                        const int32_t* flags, PqHeader* hdr) {
   __shared__ uint32_t buf[kFrag / 4];
-  __shared__ uint32_t wbuf[kInWin / 4 + 4];
+  __shared__ __align__(16) uint32_t wbuf[kInWin / 4 + 4];
+  __shared__ int32_t mark[64];
   uint8_t* fb = reinterpret_cast<uint8_t*>(buf);
   const int32_t ci = frag_cpage[blockIdx.x];
   if (flags[ci] != 0) return;
@@ -238,30 +285,49 @@ __global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, cons
     w.ensure(ip, 64 + 8);
     int32_t c_adv, c_len, c_off;
     snappy_candidate(w.win, ip + lane - w.wbase, c_adv, c_len, c_off);
-    int32_t rel = 0;
-    while (rel < 64 && q < fe) {
-      const int32_t at = ip + rel;
-      const int32_t adv = __builtin_amdgcn_readlane(c_adv, rel);
-      const int32_t len = __builtin_amdgcn_readlane(c_len, rel);
-      const int32_t off = __builtin_amdgcn_readlane(c_off, rel);
-      const bool literal = off == 0;
-      // the scan checked the chain; these checks keep every access in bounds regardless
-      if (at >= w.in_len || len > fe - q || adv > w.in_len - at || (!literal && (off <= 0 || off > q - fs))) {
-        bad = true;
-        break;
-      }
-      const int32_t lq = q - fs;  // position in the fragment
-      if (literal) {
-        const int32_t src = at + adv - len;
+    const int32_t nxt = lane + c_adv;
+    int64_t incl;
+    const uint64_t on = snappy_elements(nxt, c_len, mark, &incl);
+    const bool el = (on >> lane) & 1;
+    const int64_t qs = (int64_t)q + incl - (el ? c_len : 0);  // this element's first output byte
+    const uint64_t live = __ballot(el && qs < fe);             // the fragment's elements in the batch
+    const bool me = (live >> lane) & 1;
+    const int32_t at = ip + lane;
+    // the scan checked the chain; these checks keep every access in bounds regardless
+    const bool badl = me && (at >= w.in_len || c_len > fe - qs || c_adv > w.in_len - at ||
+                             (c_off != 0 && (c_off <= 0 || c_off > qs - fs)));
+    if (__ballot(badl)) {
+      bad = true;
+      break;
+    }
+    // short literals: each lane writes its own; they read nothing of the output
+    const bool short_lit = me && c_off == 0 && c_len <= 64;
+    if (short_lit) {
+      const int32_t src = at + c_adv - c_len, lq = (int32_t)(qs - fs);
+      const bool in_win = src >= w.wbase && src + c_len <= w.wbase + kInWin;
+      for (int32_t j = 0; j < c_len; j++) fb[lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
+    }
+    __syncthreads();  // (one wave: for the compiler, the bytes other lanes wrote)
+    // copies (which read earlier output) and long literals, in order, each by the whole wave
+    uint64_t rest = live & ~__ballot(short_lit);
+    while (rest) {
+      const int l = __builtin_ctzll(rest);
+      rest &= rest - 1;
+      const int32_t len = __builtin_amdgcn_readlane(c_len, l);
+      const int32_t off = __builtin_amdgcn_readlane(c_off, l);
+      const int32_t lq = __builtin_amdgcn_readlane((int32_t)(qs - fs), l);
+      if (off == 0) {
+        const int32_t src = ip + l + __builtin_amdgcn_readlane(c_adv, l) - len;
         const bool in_win = src >= w.wbase && src + len <= w.wbase + kInWin;
         for (int32_t j = lane; j < len; j += 64) fb[lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
       } else if (lane < len) {
         fb[lq + lane] = fb[lq - off + (off >= len ? lane : lane % off)];
       }
-      q += len;
-      rel += adv;
+      __syncthreads();
     }
-    ip += rel;
+    const int last = 63 - __builtin_clzll(live);
+    q = (int32_t)((int64_t)q + __shfl(incl, last));
+    ip += __shfl(nxt, last);
   }
   if (bad) {
     if (lane == 0) pq_error(hdr, TQ_EINVAL);
