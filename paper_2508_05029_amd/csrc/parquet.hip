@@ -133,22 +133,23 @@ struct InWindow {
   int64_t c_off;
   int32_t in_len;
   int32_t wbase;
+  template <int NT = 64>  // the workgroup's threads
   __device__ void ensure(int32_t at, int32_t need) {
     if (at >= wbase && at + need <= wbase + kInWin) return;
     // 16-byte loads, all issued before any is stored: one memory round trip
     const int64_t abs0 = (c_off + at) & ~(int64_t)15;
     wbase = (int32_t)(abs0 - c_off);
-    constexpr int kV = (kInWin / 16 + 1 + 63) / 64;  // loads per lane
+    constexpr int kV = (kInWin / 16 + 1 + NT - 1) / NT;  // loads per thread
     v4i32 t[kV];
 #pragma unroll
     for (int u = 0; u < kV; u++) {
-      const int i = (int)threadIdx.x + 64 * u;
+      const int i = (int)threadIdx.x + NT * u;
       const int64_t a = abs0 + 16 * (int64_t)i;  // a load starting before the input's end stays in the padded area
       t[u] = i < kInWin / 16 + 1 && a < c_off + in_len ? *reinterpret_cast<const v4i32*>(raw + a) : v4i32{0, 0, 0, 0};
     }
 #pragma unroll
     for (int u = 0; u < kV; u++) {
-      const int i = (int)threadIdx.x + 64 * u;
+      const int i = (int)threadIdx.x + NT * u;
       if (i < kInWin / 16 + 1) reinterpret_cast<v4i32*>(win)[i] = t[u];
     }
     __syncthreads();
@@ -158,8 +159,9 @@ struct InWindow {
 
 // The length preamble (a varint) of a Snappy body; its size in *ip, false
 // if malformed.
+template <int NT = 64>
 __device__ bool snappy_preamble(InWindow& w, uint32_t* ulen, int32_t* ip) {
-  w.ensure(0, 8);
+  w.ensure<NT>(0, 8);
   uint32_t v = 0;
   int32_t i = 0;
   for (int sh = 0;; sh += 7) {
@@ -209,54 +211,154 @@ __device__ uint64_t snappy_elements(int32_t nxt, int32_t c_len, int32_t* mark, i
   return on;
 }
 
-// Pass 1, one wave per compressed body: follows the element chain (bounds
-// checked), records where each 64 KiB output fragment's first element starts,
-// and flags the body when an element crosses a fragment or copies from
-// before its fragment (then the body is inflated by one wave, in order).
-// flags: 0 fragments independent, 1 inflate in order, 2 malformed.
-__global__ __launch_bounds__(64) void k_pq_snappy_scan(const PqPage* pages, const int32_t* cpages, const uint8_t* raw,
-                                                       int32_t* frag_in, int32_t* flags, PqHeader* hdr) {
+// Pass 1, one workgroup of kScanWaves waves per compressed body: follows the
+// element chain, records where each 64 KiB output fragment's first element
+// starts, and flags the body when an element crosses a fragment or copies
+// from before its fragment (then the body is inflated by one wave, in order,
+// with every access checked). flags: 0 fragments independent, 1 inflate in
+// order, 2 malformed.
+//
+// A step covers kScanStep input bytes, 64 per wave, each thread decoding the
+// element that would start at its byte. (1) Each wave finds, by pointer
+// doubling, where the chain from each of its lanes leaves the wave's 64 bytes
+// and the output bytes written on the way. (2) One thread composes the waves:
+// from the step's first byte it hops wave by wave (at most kScanWaves hops),
+// giving each wave the lane its elements start at and the output position
+// there. (3) Each wave marks its elements (doubling again) and their output
+// positions (a prefix sum).
+constexpr int kScanWaves = 16;
+constexpr int kScanStep = 64 * kScanWaves;
+// element lengths are summed in 32 bits clamped to this; a body with a longer
+// element is flagged for the in-order pass
+constexpr int32_t kLenClamp = 1 << 24;
+
+__global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* pages, const int32_t* cpages,
+                                                              const uint8_t* raw, int32_t* frag_in, int32_t* flags,
+                                                              PqHeader* hdr) {
   __shared__ __align__(16) uint32_t wbuf[kInWin / 4 + 4];
-  __shared__ int32_t mark[64];
+  __shared__ int32_t ex[kScanStep];    // where the chain from each byte leaves its wave (step-relative)
+  __shared__ uint32_t sm[kScanStep];   // the output bytes of its elements up to there
+  __shared__ int32_t mark[kScanStep];
+  __shared__ int32_t ent[kScanWaves];  // each wave's first element (lane; -1: none)
+  __shared__ int64_t qent[kScanWaves];  // and its output position
+  __shared__ int32_t endp[kScanWaves];  // each wave's first element at or past the output's end (-1: none)
+  __shared__ int64_t endq[kScanWaves];
+  __shared__ int32_t s_exit;           // where the chain leaves the step (step-relative)
+  __shared__ int64_t s_q;              // and the output position there
+  __shared__ int32_t s_dep;
   const PqPage pg = pages[cpages[blockIdx.x]];
   InWindow w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
-  const int32_t out_len = (int32_t)pg.u_len;
+  const int64_t out_len = pg.u_len;
   int32_t* fi = frag_in + pg.frag0;
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  if (t == 0) s_dep = 0;
   uint32_t ulen;
   int32_t ip;
-  bool bad = !snappy_preamble(w, &ulen, &ip) || ulen != (uint32_t)out_len;
-  bool dep = false;
-  int32_t q = 0;
-  while (!bad && q < out_len) {
-    w.ensure(ip, 64 + 8);
+  bool bad = !snappy_preamble<kScanStep>(w, &ulen, &ip) || ulen != (uint32_t)out_len;
+  bool dep = false, done = bad;
+  int64_t q = 0;
+  __syncthreads();
+  // every thread holds the same ip, q, done: the loop is uniform
+  while (!done) {
+    w.ensure<kScanStep>(ip, kScanStep + 8);
     int32_t c_adv, c_len, c_off;
-    snappy_candidate(w.win, ip + lane - w.wbase, c_adv, c_len, c_off);
-    const int32_t nxt = lane + c_adv;  // the next element's candidate (>= 64: past the batch)
-    int64_t x;
-    const uint64_t on = snappy_elements(nxt, c_len, mark, &x);
+    snappy_candidate(w.win, ip + t - w.wbase, c_adv, c_len, c_off);
+    const uint32_t own = (uint32_t)min(c_len, kLenClamp);
+    // (1) jk[k]: the start 2^k elements on (>= 64: the chain has left the wave)
+    int32_t jk[6];
+    int32_t J = lane + c_adv;
+    uint32_t S = own;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      jk[k] = J;
+      const int src = J < 64 ? J : lane;
+      const int32_t Jn = __shfl(J, src);
+      const uint32_t Sn = __shfl(S, src);
+      if (J < 64) {
+        J = Jn;
+        S += Sn;
+      }
+    }
+    ex[t] = wv * 64 + J;
+    sm[t] = S;
+    __syncthreads();
+    // (2)
+    if (t == 0) {
+      for (int i = 0; i < kScanWaves; i++) ent[i] = -1;
+      int32_t pos = 0;
+      int64_t qq = q;
+      while (pos < kScanStep) {
+        ent[pos >> 6] = pos & 63;
+        qent[pos >> 6] = qq;
+        qq += sm[pos];
+        pos = ex[pos];
+      }
+      s_exit = pos;
+      s_q = qq;
+    }
+    __syncthreads();
+    // (3)
+    const int32_t e = ent[wv];
+    uint64_t on = e >= 0 ? 1ull << e : 0ull;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      mark[t] = 0;
+      if ((on >> lane & 1) && jk[k] < 64) mark[wv * 64 + jk[k]] = 1;
+      __syncthreads();
+      on |= __ballot(mark[t] != 0);
+      __syncthreads();
+    }
     const bool el = (on >> lane) & 1;
-    const int64_t qs = (int64_t)q + x - (el ? c_len : 0);  // this element's first output byte
+    uint32_t x = el ? own : 0u;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    const int64_t qs = (e >= 0 ? qent[wv] : 0) + (int64_t)(x - (el ? own : 0u));  // this element's first output byte
+    const uint64_t endm = __ballot(el && qs >= out_len);
+    const int fl = endm ? __builtin_ctzll(endm) : 0;
+    const int64_t fq = __shfl(qs, fl);
+    if (lane == 0) {
+      endp[wv] = endm ? wv * 64 + fl : -1;
+      endq[wv] = fq;
+    }
     if (el && qs < out_len) {
       const int64_t fs = qs & ~(int64_t)(kFrag - 1);
-      if (qs == fs) fi[qs >> 16] = ip + lane;
+      if (qs == fs) fi[qs >> 16] = ip + t;
+      if (c_len > kLenClamp || qs + c_len > fs + kFrag || (c_off != 0 && (c_off < 0 || qs - c_off < fs))) s_dep = 1;
     }
-    dep = dep || __ballot(el && qs < out_len &&
-                          ((qs + c_len > (qs & ~(int64_t)(kFrag - 1)) + kFrag) ||
-                           qs - c_off < (qs & ~(int64_t)(kFrag - 1)) || c_off < 0)) != 0;
-    // the batch ends at its last element that starts below the output's end
-    // (past it, the candidates read beyond the input: no elements)
-    const uint64_t live = __ballot(el && qs < out_len);  // lane 0 is live: q < out_len here
-    const int last = 63 - __builtin_clzll(live);
-    const int64_t qn = (int64_t)q + __shfl(x, last);
-    q = qn > (int64_t)INT32_MAX ? INT32_MAX : (int32_t)qn;
-    ip += __shfl(nxt, last);
-    if (ip > w.in_len || ip < 0) bad = true;
+    __syncthreads();
+    // the chain's end: the first element at or past the output's end, which
+    // must start at the input's end exactly at the output's end
+    int32_t endpos = -1;
+    int64_t eq = 0;
+    for (int i = 0; i < kScanWaves; i++)
+      if (endp[i] >= 0) {
+        endpos = endp[i];
+        eq = endq[i];
+        break;
+      }
+    if (s_dep != 0) {
+      dep = true;
+      done = true;
+    } else if (endpos >= 0) {
+      done = true;
+      bad = (int64_t)ip + endpos != w.in_len || eq != out_len;
+    } else {
+      const int64_t nip = (int64_t)ip + s_exit;
+      q = s_q;
+      if (nip > w.in_len) {
+        bad = true;
+        done = true;
+      } else {
+        ip = (int32_t)nip;
+      }
+    }
   }
-  if (!bad && (ip != w.in_len || q != out_len)) bad = true;  // the chain must end at both ends
-  if (lane == 0) {
-    flags[blockIdx.x] = bad ? 2 : dep ? 1 : 0;
-    if (bad) pq_error(hdr, TQ_EINVAL);
+  if (t == 0) {
+    flags[blockIdx.x] = dep ? 1 : bad ? 2 : 0;
+    if (bad && !dep) pq_error(hdr, TQ_EINVAL);
   }
 }
 
@@ -960,7 +1062,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
       const int32_t* cl = reinterpret_cast<const int32_t*>(W + L.compl_);
       int32_t* frag_in = reinterpret_cast<int32_t*>(W + L.frag_in);
       int32_t* flags = reinterpret_cast<int32_t*>(W + L.cflags);
-      hipLaunchKernelGGL(k_pq_snappy_scan, dim3((int)comp_pages.size()), dim3(64), 0, stream, dp, cl, raw, frag_in,
+      hipLaunchKernelGGL(k_pq_snappy_scan, dim3((int)comp_pages.size()), dim3(kScanStep), 0, stream, dp, cl, raw, frag_in,
                          flags, hdr);
       if (p->frags > 0)
         hipLaunchKernelGGL(k_pq_snappy_frag, dim3((int)p->frags), dim3(64), 0, stream, dp, cl,
