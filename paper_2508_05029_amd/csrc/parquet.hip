@@ -219,13 +219,15 @@ __device__ uint64_t snappy_elements(int32_t nxt, int32_t c_len, int32_t* mark, i
 // order, 2 malformed.
 //
 // A step covers kScanStep input bytes, 64 per wave, each thread decoding the
-// element that would start at its byte. (1) Each wave finds, by pointer
-// doubling, where the chain from each of its lanes leaves the wave's 64 bytes
-// and the output bytes written on the way. (2) One thread composes the waves:
-// from the step's first byte it hops wave by wave (at most kScanWaves hops),
-// giving each wave the lane its elements start at and the output position
-// there. (3) Each wave marks its elements (doubling again) and their output
-// positions (a prefix sum).
+// element that would start at its byte. (1) Each wave builds, by pointer
+// doubling, the start 2^k elements on from each lane and the output bytes of
+// those 2^k elements (k < 6), up to where the chain leaves the wave's 64
+// bytes. (2) One thread composes the waves: from the step's first byte it hops
+// wave by wave (at most kScanWaves hops), giving each wave the lane its
+// elements start at and the output position there. (3) Each lane, from its
+// wave's first element, jumps 2^k elements (k = 5 .. 0) while that lands at
+// or before it: it is an element if it lands on itself, and the jumps' output
+// bytes give its output position.
 constexpr int kScanWaves = 16;
 constexpr int kScanStep = 64 * kScanWaves;
 // element lengths are summed in 32 bits clamped to this; a body with a longer
@@ -236,16 +238,14 @@ __global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* page
                                                               const uint8_t* raw, int32_t* frag_in, int32_t* flags,
                                                               PqHeader* hdr) {
   __shared__ __align__(16) uint32_t wbuf[kInWin / 4 + 4];
-  __shared__ int32_t ex[kScanStep];    // where the chain from each byte leaves its wave (step-relative)
-  __shared__ uint32_t sm[kScanStep];   // the output bytes of its elements up to there
-  __shared__ int32_t mark[kScanStep];
+  __shared__ int2 exs[kScanStep];      // where the chain from each byte leaves its wave (step-relative),
+                                       // and the output bytes of its elements up to there
   __shared__ int32_t ent[kScanWaves];  // each wave's first element (lane; -1: none)
   __shared__ int64_t qent[kScanWaves];  // and its output position
-  __shared__ int32_t endp[kScanWaves];  // each wave's first element at or past the output's end (-1: none)
-  __shared__ int64_t endq[kScanWaves];
   __shared__ int32_t s_exit;           // where the chain leaves the step (step-relative)
   __shared__ int64_t s_q;              // and the output position there
   __shared__ int32_t s_dep;
+  __shared__ uint32_t s_end;           // the first element at or past the output's end: position << 1 | malformed
   const PqPage pg = pages[cpages[blockIdx.x]];
   InWindow w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
   const int64_t out_len = pg.u_len;
@@ -263,14 +263,15 @@ __global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* page
     w.ensure<kScanStep>(ip, kScanStep + 8);
     int32_t c_adv, c_len, c_off;
     snappy_candidate(w.win, ip + t - w.wbase, c_adv, c_len, c_off);
-    const uint32_t own = (uint32_t)min(c_len, kLenClamp);
-    // (1) jk[k]: the start 2^k elements on (>= 64: the chain has left the wave)
+    // (1) jk[k]: the start 2^k elements on (>= 64: past the wave); sk[k]: their output bytes
     int32_t jk[6];
+    uint32_t sk[6];
     int32_t J = lane + c_adv;
-    uint32_t S = own;
+    uint32_t S = (uint32_t)min(c_len, kLenClamp);
 #pragma unroll
     for (int k = 0; k < 6; k++) {
       jk[k] = J;
+      sk[k] = S;
       const int src = J < 64 ? J : lane;
       const int32_t Jn = __shfl(J, src);
       const uint32_t Sn = __shfl(S, src);
@@ -279,8 +280,7 @@ __global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* page
         S += Sn;
       }
     }
-    ex[t] = wv * 64 + J;
-    sm[t] = S;
+    exs[t] = make_int2(wv * 64 + J, (int32_t)S);  // S <= 64 * kLenClamp
     __syncthreads();
     // (2)
     if (t == 0) {
@@ -288,63 +288,50 @@ __global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* page
       int32_t pos = 0;
       int64_t qq = q;
       while (pos < kScanStep) {
+        const int2 v = exs[pos];
         ent[pos >> 6] = pos & 63;
         qent[pos >> 6] = qq;
-        qq += sm[pos];
-        pos = ex[pos];
+        qq += v.y;
+        pos = v.x;
       }
       s_exit = pos;
       s_q = qq;
+      s_end = UINT32_MAX;
     }
     __syncthreads();
     // (3)
     const int32_t e = ent[wv];
-    uint64_t on = e >= 0 ? 1ull << e : 0ull;
+    int32_t pos = e < 0 ? 0 : e;
+    uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
-      mark[t] = 0;
-      if ((on >> lane & 1) && jk[k] < 64) mark[wv * 64 + jk[k]] = 1;
-      __syncthreads();
-      on |= __ballot(mark[t] != 0);
-      __syncthreads();
+    for (int k = 5; k >= 0; k--) {
+      const int32_t c = __shfl(jk[k], pos);
+      const uint32_t a = __shfl(sk[k], pos);
+      if (c <= lane) {
+        pos = c;
+        acc += a;
+      }
     }
-    const bool el = (on >> lane) & 1;
-    uint32_t x = el ? own : 0u;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_up(x, d);
-      if (lane >= d) x += y;
-    }
-    const int64_t qs = (e >= 0 ? qent[wv] : 0) + (int64_t)(x - (el ? own : 0u));  // this element's first output byte
+    const bool el = e >= 0 && e <= lane && pos == lane;
+    const int64_t qs = (e >= 0 ? qent[wv] : 0) + (int64_t)acc;  // an element's first output byte
+    // the chain's end: its first element at or past the output's end, which
+    // must start at the input's end exactly at the output's end
     const uint64_t endm = __ballot(el && qs >= out_len);
-    const int fl = endm ? __builtin_ctzll(endm) : 0;
-    const int64_t fq = __shfl(qs, fl);
-    if (lane == 0) {
-      endp[wv] = endm ? wv * 64 + fl : -1;
-      endq[wv] = fq;
-    }
+    if (endm && lane == __builtin_ctzll(endm))
+      atomicMin(&s_end, (uint32_t)t << 1 | (uint32_t)((int64_t)ip + t != w.in_len || qs != out_len));
     if (el && qs < out_len) {
       const int64_t fs = qs & ~(int64_t)(kFrag - 1);
       if (qs == fs) fi[qs >> 16] = ip + t;
       if (c_len > kLenClamp || qs + c_len > fs + kFrag || (c_off != 0 && (c_off < 0 || qs - c_off < fs))) s_dep = 1;
     }
     __syncthreads();
-    // the chain's end: the first element at or past the output's end, which
-    // must start at the input's end exactly at the output's end
-    int32_t endpos = -1;
-    int64_t eq = 0;
-    for (int i = 0; i < kScanWaves; i++)
-      if (endp[i] >= 0) {
-        endpos = endp[i];
-        eq = endq[i];
-        break;
-      }
+    const uint32_t end = s_end;
     if (s_dep != 0) {
       dep = true;
       done = true;
-    } else if (endpos >= 0) {
+    } else if (end != UINT32_MAX) {
       done = true;
-      bad = (int64_t)ip + endpos != w.in_len || eq != out_len;
+      bad = (end & 1) != 0;
     } else {
       const int64_t nip = (int64_t)ip + s_exit;
       q = s_q;
