@@ -124,10 +124,11 @@ __device__ __forceinline__ void snappy_candidate(const uint32_t* win, int32_t i,
   if ((t & 3) != 0 && c_off == 0) c_off = -1;  // c_off == 0 marks a literal and nothing else
 }
 
-// An LDS window of a compressed body: input bytes [wbase, wbase + kInWin),
+// An LDS window of a compressed body: input bytes [wbase, wbase + WIN),
 // loaded as aligned dwords of the raw area (wbase may be up to 3 bytes
 // before 0). ensure() is called alike by every lane of the wave.
-struct InWindow {
+template <int WIN>
+struct InWindowT {
   uint32_t* win;
   const uint8_t* raw;
   int64_t c_off;
@@ -135,27 +136,28 @@ struct InWindow {
   int32_t wbase;
   template <int NT = 64>  // the workgroup's threads
   __device__ void ensure(int32_t at, int32_t need) {
-    if (at >= wbase && at + need <= wbase + kInWin) return;
+    if (at >= wbase && at + need <= wbase + WIN) return;
     // 16-byte loads, all issued before any is stored: one memory round trip
     const int64_t abs0 = (c_off + at) & ~(int64_t)15;
     wbase = (int32_t)(abs0 - c_off);
-    constexpr int kV = (kInWin / 16 + 1 + NT - 1) / NT;  // loads per thread
+    constexpr int kV = (WIN / 16 + 1 + NT - 1) / NT;  // loads per thread
     v4i32 t[kV];
 #pragma unroll
     for (int u = 0; u < kV; u++) {
       const int i = (int)threadIdx.x + NT * u;
       const int64_t a = abs0 + 16 * (int64_t)i;  // a load starting before the input's end stays in the padded area
-      t[u] = i < kInWin / 16 + 1 && a < c_off + in_len ? *reinterpret_cast<const v4i32*>(raw + a) : v4i32{0, 0, 0, 0};
+      t[u] = i < WIN / 16 + 1 && a < c_off + in_len ? *reinterpret_cast<const v4i32*>(raw + a) : v4i32{0, 0, 0, 0};
     }
 #pragma unroll
     for (int u = 0; u < kV; u++) {
       const int i = (int)threadIdx.x + NT * u;
-      if (i < kInWin / 16 + 1) reinterpret_cast<v4i32*>(win)[i] = t[u];
+      if (i < WIN / 16 + 1) reinterpret_cast<v4i32*>(win)[i] = t[u];
     }
     __syncthreads();
   }
   __device__ uint32_t byte(int32_t at) const { return in_byte(win, at - wbase); }
 };
+using InWindow = InWindowT<kInWin>;
 
 // The length preamble (a varint) of a Snappy body; its size in *ip, false
 // if malformed.
@@ -177,39 +179,6 @@ __device__ bool snappy_preamble(InWindow& w, uint32_t* ulen, int32_t* ip) {
 }
 
 constexpr int kFrag = 65536;  // the reference compressor's independent fragments
-
-// The elements that start among a batch's 64 candidates (lane i: the
-// element that would start at the batch's byte i, nxt = i + its input bytes),
-// found in parallel by pointer doubling: after step k every lane knows the
-// start 2^(k+1) elements after its own, and the set of starts reached from
-// lane 0 doubles; six steps reach every element that starts in the batch.
-// Returns them as a lane mask; *incl: the inclusive prefix sum of their
-// output lengths (0 for other lanes' own term).
-__device__ uint64_t snappy_elements(int32_t nxt, int32_t c_len, int32_t* mark, int64_t* incl) {
-  const int lane = threadIdx.x;
-  int32_t J = nxt;
-  uint64_t on = 1;
-#pragma unroll
-  for (int k = 0; k < 6; k++) {
-    mark[lane] = 0;
-    if ((on >> lane & 1) && J < 64) mark[J] = 1;
-    // (a barrier, though the workgroup is one wave, so that the compiler
-    // reads the marks other lanes wrote instead of this lane's own zero)
-    __syncthreads();
-    on |= __ballot(mark[lane] != 0);
-    __syncthreads();
-    const int32_t jj = __shfl(J, J < 64 ? J : lane);
-    J = J < 64 ? jj : J;
-  }
-  int64_t x = (on >> lane & 1) ? (int64_t)c_len : 0;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int64_t y = __shfl_up(x, d);
-    if (lane >= d) x += y;
-  }
-  *incl = x;
-  return on;
-}
 
 // Pass 1, one workgroup of kScanWaves waves per compressed body: follows the
 // element chain, records where each 64 KiB output fragment's first element
@@ -350,20 +319,29 @@ __global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* page
 }
 
 // Pass 2, one wave per 64 KiB fragment of a body whose fragments are
-// independent: its elements are executed in order into an LDS copy of the
-// fragment, which is then written out.
+// independent, inflated into an LDS copy of the fragment that is then written
+// out. A batch: lane i decodes the element that would start at input byte
+// ip + i; doubling and lifting (as in the scan, from lane 0) give the
+// elements and their output positions. Literal payload bytes among the
+// batch's 64 input bytes are stored by the lanes holding them (one store);
+// the payload of a literal running past them, by the whole wave; then the
+// copies, which read earlier output, in order. A wave's LDS accesses take
+// effect in program order, so between copies only the compiler is fenced.
+constexpr int kFragWin = 8192;  // (64 KiB fragment + this window: two workgroups per CU)
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
 __global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, const int32_t* cpages,
                                                        const int32_t* frag_cpage, uint8_t* raw, const int32_t* frag_in,
                                                        const int32_t* flags, PqHeader* hdr) {
   __shared__ uint32_t buf[kFrag / 4];
-  __shared__ __align__(16) uint32_t wbuf[kInWin / 4 + 4];
-  __shared__ int32_t mark[64];
+  __shared__ __align__(16) uint32_t wbuf[kFragWin / 4 + 4];
   uint8_t* fb = reinterpret_cast<uint8_t*>(buf);
   const int32_t ci = frag_cpage[blockIdx.x];
   if (flags[ci] != 0) return;
   const PqPage pg = pages[cpages[ci]];
   const int32_t f = (int32_t)(blockIdx.x - pg.frag0);
-  InWindow w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
+  InWindowT<kFragWin> w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
   const int32_t out_len = (int32_t)pg.u_len;
   const int32_t fs = f * kFrag, fe = min(fs + kFrag, out_len);
   const int lane = threadIdx.x;
@@ -373,55 +351,87 @@ __global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, cons
   while (!bad && q < fe) {
     w.ensure(ip, 64 + 8);
     int32_t c_adv, c_len, c_off;
-    snappy_candidate(w.win, ip + lane - w.wbase, c_adv, c_len, c_off);
-    const int32_t nxt = lane + c_adv;
-    int64_t incl;
-    const uint64_t on = snappy_elements(nxt, c_len, mark, &incl);
-    const bool el = (on >> lane) & 1;
-    const int64_t qs = (int64_t)q + incl - (el ? c_len : 0);  // this element's first output byte
-    const uint64_t live = __ballot(el && qs < fe);             // the fragment's elements in the batch
+    const int32_t wi = ip + lane - w.wbase;
+    snappy_candidate(w.win, wi, c_adv, c_len, c_off);
+    const uint32_t mine = in_byte(w.win, wi);  // input byte ip + lane
+    int32_t jk[6];
+    uint32_t sk[6];
+    int32_t J = lane + c_adv;
+    uint32_t S = (uint32_t)min(c_len, kLenClamp);
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      jk[k] = J;
+      sk[k] = S;
+      const int src = J < 64 ? J : lane;
+      const int32_t Jn = __shfl(J, src);
+      const uint32_t Sn = __shfl(S, src);
+      if (J < 64) {
+        J = Jn;
+        S += Sn;
+      }
+    }
+    int32_t pos = 0;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 5; k >= 0; k--) {
+      const int32_t c = __shfl(jk[k], pos);
+      const uint32_t a = __shfl(sk[k], pos);
+      if (c <= lane) {
+        pos = c;
+        acc += a;
+      }
+    }
+    const int64_t qs = (int64_t)q + acc;  // an element's first output byte
+    const uint64_t live = __ballot(pos == lane && qs < fe);  // the fragment's elements in the batch (lane 0: q < fe)
     const bool me = (live >> lane) & 1;
     const int32_t at = ip + lane;
-    // the scan checked the chain; these checks keep every access in bounds regardless
+    // the scan checked the chain; these checks keep every access in bounds
+    // regardless (a length past the fragment also catches a clamped one)
     const bool badl = me && (at >= w.in_len || c_len > fe - qs || c_adv > w.in_len - at ||
                              (c_off != 0 && (c_off <= 0 || c_off > qs - fs)));
     if (__ballot(badl)) {
       bad = true;
       break;
     }
-    // short literals: each lane writes its own; they read nothing of the output
-    const bool short_lit = me && c_off == 0 && c_len <= 64;
-    if (short_lit) {
-      const int32_t src = at + c_adv - c_len, lq = (int32_t)(qs - fs);
-      const bool in_win = src >= w.wbase && src + c_len <= w.wbase + kInWin;
-      for (int32_t j = 0; j < c_len; j++) fb[lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
+    const int32_t lq = (int32_t)(qs - fs);  // (live lanes) its offset in the fragment
+    // literal payload bytes among the batch's input bytes: lane j's byte
+    // belongs to the last element starting at or before j
+    const int eo = 63 - __builtin_clzll(live & ((2ull << lane) - 1));
+    const int32_t e_len = __shfl(c_len, eo), e_adv = __shfl(c_adv, eo), e_off = __shfl(c_off, eo);
+    const int32_t e_lq = __shfl(lq, eo);
+    const int32_t rel = lane - (eo + e_adv - e_len);  // its place in that element's payload
+    if (e_off == 0 && rel >= 0 && rel < e_len) fb[e_lq + rel] = (uint8_t)mine;
+    // the batch's last element: a literal may run past the batch's input bytes
+    const int L = 63 - __builtin_clzll(live);
+    const int32_t l_len = __builtin_amdgcn_readlane(c_len, L), l_adv = __builtin_amdgcn_readlane(c_adv, L);
+    const int32_t l_off = __builtin_amdgcn_readlane(c_off, L), l_lq = __builtin_amdgcn_readlane(lq, L);
+    if (l_off == 0 && L + l_adv > 64) {
+      const int32_t p0 = L + l_adv - l_len;  // payload start, batch-relative
+      const int32_t src = ip + p0;
+      const bool in_win = src >= w.wbase && src + l_len <= w.wbase + kFragWin;
+      for (int32_t j = max(0, 64 - p0) + lane; j < l_len; j += 64)
+        fb[l_lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
     }
-    __syncthreads();  // (one wave: for the compiler, the bytes other lanes wrote)
-    // copies (which read earlier output) and long literals, in order, each by the whole wave
-    uint64_t rest = live & ~__ballot(short_lit);
+    compiler_fence();
+    // copies, in order
+    uint64_t rest = live & __ballot(c_off != 0);
     while (rest) {
       const int l = __builtin_ctzll(rest);
       rest &= rest - 1;
       const int32_t len = __builtin_amdgcn_readlane(c_len, l);
       const int32_t off = __builtin_amdgcn_readlane(c_off, l);
-      const int32_t lq = __builtin_amdgcn_readlane((int32_t)(qs - fs), l);
-      if (off == 0) {
-        const int32_t src = ip + l + __builtin_amdgcn_readlane(c_adv, l) - len;
-        const bool in_win = src >= w.wbase && src + len <= w.wbase + kInWin;
-        for (int32_t j = lane; j < len; j += 64) fb[lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
-      } else if (lane < len) {
-        fb[lq + lane] = fb[lq - off + (off >= len ? lane : lane % off)];
-      }
-      __syncthreads();
+      const int32_t dq = __builtin_amdgcn_readlane(lq, l);
+      if (lane < len) fb[dq + lane] = fb[dq - off + (off >= len ? lane : lane % off)];
+      compiler_fence();
     }
-    const int last = 63 - __builtin_clzll(live);
-    q = (int32_t)((int64_t)q + __shfl(incl, last));
-    ip += __shfl(nxt, last);
+    q = fs + l_lq + l_len;
+    ip += L + l_adv;
   }
   if (bad) {
     if (lane == 0) pq_error(hdr, TQ_EINVAL);
     return;
   }
+  __syncthreads();
   uint32_t* dst = reinterpret_cast<uint32_t*>(raw + pg.u_off + fs);  // 256-aligned, padded past the body
   for (int i = lane; i < ((fe - fs + 3) >> 2); i += 64) dst[i] = buf[i];
 }
