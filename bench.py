@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0
 PROBE_COUNTERS = {
     "sources": ["paper_2508_05029_amd/csrc/join_ops.hip", "paper_2508_05029_amd/csrc/table.h",
                 "paper_2508_05029_amd/csrc/groupby.h", "paper_2508_05029_amd/csrc/common.h"],
-    "sha1": "4edc09dcced0011b0885e3dd8515b4ae4a86d035",
-    "fetch_kib": 115494.4, "fetch_scale": 2.000,
-    "write_kib": 104.0, "write_scale": 0.995,
+    "sha1": "ae46ba7129ced972be58d896c4775a64da8eabcd",
+    "fetch_kib": 115002.3, "fetch_scale": 2.000,
+    "write_kib": 104.0, "write_scale": 0.9955,
 }
 
 
@@ -289,7 +289,7 @@ def bench_join_agg(args):
         "kernel_ms": {k: round(v, 5) for k, v in kern_ms.items()},
         "roofline": {"bound": "hbm", "achieved": round(probe_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(probe_gbs / HBM_PEAK_GBS, 4), "traffic": probe_traffic(),
-                     "kernel": "k_probe_pipe (join probe + fused group-by)", "bytes_per_launch": probe_bytes},
+                     "kernel": "k_probe_compact (join probe + fused group-by)", "bytes_per_launch": probe_bytes},
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "parity_vs_oracle": parity,

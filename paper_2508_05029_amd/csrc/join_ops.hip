@@ -995,6 +995,259 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   agg.flush(T);
 }
 
+// The fast aggregating probe behind the Bloom filter with the rows that pass
+// the filter compacted across the wave before the table stages. Most probe
+// rows have no partner and the filter drops most of those; the tag, slot and
+// aggregation stages then run on 64-row tiles of the survivors instead of on
+// every row slot. Stage 1, per tile of 2 rows per lane (columns requested
+// two tiles ahead): hash and filter test; the survivors move to the wave's
+// compaction buffer (three 64-row register tiles, B0, B1, B2) with one
+// ds_permute per 32-bit word: survivors to the buffer's next free lanes, the
+// rest to the remaining lanes, so the lane map is a permutation. Stage 2, once
+// per two tiles (and before a tile when the buffer might not take its rows):
+// the buffer's first tile (full, or what there is) goes through a three-deep
+// pipeline: its tag loads are issued; the tile before it turns its tags into
+// slot loads; the one before that is finished (aggregated, or queued for the
+// chain walk).
+constexpr int kCmpSets = 2;  // column tiles in flight per wave (even)
+constexpr int kCmpQLimit = kPipeQ - kWave;  // a finish queues at most 64 rows
+
+// A compacted row: its key, its sum's value (evaluated before the row is
+// compacted: fewer words to move and to hold), its offset from the wave's
+// first row.
+struct CRow {
+  int64_t k, e;
+  uint32_t r;
+};
+__device__ __forceinline__ CRow crow_select(bool take, const CRow& a, const CRow& b) {
+  return CRow{take ? a.k : b.k, take ? a.e : b.e, take ? a.r : b.r};
+}
+
+template <int NC, int NE>
+__global__ __launch_bounds__(kBloomPipeBlock, 1) void k_probe_compact(const TableHeader* h, const int64_t* pkeys,
+                                                                      int64_t n, RowPlan P, AggTarget T, UnitPlan U,
+                                                                      int agg_lds) {
+  static_assert(NC <= 2 && NE == 1, "fast plan with one sum");
+  constexpr int R = kPipeRows;
+  __shared__ uint32_t bloom[kBloomWordsMax];
+  extern __shared__ __align__(16) char smem[];
+  if (h->magic != kTableMagic || h->err) return;  // a failed build inserted nothing: no row can match
+  if (!state_matches(T)) return;
+  const int log2w = h->bloom_log2w;
+  const int nbw = log2w ? 1 << log2w : 0;
+  {
+    constexpr int kU = kBloomWordsMax / 4 / kBloomPipeBlock;
+    const v4i32* gb = reinterpret_cast<const v4i32*>(scratch_bloom(const_cast<TableHeader*>(h), h->cap_max));
+    v4i32 t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int i = (int)threadIdx.x + u * kBloomPipeBlock;
+      if (i < nbw / 4) t[u] = gb[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int i = (int)threadIdx.x + u * kBloomPipeBlock;
+      if (i < nbw / 4) reinterpret_cast<v4i32*>(bloom)[i] = t[u];
+    }
+  }
+  LdsAgg<kDense> agg;
+  agg.defer = true;
+  agg.init(T, smem);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  uint32_t* qrow = reinterpret_cast<uint32_t*>(smem + agg_lds) + (int64_t)wave * kPipeQ;  // queued rows
+  Probe pr;
+  pr.setup(h);
+  const int64_t n_main = n & ~(int64_t)(R - 1);  // rows in full tiles
+  const v2i64* kcol = reinterpret_cast<const v2i64*>(pkeys);
+  const v2i64* ccol[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) ccol[c] = c < P.ncol ? static_cast<const v2i64*>(P.col[c].p) : kcol;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * R;
+  const int64_t wbase = ((int64_t)blockIdx.x * blockDim.x + wave * kWave) * R;  // the wave's first row
+  int qn = 0;
+  const int ne = P.ne;
+  const uint64_t udomain = (uint64_t)T.domain;
+  const uint32_t gstride = (uint32_t)T.stride;
+  bool bad = false;
+
+  auto drain_all = [&] {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int q0 = 0; q0 < qn; q0 += kWave) {
+      bool ok1[1] = {q0 + lane < qn};
+      int64_t k1[1] = {0}, e1[NE];
+#pragma unroll
+      for (int j = 0; j < NE; j++) e1[j] = 0;
+      if (ok1[0]) {
+        const int64_t row = wbase + qrow[q0 + lane];
+        int64_t v1[NC][1];
+#pragma unroll
+        for (int c = 0; c < NC; c++) v1[c][0] = c < P.ncol ? reinterpret_cast<const int64_t*>(ccol[c])[row] : 0;
+        k1[0] = pkeys[row];
+#pragma unroll
+        for (int j = 0; j < NE; j++) e1[j] = j < P.ne ? eval_expr<NC>(P.expr[j], v1, 0) : 0;
+      }
+      pr.walk(ok1, k1, [&](const bool (&hit)[1], const int64_t (&pay)[1]) {
+        if (hit[0]) agg.add(T, pay[0], e1, P.ne);
+      });
+    }
+    qn = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
+
+  // the compaction buffer: B0, B1, B2, `fill` rows (the same in every lane)
+  CRow B0{0, 0, 0u}, B1 = B0, B2 = B0;
+  int fill = 0;
+  // stage 2: Y has its tag loads in flight, X its slot loads
+  CRow Y = B0, X = B0;
+  uint32_t ytg = 0, yb = 0, xsm = 0;
+  bool yv = false, xv = false, xse = true;
+  v4i32 ytw = v4i32{0, 0, 0, 0};
+  v2i64 xkv = v2i64{0, 0};
+
+  // One step of stage 2, with Z (valid lanes: zv) entering it.
+  auto advance = [&](bool zv, const CRow Z) {
+    {  // finish X
+      const bool hit = xsm != 0u && xkv.x == X.k;
+      const uint32_t rest = xsm & (xsm - 1u);
+      const bool done = !xv || (xsm == 0u && xse) || (hit && pr.unique) || (rest == 0u && xse);
+      const bool addit = done && hit;
+      const uint64_t key = (uint64_t)xkv.y;
+      const bool in = key < udomain;
+      bad = bad || (addit && !in);  // latched after the loop
+      if (addit && in) {  // key < domain <= 4096 (dense partials): a 24-bit multiply
+        unsigned long long* d = reinterpret_cast<unsigned long long*>(agg.vals) + __umul24((uint32_t)key, gstride);
+        atomicAdd(d, 1ull);
+        if (ne > 0) atomicAdd(d + 1, (unsigned long long)X.e);
+      }
+      const bool slow = !done;
+      const uint64_t bal = __ballot(slow);
+      if (bal) {
+        if (slow) {
+          const int rank =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          qrow[qn + rank] = X.r;
+        }
+        qn += __popcll(bal);
+      }
+    }
+    {  // Y -> X: tags to slot loads
+      X = Y;
+      xv = yv;
+      xsm = yv ? tag_match(ytw, ytg) : 0u;
+      xse = yv ? has_empty(ytw) : true;
+      xkv = pr.slots[xsm ? (int64_t)yb * kBucket + __builtin_ctz(xsm) : 0];
+    }
+    asm volatile("" ::: "memory");
+    {  // Z -> Y: tag loads
+      const uint64_t hh = mulhash(Z.k);
+      Y = Z;
+      yv = zv;
+      yb = (uint32_t)bucket_of(hh, pr.skip, pr.log2b);
+      ytg = hash_tag(hh);
+      ytw = pr.groups[zv ? yb : 0u];
+    }
+    asm volatile("" ::: "memory");
+    if (qn > kCmpQLimit) drain_all();
+  };
+  // B0 (its first min(fill, 64) rows) into stage 2; the others move up
+  auto emit = [&] {
+    const int cnt = fill < kWave ? fill : kWave;
+    advance(lane < cnt, B0);
+    B0 = B1;
+    B1 = B2;
+    fill = fill > kWave ? fill - kWave : 0;
+  };
+  // appends the lanes' rows with `live` set to the buffer (fill <= 128)
+  auto push = [&](bool live, const CRow& row) {
+    const uint64_t m = __ballot(live);
+    if (m == 0) return;
+    const int cnt = __popcll(m);
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const int addr = ((fill + (live ? rank : cnt + lane - rank)) & (kWave - 1)) * 4;
+    auto perm32 = [&](uint32_t x) { return (uint32_t)__builtin_amdgcn_ds_permute(addr, (int)x); };
+    auto perm = [&](int64_t x) {
+      const uint32_t lo = perm32((uint32_t)x), hi = perm32((uint32_t)((uint64_t)x >> 32));
+      return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
+    const CRow rv{perm(row.k), perm(row.e), perm32(row.r)};
+    // the tile holding position `fill` takes the new rows from lane fill % 64
+    // on; rows past its end land in the lanes below and start the next tile
+    // (selects, not branches: stores under a branch would be merged into
+    // indexed ones, and the buffer would live in scratch memory)
+    const bool take = lane >= (fill & (kWave - 1));
+    const int t = fill >> 6;  // 0, 1, or 2 (fill == 128)
+    B2 = crow_select(t == 1 || (t == 2 && take), rv, B2);
+    B1 = crow_select(t == 0 || (t == 1 && take), rv, B1);
+    B0 = crow_select(t == 0 && take, rv, B0);
+    fill += cnt;
+  };
+  // stage 1 of one tile (rows rt, rt + 1 of each lane)
+  auto stage1 = [&](const v2i64 (&cv)[NC], const v2i64& ck, int64_t rt) {
+    const int64_t kk[R] = {ck.x, ck.y};
+    int64_t v[NC][R];
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      v[c][0] = cv[c].x;
+      v[c][1] = cv[c].y;
+    }
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+      const uint64_t hh = mulhash(kk[i]);
+      bool live = rt < n_main && pr.selected(hh);
+      if (nbw) {  // a key the filter rejects is not in the build
+        const uint32_t m = bloom_bits(hh);
+        live = live && (bloom[bloom_word(hh, pr.skip, log2w)] & m) == m;
+      }
+      const CRow row{kk[i], ne > 0 ? eval_unit<NC>(U.s[0], v, i) : 0, (uint32_t)(rt + i - wbase)};
+      push(live, row);
+    }
+  };
+  auto load_cols = [&](v2i64 (&cv)[NC], v2i64& ck, int64_t rt) {  // a tile past the last reads tile 0
+    const int64_t q = (rt < n_main ? rt : 0) / R;
+    ck = ntload(kcol + q);
+#pragma unroll
+    for (int c = 0; c < NC; c++) cv[c] = ntload(ccol[c] + q);
+  };
+
+  v2i64 cv[kCmpSets][NC], ck[kCmpSets];
+  int64_t r = wbase + lane * R;
+#pragma unroll
+  for (int s = 0; s < kCmpSets; s++) load_cols(cv[s], ck[s], r + s * stride);
+  asm volatile("" ::: "memory");
+  __syncthreads();  // the filter, the partials and the queues are ready
+  for (int64_t t0 = wbase; t0 < n_main; t0 += kCmpSets * stride, r += kCmpSets * stride) {
+#pragma unroll
+    for (int s = 0; s < kCmpSets; s++) {
+      while (fill > kWave) emit();  // (rare) so that the buffer takes this tile's 128 rows
+      stage1(cv[s], ck[s], r + s * stride);
+      asm volatile("" ::: "memory");
+      load_cols(cv[s], ck[s], r + (s + kCmpSets) * stride);
+      asm volatile("" ::: "memory");
+      if (s & 1) emit();
+    }
+  }
+  while (fill > 0) emit();
+  advance(false, CRow{0, 0, 0u});
+  advance(false, CRow{0, 0, 0u});
+  if (qn > 0) drain_all();
+  if (n_main < n && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the row of the partial last tile
+    const int64_t rt = n_main;
+    int64_t v[NC][1];
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c][0] = c < P.ncol ? static_cast<const int64_t*>(P.col[c].p)[rt] : 0;
+    bool ok1[1] = {eval_preds<NC>(P, v, 0)};
+    int64_t k1[1] = {pkeys[rt]}, e1[NE];
+#pragma unroll
+    for (int j = 0; j < NE; j++) e1[j] = j < P.ne ? eval_expr<NC>(P.expr[j], v, 0) : 0;
+    pr.walk(ok1, k1, [&](const bool (&hit)[1], const int64_t (&pay)[1]) {
+      if (hit[0]) agg.add(T, pay[0], e1, P.ne);
+    });
+  }
+  agg.bad = agg.bad || bad;
+  agg.flush(T);
+}
+
 // Match count of each block's contiguous row range (pairs mode, pass 1).
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_probe_count(const TableHeader* h, const int64_t* pkeys, int64_t n,
@@ -1277,8 +1530,8 @@ tq_status tq_join_probe(const void* d_table, const int64_t* d_probe_keys, int64_
           if constexpr (M == kDense && NC <= 2 && NE == 1) {  // (two sums would spill registers to memory)
             if (fast) {
               if (bloom)
-                hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, true, true>), grid, block, agg_lds + q, stream, h,
-                                   d_probe_keys + c0, nc, Pc, T, U, agg_lds);
+                hipLaunchKernelGGL((k_probe_compact<NC, NE>), grid, block, agg_lds + q, stream, h, d_probe_keys + c0,
+                                   nc, Pc, T, U, agg_lds);
               else
                 hipLaunchKernelGGL((k_probe_pipe<M, NC, NE, false, true>), grid, block, agg_lds + q, stream, h,
                                    d_probe_keys + c0, nc, Pc, T, U, agg_lds);
