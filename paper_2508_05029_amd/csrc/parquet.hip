@@ -66,17 +66,19 @@ __global__ void k_pq_zero(uint32_t* words, int64_t n) {
 
 // ------------------------------------------------------------------ Snappy
 //
-// One wave per compressed page body. The format (Snappy's raw block: the
-// uncompressed length as a varint, then elements: a literal of n bytes that
-// follow its tag, or a copy of n bytes from `offset` bytes back in the
-// output, which may overlap what it writes) is sequential. In a batch, lane i
-// decodes the element that would start at input byte ip + i; following the
-// chain of real elements from lane 0 then takes register reads only, and each
-// element's bytes are moved by the lanes in parallel. The output goes through
-// a 64 KiB LDS ring holding the last 64 KiB written (every copy offset below
-// 65536 reads from it) and is written to the device buffer 8 KiB at a time.
-// A wave's LDS accesses take effect in program order, so a lane reads the
-// bytes other lanes wrote for earlier elements without a barrier.
+// The format (Snappy's raw block: the uncompressed length as a varint, then
+// elements: a literal of n bytes that follow its tag, or a copy of n bytes
+// from `offset` bytes back in the output, which may overlap what it writes)
+// is sequential: an element's start is known only from the one before. Three
+// passes: k_pq_snappy_scan finds the chain of every body (a workgroup per
+// body; in each step each thread decodes the element that would start at its
+// byte, and the real chain is picked out by pointer doubling) and where each
+// 64 KiB output fragment's first element starts; k_pq_snappy_frag inflates
+// the fragments independently, one wave each in LDS, when no element crosses
+// a fragment or copies from before its own (what the reference compressor
+// writes, compressing 64 KiB at a time); k_pq_snappy inflates any other body
+// with one wave in order, through a 64 KiB LDS ring holding the last 64 KiB
+// written, 8 KiB at a time to the device buffer.
 constexpr int kRing = 65536;
 constexpr int kFlushBytes = 8192;
 constexpr int kInWin = 16384;
