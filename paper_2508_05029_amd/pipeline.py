@@ -585,9 +585,12 @@ class ParquetScan:
     """Scan of a Parquet file's columns into device tensors: tq_parquet_preload
     (byte ranges merged and read into pool pages by a host thread), then
     tq_parquet_decode (pages copied to the device and decoded there). The
-    work buffer grows to the largest preload seen; outputs are new tensors."""
+    work buffer grows to the largest preload seen; outputs are new tensors.
+    read_pipelined decodes successive row groups on `pipe_streams` streams in
+    turn (the caller's and its own), each with its own work buffer, so that
+    one row group's kernels run beside the next one's copies and kernels."""
 
-    def __init__(self, path: str, columns, pool, merge_gap: int = 1 << 20, device="cuda"):
+    def __init__(self, path: str, columns, pool, merge_gap: int = 1 << 20, device="cuda", pipe_streams: int = 4):
         self.file = tq.ParquetFile(path)
         meta = self.file.columns()
         names = [m[0] for m in meta]
@@ -598,6 +601,11 @@ class ParquetScan:
         self.merge_gap = merge_gap
         self.device = device
         self.work = None
+        if pipe_streams < 1:
+            raise ValueError("pipe_streams must be at least 1")
+        self.pipe_streams = [torch.cuda.Stream(device=device) for _ in range(pipe_streams - 1)]
+        self.pipe_works = [None] * (pipe_streams - 1)  # each allocated on its stream
+        self.last_works = []  # the work buffers of the last read, for check()
 
     def preload(self, rg0: int = 0, rg1=None):
         rg1 = self.file.num_row_groups if rg1 is None else rg1
@@ -616,6 +624,7 @@ class ParquetScan:
             data[name], valid[name] = d[:n], v
             outs.append((d, v))
         pl.decode(self.work, outs, stream)
+        self.last_works = [self.work]
         return data, valid
 
     def read_pipelined(self, stream=None):
@@ -633,22 +642,46 @@ class ParquetScan:
                            if nullable else None)
         if nrg == 0:
             return {k: v[:0] for k, v in data.items()}, valid
+        main = torch.cuda.current_stream(self.device) if stream is None else stream
+        side = self.pipe_streams[:max(0, min(len(self.pipe_streams), nrg - 1))]
+        for s_ in side:
+            s_.wait_stream(main)  # the outputs were allocated on the caller's stream
         nxt = self.preload(0, 1)
         row = 0
+        self.last_works = []
         for g in range(nrg):
             cur = nxt
             nxt = self.preload(g + 1, g + 2) if g + 1 < nrg else None
             need = cur.work_bytes()
-            if self.work is None or self.work.numel() < need:
-                self.work = torch.empty(need, dtype=torch.uint8, device=self.device)
+            k = g % (len(side) + 1)
+            st = main if k == 0 else side[k - 1]
+            if k == 0:
+                if self.work is None or self.work.numel() < need:
+                    self.work = torch.empty(need, dtype=torch.uint8, device=self.device)
+                work = self.work
+            else:
+                if self.pipe_works[k - 1] is None or self.pipe_works[k - 1].numel() < need:
+                    with torch.cuda.stream(st):  # freed and reused in this stream's order
+                        self.pipe_works[k - 1] = None
+                        self.pipe_works[k - 1] = torch.empty(need, dtype=torch.uint8, device=self.device)
+                work = self.pipe_works[k - 1]
             rows = cur.rows
             if any(v is not None for v in valid.values()) and row % 32:
                 raise ValueError("a row group of a nullable column starts off a 32-row boundary")
             outs = [(data[name][row:row + rows], None if valid[name] is None else valid[name][row // 8:])
                     for name in self.names]
-            cur.decode(self.work, outs, stream)
+            cur.decode(work, outs, st)
+            if all(w is not work for w in self.last_works):
+                self.last_works.append(work)
             cur.free()
             row += rows
+        for s_ in side:
+            main.wait_stream(s_)
+        for name in self.names:  # used on the side streams: not reused before their work is done
+            for s_ in side:
+                data[name].record_stream(s_)
+                if valid[name] is not None:
+                    valid[name].record_stream(s_)
         return {k: v[:n] for k, v in data.items()}, valid
 
     def read(self, rg0: int = 0, rg1=None, stream=None):
@@ -659,7 +692,9 @@ class ParquetScan:
             pl.free()
 
     def check(self, stream=None):
-        tq.check(self.work, stream)
+        """Raises the error a kernel of the last decode or read latched."""
+        for w in self.last_works:
+            tq.check(w, stream)
 
 
 class StringGroupBy:

@@ -172,16 +172,18 @@ def test_snappy_repeats_and_runs(tmp_path):
     check(cols, [0, 1], res, 0, rows)
 
 
-@pytest.mark.parametrize("codec", ["NONE", "snappy"])
-def test_pipelined_row_groups_equal_the_whole_read(tmp_path, codec):
+@pytest.mark.parametrize("codec,streams", [("NONE", 4), ("snappy", 4), ("snappy", 1), ("snappy", 2)])
+def test_pipelined_row_groups_equal_the_whole_read(tmp_path, codec, streams):
     """read_pipelined (each row group decoded into its slice of one set of
-    columns while the next one's bytes are read) equals what pyarrow wrote."""
+    columns while the next one's bytes are read, successive row groups on
+    `streams` streams in turn) equals what pyarrow wrote, also when read twice."""
     cols = pqfiles.columns(100_000, 28)
     path = pqfiles.write(str(tmp_path / "pipe.parquet"), cols, row_group_size=20_000, data_page_size=32_768,
                          compression=codec)
     pool = tq.PagePool(1 << 20, 64)
     names = [c[0] for c in cols]
-    scan = pipeline.ParquetScan(path, names, pool)
+    scan = pipeline.ParquetScan(path, names, pool, pipe_streams=streams)
+    scan.read_pipelined()
     data, valid = scan.read_pipelined()
     scan.check()
     for c, name in enumerate(names):
