@@ -189,60 +189,72 @@ constexpr int kFrag = 65536;  // the reference compressor's independent fragment
 // with every access checked). flags: 0 fragments independent, 1 inflate in
 // order, 2 malformed.
 //
-// A step covers kScanStep input bytes, 64 per wave, each thread decoding the
+// The body is taken in blocks of kScanBlk input bytes, 64 per sub-batch, one
+// sub-batch per wave of waves 1 .. kScanWaves - 1, each thread decoding the
 // element that would start at its byte. (1) Each wave builds, by pointer
 // doubling, the start 2^k elements on from each lane and the output bytes of
-// those 2^k elements (k < 6), up to where the chain leaves the wave's 64
-// bytes. (2) One thread composes the waves: from the step's first byte it hops
-// wave by wave (at most kScanWaves hops), giving each wave the lane its
-// elements start at and the output position there. (3) Each lane, from its
-// wave's first element, jumps 2^k elements (k = 5 .. 0) while that lands at
-// or before it: it is an element if it lands on itself, and the jumps' output
-// bytes give its output position.
+// those 2^k elements (k < 6), up to where the chain leaves the sub-batch.
+// (2) Wave 0 walks the chain through the block a sub-batch per hop (register
+// reads of the sub-batches' exits), giving each sub-batch the lane its
+// elements start at and the output position there. (3) Each lane, from its sub-batch's first
+// element, jumps 2^k elements (k = 5 .. 0) while that lands at or before it:
+// it is an element if it lands on itself, and the jumps' output bytes give
+// its output position. The three run as a pipeline, one barrier per block:
+// while wave 0 walks block i, the other waves build block i + 1's tables
+// and mark block i - 1's elements. A block starts where the one before it
+// ends, or where the chain is when a literal has skipped a whole block.
 constexpr int kScanWaves = 16;
-constexpr int kScanStep = 64 * kScanWaves;
+constexpr int kScanSub = kScanWaves - 1;   // sub-batches per block
+constexpr int kScanBlk = 64 * kScanSub;    // input bytes per block
 // element lengths are summed in 32 bits clamped to this; a body with a longer
 // element is flagged for the in-order pass
 constexpr int32_t kLenClamp = 1 << 24;
 
-__global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* pages, const int32_t* cpages,
-                                                              const uint8_t* raw, int32_t* frag_in, int32_t* flags,
-                                                              PqHeader* hdr) {
+// A lane's doubling tables for one block (phase 1, kept for phase 3).
+struct ScanTab {
+  int32_t jk[6];   // the start 2^k elements on, sub-batch-relative (>= 64: past it)
+  uint32_t sk[6];  // the output bytes of those 2^k elements
+  int32_t len, off;
+};
+
+__global__ __launch_bounds__(64 * kScanWaves) void k_pq_snappy_scan(const PqPage* pages, const int32_t* cpages,
+                                                                    const uint8_t* raw, int32_t* frag_in,
+                                                                    int32_t* flags, PqHeader* hdr) {
   __shared__ __align__(16) uint32_t wbuf[kInWin / 4 + 4];
-  __shared__ int2 exs[kScanStep];      // where the chain from each byte leaves its wave (step-relative),
-                                       // and the output bytes of its elements up to there
-  __shared__ int32_t ent[kScanWaves];  // each wave's first element (lane; -1: none)
-  __shared__ int64_t qent[kScanWaves];  // and its output position
-  __shared__ int32_t s_exit;           // where the chain leaves the step (step-relative)
-  __shared__ int64_t s_q;              // and the output position there
-  __shared__ int32_t s_dep;
-  __shared__ uint32_t s_end;           // the first element at or past the output's end: position << 1 | malformed
+  __shared__ int2 exs[2][kScanBlk];      // where the chain from each byte leaves its sub-batch
+                                         // (block-relative), and the output bytes up to there
+  __shared__ int32_t ent[2][kScanSub];   // each sub-batch's first element (lane; -1: none)
+  __shared__ int64_t qent[2][kScanSub];  // and its output position
+  __shared__ uint32_t s_end[2];          // the first element at or past the output's end:
+                                         // position << 1 | malformed (per iteration parity)
+  __shared__ int64_t s_pos;              // the walker's place in the chain after its block
+  __shared__ int32_t s_dep, s_bad;
   const PqPage pg = pages[cpages[blockIdx.x]];
   InWindow w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
   const int64_t out_len = pg.u_len;
   int32_t* fi = frag_in + pg.frag0;
-  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
-  if (t == 0) s_dep = 0;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63, sb = wv - 1;
   uint32_t ulen;
-  int32_t ip;
-  bool bad = !snappy_preamble<kScanStep>(w, &ulen, &ip) || ulen != (uint32_t)out_len;
-  bool dep = false, done = bad;
-  int64_t q = 0;
-  __syncthreads();
-  // every thread holds the same ip, q, done: the loop is uniform
-  while (!done) {
-    w.ensure<kScanStep>(ip, kScanStep + 8);
+  int32_t ip0;
+  bool bad = !snappy_preamble<64 * kScanWaves>(w, &ulen, &ip0) || ulen != (uint32_t)out_len;
+  if (t == 0) {
+    s_dep = 0;
+    s_bad = 0;
+    s_end[0] = s_end[1] = UINT32_MAX;
+    s_pos = ip0;
+  }
+  // (1) for the block at bs, into exs[par] and T (waves 1 ..)
+  auto tables = [&](int64_t bs, int par, ScanTab& T) {
     int32_t c_adv, c_len, c_off;
-    snappy_candidate(w.win, ip + t - w.wbase, c_adv, c_len, c_off);
-    // (1) jk[k]: the start 2^k elements on (>= 64: past the wave); sk[k]: their output bytes
-    int32_t jk[6];
-    uint32_t sk[6];
+    snappy_candidate(w.win, (int32_t)(bs - w.wbase) + 64 * sb + lane, c_adv, c_len, c_off);
+    T.len = c_len;
+    T.off = c_off;
     int32_t J = lane + c_adv;
     uint32_t S = (uint32_t)min(c_len, kLenClamp);
 #pragma unroll
     for (int k = 0; k < 6; k++) {
-      jk[k] = J;
-      sk[k] = S;
+      T.jk[k] = J;
+      T.sk[k] = S;
       const int src = J < 64 ? J : lane;
       const int32_t Jn = __shfl(J, src);
       const uint32_t Sn = __shfl(S, src);
@@ -251,68 +263,121 @@ __global__ __launch_bounds__(kScanStep) void k_pq_snappy_scan(const PqPage* page
         S += Sn;
       }
     }
-    exs[t] = make_int2(wv * 64 + J, (int32_t)S);  // S <= 64 * kLenClamp
-    __syncthreads();
-    // (2)
-    if (t == 0) {
-      for (int i = 0; i < kScanWaves; i++) ent[i] = -1;
-      int32_t pos = 0;
-      int64_t qq = q;
-      while (pos < kScanStep) {
-        const int2 v = exs[pos];
-        ent[pos >> 6] = pos & 63;
-        qent[pos >> 6] = qq;
-        qq += v.y;
-        pos = v.x;
-      }
-      s_exit = pos;
-      s_q = qq;
-      s_end = UINT32_MAX;
-    }
-    __syncthreads();
-    // (3)
-    const int32_t e = ent[wv];
+    exs[par][64 * sb + lane] = make_int2(64 * sb + J, (int32_t)S);  // S <= 64 * kLenClamp
+  };
+  // (3) for the block at bs (walked into ent[par]), iteration parity ipar
+  auto mark = [&](int64_t bs, int par, int ipar, const ScanTab& T) {
+    const int32_t e = ent[par][sb];
     int32_t pos = e < 0 ? 0 : e;
     uint32_t acc = 0;
 #pragma unroll
     for (int k = 5; k >= 0; k--) {
-      const int32_t c = __shfl(jk[k], pos);
-      const uint32_t a = __shfl(sk[k], pos);
+      const int32_t c = __shfl(T.jk[k], pos);
+      const uint32_t a = __shfl(T.sk[k], pos);
       if (c <= lane) {
         pos = c;
         acc += a;
       }
     }
     const bool el = e >= 0 && e <= lane && pos == lane;
-    const int64_t qs = (e >= 0 ? qent[wv] : 0) + (int64_t)acc;  // an element's first output byte
+    const int64_t qs = (e >= 0 ? qent[par][sb] : 0) + (int64_t)acc;  // an element's first output byte
+    const int64_t at = bs + 64 * sb + lane;                          // and its first input byte
     // the chain's end: its first element at or past the output's end, which
     // must start at the input's end exactly at the output's end
     const uint64_t endm = __ballot(el && qs >= out_len);
     if (endm && lane == __builtin_ctzll(endm))
-      atomicMin(&s_end, (uint32_t)t << 1 | (uint32_t)((int64_t)ip + t != w.in_len || qs != out_len));
+      atomicMin(&s_end[ipar], (uint32_t)at << 1 | (uint32_t)(at != w.in_len || qs != out_len));
     if (el && qs < out_len) {
       const int64_t fs = qs & ~(int64_t)(kFrag - 1);
-      if (qs == fs) fi[qs >> 16] = ip + t;
-      if (c_len > kLenClamp || qs + c_len > fs + kFrag || (c_off != 0 && (c_off < 0 || qs - c_off < fs))) s_dep = 1;
+      if (qs == fs) fi[qs >> 16] = (int32_t)at;
+      if (T.len > kLenClamp || qs + T.len > fs + kFrag || (T.off != 0 && (T.off < 0 || qs - T.off < fs)))
+        s_dep = 1;
+    }
+  };
+  // (2) the walker, wave 0: the chain through the block at bs (tables
+  // exs[par]). The wave holds the block's exits in registers (lane l of ex[s]:
+  // sub-batch s's byte l) and hops with register reads only, sub-batch by
+  // sub-batch; lane s then stores sub-batch s's entry.
+  int64_t wpos = ip0, wq = 0;  // (wave 0) the chain's next element and its output position
+  bool wstop = false;          // (wave 0) the sub-batch of the chain's end is recorded
+  auto walk = [&](int64_t bs, int par) {
+    int2 ex[kScanSub];
+#pragma unroll
+    for (int s = 0; s < kScanSub; s++) ex[s] = exs[par][64 * s + lane];
+    int32_t my_ent = -1;
+    int64_t my_q = 0;
+    int64_t rel = wstop ? (int64_t)kScanBlk : wpos - bs;  // >= 0: a block starts at or before the chain's place
+#pragma unroll
+    for (int s = 0; s < kScanSub; s++) {
+      if (!wstop && (rel >> 6) == s) {  // (uniform)
+        const int l = (int)(rel & 63);
+        if (lane == s) {
+          my_ent = l;
+          my_q = wq;
+        }
+        if (wq >= out_len) {
+          wstop = true;  // this sub-batch holds the chain's end (phase 3 finds it)
+        } else {
+          wq += __builtin_amdgcn_readlane(ex[s].y, l);
+          rel = __builtin_amdgcn_readlane(ex[s].x, l);
+        }
+      }
+    }
+    if (lane < kScanSub) {
+      ent[par][lane] = my_ent;
+      qent[par][lane] = my_q;
+    }
+    if (!wstop) {
+      wpos = bs + rel;
+      // the chain left the input short of the output's end
+      if (lane == 0 && wpos > w.in_len && wq < out_len) s_bad = 1;
+    }
+    if (lane == 0) s_pos = wpos;
+  };
+
+  ScanTab A, B, C;  // the tables of blocks i - 1, i, i + 1
+  bool dep = false, done = bad;
+  int64_t b_prev = 0, b_cur = ip0, entry = ip0;
+  __syncthreads();
+  if (!done) {
+    w.ensure<64 * kScanWaves>(b_cur, kScanBlk + 8);
+    if (wv > 0) tables(b_cur, 0, B);
+  }
+  __syncthreads();
+  // every thread holds the same block starts and `done`: the loop is uniform
+  for (int64_t i = 0; !done; i++) {
+    // block i + 1 starts after block i, or where the chain is if it is past
+    // block i already (a literal skipped it)
+    const int64_t b_next = entry > b_cur + kScanBlk ? entry : b_cur + kScanBlk;
+    w.ensure<64 * kScanWaves>(b_next, kScanBlk + 8);
+    const int par = (int)(i & 1);
+    if (wv > 0) {
+      if (i > 0) mark(b_prev, par ^ 1, par, A);
+      tables(b_next, par ^ 1, C);
+    } else {
+      walk(b_cur, par);
+      if (lane == 0) s_end[par ^ 1] = UINT32_MAX;  // for the next iteration's marks
     }
     __syncthreads();
-    const uint32_t end = s_end;
+    // the shared state is read between two barriers: no thread writes it
+    // again before every thread has read it
+    const uint32_t end = s_end[par];
+    entry = s_pos;
     if (s_dep != 0) {
       dep = true;
       done = true;
     } else if (end != UINT32_MAX) {
       done = true;
       bad = (end & 1) != 0;
-    } else {
-      const int64_t nip = (int64_t)ip + s_exit;
-      q = s_q;
-      if (nip > w.in_len) {
-        bad = true;
-        done = true;
-      } else {
-        ip = (int32_t)nip;
-      }
+    } else if (s_bad != 0) {
+      bad = true;
+      done = true;
     }
+    __syncthreads();
+    A = B;
+    B = C;
+    b_prev = b_cur;
+    b_cur = b_next;
   }
   if (t == 0) {
     flags[blockIdx.x] = dep ? 1 : bad ? 2 : 0;
@@ -1061,7 +1126,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
       const int32_t* cl = reinterpret_cast<const int32_t*>(W + L.compl_);
       int32_t* frag_in = reinterpret_cast<int32_t*>(W + L.frag_in);
       int32_t* flags = reinterpret_cast<int32_t*>(W + L.cflags);
-      hipLaunchKernelGGL(k_pq_snappy_scan, dim3((int)comp_pages.size()), dim3(kScanStep), 0, stream, dp, cl, raw, frag_in,
+      hipLaunchKernelGGL(k_pq_snappy_scan, dim3((int)comp_pages.size()), dim3(64 * kScanWaves), 0, stream, dp, cl, raw, frag_in,
                          flags, hdr);
       if (p->frags > 0)
         hipLaunchKernelGGL(k_pq_snappy_frag, dim3((int)p->frags), dim3(64), 0, stream, dp, cl,
