@@ -196,13 +196,15 @@ constexpr int kFrag = 65536;  // the reference compressor's independent fragment
 // those 2^k elements (k < 6), up to where the chain leaves the sub-batch.
 // (2) Wave 0 walks the chain through the block a sub-batch per hop (register
 // reads of the sub-batches' exits), giving each sub-batch the lane its
-// elements start at and the output position there. (3) Each lane, from its sub-batch's first
-// element, jumps 2^k elements (k = 5 .. 0) while that lands at or before it:
-// it is an element if it lands on itself, and the jumps' output bytes give
-// its output position. The three run as a pipeline, one barrier per block:
-// while wave 0 walks block i, the other waves build block i + 1's tables
-// and mark block i - 1's elements. A block starts where the one before it
-// ends, or where the chain is when a literal has skipped a whole block.
+// elements start at and the output position there. (3) Each lane, from its
+// sub-batch's first element, jumps 2^k elements (k = 5 .. 0) while that
+// lands at or before it: it is an element if it lands on itself, and the
+// jumps' output bytes give its output position. The three run as a pipeline
+// with one pair of barriers per block: while wave 0 walks block i, the other
+// waves build block i + 1's tables and mark block i - 1's elements. A block
+// starts where the one before it ends, or where the chain is when a literal
+// has skipped a whole block. (A register walk per element in (3), in place of
+// the jumps, took 1.7x as long.)
 constexpr int kScanWaves = 16;
 constexpr int kScanSub = kScanWaves - 1;   // sub-batches per block
 constexpr int kScanBlk = 64 * kScanSub;    // input bytes per block
