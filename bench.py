@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 PROBE_COUNTERS = {
     "sources": ["paper_2508_05029_amd/csrc/join_ops.hip", "paper_2508_05029_amd/csrc/table.h",
                 "paper_2508_05029_amd/csrc/groupby.h", "paper_2508_05029_amd/csrc/common.h"],
-    "sha1": "ae46ba7129ced972be58d896c4775a64da8eabcd",
-    "fetch_kib": 115002.3, "fetch_scale": 2.000,
+    "sha1": "d2ae21851057d1c8403a520400b508ad1e12574d",
+    "fetch_kib": 115010.8, "fetch_scale": 2.000,
     "write_kib": 104.0, "write_scale": 0.9955,
 }
 

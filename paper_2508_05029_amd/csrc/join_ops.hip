@@ -1211,8 +1211,10 @@ __global__ __launch_bounds__(kBloomPipeBlock, 1) void k_probe_compact(const Tabl
 
   v2i64 cv[kCmpSets][NC], ck[kCmpSets];
   int64_t r = wbase + lane * R;
+  if (n_main > 0) {  // (with no full tile there is no tile 0 to read in its place)
 #pragma unroll
-  for (int s = 0; s < kCmpSets; s++) load_cols(cv[s], ck[s], r + s * stride);
+    for (int s = 0; s < kCmpSets; s++) load_cols(cv[s], ck[s], r + s * stride);
+  }
   asm volatile("" ::: "memory");
   __syncthreads();  // the filter, the partials and the queues are ready
   for (int64_t t0 = wbase; t0 < n_main; t0 += kCmpSets * stride, r += kCmpSets * stride) {
