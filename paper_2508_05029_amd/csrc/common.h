@@ -187,12 +187,16 @@ __host__ __device__ inline size_t block_rows_bytes(int64_t cap_max) {
   return ((size_t)part_grid_max(cap_max) * 4 + 255) & ~(size_t)255;
 }
 // Bloom words (32-bit) for a table of `cap` slots: two bits per slot, between
-// two words per region and 128 KiB (the LDS a probe workgroup gives it).
+// two words per region and 2 MiB. Up to 128 KiB (the LDS a probe workgroup
+// gives it) a probe reads the filter from LDS, past that from device memory,
+// where one XCD's 4 MiB L2 can hold it.
 constexpr int kBloomWordsMax = 32768;
 constexpr int kLog2BloomWordsMax = 15;
+constexpr int kGBloomWordsMax = 1 << 19;
+constexpr int kLog2GBloomWordsMax = 19;
 __host__ __device__ inline int64_t bloom_words_max(int64_t cap) {
   const int64_t w = cap / 16;
-  return w < 2 * kRegionBins ? 2 * kRegionBins : (w > kBloomWordsMax ? kBloomWordsMax : w);
+  return w < 2 * kRegionBins ? 2 * kRegionBins : (w > kGBloomWordsMax ? kGBloomWordsMax : w);
 }
 __host__ __device__ inline size_t scratch_bytes(int64_t cap_max) {
   return block_rows_bytes(cap_max) + (size_t)part_grid_max(cap_max) * kMetaStride * 4 + (size_t)cap_max * 16 +
@@ -246,16 +250,19 @@ __device__ __forceinline__ bool in_partition(uint64_t h, int skip, uint32_t flag
 // Bloom filter of a region-built table, from the key's multiplicative hash h:
 // the key's region (as for its bucket) selects a block of 2^(log2w -
 // kLog2Bins) 32-bit words, bits 19.. of h the word in the block and three bit
-// positions in it (bits that the tag, the slot start and the bucket index of
-// tables up to 2^(23 - skip) buckets leave unused).
+// positions in it, from the bits above those (from bit 26 at least): bits
+// that the tag, the slot start and the bucket index of tables up to 2^(23 -
+// skip) buckets leave unused (the largest filters share one or two with the
+// bucket index of the largest tables).
 __device__ __forceinline__ uint32_t bloom_word(uint64_t h, int skip, int log2w) {
   const uint32_t region = (uint32_t)((h << skip) >> (64 - kLog2Bins));
   const int sub_bits = log2w - kLog2Bins;
   const uint32_t sub = (uint32_t)(h >> 19) & ((1u << sub_bits) - 1u);
   return (region << sub_bits) | sub;
 }
-__device__ __forceinline__ uint32_t bloom_bits(uint64_t h) {
-  const uint32_t x = (uint32_t)(h >> 26);
+__device__ __forceinline__ uint32_t bloom_bits(uint64_t h, int log2w = kLog2BloomWordsMax) {
+  const int sub_bits = log2w - kLog2Bins;
+  const uint32_t x = (uint32_t)(h >> (sub_bits > 7 ? 19 + sub_bits : 26));
   return (1u << (x & 31u)) | (1u << ((x >> 5) & 31u)) | (1u << ((x >> 10) & 31u));
 }
 

@@ -244,7 +244,6 @@ constexpr int kMinRegionLog2Cap = kLog2Bucket + kLog2Bins;  // a region of at le
 constexpr int kMaxRegionLog2Cap = 11 + kLog2Bins;            // at most kMaxRegionSlots slots
 constexpr int kMaxPassLog2Cap = kMaxRegionLog2Cap + 4;        // regions of up to 16 LDS domains
 constexpr int kMaxSubs = 1 << (kMaxPassLog2Cap - kMaxRegionLog2Cap);
-constexpr int kMaxBloomLog2Cap = kMaxRegionLog2Cap + 1;       // the largest filter's 2^20 bits: >= 2 per key
 
 template <int NC>
 __global__ __launch_bounds__(kPartBlock) void k_build_part(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
@@ -323,7 +322,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   __shared__ uint32_t ltag[kMaxRegionSlots / 2];
   __shared__ v2i64 lslot[kMaxRegionSlots];
   __shared__ int64_t ws[2 * kFinBlock / kWave];
-  __shared__ uint32_t lbloom[kBloomWordsMax / kRegionBins];
+  __shared__ uint32_t lbloom[kGBloomWordsMax / kRegionBins];
   __shared__ uint32_t sub_cnt[kMaxSubs], sub_fill[kMaxSubs], sub_off[kMaxSubs + 1];
   const int j = region_of_workgroup(blockIdx.x), tid = threadIdx.x;
   const uint32_t* meta = scratch_meta(h, cap_max) + j;  // region j's counts, block b at meta[b * kMetaStride]
@@ -339,7 +338,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     if (b == tid) m0 = m;
   }
   ltag[tid] = 0u;  // kFinBlock == kMaxRegionSlots / 2
-  if (tid < kBloomWordsMax / kRegionBins) lbloom[tid] = 0u;
+  for (int i = tid; i < kGBloomWordsMax / kRegionBins; i += kFinBlock) lbloom[i] = 0u;
   if (tid < kMaxSubs) sub_cnt[tid] = sub_fill[tid] = 0u;
   if (h->magic != kTableMagic) return;
   int64_t rows = rb, mine = cj;  // all rows; rows of region j
@@ -362,10 +361,12 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   const int sub_log2 = multi ? l - kMaxRegionLog2Cap : 0;
   const int64_t region_slots = in_range ? (int64_t)1 << (l - kLog2Bins) : 0;
   const bool fits = in_range && (multi || mine <= region_slots - std::max<int64_t>(1, region_slots / 8));
-  // Bloom words (log2) for this capacity: bloom_words_max(2^l); none where the
-  // filter's fixed size would leave too few bits per key to reject much
-  const int log2w = l <= kMaxBloomLog2Cap ? std::min(std::max(l - 4, kLog2Bins + 1), kLog2BloomWordsMax) : 0;
-  static_assert(kBloomWordsMax == 1 << kLog2BloomWordsMax && kRegionBins == 1 << kLog2Bins, "bloom size rule");
+  // Bloom words (log2) for this capacity: bloom_words_max(2^l), two bits per
+  // slot (every region-built capacity has its filter)
+  const int log2w = in_range ? std::max(l - 4, kLog2Bins + 1) : 0;
+  static_assert(kBloomWordsMax == 1 << kLog2BloomWordsMax && kRegionBins == 1 << kLog2Bins &&
+                    kGBloomWordsMax == 1 << kLog2GBloomWordsMax && kMaxPassLog2Cap - 4 <= kLog2GBloomWordsMax,
+                "bloom size rule");
   const int log2g = std::min(l, kMaxRegionLog2Cap) - kLog2Bucket - kLog2Bins;  // buckets per domain
   if (blockIdx.x == 0 && tid == 0) {
     h->cap_max = cap_max;
@@ -458,7 +459,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     stuck = stuck || !done;
   };
   auto add_bloom = [&](uint64_t hh) {
-    if (nbw) atomicOr(&lbloom[bloom_word(hh, skip, log2w) & (uint32_t)(nbw - 1)], bloom_bits(hh));
+    if (nbw) atomicOr(&lbloom[bloom_word(hh, skip, log2w) & (uint32_t)(nbw - 1)], bloom_bits(hh, log2w));
   };
   // Writes LDS domain d (of the whole table) out.
   auto write_domain = [&](int64_t d) {
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
     }
   }
   if (stuck) latch_error(&h->err, TQ_EFULL);
-  if (tid < nbw) scratch_bloom(h, cap_max)[(size_t)j * nbw + tid] = lbloom[tid];
+  for (int i = tid; i < nbw; i += kFinBlock) scratch_bloom(h, cap_max)[(size_t)j * nbw + i] = lbloom[i];
 }
 
 constexpr int kFallbackBlocks = 16;  // two per XCD; the global-CAS insert, when needed, strides over every row
@@ -762,7 +763,8 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
   extern __shared__ __align__(16) char smem[];
   if (h->magic != kTableMagic || h->err) return;  // a failed build inserted nothing: no row can match
   if (!state_matches(T)) return;
-  const int log2w = BLOOM ? h->bloom_log2w : 0;
+  // (a filter larger than the LDS copy, in device memory only, is not used here)
+  const int log2w = BLOOM && h->bloom_log2w <= kLog2BloomWordsMax ? h->bloom_log2w : 0;
   const int nbw = log2w ? 1 << log2w : 0;
   if (BLOOM) {
     // every load of the copy first, then every LDS store: one round trip to
@@ -1000,15 +1002,16 @@ __global__ __launch_bounds__(BLOOM ? kBloomPipeBlock : kAggBlock, BLOOM ? 1 : kP
 // rows have no partner and the filter drops most of those; the tag, slot and
 // aggregation stages then run on 64-row tiles of the survivors instead of on
 // every row slot. Stage 1, per tile of 2 rows per lane (columns requested
-// two tiles ahead): hash and filter test; the survivors move to the wave's
-// compaction buffer (three 64-row register tiles, B0, B1, B2) with one
-// ds_permute per 32-bit word: survivors to the buffer's next free lanes, the
-// rest to the remaining lanes, so the lane map is a permutation. Stage 2, once
-// per two tiles (and before a tile when the buffer might not take its rows):
-// the buffer's first tile (full, or what there is) goes through a three-deep
-// pipeline: its tag loads are issued; the tile before it turns its tags into
-// slot loads; the one before that is finished (aggregated, or queued for the
-// chain walk).
+// two tiles ahead): hash and filter test (the filter in LDS, or in device
+// memory when it is larger than the LDS copy: tables past 2^19 slots); the
+// survivors move to the wave's compaction buffer (three 64-row register
+// tiles, B0, B1, B2) with one ds_permute per 32-bit word: survivors to the
+// buffer's next free lanes, the rest to the remaining lanes, so the lane map
+// is a permutation. Stage 2, once per two tiles (and before a tile when the
+// buffer might not take its rows): the buffer's first tile (full, or what
+// there is) goes through a three-deep pipeline: its tag loads are issued;
+// the tile before it turns its tags into slot loads; the one before that is
+// finished (aggregated, or queued for the chain walk).
 constexpr int kCmpSets = 2;  // column tiles in flight per wave (even)
 constexpr int kCmpQLimit = kPipeQ - kWave;  // a finish queues at most 64 rows
 
@@ -1035,9 +1038,13 @@ __global__ __launch_bounds__(kBloomPipeBlock, 1) void k_probe_compact(const Tabl
   if (!state_matches(T)) return;
   const int log2w = h->bloom_log2w;
   const int nbw = log2w ? 1 << log2w : 0;
-  {
+  // a filter past the LDS copy's size is read from device memory, one tile
+  // ahead of its test (stage1_issue / stage1_test); the same in every lane
+  const bool gfilter = nbw > kBloomWordsMax;
+  const uint32_t* gbloom = scratch_bloom(const_cast<TableHeader*>(h), h->cap_max);
+  if (!gfilter) {
     constexpr int kU = kBloomWordsMax / 4 / kBloomPipeBlock;
-    const v4i32* gb = reinterpret_cast<const v4i32*>(scratch_bloom(const_cast<TableHeader*>(h), h->cap_max));
+    const v4i32* gb = reinterpret_cast<const v4i32*>(gbloom);
     v4i32 t[kU];
 #pragma unroll
     for (int u = 0; u < kU; u++) {
@@ -1195,8 +1202,16 @@ __global__ __launch_bounds__(kBloomPipeBlock, 1) void k_probe_compact(const Tabl
       const uint64_t hh = mulhash(kk[i]);
       bool live = rt < n_main && pr.selected(hh);
       if (nbw) {  // a key the filter rejects is not in the build
-        const uint32_t m = bloom_bits(hh);
-        live = live && (bloom[bloom_word(hh, pr.skip, log2w)] & m) == m;
+        const uint32_t wd = bloom_word(hh, pr.skip, log2w);
+        // (each branch tests its own load: a use after the branches would
+        // wait for the loads of both kinds)
+        if (gfilter) {
+          const uint32_t m = bloom_bits(hh, log2w);
+          live = live && (gbloom[rt < n_main ? wd : 0u] & m) == m;
+        } else {
+          const uint32_t m = bloom_bits(hh);  // (log2w <= kLog2BloomWordsMax)
+          live = live && (bloom[wd] & m) == m;
+        }
       }
       const CRow row{kk[i], ne > 0 ? eval_unit<NC>(U.s[0], v, i) : 0, (uint32_t)(rt + i - wbase)};
       push(live, row);

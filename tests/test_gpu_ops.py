@@ -332,9 +332,9 @@ def test_join_build_paths(case):
     assert log2cap == {"multipass": 21, "multipass_16": 23, "cas_large_table": 24,
                        "cas_domain_overflow": 21}.get(case, log2cap)
     assert log2g == (min(log2cap, 19) - 11 if regions else log2cap - 3)
-    # two filter bits per slot, 512 to 32768 words of 32 bits; only a region build has one, and
-    # only up to 2^20 slots (past that the largest filter has under two bits per key)
-    assert bloom_log2w == (min(max(log2cap - 4, 9), 15) if regions and log2cap <= 20 else 0)
+    # two filter bits per slot, 512 to 2^19 words of 32 bits (past 32768 words a probe reads it
+    # from device memory instead of LDS); only a region build (up to 2^23 slots) has one
+    assert bloom_log2w == (max(log2cap - 4, 9) if regions else 0)
     total, pr, br = oracle.join_pairs(bk[keep], pk)
     cap = max(total, 1)
     rows = torch.empty(cap, dtype=torch.int64, device=DEV)
