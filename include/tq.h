@@ -146,9 +146,10 @@ tq_status tq_hash_partition_noalloc(const int64_t* d_keys, const tq_col* payload
  * per slot (0 = empty), a 16-byte {key, payload} slot array, and a build
  * scratch area of about the slot array's size (the rows grouped by table
  * region, alternate tags for a fallback build, and a Bloom filter of the keys
- * that probes use to skip rows with no partner, for tables of up to 2^20
- * slots). A build fills the table region by region in LDS (256 regions; past
- * 2^19 slots each region as domains of 2048 slots, one after the other), or,
+ * that probes use to skip rows with no partner, two bits per slot for tables
+ * built region by region). A build fills the table region by region in LDS
+ * (256 regions; past 2^19 slots each region as domains of 2048 slots, one
+ * after the other), or,
  * past 2^23 slots or when some region or domain gets more rows than it holds
  * with an eighth free, inserts with global atomics.
  * Any int64 key is allowed; duplicate build keys are kept (many-to-many).
