@@ -1038,8 +1038,8 @@ __global__ __launch_bounds__(kBloomPipeBlock, 1) void k_probe_compact(const Tabl
   if (!state_matches(T)) return;
   const int log2w = h->bloom_log2w;
   const int nbw = log2w ? 1 << log2w : 0;
-  // a filter past the LDS copy's size is read from device memory, one tile
-  // ahead of its test (stage1_issue / stage1_test); the same in every lane
+  // a filter past the LDS copy's size is read from device memory (the same
+  // choice in every lane)
   const bool gfilter = nbw > kBloomWordsMax;
   const uint32_t* gbloom = scratch_bloom(const_cast<TableHeader*>(h), h->cap_max);
   if (!gfilter) {
