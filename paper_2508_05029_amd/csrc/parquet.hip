@@ -181,6 +181,10 @@ __device__ bool snappy_preamble(InWindow& w, uint32_t* ulen, int32_t* ip) {
 }
 
 constexpr int kFrag = 65536;  // the reference compressor's independent fragments
+// Every element takes at least two input bytes (a tag and a literal byte, or a
+// copy's tag and offset), so a chain crosses 64 bytes in at most 32 hops: five
+// doubling (or lifting) steps of 2^k hops cover it.
+constexpr int kHops = 5;
 
 // Pass 1, one workgroup of kScanWaves waves per compressed body: follows the
 // element chain, records where each 64 KiB output fragment's first element
@@ -193,11 +197,11 @@ constexpr int kFrag = 65536;  // the reference compressor's independent fragment
 // sub-batch per wave of waves 1 .. kScanWaves - 1, each thread decoding the
 // element that would start at its byte. (1) Each wave builds, by pointer
 // doubling, the start 2^k elements on from each lane and the output bytes of
-// those 2^k elements (k < 6), up to where the chain leaves the sub-batch.
+// those 2^k elements (k < kHops), up to where the chain leaves the sub-batch.
 // (2) Wave 0 walks the chain through the block a sub-batch per hop (register
 // reads of the sub-batches' exits), giving each sub-batch the lane its
 // elements start at and the output position there. (3) Each lane, from its
-// sub-batch's first element, jumps 2^k elements (k = 5 .. 0) while that
+// sub-batch's first element, jumps 2^k elements (k = kHops - 1 .. 0) while that
 // lands at or before it: it is an element if it lands on itself, and the
 // jumps' output bytes give its output position. The three run as a pipeline
 // with one pair of barriers per block: while wave 0 walks block i, the other
@@ -214,8 +218,8 @@ constexpr int32_t kLenClamp = 1 << 24;
 
 // A lane's doubling tables for one block (phase 1, kept for phase 3).
 struct ScanTab {
-  int32_t jk[6];   // the start 2^k elements on, sub-batch-relative (>= 64: past it)
-  uint32_t sk[6];  // the output bytes of those 2^k elements
+  int32_t jk[kHops];   // the start 2^k elements on, sub-batch-relative (>= 64: past it)
+  uint32_t sk[kHops];  // the output bytes of those 2^k elements
   int32_t len, off;
 };
 
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void k_pq_snappy_scan(const PqPage
     int32_t J = lane + c_adv;
     uint32_t S = (uint32_t)min(c_len, kLenClamp);
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
+    for (int k = 0; k < kHops; k++) {
       T.jk[k] = J;
       T.sk[k] = S;
       const int src = J < 64 ? J : lane;
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(64 * kScanWaves) void k_pq_snappy_scan(const PqPage
     int32_t pos = e < 0 ? 0 : e;
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 5; k >= 0; k--) {
+    for (int k = kHops - 1; k >= 0; k--) {
       const int32_t c = __shfl(T.jk[k], pos);
       const uint32_t a = __shfl(T.sk[k], pos);
       if (c <= lane) {
@@ -423,12 +427,12 @@ __global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, cons
     const int32_t wi = ip + lane - w.wbase;
     snappy_candidate(w.win, wi, c_adv, c_len, c_off);
     const uint32_t mine = in_byte(w.win, wi);  // input byte ip + lane
-    int32_t jk[6];
-    uint32_t sk[6];
+    int32_t jk[kHops];
+    uint32_t sk[kHops];
     int32_t J = lane + c_adv;
     uint32_t S = (uint32_t)min(c_len, kLenClamp);
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
+    for (int k = 0; k < kHops; k++) {
       jk[k] = J;
       sk[k] = S;
       const int src = J < 64 ? J : lane;
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, cons
     int32_t pos = 0;
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 5; k >= 0; k--) {
+    for (int k = kHops - 1; k >= 0; k--) {
       const int32_t c = __shfl(jk[k], pos);
       const uint32_t a = __shfl(sk[k], pos);
       if (c <= lane) {
