@@ -230,6 +230,10 @@ def _hand_page(seed, plan):
     ("far", [("lit", 70_000), ("copy", 68_000, 64), ("copy", 65_536, 40), ("copy", 1, 64), ("copy", 3, 17)]),
     # a literal across the 64 KiB boundary, then copies reaching back over it
     ("across", [("lit", 65_530), ("lit", 20), ("copy", 30, 64), ("lit", 80_000), ("copy", 70_000, 10)]),
+    # literals of about a chain-scan block (960 input bytes) or two, each followed by short
+    # elements, so that chains leave blocks at every offset and skip whole blocks: one fragment
+    ("block_edges", [e for k in range(40) for e in (("lit", 950 + (k * 7) % 30 + 960 * (k % 2)), ("copy", 8, 40 + k % 25),
+                                                     ("lit", 1 + k % 3), ("copy", 1 + k % 5, 64))]),
 ])
 def test_hand_built_snappy_pages(tmp_path, name, plan):
     import pyarrow.parquet as pq
