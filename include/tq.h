@@ -712,7 +712,8 @@ tq_status tq_parquet_chunk(const tq_parquet* pq, int32_t rg, int32_t c, int64_t*
 /* Byte Range Pre-loading: the chunks of columns h_cols[0..ncol) in row
  * groups [rg0, rg1), sorted by offset, ranges at most merge_gap bytes apart
  * merged into one read; pool pages are taken for every read (TQ_ENOMEM if the
- * pool has too few) and a host thread starts reading into them; the call
+ * pool has too few) and up to four host threads start reading into them,
+ * each taking the next piece of at most 2 MiB within one page; the call
  * returns at once. The file handle and the pool must outlive the preload
  * (tq_preload_free waits for the reads). */
 tq_status tq_parquet_preload(tq_parquet* pq, tq_pagepool* pool, int32_t rg0, int32_t rg1, const int32_t* h_cols,

@@ -1,6 +1,6 @@
 // Parquet scan, host side: the file footer (Thrift compact protocol), the
 // byte ranges of the column chunks a scan needs, merged when close (Byte
-// Range Pre-loading, Section 3.3.3), read ahead into pool pages by a thread
+// Range Pre-loading, Section 3.3.3), read ahead into pool pages by threads
 // of their own, and the page headers walked once the bytes are in host
 // memory. The pages themselves are decoded on the GPU (parquet.hip).
 #include "parquet.h"
@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <system_error>
 
 #include "common.h"
 
@@ -307,24 +308,30 @@ int64_t raw_of(const tq_preload* p, int64_t file_off) {
   return -1;
 }
 
-void read_all(tq_preload* p) {
-  const size_t pb = tq_pagepool_page_bytes(p->pool);
-  for (tq_parquet_read& r : p->reads) {
-    int64_t done = 0;
-    for (size_t i = 0; i < r.pages.size(); i++) {
-      char* dst = static_cast<char*>(tq_pagepool_page(p->pool, r.pages[i]));
-      const int64_t want = std::min<int64_t>((int64_t)pb, r.bytes - done);
-      int64_t got = 0;
-      while (got < want) {
-        const ssize_t k = pread(p->pq->fd, dst + got, (size_t)(want - got), (off_t)(r.file_off + done + got));
-        if (k <= 0) {
+// Reader threads per preload, and the largest piece one of them reads at a
+// time: one thread copies from the page cache at well under the host's memory
+// bandwidth, so the merged ranges are split and read by several at once.
+constexpr int kPqReaders = 4;
+constexpr int64_t kPqReadPiece = 2 << 20;
+
+void read_pieces(tq_preload* p) {
+  for (;;) {
+    const int64_t t = p->next_piece.fetch_add(1);
+    if (t >= (int64_t)p->pieces.size() || p->read_failed.load()) return;
+    const tq_parquet_piece& pc = p->pieces[(size_t)t];
+    int64_t got = 0;
+    while (got < pc.bytes) {
+      const ssize_t k = pread(p->pq->fd, pc.dst + got, (size_t)(pc.bytes - got), (off_t)(pc.file_off + got));
+      if (k <= 0) {
+        std::lock_guard<std::mutex> lock(p->read_mu);
+        if (!p->read_status) {
           p->read_status = TQ_EINVAL;
           p->read_error = "reading " + p->pq->path + " failed";
-          return;
         }
-        got += k;
+        p->read_failed.store(true);
+        return;
       }
-      done += want;
+      got += k;
     }
   }
 }
@@ -518,7 +525,8 @@ size_t pq_work_bytes(const tq_preload* p) { return pq_layout(p).total; }
 
 tq_status pq_join(tq_preload* p) {
   if (!p->joined) {
-    if (p->reader.joinable()) p->reader.join();
+    for (std::thread& t : p->readers)
+      if (t.joinable()) t.join();
     p->joined = true;
   }
   if (p->read_status) return fail(p->read_status, "%s", p->read_error.c_str());
@@ -725,7 +733,20 @@ tq_status tq_parquet_preload(tq_parquet* pq, tq_pagepool* pool, int32_t rg0, int
     raw += align256(r.bytes);
   }
   p->raw_bytes = raw;
-  p->reader = std::thread(read_all, p);
+  for (const tq_parquet_read& r : p->reads)
+    for (size_t i = 0; i < r.pages.size(); i++) {
+      char* page = static_cast<char*>(tq_pagepool_page(pool, r.pages[i]));
+      const int64_t page_end = std::min<int64_t>((int64_t)((i + 1) * pb), r.bytes);
+      for (int64_t at = (int64_t)(i * pb); at < page_end; at += kPqReadPiece)
+        p->pieces.push_back(tq_parquet_piece{r.file_off + at, std::min(kPqReadPiece, page_end - at),
+                                             page + (at - (int64_t)(i * pb))});
+    }
+  const int nthreads = (int)std::min<int64_t>(kPqReaders, (int64_t)p->pieces.size());
+  try {
+    for (int t = 0; t < nthreads; t++) p->readers.emplace_back(read_pieces, p);
+  } catch (const std::system_error&) {  // no more threads: those started (or this one) read the rest
+    if (p->readers.empty()) read_pieces(p);
+  }
   *out = p;
   return TQ_OK;
 }

@@ -4,6 +4,8 @@
 
 #include <stdint.h>
 
+#include <atomic>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -107,6 +109,12 @@ struct tq_parquet_read {
   std::vector<int32_t> pages;  // pool pages holding it, in order
 };
 
+// A piece of a read: at most kPqReadPiece bytes inside one pool page.
+struct tq_parquet_piece {
+  int64_t file_off, bytes;
+  char* dst;
+};
+
 struct tq_preload {
   tq_parquet* pq = nullptr;
   tq_pagepool* pool = nullptr;
@@ -115,7 +123,11 @@ struct tq_preload {
   std::vector<tq_parquet_read> reads;
   int64_t raw_bytes = 0;
   int64_t rows = 0;
-  std::thread reader;
+  std::vector<tq_parquet_piece> pieces;
+  std::vector<std::thread> readers;  // each takes the next piece until none is left
+  std::atomic<int64_t> next_piece{0};
+  std::atomic<bool> read_failed{false};
+  std::mutex read_mu;  // guards read_status / read_error
   bool joined = false;
   bool decoded = false;  // a preload is decoded once: its pages go back to the pool
   tq_status read_status = TQ_OK;

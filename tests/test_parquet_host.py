@@ -139,6 +139,39 @@ def test_refused_files(tmp_path):
     assert pool.free_pages() == 16
 
 
+def test_large_pages_are_read_in_pieces(tmp_path):
+    """Pool pages of 8 MiB are read as 2 MiB pieces by several threads: with a
+    page header every 64 KiB, a piece left unread breaks the walk."""
+    cols = pqfiles.columns(600_000, 13)
+    path = pqfiles.write(str(tmp_path / "big.parquet"), cols, data_page_size=65_536)
+    f = tq.ParquetFile(path)
+    pool = tq.PagePool(8 << 20, 8, pinned=False)
+    sel = list(range(len(cols)))
+    pl = f.preload(pool, 0, f.num_row_groups, sel, merge_gap=1 << 20)
+    assert sum(n for _, n in pl.reads()) > 4 << 20  # several pieces per page
+    assert pl.work_bytes() > 0
+    pages = pl.pages()
+    for c in sel:
+        data = [(r0, n) for r0, n, col, kind, _ in pages if col == c and kind == 0]
+        assert data[0][0] == 0 and all(a[0] + a[1] == b[0] for a, b in zip(data, data[1:]))
+        assert data[-1][0] + data[-1][1] == 600_000
+    pl.free()
+    assert pool.free_pages() == 8
+
+
+def test_file_cut_after_open_fails_the_read(tmp_path):
+    cols = pqfiles.columns(200_000, 14)
+    path = pqfiles.write(str(tmp_path / "cut.parquet"), cols, data_page_size=65_536)
+    f = tq.ParquetFile(path)  # footer read while the file is whole
+    os.truncate(path, os.path.getsize(path) // 3)
+    pool = tq.PagePool(1 << 20, 16, pinned=False)
+    pl = f.preload(pool, 0, f.num_row_groups, list(range(len(cols))), merge_gap=1 << 20)
+    with pytest.raises(tq.TqError, match="reading"):
+        pl.work_bytes()
+    pl.free()
+    assert pool.free_pages() == 16
+
+
 def test_pool_too_small_is_refused(small):
     path, _ = small
     f = tq.ParquetFile(path)
