@@ -136,7 +136,9 @@ struct InWindowT {
   int64_t c_off;
   int32_t in_len;
   int32_t wbase;
-  template <int NT = 64>  // the workgroup's threads
+  // NT: the threads that load (the workgroup, or one wave of it: then kSync
+  // false, and only that wave reads the window)
+  template <int NT = 64, bool kSync = true>
   __device__ void ensure(int32_t at, int32_t need) {
     if (at >= wbase && at + need <= wbase + WIN) return;
     // 16-byte loads, all issued before any is stored: one memory round trip
@@ -155,7 +157,10 @@ struct InWindowT {
       const int i = (int)threadIdx.x + NT * u;
       if (i < WIN / 16 + 1) reinterpret_cast<v4i32*>(win)[i] = t[u];
     }
-    __syncthreads();
+    if (kSync)
+      __syncthreads();
+    else
+      asm volatile("" ::: "memory");  // one wave's LDS accesses take effect in program order
   }
   __device__ uint32_t byte(int32_t at) const { return in_byte(win, at - wbase); }
 };
@@ -391,122 +396,166 @@ __global__ __launch_bounds__(64 * kScanWaves) void k_pq_snappy_scan(const PqPage
   }
 }
 
-// Pass 2, one wave per 64 KiB fragment of a body whose fragments are
-// independent, inflated into an LDS copy of the fragment that is then written
-// out. A batch: lane i decodes the element that would start at input byte
-// ip + i; doubling and lifting (as in the scan, from lane 0) give the
-// elements and their output positions. Literal payload bytes among the
-// batch's 64 input bytes are stored by the lanes holding them (one store);
-// the payload of a literal running past them, by the whole wave; then the
-// copies, which read earlier output, in order. A wave's LDS accesses take
-// effect in program order, so between copies only the compiler is fenced.
-constexpr int kFragWin = 8192;  // (64 KiB fragment + this window: two workgroups per CU)
+// Pass 2, one workgroup of two waves per 64 KiB fragment of a body whose
+// fragments are independent, inflated into an LDS copy of the fragment that is
+// then written out. Wave 0 parses. A batch: lane i decodes the element that
+// would start at input byte ip + i; doubling and lifting (as in the scan, from
+// lane 0) give the elements and their output positions. Wave 0 stores the
+// literal payload bytes (those among the batch's 64 input bytes by the lanes
+// holding them, the payload of a literal running past them by the whole wave)
+// and queues the batch's copies; wave 1 runs the copies, which read earlier
+// output, in order. They work in rounds: wave 0 parses up to kFragQ batches
+// into one half of the queue while wave 1 runs the copies the other half took
+// in the round before; a barrier ends each round and makes its literal bytes
+// visible to the copies of the next. A wave's LDS accesses take effect in
+// program order, so between copies only the compiler is fenced.
+constexpr int kFragWin = 8192;  // (64 KiB fragment + this window + the queue: two workgroups per CU)
+constexpr int kFragQ = 4;       // batches per round
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-__global__ __launch_bounds__(64) void k_pq_snappy_frag(const PqPage* pages, const int32_t* cpages,
-                                                       const int32_t* frag_cpage, uint8_t* raw, const int32_t* frag_in,
-                                                       const int32_t* flags, PqHeader* hdr) {
+__global__ __launch_bounds__(2 * kWave) void k_pq_snappy_frag(const PqPage* pages, const int32_t* cpages,
+                                                              const int32_t* frag_cpage, uint8_t* raw,
+                                                              const int32_t* frag_in, const int32_t* flags,
+                                                              PqHeader* hdr) {
   __shared__ uint32_t buf[kFrag / 4];
   __shared__ __align__(16) uint32_t wbuf[kFragWin / 4 + 4];
+  __shared__ uint2 cq[2][kFragQ][kWave];  // a queued batch, per lane: output offset | length << 16, copy offset
+  __shared__ uint64_t cmask[2][kFragQ];   // the lanes of its copies
+  __shared__ int32_t s_nb[2], s_done, s_bad;
   uint8_t* fb = reinterpret_cast<uint8_t*>(buf);
   const int32_t ci = frag_cpage[blockIdx.x];
   if (flags[ci] != 0) return;
   const PqPage pg = pages[cpages[ci]];
   const int32_t f = (int32_t)(blockIdx.x - pg.frag0);
-  InWindowT<kFragWin> w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};
   const int32_t out_len = (int32_t)pg.u_len;
   const int32_t fs = f * kFrag, fe = min(fs + kFrag, out_len);
-  const int lane = threadIdx.x;
-  const uint8_t* in = raw + pg.c_off;
-  int32_t ip = frag_in[pg.frag0 + f], q = fs;
-  bool bad = ip < 0 || ip >= w.in_len;
-  while (!bad && q < fe) {
-    w.ensure(ip, 64 + 8);
-    int32_t c_adv, c_len, c_off;
-    const int32_t wi = ip + lane - w.wbase;
-    snappy_candidate(w.win, wi, c_adv, c_len, c_off);
-    const uint32_t mine = in_byte(w.win, wi);  // input byte ip + lane
-    int32_t jk[kHops];
-    uint32_t sk[kHops];
-    int32_t J = lane + c_adv;
-    uint32_t S = (uint32_t)min(c_len, kLenClamp);
-#pragma unroll
-    for (int k = 0; k < kHops; k++) {
-      jk[k] = J;
-      sk[k] = S;
-      const int src = J < 64 ? J : lane;
-      const int32_t Jn = __shfl(J, src);
-      const uint32_t Sn = __shfl(S, src);
-      if (J < 64) {
-        J = Jn;
-        S += Sn;
-      }
-    }
-    int32_t pos = 0;
-    uint32_t acc = 0;
-#pragma unroll
-    for (int k = kHops - 1; k >= 0; k--) {
-      const int32_t c = __shfl(jk[k], pos);
-      const uint32_t a = __shfl(sk[k], pos);
-      if (c <= lane) {
-        pos = c;
-        acc += a;
-      }
-    }
-    const int64_t qs = (int64_t)q + acc;  // an element's first output byte
-    const uint64_t live = __ballot(pos == lane && qs < fe);  // the fragment's elements in the batch (lane 0: q < fe)
-    const bool me = (live >> lane) & 1;
-    const int32_t at = ip + lane;
-    // the scan checked the chain; these checks keep every access in bounds
-    // regardless (a length past the fragment also catches a clamped one)
-    const bool badl = me && (at >= w.in_len || c_len > fe - qs || c_adv > w.in_len - at ||
-                             (c_off != 0 && (c_off <= 0 || c_off > qs - fs)));
-    if (__ballot(badl)) {
-      bad = true;
-      break;
-    }
-    const int32_t lq = (int32_t)(qs - fs);  // (live lanes) its offset in the fragment
-    // literal payload bytes among the batch's input bytes: lane j's byte
-    // belongs to the last element starting at or before j
-    const int eo = 63 - __builtin_clzll(live & ((2ull << lane) - 1));
-    const int32_t e_len = __shfl(c_len, eo), e_adv = __shfl(c_adv, eo), e_off = __shfl(c_off, eo);
-    const int32_t e_lq = __shfl(lq, eo);
-    const int32_t rel = lane - (eo + e_adv - e_len);  // its place in that element's payload
-    if (e_off == 0 && rel >= 0 && rel < e_len) fb[e_lq + rel] = (uint8_t)mine;
-    // the batch's last element: a literal may run past the batch's input bytes
-    const int L = 63 - __builtin_clzll(live);
-    const int32_t l_len = __builtin_amdgcn_readlane(c_len, L), l_adv = __builtin_amdgcn_readlane(c_adv, L);
-    const int32_t l_off = __builtin_amdgcn_readlane(c_off, L), l_lq = __builtin_amdgcn_readlane(lq, L);
-    if (l_off == 0 && L + l_adv > 64) {
-      const int32_t p0 = L + l_adv - l_len;  // payload start, batch-relative
-      const int32_t src = ip + p0;
-      const bool in_win = src >= w.wbase && src + l_len <= w.wbase + kFragWin;
-      for (int32_t j = max(0, 64 - p0) + lane; j < l_len; j += 64)
-        fb[l_lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
-    }
-    compiler_fence();
-    // copies, in order
-    uint64_t rest = live & __ballot(c_off != 0);
-    while (rest) {
-      const int l = __builtin_ctzll(rest);
-      rest &= rest - 1;
-      const int32_t len = __builtin_amdgcn_readlane(c_len, l);
-      const int32_t off = __builtin_amdgcn_readlane(c_off, l);
-      const int32_t dq = __builtin_amdgcn_readlane(lq, l);
-      if (lane < len) fb[dq + lane] = fb[dq - off + (off >= len ? lane : lane % off)];
-      compiler_fence();
-    }
-    q = fs + l_lq + l_len;
-    ip += L + l_adv;
-  }
-  if (bad) {
-    if (lane == 0) pq_error(hdr, TQ_EINVAL);
-    return;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (threadIdx.x == 0) {
+    s_nb[0] = s_nb[1] = 0;
+    s_done = s_bad = 0;
   }
   __syncthreads();
+  InWindowT<kFragWin> w{wbuf, raw, pg.c_off, (int32_t)pg.c_len, INT32_MIN / 2};  // wave 0's
+  const uint8_t* in = raw + pg.c_off;
+  int32_t ip = frag_in[pg.frag0 + f], q = fs;
+  bool parsed = false, failed = false;  // the same in every thread
+  for (int r = 0;; r++) {
+    const int par = r & 1;
+    if (wave == 0 && !parsed) {
+      int nb = 0;
+      bool bad = ip < 0 || ip >= w.in_len;
+      while (!bad && nb < kFragQ && q < fe) {
+        w.template ensure<kWave, false>(ip, 64 + 8);
+        int32_t c_adv, c_len, c_off;
+        const int32_t wi = ip + lane - w.wbase;
+        snappy_candidate(w.win, wi, c_adv, c_len, c_off);
+        const uint32_t mine = in_byte(w.win, wi);  // input byte ip + lane
+        int32_t jk[kHops];
+        uint32_t sk[kHops];
+        int32_t J = lane + c_adv;
+        uint32_t S = (uint32_t)min(c_len, kLenClamp);
+#pragma unroll
+        for (int k = 0; k < kHops; k++) {
+          jk[k] = J;
+          sk[k] = S;
+          const int src = J < 64 ? J : lane;
+          const int32_t Jn = __shfl(J, src);
+          const uint32_t Sn = __shfl(S, src);
+          if (J < 64) {
+            J = Jn;
+            S += Sn;
+          }
+        }
+        int32_t pos = 0;
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = kHops - 1; k >= 0; k--) {
+          const int32_t c = __shfl(jk[k], pos);
+          const uint32_t a = __shfl(sk[k], pos);
+          if (c <= lane) {
+            pos = c;
+            acc += a;
+          }
+        }
+        const int64_t qs = (int64_t)q + acc;  // an element's first output byte
+        const uint64_t live = __ballot(pos == lane && qs < fe);  // the fragment's elements in the batch (lane 0: q < fe)
+        const bool me = (live >> lane) & 1;
+        const int32_t at = ip + lane;
+        // the scan checked the chain; these checks keep every access in bounds
+        // regardless (a length past the fragment also catches a clamped one)
+        const bool badl = me && (at >= w.in_len || c_len > fe - qs || c_adv > w.in_len - at ||
+                                 (c_off != 0 && (c_off <= 0 || c_off > qs - fs)));
+        if (__ballot(badl)) {
+          bad = true;
+          break;
+        }
+        const int32_t lq = (int32_t)(qs - fs);  // (live lanes) its offset in the fragment, below 2^16
+        // literal payload bytes among the batch's input bytes: lane j's byte
+        // belongs to the last element starting at or before j
+        const int eo = 63 - __builtin_clzll(live & ((2ull << lane) - 1));
+        const int32_t e_len = __shfl(c_len, eo), e_adv = __shfl(c_adv, eo), e_off = __shfl(c_off, eo);
+        const int32_t e_lq = __shfl(lq, eo);
+        const int32_t rel = lane - (eo + e_adv - e_len);  // its place in that element's payload
+        if (e_off == 0 && rel >= 0 && rel < e_len) fb[e_lq + rel] = (uint8_t)mine;
+        // the batch's last element: a literal may run past the batch's input bytes
+        const int L = 63 - __builtin_clzll(live);
+        const int32_t l_len = __builtin_amdgcn_readlane(c_len, L), l_adv = __builtin_amdgcn_readlane(c_adv, L);
+        const int32_t l_off = __builtin_amdgcn_readlane(c_off, L), l_lq = __builtin_amdgcn_readlane(lq, L);
+        if (l_off == 0 && L + l_adv > 64) {
+          const int32_t p0 = L + l_adv - l_len;  // payload start, batch-relative
+          const int32_t src = ip + p0;
+          const bool in_win = src >= w.wbase && src + l_len <= w.wbase + kFragWin;
+          for (int32_t j = max(0, 64 - p0) + lane; j < l_len; j += 64)
+            fb[l_lq + j] = in_win ? (uint8_t)w.byte(src + j) : in[src + j];
+        }
+        // the copies (at most 64 bytes each) go to the queue
+        const uint64_t copies = live & __ballot(c_off != 0);
+        cq[par][nb][lane] = make_uint2(((uint32_t)lq & 0xffffu) | ((uint32_t)c_len << 16), (uint32_t)c_off);
+        if (lane == 0) cmask[par][nb] = copies;
+        nb++;
+        q = fs + l_lq + l_len;
+        ip += L + l_adv;
+      }
+      if (lane == 0) {
+        s_nb[par] = nb;
+        if (bad) s_bad = 1;
+        if (!bad && q >= fe) s_done = 1;
+      }
+    } else if (wave == 1 && r > 0) {
+      // the copies queued in the round before, in order
+      const int cp = par ^ 1;
+      const int nb = s_nb[cp];
+      for (int b = 0; b < nb; b++) {
+        uint64_t rest = cmask[cp][b];
+        const uint2 e = cq[cp][b][lane];
+        while (rest) {
+          const int l = __builtin_ctzll(rest);
+          rest &= rest - 1;
+          const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)e.x, l);
+          const int32_t off = __builtin_amdgcn_readlane((int)e.y, l);
+          const int32_t dq = (int32_t)(x & 0xffffu), len = (int32_t)(x >> 16);
+          if (lane < len) fb[dq + lane] = fb[dq - off + (off >= len ? lane : lane % off)];
+          compiler_fence();
+        }
+      }
+    }
+    __syncthreads();
+    const bool done = s_done != 0, bad = s_bad != 0;  // read between two barriers: written only before the first
+    __syncthreads();
+    if (bad) {
+      failed = true;
+      break;
+    }
+    if (parsed) break;  // this round ran the last queued copies
+    parsed = done;
+  }
+  if (failed) {
+    if (threadIdx.x == 0) pq_error(hdr, TQ_EINVAL);
+    return;
+  }
   uint32_t* dst = reinterpret_cast<uint32_t*>(raw + pg.u_off + fs);  // 256-aligned, padded past the body
-  for (int i = lane; i < ((fe - fs + 3) >> 2); i += 64) dst[i] = buf[i];
+  for (int i = threadIdx.x; i < ((fe - fs + 3) >> 2); i += 2 * kWave) dst[i] = buf[i];
 }
 
 // A body the scan flagged (1), inflated by one wave in order through a 64 KiB
@@ -1135,7 +1184,7 @@ tq_status tq_parquet_decode(tq_preload* p, void* d_work, size_t work_bytes, cons
       hipLaunchKernelGGL(k_pq_snappy_scan, dim3((int)comp_pages.size()), dim3(64 * kScanWaves), 0, stream, dp, cl, raw, frag_in,
                          flags, hdr);
       if (p->frags > 0)
-        hipLaunchKernelGGL(k_pq_snappy_frag, dim3((int)p->frags), dim3(64), 0, stream, dp, cl,
+        hipLaunchKernelGGL(k_pq_snappy_frag, dim3((int)p->frags), dim3(2 * kWave), 0, stream, dp, cl,
                            reinterpret_cast<const int32_t*>(W + L.frag_cp), raw, frag_in, flags, hdr);
       hipLaunchKernelGGL(k_pq_snappy, dim3((int)comp_pages.size()), dim3(64), 0, stream, dp, cl, raw, flags, hdr);
     }
