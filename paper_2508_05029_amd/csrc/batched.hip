@@ -28,6 +28,7 @@ constexpr int kMaxChunks = 8;    // domain <= 65536
 constexpr int kCtr = 16;         // counters per instance: chunk counts at [8..16)
 constexpr int kPhases = 4;       // build, probe, finalize (single chunk or chunk counts), chunk writes
 constexpr int kBPR = 2;          // rows per lane in probe items
+constexpr int kBuildQ = 2 * 64;  // a build item's per-wave queue of kept rows (at most 63 + 64)
 constexpr int kMinBloomWords = 64;    // an instance's filter: 2 bits per build row, 256 B to 32 KiB
 constexpr int kMaxBloomWords = 8192;
 
@@ -322,20 +323,39 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, 
     int64_t* ctr = ctrs + inst * kCtr;
 
     if (PHASE == 0 && type == kItBuild) {
+      // The rows that pass the predicates (most do not) are compacted per
+      // wave into an LDS queue of (key, payload) and inserted 64 at a time,
+      // one per lane, with the instance's filter bits: each CAS round then
+      // works on a full wave of rows instead of a few lanes of four.
       const TableHeader* th = static_cast<const TableHeader*>(I.table);
       uint32_t* words = table_tags(const_cast<TableHeader*>(th));
       v2i64* slots = reinterpret_cast<v2i64*>(table_slots(const_cast<TableHeader*>(th), I.cap_max));
       const int64_t lo = idx * I.build_tile, hi = min(I.n_dim, lo + I.build_tile);
+      const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+      v2i64* bq = reinterpret_cast<v2i64*>(smem) + wave * kBuildQ;  // this wave's queue
+      int qn = 0;  // queued rows (the same in every lane)
+      auto insert_queued = [&](int cnt) {  // entries [0, cnt), cnt <= 64
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        bool pend[1] = {lane < cnt};
+        const v2i64 e = pend[0] ? bq[lane] : v2i64{0, 0};
+        int64_t k1[1] = {e.x}, p1[1] = {e.y};
+        if (pend[0]) {
+          const uint64_t hh = mulhash(k1[0]);
+          atomicOr(&I.bloom[inst_bloom_word(hh, I.bloom_nw)], bloom_bits(hh));
+        }
+        table_insert<1>(words, slots, I.log2cap, 0, pend, k1, p1);
+      };
       DCol dc[4];
 #pragma unroll
       for (int c = 0; c < 4; c++) dc[c] = DCol{I.dcol[c] ? I.dcol[c] : I.dcol[0], Q.dtype[c] ? Q.dtype[c] : 8};
-      for (int64_t r0 = lo + (int64_t)threadIdx.x * kRows; r0 < hi; r0 += (int64_t)blockDim.x * kRows) {
+      // the loop runs alike in every lane of a wave (lanes past the tile hold no rows)
+      for (int64_t wb = lo + (int64_t)wave * kWave * kRows; wb < hi; wb += (int64_t)blockDim.x * kRows) {
+        const int64_t r0 = wb + (int64_t)lane * kRows;
         const bool full = r0 + kRows <= hi;
         int64_t v[4][kRows];
-        bool pend[kRows];
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-          if (c < Q.ndim) load4(dc[c], r0, full, hi, v[c]);
+          if (c < Q.ndim && r0 < hi) load4(dc[c], r0, full, hi, v[c]);
           else {
 #pragma unroll
             for (int i = 0; i < kRows; i++) v[c][i] = 0;
@@ -353,14 +373,23 @@ __global__ __launch_bounds__(kBBlock) void k_batched(BQuery Q, WorkHeader* hdr, 
               ok = ok && x >= Q.pred[j].lo && x <= Q.pred[j].hi;
             }
           }
-          pend[i] = ok;
-          if (ok) {
-            const uint64_t hh = mulhash(v[0][i]);
-            atomicOr(&I.bloom[inst_bloom_word(hh, I.bloom_nw)], bloom_bits(hh));
+          const uint64_t m = __ballot(ok);
+          if (ok) bq[qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+              v2i64{v[0][i], v[1][i]};
+          qn += __builtin_popcountll(m);
+          if (qn >= kWave) {
+            insert_queued(kWave);
+            // the rest (fewer than 64) moves to the front
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const bool mv = lane < qn - kWave;
+            const v2i64 t = mv ? bq[kWave + lane] : v2i64{0, 0};
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (mv) bq[lane] = t;
+            qn -= kWave;
           }
         }
-        table_insert<kRows>(words, slots, I.log2cap, 0, pend, v[0], v[1]);
       }
+      if (qn > 0) insert_queued(qn);
     } else if (PHASE == 1 && type == kItProbe) {
       if (I.domain * (1 + Q.nsum) * 8 <= kLdsAggBytes) probe_item<kDense>(Q, I, idx, smem, &hdr->err);
       else probe_item<kHash>(Q, I, idx, smem, &hdr->err);
