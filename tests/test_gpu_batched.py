@@ -119,3 +119,29 @@ def test_batched_sums_wrap_mod_2_64_like_the_oracle():
     job.run()
     job.check()
     check_all(job, insts)
+
+
+@pytest.mark.parametrize("window", [(0, 1 << 30), (-5, -1), (100, 100)])
+def test_build_keeps_every_row_none_or_few(window):
+    """The build items compact the rows they keep per wave before inserting
+    them: every dimension row kept (the queue fills on every step), none, or
+    one date's rows, with 1088-row build tiles whose last wave is partial."""
+    import dataclasses
+    say(f"batched build window={window}")
+
+    def query(G):
+        return dataclasses.replace(wl.batched_query(G), build_preds=[wl.Pred("date", *window)])
+
+    insts = make_instances(24, seed=wl.BATCH_SEED + 400)
+    job = pipeline.BatchedJoinAgg(query(8), insts, [(0.5, 1088, 4096)] * len(insts))
+    job.run()
+    job.check()
+    got = job.results(range(len(insts)))
+    kept = 0
+    for i, (d, f, G) in enumerate(insts):
+        want = oracle.join_agg(d, f, query(G))
+        kept += want["join_rows"]
+        assert got[i]["keys"].tolist() == want["keys"].tolist(), i
+        assert got[i]["count"].tolist() == want["count"].tolist(), i
+        assert got[i]["sums"].tolist() == want["sums"].tolist(), i
+    assert (kept > 0) == (window[1] >= 0)
