@@ -234,6 +234,10 @@ def _hand_page(seed, plan):
     # elements, so that chains leave blocks at every offset and skip whole blocks: one fragment
     ("block_edges", [e for k in range(40) for e in (("lit", 950 + (k * 7) % 30 + 960 * (k % 2)), ("copy", 8, 40 + k % 25),
                                                      ("lit", 1 + k % 3), ("copy", 1 + k % 5, 64))]),
+    # a last fragment of 88 bytes after one that a single literal fills: one batch each
+    ("tail_fragment", [("lit", 65_536), ("lit", 16), ("copy", 8, 64), ("copy", 3, 7)]),
+    # three fragments that are one literal each, then five bytes
+    ("literal_fragments", [("lit", 65_536)] * 3 + [("lit", 5)]),
 ])
 def test_hand_built_snappy_pages(tmp_path, name, plan):
     import pyarrow.parquet as pq
