@@ -525,7 +525,7 @@ __global__ __launch_bounds__(kFinBlock) void k_build_regions(TableHeader* h, int
   for (int i = tid; i < nbw; i += kFinBlock) scratch_bloom(h, cap_max)[(size_t)j * nbw + i] = lbloom[i];
 }
 
-constexpr int kFallbackBlocks = 16;  // two per XCD; the global-CAS insert, when needed, strides over every row
+constexpr int kFallbackBlocks = 16;  // two per XCD, for tables that cannot leave the regions' range
 
 template <int NC>
 __global__ __launch_bounds__(kBlock) void k_build_fallback(RowPlan P, const int64_t* keys, DCol payload, int64_t n,
@@ -1439,9 +1439,13 @@ static tq_status join_build(void* d_table, size_t bytes, const int64_t* d_keys, 
     hipLaunchKernelGGL(k_build_regions, dim3(kRegionBins), dim3(kFinBlock), 0, stream, h, cap_max, (int)part_grid,
                        load_factor, skip, flags, cap_rule(load_factor));
     // the fallback does nothing unless a region overflowed (rare: keys whose hashes
-    // crowd one region); a small grid keeps the launch that finds nothing to do cheap
-    // (dispatching hundreds of workgroups that return at once took about 4 us)
-    TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_fallback<NC>, dim3(kFallbackBlocks), dim3(kBlock), 0,
+    // crowd one region) or the table is past the regions' range, which only a buffer
+    // of more than 2^kMaxPassLog2Cap slots allows; for a smaller one a small grid
+    // keeps the launch that finds nothing to do cheap (dispatching hundreds of
+    // workgroups that return at once took about 4 us), for a larger one the grid is
+    // sized for inserting every row
+    const int fb_grid = cap_max > ((int64_t)1 << kMaxPassLog2Cap) ? stream_grid(n, 2) : kFallbackBlocks;
+    TQ_DISPATCH_NC(P.ncol, NC, hipLaunchKernelGGL(k_build_fallback<NC>, dim3(fb_grid), dim3(kBlock), 0,
                                                   stream, P, d_keys, pc, n, h, cap_max, key_valid));
     TQ_HIP(hipGetLastError());
     return TQ_OK;
